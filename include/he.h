@@ -1,0 +1,169 @@
+/*
+ * he.h — C ABI of the MI355X (gfx950) RNS-CKKS hot path under FHEON's
+ * encrypted CNN layers (arXiv 2510.03996).
+ *
+ * The paper's layers (Section "Secure Neural Network Layers") are built from
+ * CKKS slot rotations, plaintext-ciphertext products, additions and rescaling
+ * over R_Q = Z_Q[X]/(X^N + 1) in RNS form (Section "Background", CKKS scheme,
+ * which also names hoisted "fast rotations").  This library implements that
+ * ciphertext arithmetic on the GPU: negacyclic NTT/iNTT, Galois automorphisms,
+ * hybrid key switching (ModUp -> key inner product -> ModDown),
+ * relinearization, rescale, pt-ct multiply-accumulate, and the layer
+ * schedules (conv2d, average pooling, global average pooling, fully
+ * connected) on top of them.
+ *
+ * Data format (all device memory is caller-owned unless stated otherwise):
+ *  - Residues are uint64 in [0, q).  A limb holds N residues in NTT form:
+ *    index j stores a(psi^(2 brv(j) + 1)) mod q, psi the minimum primitive
+ *    2N-th root of unity mod q (bit-reversed evaluation order).
+ *  - Moduli are numbered 0..L-1 for the ciphertext primes q_i (q_0 first,
+ *    rescale drops the highest active index) and L..L+K-1 for the special
+ *    primes p_k of hybrid key switching.
+ *  - A ciphertext at level l (l active limbs q_0..q_{l-1}) is he_ct:
+ *    `data` points to [2][cap][N] uint64 (c0 limbs at data, c1 limbs at
+ *    data + cap*N), cap >= l.
+ *  - A plaintext is he_pt: [level][N] uint64 in NTT form; operations use its
+ *    first l limbs.
+ *  - An evaluation key is [dnum][2][L+K][N] uint64 in NTT form: for digit j
+ *    (alpha consecutive Q limbs), poly 0 is b_j and poly 1 is a_j with
+ *    b_j = -a_j s + e_j + [P]_{q_i} s' on the digit's limbs and -a_j s + e_j
+ *    elsewhere (a key from s' to s; s' = phi_g(s) for a rotation, s^2 for
+ *    relinearization).  dnum = ceil(L / alpha).
+ *
+ * Conventions: every call returns HE_OK (0) or a negative HE_E* code and
+ * never throws; he_last_error() gives a thread-local message.  Work is
+ * enqueued asynchronously on the given HIP stream (NULL = default stream);
+ * host-side scale/level fields of output structs are written before return.
+ * Outputs must not alias inputs unless a call says so.
+ */
+#ifndef HE_H_
+#define HE_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HE_OK 0
+#define HE_EINVAL (-1)       /* bad argument, shape or aliasing */
+#define HE_ENOKEY (-2)       /* evaluation key not resident */
+#define HE_ELEVEL (-3)       /* level mismatch or exhausted */
+#define HE_ESCALE (-4)       /* scale mismatch in an addition */
+#define HE_ENOMEM (-5)       /* device allocation failed */
+#define HE_EHIP (-6)         /* HIP runtime error */
+#define HE_EUNSUPPORTED (-7) /* valid request this library does not implement */
+
+#define HE_MAX_Q 60
+#define HE_MAX_P 16
+#define HE_KEY_RELIN ((int32_t)0x7fffffff) /* key id of the relinearization key */
+
+typedef struct he_ctx he_ctx;
+typedef void* he_stream; /* hipStream_t */
+
+/* CKKS parameters.  Primes are either given (q[i], p[k] non-zero) or chosen
+ * by the rule: for bit size b the largest not-yet-taken prime q = k 2N + 1
+ * with 2^(b-1) < q < 2^b, allocated in the order q_0, q_1..q_{L-1}, p_0..
+ * (the paper fixes only bit sizes; Section "HE Security Parameters").
+ * Every prime must be < 2^61 and = 1 mod 2N. */
+typedef struct {
+  int32_t log_n;            /* N = 2^log_n, 12 <= log_n <= 16 */
+  int32_t n_q;              /* L, 1..HE_MAX_Q */
+  int32_t n_p;              /* K, 1..HE_MAX_P */
+  int32_t alpha;            /* Q limbs per key-switching digit; alpha <= K */
+  int32_t q_bits[HE_MAX_Q]; /* used when q[i] == 0 */
+  int32_t p_bits[HE_MAX_P]; /* used when p[k] == 0 */
+  uint64_t q[HE_MAX_Q];
+  uint64_t p[HE_MAX_P];
+} he_params;
+
+typedef struct {
+  uint64_t* data; /* device [2][cap][N] */
+  int32_t level;  /* active limbs l */
+  int32_t cap;    /* limb capacity per polynomial */
+  double scale;   /* CKKS scaling factor carried with the ciphertext */
+} he_ct;
+
+typedef struct {
+  const uint64_t* data; /* device [level][N] */
+  int32_t level;
+  double scale;
+} he_pt;
+
+/* ------------------------------------------------------------ context */
+/* Create a context on `device`: chooses primes, builds twiddle / basis-
+ * conversion tables and a workspace pool in device memory (owned by the
+ * library until he_ctx_destroy).  HE_EINVAL for unsupported parameters. */
+int he_ctx_create(const he_params* params, int device, he_ctx** out);
+int he_ctx_destroy(he_ctx* ctx);
+/* Copy the L + K moduli (q_0..q_{L-1}, p_0..p_{K-1}) to host `out`. */
+int he_ctx_moduli(const he_ctx* ctx, uint64_t* out, int cap);
+int he_ctx_info(const he_ctx* ctx, int32_t* log_n, int32_t* n_q, int32_t* n_p, int32_t* alpha);
+const char* he_last_error(void);
+
+/* ------------------------------------------------------------ keys
+ * Evaluation keys are the paper's "rotation keys" and relinearization key
+ * (Section "Evaluation Keys Management"): preloaded into HBM and kept
+ * resident until evicted.  `src` holds one key in the layout above
+ * ([dnum][2][L+K][N], host or device memory per src_on_device); the library
+ * copies it into its own storage (converted to an internal form).
+ * key_id: a rotation amount r (slot i <- slot i + r; ids are reduced mod N/2)
+ * or HE_KEY_RELIN. */
+int he_key_upload(he_ctx* ctx, int32_t key_id, const uint64_t* src, size_t bytes, int src_on_device,
+                  he_stream stream);
+int he_key_evict(he_ctx* ctx, int32_t key_id);
+int he_key_count(const he_ctx* ctx);
+size_t he_key_bytes(const he_ctx* ctx); /* bytes of one key */
+
+/* ------------------------------------------------------------ ring ops */
+/* In-place negacyclic NTT (inverse = 0) or iNTT (inverse = 1, includes N^-1)
+ * of n_limbs consecutive limbs at `poly` ([n_limbs][N], device), limb t taken
+ * modulo modulus index first_limb + t.  Moduli indices beyond L-1 address
+ * the special primes. */
+int he_ntt(he_ctx* ctx, uint64_t* poly, int n_limbs, int first_limb, int inverse, he_stream stream);
+
+/* Slot rotation Rot_r (slot i <- slot i + r), the paper's rotation
+ * (Sections "Secure Convolution Layer", Algorithm 1): Galois automorphism
+ * X -> X^g, g = 5^(r mod N/2) mod 2N, with hybrid key switching.  Pinned
+ * formula: ModUp(c1) -> phi_g on the extended digits -> inner product with
+ * evk_r -> ModDown, out = (phi_g(c0) + u0, u1).  Equal to he_rotate_hoisted
+ * with one index.  r = 0 (mod N/2) copies.  HE_ENOKEY if evk_r is absent. */
+int he_rotate(he_ctx* ctx, const he_ct* in, int32_t r, he_ct* out, he_stream stream);
+
+/* Hoisted rotations ("fast rotations"): one ModUp of c1 shared by n
+ * rotations; outs[t] = Rot_{r[t]}(in).  Outputs must not alias the input. */
+int he_rotate_hoisted(he_ctx* ctx, const he_ct* in, const int32_t* r, int n, he_ct* outs, he_stream stream);
+
+/* out (+)= in (.) pt limb-wise at the ciphertext's level (pt-ct product of
+ * the paper's convolution/pooling/FC MACs).  accumulate = 0: out = in*pt,
+ * out.scale = in.scale * pt.scale.  accumulate = 1: out += in*pt, requiring
+ * out.level == in.level and out.scale == in.scale * pt.scale (HE_ESCALE).
+ * out may alias in when accumulate == 0. */
+int he_mul_plain(he_ctx* ctx, const he_ct* in, const he_pt* pt, he_ct* out, int accumulate, he_stream stream);
+
+/* Exact ring additions; equal levels (HE_ELEVEL) and equal scales
+ * (HE_ESCALE) required.  out may alias a or b. */
+int he_add(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct* out, he_stream stream);
+int he_sub(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct* out, he_stream stream);
+/* c0 += pt (scales must match).  out may alias a. */
+int he_add_plain(he_ctx* ctx, const he_ct* a, const he_pt* pt, he_ct* out, he_stream stream);
+
+/* Floor rescale by the top prime q_t (t = level-1):
+ * c'_i = (c_i - ([c]_{q_t} mod q_i)) q_t^{-1} mod q_i; scale /= q_t.
+ * HE_ELEVEL at level 1.  out may alias in. */
+int he_rescale(he_ctx* ctx, const he_ct* in, he_ct* out, he_stream stream);
+/* Keep limbs q_0..q_{level-1} (level alignment, no scale change). */
+int he_drop_level(he_ctx* ctx, const he_ct* in, int level, he_ct* out, he_stream stream);
+
+/* Ciphertext product with relinearization (no rescale): tensor
+ * (a0 b0, a0 b1 + a1 b0, a1 b1), then d2 key-switched with the HE_KEY_RELIN
+ * key.  Equal levels required; out.scale = a.scale * b.scale. */
+int he_mul_relin(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct* out, he_stream stream);
+/* Relinearize a 3-part ciphertext d ([3][level][N], device) into out. */
+int he_relin(he_ctx* ctx, const uint64_t* d, int level, double scale, he_ct* out, he_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HE_H_ */

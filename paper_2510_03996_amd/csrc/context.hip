@@ -1,0 +1,346 @@
+// Context creation: prime chain, NTT twiddles, basis-conversion constants,
+// resident key store and the workspace pool.
+#include <cstring>
+#include <string>
+
+#include "internal.h"
+
+namespace he {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+int hip_error(hipError_t e, const char* what) {
+  return set_error(HE_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------- host modular helpers
+typedef unsigned __int128 u128;
+static uint64_t hmul(uint64_t a, uint64_t b, uint64_t q) { return (uint64_t)((u128)a * b % q); }
+static uint64_t hpow(uint64_t a, uint64_t e, uint64_t q) {
+  uint64_t r = 1 % q;
+  a %= q;
+  for (; e; e >>= 1) {
+    if (e & 1) r = hmul(r, a, q);
+    a = hmul(a, a, q);
+  }
+  return r;
+}
+static uint64_t hinv(uint64_t a, uint64_t q) { return hpow(a, q - 2, q); }
+static uint64_t shoup_of(uint64_t w, uint64_t q) { return (uint64_t)(((u128)w << 64) / q); }
+
+static bool miller_rabin(uint64_t n) {
+  if (n < 2) return false;
+  static const uint64_t bases[] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  for (uint64_t b : bases) {
+    if (n % b == 0) return n == b;
+  }
+  uint64_t d = n - 1;
+  int s = 0;
+  while (!(d & 1)) { d >>= 1; s++; }
+  for (uint64_t b : bases) {
+    uint64_t x = hpow(b, d, n);
+    if (x == 1 || x == n - 1) continue;
+    bool composite = true;
+    for (int r = 1; r < s; r++) {
+      x = hmul(x, x, n);
+      if (x == n - 1) { composite = false; break; }
+    }
+    if (composite) return false;
+  }
+  return true;
+}
+
+static int brv(int x, int logn) {
+  int r = 0;
+  for (int i = 0; i < logn; i++) { r = (r << 1) | (x & 1); x >>= 1; }
+  return r;
+}
+
+// minimum primitive 2N-th root of unity mod q
+static uint64_t min_psi(uint64_t q, uint64_t n) {
+  uint64_t cand = 0;
+  for (uint64_t x = 2;; x++) {
+    cand = hpow(x, (q - 1) / (2 * n), q);
+    if (hpow(cand, n, q) == q - 1) break;
+  }
+  uint64_t sq = hmul(cand, cand, q), cur = cand, best = cand;
+  for (uint64_t t = 1; t < n; t++) {
+    cur = hmul(cur, sq, q);
+    if (cur < best) best = cur;
+  }
+  return best;
+}
+
+LimbMap range_map(int first_pos, int n, int first_mod) {
+  LimbMap m{};
+  m.n = n;
+  for (int i = 0; i < n; i++) {
+    m.pos[i] = (uint8_t)(first_pos + i);
+    m.mod[i] = (uint8_t)(first_mod + i);
+  }
+  return m;
+}
+
+LimbMap ext_map(const Ctx* c, int level) {
+  LimbMap m{};
+  m.n = level + c->K;
+  for (int i = 0; i < m.n; i++) {
+    m.pos[i] = (uint8_t)i;
+    m.mod[i] = (uint8_t)(i < level ? i : c->L + (i - level));
+  }
+  return m;
+}
+
+int32_t norm_key_id(const Ctx* c, int32_t id) {
+  if (id == HE_KEY_RELIN) return id;
+  int32_t h = c->n / 2;
+  int32_t r = id % h;
+  return r < 0 ? r + h : r;
+}
+
+uint32_t galois_elt(const Ctx* c, int32_t r) {
+  uint64_t two_n = 2 * (uint64_t)c->n;
+  return (uint32_t)hpow(5, (uint64_t)norm_key_id(c, r), two_n);
+}
+
+template <class T>
+static int dev_alloc(Ctx* c, T** p, size_t count) {
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, count * sizeof(T));
+  if (e != hipSuccess) return set_error(HE_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  c->allocs.push_back(v);
+  *p = (T*)v;
+  return HE_OK;
+}
+
+static int build_bconv(Ctx* c, BConvTab& t, const std::vector<int>& in_pos, const std::vector<int>& in_mod,
+                       const std::vector<int>& out_pos, const std::vector<int>& out_mod) {
+  t.nin = (int)in_mod.size();
+  t.nout = (int)out_mod.size();
+  t.in.n = t.nin;
+  t.out.n = t.nout;
+  for (int i = 0; i < t.nin; i++) { t.in.pos[i] = (uint8_t)in_pos[i]; t.in.mod[i] = (uint8_t)in_mod[i]; }
+  for (int p = 0; p < t.nout; p++) { t.out.pos[p] = (uint8_t)out_pos[p]; t.out.mod[p] = (uint8_t)out_mod[p]; }
+  std::vector<uint64_t> h(2 * t.nin + (size_t)t.nin * t.nout);
+  for (int i = 0; i < t.nin; i++) {
+    uint64_t qi = c->mod[in_mod[i]];
+    // (Qin / q_i) mod q_i
+    uint64_t prod = 1 % qi;
+    for (int i2 = 0; i2 < t.nin; i2++)
+      if (i2 != i) prod = hmul(prod, c->mod[in_mod[i2]] % qi, qi);
+    uint64_t w = hinv(prod, qi);
+    h[i] = w;
+    h[t.nin + i] = shoup_of(w, qi);
+    for (int p = 0; p < t.nout; p++) {
+      uint64_t po = c->mod[out_mod[p]];
+      uint64_t v = 1 % po;
+      for (int i2 = 0; i2 < t.nin; i2++)
+        if (i2 != i) v = hmul(v, c->mod[in_mod[i2]] % po, po);
+      uint64_t r64 = (uint64_t)(((u128)1 << 64) % po);
+      h[2 * t.nin + (size_t)i * t.nout + p] = hmul(v, r64, po);
+    }
+  }
+  int rc = dev_alloc(c, &t.d, h.size());
+  if (rc) return rc;
+  HE_HIP(hipMemcpy(t.d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  return HE_OK;
+}
+
+static int ctx_init(Ctx* c, const he_params* p) {
+  c->log_n = p->log_n;
+  c->n = 1 << p->log_n;
+  c->L = p->n_q;
+  c->K = p->n_p;
+  c->alpha = p->alpha;
+  const uint64_t two_n = 2 * (uint64_t)c->n;
+  // ---- primes
+  std::vector<uint64_t> taken;
+  std::map<int, uint64_t> next_k;
+  auto take = [&](int b, uint64_t* out) -> int {
+    if (b < 20 || b > 61) return set_error(HE_EINVAL, "prime bit size must be in [20, 61]");
+    uint64_t k = next_k.count(b) ? next_k[b] : (((uint64_t)1 << b) - 2) / two_n;
+    for (;; k--) {
+      uint64_t q = k * two_n + 1;
+      if (k == 0 || q <= ((uint64_t)1 << (b - 1))) return set_error(HE_EINVAL, "ran out of primes");
+      if (q >= ((uint64_t)1 << b)) continue;
+      bool used = false;
+      for (uint64_t t : taken) used |= (t == q);
+      if (used || !miller_rabin(q)) continue;
+      taken.push_back(q);
+      next_k[b] = k - 1;
+      *out = q;
+      return HE_OK;
+    }
+  };
+  c->mod.assign(c->L + c->K, 0);
+  for (int i = 0; i < c->L; i++) {
+    if (p->q[i]) { c->mod[i] = p->q[i]; taken.push_back(p->q[i]); }
+  }
+  for (int k = 0; k < c->K; k++) {
+    if (p->p[k]) { c->mod[c->L + k] = p->p[k]; taken.push_back(p->p[k]); }
+  }
+  for (int i = 0; i < c->L; i++)
+    if (!c->mod[i]) { int rc = take(p->q_bits[i], &c->mod[i]); if (rc) return rc; }
+  for (int k = 0; k < c->K; k++)
+    if (!c->mod[c->L + k]) { int rc = take(p->p_bits[k], &c->mod[c->L + k]); if (rc) return rc; }
+  for (uint64_t q : c->mod) {
+    if (q >= ((uint64_t)1 << 61) || q % two_n != 1 || !miller_rabin(q))
+      return set_error(HE_EINVAL, "every modulus must be a prime < 2^61 with q = 1 mod 2N");
+  }
+  // ---- per-modulus constants and twiddles
+  const int M = c->L + c->K;
+  const size_t N = c->n;
+  c->psi.resize(M);
+  c->hmod.resize(M);
+  std::vector<uint64_t> tw(M * N), twp(M * N), itw(M * N), itwp(M * N), pw(N), ipw(N);
+  for (int m = 0; m < M; m++) {
+    uint64_t q = c->mod[m];
+    uint64_t psi = min_psi(q, N), ipsi = hinv(psi, q);
+    c->psi[m] = psi;
+    pw[0] = ipw[0] = 1;
+    for (size_t k = 1; k < N; k++) { pw[k] = hmul(pw[k - 1], psi, q); ipw[k] = hmul(ipw[k - 1], ipsi, q); }
+    for (size_t k = 0; k < N; k++) {
+      int b = brv((int)k, c->log_n);
+      tw[m * N + k] = pw[b];
+      twp[m * N + k] = shoup_of(pw[b], q);
+      itw[m * N + k] = ipw[b];
+      itwp[m * N + k] = shoup_of(ipw[b], q);
+    }
+    ModInfo& mi = c->hmod[m];
+    mi.q = q;
+    uint64_t inv = 1;
+    for (int it = 0; it < 7; it++) inv *= 2 - q * inv;  // Newton: q^{-1} mod 2^64
+    mi.qinv = inv;
+    uint64_t r64 = (uint64_t)(((u128)1 << 64) % q);
+    mi.r2 = hmul(r64, r64, q);
+    int kb = 64 - __builtin_clzll(q);
+    mi.k = kb;
+    mi.mu = (uint64_t)(((u128)1 << (2 * kb)) / q);
+    mi.ninv = hinv(N % q, q);
+    mi.ninv_p = shoup_of(mi.ninv, q);
+    mi.pad = 0;
+  }
+  int rc;
+  if ((rc = dev_alloc(c, &c->d_mod, M))) return rc;
+  if ((rc = dev_alloc(c, &c->d_tw, M * N))) return rc;
+  if ((rc = dev_alloc(c, &c->d_twp, M * N))) return rc;
+  if ((rc = dev_alloc(c, &c->d_itw, M * N))) return rc;
+  if ((rc = dev_alloc(c, &c->d_itwp, M * N))) return rc;
+  HE_HIP(hipMemcpy(c->d_mod, c->hmod.data(), M * sizeof(ModInfo), hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(c->d_tw, tw.data(), M * N * 8, hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(c->d_twp, twp.data(), M * N * 8, hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(c->d_itw, itw.data(), M * N * 8, hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(c->d_itwp, itwp.data(), M * N * 8, hipMemcpyHostToDevice));
+  // ---- basis conversion tables for every level
+  c->modup.assign(c->L + 1, {});
+  c->moddown.assign(c->L + 1, {});
+  c->d_rescale.assign(c->L + 1, nullptr);
+  c->d_pinv.assign(c->L + 1, nullptr);
+  for (int l = 1; l <= c->L; l++) {
+    int dn = c->dnum(l);
+    c->modup[l].resize(dn);
+    for (int j = 0; j < dn; j++) {
+      std::vector<int> ip, im, op, om;
+      int lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, l);
+      for (int i = lo; i < hi; i++) { ip.push_back(i); im.push_back(i); }
+      for (int i = 0; i < l; i++)
+        if (i < lo || i >= hi) { op.push_back(i); om.push_back(i); }
+      for (int k = 0; k < c->K; k++) { op.push_back(l + k); om.push_back(c->L + k); }
+      if ((rc = build_bconv(c, c->modup[l][j], ip, im, op, om))) return rc;
+    }
+    std::vector<int> ip, im, op, om;
+    for (int k = 0; k < c->K; k++) { ip.push_back(l + k); im.push_back(c->L + k); }
+    for (int i = 0; i < l; i++) { op.push_back(i); om.push_back(i); }
+    if ((rc = build_bconv(c, c->moddown[l], ip, im, op, om))) return rc;
+    // P^{-1} mod q_i
+    std::vector<uint64_t> pv(2 * l);
+    for (int i = 0; i < l; i++) {
+      uint64_t qi = c->mod[i], P = 1;
+      for (int k = 0; k < c->K; k++) P = hmul(P, c->mod[c->L + k] % qi, qi);
+      pv[i] = hinv(P, qi);
+      pv[l + i] = shoup_of(pv[i], qi);
+    }
+    if ((rc = dev_alloc(c, &c->d_pinv[l], 2 * l))) return rc;
+    HE_HIP(hipMemcpy(c->d_pinv[l], pv.data(), 2 * l * 8, hipMemcpyHostToDevice));
+    if (l >= 2) {
+      std::vector<uint64_t> rv(2 * (l - 1));
+      uint64_t qt = c->mod[l - 1];
+      for (int i = 0; i < l - 1; i++) {
+        rv[i] = hinv(qt % c->mod[i], c->mod[i]);
+        rv[l - 1 + i] = shoup_of(rv[i], c->mod[i]);
+      }
+      if ((rc = dev_alloc(c, &c->d_rescale[l], 2 * (l - 1)))) return rc;
+      HE_HIP(hipMemcpy(c->d_rescale[l], rv.data(), 2 * (l - 1) * 8, hipMemcpyHostToDevice));
+    }
+  }
+  // ---- workspace: one top-level key switch + tensor + rescale scratch
+  const size_t L = c->L, K = c->K, D = c->dnum(c->L);
+  c->ws_words = ws_words(c);
+  if ((rc = dev_alloc(c, &c->ws, c->ws_words))) return rc;
+  c->key_words = D * 2 * (L + K) * N;
+  return HE_OK;
+}
+
+}  // namespace he
+
+using namespace he;
+
+extern "C" {
+
+const char* he_last_error(void) { return g_err.c_str(); }
+
+int he_ctx_create(const he_params* p, int device, he_ctx** out) {
+  if (!p || !out) return set_error(HE_EINVAL, "null argument");
+  *out = nullptr;
+  if (p->log_n < 12 || p->log_n > 16 || p->log_n % 2)
+    return set_error(HE_EINVAL, "log_n must be 12, 14 or 16");
+  if (p->n_q < 1 || p->n_q > HE_MAX_Q || p->n_p < 1 || p->n_p > HE_MAX_P || p->n_q + p->n_p > MAXL)
+    return set_error(HE_EINVAL, "bad number of primes");
+  if (p->alpha < 1 || p->alpha > p->n_q || p->alpha > MAX_BCONV_IN || p->n_p > MAX_BCONV_IN)
+    return set_error(HE_EINVAL, "alpha must be in [1, min(L, 8)] and K <= 8");
+  if ((p->n_q + p->alpha - 1) / p->alpha > 8) return set_error(HE_EINVAL, "at most 8 key-switching digits");
+  hipError_t e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_error(e, "hipSetDevice");
+  he_ctx* h = new he_ctx();
+  h->c.device = device;
+  int rc = ctx_init(&h->c, p);
+  if (rc) {
+    he_ctx_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return HE_OK;
+}
+
+int he_ctx_destroy(he_ctx* h) {
+  if (!h) return HE_OK;
+  hipSetDevice(h->c.device);
+  hipDeviceSynchronize();
+  for (auto& kv : h->c.keys) hipFree(kv.second);
+  for (void* p : h->c.allocs) hipFree(p);
+  delete h;
+  return HE_OK;
+}
+
+int he_ctx_moduli(const he_ctx* h, uint64_t* out, int cap) {
+  if (!h || !out) return set_error(HE_EINVAL, "null argument");
+  int M = h->c.L + h->c.K;
+  if (cap < M) return set_error(HE_EINVAL, "output too small");
+  for (int i = 0; i < M; i++) out[i] = h->c.mod[i];
+  return M;
+}
+
+int he_ctx_info(const he_ctx* h, int32_t* log_n, int32_t* n_q, int32_t* n_p, int32_t* alpha) {
+  if (!h) return set_error(HE_EINVAL, "null argument");
+  if (log_n) *log_n = h->c.log_n;
+  if (n_q) *n_q = h->c.L;
+  if (n_p) *n_p = h->c.K;
+  if (alpha) *alpha = h->c.alpha;
+  return HE_OK;
+}
+
+}  // extern "C"

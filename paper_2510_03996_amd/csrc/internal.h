@@ -1,0 +1,105 @@
+// Library-internal context, tables and helpers (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/he.h"
+#include "elem_core.h"
+
+namespace he {
+
+constexpr int MAXL = 64;  // max limbs in any basis (L + K)
+
+// Basis-conversion table: nin input moduli -> nout output moduli.
+// Device layout: [nin] w, [nin] w' (Shoup of (Qin/q_i)^{-1} mod q_i), then
+// [nin][nout] Montgomery constants (Qin/q_i mod p) * 2^64 mod p.
+struct BConvTab {
+  int nin = 0, nout = 0;
+  LimbMap in{}, out{};
+  uint64_t* d = nullptr;
+};
+
+struct Ctx {
+  int device = 0;
+  int log_n = 0, n = 0, L = 0, K = 0, alpha = 0;
+  std::vector<uint64_t> mod;  // L + K moduli
+  std::vector<uint64_t> psi;
+  std::vector<ModInfo> hmod;
+  ModInfo* d_mod = nullptr;
+  uint64_t *d_tw = nullptr, *d_twp = nullptr, *d_itw = nullptr, *d_itwp = nullptr;  // [L+K][N]
+  // modup[level][digit]; moddown[level]
+  std::vector<std::vector<BConvTab>> modup;
+  std::vector<BConvTab> moddown;
+  // per level l (>= 2): Shoup pairs of q_{l-1}^{-1} mod q_i (i < l-1): [2][l-1]
+  std::vector<uint64_t*> d_rescale;
+  // per level l: Shoup pairs of P^{-1} mod q_i: [2][l]
+  std::vector<uint64_t*> d_pinv;
+  // resident evaluation keys (Montgomery form), by normalised id
+  std::map<int32_t, uint64_t*> keys;
+  size_t key_words = 0;
+  // workspace pool (one key switch at the top level)
+  uint64_t* ws = nullptr;
+  size_t ws_words = 0;
+  std::vector<void*> allocs;
+
+  int dnum(int level) const { return (level + alpha - 1) / alpha; }
+  size_t limb_words() const { return (size_t)n; }
+};
+
+// thread-local error reporting
+int set_error(int code, const std::string& msg);
+int hip_error(hipError_t e, const char* what);
+#define HE_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_error(e_, #call); \
+  } while (0)
+
+// NTT over the limbs listed in `map`, for nbatch arrays batch_stride words
+// apart (all arrays share the map).
+int ntt_launch(Ctx* c, uint64_t* data, size_t batch_stride, int nbatch, const LimbMap& map, bool inverse,
+               hipStream_t s);
+LimbMap range_map(int first_pos, int n, int first_mod);
+// positions 0..l-1 -> q_0..q_{l-1}, positions l..l+K-1 -> p_0..p_{K-1}
+LimbMap ext_map(const Ctx* c, int level);
+
+// Workspace regions for one in-flight key switch / tensor / rescale.
+struct WS {
+  uint64_t *coeff, *ext, *u, *y, *t3, *rs;
+};
+inline WS ws_layout(const Ctx* c, uint64_t* base) {
+  const size_t N = c->n, L = c->L, K = c->K, D = c->dnum(c->L);
+  WS w;
+  w.coeff = base;
+  w.ext = w.coeff + L * N;
+  w.u = w.ext + D * (L + K) * N;
+  w.y = w.u + 2 * (L + K) * N;
+  w.t3 = w.y + 2 * L * N;
+  w.rs = w.t3 + 3 * L * N;
+  return w;
+}
+inline size_t ws_words(const Ctx* c) {
+  const size_t N = c->n, L = c->L, K = c->K, D = c->dnum(c->L);
+  return N * (L + D * (L + K) + 2 * (L + K) + 2 * L + 3 * L + 2 * L);
+}
+
+// key-switching building blocks (keyswitch.hip)
+int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s);
+// inner product with `key` (Montgomery form), automorphism g on the extended
+// digits, ModDown, and out0 = add0[phi_g] + u0', out1 = add1 + u1'.
+int ks_apply(Ctx* c, const WS& w, int level, const uint64_t* key, uint32_t g, const uint64_t* add0,
+             const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s);
+const uint64_t* find_key(Ctx* c, int32_t id);
+
+int32_t norm_key_id(const Ctx* c, int32_t id);
+uint32_t galois_elt(const Ctx* c, int32_t r);
+
+}  // namespace he
+
+struct he_ctx {
+  he::Ctx c;
+};

@@ -1,0 +1,259 @@
+// Hybrid key switching (ModUp -> key inner product -> ModDown), rotations,
+// hoisted rotations, relinearization, and the resident key store.
+//
+// Pinned formula for every key switch (one formula for plain and hoisted
+// rotations): digits of c1 are basis-extended once (ModUp), the Galois
+// automorphism phi_g is applied to the extended digits as an NTT-form index
+// gather fused into the inner-product load, then ModDown.
+#include "internal.h"
+
+namespace he {
+
+// ---------------------------------------------------------------- kernels
+__global__ __launch_bounds__(256) void k_bconv(const uint64_t* __restrict__ in, size_t in_bs,
+                                               uint64_t* __restrict__ out, size_t out_bs, LimbMap im, LimbMap om,
+                                               const uint64_t* __restrict__ tab, const ModInfo* __restrict__ mods,
+                                               int logn) {
+  const size_t n = (size_t)1 << logn;
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bconv_elem(in + blockIdx.y * in_bs, out + blockIdx.y * out_bs, n, k, im, om, tab, mods);
+}
+
+__global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, size_t ext_stride, int dnum,
+                                            const uint64_t* __restrict__ key, size_t key_digit_stride,
+                                            size_t key_poly_stride, int level, int L, uint32_t g, int logn,
+                                            const ModInfo* __restrict__ mods, uint64_t* __restrict__ u,
+                                            size_t u_poly_stride) {
+  const size_t n = (size_t)1 << logn;
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pos = blockIdx.y;
+  const int mod = pos < level ? pos : L + (pos - level);
+  const uint32_t src = g == 1 ? k : automorph_src(k, g, logn);
+  ip_elem(ext, ext_stride, dnum, key, key_digit_stride, key_poly_stride, pos, mod, n, k, src, mods[mod], u, u,
+          u_poly_stride);
+}
+
+// out_z[i][k] = add_z + (u_z[i][k] - y_z[i][k]) P^{-1}, z = blockIdx.z;
+// add_0 = phi_g(add0)[i][k] (g = 1: no permutation), add_1 = add1[i][k].
+__global__ __launch_bounds__(256) void k_moddown_combine(const uint64_t* __restrict__ u, size_t u_ps,
+                                                         const uint64_t* __restrict__ y, size_t y_ps,
+                                                         const uint64_t* add0, const uint64_t* add1, uint32_t g,
+                                                         uint64_t* out0, uint64_t* out1, int level, int logn,
+                                                         const ModInfo* __restrict__ mods,
+                                                         const uint64_t* __restrict__ pinv) {
+  const size_t n = (size_t)1 << logn;
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, z = blockIdx.z;
+  const uint64_t q = mods[i].q;
+  uint64_t a = 0;
+  if (z == 0 && add0) a = add0[(size_t)i * n + (g == 1 ? k : automorph_src(k, g, logn))];
+  if (z == 1 && add1) a = add1[(size_t)i * n + k];
+  const uint64_t v = moddown_elem(u[z * u_ps + (size_t)i * n + k], y[z * y_ps + (size_t)i * n + k], a, pinv[i],
+                                  pinv[level + i], q);
+  (z == 0 ? out0 : out1)[(size_t)i * n + k] = v;
+}
+
+// x -> x 2^64 mod q on every limb of a [dnum][2][L+K][N] key
+__global__ __launch_bounds__(256) void k_to_mont(uint64_t* key, int M, int logn, const ModInfo* __restrict__ mods) {
+  const size_t n = (size_t)1 << logn;
+  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int limb = blockIdx.y;  // over dnum*2*M
+  const ModInfo mi = mods[limb % M];
+  uint64_t* p = key + (size_t)limb * n + k;
+  *p = mont_redc(mul_wide(*p % mi.q, mi.r2), mi.q, mi.qinv);
+}
+
+// ---------------------------------------------------------------- building blocks
+int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) {
+  const size_t N = c->n;
+  const int K = c->K;
+  const size_t ext_stride = (size_t)(level + K) * N;
+  int rc;
+  HE_HIP(hipMemcpyAsync(w.coeff, c1, (size_t)level * N * 8, hipMemcpyDeviceToDevice, s));
+  if ((rc = ntt_launch(c, w.coeff, 0, 1, range_map(0, level, 0), true, s))) return rc;
+  const int dn = c->dnum(level);
+  for (int j = 0; j < dn; j++) {
+    const BConvTab& t = c->modup[level][j];
+    uint64_t* ext = w.ext + j * ext_stride;
+    const int lo = j * c->alpha;
+    HE_HIP(hipMemcpyAsync(ext + (size_t)lo * N, c1 + (size_t)lo * N, (size_t)t.nin * N * 8,
+                          hipMemcpyDeviceToDevice, s));
+    k_bconv<<<dim3(N / 256, 1), 256, 0, s>>>(w.coeff, 0, ext, 0, t.in, t.out, t.d, c->d_mod, c->log_n);
+    HE_HIP(hipGetLastError());
+    if ((rc = ntt_launch(c, ext, 0, 1, t.out, false, s))) return rc;
+  }
+  return HE_OK;
+}
+
+int ks_apply(Ctx* c, const WS& w, int level, const uint64_t* key, uint32_t g, const uint64_t* add0,
+             const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s) {
+  const size_t N = c->n;
+  const int K = c->K, L = c->L;
+  const size_t E = (size_t)(level + K);
+  const size_t kps = (size_t)(L + K) * N;  // key poly stride
+  int rc;
+  k_ip<<<dim3(N / 256, E), 256, 0, s>>>(w.ext, E * N, c->dnum(level), key, 2 * kps, kps, level, L, g, c->log_n,
+                                        c->d_mod, w.u, E * N);
+  HE_HIP(hipGetLastError());
+  // ModDown of u0 and u1: P limbs to coefficient form, convert to Q_l, back to NTT form
+  if ((rc = ntt_launch(c, w.u, E * N, 2, range_map(level, K, L), true, s))) return rc;
+  const BConvTab& t = c->moddown[level];
+  k_bconv<<<dim3(N / 256, 2), 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, t.in, t.out, t.d, c->d_mod,
+                                           c->log_n);
+  HE_HIP(hipGetLastError());
+  if ((rc = ntt_launch(c, w.y, (size_t)level * N, 2, range_map(0, level, 0), false, s))) return rc;
+  k_moddown_combine<<<dim3(N / 256, level, 2), 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, add0, add1, g, out0,
+                                                             out1, level, c->log_n, c->d_mod, c->d_pinv[level]);
+  HE_HIP(hipGetLastError());
+  return HE_OK;
+}
+
+const uint64_t* find_key(Ctx* c, int32_t id) {
+  auto it = c->keys.find(norm_key_id(c, id));
+  return it == c->keys.end() ? nullptr : it->second;
+}
+
+int check_ct(const Ctx* c, const he_ct* x, const char* what);
+int check_out(const Ctx* c, const he_ct* x, int need_level);
+
+}  // namespace he
+
+using namespace he;
+
+extern "C" {
+
+int he_key_upload(he_ctx* h, int32_t key_id, const uint64_t* src, size_t bytes, int src_on_device, he_stream st) {
+  if (!h || !src) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  if (bytes != c->key_words * 8) return set_error(HE_EINVAL, "key size must be dnum*2*(L+K)*N*8 bytes");
+  hipStream_t s = (hipStream_t)st;
+  const int32_t id = norm_key_id(c, key_id);
+  uint64_t* d = nullptr;
+  auto it = c->keys.find(id);
+  if (it != c->keys.end()) {
+    d = it->second;
+  } else {
+    hipError_t e = hipMalloc((void**)&d, bytes);
+    if (e != hipSuccess) return set_error(HE_ENOMEM, std::string("key allocation: ") + hipGetErrorString(e));
+    c->keys[id] = d;
+  }
+  HE_HIP(hipMemcpyAsync(d, src, bytes, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
+  const int M = c->L + c->K;
+  const int limbs = c->dnum(c->L) * 2 * M;
+  k_to_mont<<<dim3(c->n / 256, limbs), 256, 0, s>>>(d, M, c->log_n, c->d_mod);
+  HE_HIP(hipGetLastError());
+  if (!src_on_device) HE_HIP(hipStreamSynchronize(s));  // host buffer may be freed after return
+  return HE_OK;
+}
+
+int he_key_evict(he_ctx* h, int32_t key_id) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  auto it = c->keys.find(norm_key_id(c, key_id));
+  if (it == c->keys.end()) return set_error(HE_ENOKEY, "key not resident");
+  HE_HIP(hipDeviceSynchronize());
+  HE_HIP(hipFree(it->second));
+  c->keys.erase(it);
+  return HE_OK;
+}
+
+int he_key_count(const he_ctx* h) { return h ? (int)h->c.keys.size() : 0; }
+size_t he_key_bytes(const he_ctx* h) { return h ? h->c.key_words * 8 : 0; }
+
+int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct* outs, he_stream st) {
+  if (!h || !r || !outs || n < 0) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in"))) return rc;
+  const int l = in->level;
+  const size_t N = c->n;
+  bool any = false;
+  for (int t = 0; t < n; t++) {
+    if ((rc = check_out(c, &outs[t], l))) return rc;
+    if (outs[t].data == in->data) return set_error(HE_EINVAL, "output aliases the input");
+    if (norm_key_id(c, r[t]) != 0) {
+      any = true;
+      if (!find_key(c, r[t])) return set_error(HE_ENOKEY, "rotation key " + std::to_string(r[t]) + " not resident");
+    }
+  }
+  hipStream_t s = (hipStream_t)st;
+  WS w = ws_layout(c, c->ws);
+  const uint64_t* c0 = in->data;
+  const uint64_t* c1 = in->data + (size_t)in->cap * N;
+  if (any && (rc = ks_modup(c, w, c1, l, s))) return rc;
+  for (int t = 0; t < n; t++) {
+    he_ct& o = outs[t];
+    uint64_t* o0 = o.data;
+    uint64_t* o1 = o.data + (size_t)o.cap * N;
+    if (norm_key_id(c, r[t]) == 0) {
+      HE_HIP(hipMemcpyAsync(o0, c0, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s));
+      HE_HIP(hipMemcpyAsync(o1, c1, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s));
+    } else {
+      if ((rc = ks_apply(c, w, l, find_key(c, r[t]), galois_elt(c, r[t]), c0, nullptr, o0, o1, s))) return rc;
+    }
+    o.level = l;
+    o.scale = in->scale;
+  }
+  return HE_OK;
+}
+
+int he_rotate(he_ctx* h, const he_ct* in, int32_t r, he_ct* out, he_stream st) {
+  return he_rotate_hoisted(h, in, &r, 1, out, st);
+}
+
+int he_relin(he_ctx* h, const uint64_t* d, int level, double scale, he_ct* out, he_stream st) {
+  if (!h || !d) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  int rc;
+  if (level < 1 || level > c->L) return set_error(HE_EINVAL, "bad level");
+  if ((rc = check_out(c, out, level))) return rc;
+  const uint64_t* key = find_key(c, HE_KEY_RELIN);
+  if (!key) return set_error(HE_ENOKEY, "relinearization key not resident");
+  hipStream_t s = (hipStream_t)st;
+  const size_t N = c->n;
+  WS w = ws_layout(c, c->ws);
+  const uint64_t* d0 = d;
+  const uint64_t* d1 = d + (size_t)level * N;
+  const uint64_t* d2 = d + 2 * (size_t)level * N;
+  if ((rc = ks_modup(c, w, d2, level, s))) return rc;
+  if ((rc = ks_apply(c, w, level, key, 1, d0, d1, out->data, out->data + (size_t)out->cap * N, s))) return rc;
+  out->level = level;
+  out->scale = scale;
+  return HE_OK;
+}
+
+}  // extern "C"
+
+namespace he {
+// (a0 b0, a0 b1 + a1 b0, a1 b1) into d [3][l][N]
+__global__ __launch_bounds__(256) void k_tensor(const uint64_t* __restrict__ a, size_t aps,
+                                                const uint64_t* __restrict__ b, size_t bps, uint64_t* __restrict__ d,
+                                                int level, int logn, const ModInfo* __restrict__ mods) {
+  const size_t n = (size_t)1 << logn;
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  const ModInfo mi = mods[i];
+  const uint64_t a0 = a[i * n + j], a1 = a[aps + i * n + j];
+  const uint64_t b0 = b[i * n + j], b1 = b[bps + i * n + j];
+  const uint64_t m0 = mul_mod(a0, b1, mi), m1 = mul_mod(a1, b0, mi);
+  d[i * n + j] = mul_mod(a0, b0, mi);
+  d[((size_t)level + i) * n + j] = add_mod(m0, m1, mi.q);
+  d[(2 * (size_t)level + i) * n + j] = mul_mod(a1, b1, mi);
+}
+}  // namespace he
+
+extern "C" int he_mul_relin(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* out, he_stream st) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, a, "a")) || (rc = check_ct(c, b, "b"))) return rc;
+  if (a->level != b->level) return set_error(HE_ELEVEL, "operands at different levels");
+  const int l = a->level;
+  if ((rc = check_out(c, out, l))) return rc;
+  const size_t N = c->n;
+  hipStream_t s = (hipStream_t)st;
+  WS w = ws_layout(c, c->ws);
+  k_tensor<<<dim3(N / 256, l), 256, 0, s>>>(a->data, a->cap * N, b->data, b->cap * N, w.t3, l, c->log_n, c->d_mod);
+  HE_HIP(hipGetLastError());
+  return he_relin(h, w.t3, l, a->scale * b->scale, out, st);
+}

@@ -1,0 +1,96 @@
+// Word-size modular arithmetic for primes q < 2^61 on gfx950.
+//
+// Integer-ALU only (no MFMA: a 64-bit modular product is not a floating-point
+// contraction).  Three reductions are used:
+//   * Shoup multiplication by a constant w with companion w' = floor(w 2^64 / q)
+//     (NTT twiddles, BConv input factors, q^{-1}, P^{-1});
+//   * Montgomery reduction of a 128-bit accumulator (key inner product, BConv
+//     sums) with constants stored premultiplied by 2^64 mod q;
+//   * Barrett reduction of a full 128-bit product for ct (.) pt products where
+//     neither operand is a precomputed constant.
+// All results are canonical residues in [0, q): any exact reduction yields the
+// same integers, which is what makes the GPU bit-identical to a plain `%`.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define HE_HD __host__ __device__ __forceinline__
+#else
+#define HE_HD inline  // plain host build (CPU emulation of kernel index math)
+#endif
+
+namespace he {
+
+HE_HD uint64_t mulhi(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+struct U128 {
+  uint64_t lo, hi;
+};
+
+HE_HD U128 mul_wide(uint64_t a, uint64_t b) { return U128{a * b, mulhi(a, b)}; }
+
+HE_HD void add_wide(U128& acc, U128 x) {
+  uint64_t lo = acc.lo + x.lo;
+  acc.hi += x.hi + (lo < x.lo ? 1 : 0);
+  acc.lo = lo;
+}
+
+HE_HD uint64_t add_mod(uint64_t a, uint64_t b, uint64_t q) {
+  uint64_t s = a + b;
+  return s >= q ? s - q : s;
+}
+HE_HD uint64_t sub_mod(uint64_t a, uint64_t b, uint64_t q) { return a >= b ? a - b : a + q - b; }
+HE_HD uint64_t neg_mod(uint64_t a, uint64_t q) { return a == 0 ? 0 : q - a; }
+
+// a * w mod q for any a < 2^64; result in [0, 2q).
+HE_HD uint64_t mul_shoup_lazy(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+  uint64_t t = mulhi(a, wp);
+  return a * w - t * q;
+}
+HE_HD uint64_t mul_shoup(uint64_t a, uint64_t w, uint64_t wp, uint64_t q) {
+  uint64_t r = mul_shoup_lazy(a, w, wp, q);
+  return r >= q ? r - q : r;
+}
+
+// Montgomery: REDC(T) = T * 2^-64 mod q for T < q 2^64, qinv = q^{-1} mod 2^64.
+HE_HD uint64_t mont_redc(U128 t, uint64_t q, uint64_t qinv) {
+  uint64_t m = t.lo * qinv;
+  uint64_t h = mulhi(m, q);
+  return t.hi >= h ? t.hi - h : t.hi + q - h;
+}
+
+// Barrett (HAC 14.42 in base 2): x < q^2 with q of k bits (2^(k-1) <= q < 2^k),
+// mu = floor(2^(2k) / q) < 2^(k+1).  Two conditional subtractions.
+HE_HD uint64_t barrett_reduce(U128 x, uint64_t q, uint64_t mu, int k) {
+  uint64_t q1 = (x.hi << (65 - k)) | (x.lo >> (k - 1));
+  uint64_t plo = q1 * mu, phi = mulhi(q1, mu);
+  uint64_t q3 = (phi << (63 - k)) | (plo >> (k + 1));
+  uint64_t r = x.lo - q3 * q;
+  if (r >= q) r -= q;
+  if (r >= q) r -= q;
+  return r;
+}
+
+// Per-modulus constants (device resident).
+struct ModInfo {
+  uint64_t q;
+  uint64_t qinv;      // q^{-1} mod 2^64 (Montgomery)
+  uint64_t r2;        // 2^128 mod q   (to Montgomery form: REDC(x * r2))
+  uint64_t mu;        // floor(2^(2k) / q) (Barrett)
+  uint64_t ninv, ninv_p;   // N^{-1} mod q and Shoup companion
+  int32_t k;          // bit length of q
+  int32_t pad;
+};
+
+HE_HD uint64_t mul_mod(uint64_t a, uint64_t b, const ModInfo& m) {
+  return barrett_reduce(mul_wide(a, b), m.q, m.mu, m.k);
+}
+
+}  // namespace he

@@ -1,0 +1,91 @@
+// NTT / iNTT kernels and launchers (see ntt_core.h for the decomposition).
+#include "internal.h"
+#include "ntt_core.h"
+
+namespace he {
+
+// grid: x = tile within limb, y = limb index in `map`, z = batch
+template <int LOGN, int PASS, bool INV>
+__global__ __launch_bounds__(256) void ntt_pass_kernel(uint64_t* __restrict__ data, size_t batch_stride, LimbMap map,
+                                                       const uint64_t* __restrict__ tw_all,
+                                                       const uint64_t* __restrict__ twp_all,
+                                                       const ModInfo* __restrict__ mods) {
+  using P = NttPass<LOGN, PASS, INV>;
+  __shared__ uint64_t lds[P::LDS_WORDS];
+  const int wg = blockIdx.x;
+  const int limb = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int m = map.mod[limb];
+  uint64_t* a = data + blockIdx.z * batch_stride + (size_t)map.pos[limb] * P::N;
+  const uint64_t* tw = tw_all + (size_t)m * P::N;
+  const uint64_t* twp = twp_all + (size_t)m * P::N;
+  const ModInfo mi = mods[m];
+  const uint64_t q = mi.q;
+  for (int e = tid; e < P::TILE; e += P::THREADS) {
+    int g, k;
+    P::tile_elem(e, g, k);
+    lds[P::lidx(g, k)] = a[P::gidx(wg, g, k)];
+  }
+  __syncthreads();
+  if (!INV) {
+    P::template round<P::R1>(lds, tid, wg, 0, tw, twp, q);
+    if (P::R2 > 0) {
+      __syncthreads();
+      P::template round<(P::R2 > 0 ? P::R2 : 1)>(lds, tid, wg, P::R1, tw, twp, q);
+    }
+  } else {
+    if (P::R2 > 0) {
+      P::template round<(P::R2 > 0 ? P::R2 : 1)>(lds, tid, wg, P::R1, tw, twp, q);
+      __syncthreads();
+    }
+    P::template round<P::R1>(lds, tid, wg, 0, tw, twp, q);
+  }
+  __syncthreads();
+  for (int e = tid; e < P::TILE; e += P::THREADS) {
+    int g, k;
+    P::tile_elem(e, g, k);
+    uint64_t v = lds[P::lidx(g, k)];
+    if (INV && PASS == 1) v = mul_shoup(v, mi.ninv, mi.ninv_p, q);
+    a[P::gidx(wg, g, k)] = v;
+  }
+}
+
+template <int LOGN>
+static int ntt_launch_n(Ctx* c, uint64_t* data, size_t batch_stride, int nbatch, const LimbMap& map, bool inverse,
+                        hipStream_t s) {
+  using P1 = NttPass<LOGN, 1, false>;
+  using P2 = NttPass<LOGN, 2, false>;
+  dim3 g1(P1::WG_PER_LIMB, map.n, nbatch), g2(P2::WG_PER_LIMB, map.n, nbatch);
+  if (!inverse) {
+    ntt_pass_kernel<LOGN, 1, false><<<g1, 256, 0, s>>>(data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
+    ntt_pass_kernel<LOGN, 2, false><<<g2, 256, 0, s>>>(data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
+  } else {
+    ntt_pass_kernel<LOGN, 2, true><<<g2, 256, 0, s>>>(data, batch_stride, map, c->d_itw, c->d_itwp, c->d_mod);
+    ntt_pass_kernel<LOGN, 1, true><<<g1, 256, 0, s>>>(data, batch_stride, map, c->d_itw, c->d_itwp, c->d_mod);
+  }
+  HE_HIP(hipGetLastError());
+  return HE_OK;
+}
+
+int ntt_launch(Ctx* c, uint64_t* data, size_t batch_stride, int nbatch, const LimbMap& map, bool inverse,
+               hipStream_t s) {
+  if (map.n <= 0 || nbatch <= 0) return HE_OK;
+  switch (c->log_n) {
+    case 12: return ntt_launch_n<12>(c, data, batch_stride, nbatch, map, inverse, s);
+    case 14: return ntt_launch_n<14>(c, data, batch_stride, nbatch, map, inverse, s);
+    case 16: return ntt_launch_n<16>(c, data, batch_stride, nbatch, map, inverse, s);
+  }
+  return set_error(HE_EINVAL, "unsupported ring degree");
+}
+
+}  // namespace he
+
+using namespace he;
+
+extern "C" int he_ntt(he_ctx* h, uint64_t* poly, int n_limbs, int first_limb, int inverse, he_stream stream) {
+  if (!h || !poly) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  if (n_limbs < 0 || first_limb < 0 || first_limb + n_limbs > c->L + c->K)
+    return set_error(HE_EINVAL, "limb range outside the moduli");
+  return ntt_launch(c, poly, 0, 1, range_map(0, n_limbs, first_limb), inverse != 0, (hipStream_t)stream);
+}

@@ -1,0 +1,123 @@
+// Negacyclic NTT over Z_q[X]/(X^N+1), N = 2^LOGN, in two LDS passes.
+//
+// Convention (the library's data format): a limb in NTT form stores at index j
+// the value a(psi^(2 brv(j) + 1)), psi the minimum primitive 2N-th root of
+// unity mod q.  The forward transform is the merged-twist Cooley-Tukey
+// recursion on natural-order input (stage s: 2^s blocks, butterfly distance
+// N / 2^(s+1), twiddle Psi[2^s + block] with Psi[k] = psi^brv(k)); the inverse
+// is the matching Gentleman-Sande recursion with Psi^{-1} and a final N^{-1}.
+//
+// MI355X mapping: one limb (up to 512 KiB) does not fit in LDS, so the
+// LOGN stages are split as L1 + L2.  Pass 1 runs stages 0..L1-1: these only
+// couple elements whose index differs by a multiple of N2 = 2^L2, i.e. the
+// N2 "columns" {c + k N2} are independent size-2^L1 transforms sharing the
+// twiddles Psi[2^s + block].  Pass 2 runs stages L1..LOGN-1 inside contiguous
+// "chunks" of N2 elements, chunk b using Psi[2^(L1+s) + b 2^s + block].
+// A workgroup stages TILE elements (several columns / chunks) in LDS; each
+// thread keeps a radix-2^r butterfly group (r <= 4 stages) in registers per
+// LDS round, so a pass costs one HBM read + write and ceil(L/4) LDS rounds.
+//
+// Everything here is __host__ __device__ so a workgroup can be emulated on the
+// CPU (round by round) with exactly the kernel's index arithmetic.
+#pragma once
+#include "modarith.h"
+
+namespace he {
+
+template <int LOGN, int PASS, bool INV>
+struct NttPass {
+  static constexpr int N = 1 << LOGN;
+  static constexpr int L1 = (LOGN + 1) / 2;
+  static constexpr int L2 = LOGN - L1;
+  static constexpr int N2 = 1 << L2;
+  static constexpr int LM = PASS == 1 ? L1 : L2;  // stages in this pass
+  static constexpr int M = 1 << LM;               // sub-transform size
+  static constexpr int TILE = N < 4096 ? N : 4096;  // elements per workgroup
+  static constexpr int G = TILE / M;              // sub-transforms per workgroup
+  static constexpr int WG_PER_LIMB = N / TILE;
+  static constexpr int THREADS = 256;
+  // pass-2 chunks get one pad word per 16 so that the stride-16 accesses of
+  // the last round fall in different LDS banks
+  static constexpr int CHUNK_WORDS = M + (M >> 4);
+  static constexpr int LDS_WORDS = PASS == 1 ? TILE : G * CHUNK_WORDS;
+
+  // global element index of (workgroup tile wg, sub-transform g, local index k)
+  HE_HD static int gidx(int wg, int g, int k) {
+    if (PASS == 1) return k * N2 + wg * G + g;
+    return (wg * G + g) * M + k;
+  }
+  HE_HD static int lidx(int g, int k) {
+    if (PASS == 1) return k * G + g;
+    return g * CHUNK_WORDS + k + (k >> 4);
+  }
+  // tile element e <-> (g, k) for the coalesced HBM <-> LDS copy
+  HE_HD static void tile_elem(int e, int& g, int& k) {
+    if (PASS == 1) { g = e % G; k = e / G; }
+    else { g = e / M; k = e % M; }
+  }
+
+  // One LDS round of R stages starting at local stage s0, for thread tid.
+  // R is a compile-time constant so the butterfly group stays in registers.
+  template <int R>
+  HE_HD static void round(uint64_t* lds, int tid, int wg, int s0, const uint64_t* tw,
+                          const uint64_t* twp, uint64_t q) {
+    constexpr int GPS = M >> R;  // groups per sub-transform
+    constexpr int TOTAL = G * GPS;
+    const int dmin = M >> (s0 + R);
+    const int span = M >> s0;
+    for (int gid = tid; gid < TOTAL; gid += THREADS) {
+      int g, gg;
+      if (PASS == 1) { g = gid % G; gg = gid / G; }
+      else { g = gid / GPS; gg = gid % GPS; }
+      const int lo = gg % dmin, hi = gg / dmin;
+      const int base = hi * span + lo;
+      uint64_t x[1 << R];
+#pragma unroll
+      for (int u = 0; u < (1 << R); u++) x[u] = lds[lidx(g, base + u * dmin)];
+      const int sub_off = PASS == 2 ? (wg * G + g) : 0;
+      if (!INV) {
+#pragma unroll
+        for (int ss = 0; ss < R; ss++) {
+          const int s = s0 + ss;
+          const int sg = (PASS == 2 ? L1 : 0) + s;
+          const int half = 1 << (R - 1 - ss);
+#pragma unroll
+          for (int u = 0; u < (1 << R); u++) {
+            if (u & half) continue;
+            const int iloc = (hi << ss) + (u >> (R - ss));
+            const int ti = (1 << sg) + (sub_off << s) + iloc;
+            const uint64_t y = mul_shoup(x[u + half], tw[ti], twp[ti], q);
+            const uint64_t a = x[u];
+            x[u] = add_mod(a, y, q);
+            x[u + half] = sub_mod(a, y, q);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int ss = R - 1; ss >= 0; ss--) {
+          const int s = s0 + ss;
+          const int sg = (PASS == 2 ? L1 : 0) + s;
+          const int half = 1 << (R - 1 - ss);
+#pragma unroll
+          for (int u = 0; u < (1 << R); u++) {
+            if (u & half) continue;
+            const int iloc = (hi << ss) + (u >> (R - ss));
+            const int ti = (1 << sg) + (sub_off << s) + iloc;
+            const uint64_t a = x[u], b = x[u + half];
+            x[u] = add_mod(a, b, q);
+            x[u + half] = mul_shoup(sub_mod(a, b, q), tw[ti], twp[ti], q);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < (1 << R); u++) lds[lidx(g, base + u * dmin)] = x[u];
+    }
+  }
+
+  // LM <= 8 stages per pass: a first round of R1 stages, then R2 = LM - R1.
+  static constexpr int R1 = LM >= 4 ? 4 : LM;
+  static constexpr int R2 = LM - R1;
+  static_assert(R2 <= 4, "at most two LDS rounds per pass");
+};
+
+}  // namespace he

@@ -1,0 +1,188 @@
+// Exact ring operations on ciphertexts: add / sub / pt-ct multiply(-accumulate),
+// rescale, level drop.  One thread per residue, limb-major coalesced access.
+#include "internal.h"
+
+namespace he {
+
+// out[k][i][j] = a[k][i][j] (+/-) b[k][i][j]   (k = poly, i = limb, j = coefficient)
+__global__ __launch_bounds__(256) void k_addsub(const uint64_t* __restrict__ a, size_t aps,
+                                                const uint64_t* __restrict__ b, size_t bps, uint64_t* out,
+                                                size_t ops, int npoly_b, int logn, const ModInfo* __restrict__ mods,
+                                                int sub) {
+  const size_t n = (size_t)1 << logn;
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, k = blockIdx.z;
+  const uint64_t q = mods[i].q;
+  const uint64_t x = a[k * aps + i * n + j];
+  uint64_t r = x;
+  if (k < npoly_b) {
+    const uint64_t y = b[k * bps + i * n + j];
+    r = sub ? sub_mod(x, y, q) : add_mod(x, y, q);
+  }
+  out[k * ops + i * n + j] = r;
+}
+
+// out[k][i][j] (+)= in[k][i][j] * pt[i][j]
+__global__ __launch_bounds__(256) void k_mul_plain(const uint64_t* in, size_t ips, const uint64_t* __restrict__ pt,
+                                                   uint64_t* out, size_t ops, int logn,
+                                                   const ModInfo* __restrict__ mods, int accumulate) {
+  const size_t n = (size_t)1 << logn;
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, k = blockIdx.z;
+  const ModInfo mi = mods[i];
+  uint64_t r = mul_mod(in[k * ips + i * n + j], pt[i * n + j], mi);
+  if (accumulate) r = add_mod(r, out[k * ops + i * n + j], mi.q);
+  out[k * ops + i * n + j] = r;
+}
+
+// R[k][i][j] = T[k][j] mod q_i  (top-limb residues broadcast to the lower limbs)
+__global__ __launch_bounds__(256) void k_bcast_reduce(const uint64_t* __restrict__ T, uint64_t* __restrict__ R,
+                                                      int nl, int logn, const ModInfo* __restrict__ mods) {
+  const size_t n = (size_t)1 << logn;
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, k = blockIdx.z;
+  R[((size_t)k * nl + i) * n + j] = reduce_word(T[k * n + j], mods[i]);
+}
+
+// out[k][i][j] = (in[k][i][j] - R[k][i][j]) * q_t^{-1} mod q_i
+__global__ __launch_bounds__(256) void k_rescale_combine(const uint64_t* in, size_t ips,
+                                                         const uint64_t* __restrict__ R, uint64_t* out, size_t ops,
+                                                         int nl, int logn, const ModInfo* __restrict__ mods,
+                                                         const uint64_t* __restrict__ tab) {
+  const size_t n = (size_t)1 << logn;
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, k = blockIdx.z;
+  const uint64_t v = rescale_elem(in[k * ips + i * n + j], R[((size_t)k * nl + i) * n + j], tab[i], tab[nl + i],
+                                  mods[i].q);
+  out[k * ops + i * n + j] = v;
+}
+
+int check_ct(const Ctx* c, const he_ct* x, const char* what) {
+  if (!x || !x->data) return set_error(HE_EINVAL, std::string(what) + ": null ciphertext");
+  if (x->level < 1 || x->level > c->L || x->cap < x->level)
+    return set_error(HE_EINVAL, std::string(what) + ": bad level/capacity");
+  return HE_OK;
+}
+
+// outputs: only the buffer and its capacity matter (level/scale are written)
+int check_out(const Ctx* c, const he_ct* x, int need_level) {
+  if (!x || !x->data) return set_error(HE_EINVAL, "out: null ciphertext");
+  if (x->cap < need_level || x->cap > c->L) return set_error(HE_EINVAL, "out: capacity too small");
+  return HE_OK;
+}
+
+static dim3 grid_for(const Ctx* c, int limbs, int polys) { return dim3(c->n / 256, limbs, polys); }
+
+}  // namespace he
+
+using namespace he;
+
+static int addsub(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* out, he_stream s, int sub) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, a, "a")) || (rc = check_ct(c, b, "b")) || (rc = check_out(c, out, a->level))) return rc;
+  if (a->level != b->level) return set_error(HE_ELEVEL, "operands at different levels");
+  if (a->scale != b->scale) return set_error(HE_ESCALE, "operands at different scales");
+  const size_t N = c->n;
+  k_addsub<<<grid_for(c, a->level, 2), 256, 0, (hipStream_t)s>>>(a->data, a->cap * N, b->data, b->cap * N,
+                                                                   out->data, out->cap * N, 2, c->log_n, c->d_mod,
+                                                                   sub);
+  HE_HIP(hipGetLastError());
+  out->level = a->level;
+  out->scale = a->scale;
+  return HE_OK;
+}
+
+extern "C" {
+
+int he_add(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* out, he_stream s) { return addsub(h, a, b, out, s, 0); }
+int he_sub(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* out, he_stream s) { return addsub(h, a, b, out, s, 1); }
+
+int he_add_plain(he_ctx* h, const he_ct* a, const he_pt* pt, he_ct* out, he_stream s) {
+  if (!h || !pt || !pt->data) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, a, "a")) || (rc = check_out(c, out, a->level))) return rc;
+  if (pt->level < a->level) return set_error(HE_ELEVEL, "plaintext has fewer limbs than the ciphertext");
+  if (pt->scale != a->scale) return set_error(HE_ESCALE, "plaintext scale differs");
+  const size_t N = c->n;
+  // poly 0 gets + pt; poly 1 is copied (npoly_b = 1)
+  k_addsub<<<grid_for(c, a->level, 2), 256, 0, (hipStream_t)s>>>(a->data, a->cap * N, pt->data, 0, out->data,
+                                                                   out->cap * N, 1, c->log_n, c->d_mod, 0);
+  HE_HIP(hipGetLastError());
+  out->level = a->level;
+  out->scale = a->scale;
+  return HE_OK;
+}
+
+int he_mul_plain(he_ctx* h, const he_ct* in, const he_pt* pt, he_ct* out, int accumulate, he_stream s) {
+  if (!h || !pt || !pt->data) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in")) || (rc = check_out(c, out, in->level))) return rc;
+  if (pt->level < in->level) return set_error(HE_ELEVEL, "plaintext has fewer limbs than the ciphertext");
+  const double sc = in->scale * pt->scale;
+  if (accumulate) {
+    if (out->data == in->data) return set_error(HE_EINVAL, "accumulate output aliases the input");
+    if (out->level != in->level) return set_error(HE_ELEVEL, "accumulator at a different level");
+    if (out->scale != sc) return set_error(HE_ESCALE, "accumulator scale differs");
+  }
+  const size_t N = c->n;
+  k_mul_plain<<<grid_for(c, in->level, 2), 256, 0, (hipStream_t)s>>>(in->data, in->cap * N, pt->data, out->data,
+                                                                      out->cap * N, c->log_n, c->d_mod,
+                                                                      accumulate ? 1 : 0);
+  HE_HIP(hipGetLastError());
+  out->level = in->level;
+  out->scale = sc;
+  return HE_OK;
+}
+
+int he_rescale(he_ctx* h, const he_ct* in, he_ct* out, he_stream st) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in"))) return rc;
+  const int l = in->level, t = l - 1;
+  if (l < 2) return set_error(HE_ELEVEL, "cannot rescale at level 1");
+  if ((rc = check_out(c, out, t))) return rc;
+  if (out->data == in->data && out->cap != in->cap) return set_error(HE_EINVAL, "in-place rescale needs equal capacity");
+  hipStream_t s = (hipStream_t)st;
+  const size_t N = c->n;
+  WS w = ws_layout(c, c->ws);
+  uint64_t* T = w.y;   // [2][N] top limbs -> coefficient form
+  uint64_t* R = w.rs;  // [2][t][N]
+  for (int k = 0; k < 2; k++)
+    HE_HIP(hipMemcpyAsync(T + k * N, in->data + (k * (size_t)in->cap + t) * N, N * 8, hipMemcpyDeviceToDevice, s));
+  if ((rc = ntt_launch(c, T, N, 2, range_map(0, 1, t), true, s))) return rc;
+  k_bcast_reduce<<<grid_for(c, t, 2), 256, 0, s>>>(T, R, t, c->log_n, c->d_mod);
+  HE_HIP(hipGetLastError());
+  if ((rc = ntt_launch(c, R, (size_t)t * N, 2, range_map(0, t, 0), false, s))) return rc;
+  k_rescale_combine<<<grid_for(c, t, 2), 256, 0, s>>>(in->data, in->cap * N, R, out->data, out->cap * N, t, c->log_n,
+                                                      c->d_mod, c->d_rescale[l]);
+  HE_HIP(hipGetLastError());
+  out->level = t;
+  out->scale = in->scale / (double)c->mod[t];
+  return HE_OK;
+}
+
+int he_drop_level(he_ctx* h, const he_ct* in, int level, he_ct* out, he_stream st) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in"))) return rc;
+  if (level < 1 || level > in->level) return set_error(HE_ELEVEL, "target level out of range");
+  if ((rc = check_out(c, out, level))) return rc;
+  const size_t N = c->n;
+  if (out->data != in->data || out->cap != in->cap) {
+    if (out->data == in->data) return set_error(HE_EINVAL, "in-place drop needs equal capacity");
+    for (int k = 0; k < 2; k++)
+      HE_HIP(hipMemcpyAsync(out->data + k * (size_t)out->cap * N, in->data + k * (size_t)in->cap * N,
+                            (size_t)level * N * 8, hipMemcpyDeviceToDevice, (hipStream_t)st));
+  }
+  out->level = level;
+  out->scale = in->scale;
+  return HE_OK;
+}
+
+}  // extern "C"

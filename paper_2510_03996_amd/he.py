@@ -1,0 +1,297 @@
+"""Python binding of the C ABI in ``include/he.h`` (argument marshalling only).
+
+Every operation runs in the gfx950 HIP library ``libfheon_hip.so``; this
+module only turns torch tensors (device memory) and the current HIP stream
+into the raw pointers and sizes the C functions take.  There is no CPU
+fallback: if the library cannot be loaded, every call raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfheon_hip.so")
+
+HE_OK = 0
+ERRORS = {
+    -1: "HE_EINVAL", -2: "HE_ENOKEY", -3: "HE_ELEVEL", -4: "HE_ESCALE",
+    -5: "HE_ENOMEM", -6: "HE_EHIP", -7: "HE_EUNSUPPORTED",
+}
+KEY_RELIN = 0x7FFFFFFF
+MAX_Q, MAX_P = 60, 16
+
+
+class HEError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+        self.name = ERRORS.get(code, "?")
+
+
+class he_params(ctypes.Structure):
+    _fields_ = [
+        ("log_n", ctypes.c_int32), ("n_q", ctypes.c_int32), ("n_p", ctypes.c_int32), ("alpha", ctypes.c_int32),
+        ("q_bits", ctypes.c_int32 * MAX_Q), ("p_bits", ctypes.c_int32 * MAX_P),
+        ("q", ctypes.c_uint64 * MAX_Q), ("p", ctypes.c_uint64 * MAX_P),
+    ]
+
+
+class he_ct(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("level", ctypes.c_int32), ("cap", ctypes.c_int32),
+                ("scale", ctypes.c_double)]
+
+
+class he_pt(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("level", ctypes.c_int32), ("scale", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libfheon_hip.so is not built; run python -m paper_2510_03996_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, c_int, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int, ctypes.c_size_t
+        P = ctypes.POINTER
+        sig = {
+            "he_ctx_create": [P(he_params), c_int, P(vp)],
+            "he_ctx_destroy": [vp],
+            "he_ctx_moduli": [vp, P(ctypes.c_uint64), c_int],
+            "he_ctx_info": [vp, P(i32), P(i32), P(i32), P(i32)],
+            "he_key_upload": [vp, i32, vp, sz, c_int, vp],
+            "he_key_evict": [vp, i32],
+            "he_key_count": [vp],
+            "he_ntt": [vp, vp, c_int, c_int, c_int, vp],
+            "he_rotate": [vp, P(he_ct), i32, P(he_ct), vp],
+            "he_rotate_hoisted": [vp, P(he_ct), P(i32), c_int, P(he_ct), vp],
+            "he_mul_plain": [vp, P(he_ct), P(he_pt), P(he_ct), c_int, vp],
+            "he_add": [vp, P(he_ct), P(he_ct), P(he_ct), vp],
+            "he_sub": [vp, P(he_ct), P(he_ct), P(he_ct), vp],
+            "he_add_plain": [vp, P(he_ct), P(he_pt), P(he_ct), vp],
+            "he_rescale": [vp, P(he_ct), P(he_ct), vp],
+            "he_drop_level": [vp, P(he_ct), c_int, P(he_ct), vp],
+            "he_mul_relin": [vp, P(he_ct), P(he_ct), P(he_ct), vp],
+            "he_relin": [vp, vp, c_int, ctypes.c_double, P(he_ct), vp],
+        }
+        for name, args in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = c_int
+        L.he_last_error.restype = ctypes.c_char_p
+        L.he_last_error.argtypes = []
+        L.he_key_bytes.restype = ctypes.c_size_t
+        L.he_key_bytes.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise HEError(rc, lib().he_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    assert t.is_cuda and t.is_contiguous() and t.dtype == torch.int64
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Ciphertext:
+    """A device ciphertext: int64 tensor [2][cap][N] holding uint64 residues."""
+
+    def __init__(self, data, level, scale):
+        self.data = data
+        self.level = int(level)
+        self.scale = float(scale)
+
+    @property
+    def cap(self):
+        return self.data.shape[1]
+
+    def c(self):
+        return he_ct(ctypes.c_void_p(self.data.data_ptr()), self.level, self.cap, self.scale)
+
+    def update(self, s):
+        self.level, self.scale = s.level, s.scale
+
+    def numpy(self):
+        """uint64 [2][level][N] copy on the host."""
+        return self.data[:, : self.level].cpu().numpy().view(np.uint64)
+
+
+class Plaintext:
+    def __init__(self, data, scale):
+        self.data = data  # int64 [level][N]
+        self.scale = float(scale)
+
+    @property
+    def level(self):
+        return self.data.shape[0]
+
+    def c(self):
+        return he_pt(ctypes.c_void_p(self.data.data_ptr()), self.level, self.scale)
+
+
+def to_device(arr_u64, device="cuda"):
+    """uint64 numpy array -> int64 device tensor with the same bits."""
+    a = np.ascontiguousarray(arr_u64, dtype=np.uint64)
+    return torch.from_numpy(a.view(np.int64)).to(device)
+
+
+class Context:
+    """A library context (moduli, tables, resident keys, workspace)."""
+
+    def __init__(self, log_n, q_bits, p_bits, alpha, device=0, primes=None):
+        p = he_params()
+        p.log_n, p.n_q, p.n_p, p.alpha = log_n, len(q_bits), len(p_bits), alpha
+        for i, b in enumerate(q_bits):
+            p.q_bits[i] = b
+        for i, b in enumerate(p_bits):
+            p.p_bits[i] = b
+        if primes is not None:
+            for i, v in enumerate(primes[0]):
+                p.q[i] = v
+            for i, v in enumerate(primes[1]):
+                p.p[i] = v
+        h = ctypes.c_void_p()
+        _check(lib().he_ctx_create(ctypes.byref(p), device, ctypes.byref(h)))
+        self.h = h
+        self.log_n, self.n = log_n, 1 << log_n
+        self.L, self.K, self.alpha = len(q_bits), len(p_bits), alpha
+        self.device = torch.device("cuda", device)
+        buf = (ctypes.c_uint64 * (self.L + self.K))()
+        _check(lib().he_ctx_moduli(h, buf, self.L + self.K))
+        self.moduli = [int(x) for x in buf]
+
+    def close(self):
+        if self.h:
+            torch.cuda.synchronize()
+            lib().he_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def dnum(self):
+        return -(-self.L // self.alpha)
+
+    def key_bytes(self):
+        return lib().he_key_bytes(self.h)
+
+    # ---- buffers
+    def new_ct(self, cap=None):
+        cap = cap or self.L
+        return Ciphertext(torch.empty((2, cap, self.n), dtype=torch.int64, device=self.device), 0, 0.0)
+
+    def ct_from_numpy(self, data_u64, scale, cap=None):
+        d = np.asarray(data_u64, dtype=np.uint64)
+        level = d.shape[1]
+        cap = cap or level
+        t = torch.zeros((2, cap, self.n), dtype=torch.int64, device=self.device)
+        t[:, :level] = to_device(d, self.device)
+        return Ciphertext(t, level, scale)
+
+    def pt_from_numpy(self, data_u64, scale):
+        return Plaintext(to_device(data_u64, self.device), scale)
+
+    # ---- keys
+    def key_upload(self, key_id, key, stream=None):
+        if isinstance(key, np.ndarray):
+            k = np.ascontiguousarray(key, dtype=np.uint64)
+            _check(lib().he_key_upload(self.h, key_id, ctypes.c_void_p(k.ctypes.data), k.nbytes, 0, _stream(stream)))
+        else:
+            _check(lib().he_key_upload(self.h, key_id, _ptr(key), key.numel() * 8, 1, _stream(stream)))
+
+    def key_evict(self, key_id):
+        _check(lib().he_key_evict(self.h, key_id))
+
+    def key_count(self):
+        return lib().he_key_count(self.h)
+
+    # ---- ops
+    def ntt(self, poly, first_limb=0, inverse=False, stream=None):
+        _check(lib().he_ntt(self.h, _ptr(poly), poly.shape[0], first_limb, 1 if inverse else 0, _stream(stream)))
+
+    def rotate(self, ct, r, out=None, stream=None):
+        out = out or self.new_ct(ct.level)
+        a, o = ct.c(), out.c()
+        _check(lib().he_rotate(self.h, ctypes.byref(a), int(r), ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    def rotate_hoisted(self, ct, rs, outs=None, stream=None):
+        outs = outs or [self.new_ct(ct.level) for _ in rs]
+        a = ct.c()
+        arr = (he_ct * len(rs))(*[o.c() for o in outs])
+        rr = (ctypes.c_int32 * len(rs))(*[int(r) for r in rs])
+        _check(lib().he_rotate_hoisted(self.h, ctypes.byref(a), rr, len(rs), arr, _stream(stream)))
+        for o, s in zip(outs, arr):
+            o.update(s)
+        return outs
+
+    def mul_plain(self, ct, pt, out=None, accumulate=False, stream=None):
+        out = out or self.new_ct(ct.level)
+        a, p, o = ct.c(), pt.c(), out.c()
+        _check(lib().he_mul_plain(self.h, ctypes.byref(a), ctypes.byref(p), ctypes.byref(o), int(accumulate),
+                                  _stream(stream)))
+        out.update(o)
+        return out
+
+    def _binary(self, fn, a, b, out, stream):
+        out = out or self.new_ct(a.level)
+        x, y, o = a.c(), b.c(), out.c()
+        _check(fn(self.h, ctypes.byref(x), ctypes.byref(y), ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    def add(self, a, b, out=None, stream=None):
+        return self._binary(lib().he_add, a, b, out, stream)
+
+    def sub(self, a, b, out=None, stream=None):
+        return self._binary(lib().he_sub, a, b, out, stream)
+
+    def mul_relin(self, a, b, out=None, stream=None):
+        return self._binary(lib().he_mul_relin, a, b, out, stream)
+
+    def add_plain(self, a, pt, out=None, stream=None):
+        out = out or self.new_ct(a.level)
+        x, p, o = a.c(), pt.c(), out.c()
+        _check(lib().he_add_plain(self.h, ctypes.byref(x), ctypes.byref(p), ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    def rescale(self, ct, out=None, stream=None):
+        out = out or self.new_ct(ct.cap)
+        a, o = ct.c(), out.c()
+        _check(lib().he_rescale(self.h, ctypes.byref(a), ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    def drop_level(self, ct, level, out=None, stream=None):
+        out = out or self.new_ct(ct.cap)
+        a, o = ct.c(), out.c()
+        _check(lib().he_drop_level(self.h, ctypes.byref(a), level, ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    def relin(self, d, level, scale, out=None, stream=None):
+        out = out or self.new_ct(level)
+        o = out.c()
+        _check(lib().he_relin(self.h, _ptr(d), level, scale, ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out

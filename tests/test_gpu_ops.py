@@ -1,0 +1,187 @@
+"""GPU vs oracle parity for the CKKS ops, bit-exact on every limb (needs MI355X)."""
+import numpy as np
+import pytest
+
+from oracle import _lib as OC
+from oracle import ckks
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+CONFIGS = ["config0", "config1", "config2"]
+
+
+@pytest.fixture(scope="module")
+def gctx():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            cache[name] = H.gpu_ctx(name)
+        return cache[name]
+
+    yield get
+    for c in cache.values():
+        c.close()
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_moduli_match_oracle(gctx, name):
+    octx, _, _ = H.oracle_ctx(name)
+    assert gctx(name).moduli == octx.pr.moduli
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_ntt_forward_inverse(gctx, name):
+    import synth
+    from paper_2510_03996_amd import he
+
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    pr = octx.pr
+    a = synth.residues(1, pr.moduli, pr.n)
+    t = he.to_device(a)
+    g.ntt(t, 0, inverse=False)
+    want = OC.ntt(a, pr.moduli, pr.psi)
+    H.assert_limbs_equal(t.cpu().numpy().view(np.uint64), want, "forward NTT")
+    g.ntt(t, 0, inverse=True)
+    H.assert_limbs_equal(t.cpu().numpy().view(np.uint64), a, "NTT round trip")
+    # a sub-range of limbs, special primes included
+    b = a[pr.L - 1:]
+    tb = he.to_device(b)
+    g.ntt(tb, pr.L - 1, inverse=True)
+    H.assert_limbs_equal(tb.cpu().numpy().view(np.uint64), OC.ntt(b, pr.moduli[pr.L - 1:], pr.psi[pr.L - 1:], True),
+                         "inverse NTT on q_top..p_K")
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_pointwise_and_rescale(gctx, name):
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    pr = octx.pr
+    _, a = H.encrypt_slots(name, 1, enc_id=0)
+    _, b = H.encrypt_slots(name, 2, enc_id=1)
+    _, pt = H.encode_slots(name, 3, pr.L)
+    ga, gb = g.ct_from_numpy(a.data, a.scale), g.ct_from_numpy(b.data, b.scale)
+    gpt = g.pt_from_numpy(pt.data, pt.scale)
+    H.assert_limbs_equal(g.add(ga, gb).numpy(), octx.add(a, b).data, "add")
+    H.assert_limbs_equal(g.sub(ga, gb).numpy(), octx.sub(a, b).data, "sub")
+    want_ap = octx.add_plain(a, ckks.Plaintext(pt.data, a.scale))
+    H.assert_limbs_equal(g.add_plain(ga, g.pt_from_numpy(pt.data, a.scale)).numpy(), want_ap.data, "add_plain")
+    m = g.mul_plain(ga, gpt)
+    om = octx.mul_plain(a, pt)
+    H.assert_limbs_equal(m.numpy(), om.data, "mul_plain")
+    assert m.scale == om.scale
+    acc = g.mul_plain(ga, gpt)
+    g.mul_plain(gb, gpt, out=acc, accumulate=True)
+    H.assert_limbs_equal(acc.numpy(), octx.add(om, octx.mul_plain(b, pt)).data, "mul_plain accumulate")
+    r = g.rescale(m)
+    orr = octx.rescale(om)
+    H.assert_limbs_equal(r.numpy(), orr.data, "rescale")
+    assert r.level == orr.level and r.scale == orr.scale
+    # in-place rescale
+    g.rescale(m, out=m)
+    H.assert_limbs_equal(m.numpy(), orr.data, "rescale in place")
+    d = g.drop_level(ga, max(1, pr.L - 2))
+    H.assert_limbs_equal(d.numpy(), octx.drop_level(a, max(1, pr.L - 2)).data, "drop_level")
+
+
+ROTS = {"config0": [1, -1, 7, -512], "config1": [1, -28, 576, -3], "config2": [1, -1, 32, -1024]}
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_rotate_single(gctx, name):
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    r = ROTS[name][0]
+    key = H.oracle_key(name, r)
+    g.key_upload(r, key)
+    _, a = H.encrypt_slots(name, 11)
+    got = g.rotate(g.ct_from_numpy(a.data, a.scale), r)
+    want = octx.rotate(a, r, {r: key})
+    H.assert_limbs_equal(got.numpy(), want.data, "rotate %d" % r)
+    assert got.scale == want.scale and got.level == want.level
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_rotate_hoisted(gctx, name):
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    rs = ROTS[name] + [0]
+    keys = H.oracle_keys(name, ROTS[name])
+    for r, k in keys.items():
+        g.key_upload(r, k)
+    _, a = H.encrypt_slots(name, 12)
+    got = g.rotate_hoisted(g.ct_from_numpy(a.data, a.scale), rs)
+    want = octx.rotate_hoisted(a, rs, keys)
+    for r, x, y in zip(rs, got, want):
+        H.assert_limbs_equal(x.numpy(), y.data, "hoisted rotation %d" % r)
+
+
+@pytest.mark.parametrize("name,level", [("config2", 13), ("config2", 8), ("config1", 5), ("config1", 2), ("config0", 2)])
+def test_rotate_lower_levels(gctx, name, level):
+    """Partial last digit and restricted keys at lower levels."""
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    r = ROTS[name][1]
+    key = H.oracle_key(name, r)
+    g.key_upload(r, key)
+    _, a = H.encrypt_slots(name, 13, level=level)
+    got = g.rotate(g.ct_from_numpy(a.data, a.scale, cap=octx.pr.L), r)
+    H.assert_limbs_equal(got.numpy(), octx.rotate(a, r, {r: key}).data, "rotate at level %d" % level)
+
+
+@pytest.mark.parametrize("name", CONFIGS)
+def test_mul_relin(gctx, name):
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    rk = H.oracle_key(name, "relin")
+    from paper_2510_03996_amd import he
+
+    g.key_upload(he.KEY_RELIN, rk)
+    _, a = H.encrypt_slots(name, 21, enc_id=0)
+    _, b = H.encrypt_slots(name, 22, enc_id=1)
+    got = g.mul_relin(g.ct_from_numpy(a.data, a.scale), g.ct_from_numpy(b.data, b.scale))
+    want = octx.mul_relin(a, b, rk)
+    H.assert_limbs_equal(got.numpy(), want.data, "mul_relin")
+    assert got.scale == want.scale
+
+
+def test_decrypted_rotation_semantics(gctx):
+    """Decrypting the GPU's rotation gives roll(v, -r) (paper's Rot direction)."""
+    name = "config1"
+    g = gctx(name)
+    octx, sk, _ = H.oracle_ctx(name)
+    r = ROTS[name][1]
+    g.key_upload(r, H.oracle_key(name, r))
+    v, a = H.encrypt_slots(name, 31)
+    got = g.rotate(g.ct_from_numpy(a.data, a.scale), r)
+    dec = octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale))
+    assert np.max(np.abs(dec - np.roll(v, -r))) < 1e-5
+
+
+def test_error_codes(gctx):
+    from paper_2510_03996_amd import he
+
+    name = "config0"
+    g = gctx(name)
+    _, a = H.encrypt_slots(name, 41)
+    ga = g.ct_from_numpy(a.data, a.scale)
+    with pytest.raises(he.HEError) as e:
+        g.rotate(ga, 3)  # key for 3 never uploaded
+    assert e.value.name == "HE_ENOKEY"
+    low = g.drop_level(ga, 2)
+    with pytest.raises(he.HEError) as e:
+        g.add(ga, low)
+    assert e.value.name == "HE_ELEVEL"
+    ga2 = g.ct_from_numpy(a.data, a.scale * 2)
+    with pytest.raises(he.HEError) as e:
+        g.add(ga, ga2)
+    assert e.value.name == "HE_ESCALE"
+    one = g.drop_level(ga, 1)
+    with pytest.raises(he.HEError) as e:
+        g.rescale(one)
+    assert e.value.name == "HE_ELEVEL"
+    with pytest.raises(he.HEError) as e:
+        g.rotate_hoisted(ga, [1], outs=[ga])
+    assert e.value.name == "HE_EINVAL"

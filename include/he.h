@@ -163,6 +163,18 @@ int he_mul_relin(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct* out, he_str
 /* Relinearize a 3-part ciphertext d ([3][level][N], device) into out. */
 int he_relin(he_ctx* ctx, const uint64_t* d, int level, double scale, he_ct* out, he_stream stream);
 
+/* ------------------------------------------------------------ measurement
+ * Per-kernel timing: after he_profile_begin, every kernel launch of this
+ * context is bracketed by a HIP event pair on its stream.  he_profile_end
+ * synchronises those events and writes a JSON object
+ *   {"<kernel>": {"launches": n, "ms": total, "bytes": B, "modmul": M}, ...}
+ * to `out` (B = algorithmic HBM bytes the launches must move, M = modular
+ * products they compute), returning its length or HE_EINVAL if cap is too
+ * small.  Profiling adds an event record per launch; leave it off when timing
+ * end-to-end throughput. */
+int he_profile_begin(he_ctx* ctx);
+int he_profile_end(he_ctx* ctx, char* out, size_t cap);
+
 #ifdef __cplusplus
 }
 #endif

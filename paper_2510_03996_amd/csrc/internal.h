@@ -23,6 +23,14 @@ struct BConvTab {
   uint64_t* d = nullptr;
 };
 
+// Optional per-kernel timing: a HIP event pair around each launch on its own
+// stream, plus the algorithmic bytes and modular products that launch moves.
+struct ProfRec {
+  const char* name;
+  hipEvent_t a, b;
+  double bytes, modmul;
+};
+
 struct Ctx {
   int device = 0;
   int log_n = 0, n = 0, L = 0, K = 0, alpha = 0;
@@ -45,9 +53,33 @@ struct Ctx {
   uint64_t* ws = nullptr;
   size_t ws_words = 0;
   std::vector<void*> allocs;
+  bool prof_on = false;
+  std::vector<ProfRec> prof;
 
   int dnum(int level) const { return (level + alpha - 1) / alpha; }
   size_t limb_words() const { return (size_t)n; }
+};
+
+// RAII timing scope around one kernel launch (no-op unless profiling is on)
+struct ProfScope {
+  Ctx* c;
+  hipStream_t s;
+  ProfRec r;
+  bool on;
+  ProfScope(Ctx* c_, const char* name, hipStream_t s_, double bytes, double modmul) : c(c_), s(s_), on(c_->prof_on) {
+    if (!on) return;
+    r.name = name;
+    r.bytes = bytes;
+    r.modmul = modmul;
+    hipEventCreate(&r.a);
+    hipEventCreate(&r.b);
+    hipEventRecord(r.a, s);
+  }
+  ~ProfScope() {
+    if (!on) return;
+    hipEventRecord(r.b, s);
+    c->prof.push_back(r);
+  }
 };
 
 // thread-local error reporting

@@ -78,7 +78,10 @@ int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) 
     const int lo = j * c->alpha;
     HE_HIP(hipMemcpyAsync(ext + (size_t)lo * N, c1 + (size_t)lo * N, (size_t)t.nin * N * 8,
                           hipMemcpyDeviceToDevice, s));
-    k_bconv<<<dim3(N / 256, 1), 256, 0, s>>>(w.coeff, 0, ext, 0, t.in, t.out, t.d, c->d_mod, c->log_n);
+    {
+      ProfScope ps(c, "bconv_modup", s, 8.0 * N * (t.nin + t.nout), (double)N * t.nin * (1 + t.nout));
+      k_bconv<<<dim3(N / 256, 1), 256, 0, s>>>(w.coeff, 0, ext, 0, t.in, t.out, t.d, c->d_mod, c->log_n);
+    }
     HE_HIP(hipGetLastError());
     if ((rc = ntt_launch(c, ext, 0, 1, t.out, false, s))) return rc;
   }
@@ -92,18 +95,29 @@ int ks_apply(Ctx* c, const WS& w, int level, const uint64_t* key, uint32_t g, co
   const size_t E = (size_t)(level + K);
   const size_t kps = (size_t)(L + K) * N;  // key poly stride
   int rc;
-  k_ip<<<dim3(N / 256, E), 256, 0, s>>>(w.ext, E * N, c->dnum(level), key, 2 * kps, kps, level, L, g, c->log_n,
-                                        c->d_mod, w.u, E * N);
+  const int dn = c->dnum(level);
+  {
+    ProfScope ps(c, "ks_inner_product", s, 8.0 * N * E * (3.0 * dn + 2), 2.0 * dn * E * N);
+    k_ip<<<dim3(N / 256, E), 256, 0, s>>>(w.ext, E * N, dn, key, 2 * kps, kps, level, L, g, c->log_n, c->d_mod, w.u,
+                                          E * N);
+  }
   HE_HIP(hipGetLastError());
   // ModDown of u0 and u1: P limbs to coefficient form, convert to Q_l, back to NTT form
   if ((rc = ntt_launch(c, w.u, E * N, 2, range_map(level, K, L), true, s))) return rc;
   const BConvTab& t = c->moddown[level];
-  k_bconv<<<dim3(N / 256, 2), 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, t.in, t.out, t.d, c->d_mod,
-                                           c->log_n);
+  {
+    ProfScope ps(c, "bconv_moddown", s, 16.0 * N * (t.nin + t.nout), 2.0 * N * t.nin * (1 + t.nout));
+    k_bconv<<<dim3(N / 256, 2), 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, t.in, t.out, t.d, c->d_mod,
+                                             c->log_n);
+  }
   HE_HIP(hipGetLastError());
   if ((rc = ntt_launch(c, w.y, (size_t)level * N, 2, range_map(0, level, 0), false, s))) return rc;
-  k_moddown_combine<<<dim3(N / 256, level, 2), 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, add0, add1, g, out0,
-                                                             out1, level, c->log_n, c->d_mod, c->d_pinv[level]);
+  {
+    ProfScope ps(c, "moddown_combine", s, 8.0 * N * level * (6 + (add0 ? 1 : 0) + (add1 ? 1 : 0)), 2.0 * N * level);
+    k_moddown_combine<<<dim3(N / 256, level, 2), 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, add0, add1, g,
+                                                               out0, out1, level, c->log_n, c->d_mod,
+                                                               c->d_pinv[level]);
+  }
   HE_HIP(hipGetLastError());
   return HE_OK;
 }
@@ -253,7 +267,10 @@ extern "C" int he_mul_relin(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* ou
   const size_t N = c->n;
   hipStream_t s = (hipStream_t)st;
   WS w = ws_layout(c, c->ws);
-  k_tensor<<<dim3(N / 256, l), 256, 0, s>>>(a->data, a->cap * N, b->data, b->cap * N, w.t3, l, c->log_n, c->d_mod);
+  {
+    ProfScope ps(c, "tensor", s, 8.0 * N * l * 7, 4.0 * N * l);
+    k_tensor<<<dim3(N / 256, l), 256, 0, s>>>(a->data, a->cap * N, b->data, b->cap * N, w.t3, l, c->log_n, c->d_mod);
+  }
   HE_HIP(hipGetLastError());
   return he_relin(h, w.t3, l, a->scale * b->scale, out, st);
 }

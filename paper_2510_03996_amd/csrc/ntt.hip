@@ -56,11 +56,22 @@ static int ntt_launch_n(Ctx* c, uint64_t* data, size_t batch_stride, int nbatch,
   using P1 = NttPass<LOGN, 1, false>;
   using P2 = NttPass<LOGN, 2, false>;
   dim3 g1(P1::WG_PER_LIMB, map.n, nbatch), g2(P2::WG_PER_LIMB, map.n, nbatch);
+  const double limbs = (double)map.n * nbatch, N = (double)P1::N;
+  const double bytes = 16.0 * N * limbs;  // one read + one write of every residue per pass
+  const double mm1 = N / 2 * P1::LM * limbs, mm2 = N / 2 * P2::LM * limbs;
   if (!inverse) {
-    ntt_pass_kernel<LOGN, 1, false><<<g1, 256, 0, s>>>(data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
+    {
+      ProfScope ps(c, "ntt_fwd_pass1", s, bytes, mm1);
+      ntt_pass_kernel<LOGN, 1, false><<<g1, 256, 0, s>>>(data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
+    }
+    ProfScope ps(c, "ntt_fwd_pass2", s, bytes, mm2);
     ntt_pass_kernel<LOGN, 2, false><<<g2, 256, 0, s>>>(data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
   } else {
-    ntt_pass_kernel<LOGN, 2, true><<<g2, 256, 0, s>>>(data, batch_stride, map, c->d_itw, c->d_itwp, c->d_mod);
+    {
+      ProfScope ps(c, "ntt_inv_pass2", s, bytes, mm2);
+      ntt_pass_kernel<LOGN, 2, true><<<g2, 256, 0, s>>>(data, batch_stride, map, c->d_itw, c->d_itwp, c->d_mod);
+    }
+    ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs);
     ntt_pass_kernel<LOGN, 1, true><<<g1, 256, 0, s>>>(data, batch_stride, map, c->d_itw, c->d_itwp, c->d_mod);
   }
   HE_HIP(hipGetLastError());

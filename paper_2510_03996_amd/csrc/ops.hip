@@ -85,6 +85,7 @@ static int addsub(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* out, he_stre
   if (a->level != b->level) return set_error(HE_ELEVEL, "operands at different levels");
   if (a->scale != b->scale) return set_error(HE_ESCALE, "operands at different scales");
   const size_t N = c->n;
+  ProfScope ps(c, "add_sub", (hipStream_t)s, 48.0 * N * a->level, 0);
   k_addsub<<<grid_for(c, a->level, 2), 256, 0, (hipStream_t)s>>>(a->data, a->cap * N, b->data, b->cap * N,
                                                                    out->data, out->cap * N, 2, c->log_n, c->d_mod,
                                                                    sub);
@@ -129,6 +130,7 @@ int he_mul_plain(he_ctx* h, const he_ct* in, const he_pt* pt, he_ct* out, int ac
     if (out->scale != sc) return set_error(HE_ESCALE, "accumulator scale differs");
   }
   const size_t N = c->n;
+  ProfScope ps(c, "mul_plain", (hipStream_t)s, 8.0 * N * in->level * (accumulate ? 7 : 5), 2.0 * N * in->level);
   k_mul_plain<<<grid_for(c, in->level, 2), 256, 0, (hipStream_t)s>>>(in->data, in->cap * N, pt->data, out->data,
                                                                       out->cap * N, c->log_n, c->d_mod,
                                                                       accumulate ? 1 : 0);
@@ -158,6 +160,7 @@ int he_rescale(he_ctx* h, const he_ct* in, he_ct* out, he_stream st) {
   k_bcast_reduce<<<grid_for(c, t, 2), 256, 0, s>>>(T, R, t, c->log_n, c->d_mod);
   HE_HIP(hipGetLastError());
   if ((rc = ntt_launch(c, R, (size_t)t * N, 2, range_map(0, t, 0), false, s))) return rc;
+  ProfScope ps(c, "rescale_combine", s, 8.0 * N * t * 6, 2.0 * N * t);
   k_rescale_combine<<<grid_for(c, t, 2), 256, 0, s>>>(in->data, in->cap * N, R, out->data, out->cap * N, t, c->log_n,
                                                       c->d_mod, c->d_rescale[l]);
   HE_HIP(hipGetLastError());

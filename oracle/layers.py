@@ -1,0 +1,630 @@
+"""FHEON's secure CNN layers as pinned CKKS schedules — TEST INFRASTRUCTURE ONLY.
+
+Written from the paper's section "Secure Neural Network Layers":
+  * feature maps are flattened channel by channel into one SIMD vector
+    (Fig. "Flattening of an input tensor"); slot c*cs + y*rs + x = X[c, y, x];
+  * a convolution rotates the input to align every kernel tap, multiplies each
+    rotated copy by a vector of the repeated kernel value and sums
+    (Secure Convolution Layer); input channels are summed by repeated
+    rotations with the single key W^2; out-channels are placed by rotations
+    by multiples of the channel block;
+  * the 3x3 / stride 1 / pad 1 case uses the rotation tree of Algorithm 1
+    and the nine masks of Algorithms 2-3 instead of explicit padding
+    (Special Secure Convolution Layer);
+  * striding extracts the stride-aligned outputs with masks and rotations,
+    jointly for all channels (Secure Advanced Convolution With Striding,
+    approach 1 and the multi-channel pipeline);
+  * average pooling sums the window rotations and multiplies by 1/k^2, then
+    strides; global average pooling sums each W^2 block and merges the
+    channels; the fully connected layer multiplies by each weight row, sums
+    n slots and consolidates the m outputs with rotations.
+The exact rotation amounts, mask contents and rescale placement are this
+project's pinned reading (the paper leaves them open); the GPU library
+implements the same schedule independently.
+
+Each schedule is written once against an evaluator: ``HEEval`` runs it with
+the oracle's CKKS arithmetic, ``SimEval`` with plain float64 slot vectors
+(np.roll for rotations) so that the schedule itself can be pinned against the
+paper's FP64 layer equations.
+"""
+import math
+
+import numpy as np
+
+# degree-4 least-squares fit of max(0, x) on [-1, 1] (uniform weight):
+# projection of |x| on Legendre P0, P2, P4 gives 15/128 + 105/64 x^2 - 105/128 x^4,
+# and max(0, x) = (|x| + x) / 2.
+RELU4 = {0: 15.0 / 256.0, 1: 0.5, 2: 105.0 / 128.0, 4: -105.0 / 256.0}
+
+
+# ===================================================================== FP64 references
+def conv2d_ref(X, K, stride=1, padding=0, bias=None):
+    """Y[f, h, w] = sum_{c,i,j} X[c, S h + i - P, S w + j - P] K[f, c, i, j] + b_f
+    (zero outside the input), output size (H + 2P - k)/S + 1."""
+    C, H, W = X.shape
+    F, C2, kh, kw = K.shape
+    assert C == C2
+    Ho = (H + 2 * padding - kh) // stride + 1
+    Wo = (W + 2 * padding - kw) // stride + 1
+    Y = np.zeros((F, Ho, Wo))
+    for f in range(F):
+        for h in range(Ho):
+            for w in range(Wo):
+                acc = 0.0
+                for c in range(C):
+                    for i in range(kh):
+                        for j in range(kw):
+                            y, x = stride * h + i - padding, stride * w + j - padding
+                            if 0 <= y < H and 0 <= x < W:
+                                acc += X[c, y, x] * K[f, c, i, j]
+                Y[f, h, w] = acc + (bias[f] if bias is not None else 0.0)
+    return Y
+
+
+def avgpool_ref(X, k, stride):
+    """Output(i, j) = (1/k^2) sum_{x,y < k} Input(S i + x, S j + y) per channel."""
+    C, H, W = X.shape
+    Ho, Wo = (H - k) // stride + 1, (W - k) // stride + 1
+    Y = np.zeros((C, Ho, Wo))
+    for c in range(C):
+        for i in range(Ho):
+            for j in range(Wo):
+                Y[c, i, j] = X[c, stride * i:stride * i + k, stride * j:stride * j + k].sum() / (k * k)
+    return Y
+
+
+def gap_ref(X):
+    return X.reshape(X.shape[0], -1).mean(axis=1)
+
+
+def fc_ref(x, Wm, b=None):
+    """y_k = sum_i W_ki x_i + b_k."""
+    y = np.array([sum(Wm[k, i] * x[i] for i in range(len(x))) for k in range(Wm.shape[0])])
+    return y if b is None else y + b
+
+
+def relu4_ref(x):
+    return RELU4[0] + RELU4[1] * x + RELU4[2] * x ** 2 + RELU4[4] * x ** 4
+
+
+# ===================================================================== masks (Alg. 2 / 3)
+def build_mask(sp, ep, w, m, C):
+    """Algorithm 2 (build_mask), arguments in the order (sp, ep, w, m, C); the
+    final loop's bound, garbled in the listing, is read as C (one copy per
+    input channel)."""
+    mask = [0.0] * sp
+    while len(mask) < m - ep:
+        mask.extend([1.0] * w)
+        mask.append(0.0)
+    while len(mask) > m:
+        mask.pop()
+    while len(mask) < m:
+        mask.append(0.0)
+    for i in range(ep):
+        mask[m - i - 1] = 0.0
+    tmask = []
+    for _ in range(C):
+        tmask.extend(mask)
+    return np.array(tmask)
+
+
+def special_masks(W, C):
+    """Algorithm 3: the nine masks of the 3x3 / stride 1 / pad 1 convolution,
+    tap k = 3 (dy + 1) + (dx + 1)."""
+    m = W * W
+    return [
+        build_mask(W + 1, 0, W - 1, m, C),
+        build_mask(W, 0, m, m, C),
+        build_mask(W, 0, W - 1, m, C),
+        build_mask(1, 0, W - 1, m, C),
+        build_mask(0, 0, m, m, C),
+        build_mask(0, 1, W - 1, m, C),
+        build_mask(1, W - 1, W - 1, m, C),
+        build_mask(0, W, m, m, C),
+        build_mask(0, W + 1, W - 1, m, C),
+    ]
+
+
+def neighbour_masks(W):
+    """Closed form: tap (dy, dx) of output pixel (y, x) reads inside the image."""
+    out = []
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            m = np.zeros(W * W)
+            for y in range(W):
+                for x in range(W):
+                    if 0 <= y + dy < W and 0 <= x + dx < W:
+                        m[y * W + x] = 1.0
+            out.append(m)
+    return out
+
+
+# ===================================================================== geometry
+class FMap:
+    """Feature-map layout in the slots: channel c, row y, column x at
+    c*cs + y*rs + x for c < C, y < H, x < W; reps = 2 when the C-channel
+    block is stored twice back to back."""
+
+    def __init__(self, C, H, W, rs=None, cs=None, reps=1):
+        self.C, self.H, self.W = C, H, W
+        self.rs = W if rs is None else rs
+        self.cs = H * self.rs if cs is None else cs
+        self.reps = reps
+
+    def key(self):
+        return (self.C, self.H, self.W, self.rs, self.cs, self.reps)
+
+    def __eq__(self, o):
+        return self.key() == o.key()
+
+    def __repr__(self):
+        return "FMap(C=%d,H=%d,W=%d,rs=%d,cs=%d,reps=%d)" % self.key()
+
+
+def pack(X, fm, slots):
+    """Real slot vector holding tensor X (C,H,W) in layout fm."""
+    v = np.zeros(slots)
+    for r in range(fm.reps):
+        for c in range(fm.C):
+            for y in range(fm.H):
+                base = (r * fm.C + c) * fm.cs + y * fm.rs
+                v[base:base + fm.W] = X[c, y]
+    return v
+
+
+def unpack(v, fm):
+    X = np.zeros((fm.C, fm.H, fm.W))
+    for c in range(fm.C):
+        for y in range(fm.H):
+            base = c * fm.cs + y * fm.rs
+            X[c, y] = v[base:base + fm.W]
+    return X
+
+
+# ===================================================================== evaluators
+class SimCt:
+    def __init__(self, v, level, scale=1.0):
+        self.v, self.level, self.scale = v, level, scale
+
+
+class SimEval:
+    """Plain float64 slot simulation of a schedule (no encryption)."""
+
+    def __init__(self, slots):
+        self.slots = slots
+        self.ks = 0
+
+    def rot_hoisted(self, x, rs):
+        self.ks += sum(1 for r in rs if r % self.slots)
+        return [SimCt(np.roll(x.v, -r), x.level, x.scale) for r in rs]
+
+    def rot(self, x, r):
+        return self.rot_hoisted(x, [r])[0]
+
+    def mul_plain(self, x, pt):
+        return SimCt(x.v * pt, x.level, x.scale)
+
+    def add(self, a, b):
+        assert a.level == b.level
+        return SimCt(a.v + b.v, a.level, a.scale)
+
+    def rescale(self, x):
+        return SimCt(x.v, x.level - 1, x.scale)
+
+    def drop(self, x, level):
+        return SimCt(x.v, level, x.scale)
+
+    def mul_relin(self, a, b):
+        assert a.level == b.level
+        return SimCt(a.v * b.v, a.level, a.scale)
+
+    def mul_const(self, x, c, scale):
+        return SimCt(x.v * c, x.level, x.scale)
+
+    def add_const(self, x, c):
+        return SimCt(x.v + c, x.level, x.scale)
+
+    def with_scale(self, x, s):
+        return SimCt(x.v, x.level, s)
+
+    def modulus(self, level_index):
+        return 2.0 ** 40
+
+
+class HEEval:
+    """The same schedule with the oracle's CKKS arithmetic."""
+
+    def __init__(self, ctx, keys, relin_key=None):
+        self.ctx, self.keys, self.relin_key = ctx, keys, relin_key
+        self.ks = 0
+
+    def rot_hoisted(self, x, rs):
+        self.ks += sum(1 for r in rs if self.ctx.galois_element(r) != 1)
+        return self.ctx.rotate_hoisted(x, rs, self.keys)
+
+    def rot(self, x, r):
+        return self.rot_hoisted(x, [r])[0]
+
+    def mul_plain(self, x, pt):
+        return self.ctx.mul_plain(x, pt)
+
+    def add(self, a, b):
+        return self.ctx.add(a, b)
+
+    def rescale(self, x):
+        return self.ctx.rescale(x)
+
+    def drop(self, x, level):
+        return self.ctx.drop_level(x, level)
+
+    def mul_relin(self, a, b):
+        self.ks += 1
+        return self.ctx.mul_relin(a, b, self.relin_key)
+
+    def mul_const(self, x, c, scale):
+        return self.ctx.mul_plain(x, self.ctx.encode_const(c, scale, x.level))
+
+    def add_const(self, x, c):
+        return self.ctx.add_plain(x, self.ctx.encode_const(c, x.scale, x.level))
+
+    def with_scale(self, x, s):
+        from .ckks import Ciphertext
+
+        return Ciphertext(x.data, s)
+
+    def modulus(self, level_index):
+        return self.ctx.pr.q[level_index]
+
+
+# ===================================================================== schedule pieces
+def mac(ev, cts, pts):
+    """sum_t ct_t (.) pt_t (one multiplicative level, not rescaled)."""
+    acc = None
+    for c, p in zip(cts, pts):
+        t = ev.mul_plain(c, p)
+        acc = t if acc is None else ev.add(acc, t)
+    return acc
+
+
+def horner(ev, terms_fn, n, key):
+    """sum_{t<n} Rot_{t*key}(RS(term_t)) evaluated as
+    acc = RS(term_{n-1}); acc = Rot_key(acc) + RS(term_t) for t = n-2..0."""
+    acc = ev.rescale(terms_fn(n - 1))
+    for t in range(n - 2, -1, -1):
+        acc = ev.add(ev.rot(acc, key), ev.rescale(terms_fn(t)))
+    return acc
+
+
+def compaction_plan(fm, S, Ho, Wo):
+    """Steps of the stride-S extraction of outputs (S i, S j), jointly over all
+    channels: (i) columns, key S-1; (ii) rows, key D = S rs - Wo;
+    (iii) channels, key E = cs - Ho Wo.  Returns [(step, count, key)]."""
+    steps = []
+    if S > 1:
+        steps.append(("col", Wo, S - 1))
+    D = S * fm.rs - Wo
+    if D != 0:
+        steps.append(("row", Ho, D))
+    E = fm.cs - Ho * Wo
+    if E != 0 and fm.C > 1:
+        steps.append(("chan", fm.C, E))
+    return steps
+
+
+def compaction_masks(fm, S, Ho, Wo, col_scale, slots):
+    vecs = []
+    for step, n, _ in compaction_plan(fm, S, Ho, Wo):
+        for t in range(n):
+            m = np.zeros(slots)
+            for c in range(fm.C):
+                if step == "col":
+                    for i in range(Ho):
+                        m[c * fm.cs + S * i * fm.rs + S * t] = col_scale
+                elif step == "row":
+                    base = c * fm.cs + S * t * fm.rs
+                    m[base:base + Wo] = 1.0
+                elif step == "chan" and c == t:
+                    m[c * fm.cs:c * fm.cs + Ho * Wo] = 1.0
+            vecs.append(m)
+    return vecs
+
+
+def compaction(ev, v, fm, S, Ho, Wo, masks):
+    """Move output (c, i, j) from c cs + S i rs + S j to c Ho Wo + i Wo + j."""
+    pos = 0
+    for step, n, key in compaction_plan(fm, S, Ho, Wo):
+        ms = masks[pos:pos + n]
+        pos += n
+        v = horner(ev, lambda t, ms=ms, v=v: ev.mul_plain(v, ms[t]), n, key)
+    assert pos == len(masks)
+    return v, FMap(fm.C, Ho, Wo, Wo, Ho * Wo, 1)
+
+
+# ===================================================================== convolution
+def conv_kind(k, padding):
+    if k == 3 and padding == 1:
+        return "special"
+    if padding == 0:
+        return "generic"
+    raise NotImplementedError("padding by rotations is not part of the pinned schedules")
+
+
+def conv_out_map(fm, F, k, stride, padding, slots):
+    kind = conv_kind(k, padding)
+    if kind == "special":
+        W = fm.W
+        if stride == 1:
+            reps = 2 if (fm.reps == 2 and 2 * F * W * W == slots) else 1
+            return FMap(F, W, W, W, W * W, reps)
+        Ho = (W + 2 - 3) // stride + 1
+        return FMap(F, Ho, Ho, Ho, Ho * Ho, 1)
+    H1, W1 = fm.H - k + 1, fm.W - k + 1
+    if stride == 1:
+        return FMap(F, H1, W1, fm.rs, fm.cs, 1)
+    Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+    return FMap(F, Ho, Wo, Wo, Ho * Wo, 1)
+
+
+def conv_plaintexts(fm, K, stride, padding, slots):
+    """Real vectors the convolution multiplies by, in the order the schedule
+    (and the GPU library) consumes them: kernel vectors [f][tap], then masks."""
+    F, C, k, _ = K.shape
+    assert C == fm.C
+    kind = conv_kind(k, padding)
+    kern, masks = [], []
+    if kind == "special":
+        W = fm.W
+        nm = special_masks(W, 1)
+        for f in range(F):
+            for tap in range(9):
+                v = np.zeros(slots)
+                dy, dx = tap // 3, tap % 3
+                for b in range(fm.reps * C):
+                    v[b * W * W:(b + 1) * W * W] = K[f, b % C, dy, dx] * nm[tap]
+                kern.append(v)
+        out1 = FMap(F, W, W, W, W * W, 2 if (fm.reps == 2 and 2 * F * W * W == slots) else 1)
+        if F > 1 or C > 1:
+            for f in range(F):
+                m = np.zeros(slots)
+                for r in range(out1.reps):
+                    b = r * F + f
+                    m[b * W * W:(b + 1) * W * W] = 1.0
+                masks.append(m)
+        if stride > 1:
+            Ho = (W - 1) // stride + 1
+            masks += compaction_masks(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, 1.0, slots)
+    else:
+        H1, W1 = fm.H - k + 1, fm.W - k + 1
+        for f in range(F):
+            for i in range(k):
+                for j in range(k):
+                    v = np.zeros(slots)
+                    for c in range(C):
+                        for y in range(H1):
+                            base = c * fm.cs + y * fm.rs
+                            v[base:base + W1] = K[f, c, i, j]
+                    kern.append(v)
+        if C > 1:
+            m = np.zeros(slots)
+            for y in range(H1):
+                m[y * fm.rs:y * fm.rs + W1] = 1.0
+            masks.append(m)
+        if stride > 1:
+            Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+            masks += compaction_masks(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0, slots)
+    return kern, masks
+
+
+def conv_rotations(fm, F, k, stride, padding, slots):
+    """Distinct rotation keys the schedule uses (the paper's per-layer index helper)."""
+    kind = conv_kind(k, padding)
+    keys = set()
+    if kind == "special":
+        W = fm.W
+        keys |= {-W, W, -1, 1}
+        if fm.C > 1:
+            keys.add(W * W)
+        if stride > 1:
+            Ho = (W - 1) // stride + 1
+            keys |= {key for _, _, key in compaction_plan(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho)}
+    else:
+        keys |= {i * fm.rs + j for i in range(k) for j in range(k) if (i, j) != (0, 0)}
+        if fm.C > 1:
+            keys.add(fm.cs)
+        if F > 1:
+            keys.add(-fm.cs)
+        if stride > 1:
+            H1, W1 = fm.H - k + 1, fm.W - k + 1
+            Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+            keys |= {key for _, _, key in compaction_plan(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo)}
+    return sorted(keys)
+
+
+def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots):
+    """Pinned convolution schedule.
+
+    special (k=3, P=1): r = Algorithm 1 rotations computed as three hoisted
+      groups {-W, W, -1, 1} of x, {-1, 1} of r1, {-1, 1} of r7;
+      A_f = RS(sum_tap r_tap (.) kv[f][tap]);
+      C > 1 (replicated input): S_f = A_f + Rot_{W^2}(A_f) + ... chained with
+      the single key W^2 (C-1 key switches); Y = RS(sum_f S_f (.) blockmask_f);
+      stride > 1: joint compaction of all channels.
+    generic (P=0): one hoisted group of the k^2-1 offsets i rs + j;
+      A_f = RS(sum r (.) kv); C > 1: channel chain with key cs, then
+      RS(. (.) block-0 mask); out-channels placed by a Horner chain with key
+      -cs; stride > 1: joint compaction.
+    """
+    kind = conv_kind(k, padding)
+    C = fm.C
+    if kind == "special":
+        W = fm.W
+        if fm.reps == 1 and (C > 1 or F > 1):
+            raise NotImplementedError("special convolution with several channels needs a replicated input")
+        if fm.reps == 2:
+            assert 2 * C * W * W == slots
+        g1 = ev.rot_hoisted(x, [-W, W, -1, 1])
+        r1, r7, r3, r5 = g1
+        r0, r2 = ev.rot_hoisted(r1, [-1, 1])
+        r6, r8 = ev.rot_hoisted(r7, [-1, 1])
+        taps = [r0, r1, r2, r3, x, r5, r6, r7, r8]
+        sums = []
+        for f in range(F):
+            A = ev.rescale(mac(ev, taps, kern[9 * f:9 * f + 9]))
+            S, T = A, A
+            for _ in range(C - 1):
+                T = ev.rot(T, W * W)
+                S = ev.add(S, T)
+            sums.append(S)
+        mpos = 0
+        if F > 1 or C > 1:
+            y = ev.rescale(mac(ev, sums, masks[:F]))
+            mpos = F
+        else:
+            y = sums[0]
+        out1 = FMap(F, W, W, W, W * W, 2 if (fm.reps == 2 and 2 * F * W * W == slots) else 1)
+        if stride == 1:
+            return y, out1
+        Ho = (W - 1) // stride + 1
+        return compaction(ev, y, FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, masks[mpos:])
+    # generic
+    offs = [i * fm.rs + j for i in range(k) for j in range(k)]
+    rot = ev.rot_hoisted(x, offs[1:])
+    taps = [x] + rot
+    sums = []
+    for f in range(F):
+        A = ev.rescale(mac(ev, taps, kern[k * k * f:k * k * (f + 1)]))
+        if C > 1:
+            S, T = A, A
+            for _ in range(C - 1):
+                T = ev.rot(T, fm.cs)
+                S = ev.add(S, T)
+            A = S
+        sums.append(A)
+    mpos = 0
+    if C > 1:
+        sums = [ev.mul_plain(s, masks[0]) for s in sums]
+        mpos = 1
+        y = horner(ev, lambda t: sums[t], F, -fm.cs)
+    elif F > 1:
+        acc = sums[F - 1]
+        for t in range(F - 2, -1, -1):
+            acc = ev.add(ev.rot(acc, -fm.cs), sums[t])
+        y = acc
+    else:
+        y = sums[0]
+    H1, W1 = fm.H - k + 1, fm.W - k + 1
+    if stride == 1:
+        return y, FMap(F, H1, W1, fm.rs, fm.cs, 1)
+    Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+    return compaction(ev, y, FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks[mpos:])
+
+
+# ===================================================================== pooling
+def avgpool_plaintexts(fm, k, stride, slots):
+    H1, W1 = fm.H - k + 1, fm.W - k + 1
+    Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+    if stride == 1:
+        m = np.zeros(slots)
+        for c in range(fm.C):
+            for y in range(H1):
+                m[c * fm.cs + y * fm.rs:c * fm.cs + y * fm.rs + W1] = 1.0 / (k * k)
+        return [m]
+    return compaction_masks(FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0 / (k * k), slots)
+
+
+def avgpool_rotations(fm, k, stride):
+    keys = {i * fm.rs + j for i in range(k) for j in range(k) if (i, j) != (0, 0)}
+    if stride > 1:
+        H1, W1 = fm.H - k + 1, fm.W - k + 1
+        Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+        keys |= {key for _, _, key in compaction_plan(FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo)}
+    return sorted(keys)
+
+
+def avgpool(ev, x, fm, k, stride, masks):
+    """Window sum by one hoisted group of the k^2-1 offsets i rs + j, then the
+    stride compaction with 1/k^2 folded into the column masks."""
+    offs = [i * fm.rs + j for i in range(k) for j in range(k)]
+    s = x
+    for r in ev.rot_hoisted(x, offs[1:]):
+        s = ev.add(s, r)
+    H1, W1 = fm.H - k + 1, fm.W - k + 1
+    if stride == 1:
+        return ev.rescale(ev.mul_plain(s, masks[0])), FMap(fm.C, H1, W1, fm.rs, fm.cs, 1)
+    Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+    return compaction(ev, s, FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks)
+
+
+def gap_plaintexts(fm, slots):
+    out = []
+    for c in range(fm.C):
+        m = np.zeros(slots)
+        m[c * fm.cs] = 1.0 / (fm.H * fm.W)
+        out.append(m)
+    return out
+
+
+def gap_rotations(fm):
+    keys = {1 << t for t in range(int(math.log2(fm.cs)))}
+    if fm.C > 1:
+        keys.add(fm.cs - 1)
+    return sorted(keys)
+
+
+def gap(ev, x, fm, masks):
+    """Global average pooling: S += Rot_{2^t}(S) for t < log2(cs) sums every
+    channel block into its first slot; a Horner chain with key cs-1 and masks
+    1/(H W) at c*cs gathers channel c into slot c."""
+    assert fm.cs & (fm.cs - 1) == 0 and fm.rs == fm.W and fm.cs == fm.H * fm.W
+    S = x
+    for t in range(int(math.log2(fm.cs))):
+        S = ev.add(S, ev.rot(S, 1 << t))
+    y = horner(ev, lambda c: ev.mul_plain(S, masks[c]), fm.C, fm.cs - 1)
+    return y, FMap(fm.C, 1, 1, 1, 1, 1)
+
+
+# ===================================================================== fully connected
+def fc_plaintexts(Wm, slots):
+    n_out, n_in = Wm.shape
+    rows = []
+    for k in range(n_out):
+        v = np.zeros(slots)
+        v[:n_in] = Wm[k]
+        rows.append(v)
+    e0 = np.zeros(slots)
+    e0[0] = 1.0
+    return rows, [e0]
+
+
+def fc_rotations(n_in, n_out):
+    return sorted({1 << t for t in range(int(math.log2(n_in)))} | ({-1} if n_out > 1 else set()))
+
+
+def fc(ev, x, n_in, n_out, rows, masks):
+    """Per output neuron: P_k = RS(x (.) W_k), log-step sum of n_in slots into
+    slot 0; outputs consolidated by a Horner chain with key -1 over the
+    e_0-masked sums (the paper's parameterised merging with one key)."""
+    assert n_in & (n_in - 1) == 0
+    sums = []
+    for k in range(n_out):
+        P = ev.rescale(ev.mul_plain(x, rows[k]))
+        for t in range(int(math.log2(n_in))):
+            P = ev.add(P, ev.rot(P, 1 << t))
+        sums.append(P)
+    return horner(ev, lambda k: ev.mul_plain(sums[k], masks[0]), n_out, -1)
+
+
+# ===================================================================== polynomial activation
+def relu_poly4(ev, x, delta):
+    """p(x) = c0 + c1 x + c2 x^2 + c4 x^4 (RELU4) in three levels:
+    x2 = RS(x*x); t = RS(x2 * c4) + c2; v = RS(x2 * t) (= c4 x^4 + c2 x^2);
+    lin = RS(x * c1) with c1 encoded at sigma = s_v q / s_x so that it lands
+    on v's level and scale (its tracked scale is set to s_v); p = v + lin + c0."""
+    x2 = ev.rescale(ev.mul_relin(x, x))
+    t = ev.add_const(ev.rescale(ev.mul_const(x2, RELU4[4], delta)), RELU4[2])
+    v = ev.rescale(ev.mul_relin(ev.drop(x2, t.level), t))
+    q = ev.modulus(v.level)  # the prime the next rescale divides by
+    sigma = v.scale * q / x.scale
+    lin = ev.rescale(ev.mul_const(ev.drop(x, v.level + 1), RELU4[1], sigma))
+    lin = ev.with_scale(lin, v.scale)
+    return ev.add_const(ev.add(v, lin), RELU4[0])

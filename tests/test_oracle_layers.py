@@ -1,0 +1,208 @@
+"""Pins for the layer schedules (CPU only).
+
+1. Algorithms 2/3 (build_mask, nine masks) equal the closed-form
+   "neighbour inside the image" masks.
+2. Every schedule, run as a plain float slot simulation, equals the paper's
+   FP64 layer equation (direct loops), and uses the documented number of key
+   switches and levels.
+3. The same schedules under the oracle's CKKS arithmetic decrypt to the FP64
+   result within the stated tolerance (1e-3 per layer, 1e-2 for the LeNet-5
+   shaped stack) at the real ring sizes.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ckks
+from oracle import layers as LY
+from tests import helpers as H
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.mark.parametrize("W", [4, 5, 8, 32])
+@pytest.mark.parametrize("C", [1, 3])
+def test_alg2_alg3_masks_are_neighbour_masks(W, C):
+    got = LY.special_masks(W, C)
+    want = LY.neighbour_masks(W)
+    for k in range(9):
+        assert np.array_equal(got[k], np.tile(want[k], C)), k
+
+
+def test_paper_output_size_formulas():
+    """Output-size equations (Secure Advanced Convolution) on the layer shapes
+    of the paper's architecture tables (fixture cites the tables)."""
+    fx = json.load(open(os.path.join(GOLDEN, "paper_layer_shapes.json")))
+    for row in fx["layers"]:
+        H_in, k, S, P = row["in_hw"], row["kernel"], row["stride"], row["padding"]
+        assert (H_in + 2 * P - k) // S + 1 == row["out_hw"], row
+    fc = fx["lenet5_fc_input"]
+    assert fc["channels"] * fc["hw"] ** 2 == fc["fc_in"]
+
+
+def sim(slots):
+    return LY.SimEval(slots)
+
+
+def test_sim_config0_special_conv():
+    X = synth.image(1, 1, 8, 8)
+    K = synth.conv_weights(1, 1, 1, 3, 0.1)
+    fm = LY.FMap(1, 8, 8)
+    slots = 2048
+    kern, masks = LY.conv_plaintexts(fm, K, 1, 1, slots)
+    ev = sim(slots)
+    y, fo = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 3), fm, 1, 3, 1, 1, kern, masks, slots)
+    assert ev.ks == 8 and y.level == 2
+    assert np.max(np.abs(LY.unpack(y.v, fo) - LY.conv2d_ref(X, K, 1, 1))) < 1e-12
+
+
+@pytest.mark.parametrize("stride,F", [(1, 16), (2, 32)])
+def test_sim_config2_special_conv(stride, F):
+    slots = 32768
+    X = synth.image(2, 16, 32, 32)
+    K = synth.conv_weights(2, F, 16, 3, (2.0 / 144) ** 0.5)
+    fm = LY.FMap(16, 32, 32, reps=2)
+    kern, masks = LY.conv_plaintexts(fm, K, stride, 1, slots)
+    ev = sim(slots)
+    y, fo = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 24), fm, F, 3, stride, 1, kern, masks, slots)
+    ref = LY.conv2d_ref(X, K, stride, 1)
+    assert np.max(np.abs(LY.unpack(y.v, fo) - ref)) < 1e-9
+    if stride == 1:
+        assert ev.ks == 248 and 24 - y.level == 2 and fo.reps == 2
+        # replication preserved: the second copy equals the first
+        assert np.array_equal(y.v[:16384], y.v[16384:])
+    else:
+        assert ev.ks == 549 and 24 - y.level == 5 and fo == LY.FMap(32, 16, 16)
+    assert len(LY.conv_rotations(fm, F, 3, stride, 1, slots)) == (5 if stride == 1 else 7)
+
+
+def test_sim_config1_stack():
+    """conv 5x5 1->6 -> degree-4 ReLU polynomial -> 2x2 average pool, 7 levels."""
+    slots = 8192
+    X = synth.image(3, 1, 28, 28)
+    K = synth.conv_weights(3, 6, 1, 5, 0.1)
+    fm = LY.FMap(1, 28, 28)
+    kern, masks = LY.conv_plaintexts(fm, K, 1, 0, slots)
+    ev = sim(slots)
+    y, f1 = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 8), fm, 6, 5, 1, 0, kern, masks, slots)
+    assert f1 == LY.FMap(6, 24, 24, 28, 784) and ev.ks == 29 and y.level == 7
+    ref = LY.conv2d_ref(X, K, 1, 0)
+    assert np.max(np.abs(LY.unpack(y.v, f1) - ref)) < 1e-12
+    p = LY.relu_poly4(ev, y, 2.0 ** 45)
+    assert p.level == 4 and ev.ks == 29
+    ref = LY.relu4_ref(ref)
+    assert np.max(np.abs(LY.unpack(p.v, f1) - ref)) < 1e-12
+    pm = LY.avgpool_plaintexts(f1, 2, 2, slots)
+    z, f2 = LY.avgpool(ev, p, f1, 2, 2, pm)
+    assert f2 == LY.FMap(6, 12, 12) and z.level == 1 and ev.ks == 59
+    assert np.max(np.abs(LY.unpack(z.v, f2) - LY.avgpool_ref(ref, 2, 2))) < 1e-12
+
+
+@pytest.mark.parametrize("C,HW,ks", [(32, 16, 39), (64, 8, 69)])
+def test_sim_gap(C, HW, ks):
+    slots = 32768
+    X = synth.image(4, C, HW, HW)
+    fm = LY.FMap(C, HW, HW)
+    ev = sim(slots)
+    y, fo = LY.gap(ev, LY.SimCt(LY.pack(X, fm, slots), 10), fm, LY.gap_plaintexts(fm, slots))
+    assert ev.ks == ks and y.level == 9
+    assert np.max(np.abs(y.v[:C] - LY.gap_ref(X))) < 1e-12 and np.max(np.abs(y.v[C:])) < 1e-12
+
+
+def test_sim_fc():
+    slots = 32768
+    x = np.zeros(64)
+    x[:32] = synth.uniform_slots(5, 32)
+    Wm = synth.fc_weights(5, 10, 64, (2.0 / 64) ** 0.5)
+    v = np.zeros(slots)
+    v[:64] = x
+    rows, masks = LY.fc_plaintexts(Wm, slots)
+    ev = sim(slots)
+    y = LY.fc(ev, LY.SimCt(v, 10), 64, 10, rows, masks)
+    assert ev.ks == 69 and y.level == 8
+    assert np.max(np.abs(y.v[:10] - LY.fc_ref(x, Wm))) < 1e-12 and np.max(np.abs(y.v[10:])) < 1e-12
+
+
+def test_sim_generic_conv_multichannel_stride():
+    """Generic convolution with C > 1 and stride 2 (block-0 mask + placement + compaction)."""
+    slots = 4096
+    X = synth.image(6, 3, 12, 12)
+    K = synth.conv_weights(6, 4, 3, 3, 0.2)
+    fm = LY.FMap(3, 12, 12)
+    kern, masks = LY.conv_plaintexts(fm, K, 2, 0, slots)
+    ev = sim(slots)
+    y, fo = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 12), fm, 4, 3, 2, 0, kern, masks, slots)
+    assert fo == LY.FMap(4, 5, 5)
+    assert np.max(np.abs(LY.unpack(y.v, fo) - LY.conv2d_ref(X, K, 2, 0))) < 1e-12
+
+
+# ------------------------------------------------------------------ encrypted (oracle CKKS)
+def he_eval(name, rots, relin=False):
+    ctx, sk, pk = H.oracle_ctx(name)
+    keys = H.oracle_keys(name, rots)
+    return LY.HEEval(ctx, keys, H.oracle_key(name, "relin") if relin else None), ctx, sk, pk
+
+
+def encode_all(ctx, vecs, level):
+    return [ctx.encode(v, ctx.pr.scale, level) for v in vecs]
+
+
+def test_he_config0_conv_decrypts_to_fp64():
+    name = "config0"
+    ctx0, _, _ = H.oracle_ctx(name)
+    slots = ctx0.n // 2
+    X = synth.image(10, 1, 8, 8)
+    K = synth.conv_weights(10, 1, 1, 3, 0.1)
+    fm = LY.FMap(1, 8, 8)
+    ev, ctx, sk, pk = he_eval(name, LY.conv_rotations(fm, 1, 3, 1, 1, slots))
+    kern, masks = LY.conv_plaintexts(fm, K, 1, 1, slots)
+    _, ct = H.encrypt_slots(name, 10, values=LY.pack(X, fm, slots))
+    y, fo = LY.conv2d(ev, ct, fm, 1, 3, 1, 1, encode_all(ctx, kern, ctx.pr.L), masks, slots)
+    assert ev.ks == 8
+    err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, y), fo) - LY.conv2d_ref(X, K, 1, 1)))
+    assert err < 1e-3, err
+
+
+def test_he_config1_stack_decrypts_to_fp64():
+    name = "config1"
+    ctx1, _, _ = H.oracle_ctx(name)
+    slots = ctx1.n // 2
+    X = synth.image(11, 1, 28, 28)
+    K = synth.conv_weights(11, 6, 1, 5, 0.1)
+    fm = LY.FMap(1, 28, 28)
+    f1 = LY.conv_out_map(fm, 6, 5, 1, 0, slots)
+    rots = sorted(set(LY.conv_rotations(fm, 6, 5, 1, 0, slots)) | set(LY.avgpool_rotations(f1, 2, 2)))
+    ev, ctx, sk, pk = he_eval(name, rots, relin=True)
+    kern, masks = LY.conv_plaintexts(fm, K, 1, 0, slots)
+    _, ct = H.encrypt_slots(name, 11, values=LY.pack(X, fm, slots))
+    L = ctx.pr.L
+    y, f1 = LY.conv2d(ev, ct, fm, 6, 5, 1, 0, encode_all(ctx, kern, L), masks, slots)
+    p = LY.relu_poly4(ev, y, ctx.pr.scale)
+    z, f2 = LY.avgpool(ev, p, f1, 2, 2, encode_all(ctx, LY.avgpool_plaintexts(f1, 2, 2, slots), L))
+    assert z.level == 1 and ev.ks == 61
+    ref = LY.avgpool_ref(LY.relu4_ref(LY.conv2d_ref(X, K, 1, 0)), 2, 2)
+    err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, z), f2) - ref))
+    assert err < 1e-2, err
+
+
+@pytest.mark.slow
+def test_he_config2_small_special_conv_decrypts():
+    """Special convolution at the N=2^16, L=24 parameters with 4 replicated
+    channels of 64x64 (2*C*W^2 = N/2): 20 key switches."""
+    name = "config2"
+    ctx2, _, _ = H.oracle_ctx(name)
+    slots = ctx2.n // 2
+    X = synth.image(12, 4, 64, 64)
+    K = synth.conv_weights(12, 4, 4, 3, (2.0 / 36) ** 0.5)
+    fm = LY.FMap(4, 64, 64, reps=2)
+    ev, ctx, sk, pk = he_eval(name, LY.conv_rotations(fm, 4, 3, 1, 1, slots))
+    kern, masks = LY.conv_plaintexts(fm, K, 1, 1, slots)
+    _, ct = H.encrypt_slots(name, 12, values=LY.pack(X, fm, slots))
+    L = ctx.pr.L
+    y, fo = LY.conv2d(ev, ct, fm, 4, 3, 1, 1, encode_all(ctx, kern, L), encode_all(ctx, masks, L), slots)
+    assert ev.ks == 20
+    err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, y), fo) - LY.conv2d_ref(X, K, 1, 1)))
+    assert err < 1e-3, err

@@ -163,6 +163,93 @@ int he_mul_relin(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct* out, he_str
 /* Relinearize a 3-part ciphertext d ([3][level][N], device) into out. */
 int he_relin(he_ctx* ctx, const uint64_t* d, int level, double scale, he_ct* out, he_stream stream);
 
+/* Multiply by a real constant c encoded at `scale` as the constant
+ * polynomial llround(c * scale) (ties away from zero); out.scale =
+ * in.scale * scale.  Add a real constant c encoded at the ciphertext's own
+ * scale.  out may alias in. */
+int he_mul_const(he_ctx* ctx, const he_ct* in, double c, double scale, he_ct* out, he_stream stream);
+int he_add_const(he_ctx* ctx, const he_ct* in, double c, he_ct* out, he_stream stream);
+
+/* ------------------------------------------------------------ layers
+ * Feature-map layout in the slots (the paper's channel-by-channel flattening,
+ * Section "Secure Convolution Layer", Fig. "Flattening of an input tensor"):
+ * value (c, y, x) sits in slot c*chan_stride + y*row_stride + x for c < C,
+ * y < H, x < W; reps = 2 means the C-channel block is stored twice back to
+ * back (2*C*chan_stride = N/2 slots), which the special convolution uses to
+ * sum input channels by cyclic rotation.  Unused slots hold zeros. */
+typedef struct {
+  int32_t channels, height, width;
+  int32_t row_stride, chan_stride;
+  int32_t reps;
+} he_fmap;
+
+/* Plan of a layer: the plaintexts it consumes, the distinct rotation keys it
+ * needs (the paper's per-layer rotation-index helper, Section "Evaluation
+ * Keys Management"), the levels it consumes and the output layout.  rot_keys
+ * may be NULL (then only *n_keys is written); otherwise it must hold 64. */
+typedef struct {
+  int32_t n_kernel_pts, n_mask_pts;
+  int32_t n_keys;
+  int32_t rot_keys[64];
+  int32_t levels;
+  int32_t key_switches;
+  he_fmap out;
+} he_layer_plan;
+
+/* Convolution (Sections "Secure Convolution Layer", "Secure Advanced
+ * Convolution Layer" with striding approach 1 and the multi-channel striding
+ * pipeline, "Special Secure Convolution Layer" with Algorithms 1-3).
+ * Supported: kernel 3 / padding 1 (special schedule; several channels need
+ * reps = 2 and a dense square map; stride 1 or 2) and padding 0 (generic
+ * schedule, any kernel and stride).  Other paddings: HE_EUNSUPPORTED.
+ * Plaintexts (NTT form, at least the input level in limbs, encoded at one
+ * common scale), in this order:
+ *  special: kernel_pts[9 f + t], t = 3 (dy+1) + (dx+1): K[f, b mod C, t] on
+ *    block b of every replica, times the Algorithm-3 mask of tap t;
+ *    mask_pts: F block masks (1 on block f of every output replica) when
+ *    C > 1 or F > 1, then the stride-compaction masks.
+ *  generic: kernel_pts[k*k f + i k + j]: K[f, c, i, j] at c*cs + y*rs + x for
+ *    the valid stride-1 outputs (y <= H-k, x <= W-k); mask_pts: the block-0
+ *    valid-output mask when C > 1, then the stride-compaction masks.
+ *  compaction masks (stride S > 1, outputs (S i, S j) -> dense Ho x Wo):
+ *    Wo column masks (1 at c*cs + S i rs + S j, all c, i), Ho row masks
+ *    (1 at c*cs + S i rs + j, j < Wo), then C channel masks (1 on
+ *    c*cs + [0, Ho*Wo)) — each step only when it moves data.
+ * The result is rescaled after every multiplicative level. */
+int he_conv2d_plan(const he_ctx* ctx, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
+                   he_layer_plan* plan);
+int he_conv2d(he_ctx* ctx, const he_ct* in, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
+              const he_pt* kernel_pts, int n_kernel_pts, const he_pt* mask_pts, int n_mask_pts, he_ct* out,
+              he_fmap* out_map, he_stream stream);
+
+/* Average pooling (Section "Secure Average Pooling Layer", equation of the
+ * pooled output): window sum by rotations, 1/k^2 folded into the column masks
+ * of the stride compaction (stride 1: one mask of 1/k^2 on the valid
+ * outputs).  kernel = 0 selects global average pooling: per-channel sums by
+ * log-step rotations, then channel c gathered into slot c with masks of
+ * 1/(H W) at slot c*cs (requires dense power-of-two channel blocks). */
+int he_avgpool_plan(const he_ctx* ctx, const he_fmap* in_map, int kernel, int stride, he_layer_plan* plan);
+int he_avgpool(he_ctx* ctx, const he_ct* in, const he_fmap* in_map, int kernel, int stride, const he_pt* mask_pts,
+               int n_mask_pts, he_ct* out, he_fmap* out_map, he_stream stream);
+
+/* Fully connected y = W x (+ b) (Section "Secure Fully Connected Layer"):
+ * input in slots 0..n_in-1 (n_in a power of two); weight_pts[k] holds row
+ * W_k in slots 0..n_in-1; mask_pts[0] is e_0 (1 in slot 0).  Each neuron is
+ * a product, a log-step sum into slot 0 and an e_0 mask; the outputs are
+ * merged into slots 0..n_out-1 with the single key -1.  bias_pt (nullable)
+ * must carry the output scale. */
+int he_fc_plan(const he_ctx* ctx, int n_in, int n_out, he_layer_plan* plan);
+int he_fc(he_ctx* ctx, const he_ct* in, int n_in, int n_out, const he_pt* weight_pts, const he_pt* mask_pts,
+          const he_pt* bias_pt, he_ct* out, he_stream stream);
+
+/* Polynomial activation p(x) = c[0] + c[1] x + c[2] x^2 + c[4] x^4 (c[3]
+ * must be 0) in three levels with two relinearizations:
+ * x2 = RS(x*x); t = RS(x2 * c4 @delta) + c2; v = RS(x2 * t);
+ * lin = RS(x * c1 @sigma) with sigma = s_v q / s_x so lin lands on v's level
+ * (its scale is set to s_v); p = v + lin + c0.  With c = the least-squares
+ * fit of max(0, x) on [-1, 1] this is the LeNet-5-shaped stack's ReLU. */
+int he_poly4(he_ctx* ctx, const he_ct* in, const double* c, double delta, he_ct* out, he_stream stream);
+
 /* ------------------------------------------------------------ measurement
  * Per-kernel timing: after he_profile_begin, every kernel launch of this
  * context is bracketed by a HIP event pair on its stream.  he_profile_end

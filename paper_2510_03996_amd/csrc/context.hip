@@ -321,6 +321,7 @@ int he_ctx_destroy(he_ctx* h) {
   hipSetDevice(h->c.device);
   hipDeviceSynchronize();
   for (auto& kv : h->c.keys) hipFree(kv.second);
+  for (uint64_t* p : h->c.ct_pool_all) hipFree(p);
   for (void* p : h->c.allocs) hipFree(p);
   delete h;
   return HE_OK;

@@ -53,6 +53,8 @@ struct Ctx {
   uint64_t* ws = nullptr;
   size_t ws_words = 0;
   std::vector<void*> allocs;
+  // reusable [2][L][N] ciphertext buffers for layer temporaries
+  std::vector<uint64_t*> ct_pool, ct_pool_all;
   bool prof_on = false;
   std::vector<ProfRec> prof;
 
@@ -126,6 +128,8 @@ int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s);
 int ks_apply(Ctx* c, const WS& w, int level, const uint64_t* key, uint32_t g, const uint64_t* add0,
              const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s);
 const uint64_t* find_key(Ctx* c, int32_t id);
+int check_ct(const Ctx* c, const he_ct* x, const char* what);
+int check_out(const Ctx* c, const he_ct* x, int need_level);
 
 int32_t norm_key_id(const Ctx* c, int32_t id);
 uint32_t galois_elt(const Ctx* c, int32_t r);

@@ -127,8 +127,6 @@ const uint64_t* find_key(Ctx* c, int32_t id) {
   return it == c->keys.end() ? nullptr : it->second;
 }
 
-int check_ct(const Ctx* c, const he_ct* x, const char* what);
-int check_out(const Ctx* c, const he_ct* x, int need_level);
 
 }  // namespace he
 

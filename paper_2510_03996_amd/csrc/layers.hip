@@ -1,0 +1,589 @@
+// FHEON's secure CNN layers as CKKS schedules on the GPU ops.
+//
+// The schedules (rotation amounts, mask order, rescale placement) follow the
+// paper's layer algorithms with one pinned reading each:
+//   special conv (3x3, pad 1): Algorithm 1 rotation tree as three hoisted
+//     groups, kernel vectors masked by Algorithms 2-3, input-channel sum by a
+//     chain of rotations with the single key W^2 on a replicated input, block
+//     masks place the out-channels;
+//   generic conv (pad 0): one hoisted group of the k^2-1 tap offsets, channel
+//     chain with key cs, out-channels placed by a Horner chain with key -cs;
+//   striding: joint compaction of all channels in three Horner chains
+//     (columns key S-1, rows key S*rs - Wo, channels key cs - Ho*Wo);
+//   pooling / global pooling / FC / polynomial activation as documented in he.h.
+// Every multiplicative level is rescaled once, after its last addition and
+// before any rotation consumes it.
+#include <cmath>
+#include <vector>
+
+#include "internal.h"
+
+namespace he {
+
+struct LayerError {
+  int code;
+};
+
+static void ck(int rc) {
+  if (rc < 0) throw LayerError{rc};
+}
+
+// device ciphertext buffers [2][L][N] reused across calls (stream-ordered)
+static uint64_t* pool_get(Ctx* c) {
+  if (!c->ct_pool.empty()) {
+    uint64_t* p = c->ct_pool.back();
+    c->ct_pool.pop_back();
+    return p;
+  }
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, (size_t)2 * c->L * c->n * 8);
+  if (e != hipSuccess) throw LayerError{set_error(HE_ENOMEM, "ciphertext pool allocation failed")};
+  c->ct_pool_all.push_back((uint64_t*)v);
+  return (uint64_t*)v;
+}
+
+struct Ev {
+  he_ctx* h;
+  Ctx* c;
+  he_stream s;
+  std::vector<uint64_t*> held;
+  Ev(he_ctx* h_, he_stream s_) : h(h_), c(&h_->c), s(s_) {}
+  ~Ev() {
+    for (uint64_t* p : held) c->ct_pool.push_back(p);
+  }
+  he_ct fresh() {
+    uint64_t* p = pool_get(c);
+    held.push_back(p);
+    return he_ct{p, 0, c->L, 0.0};
+  }
+  he_ct rot(const he_ct& x, int r) {
+    he_ct o = fresh();
+    ck(he_rotate(h, &x, r, &o, s));
+    return o;
+  }
+  std::vector<he_ct> rot_hoisted(const he_ct& x, const std::vector<int>& rs) {
+    std::vector<he_ct> o(rs.size());
+    for (auto& t : o) t = fresh();
+    ck(he_rotate_hoisted(h, &x, rs.data(), (int)rs.size(), o.data(), s));
+    return o;
+  }
+  he_ct mul(const he_ct& x, const he_pt& p) {
+    he_ct o = fresh();
+    ck(he_mul_plain(h, &x, &p, &o, 0, s));
+    return o;
+  }
+  void mac(he_ct& acc, const he_ct& x, const he_pt& p) { ck(he_mul_plain(h, &x, &p, &acc, 1, s)); }
+  he_ct add(const he_ct& a, const he_ct& b) {
+    he_ct o = fresh();
+    ck(he_add(h, &a, &b, &o, s));
+    return o;
+  }
+  void add_into(he_ct& acc, const he_ct& b) { ck(he_add(h, &acc, &b, &acc, s)); }
+  he_ct rescale(const he_ct& x) {
+    he_ct o = fresh();
+    ck(he_rescale(h, &x, &o, s));
+    return o;
+  }
+  he_ct mul_relin(const he_ct& a, const he_ct& b) {
+    he_ct o = fresh();
+    ck(he_mul_relin(h, &a, &b, &o, s));
+    return o;
+  }
+  he_ct mul_const(const he_ct& x, double v, double scale) {
+    he_ct o = fresh();
+    ck(he_mul_const(h, &x, v, scale, &o, s));
+    return o;
+  }
+  he_ct add_const(const he_ct& x, double v) {
+    he_ct o = fresh();
+    ck(he_add_const(h, &x, v, &o, s));
+    return o;
+  }
+  static he_ct drop(const he_ct& x, int level) { return he_ct{x.data, level, x.cap, x.scale}; }
+  // return a temporary's buffer to the pool (later uses are stream-ordered after
+  // every kernel already enqueued on it)
+  void release(const he_ct& x) {
+    for (size_t i = 0; i < held.size(); i++)
+      if (held[i] == x.data) {
+        c->ct_pool.push_back(held[i]);
+        held[i] = held.back();
+        held.pop_back();
+        return;
+      }
+  }
+  he_ct copy(const he_ct& x) {
+    he_ct o = fresh();
+    ck(he_drop_level(h, &x, x.level, &o, s));
+    return o;
+  }
+  // consuming forms: the inputs are temporaries released after use
+  he_ct rescale_take(const he_ct& x) {
+    he_ct o = rescale(x);
+    release(x);
+    return o;
+  }
+  he_ct rot_take(const he_ct& x, int r) {
+    he_ct o = rot(x, r);
+    release(x);
+    return o;
+  }
+  he_ct add_take(const he_ct& a, const he_ct& b) {
+    ck(he_add(h, &a, &b, const_cast<he_ct*>(&a), s));
+    release(b);
+    return a;
+  }
+  void copy_out(const he_ct& x, he_ct* out) {
+    ck(he_drop_level(h, &x, x.level, out, s));
+  }
+};
+
+// sum_t ct_t (.) pt_t, one level, not rescaled
+static he_ct mac_all(Ev& ev, const std::vector<he_ct>& cts, const he_pt* pts) {
+  he_ct acc = ev.mul(cts[0], pts[0]);
+  for (size_t t = 1; t < cts.size(); t++) ev.mac(acc, cts[t], pts[t]);
+  return acc;
+}
+
+// ---------------------------------------------------------------- compaction
+struct Step {
+  int kind, n, key;  // kind 0 col, 1 row, 2 chan
+};
+
+static std::vector<Step> compaction_plan(const he_fmap& fm, int S, int Ho, int Wo) {
+  std::vector<Step> st;
+  if (S > 1) st.push_back({0, Wo, S - 1});
+  int D = S * fm.row_stride - Wo;
+  if (D != 0) st.push_back({1, Ho, D});
+  int E = fm.chan_stride - Ho * Wo;
+  if (E != 0 && fm.channels > 1) st.push_back({2, fm.channels, E});
+  return st;
+}
+static int compaction_masks(const std::vector<Step>& st) {
+  int n = 0;
+  for (auto& x : st) n += x.n;
+  return n;
+}
+
+// acc = RS(v.m_{n-1}); acc = Rot_key(acc) + RS(v.m_t), t = n-2..0
+static he_ct horner_masked(Ev& ev, const he_ct& v, const he_pt* m, int n, int key) {
+  he_ct acc = ev.rescale_take(ev.mul(v, m[n - 1]));
+  for (int t = n - 2; t >= 0; t--) acc = ev.add_take(ev.rot_take(acc, key), ev.rescale_take(ev.mul(v, m[t])));
+  return acc;
+}
+
+static he_ct compaction(Ev& ev, const he_ct& v, const he_fmap& fm, int S, int Ho, int Wo, const he_pt* masks,
+                        he_fmap* out_map) {
+  he_ct cur = v;
+  int pos = 0;
+  for (const Step& st : compaction_plan(fm, S, Ho, Wo)) {
+    he_ct nxt = horner_masked(ev, cur, masks + pos, st.n, st.key);
+    if (pos > 0) ev.release(cur);
+    cur = nxt;
+    pos += st.n;
+  }
+  *out_map = he_fmap{fm.channels, Ho, Wo, Wo, Ho * Wo, 1};
+  return cur;
+}
+
+static void add_keys(std::vector<int>& keys, int k) {
+  for (int x : keys)
+    if (x == k) return;
+  keys.push_back(k);
+}
+
+// ---------------------------------------------------------------- conv plan
+static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P, he_layer_plan* pl) {
+  if (!fm || !pl || F < 1 || k < 1 || S < 1) return set_error(HE_EINVAL, "bad convolution arguments");
+  const int slots = c->n / 2;
+  const int C = fm->channels;
+  std::vector<int> keys;
+  *pl = he_layer_plan{};
+  int ks = 0, lv = 0, nmask = 0;
+  if (k == 3 && P == 1) {
+    const int W = fm->width;
+    if (fm->height != W || fm->row_stride != W || fm->chan_stride != W * W)
+      return set_error(HE_EUNSUPPORTED, "special convolution needs a dense square feature map");
+    if (fm->reps == 1 && (C > 1 || F > 1))
+      return set_error(HE_EUNSUPPORTED, "special convolution with several channels needs a replicated input");
+    if (fm->reps == 2 && 2 * C * W * W != slots) return set_error(HE_EINVAL, "replicated map must fill N/2 slots");
+    if (F * W * W > slots) return set_error(HE_EINVAL, "output channels do not fit the slots");
+    if (S > 2) return set_error(HE_EUNSUPPORTED, "special convolution supports stride 1 or 2");
+    for (int r : {-W, W, -1, 1}) add_keys(keys, r);
+    ks = 8;
+    lv = 1;
+    if (C > 1) { add_keys(keys, W * W); ks += F * (C - 1); }
+    if (C > 1 || F > 1) { nmask = F; lv++; }
+    he_fmap o1{F, W, W, W, W * W, (fm->reps == 2 && 2 * F * W * W == slots) ? 2 : 1};
+    pl->out = o1;
+    if (S > 1) {
+      int Ho = (W - 1) / S + 1;
+      he_fmap f1{F, W, W, W, W * W, 1};
+      auto st = compaction_plan(f1, S, Ho, Ho);
+      for (auto& x : st) { add_keys(keys, x.key); ks += x.n - 1; lv++; }
+      nmask += compaction_masks(st);
+      pl->out = he_fmap{F, Ho, Ho, Ho, Ho * Ho, 1};
+    }
+    pl->n_kernel_pts = 9 * F;
+  } else if (P == 0) {
+    const int H1 = fm->height - k + 1, W1 = fm->width - k + 1;
+    if (H1 < 1 || W1 < 1) return set_error(HE_EINVAL, "kernel larger than the input");
+    if (F * fm->chan_stride > slots) return set_error(HE_EINVAL, "output channels do not fit the slots");
+    for (int i = 0; i < k; i++)
+      for (int j = 0; j < k; j++)
+        if (i || j) add_keys(keys, i * fm->row_stride + j);
+    ks = k * k - 1;
+    lv = 1;
+    if (C > 1) { add_keys(keys, fm->chan_stride); ks += F * (C - 1); nmask = 1; lv++; }
+    if (F > 1) { add_keys(keys, -fm->chan_stride); ks += F - 1; }
+    pl->out = he_fmap{F, H1, W1, fm->row_stride, fm->chan_stride, 1};
+    if (S > 1) {
+      int Ho = (fm->height - k) / S + 1, Wo = (fm->width - k) / S + 1;
+      he_fmap f1{F, H1, W1, fm->row_stride, fm->chan_stride, 1};
+      auto st = compaction_plan(f1, S, Ho, Wo);
+      for (auto& x : st) { add_keys(keys, x.key); ks += x.n - 1; lv++; }
+      nmask += compaction_masks(st);
+      pl->out = he_fmap{F, Ho, Wo, Wo, Ho * Wo, 1};
+    }
+    pl->n_kernel_pts = k * k * F;
+  } else {
+    return set_error(HE_EUNSUPPORTED, "padding other than 0 (or 1 with a 3x3 kernel) is not implemented");
+  }
+  pl->n_mask_pts = nmask;
+  pl->levels = lv;
+  pl->key_switches = ks;
+  pl->n_keys = (int)keys.size();
+  for (int i = 0; i < pl->n_keys && i < 64; i++) pl->rot_keys[i] = keys[i];
+  return HE_OK;
+}
+
+static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, int S, int P, const he_pt* kern,
+                      const he_pt* masks, he_fmap* out_map) {
+  const int C = fm.channels;
+  if (k == 3 && P == 1) {
+    const int W = fm.width;
+    auto g1 = ev.rot_hoisted(x, {-W, W, -1, 1});  // r1, r7, r3, r5
+    auto g2 = ev.rot_hoisted(g1[0], {-1, 1});     // r0, r2
+    auto g3 = ev.rot_hoisted(g1[1], {-1, 1});     // r6, r8
+    std::vector<he_ct> taps = {g2[0], g1[0], g2[1], g1[2], x, g1[3], g3[0], g1[1], g3[1]};
+    const bool place = C > 1 || F > 1;
+    he_ct y{};
+    for (int f = 0; f < F; f++) {
+      he_ct A = ev.rescale_take(mac_all(ev, taps, kern + 9 * f));
+      he_ct Ssum = A;
+      if (C > 1) {
+        // S_f = A_f + Rot_{W^2}(A_f) + Rot_{2 W^2}(A_f) + ..., chained with the single key W^2
+        Ssum = ev.copy(A);
+        he_ct T = A;
+        for (int cc = 1; cc < C; cc++) {
+          he_ct T2 = ev.rot(T, W * W);
+          ev.release(T);
+          ck(he_add(ev.h, &Ssum, &T2, &Ssum, ev.s));
+          T = T2;
+        }
+        ev.release(T);
+      }
+      if (place) {
+        if (f == 0) y = ev.mul(Ssum, masks[0]);
+        else ev.mac(y, Ssum, masks[f]);
+        ev.release(Ssum);
+      } else {
+        y = Ssum;
+      }
+    }
+    int mpos = 0;
+    if (place) {
+      y = ev.rescale_take(y);
+      mpos = F;
+    }
+    for (int t = 0; t < 9; t++)
+      if (t != 4) ev.release(taps[t]);
+    const int slots = ev.c->n / 2;
+    *out_map = he_fmap{F, W, W, W, W * W, (fm.reps == 2 && 2 * F * W * W == slots) ? 2 : 1};
+    if (S == 1) return y;
+    int Ho = (W - 1) / S + 1;
+    he_ct z = compaction(ev, y, he_fmap{F, W, W, W, W * W, 1}, S, Ho, Ho, masks + mpos, out_map);
+    ev.release(y);
+    return z;
+  }
+  // generic
+  std::vector<int> offs;
+  for (int i = 0; i < k; i++)
+    for (int j = 0; j < k; j++)
+      if (i || j) offs.push_back(i * fm.row_stride + j);
+  auto rots = ev.rot_hoisted(x, offs);
+  std::vector<he_ct> taps;
+  taps.push_back(x);
+  for (auto& r : rots) taps.push_back(r);
+  const int cs = fm.chan_stride;
+  he_ct acc{};
+  for (int f = F - 1; f >= 0; f--) {
+    he_ct A = ev.rescale_take(mac_all(ev, taps, kern + k * k * f));
+    he_ct term = A;
+    if (C > 1) {
+      he_ct sum = ev.copy(A);
+      he_ct T = A;
+      for (int cc = 1; cc < C; cc++) {
+        he_ct T2 = ev.rot(T, cs);
+        ev.release(T);
+        ck(he_add(ev.h, &sum, &T2, &sum, ev.s));
+        T = T2;
+      }
+      ev.release(T);
+      term = ev.rescale_take(ev.mul(sum, masks[0]));
+      ev.release(sum);
+    }
+    acc = (f == F - 1) ? term : ev.add_take(ev.rot_take(acc, -cs), term);
+  }
+  for (auto& r : rots) ev.release(r);
+  const int H1 = fm.height - k + 1, W1 = fm.width - k + 1;
+  *out_map = he_fmap{F, H1, W1, fm.row_stride, cs, 1};
+  if (S == 1) return acc;
+  int Ho = (fm.height - k) / S + 1, Wo = (fm.width - k) / S + 1;
+  he_ct z = compaction(ev, acc, he_fmap{F, H1, W1, fm.row_stride, cs, 1}, S, Ho, Wo, masks + (C > 1 ? 1 : 0),
+                       out_map);
+  ev.release(acc);
+  return z;
+}
+
+// ---------------------------------------------------------------- pooling plan
+static int pool_plan(const Ctx* c, const he_fmap* fm, int k, int S, he_layer_plan* pl) {
+  if (!fm || !pl || k < 0 || S < 1) return set_error(HE_EINVAL, "bad pooling arguments");
+  *pl = he_layer_plan{};
+  std::vector<int> keys;
+  int ks = 0;
+  if (k == 0) {
+    const int cs = fm->chan_stride;
+    if (fm->row_stride != fm->width || cs != fm->height * fm->width || (cs & (cs - 1)))
+      return set_error(HE_EUNSUPPORTED, "global pooling needs dense power-of-two channel blocks");
+    for (int t = 1; t < cs; t <<= 1) { add_keys(keys, t); ks++; }
+    if (fm->channels > 1) { add_keys(keys, cs - 1); ks += fm->channels - 1; }
+    pl->n_mask_pts = fm->channels;
+    pl->levels = 1;
+    pl->out = he_fmap{fm->channels, 1, 1, 1, 1, 1};
+  } else {
+    const int H1 = fm->height - k + 1, W1 = fm->width - k + 1;
+    if (H1 < 1 || W1 < 1) return set_error(HE_EINVAL, "window larger than the input");
+    for (int i = 0; i < k; i++)
+      for (int j = 0; j < k; j++)
+        if (i || j) { add_keys(keys, i * fm->row_stride + j); ks++; }
+    if (S == 1) {
+      pl->n_mask_pts = 1;
+      pl->levels = 1;
+      pl->out = he_fmap{fm->channels, H1, W1, fm->row_stride, fm->chan_stride, 1};
+    } else {
+      int Ho = (fm->height - k) / S + 1, Wo = (fm->width - k) / S + 1;
+      he_fmap f1{fm->channels, H1, W1, fm->row_stride, fm->chan_stride, 1};
+      auto st = compaction_plan(f1, S, Ho, Wo);
+      for (auto& x : st) { add_keys(keys, x.key); ks += x.n - 1; }
+      pl->n_mask_pts = compaction_masks(st);
+      pl->levels = (int)st.size();
+      pl->out = he_fmap{fm->channels, Ho, Wo, Wo, Ho * Wo, 1};
+    }
+  }
+  pl->key_switches = ks;
+  pl->n_keys = (int)keys.size();
+  for (int i = 0; i < pl->n_keys && i < 64; i++) pl->rot_keys[i] = keys[i];
+  return HE_OK;
+}
+
+static he_ct pool_run(Ev& ev, const he_ct& x, const he_fmap& fm, int k, int S, const he_pt* masks,
+                      he_fmap* out_map) {
+  if (k == 0) {
+    const int cs = fm.chan_stride;
+    he_ct Ssum = ev.copy(x);
+    for (int t = 1; t < cs; t <<= 1) Ssum = ev.add_take(Ssum, ev.rot(Ssum, t));
+    *out_map = he_fmap{fm.channels, 1, 1, 1, 1, 1};
+    he_ct y = horner_masked(ev, Ssum, masks, fm.channels, cs - 1);
+    ev.release(Ssum);
+    return y;
+  }
+  std::vector<int> offs;
+  for (int i = 0; i < k; i++)
+    for (int j = 0; j < k; j++)
+      if (i || j) offs.push_back(i * fm.row_stride + j);
+  auto rots = ev.rot_hoisted(x, offs);
+  he_ct s = ev.add(x, rots[0]);
+  for (size_t t = 1; t < rots.size(); t++) ev.add_into(s, rots[t]);
+  for (auto& r : rots) ev.release(r);
+  const int H1 = fm.height - k + 1, W1 = fm.width - k + 1;
+  he_fmap f1{fm.channels, H1, W1, fm.row_stride, fm.chan_stride, 1};
+  if (S == 1) {
+    *out_map = f1;
+    return ev.rescale_take(ev.mul(s, masks[0]));
+  }
+  int Ho = (fm.height - k) / S + 1, Wo = (fm.width - k) / S + 1;
+  he_ct z = compaction(ev, s, f1, S, Ho, Wo, masks, out_map);
+  ev.release(s);
+  return z;
+}
+
+static int fc_plan_impl(int n_in, int n_out, he_layer_plan* pl) {
+  if (!pl || n_in < 1 || (n_in & (n_in - 1)) || n_out < 1)
+    return set_error(HE_EINVAL, "n_in must be a power of two and n_out >= 1");
+  *pl = he_layer_plan{};
+  std::vector<int> keys;
+  int ks = 0;
+  for (int t = 1; t < n_in; t <<= 1) { add_keys(keys, t); ks += n_out; }
+  if (n_out > 1) { add_keys(keys, -1); ks += n_out - 1; }
+  pl->n_kernel_pts = n_out;
+  pl->n_mask_pts = 1;
+  pl->levels = 2;
+  pl->key_switches = ks;
+  pl->out = he_fmap{n_out, 1, 1, 1, 1, 1};
+  pl->n_keys = (int)keys.size();
+  for (int i = 0; i < pl->n_keys && i < 64; i++) pl->rot_keys[i] = keys[i];
+  return HE_OK;
+}
+
+}  // namespace he
+
+using namespace he;
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const LayerError& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    return set_error(HE_ENOMEM, "host allocation failed");
+  }
+}
+
+static int check_pts(const Ctx* c, const he_pt* p, int n, int level, const char* what) {
+  if (n > 0 && !p) return set_error(HE_EINVAL, std::string(what) + ": null plaintext array");
+  for (int i = 0; i < n; i++)
+    if (!p[i].data || p[i].level < level)
+      return set_error(HE_ELEVEL, std::string(what) + ": plaintext with too few limbs");
+  (void)c;
+  return HE_OK;
+}
+
+
+extern "C" {
+
+int he_conv2d_plan(const he_ctx* h, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
+                   he_layer_plan* plan) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  return conv_plan(&h->c, in_map, out_ch, kernel, stride, padding, plan);
+}
+
+int he_conv2d(he_ctx* h, const he_ct* in, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
+              const he_pt* kernel_pts, int n_kernel_pts, const he_pt* mask_pts, int n_mask_pts, he_ct* out,
+              he_fmap* out_map, he_stream s) {
+  if (!h || !out_map) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  he_layer_plan pl;
+  int rc;
+  if ((rc = check_ct(c, in, "in"))) return rc;
+  if ((rc = conv_plan(c, in_map, out_ch, kernel, stride, padding, &pl))) return rc;
+  if (n_kernel_pts != pl.n_kernel_pts || n_mask_pts != pl.n_mask_pts)
+    return set_error(HE_EINVAL, "plaintext counts differ from the layer plan");
+  if (in->level <= pl.levels) return set_error(HE_ELEVEL, "not enough levels for the convolution");
+  if ((rc = check_out(c, out, in->level - pl.levels))) return rc;
+  if ((rc = check_pts(c, kernel_pts, n_kernel_pts, in->level, "kernel_pts"))) return rc;
+  if ((rc = check_pts(c, mask_pts, n_mask_pts, in->level - pl.levels + 1, "mask_pts"))) return rc;
+  for (int i = 0; i < pl.n_keys; i++)
+    if (!find_key(c, pl.rot_keys[i]))
+      return set_error(HE_ENOKEY, "rotation key " + std::to_string(pl.rot_keys[i]) + " not resident");
+  return guarded([&] {
+    Ev ev(h, s);
+    he_ct y = conv_run(ev, *in, *in_map, out_ch, kernel, stride, padding, kernel_pts, mask_pts, out_map);
+    ev.copy_out(y, out);
+    return HE_OK;
+  });
+}
+
+int he_avgpool_plan(const he_ctx* h, const he_fmap* in_map, int kernel, int stride, he_layer_plan* plan) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  return pool_plan(&h->c, in_map, kernel, stride, plan);
+}
+
+int he_avgpool(he_ctx* h, const he_ct* in, const he_fmap* in_map, int kernel, int stride, const he_pt* mask_pts,
+               int n_mask_pts, he_ct* out, he_fmap* out_map, he_stream s) {
+  if (!h || !out_map) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  he_layer_plan pl;
+  int rc;
+  if ((rc = check_ct(c, in, "in"))) return rc;
+  if ((rc = pool_plan(c, in_map, kernel, stride, &pl))) return rc;
+  if (n_mask_pts != pl.n_mask_pts) return set_error(HE_EINVAL, "mask count differs from the layer plan");
+  if (in->level <= pl.levels) return set_error(HE_ELEVEL, "not enough levels for the pooling");
+  if ((rc = check_out(c, out, in->level - pl.levels))) return rc;
+  if ((rc = check_pts(c, mask_pts, n_mask_pts, in->level, "mask_pts"))) return rc;
+  for (int i = 0; i < pl.n_keys; i++)
+    if (!find_key(c, pl.rot_keys[i]))
+      return set_error(HE_ENOKEY, "rotation key " + std::to_string(pl.rot_keys[i]) + " not resident");
+  return guarded([&] {
+    Ev ev(h, s);
+    he_ct y = pool_run(ev, *in, *in_map, kernel, stride, mask_pts, out_map);
+    ev.copy_out(y, out);
+    return HE_OK;
+  });
+}
+
+int he_fc_plan(const he_ctx* h, int n_in, int n_out, he_layer_plan* plan) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  return fc_plan_impl(n_in, n_out, plan);
+}
+
+int he_fc(he_ctx* h, const he_ct* in, int n_in, int n_out, const he_pt* weight_pts, const he_pt* mask_pts,
+          const he_pt* bias_pt, he_ct* out, he_stream s) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  he_layer_plan pl;
+  int rc;
+  if ((rc = check_ct(c, in, "in"))) return rc;
+  if ((rc = fc_plan_impl(n_in, n_out, &pl))) return rc;
+  if (n_in > c->n / 2 || n_out > c->n / 2) return set_error(HE_EINVAL, "vector longer than the slots");
+  if (in->level <= 2) return set_error(HE_ELEVEL, "not enough levels for the fully connected layer");
+  if ((rc = check_out(c, out, in->level - 2))) return rc;
+  if ((rc = check_pts(c, weight_pts, n_out, in->level, "weight_pts")) ||
+      (rc = check_pts(c, mask_pts, 1, in->level - 1, "mask_pts")))
+    return rc;
+  for (int i = 0; i < pl.n_keys; i++)
+    if (!find_key(c, pl.rot_keys[i]))
+      return set_error(HE_ENOKEY, "rotation key " + std::to_string(pl.rot_keys[i]) + " not resident");
+  return guarded([&] {
+    Ev ev(h, s);
+    auto neuron = [&](int k) {
+      he_ct P = ev.rescale_take(ev.mul(*in, weight_pts[k]));
+      for (int t = 1; t < n_in; t <<= 1) P = ev.add_take(P, ev.rot(P, t));
+      he_ct r = ev.rescale_take(ev.mul(P, mask_pts[0]));
+      ev.release(P);
+      return r;
+    };
+    he_ct acc = neuron(n_out - 1);
+    for (int k = n_out - 2; k >= 0; k--) acc = ev.add_take(ev.rot_take(acc, -1), neuron(k));
+    if (bias_pt) ck(he_add_plain(h, &acc, bias_pt, &acc, s));
+    ev.copy_out(acc, out);
+    return HE_OK;
+  });
+}
+
+int he_poly4(he_ctx* h, const he_ct* in, const double* cf, double delta, he_ct* out, he_stream s) {
+  if (!h || !cf) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in"))) return rc;
+  if (cf[3] != 0.0) return set_error(HE_EUNSUPPORTED, "the cubic coefficient must be zero");
+  if (in->level <= 3) return set_error(HE_ELEVEL, "the polynomial needs three levels");
+  if ((rc = check_out(c, out, in->level - 3))) return rc;
+  if (!find_key(c, HE_KEY_RELIN)) return set_error(HE_ENOKEY, "relinearization key not resident");
+  return guarded([&] {
+    Ev ev(h, s);
+    const he_ct& x = *in;
+    he_ct x2 = ev.rescale(ev.mul_relin(x, x));
+    he_ct t = ev.add_const(ev.rescale(ev.mul_const(x2, cf[4], delta)), cf[2]);
+    he_ct v = ev.rescale(ev.mul_relin(Ev::drop(x2, t.level), t));
+    const double q = (double)c->mod[v.level];
+    const double sigma = v.scale * q / x.scale;
+    he_ct lin = ev.rescale(ev.mul_const(Ev::drop(x, v.level + 1), cf[1], sigma));
+    lin.scale = v.scale;
+    he_ct p = ev.add_const(ev.add(v, lin), cf[0]);
+    ev.copy_out(p, out);
+    return HE_OK;
+  });
+}
+
+}  // extern "C"

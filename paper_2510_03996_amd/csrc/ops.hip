@@ -1,5 +1,7 @@
 // Exact ring operations on ciphertexts: add / sub / pt-ct multiply(-accumulate),
 // rescale, level drop.  One thread per residue, limb-major coalesced access.
+#include <cmath>
+
 #include "internal.h"
 
 namespace he {
@@ -55,6 +57,40 @@ __global__ __launch_bounds__(256) void k_rescale_combine(const uint64_t* in, siz
   const uint64_t v = rescale_elem(in[k * ips + i * n + j], R[((size_t)k * nl + i) * n + j], tab[i], tab[nl + i],
                                   mods[i].q);
   out[k * ops + i * n + j] = v;
+}
+
+// per-limb scalar constants (Shoup pairs) for constant-polynomial plaintexts
+struct Scalars {
+  uint64_t w[64];
+  uint64_t wp[64];
+};
+
+// mode 0: out[k][i][j] = in[k][i][j] * w_i;  mode 1: out[0] = in[0] + w_i, out[1] = in[1]
+__global__ __launch_bounds__(256) void k_scalar(const uint64_t* in, size_t ips, uint64_t* out, size_t ops, int logn,
+                                                const ModInfo* __restrict__ mods, Scalars sc, int mode) {
+  const size_t n = (size_t)1 << logn;
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, k = blockIdx.z;
+  const uint64_t q = mods[i].q;
+  const uint64_t x = in[k * ips + i * n + j];
+  uint64_t r;
+  if (mode == 0) r = mul_shoup(x, sc.w[i], sc.wp[i], q);
+  else r = k == 0 ? add_mod(x, sc.w[i], q) : x;
+  out[k * ops + i * n + j] = r;
+}
+
+// llround(c * scale) reduced into every active limb (ties away from zero)
+static int const_residues(const Ctx* c, double v, double scale, int level, Scalars* sc) {
+  const double x = v * scale;
+  if (!(std::fabs(x) < 9.0e18)) return set_error(HE_EINVAL, "constant times scale does not fit 64 bits");
+  const long long r = llround(x);
+  for (int i = 0; i < level; i++) {
+    const uint64_t q = c->mod[i];
+    uint64_t m = r >= 0 ? (uint64_t)r % q : (q - ((uint64_t)(-(r + 1)) + 1) % q) % q;
+    sc->w[i] = m;
+    sc->wp[i] = (uint64_t)(((unsigned __int128)m << 64) / q);
+  }
+  return HE_OK;
 }
 
 int check_ct(const Ctx* c, const he_ct* x, const char* what) {
@@ -166,6 +202,39 @@ int he_rescale(he_ctx* h, const he_ct* in, he_ct* out, he_stream st) {
   HE_HIP(hipGetLastError());
   out->level = t;
   out->scale = in->scale / (double)c->mod[t];
+  return HE_OK;
+}
+
+int he_mul_const(he_ctx* h, const he_ct* in, double v, double scale, he_ct* out, he_stream st) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in")) || (rc = check_out(c, out, in->level))) return rc;
+  Scalars sc;
+  if ((rc = const_residues(c, v, scale, in->level, &sc))) return rc;
+  const size_t N = c->n;
+  ProfScope ps(c, "mul_const", (hipStream_t)st, 32.0 * N * in->level, 2.0 * N * in->level);
+  k_scalar<<<grid_for(c, in->level, 2), 256, 0, (hipStream_t)st>>>(in->data, in->cap * N, out->data, out->cap * N,
+                                                                     c->log_n, c->d_mod, sc, 0);
+  HE_HIP(hipGetLastError());
+  out->level = in->level;
+  out->scale = in->scale * scale;
+  return HE_OK;
+}
+
+int he_add_const(he_ctx* h, const he_ct* in, double v, he_ct* out, he_stream st) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in")) || (rc = check_out(c, out, in->level))) return rc;
+  Scalars sc;
+  if ((rc = const_residues(c, v, in->scale, in->level, &sc))) return rc;
+  const size_t N = c->n;
+  k_scalar<<<grid_for(c, in->level, 2), 256, 0, (hipStream_t)st>>>(in->data, in->cap * N, out->data, out->cap * N,
+                                                                     c->log_n, c->d_mod, sc, 1);
+  HE_HIP(hipGetLastError());
+  out->level = in->level;
+  out->scale = in->scale;
   return HE_OK;
 }
 

@@ -47,6 +47,29 @@ class he_pt(ctypes.Structure):
     _fields_ = [("data", ctypes.c_void_p), ("level", ctypes.c_int32), ("scale", ctypes.c_double)]
 
 
+class he_fmap(ctypes.Structure):
+    _fields_ = [("channels", ctypes.c_int32), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("row_stride", ctypes.c_int32), ("chan_stride", ctypes.c_int32), ("reps", ctypes.c_int32)]
+
+    def key(self):
+        return (self.channels, self.height, self.width, self.row_stride, self.chan_stride, self.reps)
+
+
+def fmap(C, H, W, rs=None, cs=None, reps=1):
+    rs = W if rs is None else rs
+    cs = H * rs if cs is None else cs
+    return he_fmap(C, H, W, rs, cs, reps)
+
+
+class he_layer_plan(ctypes.Structure):
+    _fields_ = [("n_kernel_pts", ctypes.c_int32), ("n_mask_pts", ctypes.c_int32), ("n_keys", ctypes.c_int32),
+                ("rot_keys", ctypes.c_int32 * 64), ("levels", ctypes.c_int32), ("key_switches", ctypes.c_int32),
+                ("out", he_fmap)]
+
+    def keys(self):
+        return [int(self.rot_keys[i]) for i in range(self.n_keys)]
+
+
 _lib = None
 
 
@@ -78,6 +101,18 @@ def lib():
             "he_drop_level": [vp, P(he_ct), c_int, P(he_ct), vp],
             "he_mul_relin": [vp, P(he_ct), P(he_ct), P(he_ct), vp],
             "he_relin": [vp, vp, c_int, ctypes.c_double, P(he_ct), vp],
+            "he_mul_const": [vp, P(he_ct), ctypes.c_double, ctypes.c_double, P(he_ct), vp],
+            "he_add_const": [vp, P(he_ct), ctypes.c_double, P(he_ct), vp],
+            "he_conv2d_plan": [vp, P(he_fmap), c_int, c_int, c_int, c_int, P(he_layer_plan)],
+            "he_conv2d": [vp, P(he_ct), P(he_fmap), c_int, c_int, c_int, c_int, P(he_pt), c_int, P(he_pt), c_int,
+                          P(he_ct), P(he_fmap), vp],
+            "he_avgpool_plan": [vp, P(he_fmap), c_int, c_int, P(he_layer_plan)],
+            "he_avgpool": [vp, P(he_ct), P(he_fmap), c_int, c_int, P(he_pt), c_int, P(he_ct), P(he_fmap), vp],
+            "he_fc_plan": [vp, c_int, c_int, P(he_layer_plan)],
+            "he_fc": [vp, P(he_ct), c_int, c_int, P(he_pt), P(he_pt), P(he_pt), P(he_ct), vp],
+            "he_poly4": [vp, P(he_ct), P(ctypes.c_double), ctypes.c_double, P(he_ct), vp],
+            "he_profile_begin": [vp],
+            "he_profile_end": [vp, ctypes.c_char_p, sz],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -141,6 +176,11 @@ class Plaintext:
 
     def c(self):
         return he_pt(ctypes.c_void_p(self.data.data_ptr()), self.level, self.scale)
+
+
+def _pts(pts):
+    arr = (he_pt * max(1, len(pts)))(*[p.c() for p in pts])
+    return arr
 
 
 def to_device(arr_u64, device="cuda"):
@@ -295,3 +335,79 @@ class Context:
         _check(lib().he_relin(self.h, _ptr(d), level, scale, ctypes.byref(o), _stream(stream)))
         out.update(o)
         return out
+
+    # ---- constants
+    def mul_const(self, ct, c, scale, out=None, stream=None):
+        out = out or self.new_ct(ct.cap)
+        a, o = ct.c(), out.c()
+        _check(lib().he_mul_const(self.h, ctypes.byref(a), float(c), float(scale), ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    def add_const(self, ct, c, out=None, stream=None):
+        out = out or self.new_ct(ct.cap)
+        a, o = ct.c(), out.c()
+        _check(lib().he_add_const(self.h, ctypes.byref(a), float(c), ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    # ---- layers
+    def conv2d_plan(self, fm, out_ch, kernel, stride, padding):
+        pl = he_layer_plan()
+        _check(lib().he_conv2d_plan(self.h, ctypes.byref(fm), out_ch, kernel, stride, padding, ctypes.byref(pl)))
+        return pl
+
+    def conv2d(self, ct, fm, out_ch, kernel, stride, padding, kernel_pts, mask_pts, out=None, stream=None):
+        out = out or self.new_ct(ct.cap)
+        a, o, om = ct.c(), out.c(), he_fmap()
+        _check(lib().he_conv2d(self.h, ctypes.byref(a), ctypes.byref(fm), out_ch, kernel, stride, padding,
+                               _pts(kernel_pts), len(kernel_pts), _pts(mask_pts), len(mask_pts), ctypes.byref(o),
+                               ctypes.byref(om), _stream(stream)))
+        out.update(o)
+        return out, om
+
+    def avgpool_plan(self, fm, kernel, stride):
+        pl = he_layer_plan()
+        _check(lib().he_avgpool_plan(self.h, ctypes.byref(fm), kernel, stride, ctypes.byref(pl)))
+        return pl
+
+    def avgpool(self, ct, fm, kernel, stride, mask_pts, out=None, stream=None):
+        out = out or self.new_ct(ct.cap)
+        a, o, om = ct.c(), out.c(), he_fmap()
+        _check(lib().he_avgpool(self.h, ctypes.byref(a), ctypes.byref(fm), kernel, stride, _pts(mask_pts),
+                                len(mask_pts), ctypes.byref(o), ctypes.byref(om), _stream(stream)))
+        out.update(o)
+        return out, om
+
+    def fc_plan(self, n_in, n_out):
+        pl = he_layer_plan()
+        _check(lib().he_fc_plan(self.h, n_in, n_out, ctypes.byref(pl)))
+        return pl
+
+    def fc(self, ct, n_in, n_out, weight_pts, mask_pts, bias_pt=None, out=None, stream=None):
+        out = out or self.new_ct(ct.cap)
+        a, o = ct.c(), out.c()
+        b = ctypes.byref(bias_pt.c()) if bias_pt is not None else None
+        _check(lib().he_fc(self.h, ctypes.byref(a), n_in, n_out, _pts(weight_pts), _pts(mask_pts), b,
+                           ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    def poly4(self, ct, coeffs, delta, out=None, stream=None):
+        out = out or self.new_ct(ct.cap)
+        a, o = ct.c(), out.c()
+        cf = (ctypes.c_double * 5)(*[float(x) for x in coeffs])
+        _check(lib().he_poly4(self.h, ctypes.byref(a), cf, float(delta), ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    # ---- measurement
+    def profile_begin(self):
+        _check(lib().he_profile_begin(self.h))
+
+    def profile_end(self):
+        import json
+
+        buf = ctypes.create_string_buffer(1 << 16)
+        n = _check(lib().he_profile_end(self.h, buf, len(buf)))
+        return json.loads(buf.value[:n].decode())

@@ -1,0 +1,220 @@
+"""GPU vs oracle parity for the layer schedules (needs MI355X).
+
+Every layer output is compared with the oracle's ciphertext on every limb
+(same keys, same encrypted input, same oracle-encoded plaintexts), and its
+decryption with the paper's FP64 layer equation.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import ckks
+from oracle import layers as LY
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+RELU_COEFFS = [LY.RELU4[0], LY.RELU4[1], LY.RELU4[2], 0.0, LY.RELU4[4]]
+
+
+@pytest.fixture(scope="module")
+def gctx():
+    cache = {}
+
+    def get(name):
+        if name not in cache:
+            cache[name] = H.gpu_ctx(name)
+        return cache[name]
+
+    yield get
+    for c in cache.values():
+        c.close()
+
+
+def setup_keys(g, name, rots, relin=False):
+    from paper_2510_03996_amd import he
+
+    for r in rots:
+        g.key_upload(r, H.oracle_key(name, r))
+    if relin:
+        g.key_upload(he.KEY_RELIN, H.oracle_key(name, "relin"))
+    return LY.HEEval(H.oracle_ctx(name)[0], H.oracle_keys(name, rots),
+                     H.oracle_key(name, "relin") if relin else None)
+
+
+def encode(octx, vecs, level):
+    return [octx.encode(v, octx.pr.scale, level) for v in vecs]
+
+
+def gpts(g, pts):
+    return [g.pt_from_numpy(p.data, p.scale) for p in pts]
+
+
+def check_ct(got, want, what):
+    H.assert_limbs_equal(got.numpy(), want.data, what)
+    assert got.level == want.level and got.scale == want.scale, what
+
+
+def fm_he(fm):
+    from paper_2510_03996_amd import he
+
+    return he.he_fmap(*fm.key())
+
+
+def encrypt_map(name, X, fm, seed, level=None):
+    octx, _, _ = H.oracle_ctx(name)
+    _, ct = H.encrypt_slots(name, seed, level=level, values=LY.pack(X, fm, octx.n // 2))
+    return ct
+
+
+def run_conv(g, name, X, K, fm, stride, padding, seed, level=None):
+    octx, sk, _ = H.oracle_ctx(name)
+    slots = octx.n // 2
+    F, _, k, _ = K.shape
+    plan = g.conv2d_plan(fm_he(fm), F, k, stride, padding)
+    assert sorted(plan.keys()) == LY.conv_rotations(fm, F, k, stride, padding, slots)
+    ev = setup_keys(g, name, plan.keys())
+    ct = encrypt_map(name, X, fm, seed, level)
+    kern, masks = LY.conv_plaintexts(fm, K, stride, padding, slots)
+    assert (plan.n_kernel_pts, plan.n_mask_pts) == (len(kern), len(masks))
+    kp, mp = encode(octx, kern, ct.level), encode(octx, masks, ct.level)
+    want, fo = LY.conv2d(ev, ct, fm, F, k, stride, padding, kp, mp, slots)
+    assert ev.ks == plan.key_switches and ct.level - want.level == plan.levels
+    got, gfm = g.conv2d(g.ct_from_numpy(ct.data, ct.scale), fm_he(fm), F, k, stride, padding, gpts(g, kp),
+                        gpts(g, mp))
+    assert gfm.key() == fo.key()
+    check_ct(got, want, "conv2d")
+    dec = LY.unpack(octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale)), fo)
+    err = np.max(np.abs(dec - LY.conv2d_ref(X, K, stride, padding)))
+    assert err < 1e-3, err
+    return got, want, fo
+
+
+def test_config0_special_conv(gctx):
+    X = synth.image(20, 1, 8, 8)
+    K = synth.conv_weights(20, 1, 1, 3, 0.1)
+    run_conv(gctx("config0"), "config0", X, K, LY.FMap(1, 8, 8), 1, 1, 20)
+
+
+def test_config1_generic_conv_multichannel_stride(gctx):
+    """C=3 -> F=4, 3x3, stride 2, pad 0 at N=2^14 (channel chain, block-0 mask, placement, compaction)."""
+    X = synth.image(21, 3, 12, 12)
+    K = synth.conv_weights(21, 4, 3, 3, 0.2)
+    run_conv(gctx("config1"), "config1", X, K, LY.FMap(3, 12, 12), 2, 0, 21)
+
+
+def test_config1_lenet_stack(gctx):
+    """LeNet-5-shaped stack: conv 5x5 1->6 -> degree-4 ReLU -> 2x2 avgpool (7 levels)."""
+    name = "config1"
+    g = gctx(name)
+    octx, sk, _ = H.oracle_ctx(name)
+    slots = octx.n // 2
+    X = synth.image(22, 1, 28, 28)
+    K = synth.conv_weights(22, 6, 1, 5, 0.1)
+    fm = LY.FMap(1, 28, 28)
+    got, want, f1 = run_conv(g, name, X, K, fm, 1, 0, 22)
+    # polynomial ReLU
+    ev = setup_keys(g, name, [], relin=True)
+    pw = LY.relu_poly4(ev, want, octx.pr.scale)
+    pg = g.poly4(got, RELU_COEFFS, octx.pr.scale)
+    check_ct(pg, pw, "poly4")
+    # pooling
+    plan = g.avgpool_plan(fm_he(f1), 2, 2)
+    assert sorted(plan.keys()) == LY.avgpool_rotations(f1, 2, 2)
+    ev = setup_keys(g, name, plan.keys())
+    mp = encode(octx, LY.avgpool_plaintexts(f1, 2, 2, slots), pw.level)
+    zw, f2 = LY.avgpool(ev, pw, f1, 2, 2, mp)
+    zg, gf2 = g.avgpool(pg, fm_he(f1), 2, 2, gpts(g, mp))
+    assert gf2.key() == f2.key() and zw.level == 1
+    check_ct(zg, zw, "avgpool")
+    ref = LY.avgpool_ref(LY.relu4_ref(LY.conv2d_ref(X, K, 1, 0)), 2, 2)
+    dec = LY.unpack(octx.decrypt(sk, ckks.Ciphertext(zg.numpy(), zg.scale)), f2)
+    assert np.max(np.abs(dec - ref)) < 1e-2
+
+
+def test_config2_small_special_conv(gctx):
+    """4 replicated channels of 64x64 at N=2^16, L=24 (20 key switches)."""
+    X = synth.image(23, 4, 64, 64)
+    K = synth.conv_weights(23, 4, 4, 3, (2.0 / 36) ** 0.5)
+    run_conv(gctx("config2"), "config2", X, K, LY.FMap(4, 64, 64, reps=2), 1, 1, 23)
+
+
+def test_config2_conv_a(gctx):
+    """ResNet-20-shaped conv 3x3 16->16, stride 1, pad 1 on a replicated 16x32x32 input (248 key switches)."""
+    X = synth.image(24, 16, 32, 32)
+    K = synth.conv_weights(24, 16, 16, 3, (2.0 / 144) ** 0.5)
+    got, want, fo = run_conv(gctx("config2"), "config2", X, K, LY.FMap(16, 32, 32, reps=2), 1, 1, 24)
+    assert fo.reps == 2
+
+
+def test_config2_conv_b(gctx):
+    """conv 3x3 16->32, stride 2, pad 1 at level 22 (549 key switches, joint stride compaction)."""
+    X = synth.image(25, 16, 32, 32)
+    K = synth.conv_weights(25, 32, 16, 3, (2.0 / 144) ** 0.5)
+    run_conv(gctx("config2"), "config2", X, K, LY.FMap(16, 32, 32, reps=2), 2, 1, 25, level=22)
+
+
+@pytest.mark.parametrize("C,HW,level", [(32, 16, 17), (64, 8, 17)])
+def test_config2_global_avgpool(gctx, C, HW, level):
+    name = "config2"
+    g = gctx(name)
+    octx, sk, _ = H.oracle_ctx(name)
+    slots = octx.n // 2
+    X = synth.image(26, C, HW, HW)
+    fm = LY.FMap(C, HW, HW)
+    plan = g.avgpool_plan(fm_he(fm), 0, 1)
+    assert sorted(plan.keys()) == LY.gap_rotations(fm)
+    ev = setup_keys(g, name, plan.keys())
+    ct = encrypt_map(name, X, fm, 26, level)
+    mp = encode(octx, LY.gap_plaintexts(fm, slots), ct.level)
+    want, fo = LY.gap(ev, ct, fm, mp)
+    got, gfo = g.avgpool(g.ct_from_numpy(ct.data, ct.scale), fm_he(fm), 0, 1, gpts(g, mp))
+    assert ev.ks == plan.key_switches
+    check_ct(got, want, "global avgpool")
+    dec = octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale))
+    assert np.max(np.abs(dec[:C] - LY.gap_ref(X))) < 1e-3
+
+
+def test_config2_fc(gctx):
+    name = "config2"
+    g = gctx(name)
+    octx, sk, _ = H.oracle_ctx(name)
+    slots = octx.n // 2
+    x = np.zeros(64)
+    x[:32] = synth.uniform_slots(27, 32)  # global pooling of 32 channels, zeros above (64-slot input)
+    Wm = synth.fc_weights(27, 10, 64, (2.0 / 64) ** 0.5)
+    plan = g.fc_plan(64, 10)
+    assert sorted(plan.keys()) == LY.fc_rotations(64, 10)
+    ev = setup_keys(g, name, plan.keys())
+    v = np.zeros(slots)
+    v[:64] = x
+    _, ct = H.encrypt_slots(name, 27, level=16, values=v)
+    rows, masks = LY.fc_plaintexts(Wm, slots)
+    rp, mp = encode(octx, rows, ct.level), encode(octx, masks, ct.level)
+    want = LY.fc(ev, ct, 64, 10, rp, mp)
+    got = g.fc(g.ct_from_numpy(ct.data, ct.scale), 64, 10, gpts(g, rp), gpts(g, mp))
+    assert ev.ks == plan.key_switches == 69
+    check_ct(got, want, "fc")
+    dec = octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale))
+    assert np.max(np.abs(dec[:10] - LY.fc_ref(x, Wm))) < 1e-3
+
+
+def test_layer_errors(gctx):
+    from paper_2510_03996_amd import he
+
+    name = "config1"
+    g = gctx(name)
+    fm = he.fmap(1, 28, 28)
+    with pytest.raises(he.HEError) as e:
+        g.conv2d_plan(fm, 6, 5, 1, 2)
+    assert e.value.name == "HE_EUNSUPPORTED"
+    _, ct = H.encrypt_slots(name, 28, level=2)
+    gct = g.ct_from_numpy(ct.data, ct.scale)
+    plan = g.conv2d_plan(fm, 6, 5, 1, 0)
+    with pytest.raises(he.HEError) as e:  # wrong plaintext count
+        g.conv2d(gct, fm, 6, 5, 1, 0, [], [])
+    assert e.value.name == "HE_EINVAL"
+    with pytest.raises(he.HEError) as e:  # level 2 cannot afford 3-level polynomial
+        g.poly4(gct, RELU_COEFFS, 2.0 ** 45)
+    assert e.value.name in ("HE_ELEVEL", "HE_ENOKEY")
+    assert plan.n_kernel_pts == 150

@@ -250,6 +250,54 @@ int he_fc(he_ctx* ctx, const he_ct* in, int n_in, int n_out, const he_pt* weight
  * fit of max(0, x) on [-1, 1] this is the LeNet-5-shaped stack's ReLU. */
 int he_poly4(he_ctx* ctx, const he_ct* in, const double* c, double delta, he_ct* out, he_stream stream);
 
+/* ------------------------------------------------------------ batching
+ * Many ciphertexts, each with its own hoisted rotation set and its own
+ * number of outputs:
+ *   out[i, o] = RS( sum_t pool[pt_index(i, o, t)] (.) Rot_{rots_i[t]}(in_i) )
+ * (the multiply-accumulate of rotated copies that every convolution and
+ * pooling stage of the paper's layers performs, Section "Secure Convolution
+ * Layer").  All inputs share one level l >= 2 and scale; the result has
+ * level l-1 and scale in_scale * pt_scale / q_{l-1}, and is bit-identical to
+ * he_rotate_hoisted + he_mul_plain (accumulate) + he_rescale per output.
+ * Layouts (device memory, caller-owned, kept alive while the batch exists):
+ *   in      [n_items][2][l][N]
+ *   pool    [n_pool][pool_level][N] (pool_level >= l)
+ *   out     [sum n_out][2][l-1][N], item-major, outputs in order
+ * Host arrays (copied at creation): n_rot[i] (1..64 distinct non-zero
+ * amounts per item, keys resident), rots (concatenated), n_out[i] >= 1,
+ * pt_index (for item i: n_out[i] x n_rot[i] pool indices, o-major).
+ * The batched schedule runs ModUp once per input, one key inner product per
+ * distinct key for all its ciphertexts, batched ModDown, one fused
+ * multiply-accumulate kernel and chunked rescaling.  HE_BATCH_GRAPH: the
+ * first he_batch_run on a (non-default) stream captures the schedule in a
+ * hipGraph, later runs replay it.  HE_BATCH_TILE128: 128-coefficient MAC
+ * tiles instead of 64.  Workspace memory is allocated at creation and
+ * released by he_batch_destroy. */
+#define HE_BATCH_GRAPH 1
+#define HE_BATCH_TILE128 2
+typedef struct he_batch he_batch;
+typedef struct {
+  int32_t n_items;
+  int32_t level;
+  double in_scale, pt_scale;
+  const uint64_t* in;
+  const int32_t* n_rot;
+  const int32_t* rots;
+  const int32_t* n_out;
+  const uint64_t* pool;
+  int32_t n_pool, pool_level;
+  const int32_t* pt_index;
+  uint64_t* out;
+} he_batch_desc;
+int he_batch_create(he_ctx* ctx, const he_batch_desc* desc, int flags, he_batch** out);
+int he_batch_run(he_batch* batch, he_stream stream);
+/* The same work through the per-op entry points, one ciphertext at a time
+ * (the plain path the batched schedule is measured against). */
+int he_batch_run_plain(he_batch* batch, he_stream stream);
+int he_batch_info(const he_batch* batch, int32_t* total_rotations, int32_t* total_outputs, int32_t* distinct_keys,
+                  double* out_scale);
+int he_batch_destroy(he_batch* batch);
+
 /* ------------------------------------------------------------ measurement
  * Per-kernel timing: after he_profile_begin, every kernel launch of this
  * context is bracketed by a HIP event pair on its stream.  he_profile_end

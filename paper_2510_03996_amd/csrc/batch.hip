@@ -1,0 +1,494 @@
+// Batched hoisted-rotation multiply-accumulate over many ciphertexts.
+//
+// Work item (ciphertext i, output o):
+//   out[i,o] = RS( sum_t pool[idx(i,o,t)] (.) Rot_{r_{i,t}}(in_i) )
+// which is the shape of every convolution / pooling stage of the paper's
+// layers (rotated copies of one input, each multiplied by a plaintext and
+// summed) and of the batched key-switching workload.
+//
+// Batched schedule (one stream, optionally captured once in a hipGraph):
+//   1. ModUp of every input at once (one iNTT, one BConv, one NTT launch);
+//   2. key-major key switching: for each distinct rotation key, ONE inner-
+//      product launch loads each key residue once and applies it to every
+//      ciphertext that uses that key (the key is read from HBM once per
+//      batch instead of once per rotation), then one batched ModDown for all
+//      of that key's rotations;
+//   3. one fused MAC launch for all outputs: each thread stages its
+//      coefficient of the input's rotated copies in LDS and accumulates every
+//      output with 128-bit products (one reduction per output residue);
+//   4. rescale of all outputs in chunks.
+// The result is bit-identical to the per-op path (he_rotate_hoisted,
+// he_mul_plain, he_rescale), which he_batch_run_plain executes for
+// comparison: every step is the same exact modular arithmetic.
+#include <algorithm>
+#include <map>
+#include <vector>
+
+#include "internal.h"
+
+namespace he {
+
+constexpr int BATCH_NMAX = 64;  // rotations per ciphertext in one batch
+
+// ---------------------------------------------------------------- kernels
+// Inner product of one key with the extended digits of every pair using it.
+// grid: x = coefficient tile, y = extended limb.  Pair p uses input item[p].
+__global__ __launch_bounds__(256) void k_ip_multi(const uint64_t* __restrict__ ext_all, size_t ext_item,
+                                                  const uint64_t* __restrict__ in_all, size_t in_item, int level,
+                                                  int K, int alpha, int dnum, const uint64_t* __restrict__ key,
+                                                  size_t key_digit_stride, size_t key_poly_stride, int L, uint32_t g,
+                                                  int logn, const ModInfo* __restrict__ mods,
+                                                  const int32_t* __restrict__ items, int npairs,
+                                                  uint64_t* __restrict__ u_all) {
+  const size_t n = (size_t)1 << logn;
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int pos = blockIdx.y;
+  const int E = level + K;
+  const int mod = pos < level ? pos : L + (pos - level);
+  const ModInfo mi = mods[mod];
+  const uint32_t src = g == 1 ? k : automorph_src(k, g, logn);
+  uint64_t kb[MAX_DIGITS], ka[MAX_DIGITS];
+  for (int j = 0; j < dnum; j++) {
+    const uint64_t* kj = key + j * key_digit_stride + (size_t)mod * n + k;
+    kb[j] = kj[0];
+    ka[j] = kj[key_poly_stride];
+  }
+  const int own = pos < level ? pos / alpha : -1;
+  const size_t En = (size_t)E * n;
+  for (int p = 0; p < npairs; p++) {
+    const int it = items[p];
+    const uint64_t* c1 = in_all + it * in_item + (size_t)level * n;
+    const uint64_t* ext = ext_all + it * ext_item;
+    U128 a0{0, 0}, a1{0, 0};
+    for (int j = 0; j < dnum; j++) {
+      const uint64_t* sp = j == own ? c1 : ext + j * En;
+      const uint64_t e = sp[(size_t)pos * n + src];
+      add_wide(a0, mul_wide(e, kb[j]));
+      add_wide(a1, mul_wide(e, ka[j]));
+    }
+    uint64_t* u = u_all + (size_t)p * 2 * En + (size_t)pos * n + k;
+    u[0] = mont_redc(a0, mi.q, mi.qinv);
+    u[En] = mont_redc(a1, mi.q, mi.qinv);
+  }
+}
+
+// ModDown epilogue for every pair of one key: z = 2 pair + poly.
+__global__ __launch_bounds__(256) void k_combine_multi(const uint64_t* __restrict__ u_all, size_t En,
+                                                       const uint64_t* __restrict__ y_all,
+                                                       const uint64_t* __restrict__ in_all, size_t in_item,
+                                                       const int32_t* __restrict__ items, uint32_t g,
+                                                       uint64_t* __restrict__ rot_out, int level, int logn,
+                                                       const ModInfo* __restrict__ mods,
+                                                       const uint64_t* __restrict__ pinv) {
+  const size_t n = (size_t)1 << logn;
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, z = blockIdx.z;
+  const int pair = z >> 1, poly = z & 1;
+  const uint64_t q = mods[i].q;
+  const size_t ln = (size_t)level * n;
+  uint64_t a = 0;
+  if (poly == 0) a = in_all[items[pair] * in_item + (size_t)i * n + (g == 1 ? k : automorph_src(k, g, logn))];
+  const uint64_t v = moddown_elem(u_all[(size_t)pair * 2 * En + poly * En + (size_t)i * n + k],
+                                  y_all[(size_t)z * ln + (size_t)i * n + k], a, pinv[i], pinv[level + i], q);
+  rot_out[(size_t)z * ln + (size_t)i * n + k] = v;
+}
+
+// out[i,o] (unrescaled) for every item: grid x = tile of TILE coefficients,
+// y = limb, z = item.  Each thread stages its coefficient of the item's n
+// rotated copies (both polynomials) in its own LDS column, then accumulates
+// every output with 128-bit products kept below q 2^64.
+template <int TILE>
+__global__ __launch_bounds__(TILE) void k_mac_multi(int nmax,const uint64_t* __restrict__ rot_all, int level, int logn,
+                                                    const ModInfo* __restrict__ mods,
+                                                    const int32_t* __restrict__ rot_off,
+                                                    const int32_t* __restrict__ rot_idx,
+                                                    const int32_t* __restrict__ out_off,
+                                                    const int32_t* __restrict__ pt_off,
+                                                    const int32_t* __restrict__ pt_index,
+                                                    const uint64_t* __restrict__ pool, size_t pool_stride,
+                                                    uint64_t* __restrict__ mac_all) {
+  extern __shared__ uint64_t rv[];  // [2 nmax][TILE]
+  const size_t n = (size_t)1 << logn;
+  const int tid = threadIdx.x;
+  const size_t k = (size_t)blockIdx.x * TILE + tid;
+  const int limb = blockIdx.y, it = blockIdx.z;
+  const ModInfo mi = mods[limb];
+  const size_t ln = (size_t)level * n;
+  const int r0 = rot_off[it], nr = rot_off[it + 1] - r0;
+  const int o0 = out_off[it], no = out_off[it + 1] - o0;
+  for (int t = 0; t < nr; t++) {
+    const uint64_t* rc = rot_all + (size_t)rot_idx[r0 + t] * 2 * ln + (size_t)limb * n + k;
+    rv[(2 * t) * TILE + tid] = rc[0];
+    rv[(2 * t + 1) * TILE + tid] = rc[ln];
+  }
+  const int32_t* pix = pt_index + pt_off[it];
+  for (int o = 0; o < no; o++) {
+    U128 a0{0, 0}, a1{0, 0};
+    for (int t = 0; t < nr; t++) {
+      const uint64_t p = pool[(size_t)pix[o * nr + t] * pool_stride + (size_t)limb * n + k];
+      add_wide(a0, mul_wide(p, rv[(2 * t) * TILE + tid]));
+      add_wide(a1, mul_wide(p, rv[(2 * t + 1) * TILE + tid]));
+      if (a0.hi >= mi.q) a0.hi -= mi.q;  // subtract q 2^64 (a multiple of q)
+      if (a1.hi >= mi.q) a1.hi -= mi.q;
+    }
+    // a < q 2^64: REDC gives a 2^-64; a second REDC against 2^128 mod q restores a mod q
+    const uint64_t v0 = mont_redc(mul_wide(mont_redc(a0, mi.q, mi.qinv), mi.r2), mi.q, mi.qinv);
+    const uint64_t v1 = mont_redc(mul_wide(mont_redc(a1, mi.q, mi.qinv), mi.r2), mi.q, mi.qinv);
+    uint64_t* dst = mac_all + (size_t)(o0 + o) * 2 * ln + (size_t)limb * n + k;
+    dst[0] = v0;
+    dst[ln] = v1;
+  }
+}
+
+// ---------------------------------------------------------------- plan
+struct KeyGroup {
+  int32_t rot;        // rotation amount (normalised)
+  uint32_t g;         // Galois element
+  const uint64_t* key;
+  int npairs;
+  int first_pair;     // index of its first pair in rot_all (key-major order)
+  int32_t* d_items;   // device: item of each pair
+};
+
+struct Batch {
+  Ctx* c = nullptr;
+  he_ctx* h = nullptr;
+  int B = 0, level = 0, npool = 0, pool_level = 0;
+  double in_scale = 0, pt_scale = 0;
+  const uint64_t* in = nullptr;
+  const uint64_t* pool = nullptr;
+  uint64_t* out = nullptr;
+  std::vector<int32_t> n_rot, n_out, rots, pt_index;  // host copies
+  std::vector<int32_t> rot_off, out_off, pt_off;
+  int total_pairs = 0, total_out = 0, max_group = 0;
+  std::vector<KeyGroup> groups;
+  // device tables
+  int32_t *d_rot_off = nullptr, *d_rot_idx = nullptr, *d_out_off = nullptr, *d_pt_off = nullptr,
+          *d_pt_index = nullptr;
+  // device workspaces
+  uint64_t *coeff = nullptr, *ext = nullptr, *u = nullptr, *y = nullptr, *rot = nullptr, *mac = nullptr,
+           *rs_T = nullptr, *rs_R = nullptr;
+  int rs_chunk = 0;
+  int mac_tile = 64;
+  int nmax = 0;  // largest rotation set
+  std::vector<void*> allocs;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  bool use_graph = false;
+  double out_scale = 0;
+};
+
+template <class T>
+static int balloc(Batch* b, T** p, size_t count) {
+  void* v = nullptr;
+  hipError_t e = hipMalloc(&v, std::max<size_t>(count, 1) * sizeof(T));
+  if (e != hipSuccess) return set_error(HE_ENOMEM, std::string("batch workspace: ") + hipGetErrorString(e));
+  b->allocs.push_back(v);
+  *p = (T*)v;
+  return HE_OK;
+}
+
+static void batch_free(Batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  for (void* p : b->allocs) hipFree(p);
+  b->allocs.clear();
+}
+
+// ---------------------------------------------------------------- execution
+static int run_batched(Batch* b, hipStream_t s) {
+  Ctx* c = b->c;
+  const size_t N = c->n;
+  const int l = b->level, K = c->K, L = c->L, dn = c->dnum(l);
+  const size_t E = (size_t)(l + K), ln = (size_t)l * N, in_item = 2 * ln;
+  const size_t ext_item = (size_t)dn * E * N;
+  int rc;
+  // 1. ModUp of every input
+  if ((rc = ntt_launch_strided(c, b->in + ln, in_item, b->coeff, ln, b->B, range_map(0, l, 0), true, s))) return rc;
+  {
+    const BConvSet& set = c->modup[l];
+    ProfScope ps(c, "bconv_modup", s, 8.0 * N * b->B * (l + (double)set.count * set.max_out),
+                 (double)N * b->B * l * (1 + set.max_out));
+    dim3 grid(N / 256, (set.max_out + BCONV_OUT_PER - 1) / BCONV_OUT_PER, b->B * set.count);
+    k_bconv<<<grid, 256, 0, s>>>(b->coeff, ln, b->ext, E * N, set.d, set.count, c->d_mod, c->log_n);
+    HE_HIP(hipGetLastError());
+  }
+  if ((rc = ntt_launch(c, b->ext, ext_item, b->B, c->modup_ntt[l], false, s))) return rc;
+  // 2. key-major key switching
+  const size_t kps = (size_t)(L + K) * N;
+  for (const KeyGroup& gk : b->groups) {
+    {
+      ProfScope ps(c, "ks_inner_product_multi", s, 8.0 * N * E * (2.0 * dn + gk.npairs * (dn + 2.0)),
+                   2.0 * dn * E * N * gk.npairs);
+      k_ip_multi<<<dim3(N / 256, E), 256, 0, s>>>(b->ext, ext_item, b->in, in_item, l, K, c->alpha, dn, gk.key, 2 * kps,
+                                                  kps, L, gk.g, c->log_n, c->d_mod, gk.d_items, gk.npairs, b->u);
+      HE_HIP(hipGetLastError());
+    }
+    const int z = 2 * gk.npairs;
+    if ((rc = ntt_launch(c, b->u, E * N, z, range_map(l, K, L), true, s))) return rc;
+    {
+      const BConvSet& set = c->moddown[l];
+      ProfScope ps(c, "bconv_moddown", s, 8.0 * N * z * (K + l), (double)N * z * K * (1 + l));
+      dim3 grid(N / 256, (set.max_out + BCONV_OUT_PER - 1) / BCONV_OUT_PER, z);
+      k_bconv<<<grid, 256, 0, s>>>(b->u, E * N, b->y, ln, set.d, 1, c->d_mod, c->log_n);
+      HE_HIP(hipGetLastError());
+    }
+    if ((rc = ntt_launch(c, b->y, ln, z, range_map(0, l, 0), false, s))) return rc;
+    {
+      ProfScope ps(c, "moddown_combine", s, 8.0 * N * l * z * 3.5, (double)N * l * z);
+      k_combine_multi<<<dim3(N / 256, l, z), 256, 0, s>>>(b->u, E * N, b->y, b->in, in_item, gk.d_items, gk.g,
+                                                          b->rot + (size_t)gk.first_pair * 2 * ln, l, c->log_n,
+                                                          c->d_mod, c->d_pinv[l]);
+      HE_HIP(hipGetLastError());
+    }
+  }
+  // 3. fused multiply-accumulate of every output
+  {
+    double terms = 0;
+    for (int i = 0; i < b->B; i++) terms += (double)b->n_rot[i] * b->n_out[i];
+    ProfScope ps(c, "mac_multi", s, 8.0 * N * l * (2.0 * b->total_pairs + terms + 2.0 * b->total_out), 2.0 * N * l * terms);
+    const size_t lds = (size_t)2 * b->nmax * b->mac_tile * 8;
+    if (b->mac_tile == 64)
+      k_mac_multi<64><<<dim3(N / 64, l, b->B), 64, lds, s>>>(b->nmax, b->rot, l, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx,
+                                                           b->d_out_off, b->d_pt_off, b->d_pt_index, b->pool,
+                                                           (size_t)b->pool_level * N, b->mac);
+    else
+      k_mac_multi<128><<<dim3(N / 128, l, b->B), 128, lds, s>>>(b->nmax, b->rot, l, c->log_n, c->d_mod, b->d_rot_off,
+                                                              b->d_rot_idx, b->d_out_off, b->d_pt_off, b->d_pt_index,
+                                                              b->pool, (size_t)b->pool_level * N, b->mac);
+    HE_HIP(hipGetLastError());
+  }
+  // 4. rescale every output (chunks of rs_chunk ciphertexts = 2 rs_chunk polynomials)
+  const int t = l - 1;
+  for (int o0 = 0; o0 < b->total_out; o0 += b->rs_chunk) {
+    const int cnt = std::min(b->rs_chunk, b->total_out - o0);
+    const int z = 2 * cnt;
+    const uint64_t* src = b->mac + (size_t)o0 * 2 * ln;
+    if ((rc = ntt_launch_strided(c, src + (size_t)t * N, ln, b->rs_T, N, z, range_map(0, 1, t), true, s))) return rc;
+    k_bcast_reduce<<<dim3(N / 256, t, z), 256, 0, s>>>(b->rs_T, b->rs_R, t, c->log_n, c->d_mod);
+    HE_HIP(hipGetLastError());
+    if ((rc = ntt_launch(c, b->rs_R, (size_t)t * N, z, range_map(0, t, 0), false, s))) return rc;
+    ProfScope ps(c, "rescale_combine", s, 8.0 * N * t * z * 3, (double)N * t * z);
+    k_rescale_combine<<<dim3(N / 256, t, z), 256, 0, s>>>(src, ln, b->rs_R, b->out + (size_t)o0 * 2 * t * N,
+                                                          (size_t)t * N, t, c->log_n, c->d_mod, c->d_rescale[l]);
+    HE_HIP(hipGetLastError());
+  }
+  return HE_OK;
+}
+
+}  // namespace he
+
+using namespace he;
+
+struct he_batch {
+  Batch b;
+};
+
+extern "C" {
+
+int he_batch_create(he_ctx* h, const he_batch_desc* d, int flags, he_batch** out) {
+  if (!h || !d || !out) return set_error(HE_EINVAL, "null argument");
+  *out = nullptr;
+  Ctx* c = &h->c;
+  if (d->n_items < 1 || d->level < 2 || d->level > c->L || !d->in || !d->out || !d->pool || d->n_pool < 1 ||
+      d->pool_level < d->level || !d->n_rot || !d->n_out || !d->rots || !d->pt_index)
+    return set_error(HE_EINVAL, "bad batch description");
+  he_batch* hb = new he_batch();
+  Batch* b = &hb->b;
+  b->c = c;
+  b->h = h;
+  b->B = d->n_items;
+  b->level = d->level;
+  b->in = d->in;
+  b->out = d->out;
+  b->pool = d->pool;
+  b->npool = d->n_pool;
+  b->pool_level = d->pool_level;
+  b->in_scale = d->in_scale;
+  b->pt_scale = d->pt_scale;
+  b->use_graph = (flags & HE_BATCH_GRAPH) != 0;
+  auto fail = [&](int rc) {
+    batch_free(b);
+    delete hb;
+    return rc;
+  };
+  // host tables
+  b->rot_off.assign(b->B + 1, 0);
+  b->out_off.assign(b->B + 1, 0);
+  b->pt_off.assign(b->B + 1, 0);
+  for (int i = 0; i < b->B; i++) {
+    const int nr = d->n_rot[i], no = d->n_out[i];
+    if (nr < 1 || nr > BATCH_NMAX || no < 1) return fail(set_error(HE_EINVAL, "each item needs 1..64 rotations and >= 1 output"));
+    b->n_rot.push_back(nr);
+    b->n_out.push_back(no);
+    b->rot_off[i + 1] = b->rot_off[i] + nr;
+    b->out_off[i + 1] = b->out_off[i] + no;
+    b->pt_off[i + 1] = b->pt_off[i] + nr * no;
+  }
+  b->total_pairs = b->rot_off[b->B];
+  b->total_out = b->out_off[b->B];
+  b->rots.assign(d->rots, d->rots + b->total_pairs);
+  b->pt_index.assign(d->pt_index, d->pt_index + b->pt_off[b->B]);
+  for (int32_t x : b->pt_index)
+    if (x < 0 || x >= b->npool) return fail(set_error(HE_EINVAL, "plaintext index outside the pool"));
+  // key groups (key-major order of all (item, rotation) pairs)
+  std::map<int32_t, std::vector<std::pair<int, int>>> by_key;  // rot -> (item, t)
+  for (int i = 0; i < b->B; i++) {
+    std::vector<int32_t> seen;
+    for (int t = 0; t < b->n_rot[i]; t++) {
+      int32_t r = norm_key_id(c, b->rots[b->rot_off[i] + t]);
+      if (r == 0) return fail(set_error(HE_EINVAL, "rotation by 0 is not a key switch"));
+      for (int32_t x : seen)
+        if (x == r) return fail(set_error(HE_EINVAL, "rotation amounts of an item must be distinct"));
+      seen.push_back(r);
+      if (!find_key(c, r)) return fail(set_error(HE_ENOKEY, "rotation key " + std::to_string(r) + " not resident"));
+      by_key[r].push_back({i, t});
+    }
+  }
+  std::vector<int32_t> rot_idx(b->total_pairs);
+  int gp = 0;
+  int rc;
+  for (auto& kv : by_key) {
+    KeyGroup g;
+    g.rot = kv.first;
+    g.g = galois_elt(c, kv.first);
+    g.key = find_key(c, kv.first);
+    g.npairs = (int)kv.second.size();
+    g.first_pair = gp;
+    std::vector<int32_t> items;
+    for (auto& it : kv.second) {
+      items.push_back(it.first);
+      rot_idx[b->rot_off[it.first] + it.second] = gp++;
+    }
+    if ((rc = balloc(b, &g.d_items, items.size()))) return fail(rc);
+    HE_HIP(hipMemcpy(g.d_items, items.data(), items.size() * 4, hipMemcpyHostToDevice));
+    b->max_group = std::max(b->max_group, g.npairs);
+    b->groups.push_back(g);
+  }
+  // device tables
+  auto up = [&](int32_t** dst, const std::vector<int32_t>& v) -> int {
+    int r = balloc(b, dst, v.size());
+    if (r) return r;
+    HE_HIP(hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice));
+    return HE_OK;
+  };
+  if ((rc = up(&b->d_rot_off, b->rot_off)) || (rc = up(&b->d_rot_idx, rot_idx)) || (rc = up(&b->d_out_off, b->out_off)) ||
+      (rc = up(&b->d_pt_off, b->pt_off)) || (rc = up(&b->d_pt_index, b->pt_index)))
+    return fail(rc);
+  // workspaces
+  const size_t N = c->n, l = b->level, K = c->K, dn = c->dnum(b->level), E = l + K;
+  b->rs_chunk = std::min(b->total_out, 128);
+  if ((rc = balloc(b, &b->coeff, (size_t)b->B * l * N)) || (rc = balloc(b, &b->ext, (size_t)b->B * dn * E * N)) ||
+      (rc = balloc(b, &b->u, (size_t)b->max_group * 2 * E * N)) || (rc = balloc(b, &b->y, (size_t)b->max_group * 2 * l * N)) ||
+      (rc = balloc(b, &b->rot, (size_t)b->total_pairs * 2 * l * N)) ||
+      (rc = balloc(b, &b->mac, (size_t)b->total_out * 2 * l * N)) || (rc = balloc(b, &b->rs_T, (size_t)2 * b->rs_chunk * N)) ||
+      (rc = balloc(b, &b->rs_R, (size_t)2 * b->rs_chunk * (l - 1) * N)))
+    return fail(rc);
+  b->mac_tile = (flags & HE_BATCH_TILE128) ? 128 : 64;
+  for (int x : b->n_rot) b->nmax = std::max(b->nmax, x);
+  {
+    const size_t lds = (size_t)2 * b->nmax * b->mac_tile * 8;
+    if (lds > 160 * 1024) return fail(set_error(HE_EINVAL, "rotation set too large for the MAC tile"));
+    if (b->mac_tile == 64)
+      HE_HIP(hipFuncSetAttribute((const void*)k_mac_multi<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    else
+      HE_HIP(hipFuncSetAttribute((const void*)k_mac_multi<128>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  }
+  b->out_scale = b->in_scale * b->pt_scale / (double)c->mod[b->level - 1];
+  *out = hb;
+  return HE_OK;
+}
+
+int he_batch_run(he_batch* hb, he_stream st) {
+  if (!hb) return set_error(HE_EINVAL, "null batch");
+  Batch* b = &hb->b;
+  hipStream_t s = (hipStream_t)st;
+  HE_HIP(hipSetDevice(b->c->device));
+  if (!b->use_graph || b->c->prof_on) return run_batched(b, s);
+  if (!b->exec) {
+    if (!s) return set_error(HE_EINVAL, "graph capture needs a non-default stream");
+    HE_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    int rc = run_batched(b, s);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+      if (g) hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
+    b->graph = g;
+    HE_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  }
+  HE_HIP(hipGraphLaunch(b->exec, s));
+  return HE_OK;
+}
+
+int he_batch_run_plain(he_batch* hb, he_stream st) {
+  if (!hb) return set_error(HE_EINVAL, "null batch");
+  Batch* b = &hb->b;
+  Ctx* c = b->c;
+  he_ctx* h = b->h;
+  const size_t N = c->n, l = b->level;
+  // temporaries: the rotated copies of one input and one accumulator
+  int nmax = 0;
+  for (int x : b->n_rot) nmax = std::max(nmax, x);
+  std::vector<uint64_t*> tmp;
+  auto cleanup = [&]() {
+    for (uint64_t* p : tmp) c->ct_pool.push_back(p);
+  };
+  for (int i = 0; i < nmax + 1; i++) {
+    if (!c->ct_pool.empty()) {
+      tmp.push_back(c->ct_pool.back());
+      c->ct_pool.pop_back();
+    } else {
+      void* v = nullptr;
+      if (hipMalloc(&v, 2 * c->L * N * 8) != hipSuccess) {
+        cleanup();
+        return set_error(HE_ENOMEM, "plain batch temporaries");
+      }
+      c->ct_pool_all.push_back((uint64_t*)v);
+      tmp.push_back((uint64_t*)v);
+    }
+  }
+  std::vector<he_ct> rot(nmax);
+  int rc = HE_OK;
+  for (int i = 0; i < b->B && !rc; i++) {
+    const int nr = b->n_rot[i];
+    he_ct in{const_cast<uint64_t*>(b->in) + (size_t)i * 2 * l * N, (int32_t)l, (int32_t)l, b->in_scale};
+    for (int t = 0; t < nr; t++) rot[t] = he_ct{tmp[t], 0, c->L, 0};
+    rc = he_rotate_hoisted(h, &in, b->rots.data() + b->rot_off[i], nr, rot.data(), st);
+    he_ct acc{tmp[nmax], 0, c->L, 0};
+    for (int o = 0; o < b->n_out[i] && !rc; o++) {
+      for (int t = 0; t < nr && !rc; t++) {
+        const int32_t pi = b->pt_index[b->pt_off[i] + o * nr + t];
+        he_pt pt{b->pool + (size_t)pi * b->pool_level * N, b->pool_level, b->pt_scale};
+        rc = he_mul_plain(h, &rot[t], &pt, &acc, t > 0, st);
+      }
+      he_ct dst{b->out + (size_t)(b->out_off[i] + o) * 2 * (l - 1) * N, 0, (int32_t)(l - 1), 0};
+      if (!rc) rc = he_rescale(h, &acc, &dst, st);
+    }
+  }
+  cleanup();
+  return rc;
+}
+
+int he_batch_info(const he_batch* hb, int32_t* total_rotations, int32_t* total_outputs, int32_t* distinct_keys,
+                  double* out_scale) {
+  if (!hb) return set_error(HE_EINVAL, "null batch");
+  const Batch* b = &hb->b;
+  if (total_rotations) *total_rotations = b->total_pairs;
+  if (total_outputs) *total_outputs = b->total_out;
+  if (distinct_keys) *distinct_keys = (int32_t)b->groups.size();
+  if (out_scale) *out_scale = b->out_scale;
+  return HE_OK;
+}
+
+int he_batch_destroy(he_batch* hb) {
+  if (!hb) return HE_OK;
+  hipDeviceSynchronize();
+  batch_free(&hb->b);
+  delete hb;
+  return HE_OK;
+}
+
+}  // extern "C"

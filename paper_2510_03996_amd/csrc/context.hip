@@ -1,5 +1,6 @@
 // Context creation: prime chain, NTT twiddles, basis-conversion constants,
 // resident key store and the workspace pool.
+#include <algorithm>
 #include <cstring>
 #include <string>
 
@@ -79,7 +80,7 @@ LimbMap range_map(int first_pos, int n, int first_mod) {
   LimbMap m{};
   m.n = n;
   for (int i = 0; i < n; i++) {
-    m.pos[i] = (uint8_t)(first_pos + i);
+    m.pos[i] = (uint16_t)(first_pos + i);
     m.mod[i] = (uint8_t)(first_mod + i);
   }
   return m;
@@ -89,7 +90,7 @@ LimbMap ext_map(const Ctx* c, int level) {
   LimbMap m{};
   m.n = level + c->K;
   for (int i = 0; i < m.n; i++) {
-    m.pos[i] = (uint8_t)i;
+    m.pos[i] = (uint16_t)i;
     m.mod[i] = (uint8_t)(i < level ? i : c->L + (i - level));
   }
   return m;
@@ -117,14 +118,16 @@ static int dev_alloc(Ctx* c, T** p, size_t count) {
   return HE_OK;
 }
 
-static int build_bconv(Ctx* c, BConvTab& t, const std::vector<int>& in_pos, const std::vector<int>& in_mod,
+// Host-side construction of one basis-conversion descriptor (constants are
+// uploaded to device memory; the descriptor points at them).
+static int build_bconv(Ctx* c, BConvDesc& t, const std::vector<int>& in_pos, const std::vector<int>& in_mod,
                        const std::vector<int>& out_pos, const std::vector<int>& out_mod) {
+  t = BConvDesc{};
   t.nin = (int)in_mod.size();
   t.nout = (int)out_mod.size();
-  t.in.n = t.nin;
-  t.out.n = t.nout;
-  for (int i = 0; i < t.nin; i++) { t.in.pos[i] = (uint8_t)in_pos[i]; t.in.mod[i] = (uint8_t)in_mod[i]; }
-  for (int p = 0; p < t.nout; p++) { t.out.pos[p] = (uint8_t)out_pos[p]; t.out.mod[p] = (uint8_t)out_mod[p]; }
+  if (t.nin > MAX_BCONV_IN || t.nout > MAX_BCONV_OUT) return set_error(HE_EINVAL, "basis conversion too wide");
+  for (int i = 0; i < t.nin; i++) { t.in_pos[i] = in_pos[i]; t.in_mod[i] = in_mod[i]; }
+  for (int p = 0; p < t.nout; p++) { t.out_pos[p] = out_pos[p]; t.out_mod[p] = out_mod[p]; }
   std::vector<uint64_t> h(2 * t.nin + (size_t)t.nin * t.nout);
   for (int i = 0; i < t.nin; i++) {
     uint64_t qi = c->mod[in_mod[i]];
@@ -144,9 +147,21 @@ static int build_bconv(Ctx* c, BConvTab& t, const std::vector<int>& in_pos, cons
       h[2 * t.nin + (size_t)i * t.nout + p] = hmul(v, r64, po);
     }
   }
-  int rc = dev_alloc(c, &t.d, h.size());
+  uint64_t* d = nullptr;
+  int rc = dev_alloc(c, &d, h.size());
   if (rc) return rc;
-  HE_HIP(hipMemcpy(t.d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+  t.tab = d;
+  return HE_OK;
+}
+
+static int upload_set(Ctx* c, BConvSet& set, const std::vector<BConvDesc>& v) {
+  set.count = (int)v.size();
+  set.max_out = 0;
+  for (auto& d : v) set.max_out = std::max(set.max_out, d.nout);
+  int rc = dev_alloc(c, &set.d, v.size());
+  if (rc) return rc;
+  HE_HIP(hipMemcpy(set.d, v.data(), v.size() * sizeof(BConvDesc), hipMemcpyHostToDevice));
   return HE_OK;
 }
 
@@ -238,11 +253,15 @@ static int ctx_init(Ctx* c, const he_params* p) {
   // ---- basis conversion tables for every level
   c->modup.assign(c->L + 1, {});
   c->moddown.assign(c->L + 1, {});
+  c->modup_ntt.assign(c->L + 1, LimbMap{});
   c->d_rescale.assign(c->L + 1, nullptr);
   c->d_pinv.assign(c->L + 1, nullptr);
   for (int l = 1; l <= c->L; l++) {
     int dn = c->dnum(l);
-    c->modup[l].resize(dn);
+    const int E = l + c->K;
+    std::vector<BConvDesc> ups(dn);
+    LimbMap& nm = c->modup_ntt[l];
+    nm.n = 0;
     for (int j = 0; j < dn; j++) {
       std::vector<int> ip, im, op, om;
       int lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, l);
@@ -250,12 +269,21 @@ static int ctx_init(Ctx* c, const he_params* p) {
       for (int i = 0; i < l; i++)
         if (i < lo || i >= hi) { op.push_back(i); om.push_back(i); }
       for (int k = 0; k < c->K; k++) { op.push_back(l + k); om.push_back(c->L + k); }
-      if ((rc = build_bconv(c, c->modup[l][j], ip, im, op, om))) return rc;
+      if ((rc = build_bconv(c, ups[j], ip, im, op, om))) return rc;
+      for (size_t p = 0; p < op.size(); p++) {
+        if (nm.n >= MAXJ) return set_error(HE_EINVAL, "too many extended limbs for one launch");
+        nm.pos[nm.n] = (uint16_t)(j * E + op[p]);
+        nm.mod[nm.n] = (uint8_t)om[p];
+        nm.n++;
+      }
     }
+    if ((rc = upload_set(c, c->modup[l], ups))) return rc;
     std::vector<int> ip, im, op, om;
     for (int k = 0; k < c->K; k++) { ip.push_back(l + k); im.push_back(c->L + k); }
     for (int i = 0; i < l; i++) { op.push_back(i); om.push_back(i); }
-    if ((rc = build_bconv(c, c->moddown[l], ip, im, op, om))) return rc;
+    std::vector<BConvDesc> dn1(1);
+    if ((rc = build_bconv(c, dn1[0], ip, im, op, om))) return rc;
+    if ((rc = upload_set(c, c->moddown[l], dn1))) return rc;
     // P^{-1} mod q_i
     std::vector<uint64_t> pv(2 * l);
     for (int i = 0; i < l; i++) {

@@ -14,13 +14,12 @@ namespace he {
 
 constexpr int MAXL = 64;  // max limbs in any basis (L + K)
 
-// Basis-conversion table: nin input moduli -> nout output moduli.
-// Device layout: [nin] w, [nin] w' (Shoup of (Qin/q_i)^{-1} mod q_i), then
-// [nin][nout] Montgomery constants (Qin/q_i mod p) * 2^64 mod p.
-struct BConvTab {
-  int nin = 0, nout = 0;
-  LimbMap in{}, out{};
-  uint64_t* d = nullptr;
+// Basis-conversion tables of one level: device descriptors (one per digit
+// for ModUp, one for ModDown) plus the largest output count.
+struct BConvSet {
+  BConvDesc* d = nullptr;  // device array
+  int count = 0;
+  int max_out = 0;
 };
 
 // Optional per-kernel timing: a HIP event pair around each launch on its own
@@ -40,8 +39,8 @@ struct Ctx {
   ModInfo* d_mod = nullptr;
   uint64_t *d_tw = nullptr, *d_twp = nullptr, *d_itw = nullptr, *d_itwp = nullptr;  // [L+K][N]
   // modup[level][digit]; moddown[level]
-  std::vector<std::vector<BConvTab>> modup;
-  std::vector<BConvTab> moddown;
+  std::vector<BConvSet> modup, moddown;
+  std::vector<LimbMap> modup_ntt;  // per level: every converted limb of every digit (ext-relative)
   // per level l (>= 2): Shoup pairs of q_{l-1}^{-1} mod q_i (i < l-1): [2][l-1]
   std::vector<uint64_t*> d_rescale;
   // per level l: Shoup pairs of P^{-1} mod q_i: [2][l]
@@ -97,6 +96,12 @@ int hip_error(hipError_t e, const char* what);
 // apart (all arrays share the map).
 int ntt_launch(Ctx* c, uint64_t* data, size_t batch_stride, int nbatch, const LimbMap& map, bool inverse,
                hipStream_t s);
+// out-of-place: the first pass reads from `src` (same positions, batch stride
+// src_bs), later passes work on `data`
+int ntt_launch_strided(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, int nbatch,
+                       const LimbMap& map, bool inverse, hipStream_t s);
+int ntt_launch_from(Ctx* c, const uint64_t* src, uint64_t* data, size_t batch_stride, int nbatch, const LimbMap& map,
+                    bool inverse, hipStream_t s);
 LimbMap range_map(int first_pos, int n, int first_mod);
 // positions 0..l-1 -> q_0..q_{l-1}, positions l..l+K-1 -> p_0..p_{K-1}
 LimbMap ext_map(const Ctx* c, int level);
@@ -125,11 +130,24 @@ inline size_t ws_words(const Ctx* c) {
 int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s);
 // inner product with `key` (Montgomery form), automorphism g on the extended
 // digits, ModDown, and out0 = add0[phi_g] + u0', out1 = add1 + u1'.
-int ks_apply(Ctx* c, const WS& w, int level, const uint64_t* key, uint32_t g, const uint64_t* add0,
-             const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s);
+int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
+             const uint64_t* add0, const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s);
 const uint64_t* find_key(Ctx* c, int32_t id);
 int check_ct(const Ctx* c, const he_ct* x, const char* what);
 int check_out(const Ctx* c, const he_ct* x, int need_level);
+
+constexpr int BCONV_OUT_PER = 8;  // basis-conversion outputs per thread
+__global__ void k_bconv(const uint64_t* __restrict__ in, size_t in_bs, uint64_t* __restrict__ out, size_t out_bs,
+                        const BConvDesc* __restrict__ descs, int zdiv, const ModInfo* __restrict__ mods, int logn);
+__global__ void k_moddown_combine(const uint64_t* __restrict__ u, size_t u_ps, const uint64_t* __restrict__ y,
+                                  size_t y_ps, const uint64_t* add0, const uint64_t* add1, uint32_t g, uint64_t* out0,
+                                  uint64_t* out1, int level, int logn, const ModInfo* __restrict__ mods,
+                                  const uint64_t* __restrict__ pinv);
+__global__ void k_bcast_reduce(const uint64_t* __restrict__ T, uint64_t* __restrict__ R, int nl, int logn,
+                               const ModInfo* __restrict__ mods);
+__global__ void k_rescale_combine(const uint64_t* in, size_t ips, const uint64_t* __restrict__ R, uint64_t* out,
+                                  size_t ops, int nl, int logn, const ModInfo* __restrict__ mods,
+                                  const uint64_t* __restrict__ tab);
 
 int32_t norm_key_id(const Ctx* c, int32_t id);
 uint32_t galois_elt(const Ctx* c, int32_t r);

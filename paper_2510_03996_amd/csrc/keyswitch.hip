@@ -10,16 +10,23 @@
 namespace he {
 
 // ---------------------------------------------------------------- kernels
+// grid: x = coefficient tile, y = group of BCONV_OUT_PER outputs, z = batch:
+// descriptor descs[z % zdiv], input in + (z / zdiv) in_bs, output out + z out_bs
 __global__ __launch_bounds__(256) void k_bconv(const uint64_t* __restrict__ in, size_t in_bs,
-                                               uint64_t* __restrict__ out, size_t out_bs, LimbMap im, LimbMap om,
-                                               const uint64_t* __restrict__ tab, const ModInfo* __restrict__ mods,
-                                               int logn) {
+                                               uint64_t* __restrict__ out, size_t out_bs,
+                                               const BConvDesc* __restrict__ descs, int zdiv,
+                                               const ModInfo* __restrict__ mods, int logn) {
   const size_t n = (size_t)1 << logn;
   const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  bconv_elem(in + blockIdx.y * in_bs, out + blockIdx.y * out_bs, n, k, im, om, tab, mods);
+  const int z = blockIdx.z;
+  const BConvDesc& d = descs[z % zdiv];
+  const int p0 = blockIdx.y * BCONV_OUT_PER;
+  if (p0 >= d.nout) return;
+  bconv_elem(in + (z / zdiv) * in_bs, out + z * out_bs, n, k, d, p0, p0 + BCONV_OUT_PER, mods);
 }
 
-__global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, size_t ext_stride, int dnum,
+__global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, size_t ext_stride,
+                                            const uint64_t* __restrict__ c1, int alpha, int dnum,
                                             const uint64_t* __restrict__ key, size_t key_digit_stride,
                                             size_t key_poly_stride, int level, int L, uint32_t g, int logn,
                                             const ModInfo* __restrict__ mods, uint64_t* __restrict__ u,
@@ -29,8 +36,8 @@ __global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, si
   const int pos = blockIdx.y;
   const int mod = pos < level ? pos : L + (pos - level);
   const uint32_t src = g == 1 ? k : automorph_src(k, g, logn);
-  ip_elem(ext, ext_stride, dnum, key, key_digit_stride, key_poly_stride, pos, mod, n, k, src, mods[mod], u, u,
-          u_poly_stride);
+  ip_elem(ext, ext_stride, pos < level ? c1 : nullptr, alpha, dnum, key, key_digit_stride, key_poly_stride, pos,
+          mod, n, k, src, mods[mod], u, u, u_poly_stride);
 }
 
 // out_z[i][k] = add_z + (u_z[i][k] - y_z[i][k]) P^{-1}, z = blockIdx.z;
@@ -64,32 +71,27 @@ __global__ __launch_bounds__(256) void k_to_mont(uint64_t* key, int M, int logn,
 }
 
 // ---------------------------------------------------------------- building blocks
+// Digits of c1 (NTT form, `level` limbs) basis-extended to Q_l u P: the
+// digits' own limbs stay in c1; every other limb of digit j is written to
+// w.ext + j (level+K) N in NTT form.
 int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) {
   const size_t N = c->n;
-  const int K = c->K;
-  const size_t ext_stride = (size_t)(level + K) * N;
+  const size_t E = (size_t)(level + c->K);
   int rc;
-  HE_HIP(hipMemcpyAsync(w.coeff, c1, (size_t)level * N * 8, hipMemcpyDeviceToDevice, s));
-  if ((rc = ntt_launch(c, w.coeff, 0, 1, range_map(0, level, 0), true, s))) return rc;
-  const int dn = c->dnum(level);
-  for (int j = 0; j < dn; j++) {
-    const BConvTab& t = c->modup[level][j];
-    uint64_t* ext = w.ext + j * ext_stride;
-    const int lo = j * c->alpha;
-    HE_HIP(hipMemcpyAsync(ext + (size_t)lo * N, c1 + (size_t)lo * N, (size_t)t.nin * N * 8,
-                          hipMemcpyDeviceToDevice, s));
-    {
-      ProfScope ps(c, "bconv_modup", s, 8.0 * N * (t.nin + t.nout), (double)N * t.nin * (1 + t.nout));
-      k_bconv<<<dim3(N / 256, 1), 256, 0, s>>>(w.coeff, 0, ext, 0, t.in, t.out, t.d, c->d_mod, c->log_n);
-    }
-    HE_HIP(hipGetLastError());
-    if ((rc = ntt_launch(c, ext, 0, 1, t.out, false, s))) return rc;
+  if ((rc = ntt_launch_from(c, c1, w.coeff, 0, 1, range_map(0, level, 0), true, s))) return rc;
+  const BConvSet& set = c->modup[level];
+  {
+    const double mm = (double)N * level * (1 + set.max_out);  // t_i products + MACs (upper bound)
+    ProfScope ps(c, "bconv_modup", s, 8.0 * N * (level + (double)set.count * set.max_out), mm);
+    dim3 grid(N / 256, (set.max_out + BCONV_OUT_PER - 1) / BCONV_OUT_PER, set.count);
+    k_bconv<<<grid, 256, 0, s>>>(w.coeff, 0, w.ext, E * N, set.d, set.count, c->d_mod, c->log_n);
   }
-  return HE_OK;
+  HE_HIP(hipGetLastError());
+  return ntt_launch(c, w.ext, 0, 1, c->modup_ntt[level], false, s);
 }
 
-int ks_apply(Ctx* c, const WS& w, int level, const uint64_t* key, uint32_t g, const uint64_t* add0,
-             const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s) {
+int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
+             const uint64_t* add0, const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s) {
   const size_t N = c->n;
   const int K = c->K, L = c->L;
   const size_t E = (size_t)(level + K);
@@ -98,17 +100,17 @@ int ks_apply(Ctx* c, const WS& w, int level, const uint64_t* key, uint32_t g, co
   const int dn = c->dnum(level);
   {
     ProfScope ps(c, "ks_inner_product", s, 8.0 * N * E * (3.0 * dn + 2), 2.0 * dn * E * N);
-    k_ip<<<dim3(N / 256, E), 256, 0, s>>>(w.ext, E * N, dn, key, 2 * kps, kps, level, L, g, c->log_n, c->d_mod, w.u,
-                                          E * N);
+    k_ip<<<dim3(N / 256, E), 256, 0, s>>>(w.ext, E * N, c1, c->alpha, dn, key, 2 * kps, kps, level, L, g,
+                                          c->log_n, c->d_mod, w.u, E * N);
   }
   HE_HIP(hipGetLastError());
   // ModDown of u0 and u1: P limbs to coefficient form, convert to Q_l, back to NTT form
   if ((rc = ntt_launch(c, w.u, E * N, 2, range_map(level, K, L), true, s))) return rc;
-  const BConvTab& t = c->moddown[level];
+  const BConvSet& set = c->moddown[level];
   {
-    ProfScope ps(c, "bconv_moddown", s, 16.0 * N * (t.nin + t.nout), 2.0 * N * t.nin * (1 + t.nout));
-    k_bconv<<<dim3(N / 256, 2), 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, t.in, t.out, t.d, c->d_mod,
-                                             c->log_n);
+    ProfScope ps(c, "bconv_moddown", s, 16.0 * N * (K + level), 2.0 * N * K * (1 + level));
+    dim3 grid(N / 256, (set.max_out + BCONV_OUT_PER - 1) / BCONV_OUT_PER, 2);
+    k_bconv<<<grid, 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, set.d, 1, c->d_mod, c->log_n);
   }
   HE_HIP(hipGetLastError());
   if ((rc = ntt_launch(c, w.y, (size_t)level * N, 2, range_map(0, level, 0), false, s))) return rc;
@@ -201,7 +203,7 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
       HE_HIP(hipMemcpyAsync(o0, c0, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s));
       HE_HIP(hipMemcpyAsync(o1, c1, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s));
     } else {
-      if ((rc = ks_apply(c, w, l, find_key(c, r[t]), galois_elt(c, r[t]), c0, nullptr, o0, o1, s))) return rc;
+      if ((rc = ks_apply(c, w, c1, l, find_key(c, r[t]), galois_elt(c, r[t]), c0, nullptr, o0, o1, s))) return rc;
     }
     o.level = l;
     o.scale = in->scale;
@@ -228,7 +230,7 @@ int he_relin(he_ctx* h, const uint64_t* d, int level, double scale, he_ct* out, 
   const uint64_t* d1 = d + (size_t)level * N;
   const uint64_t* d2 = d + 2 * (size_t)level * N;
   if ((rc = ks_modup(c, w, d2, level, s))) return rc;
-  if ((rc = ks_apply(c, w, level, key, 1, d0, d1, out->data, out->data + (size_t)out->cap * N, s))) return rc;
+  if ((rc = ks_apply(c, w, d2, level, key, 1, d0, d1, out->data, out->data + (size_t)out->cap * N, s))) return rc;
   out->level = level;
   out->scale = scale;
   return HE_OK;

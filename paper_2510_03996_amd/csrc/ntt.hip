@@ -6,7 +6,8 @@ namespace he {
 
 // grid: x = tile within limb, y = limb index in `map`, z = batch
 template <int LOGN, int PASS, bool INV>
-__global__ __launch_bounds__(256) void ntt_pass_kernel(uint64_t* __restrict__ data, size_t batch_stride, LimbMap map,
+__global__ __launch_bounds__(256) void ntt_pass_kernel(const uint64_t* src, size_t src_bs, uint64_t* data,
+                                                       size_t batch_stride, LimbMap map,
                                                        const uint64_t* __restrict__ tw_all,
                                                        const uint64_t* __restrict__ twp_all,
                                                        const ModInfo* __restrict__ mods) {
@@ -16,6 +17,7 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(uint64_t* __restrict__ da
   const int limb = blockIdx.y;
   const int tid = threadIdx.x;
   const int m = map.mod[limb];
+  const uint64_t* ain = src + blockIdx.z * src_bs + (size_t)map.pos[limb] * P::N;
   uint64_t* a = data + blockIdx.z * batch_stride + (size_t)map.pos[limb] * P::N;
   const uint64_t* tw = tw_all + (size_t)m * P::N;
   const uint64_t* twp = twp_all + (size_t)m * P::N;
@@ -24,7 +26,7 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(uint64_t* __restrict__ da
   for (int e = tid; e < P::TILE; e += P::THREADS) {
     int g, k;
     P::tile_elem(e, g, k);
-    lds[P::lidx(g, k)] = a[P::gidx(wg, g, k)];
+    lds[P::lidx(g, k)] = ain[P::gidx(wg, g, k)];
   }
   __syncthreads();
   if (!INV) {
@@ -44,15 +46,13 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(uint64_t* __restrict__ da
   for (int e = tid; e < P::TILE; e += P::THREADS) {
     int g, k;
     P::tile_elem(e, g, k);
-    uint64_t v = lds[P::lidx(g, k)];
-    if (INV && PASS == 1) v = mul_shoup(v, mi.ninv, mi.ninv_p, q);
-    a[P::gidx(wg, g, k)] = v;
+    a[P::gidx(wg, g, k)] = P::finish(lds[P::lidx(g, k)], mi.ninv, mi.ninv_p, q);
   }
 }
 
 template <int LOGN>
-static int ntt_launch_n(Ctx* c, uint64_t* data, size_t batch_stride, int nbatch, const LimbMap& map, bool inverse,
-                        hipStream_t s) {
+static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
+                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
   using P1 = NttPass<LOGN, 1, false>;
   using P2 = NttPass<LOGN, 2, false>;
   dim3 g1(P1::WG_PER_LIMB, map.n, nbatch), g2(P2::WG_PER_LIMB, map.n, nbatch);
@@ -62,31 +62,43 @@ static int ntt_launch_n(Ctx* c, uint64_t* data, size_t batch_stride, int nbatch,
   if (!inverse) {
     {
       ProfScope ps(c, "ntt_fwd_pass1", s, bytes, mm1);
-      ntt_pass_kernel<LOGN, 1, false><<<g1, 256, 0, s>>>(data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
+      ntt_pass_kernel<LOGN, 1, false><<<g1, 256, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
     }
     ProfScope ps(c, "ntt_fwd_pass2", s, bytes, mm2);
-    ntt_pass_kernel<LOGN, 2, false><<<g2, 256, 0, s>>>(data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
+    ntt_pass_kernel<LOGN, 2, false><<<g2, 256, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
   } else {
     {
       ProfScope ps(c, "ntt_inv_pass2", s, bytes, mm2);
-      ntt_pass_kernel<LOGN, 2, true><<<g2, 256, 0, s>>>(data, batch_stride, map, c->d_itw, c->d_itwp, c->d_mod);
+      ntt_pass_kernel<LOGN, 2, true><<<g2, 256, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_itw, c->d_itwp,
+                                                         c->d_mod);
     }
     ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs);
-    ntt_pass_kernel<LOGN, 1, true><<<g1, 256, 0, s>>>(data, batch_stride, map, c->d_itw, c->d_itwp, c->d_mod);
+    ntt_pass_kernel<LOGN, 1, true><<<g1, 256, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_mod);
   }
   HE_HIP(hipGetLastError());
   return HE_OK;
 }
 
-int ntt_launch(Ctx* c, uint64_t* data, size_t batch_stride, int nbatch, const LimbMap& map, bool inverse,
-               hipStream_t s) {
+int ntt_launch_strided(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, int nbatch,
+                       const LimbMap& map, bool inverse, hipStream_t s) {
   if (map.n <= 0 || nbatch <= 0) return HE_OK;
+  if (nbatch > 65535) return set_error(HE_EINVAL, "NTT batch too large for one launch");
   switch (c->log_n) {
-    case 12: return ntt_launch_n<12>(c, data, batch_stride, nbatch, map, inverse, s);
-    case 14: return ntt_launch_n<14>(c, data, batch_stride, nbatch, map, inverse, s);
-    case 16: return ntt_launch_n<16>(c, data, batch_stride, nbatch, map, inverse, s);
+    case 12: return ntt_launch_n<12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+    case 14: return ntt_launch_n<14>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+    case 16: return ntt_launch_n<16>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
   }
   return set_error(HE_EINVAL, "unsupported ring degree");
+}
+
+int ntt_launch_from(Ctx* c, const uint64_t* src, uint64_t* data, size_t batch_stride, int nbatch, const LimbMap& map,
+                    bool inverse, hipStream_t s) {
+  return ntt_launch_strided(c, src, batch_stride, data, batch_stride, nbatch, map, inverse, s);
+}
+
+int ntt_launch(Ctx* c, uint64_t* data, size_t batch_stride, int nbatch, const LimbMap& map, bool inverse,
+               hipStream_t s) {
+  return ntt_launch_from(c, data, data, batch_stride, nbatch, map, inverse, s);
 }
 
 }  // namespace he

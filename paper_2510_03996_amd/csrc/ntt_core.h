@@ -86,10 +86,12 @@ struct NttPass {
             if (u & half) continue;
             const int iloc = (hi << ss) + (u >> (R - ss));
             const int ti = (1 << sg) + (sub_off << s) + iloc;
-            const uint64_t y = mul_shoup(x[u + half], tw[ti], twp[ti], q);
-            const uint64_t a = x[u];
-            x[u] = add_mod(a, y, q);
-            x[u + half] = sub_mod(a, y, q);
+            // Harvey butterfly: inputs in [0, 4q), outputs in [0, 4q)
+            const uint64_t y = mul_shoup_lazy(x[u + half], tw[ti], twp[ti], q);
+            uint64_t a = x[u];
+            a = a >= 2 * q ? a - 2 * q : a;
+            x[u] = a + y;
+            x[u + half] = a - y + 2 * q;
           }
         }
       } else {
@@ -103,15 +105,32 @@ struct NttPass {
             if (u & half) continue;
             const int iloc = (hi << ss) + (u >> (R - ss));
             const int ti = (1 << sg) + (sub_off << s) + iloc;
+            // Gentleman-Sande with lazy reduction: inputs and outputs in [0, 2q)
             const uint64_t a = x[u], b = x[u + half];
-            x[u] = add_mod(a, b, q);
-            x[u + half] = mul_shoup(sub_mod(a, b, q), tw[ti], twp[ti], q);
+            const uint64_t sm = a + b;
+            x[u] = sm >= 2 * q ? sm - 2 * q : sm;
+            x[u + half] = mul_shoup_lazy(a - b + 2 * q, tw[ti], twp[ti], q);
           }
         }
       }
 #pragma unroll
       for (int u = 0; u < (1 << R); u++) lds[lidx(g, base + u * dmin)] = x[u];
     }
+  }
+
+  // Value written back to HBM after the pass: the forward transform leaves
+  // pass 1 lazily reduced ([0, 4q)) and canonicalises after pass 2; the
+  // inverse multiplies by N^{-1} and canonicalises after pass 1.
+  HE_HD static uint64_t finish(uint64_t v, uint64_t ninv, uint64_t ninvp, uint64_t q) {
+    if (!INV && PASS == 2) {
+      v = v >= 2 * q ? v - 2 * q : v;
+      return v >= q ? v - q : v;
+    }
+    if (INV && PASS == 1) {
+      v = mul_shoup_lazy(v, ninv, ninvp, q);
+      return v >= q ? v - q : v;
+    }
+    return v;
   }
 
   // LM <= 8 stages per pass: a first round of R1 stages, then R2 = LM - R1.

@@ -70,6 +70,16 @@ class he_layer_plan(ctypes.Structure):
         return [int(self.rot_keys[i]) for i in range(self.n_keys)]
 
 
+class he_batch_desc(ctypes.Structure):
+    _fields_ = [("n_items", ctypes.c_int32), ("level", ctypes.c_int32), ("in_scale", ctypes.c_double),
+                ("pt_scale", ctypes.c_double), ("in_", ctypes.c_void_p), ("n_rot", ctypes.POINTER(ctypes.c_int32)),
+                ("rots", ctypes.POINTER(ctypes.c_int32)), ("n_out", ctypes.POINTER(ctypes.c_int32)),
+                ("pool", ctypes.c_void_p), ("n_pool", ctypes.c_int32), ("pool_level", ctypes.c_int32),
+                ("pt_index", ctypes.POINTER(ctypes.c_int32)), ("out", ctypes.c_void_p)]
+
+
+BATCH_GRAPH, BATCH_TILE128 = 1, 2
+
 _lib = None
 
 
@@ -111,6 +121,11 @@ def lib():
             "he_fc_plan": [vp, c_int, c_int, P(he_layer_plan)],
             "he_fc": [vp, P(he_ct), c_int, c_int, P(he_pt), P(he_pt), P(he_pt), P(he_ct), vp],
             "he_poly4": [vp, P(he_ct), P(ctypes.c_double), ctypes.c_double, P(he_ct), vp],
+            "he_batch_create": [vp, P(he_batch_desc), c_int, P(vp)],
+            "he_batch_run": [vp, vp],
+            "he_batch_run_plain": [vp, vp],
+            "he_batch_info": [vp, P(i32), P(i32), P(i32), P(ctypes.c_double)],
+            "he_batch_destroy": [vp],
             "he_profile_begin": [vp],
             "he_profile_end": [vp, ctypes.c_char_p, sz],
         }
@@ -411,3 +426,58 @@ class Context:
         buf = ctypes.create_string_buffer(1 << 16)
         n = _check(lib().he_profile_end(self.h, buf, len(buf)))
         return json.loads(buf.value[:n].decode())
+
+
+class Batch:
+    """Batched hoisted-rotation multiply-accumulate (see he_batch_create).
+
+    inp: int64 device tensor [B][2][l][N]; rot_sets: list of B lists of
+    rotation amounts; n_outs: list of B output counts; pool: int64 device
+    tensor [P][pool_level][N]; pt_index: list of B lists (n_out x n_rot,
+    o-major) of pool indices; out: int64 device tensor [sum n_outs][2][l-1][N].
+    """
+
+    def __init__(self, ctx, inp, level, in_scale, rot_sets, n_outs, pool, pt_scale, pt_index, out, flags=0):
+        self.ctx = ctx
+        self.keep = (inp, pool, out)
+        B = len(rot_sets)
+        self._n_rot = (ctypes.c_int32 * B)(*[len(r) for r in rot_sets])
+        flat = [int(x) for r in rot_sets for x in r]
+        self._rots = (ctypes.c_int32 * len(flat))(*flat)
+        self._n_out = (ctypes.c_int32 * B)(*[int(m) for m in n_outs])
+        fi = [int(x) for lst in pt_index for x in lst]
+        self._pti = (ctypes.c_int32 * len(fi))(*fi)
+        d = he_batch_desc()
+        d.n_items, d.level, d.in_scale, d.pt_scale = B, level, in_scale, pt_scale
+        d.in_ = inp.data_ptr()
+        d.n_rot, d.rots, d.n_out = self._n_rot, self._rots, self._n_out
+        d.pool, d.n_pool, d.pool_level = pool.data_ptr(), pool.shape[0], pool.shape[1]
+        d.pt_index = self._pti
+        d.out = out.data_ptr()
+        h = ctypes.c_void_p()
+        _check(lib().he_batch_create(ctx.h, ctypes.byref(d), flags, ctypes.byref(h)))
+        self.h = h
+
+    def run(self, stream=None):
+        _check(lib().he_batch_run(self.h, _stream(stream)))
+
+    def run_plain(self, stream=None):
+        _check(lib().he_batch_run_plain(self.h, _stream(stream)))
+
+    def info(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        sc = ctypes.c_double()
+        _check(lib().he_batch_info(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(sc)))
+        return {"rotations": a.value, "outputs": b.value, "keys": c.value, "out_scale": sc.value}
+
+    def close(self):
+        if self.h:
+            torch.cuda.synchronize()
+            lib().he_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

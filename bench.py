@@ -1,17 +1,28 @@
 #!/usr/bin/env python3
-"""Benchmark: CKKS key-switch rotations/s at N=2^16, L=24 on one MI355X.
+"""Benchmark of the MI355X CKKS hot path under FHEON's encrypted CNN layers.
 
-A step is one batch of ROT_PER_STEP slot rotations (Galois automorphism +
-hybrid key switching: ModUp -> key inner product -> ModDown) of one
-ciphertext at the top level (L=24 limbs: one 60-bit + 23 50-bit primes,
-K=8 60-bit special primes, dnum=3), cycling through three resident rotation
-keys (3 x 96 MiB, more than the 256 MB Infinity Cache) so keys stream from
-HBM.  Inputs (ciphertext and key limbs) are seeded uniform residues, which is
-what RLWE ciphertexts and keys look like; they are resident in HBM before the
-timed region starts.
+Headline (``value``): key-switch rotations/s at N=2^16, L=24 — a step is one
+batch of ROT_PER_STEP plain slot rotations (Galois automorphism + hybrid key
+switching: ModUp -> key inner product -> ModDown) of one ciphertext at the
+top level (one 60-bit + 23 50-bit primes, K=8 60-bit special primes,
+dnum=3), cycling through three resident rotation keys (3 x 96 MiB, more than
+the 256 MB Infinity Cache) so keys stream from HBM.
 
-Prints one JSON line (see the design doc for the fields).  --gpus > 1 is refused:
-this build targets one GPU.
+Measured in the same run and reported beside it:
+  * roofline of the dominant kernel, from HIP events around every launch;
+  * layer latencies: the tiny conv (N=2^12), the LeNet-5-shaped stack
+    (N=2^14), and the ResNet-20-shaped conv A / conv B / global pooling / FC
+    (N=2^16);
+  * batched key switching: 64 ciphertexts with seeded hoisted rotation sets
+    of 9-49 indices from a 7x7-window key pool and 1-32 outputs each,
+    batched + graph-captured vs the per-op path, same GPU;
+  * serving: Poisson arrivals of LeNet-shaped (3/4) and ResNet-shaped (1/4)
+    requests, continuous batching vs sequential FIFO on the same trace;
+  * the CPU oracle on a bounded sample (a baseline, not a target).
+Inputs are seeded synthetic residues (what RLWE ciphertexts, keys and
+encoded plaintexts look like), resident in HBM before each timed region.
+
+--gpus > 1 is refused: this build measures one GPU.
 """
 import argparse
 import json
@@ -22,7 +33,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-CFG = dict(log_n=16, q_bits=[60] + [50] * 23, p_bits=[60] * 8, alpha=8, log_scale=50)
+CFG0 = dict(log_n=12, q_bits=[54, 40, 40], p_bits=[55], alpha=1)
+CFG1 = dict(log_n=14, q_bits=[60] + [45] * 7, p_bits=[60, 60], alpha=2)
+CFG2 = dict(log_n=16, q_bits=[60] + [50] * 23, p_bits=[60] * 8, alpha=8)
 ROTATIONS = [1, -1, 32]
 ROT_PER_STEP = 48
 HBM_PEAK_GBS = 8000.0
@@ -39,53 +52,72 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the CPU baseline sample")
+    ap.add_argument("--only-headline", action="store_true", help="skip layers / batched / serving sections")
+    ap.add_argument("--serve-requests", type=int, default=60)
     return ap.parse_args()
 
 
-def cpu_baseline(budget_s):
-    """The oracle (test infrastructure) timed on the host on a bounded sample:
-    whole single rotations at the same parameters, as many as fit the budget."""
-    from oracle import ckks
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def new_ctx(cfg):
+    from paper_2510_03996_amd import he
+
+    return he.Context(cfg["log_n"], cfg["q_bits"], cfg["p_bits"], cfg["alpha"])
+
+
+def upload_synthetic_keys(ctx, keys, seed, relin=False):
     import synth
+    from paper_2510_03996_amd import he
 
-    pr = ckks.Params(**CFG)
-    ctx = ckks.Context(pr)
-    sk, pk = ctx.keygen(7)
-    key = ctx.gen_rotation_key(sk, ROTATIONS[0], 7)
-    ct = ctx.encrypt(pk, ctx.encode(synth.uniform_slots(1, pr.n // 2), pr.scale, pr.L), 7)
-    done, t0 = 0, time.perf_counter()
-    while True:
-        ctx.rotate(ct, ROTATIONS[0], {ROTATIONS[0]: key})
-        done += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or done >= 50:
-            break
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": done / el, "unit": "rotations/s", "cores": threads, "kind": "oracle",
-            "sample": "%d single key-switch rotations at N=2^16 L=24 K=8 dnum=3 (%.1f s)" % (done, el)}
+    ids = list(keys) + ([he.KEY_RELIN] if relin else [])
+    for t, r in enumerate(ids):
+        k = synth.device_residues(seed * 7919 + t, ctx.moduli, ctx.n, lead=(ctx.dnum, 2))
+        ctx.key_upload(r, k)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus %d refused)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def synthetic_pts(ctx, count, level, seed, scale):
+    import synth
+    from paper_2510_03996_amd import he
+
+    if count == 0:
+        return []
+    block = synth.device_residues(seed, ctx.moduli[:level], ctx.n, lead=(count,))
+    return [he.Plaintext(block[i], scale) for i in range(count)]
+
+
+def synthetic_ct(ctx, level, seed, scale):
+    import synth
+    from paper_2510_03996_amd import he
+
+    d = synth.device_residues(seed, ctx.moduli[:level], ctx.n, lead=(2,))
+    return he.Ciphertext(d.contiguous(), level, scale)
+
+
+def timed(fn, reps, stream):
+    import torch
+
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    stream.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+# ---------------------------------------------------------------- headline
+def headline(args):
     import torch
 
     import synth
     from paper_2510_03996_amd import he
 
-    torch.cuda.init()
-    dev = torch.device("cuda", 0)
-    ctx = he.Context(CFG["log_n"], CFG["q_bits"], CFG["p_bits"], CFG["alpha"])
-    N, L, K = ctx.n, ctx.L, ctx.K
-    dnum = ctx.dnum
-    # resident inputs: three rotation keys and one ciphertext (seeded residues)
-    for i, r in enumerate(ROTATIONS):
-        key = synth.residues(100 + i, ctx.moduli, N)  # [L+K][N] pattern, tiled to the key shape
-        full = he.to_device(key).unsqueeze(0).unsqueeze(0).expand(dnum, 2, L + K, N).contiguous()
-        ctx.key_upload(r, full)
-    ct = ctx.ct_from_numpy(synth.residues(1, ctx.moduli[:L], N)[None].repeat(2, 0), 2.0 ** 50)
+    ctx = new_ctx(CFG2)
+    N, L, K, dnum = ctx.n, ctx.L, ctx.K, ctx.dnum
+    upload_synthetic_keys(ctx, ROTATIONS, 1)
+    ct = synthetic_ct(ctx, L, 2, 2.0 ** 50)
     outs = [ctx.new_ct(L), ctx.new_ct(L)]
     stream = torch.cuda.current_stream()
 
@@ -102,14 +134,11 @@ def main():
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     rot_s = args.steps * ROT_PER_STEP / el
-
-    # live per-kernel roofline: same steps again with HIP events around each launch
-    he.lib().he_profile_begin(ctx.h)
+    # live per-kernel roofline: the same steps again with HIP events around each launch
+    ctx.profile_begin()
     for _ in range(args.steps):
         step()
-    buf = he.ctypes.create_string_buffer(1 << 16)
-    n = he.lib().he_profile_end(ctx.h, buf, len(buf))
-    kern = json.loads(buf.value[:n].decode())
+    kern = ctx.profile_end()
     dom_name = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dom_name]
     sec = d["ms"] / 1e3
@@ -125,6 +154,217 @@ def main():
     roof.update({"traffic": None, "kernel": dom_name, "avg_launch_us": round(d["ms"] / d["launches"] * 1e3, 2),
                  "hbm_GBs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4), "gmodmul_s": round(gmm, 1)})
     ks_bytes = 2 * L * N * 8 + 2 * dnum * (L + K) * N * 8 + 2 * L * N * 8
+    ctx.close()
+    return rot_s, el, roof, kern, ks_bytes, (L, K, dnum)
+
+
+# ---------------------------------------------------------------- layers
+def layer_latencies(reps=3):
+    import torch
+
+    from paper_2510_03996_amd import he, models
+
+    out = {}
+    s = torch.cuda.current_stream()
+    # tiny conv, N=2^12
+    c0 = new_ctx(CFG0)
+    fm = he.fmap(1, 8, 8)
+    pl = c0.conv2d_plan(fm, 1, 3, 1, 1)
+    upload_synthetic_keys(c0, pl.keys(), 10)
+    ct = synthetic_ct(c0, 3, 11, 2.0 ** 40)
+    kp = synthetic_pts(c0, pl.n_kernel_pts, 3, 12, 2.0 ** 40)
+    out["conv3x3_1x8x8_n12_ms"] = round(timed(lambda: c0.conv2d(ct, fm, 1, 3, 1, 1, kp, [], stream=s), reps, s) * 1e3, 3)
+    c0.close()
+    # LeNet-5-shaped stack, N=2^14
+    c1 = new_ctx(CFG1)
+    fm0, pc, pp, keys = models.lenet_plan(c1)
+    upload_synthetic_keys(c1, keys, 20, relin=True)
+    chain = models.lenet_chain(c1, synthetic_pts(c1, pc.n_kernel_pts, 8, 21, 2.0 ** 45),
+                               synthetic_pts(c1, pp.n_mask_pts, 8, 22, 2.0 ** 45), 2.0 ** 45)
+    ct = synthetic_ct(c1, 8, 23, 2.0 ** 45)
+
+    def run_chain(ch, x):
+        for st in ch.stages:
+            x = st(x, s)
+        return x
+
+    out["lenet5_stack_n14_ms"] = round(timed(lambda: run_chain(chain, ct), reps, s) * 1e3, 3)
+    c1.close()
+    # ResNet-20-shaped layers, N=2^16
+    c2 = new_ctx(CFG2)
+    fm0, pa, pb, pg, pf, keys = models.resnet_plan(c2)
+    upload_synthetic_keys(c2, keys, 30)
+    sc = 2.0 ** 50
+    ct = synthetic_ct(c2, 24, 31, sc)
+    ak, am = synthetic_pts(c2, pa.n_kernel_pts, 24, 32, sc), synthetic_pts(c2, pa.n_mask_pts, 24, 33, sc)
+    out["resnet_convA_16x32x32_n16_ms"] = round(timed(lambda: c2.conv2d(ct, fm0, 16, 3, 1, 1, ak, am, stream=s), reps, s) * 1e3, 3)
+    del ak, am
+    ctb = synthetic_ct(c2, 22, 34, sc)
+    bk, bm = synthetic_pts(c2, pb.n_kernel_pts, 22, 35, sc), synthetic_pts(c2, pb.n_mask_pts, 22, 36, sc)
+    out["resnet_convB_s2_n16_ms"] = round(timed(lambda: c2.conv2d(ctb, pa.out, 32, 3, 2, 1, bk, bm, stream=s), reps, s) * 1e3, 3)
+    del bk, bm
+    ctg = synthetic_ct(c2, 17, 37, sc)
+    gm = synthetic_pts(c2, pg.n_mask_pts, 17, 38, sc)
+    out["resnet_gap_32x16x16_n16_ms"] = round(timed(lambda: c2.avgpool(ctg, pb.out, 0, 1, gm, stream=s), reps, s) * 1e3, 3)
+    ctf = synthetic_ct(c2, 16, 39, sc)
+    fr, fmk = synthetic_pts(c2, 10, 16, 40, sc), synthetic_pts(c2, 1, 16, 41, sc)
+    out["resnet_fc_64x10_n16_ms"] = round(timed(lambda: c2.fc(ctf, 64, 10, fr, fmk, stream=s), reps, s) * 1e3, 3)
+    out["key_switches"] = {"conv3x3_n12": 8, "lenet5_stack": pc.key_switches + pp.key_switches + 2,
+                           "resnet_convA": pa.key_switches, "resnet_convB": pb.key_switches,
+                           "resnet_gap": pg.key_switches, "resnet_fc": pf.key_switches}
+    c2.close()
+    return out
+
+
+# ---------------------------------------------------------------- batched
+def batched(reps=2):
+    import torch
+
+    import synth
+    from paper_2510_03996_amd import he
+
+    ctx = new_ctx(CFG2)
+    L, N = ctx.L, ctx.n
+    pool_offsets = [dy * 32 + dx for dy in range(-3, 4) for dx in range(-3, 4) if (dy, dx) != (0, 0)] + [1024]
+    B = 64
+    sets, outs = synth.rotation_sets(7, B, pool_offsets, 9, 49, 1, 32)
+    upload_synthetic_keys(ctx, pool_offsets, 50)
+    inp = synth.device_residues(51, ctx.moduli[:L], N, lead=(B, 2))
+    pool = synth.device_residues(52, ctx.moduli[:L], N, lead=(64,))
+    pos = lambda i, t: t
+    pti = [[(i + 7 * o + 13 * pos(i, t)) % 64 for o in range(outs[i]) for t in range(len(sets[i]))] for i in range(B)]
+    total = sum(outs)
+    out_b = torch.empty((total, 2, L - 1, N), dtype=torch.int64, device="cuda")
+    out_p = torch.empty_like(out_b)
+    s = torch.cuda.Stream()
+    res = {}
+    rot = sum(len(x) for x in sets)
+    with torch.cuda.stream(s):
+        bt = he.Batch(ctx, inp, L, 2.0 ** 50, sets, outs, pool, 2.0 ** 50, pti, out_b, he.BATCH_GRAPH)
+        tb = timed(lambda: bt.run(s), reps, s)
+        pl = he.Batch(ctx, inp, L, 2.0 ** 50, sets, outs, pool, 2.0 ** 50, pti, out_p, 0)
+        tp = timed(lambda: pl.run_plain(s), 1, s)
+        same = bool(torch.equal(out_b, out_p))
+        ctx.profile_begin()
+        bt.run(s)
+        s.synchronize()
+        kern = ctx.profile_end()
+        info = bt.info()
+        bt.close()
+        pl.close()
+    ctx.close()
+    res = {"workload": "64 ciphertexts N=2^16 L=24, hoisted sets of 9-49 rotations from a 49-key pool, 1-32 outputs",
+           "rotations": info["rotations"], "outputs": info["outputs"], "mac_terms": sum(len(a) * m for a, m in zip(sets, outs)),
+           "distinct_keys": info["keys"], "batched_s": round(tb, 4), "plain_s": round(tp, 4),
+           "batched_rotations_per_s": round(rot / tb, 1), "plain_rotations_per_s": round(rot / tp, 1),
+           "speedup": round(tp / tb, 3), "bit_identical": same,
+           "kernels_ms": {k: round(v["ms"], 2) for k, v in kern.items()}}
+    return res
+
+
+# ---------------------------------------------------------------- serving
+def synthetic_serving_models(seed=1):
+    """LeNet-shaped (N=2^14) and ResNet-shaped (N=2^16) models with synthetic
+    resident keys and weight plaintexts; returns (models, make_input)."""
+    from paper_2510_03996_amd import models, serve
+
+    c1 = new_ctx(CFG1)
+    fm0, pc, pp, k1 = models.lenet_plan(c1)
+    upload_synthetic_keys(c1, k1, seed * 100 + 1, relin=True)
+    lenet = models.lenet_chain(c1, synthetic_pts(c1, pc.n_kernel_pts, 8, seed * 100 + 2, 2.0 ** 45),
+                               synthetic_pts(c1, pp.n_mask_pts, 8, seed * 100 + 3, 2.0 ** 45), 2.0 ** 45)
+    c2 = new_ctx(CFG2)
+    fm0, pa, pb, pg, pf, k2 = models.resnet_plan(c2)
+    upload_synthetic_keys(c2, k2, seed * 100 + 4)
+    sc = 2.0 ** 50
+    resnet = models.resnet_chain(
+        c2, synthetic_pts(c2, pa.n_kernel_pts, 24, seed * 100 + 5, sc), synthetic_pts(c2, pa.n_mask_pts, 24, seed * 100 + 6, sc),
+        synthetic_pts(c2, pb.n_kernel_pts, 22, seed * 100 + 7, sc), synthetic_pts(c2, pb.n_mask_pts, 22, seed * 100 + 8, sc),
+        synthetic_pts(c2, pg.n_mask_pts, 17, seed * 100 + 9, sc), synthetic_pts(c2, 10, 16, seed * 100 + 10, sc),
+        synthetic_pts(c2, 1, 16, seed * 100 + 11, sc))
+    nbuf = 24
+    ms = {"lenet": serve.Model("lenet", c1, lenet.stages, nbuf, c1.lane_bytes(nbuf) + 4 * 2 * 8 * c1.n * 8),
+          "resnet": serve.Model("resnet", c2, resnet.stages, nbuf, c2.lane_bytes(nbuf) + 4 * 2 * 24 * c2.n * 8)}
+
+    def make_input(kind, sd):
+        if kind == "lenet":
+            return synthetic_ct(c1, 8, sd, 2.0 ** 45)
+        return synthetic_ct(c2, 24, sd, sc)
+
+    return ms, make_input
+
+
+def serving(n_req):
+    import numpy as np
+
+    import synth
+    from paper_2510_03996_amd import serve
+
+    ms, make_input = synthetic_serving_models(3)
+    srv = serve.Server(ms, slots=4)
+    # mean plain service time from one request of each kind, run alone
+    warm = [serve.Request(i, k, 0.0, make_input(k, 900 + i)) for i, k in enumerate(["lenet", "resnet", "lenet", "resnet"])]
+    w = srv.serve(warm, "sequential")
+    t_len = np.mean([r.t_done - r.t_admit for r in w if r.kind == "lenet"])
+    t_res = np.mean([r.t_done - r.t_admit for r in w if r.kind == "resnet"])
+    mean_service = 0.75 * t_len + 0.25 * t_res
+    res = {"workload": "Poisson arrivals, LeNet-5-shaped N=2^14 (3/4) and ResNet-20-shaped N=2^16 (1/4) requests",
+           "requests": n_req, "slots": 4, "service_ms": {"lenet": round(t_len * 1e3, 2), "resnet": round(t_res * 1e3, 2)}}
+    kinds = ["lenet" if k == 0 else "resnet" for k in synth.request_mix(11, n_req)]
+    inputs = [make_input(k, 1000 + i) for i, k in enumerate(kinds)]
+    for load in (0.7, 0.9, 1.5):
+        rate = load / mean_service
+        arr = synth.poisson_arrivals(12, rate, n_req)
+        row = {"rate_req_s": round(rate, 2)}
+        for mode in ("sequential", "continuous"):
+            log("serving load %.1f, %s" % (load, mode))
+            reqs = [serve.Request(i, k, arr[i], inputs[i]) for i, k in enumerate(kinds)]
+            done = srv.serve(reqs, mode)
+            lat = [r.latency for r in done]
+            span = max(r.t_done for r in done) - min(r.arrival for r in done)
+            row[mode] = {"req_per_s": round(len(done) / span, 2), "p50_ms": round(serve.percentile(lat, 50) * 1e3, 2),
+                         "p99_ms": round(serve.percentile(lat, 99) * 1e3, 2)}
+        row["max_in_flight"] = srv.max_active
+        res["load_%.1f" % load] = row
+    srv.close()
+    for m in ms.values():
+        m.ctx.close()
+    return res
+
+
+def cpu_baseline(budget_s):
+    """The oracle (test infrastructure) timed on the host on a bounded sample:
+    whole single rotations at the headline parameters, as many as fit the budget."""
+    from oracle import ckks
+    import synth
+
+    pr = ckks.Params(**dict(CFG2, log_scale=50))
+    ctx = ckks.Context(pr)
+    sk, pk = ctx.keygen(7)
+    key = ctx.gen_rotation_key(sk, ROTATIONS[0], 7)
+    ct = ctx.encrypt(pk, ctx.encode(synth.uniform_slots(1, pr.n // 2), pr.scale, pr.L), 7)
+    done, t0 = 0, time.perf_counter()
+    while True:
+        ctx.rotate(ct, ROTATIONS[0], {ROTATIONS[0]: key})
+        done += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or done >= 50:
+            break
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(done / el, 3), "unit": "rotations/s", "cores": threads, "kind": "oracle",
+            "sample": "%d single key-switch rotations at N=2^16 L=24 K=8 dnum=3 (%.1f s)" % (done, el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (--gpus %d refused)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    torch.cuda.init()
+    log("headline: plain key-switch rotations")
+    rot_s, el, roof, kern, ks_bytes, (L, K, dnum) = headline(args)
     result = {
         "metric": "key-switch rotations/s at N=2^16 L=24",
         "value": round(rot_s, 1),
@@ -145,10 +385,17 @@ def main():
         "roofline": roof,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in kern.items()},
     }
+    if not args.only_headline:
+        log("layer latencies")
+        result["layers"] = layer_latencies()
+        log("batched key switching (64 ciphertexts)")
+        result["batched"] = batched()
+        log("serving")
+        result["serving"] = serving(args.serve_requests)
     if not args.no_cpu:
+        log("cpu baseline (oracle)")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
-    ctx.close()
-    print(json.dumps(result))
+    print(json.dumps(result), flush=True)
 
 
 if __name__ == "__main__":

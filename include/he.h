@@ -102,6 +102,17 @@ int he_ctx_moduli(const he_ctx* ctx, uint64_t* out, int cap);
 int he_ctx_info(const he_ctx* ctx, int32_t* log_n, int32_t* n_q, int32_t* n_p, int32_t* alpha);
 const char* he_last_error(void);
 
+/* Execution lanes.  Calls on different streams of one context may run
+ * concurrently on the device: each stream gets its own key-switch workspace
+ * and pool of temporary ciphertexts (a "lane", created on first use).  Calls
+ * on the same stream are ordered.  he_lane_reserve pre-allocates the lane of
+ * `stream` with n_ct_buffers temporaries (so later calls allocate nothing
+ * unless a layer needs more); he_lane_release synchronises the stream and
+ * frees its lane; he_lane_bytes gives the device bytes of one lane. */
+int he_lane_reserve(he_ctx* ctx, he_stream stream, int n_ct_buffers);
+int he_lane_release(he_ctx* ctx, he_stream stream);
+size_t he_lane_bytes(const he_ctx* ctx, int n_ct_buffers);
+
 /* ------------------------------------------------------------ keys
  * Evaluation keys are the paper's "rotation keys" and relinearization key
  * (Section "Evaluation Keys Management"): preloaded into HBM and kept

@@ -432,23 +432,19 @@ int he_batch_run_plain(he_batch* hb, he_stream st) {
   // temporaries: the rotated copies of one input and one accumulator
   int nmax = 0;
   for (int x : b->n_rot) nmax = std::max(nmax, x);
+  Lane* lane = lane_for(c, (hipStream_t)st);
+  if (!lane) return HE_ENOMEM;
   std::vector<uint64_t*> tmp;
   auto cleanup = [&]() {
-    for (uint64_t* p : tmp) c->ct_pool.push_back(p);
+    for (uint64_t* p : tmp) lane->ct_pool.push_back(p);
   };
   for (int i = 0; i < nmax + 1; i++) {
-    if (!c->ct_pool.empty()) {
-      tmp.push_back(c->ct_pool.back());
-      c->ct_pool.pop_back();
-    } else {
-      void* v = nullptr;
-      if (hipMalloc(&v, 2 * c->L * N * 8) != hipSuccess) {
-        cleanup();
-        return set_error(HE_ENOMEM, "plain batch temporaries");
-      }
-      c->ct_pool_all.push_back((uint64_t*)v);
-      tmp.push_back((uint64_t*)v);
+    uint64_t* p = lane_ct_get(c, lane);
+    if (!p) {
+      cleanup();
+      return HE_ENOMEM;
     }
+    tmp.push_back(p);
   }
   std::vector<he_ct> rot(nmax);
   int rc = HE_OK;

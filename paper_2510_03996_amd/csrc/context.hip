@@ -313,6 +313,47 @@ static int ctx_init(Ctx* c, const he_params* p) {
   return HE_OK;
 }
 
+Lane* lane_for(Ctx* c, hipStream_t s) {
+  std::lock_guard<std::mutex> lk(c->lanes_mu);
+  auto it = c->lanes.find(s);
+  if (it != c->lanes.end()) return it->second;
+  Lane* ln = new Lane();
+  if (s == nullptr) {
+    ln->ws = c->ws;
+  } else {
+    void* v = nullptr;
+    if (hipMalloc(&v, c->ws_words * 8) != hipSuccess) {
+      delete ln;
+      set_error(HE_ENOMEM, "lane workspace allocation failed");
+      return nullptr;
+    }
+    ln->ws = (uint64_t*)v;
+  }
+  c->lanes[s] = ln;
+  return ln;
+}
+
+uint64_t* lane_ct_get(Ctx* c, Lane* ln) {
+  if (!ln->ct_pool.empty()) {
+    uint64_t* p = ln->ct_pool.back();
+    ln->ct_pool.pop_back();
+    return p;
+  }
+  void* v = nullptr;
+  if (hipMalloc(&v, (size_t)2 * c->L * c->n * 8) != hipSuccess) {
+    set_error(HE_ENOMEM, "ciphertext buffer allocation failed");
+    return nullptr;
+  }
+  ln->ct_all.push_back((uint64_t*)v);
+  return (uint64_t*)v;
+}
+
+static void lane_free(Ctx* c, hipStream_t s, Lane* ln) {
+  for (uint64_t* p : ln->ct_all) hipFree(p);
+  if (s != nullptr && ln->ws) hipFree(ln->ws);
+  delete ln;
+}
+
 }  // namespace he
 
 using namespace he;
@@ -320,6 +361,41 @@ using namespace he;
 extern "C" {
 
 const char* he_last_error(void) { return g_err.c_str(); }
+
+int he_lane_reserve(he_ctx* h, he_stream stream, int n_ct_buffers) {
+  if (!h || n_ct_buffers < 0) return set_error(HE_EINVAL, "bad argument");
+  Ctx* c = &h->c;
+  Lane* ln = lane_for(c, (hipStream_t)stream);
+  if (!ln) return HE_ENOMEM;
+  std::vector<uint64_t*> got;
+  for (int i = 0; i < n_ct_buffers; i++) {
+    uint64_t* p = lane_ct_get(c, ln);
+    if (!p) {
+      for (uint64_t* q : got) ln->ct_pool.push_back(q);
+      return HE_ENOMEM;
+    }
+    got.push_back(p);
+  }
+  for (uint64_t* q : got) ln->ct_pool.push_back(q);
+  return HE_OK;
+}
+
+int he_lane_release(he_ctx* h, he_stream stream) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  HE_HIP(hipStreamSynchronize((hipStream_t)stream));
+  std::lock_guard<std::mutex> lk(c->lanes_mu);
+  auto it = c->lanes.find((hipStream_t)stream);
+  if (it == c->lanes.end()) return HE_OK;
+  lane_free(c, it->first, it->second);
+  c->lanes.erase(it);
+  return HE_OK;
+}
+
+size_t he_lane_bytes(const he_ctx* h, int n_ct_buffers) {
+  if (!h) return 0;
+  return h->c.ws_words * 8 + (size_t)n_ct_buffers * 2 * h->c.L * h->c.n * 8;
+}
 
 int he_ctx_create(const he_params* p, int device, he_ctx** out) {
   if (!p || !out) return set_error(HE_EINVAL, "null argument");
@@ -349,7 +425,8 @@ int he_ctx_destroy(he_ctx* h) {
   hipSetDevice(h->c.device);
   hipDeviceSynchronize();
   for (auto& kv : h->c.keys) hipFree(kv.second);
-  for (uint64_t* p : h->c.ct_pool_all) hipFree(p);
+  for (auto& kv : h->c.lanes) lane_free(&h->c, kv.first, kv.second);
+  h->c.lanes.clear();
   for (void* p : h->c.allocs) hipFree(p);
   delete h;
   return HE_OK;

@@ -4,6 +4,7 @@
 
 #include <cstdint>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -30,6 +31,16 @@ struct ProfRec {
   double bytes, modmul;
 };
 
+// Per-stream execution lane: the key-switch workspace and the pool of
+// temporary ciphertext buffers used by work enqueued on one stream.  Work on
+// different streams never shares scratch memory, so requests issued on
+// different streams may overlap on the device.
+struct Lane {
+  uint64_t* ws = nullptr;
+  std::vector<uint64_t*> ct_pool;  // free [2][L][N] buffers
+  std::vector<uint64_t*> ct_all;   // every buffer this lane allocated
+};
+
 struct Ctx {
   int device = 0;
   int log_n = 0, n = 0, L = 0, K = 0, alpha = 0;
@@ -52,8 +63,9 @@ struct Ctx {
   uint64_t* ws = nullptr;
   size_t ws_words = 0;
   std::vector<void*> allocs;
-  // reusable [2][L][N] ciphertext buffers for layer temporaries
-  std::vector<uint64_t*> ct_pool, ct_pool_all;
+  // execution lanes by stream (the default stream's lane uses `ws`)
+  std::map<hipStream_t, Lane*> lanes;
+  std::mutex lanes_mu;
   bool prof_on = false;
   std::vector<ProfRec> prof;
 
@@ -133,6 +145,9 @@ int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s);
 int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
              const uint64_t* add0, const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s);
 const uint64_t* find_key(Ctx* c, int32_t id);
+// lane of a stream (created on first use; throws nothing, returns null on allocation failure)
+Lane* lane_for(Ctx* c, hipStream_t s);
+uint64_t* lane_ct_get(Ctx* c, Lane* ln);  // null on allocation failure
 int check_ct(const Ctx* c, const he_ct* x, const char* what);
 int check_out(const Ctx* c, const he_ct* x, int need_level);
 

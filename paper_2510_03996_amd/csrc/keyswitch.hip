@@ -191,7 +191,9 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
     }
   }
   hipStream_t s = (hipStream_t)st;
-  WS w = ws_layout(c, c->ws);
+  Lane* lane = lane_for(c, s);
+  if (!lane) return HE_ENOMEM;
+  WS w = ws_layout(c, lane->ws);
   const uint64_t* c0 = in->data;
   const uint64_t* c1 = in->data + (size_t)in->cap * N;
   if (any && (rc = ks_modup(c, w, c1, l, s))) return rc;
@@ -225,7 +227,9 @@ int he_relin(he_ctx* h, const uint64_t* d, int level, double scale, he_ct* out, 
   if (!key) return set_error(HE_ENOKEY, "relinearization key not resident");
   hipStream_t s = (hipStream_t)st;
   const size_t N = c->n;
-  WS w = ws_layout(c, c->ws);
+  Lane* lane = lane_for(c, s);
+  if (!lane) return HE_ENOMEM;
+  WS w = ws_layout(c, lane->ws);
   const uint64_t* d0 = d;
   const uint64_t* d1 = d + (size_t)level * N;
   const uint64_t* d2 = d + 2 * (size_t)level * N;
@@ -266,7 +270,9 @@ extern "C" int he_mul_relin(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* ou
   if ((rc = check_out(c, out, l))) return rc;
   const size_t N = c->n;
   hipStream_t s = (hipStream_t)st;
-  WS w = ws_layout(c, c->ws);
+  Lane* lane = lane_for(c, s);
+  if (!lane) return HE_ENOMEM;
+  WS w = ws_layout(c, lane->ws);
   {
     ProfScope ps(c, "tensor", s, 8.0 * N * l * 7, 4.0 * N * l);
     k_tensor<<<dim3(N / 256, l), 256, 0, s>>>(a->data, a->cap * N, b->data, b->cap * N, w.t3, l, c->log_n, c->d_mod);

@@ -28,31 +28,23 @@ static void ck(int rc) {
   if (rc < 0) throw LayerError{rc};
 }
 
-// device ciphertext buffers [2][L][N] reused across calls (stream-ordered)
-static uint64_t* pool_get(Ctx* c) {
-  if (!c->ct_pool.empty()) {
-    uint64_t* p = c->ct_pool.back();
-    c->ct_pool.pop_back();
-    return p;
-  }
-  void* v = nullptr;
-  hipError_t e = hipMalloc(&v, (size_t)2 * c->L * c->n * 8);
-  if (e != hipSuccess) throw LayerError{set_error(HE_ENOMEM, "ciphertext pool allocation failed")};
-  c->ct_pool_all.push_back((uint64_t*)v);
-  return (uint64_t*)v;
-}
-
+// Layer evaluator: temporaries come from the stream's lane pool and go back
+// to it (later reuse is stream-ordered after every kernel enqueued on them).
 struct Ev {
   he_ctx* h;
   Ctx* c;
   he_stream s;
+  Lane* lane;
   std::vector<uint64_t*> held;
-  Ev(he_ctx* h_, he_stream s_) : h(h_), c(&h_->c), s(s_) {}
+  Ev(he_ctx* h_, he_stream s_) : h(h_), c(&h_->c), s(s_), lane(lane_for(&h_->c, (hipStream_t)s_)) {
+    if (!lane) throw LayerError{HE_ENOMEM};
+  }
   ~Ev() {
-    for (uint64_t* p : held) c->ct_pool.push_back(p);
+    for (uint64_t* p : held) lane->ct_pool.push_back(p);
   }
   he_ct fresh() {
-    uint64_t* p = pool_get(c);
+    uint64_t* p = lane_ct_get(c, lane);
+    if (!p) throw LayerError{HE_ENOMEM};
     held.push_back(p);
     return he_ct{p, 0, c->L, 0.0};
   }
@@ -105,7 +97,7 @@ struct Ev {
   void release(const he_ct& x) {
     for (size_t i = 0; i < held.size(); i++)
       if (held[i] == x.data) {
-        c->ct_pool.push_back(held[i]);
+        lane->ct_pool.push_back(held[i]);
         held[i] = held.back();
         held.pop_back();
         return;

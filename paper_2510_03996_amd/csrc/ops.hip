@@ -187,7 +187,9 @@ int he_rescale(he_ctx* h, const he_ct* in, he_ct* out, he_stream st) {
   if (out->data == in->data && out->cap != in->cap) return set_error(HE_EINVAL, "in-place rescale needs equal capacity");
   hipStream_t s = (hipStream_t)st;
   const size_t N = c->n;
-  WS w = ws_layout(c, c->ws);
+  Lane* lane = lane_for(c, s);
+  if (!lane) return HE_ENOMEM;
+  WS w = ws_layout(c, lane->ws);
   uint64_t* T = w.y;   // [2][N] top limbs -> coefficient form
   uint64_t* R = w.rs;  // [2][t][N]
   for (int k = 0; k < 2; k++)

@@ -126,6 +126,8 @@ def lib():
             "he_batch_run_plain": [vp, vp],
             "he_batch_info": [vp, P(i32), P(i32), P(i32), P(ctypes.c_double)],
             "he_batch_destroy": [vp],
+            "he_lane_reserve": [vp, vp, c_int],
+            "he_lane_release": [vp, vp],
             "he_profile_begin": [vp],
             "he_profile_end": [vp, ctypes.c_char_p, sz],
         }
@@ -137,6 +139,8 @@ def lib():
         L.he_last_error.argtypes = []
         L.he_key_bytes.restype = ctypes.c_size_t
         L.he_key_bytes.argtypes = [vp]
+        L.he_lane_bytes.restype = ctypes.c_size_t
+        L.he_lane_bytes.argtypes = [vp, c_int]
         _lib = L
     return _lib
 
@@ -415,6 +419,16 @@ class Context:
         _check(lib().he_poly4(self.h, ctypes.byref(a), cf, float(delta), ctypes.byref(o), _stream(stream)))
         out.update(o)
         return out
+
+    # ---- lanes
+    def lane_reserve(self, stream, n_ct_buffers):
+        _check(lib().he_lane_reserve(self.h, _stream(stream), n_ct_buffers))
+
+    def lane_release(self, stream):
+        _check(lib().he_lane_release(self.h, _stream(stream)))
+
+    def lane_bytes(self, n_ct_buffers):
+        return lib().he_lane_bytes(self.h, n_ct_buffers)
 
     # ---- measurement
     def profile_begin(self):

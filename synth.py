@@ -60,3 +60,17 @@ def poisson_arrivals(seed, rate, count, stream=6):
 def request_mix(seed, count, p_small=0.75, stream=7):
     """Request kinds: 0 (small ring) with probability p_small, else 1."""
     return (rng(seed, stream).uniform(0, 1, count) >= p_small).astype(np.int64)
+
+
+def device_residues(seed, moduli, n, lead=(), device="cuda"):
+    """int64 torch tensor [*lead][len(moduli)][n] on `device`, limb i uniform in
+    [0, moduli[i]) — large seeded stand-ins for keys / ciphertexts /
+    plaintexts generated directly in device memory."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    out = torch.empty(tuple(lead) + (len(moduli), n), dtype=torch.int64, device=device)
+    for i, q in enumerate(moduli):
+        out[..., i, :] = torch.randint(0, int(q), tuple(lead) + (n,), generator=g, dtype=torch.int64, device=device)
+    return out

@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the CPU baseline sample")
     ap.add_argument("--only-headline", action="store_true", help="skip layers / batched / serving sections")
+    ap.add_argument("--only", choices=["layers", "batched", "serving"], default=None,
+                    help="run the headline plus one section (profiling runs)")
     ap.add_argument("--serve-requests", type=int, default=60)
     return ap.parse_args()
 
@@ -240,7 +242,7 @@ def batched(reps=2):
     res = {}
     rot = sum(len(x) for x in sets)
     with torch.cuda.stream(s):
-        bt = he.Batch(ctx, inp, L, 2.0 ** 50, sets, outs, pool, 2.0 ** 50, pti, out_b, he.BATCH_GRAPH)
+        bt = he.Batch(ctx, inp, L, 2.0 ** 50, sets, outs, pool, 2.0 ** 50, pti, out_b, he.BATCH_GRAPH | he.BATCH_TUNE)
         tb = timed(lambda: bt.run(s), reps, s)
         pl = he.Batch(ctx, inp, L, 2.0 ** 50, sets, outs, pool, 2.0 ** 50, pti, out_p, 0)
         tp = timed(lambda: pl.run_plain(s), 1, s)
@@ -250,6 +252,7 @@ def batched(reps=2):
         s.synchronize()
         kern = ctx.profile_end()
         info = bt.info()
+        tune = bt.tuning()
         bt.close()
         pl.close()
     ctx.close()
@@ -257,7 +260,7 @@ def batched(reps=2):
            "rotations": info["rotations"], "outputs": info["outputs"], "mac_terms": sum(len(a) * m for a, m in zip(sets, outs)),
            "distinct_keys": info["keys"], "batched_s": round(tb, 4), "plain_s": round(tp, 4),
            "batched_rotations_per_s": round(rot / tb, 1), "plain_rotations_per_s": round(rot / tp, 1),
-           "speedup": round(tp / tb, 3), "bit_identical": same,
+           "speedup": round(tp / tb, 3), "bit_identical": same, "autotune": tune,
            "kernels_ms": {k: round(v["ms"], 2) for k, v in kern.items()}}
     return res
 
@@ -385,11 +388,14 @@ def main():
         "roofline": roof,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in kern.items()},
     }
-    if not args.only_headline:
+    sections = [] if args.only_headline else ([args.only] if args.only else ["layers", "batched", "serving"])
+    if "layers" in sections:
         log("layer latencies")
         result["layers"] = layer_latencies()
+    if "batched" in sections:
         log("batched key switching (64 ciphertexts)")
         result["batched"] = batched()
+    if "serving" in sections:
         log("serving")
         result["serving"] = serving(args.serve_requests)
     if not args.no_cpu:

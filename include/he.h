@@ -281,11 +281,14 @@ int he_poly4(he_ctx* ctx, const he_ct* in, const double* c, double delta, he_ct*
  * distinct key for all its ciphertexts, batched ModDown, one fused
  * multiply-accumulate kernel and chunked rescaling.  HE_BATCH_GRAPH: the
  * first he_batch_run on a (non-default) stream captures the schedule in a
- * hipGraph, later runs replay it.  HE_BATCH_TILE128: 128-coefficient MAC
- * tiles instead of 64.  Workspace memory is allocated at creation and
- * released by he_batch_destroy. */
+ * hipGraph, later runs replay it.  The fused multiply-accumulate keeps a
+ * group of 8 outputs in registers (HE_BATCH_MAC4: 4); HE_BATCH_TUNE times
+ * both groupings on the batch's own shapes at creation and keeps the
+ * faster.  Workspace memory is allocated at creation and released by
+ * he_batch_destroy. */
 #define HE_BATCH_GRAPH 1
-#define HE_BATCH_TILE128 2
+#define HE_BATCH_MAC4 2
+#define HE_BATCH_TUNE 4
 typedef struct he_batch he_batch;
 typedef struct {
   int32_t n_items;
@@ -307,6 +310,9 @@ int he_batch_run(he_batch* batch, he_stream stream);
 int he_batch_run_plain(he_batch* batch, he_stream stream);
 int he_batch_info(const he_batch* batch, int32_t* total_rotations, int32_t* total_outputs, int32_t* distinct_keys,
                   double* out_scale);
+/* The MAC grouping in use and, after HE_BATCH_TUNE, the timed milliseconds
+ * of the 4- and 8-output groupings (0 when not tuned). */
+int he_batch_tuning(const he_batch* batch, int32_t* mac_outputs_per_group, float* ms_group4, float* ms_group8);
 int he_batch_destroy(he_batch* batch);
 
 /* ------------------------------------------------------------ measurement

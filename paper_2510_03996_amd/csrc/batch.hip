@@ -93,51 +93,77 @@ __global__ __launch_bounds__(256) void k_combine_multi(const uint64_t* __restric
   rot_out[(size_t)z * ln + (size_t)i * n + k] = v;
 }
 
-// out[i,o] (unrescaled) for every item: grid x = tile of TILE coefficients,
-// y = limb, z = item.  Each thread stages its coefficient of the item's n
-// rotated copies (both polynomials) in its own LDS column, then accumulates
-// every output with 128-bit products kept below q 2^64.
-template <int TILE>
-__global__ __launch_bounds__(TILE) void k_mac_multi(int nmax,const uint64_t* __restrict__ rot_all, int level, int logn,
-                                                    const ModInfo* __restrict__ mods,
-                                                    const int32_t* __restrict__ rot_off,
-                                                    const int32_t* __restrict__ rot_idx,
-                                                    const int32_t* __restrict__ out_off,
-                                                    const int32_t* __restrict__ pt_off,
-                                                    const int32_t* __restrict__ pt_index,
-                                                    const uint64_t* __restrict__ pool, size_t pool_stride,
-                                                    uint64_t* __restrict__ mac_all) {
-  extern __shared__ uint64_t rv[];  // [2 nmax][TILE]
+// out[i,o] (unrescaled) for every item: grid x = item, y = tile of 256
+// coefficients, z = limb.  A thread keeps OG outputs' 128-bit accumulators
+// (both polynomials) in registers and streams the item's rotated copies once
+// per group of OG outputs (the copies of one tile stay in L2 between groups);
+// every (output, rotation) plaintext residue is read once.  Accumulators stay
+// below 4 q 2^64 by subtracting 2 q 2^64 (a multiple of q) after every second
+// term; two REDCs give the canonical residue.
+template <int OG>
+__global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ rot_all, int level, int logn,
+                                                   const ModInfo* __restrict__ mods,
+                                                   const int32_t* __restrict__ rot_off,
+                                                   const int32_t* __restrict__ rot_idx,
+                                                   const int32_t* __restrict__ out_off,
+                                                   const int32_t* __restrict__ pt_off,
+                                                   const int32_t* __restrict__ pt_index,
+                                                   const uint64_t* __restrict__ pool, size_t pool_stride,
+                                                   uint64_t* __restrict__ mac_all) {
   const size_t n = (size_t)1 << logn;
-  const int tid = threadIdx.x;
-  const size_t k = (size_t)blockIdx.x * TILE + tid;
-  const int limb = blockIdx.y, it = blockIdx.z;
+  const size_t k = (size_t)blockIdx.y * 256 + threadIdx.x;
+  const int limb = blockIdx.z, it = blockIdx.x;
   const ModInfo mi = mods[limb];
+  const uint64_t q2 = 2 * mi.q;
   const size_t ln = (size_t)level * n;
   const int r0 = rot_off[it], nr = rot_off[it + 1] - r0;
   const int o0 = out_off[it], no = out_off[it + 1] - o0;
-  for (int t = 0; t < nr; t++) {
-    const uint64_t* rc = rot_all + (size_t)rot_idx[r0 + t] * 2 * ln + (size_t)limb * n + k;
-    rv[(2 * t) * TILE + tid] = rc[0];
-    rv[(2 * t + 1) * TILE + tid] = rc[ln];
-  }
   const int32_t* pix = pt_index + pt_off[it];
-  for (int o = 0; o < no; o++) {
-    U128 a0{0, 0}, a1{0, 0};
+  const uint64_t* poolk = pool + (size_t)limb * n + k;
+  for (int og = 0; og < no; og += OG) {
+    const int cnt = no - og < OG ? no - og : OG;
+    U128 a[OG][2];
+#pragma unroll
+    for (int u = 0; u < OG; u++) a[u][0] = a[u][1] = U128{0, 0};
     for (int t = 0; t < nr; t++) {
-      const uint64_t p = pool[(size_t)pix[o * nr + t] * pool_stride + (size_t)limb * n + k];
-      add_wide(a0, mul_wide(p, rv[(2 * t) * TILE + tid]));
-      add_wide(a1, mul_wide(p, rv[(2 * t + 1) * TILE + tid]));
-      if (a0.hi >= mi.q) a0.hi -= mi.q;  // subtract q 2^64 (a multiple of q)
-      if (a1.hi >= mi.q) a1.hi -= mi.q;
+      const uint64_t* rc = rot_all + (size_t)rot_idx[r0 + t] * 2 * ln + (size_t)limb * n + k;
+      const uint64_t x0 = rc[0], x1 = rc[ln];
+#pragma unroll
+      for (int u = 0; u < OG; u++) {
+        if (u < cnt) {
+          const uint64_t p = poolk[(size_t)pix[(og + u) * nr + t] * pool_stride];
+          add_wide(a[u][0], mul_wide(p, x0));
+          add_wide(a[u][1], mul_wide(p, x1));
+          if (t & 1) {
+            if (a[u][0].hi >= q2) a[u][0].hi -= q2;
+            if (a[u][1].hi >= q2) a[u][1].hi -= q2;
+          }
+        }
+      }
     }
-    // a < q 2^64: REDC gives a 2^-64; a second REDC against 2^128 mod q restores a mod q
-    const uint64_t v0 = mont_redc(mul_wide(mont_redc(a0, mi.q, mi.qinv), mi.r2), mi.q, mi.qinv);
-    const uint64_t v1 = mont_redc(mul_wide(mont_redc(a1, mi.q, mi.qinv), mi.r2), mi.q, mi.qinv);
-    uint64_t* dst = mac_all + (size_t)(o0 + o) * 2 * ln + (size_t)limb * n + k;
-    dst[0] = v0;
-    dst[ln] = v1;
+#pragma unroll
+    for (int u = 0; u < OG; u++) {
+      if (u < cnt) {
+        uint64_t* dst = mac_all + (size_t)(o0 + og + u) * 2 * ln + (size_t)limb * n + k;
+#pragma unroll
+        for (int z = 0; z < 2; z++) {
+          U128 v = a[u][z];
+          if (v.hi >= q2) v.hi -= q2;
+          if (v.hi >= mi.q) v.hi -= mi.q;
+          dst[z * ln] = mont_redc(mul_wide(mont_redc(v, mi.q, mi.qinv), mi.r2), mi.q, mi.qinv);
+        }
+      }
+    }
   }
+}
+
+static void launch_mac(int og, dim3 grid, hipStream_t s, const uint64_t* rot, int l, int logn, const ModInfo* mods,
+                       const int32_t* ro, const int32_t* ri, const int32_t* oo, const int32_t* po, const int32_t* pi,
+                       const uint64_t* pool, size_t ps, uint64_t* mac) {
+  if (og == 4)
+    k_mac_multi<4><<<grid, 256, 0, s>>>(rot, l, logn, mods, ro, ri, oo, po, pi, pool, ps, mac);
+  else
+    k_mac_multi<8><<<grid, 256, 0, s>>>(rot, l, logn, mods, ro, ri, oo, po, pi, pool, ps, mac);
 }
 
 // ---------------------------------------------------------------- plan
@@ -169,12 +195,13 @@ struct Batch {
   uint64_t *coeff = nullptr, *ext = nullptr, *u = nullptr, *y = nullptr, *rot = nullptr, *mac = nullptr,
            *rs_T = nullptr, *rs_R = nullptr;
   int rs_chunk = 0;
-  int mac_tile = 64;
-  int nmax = 0;  // largest rotation set
+  int mac_og = 8;  // outputs per register group in the fused MAC (autotuned)
+  int nmax = 0;    // largest rotation set
   std::vector<void*> allocs;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool use_graph = false;
+  float tuned_ms[2] = {0, 0};
   double out_scale = 0;
 };
 
@@ -247,15 +274,8 @@ static int run_batched(Batch* b, hipStream_t s) {
     double terms = 0;
     for (int i = 0; i < b->B; i++) terms += (double)b->n_rot[i] * b->n_out[i];
     ProfScope ps(c, "mac_multi", s, 8.0 * N * l * (2.0 * b->total_pairs + terms + 2.0 * b->total_out), 2.0 * N * l * terms);
-    const size_t lds = (size_t)2 * b->nmax * b->mac_tile * 8;
-    if (b->mac_tile == 64)
-      k_mac_multi<64><<<dim3(N / 64, l, b->B), 64, lds, s>>>(b->nmax, b->rot, l, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx,
-                                                           b->d_out_off, b->d_pt_off, b->d_pt_index, b->pool,
-                                                           (size_t)b->pool_level * N, b->mac);
-    else
-      k_mac_multi<128><<<dim3(N / 128, l, b->B), 128, lds, s>>>(b->nmax, b->rot, l, c->log_n, c->d_mod, b->d_rot_off,
-                                                              b->d_rot_idx, b->d_out_off, b->d_pt_off, b->d_pt_index,
-                                                              b->pool, (size_t)b->pool_level * N, b->mac);
+    launch_mac(b->mac_og, dim3(b->B, N / 256, l), s, b->rot, l, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx,
+               b->d_out_off, b->d_pt_off, b->d_pt_index, b->pool, (size_t)b->pool_level * N, b->mac);
     HE_HIP(hipGetLastError());
   }
   // 4. rescale every output (chunks of rs_chunk ciphertexts = 2 rs_chunk polynomials)
@@ -384,15 +404,37 @@ int he_batch_create(he_ctx* h, const he_batch_desc* d, int flags, he_batch** out
       (rc = balloc(b, &b->mac, (size_t)b->total_out * 2 * l * N)) || (rc = balloc(b, &b->rs_T, (size_t)2 * b->rs_chunk * N)) ||
       (rc = balloc(b, &b->rs_R, (size_t)2 * b->rs_chunk * (l - 1) * N)))
     return fail(rc);
-  b->mac_tile = (flags & HE_BATCH_TILE128) ? 128 : 64;
   for (int x : b->n_rot) b->nmax = std::max(b->nmax, x);
-  {
-    const size_t lds = (size_t)2 * b->nmax * b->mac_tile * 8;
-    if (lds > 160 * 1024) return fail(set_error(HE_EINVAL, "rotation set too large for the MAC tile"));
-    if (b->mac_tile == 64)
-      HE_HIP(hipFuncSetAttribute((const void*)k_mac_multi<64>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    else
-      HE_HIP(hipFuncSetAttribute((const void*)k_mac_multi<128>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  b->mac_og = (flags & HE_BATCH_MAC4) ? 4 : 8;
+  if (flags & HE_BATCH_TUNE) {
+    // time both register groupings of the fused MAC on this batch's shapes
+    // (workspace contents are irrelevant to the timing) and keep the faster
+    hipStream_t ts;
+    HE_HIP(hipStreamCreate(&ts));
+    hipEvent_t e0, e1;
+    HE_HIP(hipEventCreate(&e0));
+    HE_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    for (int og : {4, 8}) {
+      dim3 grid(b->B, N / 256, l);
+      launch_mac(og, grid, ts, b->rot, l, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx, b->d_out_off, b->d_pt_off,
+                 b->d_pt_index, b->pool, (size_t)b->pool_level * N, b->mac);
+      HE_HIP(hipEventRecord(e0, ts));
+      launch_mac(og, grid, ts, b->rot, l, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx, b->d_out_off, b->d_pt_off,
+                 b->d_pt_index, b->pool, (size_t)b->pool_level * N, b->mac);
+      HE_HIP(hipEventRecord(e1, ts));
+      HE_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      HE_HIP(hipEventElapsedTime(&ms, e0, e1));
+      b->tuned_ms[og == 4 ? 0 : 1] = ms;
+      if (ms < best) {
+        best = ms;
+        b->mac_og = og;
+      }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipStreamDestroy(ts);
   }
   b->out_scale = b->in_scale * b->pt_scale / (double)c->mod[b->level - 1];
   *out = hb;
@@ -476,6 +518,14 @@ int he_batch_info(const he_batch* hb, int32_t* total_rotations, int32_t* total_o
   if (total_outputs) *total_outputs = b->total_out;
   if (distinct_keys) *distinct_keys = (int32_t)b->groups.size();
   if (out_scale) *out_scale = b->out_scale;
+  return HE_OK;
+}
+
+int he_batch_tuning(const he_batch* hb, int32_t* mac_outputs_per_group, float* ms_group4, float* ms_group8) {
+  if (!hb) return set_error(HE_EINVAL, "null batch");
+  if (mac_outputs_per_group) *mac_outputs_per_group = hb->b.mac_og;
+  if (ms_group4) *ms_group4 = hb->b.tuned_ms[0];
+  if (ms_group8) *ms_group8 = hb->b.tuned_ms[1];
   return HE_OK;
 }
 

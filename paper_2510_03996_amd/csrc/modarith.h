@@ -13,6 +13,7 @@
 #pragma once
 #include <stdint.h>
 
+#include <math.h>
 #if defined(__HIPCC__)
 #include <hip/hip_runtime.h>
 #define HE_HD __host__ __device__ __forceinline__
@@ -78,6 +79,21 @@ HE_HD uint64_t barrett_reduce(U128 x, uint64_t q, uint64_t mu, int k) {
   return r;
 }
 
+// FP64 product for primes q < 2^50 (residues kept below 4q < 2^52, exact in a
+// double): with wq = fl(w/q), quot = floor(fl(a wq)) is within 1 of
+// floor(a w / q) (|a (wq - w/q)| <= 2^52 2^-54 and the rounding of a wq adds
+// at most 2^-2), so r = a w - quot q lies in [-q, 2q).  a w = hi + lo exactly
+// (two-product with one FMA), hi - quot q is an integer below 2^53 in
+// magnitude and therefore exact in one FMA, and r = (hi - quot q) + lo is
+// exact as well.  Returns r in [0, 2q) (same range as mul_shoup_lazy).
+HE_HD double mul_f64_lazy(double a, double w, double wq, double q) {
+  const double quot = floor(a * wq);
+  const double hi = a * w;
+  const double lo = fma(a, w, -hi);
+  const double r = fma(-quot, q, hi) + lo;
+  return r < 0.0 ? r + q : r;
+}
+
 // Per-modulus constants (device resident).
 struct ModInfo {
   uint64_t q;
@@ -87,6 +103,7 @@ struct ModInfo {
   uint64_t ninv, ninv_p;   // N^{-1} mod q and Shoup companion
   int32_t k;          // bit length of q
   int32_t pad;
+  double dninv, dninvq;  // N^{-1} and N^{-1}/q as doubles (FP64 NTT path, q < 2^50)
 };
 
 HE_HD uint64_t mul_mod(uint64_t a, uint64_t b, const ModInfo& m) {

@@ -118,6 +118,77 @@ struct NttPass {
     }
   }
 
+  // FP64 round for q < 2^50: identical butterflies on exact doubles, products
+  // by mul_f64_lazy (full-rate FMA instead of half-rate 32-bit multiplies).
+  template <int R>
+  HE_HD static void round_f64(double* lds, int tid, int wg, int s0, const double* tw, const double* twq, double q) {
+    constexpr int GPS = M >> R;
+    constexpr int TOTAL = G * GPS;
+    const int dmin = M >> (s0 + R);
+    const int span = M >> s0;
+    const double q2 = 2.0 * q;
+    for (int gid = tid; gid < TOTAL; gid += THREADS) {
+      int g, gg;
+      if (PASS == 1) { g = gid % G; gg = gid / G; }
+      else { g = gid / GPS; gg = gid % GPS; }
+      const int lo = gg % dmin, hi = gg / dmin;
+      const int base = hi * span + lo;
+      double x[1 << R];
+#pragma unroll
+      for (int u = 0; u < (1 << R); u++) x[u] = lds[lidx(g, base + u * dmin)];
+      const int sub_off = PASS == 2 ? (wg * G + g) : 0;
+      if (!INV) {
+#pragma unroll
+        for (int ss = 0; ss < R; ss++) {
+          const int s = s0 + ss;
+          const int sg = (PASS == 2 ? L1 : 0) + s;
+          const int half = 1 << (R - 1 - ss);
+#pragma unroll
+          for (int u = 0; u < (1 << R); u++) {
+            if (u & half) continue;
+            const int iloc = (hi << ss) + (u >> (R - ss));
+            const int ti = (1 << sg) + (sub_off << s) + iloc;
+            const double y = mul_f64_lazy(x[u + half], tw[ti], twq[ti], q);
+            double a = x[u];
+            a = a >= q2 ? a - q2 : a;
+            x[u] = a + y;
+            x[u + half] = a - y + q2;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int ss = R - 1; ss >= 0; ss--) {
+          const int s = s0 + ss;
+          const int sg = (PASS == 2 ? L1 : 0) + s;
+          const int half = 1 << (R - 1 - ss);
+#pragma unroll
+          for (int u = 0; u < (1 << R); u++) {
+            if (u & half) continue;
+            const int iloc = (hi << ss) + (u >> (R - ss));
+            const int ti = (1 << sg) + (sub_off << s) + iloc;
+            const double a = x[u], b = x[u + half];
+            const double sm = a + b;
+            x[u] = sm >= q2 ? sm - q2 : sm;
+            x[u + half] = mul_f64_lazy(a - b + q2, tw[ti], twq[ti], q);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < (1 << R); u++) lds[lidx(g, base + u * dmin)] = x[u];
+    }
+  }
+
+  HE_HD static uint64_t finish_f64(double v, double ninv, double ninvq, double q) {
+    if (!INV && PASS == 2) {
+      v = v >= 2.0 * q ? v - 2.0 * q : v;
+      v = v >= q ? v - q : v;
+    } else if (INV && PASS == 1) {
+      v = mul_f64_lazy(v, ninv, ninvq, q);
+      v = v >= q ? v - q : v;
+    }
+    return (uint64_t)v;
+  }
+
   // Value written back to HBM after the pass: the forward transform leaves
   // pass 1 lazily reduced ([0, 4q)) and canonicalises after pass 2; the
   // inverse multiplies by N^{-1} and canonicalises after pass 1.

@@ -78,7 +78,7 @@ class he_batch_desc(ctypes.Structure):
                 ("pt_index", ctypes.POINTER(ctypes.c_int32)), ("out", ctypes.c_void_p)]
 
 
-BATCH_GRAPH, BATCH_TILE128 = 1, 2
+BATCH_GRAPH, BATCH_MAC4, BATCH_TUNE = 1, 2, 4
 
 _lib = None
 
@@ -126,6 +126,7 @@ def lib():
             "he_batch_run_plain": [vp, vp],
             "he_batch_info": [vp, P(i32), P(i32), P(i32), P(ctypes.c_double)],
             "he_batch_destroy": [vp],
+            "he_batch_tuning": [vp, P(i32), P(ctypes.c_float), P(ctypes.c_float)],
             "he_lane_reserve": [vp, vp, c_int],
             "he_lane_release": [vp, vp],
             "he_profile_begin": [vp],
@@ -483,6 +484,11 @@ class Batch:
         sc = ctypes.c_double()
         _check(lib().he_batch_info(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c), ctypes.byref(sc)))
         return {"rotations": a.value, "outputs": b.value, "keys": c.value, "out_scale": sc.value}
+
+    def tuning(self):
+        og, a, b = ctypes.c_int32(), ctypes.c_float(), ctypes.c_float()
+        _check(lib().he_batch_tuning(self.h, ctypes.byref(og), ctypes.byref(a), ctypes.byref(b)))
+        return {"mac_outputs_per_group": og.value, "ms_group4": round(a.value, 3), "ms_group8": round(b.value, 3)}
 
     def close(self):
         if self.h:

@@ -69,7 +69,7 @@ def oracle_outputs(name, sets, outs, cts, pool, pti):
     return res
 
 
-@pytest.mark.parametrize("name,flags", [("config1", 0), ("config1", 1), ("config2", 1)])
+@pytest.mark.parametrize("name,flags", [("config1", 0), ("config1", 1), ("config1", 2), ("config2", 5)])
 def test_batch_matches_plain_and_oracle(name, flags):
     B = 3 if name == "config2" else 5
     octx, sets, outs, cts, pool, pti = make_batch(name, B, 6, 2, 4, 1, 3, seed=31)

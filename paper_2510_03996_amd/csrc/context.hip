@@ -212,6 +212,7 @@ static int ctx_init(Ctx* c, const he_params* p) {
   c->psi.resize(M);
   c->hmod.resize(M);
   std::vector<uint64_t> tw(M * N), twp(M * N), itw(M * N), itwp(M * N), pw(N), ipw(N);
+  std::vector<double> dtw(M * N), dtwq(M * N), ditw(M * N), ditwq(M * N);
   for (int m = 0; m < M; m++) {
     uint64_t q = c->mod[m];
     uint64_t psi = min_psi(q, N), ipsi = hinv(psi, q);
@@ -224,6 +225,10 @@ static int ctx_init(Ctx* c, const he_params* p) {
       twp[m * N + k] = shoup_of(pw[b], q);
       itw[m * N + k] = ipw[b];
       itwp[m * N + k] = shoup_of(ipw[b], q);
+      dtw[m * N + k] = (double)pw[b];
+      dtwq[m * N + k] = (double)pw[b] / (double)q;
+      ditw[m * N + k] = (double)ipw[b];
+      ditwq[m * N + k] = (double)ipw[b] / (double)q;
     }
     ModInfo& mi = c->hmod[m];
     mi.q = q;
@@ -238,6 +243,8 @@ static int ctx_init(Ctx* c, const he_params* p) {
     mi.ninv = hinv(N % q, q);
     mi.ninv_p = shoup_of(mi.ninv, q);
     mi.pad = 0;
+    mi.dninv = (double)mi.ninv;
+    mi.dninvq = (double)mi.ninv / (double)q;
   }
   int rc;
   if ((rc = dev_alloc(c, &c->d_mod, M))) return rc;
@@ -245,11 +252,19 @@ static int ctx_init(Ctx* c, const he_params* p) {
   if ((rc = dev_alloc(c, &c->d_twp, M * N))) return rc;
   if ((rc = dev_alloc(c, &c->d_itw, M * N))) return rc;
   if ((rc = dev_alloc(c, &c->d_itwp, M * N))) return rc;
+  if ((rc = dev_alloc(c, &c->d_dtw, M * N))) return rc;
+  if ((rc = dev_alloc(c, &c->d_dtwq, M * N))) return rc;
+  if ((rc = dev_alloc(c, &c->d_ditw, M * N))) return rc;
+  if ((rc = dev_alloc(c, &c->d_ditwq, M * N))) return rc;
   HE_HIP(hipMemcpy(c->d_mod, c->hmod.data(), M * sizeof(ModInfo), hipMemcpyHostToDevice));
   HE_HIP(hipMemcpy(c->d_tw, tw.data(), M * N * 8, hipMemcpyHostToDevice));
   HE_HIP(hipMemcpy(c->d_twp, twp.data(), M * N * 8, hipMemcpyHostToDevice));
   HE_HIP(hipMemcpy(c->d_itw, itw.data(), M * N * 8, hipMemcpyHostToDevice));
   HE_HIP(hipMemcpy(c->d_itwp, itwp.data(), M * N * 8, hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(c->d_dtw, dtw.data(), M * N * 8, hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(c->d_dtwq, dtwq.data(), M * N * 8, hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(c->d_ditw, ditw.data(), M * N * 8, hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(c->d_ditwq, ditwq.data(), M * N * 8, hipMemcpyHostToDevice));
   // ---- basis conversion tables for every level
   c->modup.assign(c->L + 1, {});
   c->moddown.assign(c->L + 1, {});

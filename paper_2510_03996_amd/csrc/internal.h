@@ -49,6 +49,8 @@ struct Ctx {
   std::vector<ModInfo> hmod;
   ModInfo* d_mod = nullptr;
   uint64_t *d_tw = nullptr, *d_twp = nullptr, *d_itw = nullptr, *d_itwp = nullptr;  // [L+K][N]
+  // FP64 twiddles w and w/q (used for primes below 2^50)
+  double *d_dtw = nullptr, *d_dtwq = nullptr, *d_ditw = nullptr, *d_ditwq = nullptr;
   // modup[level][digit]; moddown[level]
   std::vector<BConvSet> modup, moddown;
   std::vector<LimbMap> modup_ntt;  // per level: every converted limb of every digit (ext-relative)

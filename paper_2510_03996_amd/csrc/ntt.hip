@@ -10,6 +10,8 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(const uint64_t* src, size
                                                        size_t batch_stride, LimbMap map,
                                                        const uint64_t* __restrict__ tw_all,
                                                        const uint64_t* __restrict__ twp_all,
+                                                       const double* __restrict__ dtw_all,
+                                                       const double* __restrict__ dtwq_all,
                                                        const ModInfo* __restrict__ mods) {
   using P = NttPass<LOGN, PASS, INV>;
   __shared__ uint64_t lds[P::LDS_WORDS];
@@ -23,6 +25,39 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(const uint64_t* src, size
   const uint64_t* twp = twp_all + (size_t)m * P::N;
   const ModInfo mi = mods[m];
   const uint64_t q = mi.q;
+  if (mi.k <= 50) {
+    // FP64 path (exact doubles, full-rate FMA products); the branch is uniform per workgroup
+    double* dl = reinterpret_cast<double*>(lds);
+    const double* dtw = dtw_all + (size_t)m * P::N;
+    const double* dtwq = dtwq_all + (size_t)m * P::N;
+    const double dq = (double)q;
+    for (int e = tid; e < P::TILE; e += P::THREADS) {
+      int g, k;
+      P::tile_elem(e, g, k);
+      dl[P::lidx(g, k)] = (double)ain[P::gidx(wg, g, k)];
+    }
+    __syncthreads();
+    if (!INV) {
+      P::template round_f64<P::R1>(dl, tid, wg, 0, dtw, dtwq, dq);
+      if (P::R2 > 0) {
+        __syncthreads();
+        P::template round_f64<(P::R2 > 0 ? P::R2 : 1)>(dl, tid, wg, P::R1, dtw, dtwq, dq);
+      }
+    } else {
+      if (P::R2 > 0) {
+        P::template round_f64<(P::R2 > 0 ? P::R2 : 1)>(dl, tid, wg, P::R1, dtw, dtwq, dq);
+        __syncthreads();
+      }
+      P::template round_f64<P::R1>(dl, tid, wg, 0, dtw, dtwq, dq);
+    }
+    __syncthreads();
+    for (int e = tid; e < P::TILE; e += P::THREADS) {
+      int g, k;
+      P::tile_elem(e, g, k);
+      a[P::gidx(wg, g, k)] = P::finish_f64(dl[P::lidx(g, k)], mi.dninv, mi.dninvq, dq);
+    }
+    return;
+  }
   for (int e = tid; e < P::TILE; e += P::THREADS) {
     int g, k;
     P::tile_elem(e, g, k);
@@ -62,18 +97,21 @@ static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* da
   if (!inverse) {
     {
       ProfScope ps(c, "ntt_fwd_pass1", s, bytes, mm1);
-      ntt_pass_kernel<LOGN, 1, false><<<g1, 256, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
+      ntt_pass_kernel<LOGN, 1, false><<<g1, 256, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_tw, c->d_twp, c->d_dtw,
+                                                             c->d_dtwq, c->d_mod);
     }
     ProfScope ps(c, "ntt_fwd_pass2", s, bytes, mm2);
-    ntt_pass_kernel<LOGN, 2, false><<<g2, 256, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_tw, c->d_twp, c->d_mod);
+    ntt_pass_kernel<LOGN, 2, false><<<g2, 256, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_tw, c->d_twp,
+                                                             c->d_dtw, c->d_dtwq, c->d_mod);
   } else {
     {
       ProfScope ps(c, "ntt_inv_pass2", s, bytes, mm2);
       ntt_pass_kernel<LOGN, 2, true><<<g2, 256, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_itw, c->d_itwp,
-                                                         c->d_mod);
+                                                         c->d_ditw, c->d_ditwq, c->d_mod);
     }
     ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs);
-    ntt_pass_kernel<LOGN, 1, true><<<g1, 256, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_mod);
+    ntt_pass_kernel<LOGN, 1, true><<<g1, 256, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_itw, c->d_itwp,
+                                                            c->d_ditw, c->d_ditwq, c->d_mod);
   }
   HE_HIP(hipGetLastError());
   return HE_OK;

@@ -156,6 +156,7 @@ def headline(args):
     roof.update({"traffic": None, "kernel": dom_name, "avg_launch_us": round(d["ms"] / d["launches"] * 1e3, 2),
                  "hbm_GBs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4), "gmodmul_s": round(gmm, 1)})
     ks_bytes = 2 * L * N * 8 + 2 * dnum * (L + K) * N * 8 + 2 * L * N * 8
+    roof["ntt_autotune"] = ctx.ntt_tuning()
     ctx.close()
     return rot_s, el, roof, kern, ks_bytes, (L, K, dnum)
 

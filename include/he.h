@@ -100,6 +100,12 @@ int he_ctx_destroy(he_ctx* ctx);
 /* Copy the L + K moduli (q_0..q_{L-1}, p_0..p_{K-1}) to host `out`. */
 int he_ctx_moduli(const he_ctx* ctx, uint64_t* out, int cap);
 int he_ctx_info(const he_ctx* ctx, int32_t* log_n, int32_t* n_q, int32_t* n_p, int32_t* alpha);
+/* NTT autotuning done at context creation: forward+inverse transforms of
+ * 8, 16, 32 and 64 limbs are timed with 4 and with 16 residues per thread;
+ * launches over at most *small_max_limbs limbs use the 4-per-thread variant.
+ * us_small / us_large (4 entries each, may be NULL) receive the timings in
+ * microseconds (0 for sizes not probed). */
+int he_ctx_ntt_tuning(const he_ctx* ctx, int32_t* small_max_limbs, float* us_small, float* us_large);
 const char* he_last_error(void);
 
 /* Execution lanes.  Calls on different streams of one context may run

@@ -325,7 +325,7 @@ static int ctx_init(Ctx* c, const he_params* p) {
   c->ws_words = ws_words(c);
   if ((rc = dev_alloc(c, &c->ws, c->ws_words))) return rc;
   c->key_words = D * 2 * (L + K) * N;
-  return HE_OK;
+  return ntt_autotune(c);
 }
 
 Lane* lane_for(Ctx* c, hipStream_t s) {
@@ -453,6 +453,16 @@ int he_ctx_moduli(const he_ctx* h, uint64_t* out, int cap) {
   if (cap < M) return set_error(HE_EINVAL, "output too small");
   for (int i = 0; i < M; i++) out[i] = h->c.mod[i];
   return M;
+}
+
+int he_ctx_ntt_tuning(const he_ctx* h, int32_t* small_max_limbs, float* us_small, float* us_large) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  if (small_max_limbs) *small_max_limbs = h->c.ntt_small_max;
+  for (int i = 0; i < 4; i++) {
+    if (us_small) us_small[i] = h->c.ntt_tune_us[0][i];
+    if (us_large) us_large[i] = h->c.ntt_tune_us[1][i];
+  }
+  return HE_OK;
 }
 
 int he_ctx_info(const he_ctx* h, int32_t* log_n, int32_t* n_q, int32_t* n_p, int32_t* alpha) {

@@ -69,6 +69,10 @@ struct Ctx {
   std::map<hipStream_t, Lane*> lanes;
   std::mutex lanes_mu;
   bool prof_on = false;
+  // NTT launches over at most this many limbs use the 4-elements-per-thread
+  // variant (set by the autotuner at context creation)
+  int ntt_small_max = 32;
+  float ntt_tune_us[2][4] = {};  // [variant][probe size] measured pass-pair times
   std::vector<ProfRec> prof;
 
   int dnum(int level) const { return (level + alpha - 1) / alpha; }
@@ -117,6 +121,7 @@ int ntt_launch_strided(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* dat
 int ntt_launch_from(Ctx* c, const uint64_t* src, uint64_t* data, size_t batch_stride, int nbatch, const LimbMap& map,
                     bool inverse, hipStream_t s);
 LimbMap range_map(int first_pos, int n, int first_mod);
+int ntt_autotune(Ctx* c);
 // positions 0..l-1 -> q_0..q_{l-1}, positions l..l+K-1 -> p_0..p_{K-1}
 LimbMap ext_map(const Ctx* c, int level);
 

@@ -1,19 +1,45 @@
 // NTT / iNTT kernels and launchers (see ntt_core.h for the decomposition).
+#include <type_traits>
+
 #include "internal.h"
 #include "ntt_core.h"
 
 namespace he {
 
+// Rounds IDX..NR-1 of a pass, forward order (integer or FP64 arithmetic).
+template <class P, int IDX, class T, class TW, class Q>
+__device__ __forceinline__ void rounds_fwd(T* lds, int tid, int wg, const TW* tw, const TW* twp, Q q) {
+  if constexpr (IDX < P::NR) {
+    if constexpr (IDX > 0) __syncthreads();
+    if constexpr (sizeof(T) == 8 && std::is_same<T, double>::value)
+      P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
+    else
+      P::template round<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
+    rounds_fwd<P, IDX + 1>(lds, tid, wg, tw, twp, q);
+  }
+}
+// Rounds IDX..0 of a pass, inverse order.
+template <class P, int IDX, class T, class TW, class Q>
+__device__ __forceinline__ void rounds_inv(T* lds, int tid, int wg, const TW* tw, const TW* twp, Q q) {
+  if constexpr (IDX >= 0) {
+    if constexpr (std::is_same<T, double>::value)
+      P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
+    else
+      P::template round<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
+    if constexpr (IDX > 0) {
+      __syncthreads();
+      rounds_inv<P, IDX - 1>(lds, tid, wg, tw, twp, q);
+    }
+  }
+}
+
 // grid: x = tile within limb, y = limb index in `map`, z = batch
-template <int LOGN, int PASS, bool INV>
-__global__ __launch_bounds__(256) void ntt_pass_kernel(const uint64_t* src, size_t src_bs, uint64_t* data,
-                                                       size_t batch_stride, LimbMap map,
-                                                       const uint64_t* __restrict__ tw_all,
-                                                       const uint64_t* __restrict__ twp_all,
-                                                       const double* __restrict__ dtw_all,
-                                                       const double* __restrict__ dtwq_all,
-                                                       const ModInfo* __restrict__ mods) {
-  using P = NttPass<LOGN, PASS, INV>;
+template <int LOGN, int PASS, bool INV, int LOG_EPT>
+__global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT>::THREADS)) void ntt_pass_kernel(
+    const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, LimbMap map,
+    const uint64_t* __restrict__ tw_all, const uint64_t* __restrict__ twp_all, const double* __restrict__ dtw_all,
+    const double* __restrict__ dtwq_all, const ModInfo* __restrict__ mods) {
+  using P = NttPass<LOGN, PASS, INV, LOG_EPT>;
   __shared__ uint64_t lds[P::LDS_WORDS];
   const int wg = blockIdx.x;
   const int limb = blockIdx.y;
@@ -21,8 +47,6 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(const uint64_t* src, size
   const int m = map.mod[limb];
   const uint64_t* ain = src + blockIdx.z * src_bs + (size_t)map.pos[limb] * P::N;
   uint64_t* a = data + blockIdx.z * batch_stride + (size_t)map.pos[limb] * P::N;
-  const uint64_t* tw = tw_all + (size_t)m * P::N;
-  const uint64_t* twp = twp_all + (size_t)m * P::N;
   const ModInfo mi = mods[m];
   const uint64_t q = mi.q;
   if (mi.k <= 50) {
@@ -37,19 +61,8 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(const uint64_t* src, size
       dl[P::lidx(g, k)] = (double)ain[P::gidx(wg, g, k)];
     }
     __syncthreads();
-    if (!INV) {
-      P::template round_f64<P::R1>(dl, tid, wg, 0, dtw, dtwq, dq);
-      if (P::R2 > 0) {
-        __syncthreads();
-        P::template round_f64<(P::R2 > 0 ? P::R2 : 1)>(dl, tid, wg, P::R1, dtw, dtwq, dq);
-      }
-    } else {
-      if (P::R2 > 0) {
-        P::template round_f64<(P::R2 > 0 ? P::R2 : 1)>(dl, tid, wg, P::R1, dtw, dtwq, dq);
-        __syncthreads();
-      }
-      P::template round_f64<P::R1>(dl, tid, wg, 0, dtw, dtwq, dq);
-    }
+    if (!INV) rounds_fwd<P, 0>(dl, tid, wg, dtw, dtwq, dq);
+    else rounds_inv<P, P::NR - 1>(dl, tid, wg, dtw, dtwq, dq);
     __syncthreads();
     for (int e = tid; e < P::TILE; e += P::THREADS) {
       int g, k;
@@ -58,25 +71,16 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(const uint64_t* src, size
     }
     return;
   }
+  const uint64_t* tw = tw_all + (size_t)m * P::N;
+  const uint64_t* twp = twp_all + (size_t)m * P::N;
   for (int e = tid; e < P::TILE; e += P::THREADS) {
     int g, k;
     P::tile_elem(e, g, k);
     lds[P::lidx(g, k)] = ain[P::gidx(wg, g, k)];
   }
   __syncthreads();
-  if (!INV) {
-    P::template round<P::R1>(lds, tid, wg, 0, tw, twp, q);
-    if (P::R2 > 0) {
-      __syncthreads();
-      P::template round<(P::R2 > 0 ? P::R2 : 1)>(lds, tid, wg, P::R1, tw, twp, q);
-    }
-  } else {
-    if (P::R2 > 0) {
-      P::template round<(P::R2 > 0 ? P::R2 : 1)>(lds, tid, wg, P::R1, tw, twp, q);
-      __syncthreads();
-    }
-    P::template round<P::R1>(lds, tid, wg, 0, tw, twp, q);
-  }
+  if (!INV) rounds_fwd<P, 0>(lds, tid, wg, tw, twp, q);
+  else rounds_inv<P, P::NR - 1>(lds, tid, wg, tw, twp, q);
   __syncthreads();
   for (int e = tid; e < P::TILE; e += P::THREADS) {
     int g, k;
@@ -85,11 +89,12 @@ __global__ __launch_bounds__(256) void ntt_pass_kernel(const uint64_t* src, size
   }
 }
 
-template <int LOGN>
-static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
+template <int LOGN, int LOG_EPT>
+static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
                         int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
-  using P1 = NttPass<LOGN, 1, false>;
-  using P2 = NttPass<LOGN, 2, false>;
+  using P1 = NttPass<LOGN, 1, false, LOG_EPT>;
+  using P2 = NttPass<LOGN, 2, false, LOG_EPT>;
+  constexpr int T = P1::THREADS;
   dim3 g1(P1::WG_PER_LIMB, map.n, nbatch), g2(P2::WG_PER_LIMB, map.n, nbatch);
   const double limbs = (double)map.n * nbatch, N = (double)P1::N;
   const double bytes = 16.0 * N * limbs;  // one read + one write of every residue per pass
@@ -97,23 +102,98 @@ static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* da
   if (!inverse) {
     {
       ProfScope ps(c, "ntt_fwd_pass1", s, bytes, mm1);
-      ntt_pass_kernel<LOGN, 1, false><<<g1, 256, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_tw, c->d_twp, c->d_dtw,
-                                                             c->d_dtwq, c->d_mod);
+      ntt_pass_kernel<LOGN, 1, false, LOG_EPT><<<g1, T, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_tw,
+                                                                c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod);
     }
     ProfScope ps(c, "ntt_fwd_pass2", s, bytes, mm2);
-    ntt_pass_kernel<LOGN, 2, false><<<g2, 256, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_tw, c->d_twp,
-                                                             c->d_dtw, c->d_dtwq, c->d_mod);
+    ntt_pass_kernel<LOGN, 2, false, LOG_EPT><<<g2, T, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_tw,
+                                                              c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod);
   } else {
     {
       ProfScope ps(c, "ntt_inv_pass2", s, bytes, mm2);
-      ntt_pass_kernel<LOGN, 2, true><<<g2, 256, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_itw, c->d_itwp,
-                                                         c->d_ditw, c->d_ditwq, c->d_mod);
+      ntt_pass_kernel<LOGN, 2, true, LOG_EPT><<<g2, T, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_itw,
+                                                               c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod);
     }
     ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs);
-    ntt_pass_kernel<LOGN, 1, true><<<g1, 256, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_itw, c->d_itwp,
-                                                            c->d_ditw, c->d_ditwq, c->d_mod);
+    ntt_pass_kernel<LOGN, 1, true, LOG_EPT><<<g1, T, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_itw,
+                                                             c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod);
   }
   HE_HIP(hipGetLastError());
+  return HE_OK;
+}
+
+// Variant choice: 4 elements per thread (1024-thread workgroups, four times
+// the waves) for small limb batches, 16 per thread for large ones; the
+// crossover is measured at context creation (ntt_autotune).
+template <int LOGN>
+static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
+                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
+  const int limbs = map.n * nbatch;
+  if (limbs <= c->ntt_small_max) return ntt_launch_v<LOGN, 2>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+  return ntt_launch_v<LOGN, 4>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+}
+
+// Autotuner: time a forward + inverse transform of `limbs` limbs with each
+// variant (on the context's own moduli, in its workspace) for a few batch
+// sizes and keep the 4-elements-per-thread variant up to the largest size at
+// which it is faster.
+int ntt_autotune(Ctx* c) {
+  const int probes[4] = {8, 16, 32, 64};
+  const size_t N = c->n;
+  const int cap = (int)(c->ws_words / N);
+  hipStream_t s;
+  HE_HIP(hipStreamCreate(&s));
+  hipEvent_t e0, e1;
+  HE_HIP(hipEventCreate(&e0));
+  HE_HIP(hipEventCreate(&e1));
+  HE_HIP(hipMemsetAsync(c->ws, 0, c->ws_words * 8, s));
+  int small_max = 0;
+  bool small_wins_so_far = true;
+  for (int pi = 0; pi < 4; pi++) {
+    const int limbs = probes[pi];
+    if (limbs > cap || limbs > MAXJ) break;
+    LimbMap m{};
+    m.n = limbs;
+    for (int i = 0; i < limbs; i++) {
+      m.pos[i] = (uint16_t)i;
+      m.mod[i] = (uint8_t)(i % (c->L + c->K));
+    }
+    float t[2];
+    for (int v = 0; v < 2; v++) {
+      auto run = [&]() -> int {
+        int rc;
+        if (c->log_n == 16) {
+          if (v == 0) { if ((rc = ntt_launch_v<16, 2>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<16, 2>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
+          else { if ((rc = ntt_launch_v<16, 4>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<16, 4>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
+        } else if (c->log_n == 14) {
+          if (v == 0) { if ((rc = ntt_launch_v<14, 2>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<14, 2>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
+          else { if ((rc = ntt_launch_v<14, 4>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<14, 4>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
+        } else {
+          if (v == 0) { if ((rc = ntt_launch_v<12, 2>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<12, 2>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
+          else { if ((rc = ntt_launch_v<12, 4>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<12, 4>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
+        }
+        return HE_OK;
+      };
+      int rc;
+      if ((rc = run())) return rc;  // warm-up
+      HE_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 5; r++)
+        if ((rc = run())) return rc;
+      HE_HIP(hipEventRecord(e1, s));
+      HE_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      HE_HIP(hipEventElapsedTime(&ms, e0, e1));
+      t[v] = ms * 1e3f / 5;
+      c->ntt_tune_us[v][pi] = t[v];
+    }
+    if (small_wins_so_far && t[0] < t[1]) small_max = limbs;
+    else small_wins_so_far = false;
+  }
+  c->ntt_small_max = small_max;
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HE_HIP(hipStreamSynchronize(s));
+  hipStreamDestroy(s);
   return HE_OK;
 }
 

@@ -24,7 +24,7 @@
 
 namespace he {
 
-template <int LOGN, int PASS, bool INV>
+template <int LOGN, int PASS, bool INV, int LOG_EPT = 4>
 struct NttPass {
   static constexpr int N = 1 << LOGN;
   static constexpr int L1 = (LOGN + 1) / 2;
@@ -35,7 +35,8 @@ struct NttPass {
   static constexpr int TILE = N < 4096 ? N : 4096;  // elements per workgroup
   static constexpr int G = TILE / M;              // sub-transforms per workgroup
   static constexpr int WG_PER_LIMB = N / TILE;
-  static constexpr int THREADS = 256;
+  // each thread keeps 2^LOG_EPT elements (one radix-2^LOG_EPT group) per round
+  static constexpr int THREADS = TILE >> LOG_EPT;
   // pass-2 chunks get one pad word per 16 so that the stride-16 accesses of
   // the last round fall in different LDS banks
   static constexpr int CHUNK_WORDS = M + (M >> 4);
@@ -204,10 +205,11 @@ struct NttPass {
     return v;
   }
 
-  // LM <= 8 stages per pass: a first round of R1 stages, then R2 = LM - R1.
-  static constexpr int R1 = LM >= 4 ? 4 : LM;
-  static constexpr int R2 = LM - R1;
-  static_assert(R2 <= 4, "at most two LDS rounds per pass");
+  // rounds of LOG_EPT stages (the last one may be shorter)
+  static constexpr int NR = (LM + LOG_EPT - 1) / LOG_EPT;
+  static constexpr int rbits(int idx) { return idx < NR - 1 ? LOG_EPT : LM - LOG_EPT * (NR - 1); }
+  static constexpr int rstart(int idx) { return idx * LOG_EPT; }
+  static_assert(NR <= 4, "at most four LDS rounds per pass");
 };
 
 }  // namespace he

@@ -45,6 +45,23 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_GMODMUL = 256 * 4 * 16 / 2 * 2.4 / 10.0  # = 1966 Gmodmul/s
 
 
+def recorded_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter passes
+    (profiles/traffic_*.json), or None when none were taken or the NTT sources
+    changed since (the file records their sha256)."""
+    import glob
+    import hashlib
+
+    src = "".join(open(os.path.join(ROOT, "paper_2510_03996_amd", "csrc", f)).read()
+                  for f in ("ntt.hip", "ntt_core.h", "modarith.h"))
+    h = hashlib.sha256(src.encode()).hexdigest()
+    for fn in glob.glob(os.path.join(ROOT, "profiles", "traffic_*.json")):
+        d = json.load(open(fn))
+        if d.get("kernel") == kernel and d.get("source_sha256") == h:
+            return d["traffic_bytes_per_launch"]
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,7 +170,7 @@ def headline(args):
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(hbm_frac, 4)}
-    roof.update({"traffic": None, "kernel": dom_name, "avg_launch_us": round(d["ms"] / d["launches"] * 1e3, 2),
+    roof.update({"traffic": recorded_traffic(dom_name), "kernel": dom_name, "avg_launch_us": round(d["ms"] / d["launches"] * 1e3, 2),
                  "hbm_GBs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4), "gmodmul_s": round(gmm, 1)})
     ks_bytes = 2 * L * N * 8 + 2 * dnum * (L + K) * N * 8 + 2 * L * N * 8
     roof["ntt_autotune"] = ctx.ntt_tuning()

@@ -101,11 +101,11 @@ int he_ctx_destroy(he_ctx* ctx);
 int he_ctx_moduli(const he_ctx* ctx, uint64_t* out, int cap);
 int he_ctx_info(const he_ctx* ctx, int32_t* log_n, int32_t* n_q, int32_t* n_p, int32_t* alpha);
 /* NTT autotuning done at context creation: forward+inverse transforms of
- * 8, 16, 32 and 64 limbs are timed with 4 and with 16 residues per thread;
- * launches over at most *small_max_limbs limbs use the 4-per-thread variant.
- * us_small / us_large (4 entries each, may be NULL) receive the timings in
- * microseconds (0 for sizes not probed). */
-int he_ctx_ntt_tuning(const he_ctx* ctx, int32_t* small_max_limbs, float* us_small, float* us_large);
+ * 8, 16, 32 and 64 limbs are timed with 4, 8 and 16 residues per thread;
+ * each batch-size bucket (<= 8, <= 16, <= 32, larger) uses its fastest.
+ * log_ept[4] receives the chosen log2(residues per thread) per bucket and
+ * us[3][4] (may be NULL) the timings in microseconds [variant][bucket]. */
+int he_ctx_ntt_tuning(const he_ctx* ctx, int32_t* log_ept, float* us);
 const char* he_last_error(void);
 
 /* Execution lanes.  Calls on different streams of one context may run

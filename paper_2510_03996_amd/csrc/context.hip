@@ -455,12 +455,12 @@ int he_ctx_moduli(const he_ctx* h, uint64_t* out, int cap) {
   return M;
 }
 
-int he_ctx_ntt_tuning(const he_ctx* h, int32_t* small_max_limbs, float* us_small, float* us_large) {
+int he_ctx_ntt_tuning(const he_ctx* h, int32_t* log_ept, float* us) {
   if (!h) return set_error(HE_EINVAL, "null context");
-  if (small_max_limbs) *small_max_limbs = h->c.ntt_small_max;
   for (int i = 0; i < 4; i++) {
-    if (us_small) us_small[i] = h->c.ntt_tune_us[0][i];
-    if (us_large) us_large[i] = h->c.ntt_tune_us[1][i];
+    if (log_ept) log_ept[i] = h->c.ntt_log_ept[i];
+    for (int v = 0; v < 3; v++)
+      if (us) us[v * 4 + i] = h->c.ntt_tune_us[v][i];
   }
   return HE_OK;
 }

@@ -69,10 +69,10 @@ struct Ctx {
   std::map<hipStream_t, Lane*> lanes;
   std::mutex lanes_mu;
   bool prof_on = false;
-  // NTT launches over at most this many limbs use the 4-elements-per-thread
-  // variant (set by the autotuner at context creation)
-  int ntt_small_max = 32;
-  float ntt_tune_us[2][4] = {};  // [variant][probe size] measured pass-pair times
+  // NTT variant (log2 residues per thread) per batch-size bucket (<= 8, 16,
+  // 32, more limbs), chosen by the autotuner at context creation
+  int ntt_log_ept[4] = {2, 2, 2, 4};
+  float ntt_tune_us[3][4] = {};  // [variant 4/8/16 per thread][probe 8/16/32/64 limbs] forward+inverse us
   std::vector<ProfRec> prof;
 
   int dnum(int level) const { return (level + alpha - 1) / alpha; }

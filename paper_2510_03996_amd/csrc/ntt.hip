@@ -1,4 +1,5 @@
 // NTT / iNTT kernels and launchers (see ntt_core.h for the decomposition).
+#include <algorithm>
 #include <type_traits>
 
 #include "internal.h"
@@ -122,21 +123,41 @@ static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* da
   return HE_OK;
 }
 
-// Variant choice: 4 elements per thread (1024-thread workgroups, four times
-// the waves) for small limb batches, 16 per thread for large ones; the
-// crossover is measured at context creation (ntt_autotune).
+// Variant choice: 4, 8 or 16 residues per thread (1024-, 512- or 256-thread
+// workgroups; more waves for small limb batches, fewer LDS rounds for large
+// ones).  The best variant per batch-size bucket is measured at context
+// creation (ntt_autotune).
+static int ntt_bucket(int limbs) { return limbs <= 8 ? 0 : limbs <= 16 ? 1 : limbs <= 32 ? 2 : 3; }
+
 template <int LOGN>
 static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
                         int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
-  const int limbs = map.n * nbatch;
-  if (limbs <= c->ntt_small_max) return ntt_launch_v<LOGN, 2>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
-  return ntt_launch_v<LOGN, 4>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+  switch (c->ntt_log_ept[ntt_bucket(map.n * nbatch)]) {
+    case 2: return ntt_launch_v<LOGN, 2>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+    case 3: return ntt_launch_v<LOGN, 3>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+    default: return ntt_launch_v<LOGN, 4>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+  }
 }
 
-// Autotuner: time a forward + inverse transform of `limbs` limbs with each
-// variant (on the context's own moduli, in its workspace) for a few batch
-// sizes and keep the 4-elements-per-thread variant up to the largest size at
-// which it is faster.
+template <int LOGN>
+static int ntt_probe(Ctx* c, int log_ept, const LimbMap& m, hipStream_t s) {
+  int rc;
+  switch (log_ept) {
+    case 2:
+      if ((rc = ntt_launch_v<LOGN, 2>(c, c->ws, 0, c->ws, 0, 1, m, false, s))) return rc;
+      return ntt_launch_v<LOGN, 2>(c, c->ws, 0, c->ws, 0, 1, m, true, s);
+    case 3:
+      if ((rc = ntt_launch_v<LOGN, 3>(c, c->ws, 0, c->ws, 0, 1, m, false, s))) return rc;
+      return ntt_launch_v<LOGN, 3>(c, c->ws, 0, c->ws, 0, 1, m, true, s);
+    default:
+      if ((rc = ntt_launch_v<LOGN, 4>(c, c->ws, 0, c->ws, 0, 1, m, false, s))) return rc;
+      return ntt_launch_v<LOGN, 4>(c, c->ws, 0, c->ws, 0, 1, m, true, s);
+  }
+}
+
+// Autotuner: time a forward + inverse transform of 8, 16, 32 and 64 limbs
+// (the context's own moduli, in its workspace) with each variant and keep the
+// fastest per bucket; larger batches use the 64-limb choice.
 int ntt_autotune(Ctx* c) {
   const int probes[4] = {8, 16, 32, 64};
   const size_t N = c->n;
@@ -147,32 +168,23 @@ int ntt_autotune(Ctx* c) {
   HE_HIP(hipEventCreate(&e0));
   HE_HIP(hipEventCreate(&e1));
   HE_HIP(hipMemsetAsync(c->ws, 0, c->ws_words * 8, s));
-  int small_max = 0;
-  bool small_wins_so_far = true;
   for (int pi = 0; pi < 4; pi++) {
-    const int limbs = probes[pi];
-    if (limbs > cap || limbs > MAXJ) break;
+    const int limbs = std::min(probes[pi], std::min(cap, MAXJ));
     LimbMap m{};
     m.n = limbs;
     for (int i = 0; i < limbs; i++) {
       m.pos[i] = (uint16_t)i;
       m.mod[i] = (uint8_t)(i % (c->L + c->K));
     }
-    float t[2];
-    for (int v = 0; v < 2; v++) {
+    float best = 1e30f;
+    for (int v = 0; v < 3; v++) {
+      const int le = 2 + v;
       auto run = [&]() -> int {
-        int rc;
-        if (c->log_n == 16) {
-          if (v == 0) { if ((rc = ntt_launch_v<16, 2>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<16, 2>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
-          else { if ((rc = ntt_launch_v<16, 4>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<16, 4>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
-        } else if (c->log_n == 14) {
-          if (v == 0) { if ((rc = ntt_launch_v<14, 2>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<14, 2>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
-          else { if ((rc = ntt_launch_v<14, 4>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<14, 4>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
-        } else {
-          if (v == 0) { if ((rc = ntt_launch_v<12, 2>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<12, 2>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
-          else { if ((rc = ntt_launch_v<12, 4>(c, c->ws, 0, c->ws, 0, 1, m, false, s)) || (rc = ntt_launch_v<12, 4>(c, c->ws, 0, c->ws, 0, 1, m, true, s))) return rc; }
+        switch (c->log_n) {
+          case 16: return ntt_probe<16>(c, le, m, s);
+          case 14: return ntt_probe<14>(c, le, m, s);
+          default: return ntt_probe<12>(c, le, m, s);
         }
-        return HE_OK;
       };
       int rc;
       if ((rc = run())) return rc;  // warm-up
@@ -183,13 +195,14 @@ int ntt_autotune(Ctx* c) {
       HE_HIP(hipEventSynchronize(e1));
       float ms = 0;
       HE_HIP(hipEventElapsedTime(&ms, e0, e1));
-      t[v] = ms * 1e3f / 5;
-      c->ntt_tune_us[v][pi] = t[v];
+      const float us = ms * 1e3f / 5;
+      c->ntt_tune_us[v][pi] = us;
+      if (us < best) {
+        best = us;
+        c->ntt_log_ept[pi] = le;
+      }
     }
-    if (small_wins_so_far && t[0] < t[1]) small_max = limbs;
-    else small_wins_so_far = false;
   }
-  c->ntt_small_max = small_max;
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   HE_HIP(hipStreamSynchronize(s));

@@ -129,7 +129,7 @@ def lib():
             "he_batch_tuning": [vp, P(i32), P(ctypes.c_float), P(ctypes.c_float)],
             "he_lane_reserve": [vp, vp, c_int],
             "he_lane_release": [vp, vp],
-            "he_ctx_ntt_tuning": [vp, P(i32), P(ctypes.c_float), P(ctypes.c_float)],
+            "he_ctx_ntt_tuning": [vp, P(i32), P(ctypes.c_float)],
             "he_profile_begin": [vp],
             "he_profile_end": [vp, ctypes.c_char_p, sz],
         }
@@ -423,11 +423,11 @@ class Context:
         return out
 
     def ntt_tuning(self):
-        m = ctypes.c_int32()
-        a, b = (ctypes.c_float * 4)(), (ctypes.c_float * 4)()
-        _check(lib().he_ctx_ntt_tuning(self.h, ctypes.byref(m), a, b))
-        return {"small_variant_max_limbs": m.value, "probe_limbs": [8, 16, 32, 64],
-                "us_4_per_thread": [round(x, 2) for x in a], "us_16_per_thread": [round(x, 2) for x in b]}
+        le = (ctypes.c_int32 * 4)()
+        us = (ctypes.c_float * 12)()
+        _check(lib().he_ctx_ntt_tuning(self.h, le, us))
+        return {"bucket_max_limbs": [8, 16, 32, "more"], "residues_per_thread": [1 << x for x in le],
+                "us_fwd_inv": {str(1 << (2 + v)): [round(us[v * 4 + i], 2) for i in range(4)] for v in range(3)}}
 
     # ---- lanes
     def lane_reserve(self, stream, n_ct_buffers):

@@ -236,7 +236,7 @@ static int run_batched(Batch* b, hipStream_t s) {
     const BConvSet& set = c->modup[l];
     ProfScope ps(c, "bconv_modup", s, 8.0 * N * b->B * (l + (double)set.count * set.max_out),
                  (double)N * b->B * l * (1 + set.max_out));
-    dim3 grid(N / 256, (set.max_out + BCONV_OUT_PER - 1) / BCONV_OUT_PER, b->B * set.count);
+    dim3 grid(N / 128, bconv_tiles_y(set), b->B * set.count);
     k_bconv<<<grid, 256, 0, s>>>(b->coeff, ln, b->ext, E * N, set.d, set.count, c->d_mod, c->log_n);
     HE_HIP(hipGetLastError());
   }
@@ -256,7 +256,7 @@ static int run_batched(Batch* b, hipStream_t s) {
     {
       const BConvSet& set = c->moddown[l];
       ProfScope ps(c, "bconv_moddown", s, 8.0 * N * z * (K + l), (double)N * z * K * (1 + l));
-      dim3 grid(N / 256, (set.max_out + BCONV_OUT_PER - 1) / BCONV_OUT_PER, z);
+      dim3 grid(N / 128, bconv_tiles_y(set), z);
       k_bconv<<<grid, 256, 0, s>>>(b->u, E * N, b->y, ln, set.d, 1, c->d_mod, c->log_n);
       HE_HIP(hipGetLastError());
     }

@@ -128,30 +128,67 @@ static int build_bconv(Ctx* c, BConvDesc& t, const std::vector<int>& in_pos, con
   if (t.nin > MAX_BCONV_IN || t.nout > MAX_BCONV_OUT) return set_error(HE_EINVAL, "basis conversion too wide");
   for (int i = 0; i < t.nin; i++) { t.in_pos[i] = in_pos[i]; t.in_mod[i] = in_mod[i]; }
   for (int p = 0; p < t.nout; p++) { t.out_pos[p] = out_pos[p]; t.out_mod[p] = out_mod[p]; }
-  std::vector<uint64_t> h(2 * t.nin + (size_t)t.nin * t.nout);
+  t.nsteps = (t.nin + 1) / 2;
+  t.ngroups = (t.nout + 3) / 4;
+  std::vector<uint64_t> pre(2 * t.nin);
+  // cst[i][p] = (Qin / q_i) 2^64 mod p (Montgomery form)
+  std::vector<uint64_t> cst((size_t)t.nin * t.nout);
   for (int i = 0; i < t.nin; i++) {
     uint64_t qi = c->mod[in_mod[i]];
-    // (Qin / q_i) mod q_i
     uint64_t prod = 1 % qi;
     for (int i2 = 0; i2 < t.nin; i2++)
       if (i2 != i) prod = hmul(prod, c->mod[in_mod[i2]] % qi, qi);
-    uint64_t w = hinv(prod, qi);
-    h[i] = w;
-    h[t.nin + i] = shoup_of(w, qi);
+    pre[i] = hinv(prod, qi);
+    pre[t.nin + i] = shoup_of(pre[i], qi);
     for (int p = 0; p < t.nout; p++) {
       uint64_t po = c->mod[out_mod[p]];
       uint64_t v = 1 % po;
       for (int i2 = 0; i2 < t.nin; i2++)
         if (i2 != i) v = hmul(v, c->mod[in_mod[i2]] % po, po);
-      uint64_t r64 = (uint64_t)(((u128)1 << 64) % po);
-      h[2 * t.nin + (size_t)i * t.nout + p] = hmul(v, r64, po);
+      cst[(size_t)i * t.nout + p] = hmul(v, (uint64_t)(((u128)1 << 64) % po), po);
     }
   }
-  uint64_t* d = nullptr;
-  int rc = dev_alloc(c, &d, h.size());
-  if (rc) return rc;
-  HE_HIP(hipMemcpy(d, h.data(), h.size() * 8, hipMemcpyHostToDevice));
-  t.tab = d;
+  // A fragments: lane l of K-step s in row tile g holds, for row r = l % 32
+  // (output p = 4 g + m, digit weight b) and input limb i = 2 s + l / 32,
+  // byte a = digit b of C_{i,a,p} = cst[i][p] 256^a mod p
+  std::vector<uint64_t> frag((size_t)t.ngroups * t.nsteps * 64, 0);
+  for (int g = 0; g < t.ngroups; g++)
+    for (int st = 0; st < t.nsteps; st++)
+      for (int l = 0; l < 64; l++) {
+        int m, b;
+        bconv_row(l % 32, m, b);
+        const int p = 4 * g + m, i = 2 * st + l / 32;
+        if (p >= t.nout || i >= t.nin) continue;
+        const uint64_t po = c->mod[out_mod[p]];
+        uint64_t word = 0, cpow = cst[(size_t)i * t.nout + p];
+        for (int a8 = 0; a8 < 8; a8++) {
+          word |= (uint64_t)(uint8_t)(int8_t)sdigit(cpow, b) << (8 * a8);
+          cpow = hmul(cpow, 256 % po, po);
+        }
+        frag[((size_t)g * t.nsteps + st) * 64 + l] = word;
+      }
+  std::vector<uint64_t> ep((size_t)t.nout * 4);
+  for (int p = 0; p < t.nout; p++) {
+    const uint64_t po = c->mod[out_mod[p]];
+    int kshift = 0;
+    while (((u128)po << kshift) < ((u128)1 << 77)) kshift++;
+    const u128 M = (u128)po << kshift;
+    ep[4 * p] = (uint64_t)M;
+    ep[4 * p + 1] = (uint64_t)(M >> 64);
+    ep[4 * p + 2] = po;
+    ep[4 * p + 3] = c->hmod[out_mod[p]].qinv;
+  }
+  uint64_t *dpre = nullptr, *dfrag = nullptr, *dep = nullptr;
+  int rc;
+  if ((rc = dev_alloc(c, &dpre, pre.size())) || (rc = dev_alloc(c, &dfrag, frag.size())) ||
+      (rc = dev_alloc(c, &dep, ep.size())))
+    return rc;
+  HE_HIP(hipMemcpy(dpre, pre.data(), pre.size() * 8, hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(dfrag, frag.data(), frag.size() * 8, hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(dep, ep.data(), ep.size() * 8, hipMemcpyHostToDevice));
+  t.tab = dpre;
+  t.frag = dfrag;
+  t.ep = dep;
   return HE_OK;
 }
 

@@ -5,7 +5,7 @@
 
 namespace he {
 
-constexpr int MAX_BCONV_IN = 8;    // Montgomery accumulator bound: nin * 2^61 * p < p 2^64
+constexpr int MAX_BCONV_IN = 8;    // input limbs of one conversion (alpha and K)
 constexpr int MAX_BCONV_OUT = 64;
 constexpr int MAXJ = 128;          // limb jobs in one batched launch
 constexpr int MAX_DIGITS = 8;      // key-switching digits (dnum)
@@ -17,16 +17,61 @@ struct LimbMap {
   uint8_t mod[MAXJ];   // modulus index (0..L-1 q_i, L.. p_k)
 };
 
-// Device-resident description of one fast basis conversion:
-// input limbs (position, modulus) -> output limbs, constants at `tab`:
-// [nin] w, [nin] w' (Shoup pair of (Qin/q_i)^{-1} mod q_i), then
-// [nin][nout] (Qin/q_i mod p) * 2^64 mod p (Montgomery form).
+// Device-resident description of one fast basis conversion (floor type):
+//   t_i = [x_i (Qin/q_i)^{-1}]_{q_i},  y_p = sum_i t_i [Qin/q_i]_p  mod p.
+// The sum is an integer matrix product evaluated on the int8 matrix cores:
+// every t_i is split into 8 signed base-256 digits d_{i,a}, and the constant
+// C_{i,a,p} = [Qin/q_i]_p 2^64 256^a mod p (Montgomery form) into 8 signed
+// digits e_{i,a,p,b}, so
+//   2^64 sum_i t_i [Qin/q_i]_p == sum_b 256^b sum_{i,a} d_{i,a} e_{i,a,p,b}  (mod p)
+// with an inner sum of at most 64 products of magnitude <= 2^14 (exact in
+// int32); one Montgomery reduction of the digit-weighted sum gives y_p.
+// One 32x32x16 MFMA covers two input limbs (K = 2 x 8 digits) for 32
+// coefficients (columns) and four outputs x 8 digits b (rows).
+//   tab:  [nin] w, [nin] w'   Shoup pair of (Qin/q_i)^{-1} mod q_i
+//   frag: [ngroups][nsteps][64] A-operand fragments (8 signed digit bytes per
+//         lane, laid out as the instruction reads them)
+//   ep:   [nout][4] per output modulus: the 128-bit offset M = p 2^k in
+//         [2^77, 2^78) (low word, high word), p, p^{-1} mod 2^64
 struct BConvDesc {
   int32_t nin, nout;
+  int32_t nsteps, ngroups;  // ceil(nin / 2) K-steps, ceil(nout / 4) row tiles
   int32_t in_pos[MAX_BCONV_IN], in_mod[MAX_BCONV_IN];
   int32_t out_pos[MAX_BCONV_OUT], out_mod[MAX_BCONV_OUT];
   const uint64_t* tab;
+  const uint64_t* frag;
+  const uint64_t* ep;
 };
+
+// Balanced base-256 digits of v < 2^61, packed as 8 int8 bytes: byte a is
+// d_a in [-128, 127] with v = sum_a d_a 256^a (the top digit is <= 33).
+HE_HD uint64_t sdigits(uint64_t v) {
+  constexpr uint64_t H = 0x0080808080808080ull;
+  return (v + H) ^ H;
+}
+HE_HD int sdigit(uint64_t v, int a) { return (int)(int8_t)(uint8_t)(sdigits(v) >> (8 * a)); }
+
+// Row r of a 32-row accumulator tile holds output m (0..3) of the tile and
+// digit weight b (0..7).  The 32x32 int32 accumulator gives lane l the rows
+// (reg & 3) + 4 (l / 32) + 8 (reg / 4), so with this assignment lane l owns
+// all eight b of outputs 2 (l / 32) and 2 (l / 32) + 1 in registers
+// 0..7 and 8..15.
+HE_HD void bconv_row(int row, int& m, int& b) {
+  const int h = (row >> 2) & 1;
+  const int reg = (row & 3) + 4 * (row >> 3);
+  m = 2 * h + (reg >> 3);
+  b = reg & 7;
+}
+
+// REDC(M + sum_b 256^b acc[b]) for |acc[b]| <= 2^20: the weighted sum has
+// magnitude < 2^76.01, so with M = p 2^k in [2^77, 2^78) the argument lies in
+// (0, 2^78.3) < p 2^64 and the result is canonical.
+HE_HD uint64_t bconv_combine(const int32_t* acc, const uint64_t* ep) {
+  const int64_t lo = (int64_t)acc[0] + (int64_t)acc[1] * 256 + (int64_t)acc[2] * 65536 + (int64_t)acc[3] * 16777216;
+  const int64_t hi = (int64_t)acc[4] + (int64_t)acc[5] * 256 + (int64_t)acc[6] * 65536 + (int64_t)acc[7] * 16777216;
+  const __int128 t = (__int128)hi * ((__int128)1 << 32) + lo + (__int128)(((unsigned __int128)ep[1] << 64) | ep[0]);
+  return mont_redc(U128{(uint64_t)t, (uint64_t)((unsigned __int128)t >> 64)}, ep[2], ep[3]);
+}
 
 HE_HD uint32_t bitrev_n(uint32_t x, int logn) {
 #if defined(__HIP_DEVICE_COMPILE__)
@@ -44,28 +89,6 @@ HE_HD uint32_t automorph_src(uint32_t j, uint32_t g, int logn) {
   const uint32_t mask2n = (2u << logn) - 1;
   uint32_t e = (uint32_t)(((uint64_t)g * (2u * bitrev_n(j, logn) + 1u)) & mask2n);
   return bitrev_n((e - 1u) >> 1, logn);
-}
-
-// Fast basis conversion of coefficient k (floor type):
-//   t_i = [x_i * (Qin/q_i)^{-1}]_{q_i},  y_p = sum_i t_i [Qin/q_i]_p mod p,
-// computed for the outputs p in [p0, p1).
-HE_HD void bconv_elem(const uint64_t* in, uint64_t* out, size_t n, size_t k, const BConvDesc& d, int p0, int p1,
-                      const ModInfo* mods) {
-  const int nin = d.nin, nout = d.nout;
-  const uint64_t* tab = d.tab;
-  uint64_t t[MAX_BCONV_IN];
-  for (int i = 0; i < nin; i++) {
-    const uint64_t q = mods[d.in_mod[i]].q;
-    t[i] = mul_shoup(in[(size_t)d.in_pos[i] * n + k], tab[i], tab[nin + i], q);
-  }
-  const uint64_t* c = tab + 2 * nin;
-  if (p1 > nout) p1 = nout;
-  for (int p = p0; p < p1; p++) {
-    const ModInfo& mp = mods[d.out_mod[p]];
-    U128 acc{0, 0};
-    for (int i = 0; i < nin; i++) add_wide(acc, mul_wide(t[i], c[i * nout + p]));
-    out[(size_t)d.out_pos[p] * n + k] = mont_redc(acc, mp.q, mp.qinv);
-  }
 }
 
 // Key inner product for extended limb `pos` (modulus mi), coefficient k:

@@ -158,7 +158,8 @@ uint64_t* lane_ct_get(Ctx* c, Lane* ln);  // null on allocation failure
 int check_ct(const Ctx* c, const he_ct* x, const char* what);
 int check_out(const Ctx* c, const he_ct* x, int need_level);
 
-constexpr int BCONV_OUT_PER = 8;  // basis-conversion outputs per thread
+constexpr int BCONV_TILES_Y = 8;  // 4-output row tiles per basis-conversion workgroup
+inline int bconv_tiles_y(const BConvSet& s) { return ((s.max_out + 3) / 4 + BCONV_TILES_Y - 1) / BCONV_TILES_Y; }
 __global__ void k_bconv(const uint64_t* __restrict__ in, size_t in_bs, uint64_t* __restrict__ out, size_t out_bs,
                         const BConvDesc* __restrict__ descs, int zdiv, const ModInfo* __restrict__ mods, int logn);
 __global__ void k_moddown_combine(const uint64_t* __restrict__ u, size_t u_ps, const uint64_t* __restrict__ y,

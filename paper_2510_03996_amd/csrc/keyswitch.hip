@@ -10,19 +10,76 @@
 namespace he {
 
 // ---------------------------------------------------------------- kernels
-// grid: x = coefficient tile, y = group of BCONV_OUT_PER outputs, z = batch:
-// descriptor descs[z % zdiv], input in + (z / zdiv) in_bs, output out + z out_bs
+// Basis conversion on the int8 matrix cores (see BConvDesc).  One wave owns
+// 32 coefficients: lane l loads t_i for i = 2 s + l / 32 (the B operand of
+// K-step s is exactly its 8 digit bytes), then every 4-output row tile takes
+// nsteps MFMAs and an epilogue that turns 8 int32 digit sums per output
+// into a residue.  grid: x = 128-coefficient block (4 waves), y = chunk of
+// BCONV_TILES_Y row tiles, z = batch: descriptor descs[z % zdiv], input
+// in + (z / zdiv) in_bs, output out + z out_bs.
+typedef int32_t v16i __attribute__((ext_vector_type(16)));
+
 __global__ __launch_bounds__(256) void k_bconv(const uint64_t* __restrict__ in, size_t in_bs,
                                                uint64_t* __restrict__ out, size_t out_bs,
                                                const BConvDesc* __restrict__ descs, int zdiv,
                                                const ModInfo* __restrict__ mods, int logn) {
+  // constants of this block's row tiles, staged once per workgroup
+  __shared__ uint64_t s_frag[BCONV_TILES_Y * (MAX_BCONV_IN / 2) * 64];
+  __shared__ uint64_t s_ep[BCONV_TILES_Y * 4 * 4];
+  __shared__ uint32_t s_pos[BCONV_TILES_Y * 4];
   const size_t n = (size_t)1 << logn;
-  const size_t k = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int half = lane >> 5;
+  const size_t k = ((size_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + (lane & 31);
   const int z = blockIdx.z;
   const BConvDesc& d = descs[z % zdiv];
-  const int p0 = blockIdx.y * BCONV_OUT_PER;
-  if (p0 >= d.nout) return;
-  bconv_elem(in + (z / zdiv) * in_bs, out + z * out_bs, n, k, d, p0, p0 + BCONV_OUT_PER, mods);
+  const int g0 = blockIdx.y * BCONV_TILES_Y;
+  if (g0 >= d.ngroups) return;  // uniform over the block
+  const int g1 = min(g0 + BCONV_TILES_Y, d.ngroups);
+  const int nin = d.nin, nsteps = d.nsteps;
+  const uint64_t* src = in + (z / zdiv) * in_bs;
+  uint64_t* dst = out + z * out_bs;
+  uint64_t x[MAX_BCONV_IN / 2];
+#pragma unroll
+  for (int s = 0; s < MAX_BCONV_IN / 2; s++) {
+    const int i = 2 * s + half;
+    x[s] = i < nin ? src[(size_t)d.in_pos[i] * n + k] : 0;
+  }
+  {
+    const uint64_t* __restrict__ fr = d.frag + (size_t)g0 * nsteps * 64;
+    const int nf = (g1 - g0) * nsteps * 64;
+    for (int e = threadIdx.x; e < nf; e += 256) s_frag[e] = fr[e];
+    const int p0 = 4 * g0, np = min(4 * g1, d.nout) - p0;
+    for (int e = threadIdx.x; e < 4 * np; e += 256) s_ep[e] = d.ep[4 * p0 + e];
+    for (int e = threadIdx.x; e < np; e += 256) s_pos[e] = (uint32_t)d.out_pos[p0 + e];
+  }
+  long bf[MAX_BCONV_IN / 2];
+#pragma unroll
+  for (int s = 0; s < MAX_BCONV_IN / 2; s++) {
+    const int i = 2 * s + half;
+    uint64_t t = 0;
+    if (i < nin) t = mul_shoup(x[s], d.tab[i], d.tab[nin + i], mods[d.in_mod[i]].q);
+    bf[s] = (long)sdigits(t);
+  }
+  __syncthreads();
+  const int np = min(4 * g1, d.nout) - 4 * g0;
+  for (int g = 0; g < g1 - g0; g++) {
+    const uint64_t* fr = s_frag + g * nsteps * 64 + lane;
+    v16i acc = {};
+#pragma unroll
+    for (int s = 0; s < MAX_BCONV_IN / 2; s++)
+      if (s < nsteps) acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)fr[s * 64], bf[s], acc, 0, 0, 0);
+#pragma unroll
+    for (int mm = 0; mm < 2; mm++) {
+      const int p = 4 * g + 2 * half + mm;
+      if (p < np) {
+        int32_t a8[8];
+#pragma unroll
+        for (int b = 0; b < 8; b++) a8[b] = acc[8 * mm + b];
+        dst[(size_t)s_pos[p] * n + k] = bconv_combine(a8, s_ep + 4 * p);
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, size_t ext_stride,
@@ -83,7 +140,7 @@ int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) 
   {
     const double mm = (double)N * level * (1 + set.max_out);  // t_i products + MACs (upper bound)
     ProfScope ps(c, "bconv_modup", s, 8.0 * N * (level + (double)set.count * set.max_out), mm);
-    dim3 grid(N / 256, (set.max_out + BCONV_OUT_PER - 1) / BCONV_OUT_PER, set.count);
+    dim3 grid(N / 128, bconv_tiles_y(set), set.count);
     k_bconv<<<grid, 256, 0, s>>>(w.coeff, 0, w.ext, E * N, set.d, set.count, c->d_mod, c->log_n);
   }
   HE_HIP(hipGetLastError());
@@ -109,7 +166,7 @@ int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t*
   const BConvSet& set = c->moddown[level];
   {
     ProfScope ps(c, "bconv_moddown", s, 16.0 * N * (K + level), 2.0 * N * K * (1 + level));
-    dim3 grid(N / 256, (set.max_out + BCONV_OUT_PER - 1) / BCONV_OUT_PER, 2);
+    dim3 grid(N / 128, bconv_tiles_y(set), 2);
     k_bconv<<<grid, 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, set.d, 1, c->d_mod, c->log_n);
   }
   HE_HIP(hipGetLastError());

@@ -101,11 +101,23 @@ int he_ctx_destroy(he_ctx* ctx);
 int he_ctx_moduli(const he_ctx* ctx, uint64_t* out, int cap);
 int he_ctx_info(const he_ctx* ctx, int32_t* log_n, int32_t* n_q, int32_t* n_p, int32_t* alpha);
 /* NTT autotuning done at context creation: forward+inverse transforms of
- * 8, 16, 32 and 64 limbs are timed with 4, 8 and 16 residues per thread;
- * each batch-size bucket (<= 8, <= 16, <= 32, larger) uses its fastest.
- * log_ept[4] receives the chosen log2(residues per thread) per bucket and
- * us[3][4] (may be NULL) the timings in microseconds [variant][bucket]. */
-int he_ctx_ntt_tuning(const he_ctx* ctx, int32_t* log_ept, float* us);
+ * 8, 16, 32 and 64 limbs are timed with each of the HE_NTT_VARIANTS kernel
+ * shapes (he_ntt_variant); each batch-size bucket (<= 8, <= 16, <= 32,
+ * larger limb counts) uses its fastest.  variant[4] (may be NULL) receives
+ * the chosen variant per bucket and us[HE_NTT_VARIANTS][4] (may be NULL)
+ * the timings in microseconds [variant][bucket]. */
+#define HE_NTT_VARIANTS 5
+int he_ctx_ntt_tuning(const he_ctx* ctx, int32_t* variant, float* us);
+/* Shape of NTT variant v (0 <= v < HE_NTT_VARIANTS): residues staged in LDS
+ * per workgroup (`tile`) and residues each thread keeps in registers per LDS
+ * round (`per_thread`).  HE_EINVAL for an unknown variant. */
+int he_ntt_variant(int v, int32_t* tile, int32_t* per_thread);
+/* Replace the autotuned choice: variant[4] gives the variant for each
+ * batch-size bucket (for example a choice saved from he_ctx_ntt_tuning, so
+ * that runs use identical kernels).  Affects later calls on every stream;
+ * do not call while work of this context is being enqueued.  HE_EINVAL for
+ * an unknown variant (nothing is changed then). */
+int he_ctx_ntt_select(he_ctx* ctx, const int32_t* variant);
 const char* he_last_error(void);
 
 /* Execution lanes.  Calls on different streams of one context may run

@@ -492,13 +492,30 @@ int he_ctx_moduli(const he_ctx* h, uint64_t* out, int cap) {
   return M;
 }
 
-int he_ctx_ntt_tuning(const he_ctx* h, int32_t* log_ept, float* us) {
+int he_ctx_ntt_tuning(const he_ctx* h, int32_t* variant, float* us) {
   if (!h) return set_error(HE_EINVAL, "null context");
   for (int i = 0; i < 4; i++) {
-    if (log_ept) log_ept[i] = h->c.ntt_log_ept[i];
-    for (int v = 0; v < 3; v++)
+    if (variant) variant[i] = h->c.ntt_var[i];
+    for (int v = 0; v < NTT_VARIANTS; v++)
       if (us) us[v * 4 + i] = h->c.ntt_tune_us[v][i];
   }
+  return HE_OK;
+}
+
+int he_ctx_ntt_select(he_ctx* h, const int32_t* variant) {
+  if (!h || !variant) return set_error(HE_EINVAL, "null argument");
+  for (int i = 0; i < 4; i++)
+    if (variant[i] < 0 || variant[i] >= NTT_VARIANTS) return set_error(HE_EINVAL, "bad NTT variant");
+  for (int i = 0; i < 4; i++) h->c.ntt_var[i] = variant[i];
+  return HE_OK;
+}
+
+int he_ntt_variant(int v, int32_t* tile, int32_t* per_thread) {
+  if (v < 0 || v >= NTT_VARIANTS || !tile || !per_thread) return set_error(HE_EINVAL, "bad NTT variant");
+  int t, e;
+  ntt_variant_shape(v, &t, &e);
+  *tile = t;
+  *per_thread = e;
   return HE_OK;
 }
 

@@ -14,6 +14,7 @@
 namespace he {
 
 constexpr int MAXL = 64;  // max limbs in any basis (L + K)
+constexpr int NTT_VARIANTS = HE_NTT_VARIANTS;  // (tile, residues per thread) kernel shapes
 
 // Basis-conversion tables of one level: device descriptors (one per digit
 // for ModUp, one for ModDown) plus the largest output count.
@@ -71,8 +72,8 @@ struct Ctx {
   bool prof_on = false;
   // NTT variant (log2 residues per thread) per batch-size bucket (<= 8, 16,
   // 32, more limbs), chosen by the autotuner at context creation
-  int ntt_log_ept[4] = {2, 2, 2, 4};
-  float ntt_tune_us[3][4] = {};  // [variant 4/8/16 per thread][probe 8/16/32/64 limbs] forward+inverse us
+  int ntt_var[4] = {0, 0, 0, 2};           // NTT variant per batch-size bucket
+  float ntt_tune_us[NTT_VARIANTS][4] = {};  // [variant][probe 8/16/32/64 limbs] forward+inverse us
   std::vector<ProfRec> prof;
 
   int dnum(int level) const { return (level + alpha - 1) / alpha; }
@@ -122,6 +123,7 @@ int ntt_launch_from(Ctx* c, const uint64_t* src, uint64_t* data, size_t batch_st
                     bool inverse, hipStream_t s);
 LimbMap range_map(int first_pos, int n, int first_mod);
 int ntt_autotune(Ctx* c);
+void ntt_variant_shape(int v, int* tile, int* per_thread);
 // positions 0..l-1 -> q_0..q_{l-1}, positions l..l+K-1 -> p_0..p_{K-1}
 LimbMap ext_map(const Ctx* c, int level);
 

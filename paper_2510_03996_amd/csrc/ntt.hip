@@ -35,12 +35,12 @@ __device__ __forceinline__ void rounds_inv(T* lds, int tid, int wg, const TW* tw
 }
 
 // grid: x = tile within limb, y = limb index in `map`, z = batch
-template <int LOGN, int PASS, bool INV, int LOG_EPT>
-__global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT>::THREADS)) void ntt_pass_kernel(
+template <int LOGN, int PASS, bool INV, int LOG_EPT, int LOG_TILE>
+__global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREADS)) void ntt_pass_kernel(
     const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, LimbMap map,
     const uint64_t* __restrict__ tw_all, const uint64_t* __restrict__ twp_all, const double* __restrict__ dtw_all,
     const double* __restrict__ dtwq_all, const ModInfo* __restrict__ mods) {
-  using P = NttPass<LOGN, PASS, INV, LOG_EPT>;
+  using P = NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>;
   __shared__ uint64_t lds[P::LDS_WORDS];
   const int wg = blockIdx.x;
   const int limb = blockIdx.y;
@@ -90,11 +90,11 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT>::THREADS)) void 
   }
 }
 
-template <int LOGN, int LOG_EPT>
+template <int LOGN, int LOG_EPT, int LOG_TILE>
 static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
                         int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
-  using P1 = NttPass<LOGN, 1, false, LOG_EPT>;
-  using P2 = NttPass<LOGN, 2, false, LOG_EPT>;
+  using P1 = NttPass<LOGN, 1, false, LOG_EPT, LOG_TILE>;
+  using P2 = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
   constexpr int T = P1::THREADS;
   dim3 g1(P1::WG_PER_LIMB, map.n, nbatch), g2(P2::WG_PER_LIMB, map.n, nbatch);
   const double limbs = (double)map.n * nbatch, N = (double)P1::N;
@@ -103,61 +103,71 @@ static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* da
   if (!inverse) {
     {
       ProfScope ps(c, "ntt_fwd_pass1", s, bytes, mm1);
-      ntt_pass_kernel<LOGN, 1, false, LOG_EPT><<<g1, T, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_tw,
+      ntt_pass_kernel<LOGN, 1, false, LOG_EPT, LOG_TILE><<<g1, T, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_tw,
                                                                 c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod);
     }
     ProfScope ps(c, "ntt_fwd_pass2", s, bytes, mm2);
-    ntt_pass_kernel<LOGN, 2, false, LOG_EPT><<<g2, T, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_tw,
+    ntt_pass_kernel<LOGN, 2, false, LOG_EPT, LOG_TILE><<<g2, T, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_tw,
                                                               c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod);
   } else {
     {
       ProfScope ps(c, "ntt_inv_pass2", s, bytes, mm2);
-      ntt_pass_kernel<LOGN, 2, true, LOG_EPT><<<g2, T, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_itw,
+      ntt_pass_kernel<LOGN, 2, true, LOG_EPT, LOG_TILE><<<g2, T, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_itw,
                                                                c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod);
     }
     ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs);
-    ntt_pass_kernel<LOGN, 1, true, LOG_EPT><<<g1, T, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_itw,
+    ntt_pass_kernel<LOGN, 1, true, LOG_EPT, LOG_TILE><<<g1, T, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_itw,
                                                              c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod);
   }
   HE_HIP(hipGetLastError());
   return HE_OK;
 }
 
-// Variant choice: 4, 8 or 16 residues per thread (1024-, 512- or 256-thread
-// workgroups; more waves for small limb batches, fewer LDS rounds for large
-// ones).  The best variant per batch-size bucket is measured at context
-// creation (ntt_autotune).
+// Variants: (tile, residues per thread) = (4096, 4), (4096, 8), (4096, 16),
+// (2048, 4), (2048, 8).  Smaller tiles and fewer residues per thread give
+// more workgroups and waves for small limb batches; large tiles with more
+// residues per thread need fewer LDS rounds and coalesce better.  The best
+// variant per batch-size bucket is measured at context creation
+// (ntt_autotune).
+static const int kNttLogTile[NTT_VARIANTS] = {12, 12, 12, 11, 11};
+static const int kNttLogEpt[NTT_VARIANTS] = {2, 3, 4, 2, 3};
+
 static int ntt_bucket(int limbs) { return limbs <= 8 ? 0 : limbs <= 16 ? 1 : limbs <= 32 ? 2 : 3; }
 
 template <int LOGN>
-static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
-                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
-  switch (c->ntt_log_ept[ntt_bucket(map.n * nbatch)]) {
-    case 2: return ntt_launch_v<LOGN, 2>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
-    case 3: return ntt_launch_v<LOGN, 3>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
-    default: return ntt_launch_v<LOGN, 4>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+static int ntt_launch_var(Ctx* c, int var, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
+                          int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
+  switch (var) {
+    case 0: return ntt_launch_v<LOGN, 2, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+    case 1: return ntt_launch_v<LOGN, 3, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+    case 3: return ntt_launch_v<LOGN, 2, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+    case 4: return ntt_launch_v<LOGN, 3, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+    default: return ntt_launch_v<LOGN, 4, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
   }
 }
 
 template <int LOGN>
-static int ntt_probe(Ctx* c, int log_ept, const LimbMap& m, hipStream_t s) {
+static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
+                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
+  return ntt_launch_var<LOGN>(c, c->ntt_var[ntt_bucket(map.n * nbatch)], src, src_bs, data, batch_stride, nbatch, map,
+                              inverse, s);
+}
+
+template <int LOGN>
+static int ntt_probe(Ctx* c, int var, const LimbMap& m, hipStream_t s) {
   int rc;
-  switch (log_ept) {
-    case 2:
-      if ((rc = ntt_launch_v<LOGN, 2>(c, c->ws, 0, c->ws, 0, 1, m, false, s))) return rc;
-      return ntt_launch_v<LOGN, 2>(c, c->ws, 0, c->ws, 0, 1, m, true, s);
-    case 3:
-      if ((rc = ntt_launch_v<LOGN, 3>(c, c->ws, 0, c->ws, 0, 1, m, false, s))) return rc;
-      return ntt_launch_v<LOGN, 3>(c, c->ws, 0, c->ws, 0, 1, m, true, s);
-    default:
-      if ((rc = ntt_launch_v<LOGN, 4>(c, c->ws, 0, c->ws, 0, 1, m, false, s))) return rc;
-      return ntt_launch_v<LOGN, 4>(c, c->ws, 0, c->ws, 0, 1, m, true, s);
-  }
+  if ((rc = ntt_launch_var<LOGN>(c, var, c->ws, 0, c->ws, 0, 1, m, false, s))) return rc;
+  return ntt_launch_var<LOGN>(c, var, c->ws, 0, c->ws, 0, 1, m, true, s);
 }
 
 // Autotuner: time a forward + inverse transform of 8, 16, 32 and 64 limbs
 // (the context's own moduli, in its workspace) with each variant and keep the
 // fastest per bucket; larger batches use the 64-limb choice.
+void ntt_variant_shape(int v, int* tile, int* per_thread) {
+  *tile = 1 << kNttLogTile[v];
+  *per_thread = 1 << kNttLogEpt[v];
+}
+
 int ntt_autotune(Ctx* c) {
   const int probes[4] = {8, 16, 32, 64};
   const size_t N = c->n;
@@ -177,13 +187,12 @@ int ntt_autotune(Ctx* c) {
       m.mod[i] = (uint8_t)(i % (c->L + c->K));
     }
     float best = 1e30f;
-    for (int v = 0; v < 3; v++) {
-      const int le = 2 + v;
+    for (int v = 0; v < NTT_VARIANTS; v++) {
       auto run = [&]() -> int {
         switch (c->log_n) {
-          case 16: return ntt_probe<16>(c, le, m, s);
-          case 14: return ntt_probe<14>(c, le, m, s);
-          default: return ntt_probe<12>(c, le, m, s);
+          case 16: return ntt_probe<16>(c, v, m, s);
+          case 14: return ntt_probe<14>(c, v, m, s);
+          default: return ntt_probe<12>(c, v, m, s);
         }
       };
       int rc;
@@ -199,7 +208,7 @@ int ntt_autotune(Ctx* c) {
       c->ntt_tune_us[v][pi] = us;
       if (us < best) {
         best = us;
-        c->ntt_log_ept[pi] = le;
+        c->ntt_var[pi] = v;
       }
     }
   }

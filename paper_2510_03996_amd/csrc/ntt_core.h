@@ -13,7 +13,7 @@
 // N2 "columns" {c + k N2} are independent size-2^L1 transforms sharing the
 // twiddles Psi[2^s + block].  Pass 2 runs stages L1..LOGN-1 inside contiguous
 // "chunks" of N2 elements, chunk b using Psi[2^(L1+s) + b 2^s + block].
-// A workgroup stages TILE elements (several columns / chunks) in LDS; each
+// A workgroup stages TILE (2048 or 4096) elements (several columns / chunks) in LDS; each
 // thread keeps a radix-2^r butterfly group (r <= 4 stages) in registers per
 // LDS round, so a pass costs one HBM read + write and ceil(L/4) LDS rounds.
 //
@@ -24,7 +24,7 @@
 
 namespace he {
 
-template <int LOGN, int PASS, bool INV, int LOG_EPT = 4>
+template <int LOGN, int PASS, bool INV, int LOG_EPT = 4, int LOG_TILE = 12>
 struct NttPass {
   static constexpr int N = 1 << LOGN;
   static constexpr int L1 = (LOGN + 1) / 2;
@@ -32,7 +32,7 @@ struct NttPass {
   static constexpr int N2 = 1 << L2;
   static constexpr int LM = PASS == 1 ? L1 : L2;  // stages in this pass
   static constexpr int M = 1 << LM;               // sub-transform size
-  static constexpr int TILE = N < 4096 ? N : 4096;  // elements per workgroup
+  static constexpr int TILE = LOGN < LOG_TILE ? N : (1 << LOG_TILE);  // elements per workgroup
   static constexpr int G = TILE / M;              // sub-transforms per workgroup
   static constexpr int WG_PER_LIMB = N / TILE;
   // each thread keeps 2^LOG_EPT elements (one radix-2^LOG_EPT group) per round

@@ -20,6 +20,7 @@ ERRORS = {
     -5: "HE_ENOMEM", -6: "HE_EHIP", -7: "HE_EUNSUPPORTED",
 }
 KEY_RELIN = 0x7FFFFFFF
+NTT_VARIANTS = 5
 MAX_Q, MAX_P = 60, 16
 
 
@@ -130,6 +131,8 @@ def lib():
             "he_lane_reserve": [vp, vp, c_int],
             "he_lane_release": [vp, vp],
             "he_ctx_ntt_tuning": [vp, P(i32), P(ctypes.c_float)],
+            "he_ntt_variant": [c_int, P(i32), P(i32)],
+            "he_ctx_ntt_select": [vp, P(i32)],
             "he_profile_begin": [vp],
             "he_profile_end": [vp, ctypes.c_char_p, sz],
         }
@@ -423,11 +426,26 @@ class Context:
         return out
 
     def ntt_tuning(self):
-        le = (ctypes.c_int32 * 4)()
-        us = (ctypes.c_float * 12)()
-        _check(lib().he_ctx_ntt_tuning(self.h, le, us))
-        return {"bucket_max_limbs": [8, 16, 32, "more"], "residues_per_thread": [1 << x for x in le],
-                "us_fwd_inv": {str(1 << (2 + v)): [round(us[v * 4 + i], 2) for i in range(4)] for v in range(3)}}
+        nv = NTT_VARIANTS
+        var = (ctypes.c_int32 * 4)()
+        us = (ctypes.c_float * (nv * 4))()
+        _check(lib().he_ctx_ntt_tuning(self.h, var, us))
+        shapes = []
+        for v in range(nv):
+            t, e = ctypes.c_int32(), ctypes.c_int32()
+            _check(lib().he_ntt_variant(v, ctypes.byref(t), ctypes.byref(e)))
+            shapes.append("%dx%d" % (t.value, e.value))
+        return {"bucket_max_limbs": [8, 16, 32, "more"], "variant_tile_x_per_thread": [shapes[v] for v in var],
+                "us_fwd_inv": {shapes[v]: [round(us[v * 4 + i], 2) for i in range(4)] for v in range(nv)}}
+
+    def ntt_select(self, variants):
+        """Pin the NTT variant of each batch-size bucket (4 entries)."""
+        _check(lib().he_ctx_ntt_select(self.h, (ctypes.c_int32 * 4)(*[int(v) for v in variants])))
+
+    def ntt_variants(self):
+        var = (ctypes.c_int32 * 4)()
+        _check(lib().he_ctx_ntt_tuning(self.h, var, None))
+        return list(var)
 
     # ---- lanes
     def lane_reserve(self, stream, n_ct_buffers):

@@ -55,6 +55,40 @@ def test_ntt_forward_inverse(gctx, name):
 
 
 @pytest.mark.parametrize("name", CONFIGS)
+def test_every_ntt_variant(gctx, name):
+    """Each (tile, residues per thread) kernel shape, pinned in turn for every
+    batch-size bucket: forward NTT, round trip and a full key-switch rotation."""
+    import synth
+    from paper_2510_03996_amd import he
+
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    pr = octx.pr
+    tuned = g.ntt_variants()
+    a = synth.residues(11, pr.moduli, pr.n)
+    want = OC.ntt(a, pr.moduli, pr.psi)
+    g.key_upload(5, H.oracle_key(name, 5))
+    _, ct = H.encrypt_slots(name, 12)
+    want_rot = octx.rotate(ct, 5, {5: H.oracle_key(name, 5)})
+    try:
+        for v in range(he.NTT_VARIANTS):
+            g.ntt_select([v] * 4)
+            t = he.to_device(a)
+            g.ntt(t, 0, inverse=False)
+            H.assert_limbs_equal(t.cpu().numpy().view(np.uint64), want, "forward NTT, variant %d" % v)
+            g.ntt(t, 0, inverse=True)
+            H.assert_limbs_equal(t.cpu().numpy().view(np.uint64), a, "round trip, variant %d" % v)
+            got = g.rotate(g.ct_from_numpy(ct.data, ct.scale), 5)
+            H.assert_limbs_equal(got.numpy(), want_rot.data, "rotation, variant %d" % v)
+    finally:
+        g.ntt_select(tuned)
+        g.key_evict(5)  # the module's contexts are shared: leave the key set as found
+    with pytest.raises(he.HEError):
+        g.ntt_select([0, 0, 0, he.NTT_VARIANTS])
+    assert g.ntt_variants() == tuned
+
+
+@pytest.mark.parametrize("name", CONFIGS)
 def test_pointwise_and_rescale(gctx, name):
     g = gctx(name)
     octx, _, _ = H.oracle_ctx(name)

@@ -282,6 +282,8 @@ static int ctx_init(Ctx* c, const he_params* p) {
     mi.pad = 0;
     mi.dninv = (double)mi.ninv;
     mi.dninvq = (double)mi.ninv / (double)q;
+    mi.dqinv = 1.0 / (double)q;
+    mi.dpad = 0.0;
   }
   int rc;
   if ((rc = dev_alloc(c, &c->d_mod, M))) return rc;

@@ -79,19 +79,27 @@ HE_HD uint64_t barrett_reduce(U128 x, uint64_t q, uint64_t mu, int k) {
   return r;
 }
 
-// FP64 product for primes q < 2^50 (residues kept below 4q < 2^52, exact in a
-// double): with wq = fl(w/q), quot = floor(fl(a wq)) is within 1 of
-// floor(a w / q) (|a (wq - w/q)| <= 2^52 2^-54 and the rounding of a wq adds
-// at most 2^-2), so r = a w - quot q lies in [-q, 2q).  a w = hi + lo exactly
-// (two-product with one FMA), hi - quot q is an integer below 2^53 in
-// magnitude and therefore exact in one FMA, and r = (hi - quot q) + lo is
-// exact as well.  Returns r in [0, 2q) (same range as mul_shoup_lazy).
-HE_HD double mul_f64_lazy(double a, double w, double wq, double q) {
-  const double quot = floor(a * wq);
+// Centred FP64 arithmetic for primes q < 2^50 (the NTT's FP64 path).
+// Residues are integer-valued doubles of magnitude below 8q < 2^53, so every
+// value is exact.  mul_f64_c(a, w, wq): with wq = fl(w/q) the estimate
+// fl(a wq) is within |a| 2^-52 <= |a| / (4q) of a w / q, so the quotient
+// quot = rint(fl(a wq)) leaves r = a w - quot q with |r| <= q (1/2 + |a| / (4q)).
+// a w = hi + lo exactly (two-product with one FMA); hi - quot q is an integer
+// below 2^53 in magnitude, hence exact in one FMA, and r = (hi - quot q) + lo
+// is exact too.  No conditional corrections are needed: callers keep |a| <= 8q
+// and re-centre with centre_f64 (|result| <= q/2 + 1) once per LDS round.
+HE_HD double mul_f64_c(double a, double w, double wq, double q) {
+  const double quot = rint(a * wq);
   const double hi = a * w;
   const double lo = fma(a, w, -hi);
-  const double r = fma(-quot, q, hi) + lo;
-  return r < 0.0 ? r + q : r;
+  return fma(-quot, q, hi) + lo;
+}
+HE_HD double centre_f64(double x, double qinv, double q) { return fma(-rint(x * qinv), q, x); }
+// canonical representative in [0, q) of an integer-valued |x| <= 8q
+HE_HD double canon_f64(double x, double qinv, double q) {
+  double r = fma(-floor(x * qinv), q, x);
+  r = r < 0.0 ? r + q : r;
+  return r >= q ? r - q : r;
 }
 
 // Per-modulus constants (device resident).
@@ -104,6 +112,8 @@ struct ModInfo {
   int32_t k;          // bit length of q
   int32_t pad;
   double dninv, dninvq;  // N^{-1} and N^{-1}/q as doubles (FP64 NTT path, q < 2^50)
+  double dqinv;          // 1/q as a double (FP64 NTT path)
+  double dpad;
 };
 
 HE_HD uint64_t mul_mod(uint64_t a, uint64_t b, const ModInfo& m) {

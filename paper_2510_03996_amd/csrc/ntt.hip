@@ -9,27 +9,27 @@ namespace he {
 
 // Rounds IDX..NR-1 of a pass, forward order (integer or FP64 arithmetic).
 template <class P, int IDX, class T, class TW, class Q>
-__device__ __forceinline__ void rounds_fwd(T* lds, int tid, int wg, const TW* tw, const TW* twp, Q q) {
+__device__ __forceinline__ void rounds_fwd(T* lds, int tid, int wg, const TW* tw, const TW* twp, Q q, Q qinv) {
   if constexpr (IDX < P::NR) {
     if constexpr (IDX > 0) __syncthreads();
-    if constexpr (sizeof(T) == 8 && std::is_same<T, double>::value)
-      P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
+    if constexpr (std::is_same<T, double>::value)
+      P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
     else
       P::template round<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
-    rounds_fwd<P, IDX + 1>(lds, tid, wg, tw, twp, q);
+    rounds_fwd<P, IDX + 1>(lds, tid, wg, tw, twp, q, qinv);
   }
 }
 // Rounds IDX..0 of a pass, inverse order.
 template <class P, int IDX, class T, class TW, class Q>
-__device__ __forceinline__ void rounds_inv(T* lds, int tid, int wg, const TW* tw, const TW* twp, Q q) {
+__device__ __forceinline__ void rounds_inv(T* lds, int tid, int wg, const TW* tw, const TW* twp, Q q, Q qinv) {
   if constexpr (IDX >= 0) {
     if constexpr (std::is_same<T, double>::value)
-      P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
+      P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
     else
       P::template round<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
     if constexpr (IDX > 0) {
       __syncthreads();
-      rounds_inv<P, IDX - 1>(lds, tid, wg, tw, twp, q);
+      rounds_inv<P, IDX - 1>(lds, tid, wg, tw, twp, q, qinv);
     }
   }
 }
@@ -55,20 +55,21 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
     double* dl = reinterpret_cast<double*>(lds);
     const double* dtw = dtw_all + (size_t)m * P::N;
     const double* dtwq = dtwq_all + (size_t)m * P::N;
-    const double dq = (double)q;
+    const double dq = (double)q, dqinv = mi.dqinv;
+    // inputs: canonical residues, or the signed intermediate of the other pass
     for (int e = tid; e < P::TILE; e += P::THREADS) {
       int g, k;
       P::tile_elem(e, g, k);
-      dl[P::lidx(g, k)] = (double)ain[P::gidx(wg, g, k)];
+      dl[P::lidx(g, k)] = (double)(int64_t)ain[P::gidx(wg, g, k)];
     }
     __syncthreads();
-    if (!INV) rounds_fwd<P, 0>(dl, tid, wg, dtw, dtwq, dq);
-    else rounds_inv<P, P::NR - 1>(dl, tid, wg, dtw, dtwq, dq);
+    if (!INV) rounds_fwd<P, 0>(dl, tid, wg, dtw, dtwq, dq, dqinv);
+    else rounds_inv<P, P::NR - 1>(dl, tid, wg, dtw, dtwq, dq, dqinv);
     __syncthreads();
     for (int e = tid; e < P::TILE; e += P::THREADS) {
       int g, k;
       P::tile_elem(e, g, k);
-      a[P::gidx(wg, g, k)] = P::finish_f64(dl[P::lidx(g, k)], mi.dninv, mi.dninvq, dq);
+      a[P::gidx(wg, g, k)] = P::finish_f64(dl[P::lidx(g, k)], mi.dninv, mi.dninvq, dq, dqinv);
     }
     return;
   }
@@ -80,8 +81,8 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
     lds[P::lidx(g, k)] = ain[P::gidx(wg, g, k)];
   }
   __syncthreads();
-  if (!INV) rounds_fwd<P, 0>(lds, tid, wg, tw, twp, q);
-  else rounds_inv<P, P::NR - 1>(lds, tid, wg, tw, twp, q);
+  if (!INV) rounds_fwd<P, 0>(lds, tid, wg, tw, twp, q, q);
+  else rounds_inv<P, P::NR - 1>(lds, tid, wg, tw, twp, q, q);
   __syncthreads();
   for (int e = tid; e < P::TILE; e += P::THREADS) {
     int g, k;

@@ -119,15 +119,19 @@ struct NttPass {
     }
   }
 
-  // FP64 round for q < 2^50: identical butterflies on exact doubles, products
-  // by mul_f64_lazy (full-rate FMA instead of half-rate 32-bit multiplies).
+  // FP64 round for q < 2^50: the same butterflies in centred arithmetic
+  // (mul_f64_c, full-rate FP64 FMA instead of 32-bit integer multiplies).
+  // Each round starts by re-centring its inputs to |x| <= q/2 + 1; over at
+  // most four stages the forward butterflies (a + y, a - y) stay below 4.2q
+  // and the inverse ones (a + b, (a - b) w) below 8q, so everything is exact.
   template <int R>
-  HE_HD static void round_f64(double* lds, int tid, int wg, int s0, const double* tw, const double* twq, double q) {
+  HE_HD static void round_f64(double* lds, int tid, int wg, int s0, const double* tw, const double* twq, double q,
+                              double qinv) {
+    static_assert(R <= 4, "the centred bounds assume at most four stages per round");
     constexpr int GPS = M >> R;
     constexpr int TOTAL = G * GPS;
     const int dmin = M >> (s0 + R);
     const int span = M >> s0;
-    const double q2 = 2.0 * q;
     for (int gid = tid; gid < TOTAL; gid += THREADS) {
       int g, gg;
       if (PASS == 1) { g = gid % G; gg = gid / G; }
@@ -136,7 +140,7 @@ struct NttPass {
       const int base = hi * span + lo;
       double x[1 << R];
 #pragma unroll
-      for (int u = 0; u < (1 << R); u++) x[u] = lds[lidx(g, base + u * dmin)];
+      for (int u = 0; u < (1 << R); u++) x[u] = centre_f64(lds[lidx(g, base + u * dmin)], qinv, q);
       const int sub_off = PASS == 2 ? (wg * G + g) : 0;
       if (!INV) {
 #pragma unroll
@@ -149,11 +153,10 @@ struct NttPass {
             if (u & half) continue;
             const int iloc = (hi << ss) + (u >> (R - ss));
             const int ti = (1 << sg) + (sub_off << s) + iloc;
-            const double y = mul_f64_lazy(x[u + half], tw[ti], twq[ti], q);
-            double a = x[u];
-            a = a >= q2 ? a - q2 : a;
+            const double y = mul_f64_c(x[u + half], tw[ti], twq[ti], q);
+            const double a = x[u];
             x[u] = a + y;
-            x[u + half] = a - y + q2;
+            x[u + half] = a - y;
           }
         }
       } else {
@@ -168,9 +171,8 @@ struct NttPass {
             const int iloc = (hi << ss) + (u >> (R - ss));
             const int ti = (1 << sg) + (sub_off << s) + iloc;
             const double a = x[u], b = x[u + half];
-            const double sm = a + b;
-            x[u] = sm >= q2 ? sm - q2 : sm;
-            x[u + half] = mul_f64_lazy(a - b + q2, tw[ti], twq[ti], q);
+            x[u] = a + b;
+            x[u + half] = mul_f64_c(a - b, tw[ti], twq[ti], q);
           }
         }
       }
@@ -179,15 +181,14 @@ struct NttPass {
     }
   }
 
-  HE_HD static uint64_t finish_f64(double v, double ninv, double ninvq, double q) {
-    if (!INV && PASS == 2) {
-      v = v >= 2.0 * q ? v - 2.0 * q : v;
-      v = v >= q ? v - q : v;
-    } else if (INV && PASS == 1) {
-      v = mul_f64_lazy(v, ninv, ninvq, q);
-      v = v >= q ? v - q : v;
-    }
-    return (uint64_t)v;
+  // FP64 value written back after the pass: the intermediate (forward pass 1,
+  // inverse pass 2) is the signed integer itself (two's complement, read back
+  // by the other pass only); the forward transform canonicalises after pass 2,
+  // the inverse multiplies by N^{-1} and canonicalises after pass 1.
+  HE_HD static uint64_t finish_f64(double v, double ninv, double ninvq, double q, double qinv) {
+    if (!INV && PASS == 2) return (uint64_t)canon_f64(v, qinv, q);
+    if (INV && PASS == 1) return (uint64_t)canon_f64(mul_f64_c(v, ninv, ninvq, q), qinv, q);
+    return (uint64_t)(int64_t)v;
   }
 
   // Value written back to HBM after the pass: the forward transform leaves

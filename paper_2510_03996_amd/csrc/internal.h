@@ -123,6 +123,21 @@ int ntt_launch_from(Ctx* c, const uint64_t* src, uint64_t* data, size_t batch_st
                     bool inverse, hipStream_t s);
 LimbMap range_map(int first_pos, int n, int first_mod);
 int ntt_autotune(Ctx* c);
+// ModDown epilogue fused into the last forward NTT pass: the transform's
+// output y never reaches HBM; instead, for z = 0, 1 and every q-limb i,
+//   out_z[i][k] = add_z[i][src_z(k)] + (u_z[i][k] - y_z[i][k]) P^{-1} mod q_i
+// with src_0 the automorphism phi_g (g = 1: identity), src_1 the identity;
+// a null add_z counts as zero.
+struct NttEpi {
+  const uint64_t* u;
+  size_t u_bs;
+  const uint64_t* add[2];
+  uint64_t* out[2];
+  const uint64_t* pinv;  // [level] P^{-1} mod q_i, then [level] Shoup companions
+  uint32_t g;
+  int32_t level;
+};
+int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& map, const NttEpi& epi, hipStream_t s);
 void ntt_variant_shape(int v, int* tile, int* per_thread);
 // positions 0..l-1 -> q_0..q_{l-1}, positions l..l+K-1 -> p_0..p_{K-1}
 LimbMap ext_map(const Ctx* c, int level);
@@ -164,10 +179,6 @@ constexpr int BCONV_TILES_Y = 8;  // 4-output row tiles per basis-conversion wor
 inline int bconv_tiles_y(const BConvSet& s) { return ((s.max_out + 3) / 4 + BCONV_TILES_Y - 1) / BCONV_TILES_Y; }
 __global__ void k_bconv(const uint64_t* __restrict__ in, size_t in_bs, uint64_t* __restrict__ out, size_t out_bs,
                         const BConvDesc* __restrict__ descs, int zdiv, const ModInfo* __restrict__ mods, int logn);
-__global__ void k_moddown_combine(const uint64_t* __restrict__ u, size_t u_ps, const uint64_t* __restrict__ y,
-                                  size_t y_ps, const uint64_t* add0, const uint64_t* add1, uint32_t g, uint64_t* out0,
-                                  uint64_t* out1, int level, int logn, const ModInfo* __restrict__ mods,
-                                  const uint64_t* __restrict__ pinv);
 __global__ void k_bcast_reduce(const uint64_t* __restrict__ T, uint64_t* __restrict__ R, int nl, int logn,
                                const ModInfo* __restrict__ mods);
 __global__ void k_rescale_combine(const uint64_t* in, size_t ips, const uint64_t* __restrict__ R, uint64_t* out,

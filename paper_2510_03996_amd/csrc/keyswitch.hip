@@ -97,26 +97,6 @@ __global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, si
           mod, n, k, src, mods[mod], u, u, u_poly_stride);
 }
 
-// out_z[i][k] = add_z + (u_z[i][k] - y_z[i][k]) P^{-1}, z = blockIdx.z;
-// add_0 = phi_g(add0)[i][k] (g = 1: no permutation), add_1 = add1[i][k].
-__global__ __launch_bounds__(256) void k_moddown_combine(const uint64_t* __restrict__ u, size_t u_ps,
-                                                         const uint64_t* __restrict__ y, size_t y_ps,
-                                                         const uint64_t* add0, const uint64_t* add1, uint32_t g,
-                                                         uint64_t* out0, uint64_t* out1, int level, int logn,
-                                                         const ModInfo* __restrict__ mods,
-                                                         const uint64_t* __restrict__ pinv) {
-  const size_t n = (size_t)1 << logn;
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y, z = blockIdx.z;
-  const uint64_t q = mods[i].q;
-  uint64_t a = 0;
-  if (z == 0 && add0) a = add0[(size_t)i * n + (g == 1 ? k : automorph_src(k, g, logn))];
-  if (z == 1 && add1) a = add1[(size_t)i * n + k];
-  const uint64_t v = moddown_elem(u[z * u_ps + (size_t)i * n + k], y[z * y_ps + (size_t)i * n + k], a, pinv[i],
-                                  pinv[level + i], q);
-  (z == 0 ? out0 : out1)[(size_t)i * n + k] = v;
-}
-
 // x -> x 2^64 mod q on every limb of a [dnum][2][L+K][N] key
 __global__ __launch_bounds__(256) void k_to_mont(uint64_t* key, int M, int logn, const ModInfo* __restrict__ mods) {
   const size_t n = (size_t)1 << logn;
@@ -170,13 +150,18 @@ int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t*
     k_bconv<<<grid, 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, set.d, 1, c->d_mod, c->log_n);
   }
   HE_HIP(hipGetLastError());
-  if ((rc = ntt_launch(c, w.y, (size_t)level * N, 2, range_map(0, level, 0), false, s))) return rc;
-  {
-    ProfScope ps(c, "moddown_combine", s, 8.0 * N * level * (6 + (add0 ? 1 : 0) + (add1 ? 1 : 0)), 2.0 * N * level);
-    k_moddown_combine<<<dim3(N / 256, level, 2), 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, add0, add1, g,
-                                                               out0, out1, level, c->log_n, c->d_mod,
-                                                               c->d_pinv[level]);
-  }
+  // back to NTT form with the ModDown epilogue fused into the last pass
+  NttEpi epi{};
+  epi.u = w.u;
+  epi.u_bs = E * N;
+  epi.add[0] = add0;
+  epi.add[1] = add1;
+  epi.out[0] = out0;
+  epi.out[1] = out1;
+  epi.pinv = c->d_pinv[level];
+  epi.g = g;
+  epi.level = level;
+  if ((rc = ntt_launch_moddown(c, w.y, (size_t)level * N, range_map(0, level, 0), epi, s))) return rc;
   HE_HIP(hipGetLastError());
   return HE_OK;
 }

@@ -34,12 +34,30 @@ __device__ __forceinline__ void rounds_inv(T* lds, int tid, int wg, const TW* tw
   }
 }
 
+// Final store of one residue: plain, or (EPI, last forward pass) the fused
+// ModDown epilogue of NttEpi for q-limb i, coefficient k, batch z.
+template <bool EPI, int LOGN>
+__device__ __forceinline__ void ntt_store(uint64_t* a, int k, uint64_t v, const NttEpi& epi, int i, int z,
+                                          uint64_t q) {
+  if constexpr (!EPI) {
+    a[k] = v;
+  } else {
+    const size_t off = (size_t)i << LOGN;
+    const uint64_t* add = epi.add[z];
+    uint64_t x = 0;
+    if (add) x = add[off + (z == 0 && epi.g != 1 ? automorph_src(k, epi.g, LOGN) : (uint32_t)k)];
+    epi.out[z][off + k] =
+        moddown_elem(epi.u[z * epi.u_bs + off + k], v, x, epi.pinv[i], epi.pinv[epi.level + i], q);
+  }
+}
+
 // grid: x = tile within limb, y = limb index in `map`, z = batch
-template <int LOGN, int PASS, bool INV, int LOG_EPT, int LOG_TILE>
+template <int LOGN, int PASS, bool INV, int LOG_EPT, int LOG_TILE, bool EPI>
 __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREADS)) void ntt_pass_kernel(
     const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, LimbMap map,
     const uint64_t* __restrict__ tw_all, const uint64_t* __restrict__ twp_all, const double* __restrict__ dtw_all,
-    const double* __restrict__ dtwq_all, const ModInfo* __restrict__ mods) {
+    const double* __restrict__ dtwq_all, const ModInfo* __restrict__ mods, NttEpi epi) {
+  static_assert(!EPI || (PASS == 2 && !INV), "the ModDown epilogue follows the last forward pass");
   using P = NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>;
   __shared__ uint64_t lds[P::LDS_WORDS];
   const int wg = blockIdx.x;
@@ -69,7 +87,8 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
     for (int e = tid; e < P::TILE; e += P::THREADS) {
       int g, k;
       P::tile_elem(e, g, k);
-      a[P::gidx(wg, g, k)] = P::finish_f64(dl[P::lidx(g, k)], mi.dninv, mi.dninvq, dq, dqinv);
+      ntt_store<EPI, LOGN>(a, P::gidx(wg, g, k), P::finish_f64(dl[P::lidx(g, k)], mi.dninv, mi.dninvq, dq, dqinv),
+                           epi, map.pos[limb], blockIdx.z, q);
     }
     return;
   }
@@ -87,13 +106,14 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
   for (int e = tid; e < P::TILE; e += P::THREADS) {
     int g, k;
     P::tile_elem(e, g, k);
-    a[P::gidx(wg, g, k)] = P::finish(lds[P::lidx(g, k)], mi.ninv, mi.ninv_p, q);
+    ntt_store<EPI, LOGN>(a, P::gidx(wg, g, k), P::finish(lds[P::lidx(g, k)], mi.ninv, mi.ninv_p, q), epi,
+                         map.pos[limb], blockIdx.z, q);
   }
 }
 
 template <int LOGN, int LOG_EPT, int LOG_TILE>
 static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
-                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
+                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr) {
   using P1 = NttPass<LOGN, 1, false, LOG_EPT, LOG_TILE>;
   using P2 = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
   constexpr int T = P1::THREADS;
@@ -101,24 +121,33 @@ static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* da
   const double limbs = (double)map.n * nbatch, N = (double)P1::N;
   const double bytes = 16.0 * N * limbs;  // one read + one write of every residue per pass
   const double mm1 = N / 2 * P1::LM * limbs, mm2 = N / 2 * P2::LM * limbs;
+  const NttEpi none{};
   if (!inverse) {
     {
       ProfScope ps(c, "ntt_fwd_pass1", s, bytes, mm1);
-      ntt_pass_kernel<LOGN, 1, false, LOG_EPT, LOG_TILE><<<g1, T, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_tw,
-                                                                c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod);
+      ntt_pass_kernel<LOGN, 1, false, LOG_EPT, LOG_TILE, false><<<g1, T, 0, s>>>(
+          src, src_bs, data, batch_stride, map, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, none);
     }
-    ProfScope ps(c, "ntt_fwd_pass2", s, bytes, mm2);
-    ntt_pass_kernel<LOGN, 2, false, LOG_EPT, LOG_TILE><<<g2, T, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_tw,
-                                                              c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod);
+    if (epi) {
+      // + u read, out write instead of y write, add_0 / add_1 reads
+      const double eb = bytes + 8.0 * N * limbs * (1 + (epi->add[0] ? 0.5 : 0) + (epi->add[1] ? 0.5 : 0));
+      ProfScope ps(c, "ntt_fwd_pass2_moddown", s, eb, mm2 + N * limbs);
+      ntt_pass_kernel<LOGN, 2, false, LOG_EPT, LOG_TILE, true><<<g2, T, 0, s>>>(
+          data, batch_stride, data, batch_stride, map, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, *epi);
+    } else {
+      ProfScope ps(c, "ntt_fwd_pass2", s, bytes, mm2);
+      ntt_pass_kernel<LOGN, 2, false, LOG_EPT, LOG_TILE, false><<<g2, T, 0, s>>>(
+          data, batch_stride, data, batch_stride, map, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, none);
+    }
   } else {
     {
       ProfScope ps(c, "ntt_inv_pass2", s, bytes, mm2);
-      ntt_pass_kernel<LOGN, 2, true, LOG_EPT, LOG_TILE><<<g2, T, 0, s>>>(src, src_bs, data, batch_stride, map, c->d_itw,
-                                                               c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod);
+      ntt_pass_kernel<LOGN, 2, true, LOG_EPT, LOG_TILE, false><<<g2, T, 0, s>>>(
+          src, src_bs, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod, none);
     }
     ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs);
-    ntt_pass_kernel<LOGN, 1, true, LOG_EPT, LOG_TILE><<<g1, T, 0, s>>>(data, batch_stride, data, batch_stride, map, c->d_itw,
-                                                             c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod);
+    ntt_pass_kernel<LOGN, 1, true, LOG_EPT, LOG_TILE, false><<<g1, T, 0, s>>>(
+        data, batch_stride, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod, none);
   }
   HE_HIP(hipGetLastError());
   return HE_OK;
@@ -137,21 +166,21 @@ static int ntt_bucket(int limbs) { return limbs <= 8 ? 0 : limbs <= 16 ? 1 : lim
 
 template <int LOGN>
 static int ntt_launch_var(Ctx* c, int var, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
-                          int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
+                          int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr) {
   switch (var) {
-    case 0: return ntt_launch_v<LOGN, 2, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
-    case 1: return ntt_launch_v<LOGN, 3, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
-    case 3: return ntt_launch_v<LOGN, 2, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
-    case 4: return ntt_launch_v<LOGN, 3, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
-    default: return ntt_launch_v<LOGN, 4, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+    case 0: return ntt_launch_v<LOGN, 2, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi);
+    case 1: return ntt_launch_v<LOGN, 3, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi);
+    case 3: return ntt_launch_v<LOGN, 2, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi);
+    case 4: return ntt_launch_v<LOGN, 3, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi);
+    default: return ntt_launch_v<LOGN, 4, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi);
   }
 }
 
 template <int LOGN>
 static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
-                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s) {
+                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr) {
   return ntt_launch_var<LOGN>(c, c->ntt_var[ntt_bucket(map.n * nbatch)], src, src_bs, data, batch_stride, nbatch, map,
-                              inverse, s);
+                              inverse, s, epi);
 }
 
 template <int LOGN>
@@ -228,6 +257,18 @@ int ntt_launch_strided(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* dat
     case 12: return ntt_launch_n<12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
     case 14: return ntt_launch_n<14>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
     case 16: return ntt_launch_n<16>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s);
+  }
+  return set_error(HE_EINVAL, "unsupported ring degree");
+}
+
+int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& map, const NttEpi& epi, hipStream_t s) {
+  if (map.n <= 0) return HE_OK;
+  // the transform runs in place on y (its scratch); results go to epi.out
+  uint64_t* yy = const_cast<uint64_t*>(y);
+  switch (c->log_n) {
+    case 12: return ntt_launch_n<12>(c, yy, y_bs, yy, y_bs, 2, map, false, s, &epi);
+    case 14: return ntt_launch_n<14>(c, yy, y_bs, yy, y_bs, 2, map, false, s, &epi);
+    case 16: return ntt_launch_n<16>(c, yy, y_bs, yy, y_bs, 2, map, false, s, &epi);
   }
   return set_error(HE_EINVAL, "unsupported ring degree");
 }

@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the CPU baseline sample")
     ap.add_argument("--only-headline", action="store_true", help="skip layers / batched / serving sections")
-    ap.add_argument("--only", choices=["layers", "batched", "serving"], default=None,
+    ap.add_argument("--only", choices=["hoisted", "layers", "batched", "serving"], default=None,
                     help="run the headline plus one section (profiling runs)")
     ap.add_argument("--serve-requests", type=int, default=60)
     return ap.parse_args()
@@ -176,6 +176,36 @@ def headline(args):
     roof["ntt_autotune"] = ctx.ntt_tuning()
     ctx.close()
     return rot_s, el, roof, kern, ks_bytes, (L, K, dnum)
+
+
+# ---------------------------------------------------------------- hoisted rotation sets
+def hoisted_sets(reps=20):
+    """he_rotate_hoisted at N=2^16 L=24: the 3x3 conv window (8 rotations, W=32)
+    and the 7x7 window plus 1024 (49 rotations), one ModUp per set."""
+    import torch
+
+    ctx = new_ctx(CFG2)
+    sets = {"set8": [dy * 32 + dx for dy in (-1, 0, 1) for dx in (-1, 0, 1) if (dy, dx) != (0, 0)],
+            "set49": [dy * 32 + dx for dy in range(-3, 4) for dx in range(-3, 4) if (dy, dx) != (0, 0)] + [1024]}
+    upload_synthetic_keys(ctx, sorted(set(sets["set8"]) | set(sets["set49"])), 3)
+    ct = synthetic_ct(ctx, ctx.L, 4, 2.0 ** 50)
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, rs in sets.items():
+        outs = [ctx.new_ct(ctx.L) for _ in rs]
+        for _ in range(2):
+            ctx.rotate_hoisted(ct, rs, outs=outs, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.rotate_hoisted(ct, rs, outs=outs, stream=stream)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = {"rotations": len(rs), "ms_per_set": round(el / reps * 1e3, 3),
+                     "rotations_per_s": round(reps * len(rs) / el, 1)}
+        del outs
+    ctx.close()
+    return out
 
 
 # ---------------------------------------------------------------- layers
@@ -406,7 +436,10 @@ def main():
         "roofline": roof,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in kern.items()},
     }
-    sections = [] if args.only_headline else ([args.only] if args.only else ["layers", "batched", "serving"])
+    sections = [] if args.only_headline else ([args.only] if args.only else ["hoisted", "layers", "batched", "serving"])
+    if "hoisted" in sections:
+        log("hoisted rotation sets (8 and 49 rotations per ModUp)")
+        result["hoisted"] = hoisted_sets()
     if "layers" in sections:
         log("layer latencies")
         result["layers"] = layer_latencies()

@@ -149,7 +149,8 @@ size_t he_key_bytes(const he_ctx* ctx); /* bytes of one key */
 /* In-place negacyclic NTT (inverse = 0) or iNTT (inverse = 1, includes N^-1)
  * of n_limbs consecutive limbs at `poly` ([n_limbs][N], device), limb t taken
  * modulo modulus index first_limb + t.  Moduli indices beyond L-1 address
- * the special primes. */
+ * the special primes.  Inputs must be canonical residues (in [0, q)); so are
+ * the outputs. */
 int he_ntt(he_ctx* ctx, uint64_t* poly, int n_limbs, int first_limb, int inverse, he_stream stream);
 
 /* Slot rotation Rot_r (slot i <- slot i + r), the paper's rotation

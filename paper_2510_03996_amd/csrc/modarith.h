@@ -95,6 +95,19 @@ HE_HD double mul_f64_c(double a, double w, double wq, double q) {
   return fma(-quot, q, hi) + lo;
 }
 HE_HD double centre_f64(double x, double qinv, double q) { return fma(-rint(x * qinv), q, x); }
+HE_HD double bits_to_f64(uint64_t b) {
+  double d;
+  __builtin_memcpy(&d, &b, 8);
+  return d;
+}
+HE_HD uint64_t f64_to_bits(double d) {
+  uint64_t b;
+  __builtin_memcpy(&b, &d, 8);
+  return b;
+}
+// Exact conversions of integers below 2^52: x is the low mantissa of 2^52 + x.
+HE_HD double u52_to_f64(uint64_t x) { return bits_to_f64(x | 0x4330000000000000ull) - 4503599627370496.0; }
+HE_HD uint64_t f64_to_u52(double v) { return f64_to_bits(v + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull; }
 // canonical representative in [0, q) of an integer-valued |x| <= 8q
 HE_HD double canon_f64(double x, double qinv, double q) {
   double r = fma(-floor(x * qinv), q, x);

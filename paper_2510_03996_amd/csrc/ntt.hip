@@ -63,9 +63,12 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
   const int wg = blockIdx.x;
   const int limb = blockIdx.y;
   const int tid = threadIdx.x;
-  const int m = map.mod[limb];
-  const uint64_t* ain = src + blockIdx.z * src_bs + (size_t)map.pos[limb] * P::N;
-  uint64_t* a = data + blockIdx.z * batch_stride + (size_t)map.pos[limb] * P::N;
+  // block-uniform: keep the limb's modulus and position (and so every base
+  // address) in scalar registers, so loads and stores use 32-bit lane offsets
+  const int m = __builtin_amdgcn_readfirstlane(map.mod[limb]);
+  const int pos = __builtin_amdgcn_readfirstlane(map.pos[limb]);
+  const uint64_t* ain = src + blockIdx.z * src_bs + (size_t)pos * P::N;
+  uint64_t* a = data + blockIdx.z * batch_stride + (size_t)pos * P::N;
   const ModInfo mi = mods[m];
   const uint64_t q = mi.q;
   if (mi.k <= 50) {
@@ -74,11 +77,11 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
     const double* dtw = dtw_all + (size_t)m * P::N;
     const double* dtwq = dtwq_all + (size_t)m * P::N;
     const double dq = (double)q, dqinv = mi.dqinv;
-    // inputs: canonical residues, or the signed intermediate of the other pass
+    // inputs: canonical residues, or the raw intermediate of the other pass
     for (int e = tid; e < P::TILE; e += P::THREADS) {
       int g, k;
       P::tile_elem(e, g, k);
-      dl[P::lidx(g, k)] = (double)(int64_t)ain[P::gidx(wg, g, k)];
+      dl[P::lidx(g, k)] = P::load_f64(ain[P::gidx(wg, g, k)]);
     }
     __syncthreads();
     if (!INV) rounds_fwd<P, 0>(dl, tid, wg, dtw, dtwq, dq, dqinv);
@@ -88,7 +91,7 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
       int g, k;
       P::tile_elem(e, g, k);
       ntt_store<EPI, LOGN>(a, P::gidx(wg, g, k), P::finish_f64(dl[P::lidx(g, k)], mi.dninv, mi.dninvq, dq, dqinv),
-                           epi, map.pos[limb], blockIdx.z, q);
+                           epi, pos, blockIdx.z, q);
     }
     return;
   }
@@ -107,7 +110,7 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
     int g, k;
     P::tile_elem(e, g, k);
     ntt_store<EPI, LOGN>(a, P::gidx(wg, g, k), P::finish(lds[P::lidx(g, k)], mi.ninv, mi.ninv_p, q), epi,
-                         map.pos[limb], blockIdx.z, q);
+                         pos, blockIdx.z, q);
   }
 }
 

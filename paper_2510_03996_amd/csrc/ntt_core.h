@@ -181,14 +181,18 @@ struct NttPass {
     }
   }
 
-  // FP64 value written back after the pass: the intermediate (forward pass 1,
-  // inverse pass 2) is the signed integer itself (two's complement, read back
-  // by the other pass only); the forward transform canonicalises after pass 2,
-  // the inverse multiplies by N^{-1} and canonicalises after pass 1.
+  // FP64 path between the passes: the intermediate (written by forward pass 1
+  // and inverse pass 2, read only by the other pass of the same transform)
+  // is kept as raw double bits; the transform's own input and output are
+  // canonical residues (< 2^50), converted exactly through the mantissa.
+  static constexpr bool IN_RAW = (!INV && PASS == 2) || (INV && PASS == 1);
+  HE_HD static double load_f64(uint64_t w) { return IN_RAW ? bits_to_f64(w) : u52_to_f64(w); }
+  // the forward transform canonicalises after pass 2, the inverse multiplies
+  // by N^{-1} and canonicalises after pass 1
   HE_HD static uint64_t finish_f64(double v, double ninv, double ninvq, double q, double qinv) {
-    if (!INV && PASS == 2) return (uint64_t)canon_f64(v, qinv, q);
-    if (INV && PASS == 1) return (uint64_t)canon_f64(mul_f64_c(v, ninv, ninvq, q), qinv, q);
-    return (uint64_t)(int64_t)v;
+    if (!INV && PASS == 2) return f64_to_u52(canon_f64(v, qinv, q));
+    if (INV && PASS == 1) return f64_to_u52(canon_f64(mul_f64_c(v, ninv, ninvq, q), qinv, q));
+    return f64_to_bits(v);
   }
 
   // Value written back to HBM after the pass: the forward transform leaves

@@ -17,7 +17,11 @@ Written from the paper's section "Secure Neural Network Layers":
   * average pooling sums the window rotations and multiplies by 1/k^2, then
     strides; global average pooling sums each W^2 block and merges the
     channels; the fully connected layer multiplies by each weight row, sums
-    n slots and consolidates the m outputs with rotations.
+    n slots and consolidates the m outputs with rotations;
+  * the secure ReLU (section "Activation Function (Secure ReLU)" and its
+    algorithm) scales the input by 1/beta with a mask when beta > 1 and
+    evaluates the degree-D Chebyshev interpolant of f(z) = beta max(0, z)
+    on [-1, 1] (D = 59 by default).
 The exact rotation amounts, mask contents and rescale placement are this
 project's pinned reading (the paper leaves them open); the GPU library
 implements the same schedule independently.
@@ -35,6 +39,9 @@ import numpy as np
 # projection of |x| on Legendre P0, P2, P4 gives 15/128 + 105/64 x^2 - 105/128 x^4,
 # and max(0, x) = (|x| + x) / 2.
 RELU4 = {0: 15.0 / 256.0, 1: 0.5, 2: 105.0 / 128.0, 4: -105.0 / 256.0}
+
+
+CHEB_DEGREE = 59  # the paper's default Chebyshev degree for the secure ReLU
 
 
 # ===================================================================== FP64 references
@@ -628,3 +635,103 @@ def relu_poly4(ev, x, delta):
     lin = ev.rescale(ev.mul_const(ev.drop(x, v.level + 1), RELU4[1], sigma))
     lin = ev.with_scale(lin, v.scale)
     return ev.add_const(ev.add(v, lin), RELU4[0])
+
+
+# ===================================================================== Chebyshev secure ReLU
+def cheb_relu_coeffs(beta, degree=CHEB_DEGREE):
+    """Chebyshev interpolant of f(z) = beta max(0, z) on [-1, 1] (the secure
+    ReLU's function after the 1/beta input scaling): with the degree + 1
+    nodes of the first kind z_k = cos(pi (k + 1/2) / (degree + 1)), the
+    coefficients are c_j = 2 / (degree + 1) sum_k f(z_k) T_j(z_k) and
+    f ~ c_0 / 2 + sum_{j >= 1} c_j T_j.  (The paper prints the node set
+    garbled; these are the roots of T_{degree+1}, the standard choice.)
+    f = beta z / 2 + beta |z| / 2: the odd part is interpolated exactly by
+    T_1 and the even part only has even terms on the symmetric nodes, so
+    c_1 = beta / 2 and every other odd coefficient is exactly zero."""
+    n = degree + 1
+    theta = np.pi * (np.arange(n) + 0.5) / n
+    fz = beta * np.maximum(0.0, np.cos(theta))
+    c = np.array([2.0 / n * float(np.sum(fz * np.cos(j * theta))) for j in range(n)])
+    c[1::2] = 0.0
+    if degree >= 1:
+        c[1] = beta / 2.0
+    return c
+
+
+def cheb_relu_ref(x, beta, degree=CHEB_DEGREE):
+    """FP64 value of the secure ReLU's polynomial at x: beta p(x / beta) with
+    p the interpolant above divided by beta, i.e. chebval(x / beta) of the
+    coefficients (c_0 halved)."""
+    c = cheb_relu_coeffs(beta, degree).copy()
+    c[0] /= 2.0
+    return np.polynomial.chebyshev.chebval(np.asarray(x) / beta, c)
+
+
+def cheb_terms(coeffs):
+    """Chebyshev indices j >= 1 the evaluation computes, ascending: every j
+    with c_j != 0 and, recursively, the factors of T_j's product rule
+    (T_{2k} = 2 T_k^2 - 1, T_{2k+1} = 2 T_k T_{k+1} - T_1)."""
+    need = set()
+    stack = [1] + [j for j in range(1, len(coeffs)) if coeffs[j] != 0.0]
+    while stack:
+        j = stack.pop()
+        if j in need:
+            continue
+        need.add(j)
+        if j >= 2:
+            stack.extend((j // 2,) if j % 2 == 0 else ((j - 1) // 2, (j + 1) // 2))
+    return sorted(need)
+
+
+def cheb_depth(j):
+    """Multiplicative depth of T_j in the product tree (T_1: 0)."""
+    return (j - 1).bit_length()
+
+
+def cheb_plan(coeffs, masked):
+    """(levels consumed, relinearizations) of cheb_eval."""
+    terms = cheb_terms(coeffs)
+    return int(masked) + max(cheb_depth(j) for j in terms) + 1, len(terms) - 1
+
+
+def cheb_lift(ev, v, level, scale, c):
+    """c v brought to `level` with tracked scale `scale`: drop v to level + 1,
+    multiply by c encoded at sigma = scale q / s_v (q the prime the rescale
+    divides by), rescale, and record `scale` (the product's scale up to the
+    rounding of sigma)."""
+    q = ev.modulus(level)
+    t = ev.rescale(ev.mul_const(ev.drop(v, level + 1), c, scale * q / v.scale))
+    return ev.with_scale(t, scale)
+
+
+def cheb_eval(ev, x, coeffs, mask_pt, delta):
+    """Secure ReLU (the paper's algorithm): v = RS(x * mask) when a 1/beta
+    scale mask is given (beta > 1), else v = x; then sum_j c_j T_j(v) + c_0/2.
+    T_j for j in cheb_terms, ascending: the factors are aligned to the lower
+    level, prod = RS(Relin(T_a T_b)), T_j = prod + prod - 1 (j even) or
+    prod + prod + lift(v, -1) (j odd).  Every term c_j T_j is a lift onto one
+    common level (one below the deepest T_j) and scale delta; the terms are
+    added in ascending j and c_0 / 2 is added last."""
+    v = ev.rescale(ev.mul_plain(x, mask_pt)) if mask_pt is not None else x
+    T = {1: v}
+    for j in cheb_terms(coeffs)[1:]:
+        a, b = (j // 2, j // 2) if j % 2 == 0 else ((j - 1) // 2, (j + 1) // 2)
+        lv = min(T[a].level, T[b].level)
+        p = ev.rescale(ev.mul_relin(ev.drop(T[a], lv), ev.drop(T[b], lv)))
+        p2 = ev.add(p, p)
+        T[j] = ev.add_const(p2, -1.0) if j % 2 == 0 else ev.add(p2, cheb_lift(ev, v, p2.level, p2.scale, -1.0))
+    lt = min(t.level for t in T.values()) - 1
+    acc = None
+    for j in sorted(T):
+        if coeffs[j] == 0.0:
+            continue
+        term = cheb_lift(ev, T[j], lt, delta, coeffs[j])
+        acc = term if acc is None else ev.add(acc, term)
+    return ev.add_const(acc, coeffs[0] / 2.0)
+
+
+def cheb_scale_mask(beta, n, slots):
+    """GenerateScaleMask(beta, n): 1/beta on the first n slots, 0 elsewhere."""
+    m = np.zeros(slots)
+    m[:n] = 1.0 / beta
+    return m

@@ -259,9 +259,16 @@ def layer_latencies(reps=3):
     ctf = synthetic_ct(c2, 16, 39, sc)
     fr, fmk = synthetic_pts(c2, 10, 16, 40, sc), synthetic_pts(c2, 1, 16, 41, sc)
     out["resnet_fc_64x10_n16_ms"] = round(timed(lambda: c2.fc(ctf, 64, 10, fr, fmk, stream=s), reps, s) * 1e3, 3)
+    # the paper's secure ReLU: degree-59 Chebyshev interpolant, beta = 4 scale mask
+    upload_synthetic_keys(c2, [], 42, relin=True)
+    cheb = he.cheb_relu_coeffs(4.0, 59)
+    ctr = synthetic_ct(c2, 24, 43, sc)
+    rmask = synthetic_pts(c2, 1, 24, 44, sc)[0]
+    out["relu_cheb59_n16_ms"] = round(timed(lambda: c2.cheb(ctr, cheb, sc, scale_mask=rmask, stream=s), reps, s) * 1e3, 3)
     out["key_switches"] = {"conv3x3_n12": 8, "lenet5_stack": pc.key_switches + pp.key_switches + 2,
                            "resnet_convA": pa.key_switches, "resnet_convB": pb.key_switches,
-                           "resnet_gap": pg.key_switches, "resnet_fc": pf.key_switches}
+                           "resnet_gap": pg.key_switches, "resnet_fc": pf.key_switches,
+                           "relu_cheb59": he.cheb_plan(cheb, True)[1]}
     c2.close()
     return out
 

@@ -280,6 +280,33 @@ int he_fc(he_ctx* ctx, const he_ct* in, int n_in, int n_out, const he_pt* weight
  * fit of max(0, x) on [-1, 1] this is the LeNet-5-shaped stack's ReLU. */
 int he_poly4(he_ctx* ctx, const he_ct* in, const double* c, double delta, he_ct* out, he_stream stream);
 
+/* Secure ReLU by Chebyshev interpolation (section "Activation Function
+ * (Secure ReLU)" and its algorithm): with a scale mask (1/beta on the n used
+ * slots, encoded by the caller at scale delta; NULL when beta <= 1) the
+ * input is first multiplied by it and rescaled; then
+ *   y = c_0 / 2 + sum_{j=1..degree} c_j T_j(v)
+ * is evaluated.  T_j are built by the product rule T_{2k} = 2 T_k^2 - 1,
+ * T_{2k+1} = 2 T_k T_{k+1} - T_1 (only the terms with nonzero coefficients
+ * and their factors, each product relinearized and rescaled); every term
+ * c_j T_j is brought to one common level with tracked scale delta by a
+ * constant multiplication encoded at delta q / scale(T_j), and c_0 / 2 is
+ * added last.  Levels consumed and relinearizations: he_cheb_plan.  out
+ * gets level in->level - levels, scale delta.  HE_ELEVEL without enough
+ * levels, HE_ENOKEY without the relinearization key, HE_EINVAL for a degree
+ * outside [1, HE_CHEB_MAX_DEGREE] or when every c_j (j >= 1) is zero. */
+#define HE_CHEB_MAX_DEGREE 255
+int he_cheb(he_ctx* ctx, const he_ct* in, const he_pt* scale_mask, const double* coeffs, int degree, double delta,
+            he_ct* out, he_stream stream);
+/* Levels consumed and relinearizations of he_cheb for these coefficients
+ * (host only). */
+int he_cheb_plan(const double* coeffs, int degree, int masked, int32_t* levels, int32_t* relins);
+/* Coefficients c_0..c_degree of the Chebyshev interpolant of
+ * f(z) = beta max(0, z) on [-1, 1] at the degree + 1 first-kind nodes
+ * cos(pi (k + 1/2) / (degree + 1)) (f ~ c_0 / 2 + sum c_j T_j); c_1 = beta/2
+ * and the other odd coefficients are exactly 0.  The paper's default
+ * degree is 59.  Host only; `coeffs` holds degree + 1 doubles. */
+int he_cheb_relu_coeffs(double beta, int degree, double* coeffs);
+
 /* ------------------------------------------------------------ batching
  * Many ciphertexts, each with its own hoisted rotation set and its own
  * number of outputs:

@@ -427,6 +427,56 @@ static int fc_plan_impl(int n_in, int n_out, he_layer_plan* pl) {
   return HE_OK;
 }
 
+// ---------------------------------------------------------------- Chebyshev secure ReLU
+// Terms T_j (j >= 1) the evaluation computes, ascending: every j with a
+// nonzero coefficient and, recursively, the factors of the product rule
+// T_{2k} = 2 T_k^2 - 1, T_{2k+1} = 2 T_k T_{k+1} - T_1.
+static std::vector<int> cheb_terms(const double* cf, int degree) {
+  std::vector<char> need(degree + 1, 0);
+  std::vector<int> stack{1};
+  for (int j = 1; j <= degree; j++)
+    if (cf[j] != 0.0) stack.push_back(j);
+  while (!stack.empty()) {
+    const int j = stack.back();
+    stack.pop_back();
+    if (need[j]) continue;
+    need[j] = 1;
+    if (j >= 2) {
+      stack.push_back(j / 2);
+      if (j % 2) stack.push_back(j / 2 + 1);
+    }
+  }
+  std::vector<int> out;
+  for (int j = 1; j <= degree; j++)
+    if (need[j]) out.push_back(j);
+  return out;
+}
+static int cheb_depth(int j) { return j <= 1 ? 0 : 32 - __builtin_clz((unsigned)(j - 1)); }
+
+static int cheb_plan_impl(const double* cf, int degree, int masked, int* levels, int* relins) {
+  if (!cf || degree < 1 || degree > HE_CHEB_MAX_DEGREE) return set_error(HE_EINVAL, "degree must be in [1, 255]");
+  bool any = false;
+  for (int j = 1; j <= degree; j++) any = any || cf[j] != 0.0;
+  if (!any) return set_error(HE_EINVAL, "every coefficient of degree >= 1 is zero");
+  const std::vector<int> t = cheb_terms(cf, degree);
+  int depth = 0;
+  for (int j : t) depth = std::max(depth, cheb_depth(j));
+  *levels = (masked ? 1 : 0) + depth + 1;
+  *relins = (int)t.size() - 1;
+  return HE_OK;
+}
+
+// c v at `level` with tracked scale `scale`: v dropped to level + 1, times c
+// encoded at sigma = scale q / s_v (q the prime the rescale divides by),
+// rescaled; the tracked scale is set to `scale` (the product's, up to the
+// rounding of sigma).
+static he_ct cheb_lift(Ev& ev, const he_ct& v, int level, double scale, double c) {
+  const double q = (double)ev.c->mod[level];
+  he_ct t = ev.rescale_take(ev.mul_const(Ev::drop(v, level + 1), c, scale * q / v.scale));
+  t.scale = scale;
+  return t;
+}
+
 }  // namespace he
 
 using namespace he;
@@ -574,6 +624,93 @@ int he_poly4(he_ctx* h, const he_ct* in, const double* cf, double delta, he_ct* 
     lin.scale = v.scale;
     he_ct p = ev.add_const(ev.add(v, lin), cf[0]);
     ev.copy_out(p, out);
+    return HE_OK;
+  });
+}
+
+int he_cheb_relu_coeffs(double beta, int degree, double* cf) {
+  if (!cf || degree < 1 || degree > HE_CHEB_MAX_DEGREE || !(beta > 0.0))
+    return set_error(HE_EINVAL, "need beta > 0 and degree in [1, 255]");
+  const int n = degree + 1;
+  const double pi = 3.14159265358979323846;
+  for (int j = 0; j < n; j++) {
+    double acc = 0.0;
+    for (int k = 0; k < n; k++) {
+      const double th = pi * (k + 0.5) / n;
+      acc += beta * std::max(0.0, std::cos(th)) * std::cos(j * th);
+    }
+    cf[j] = 2.0 / n * acc;
+  }
+  // f = beta z / 2 + beta |z| / 2: the odd part is exactly beta T_1 / 2
+  for (int j = 1; j < n; j += 2) cf[j] = 0.0;
+  cf[1] = beta / 2.0;
+  return HE_OK;
+}
+
+int he_cheb_plan(const double* coeffs, int degree, int masked, int32_t* levels, int32_t* relins) {
+  if (!levels || !relins) return set_error(HE_EINVAL, "null argument");
+  int l = 0, r = 0;
+  int rc = cheb_plan_impl(coeffs, degree, masked, &l, &r);
+  if (rc) return rc;
+  *levels = l;
+  *relins = r;
+  return HE_OK;
+}
+
+int he_cheb(he_ctx* h, const he_ct* in, const he_pt* scale_mask, const double* cf, int degree, double delta,
+            he_ct* out, he_stream s) {
+  if (!h || !cf) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  int rc, levels = 0, relins = 0;
+  if ((rc = check_ct(c, in, "in"))) return rc;
+  if ((rc = cheb_plan_impl(cf, degree, scale_mask != nullptr, &levels, &relins))) return rc;
+  if (in->level <= levels)
+    return set_error(HE_ELEVEL, "the Chebyshev evaluation needs " + std::to_string(levels) + " levels");
+  if (scale_mask && (rc = check_pts(c, scale_mask, 1, in->level, "scale_mask"))) return rc;
+  if ((rc = check_out(c, out, in->level - levels))) return rc;
+  if (!find_key(c, HE_KEY_RELIN)) return set_error(HE_ENOKEY, "relinearization key not resident");
+  const std::vector<int> terms = cheb_terms(cf, degree);
+  return guarded([&] {
+    Ev ev(h, s);
+    const he_ct v = scale_mask ? ev.rescale_take(ev.mul(*in, *scale_mask)) : *in;
+    std::vector<he_ct> T(degree + 1);
+    std::vector<char> have(degree + 1, 0);
+    T[1] = v;
+    have[1] = 1;
+    for (size_t t = 1; t < terms.size(); t++) {
+      const int j = terms[t];
+      const int a = j / 2, b = j - j / 2;
+      const int lv = std::min(T[a].level, T[b].level);
+      he_ct p = ev.rescale_take(ev.mul_relin(Ev::drop(T[a], lv), Ev::drop(T[b], lv)));
+      he_ct p2 = ev.add(p, p);
+      ev.release(p);
+      if (j % 2 == 0) {
+        T[j] = ev.add_const(p2, -1.0);
+      } else {
+        he_ct l = cheb_lift(ev, v, p2.level, p2.scale, -1.0);
+        T[j] = ev.add(p2, l);
+        ev.release(l);
+      }
+      ev.release(p2);
+      have[j] = 1;
+    }
+    int lt = T[1].level;
+    for (int j : terms) lt = std::min(lt, T[j].level);
+    lt -= 1;
+    he_ct acc{};
+    bool first = true;
+    for (int j : terms) {
+      if (cf[j] == 0.0) continue;
+      he_ct term = cheb_lift(ev, T[j], lt, delta, cf[j]);
+      if (first) {
+        acc = term;
+        first = false;
+      } else {
+        acc = ev.add_take(acc, term);
+      }
+    }
+    he_ct y = ev.add_const(acc, cf[0] / 2.0);
+    ev.copy_out(y, out);
     return HE_OK;
   });
 }

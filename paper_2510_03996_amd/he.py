@@ -122,6 +122,9 @@ def lib():
             "he_fc_plan": [vp, c_int, c_int, P(he_layer_plan)],
             "he_fc": [vp, P(he_ct), c_int, c_int, P(he_pt), P(he_pt), P(he_pt), P(he_ct), vp],
             "he_poly4": [vp, P(he_ct), P(ctypes.c_double), ctypes.c_double, P(he_ct), vp],
+            "he_cheb": [vp, P(he_ct), P(he_pt), P(ctypes.c_double), c_int, ctypes.c_double, P(he_ct), vp],
+            "he_cheb_plan": [P(ctypes.c_double), c_int, c_int, P(i32), P(i32)],
+            "he_cheb_relu_coeffs": [ctypes.c_double, c_int, P(ctypes.c_double)],
             "he_batch_create": [vp, P(he_batch_desc), c_int, P(vp)],
             "he_batch_run": [vp, vp],
             "he_batch_run_plain": [vp, vp],
@@ -425,6 +428,18 @@ class Context:
         out.update(o)
         return out
 
+    def cheb(self, ct, coeffs, delta, scale_mask=None, out=None, stream=None):
+        """Secure ReLU / Chebyshev series (he_cheb); coeffs = c_0..c_D."""
+        levels, _ = cheb_plan(coeffs, scale_mask is not None)
+        out = out or self.new_ct(max(ct.level - levels, 1))
+        a, o = ct.c(), out.c()
+        cf = (ctypes.c_double * len(coeffs))(*[float(x) for x in coeffs])
+        m = ctypes.byref(scale_mask.c()) if scale_mask is not None else None
+        _check(lib().he_cheb(self.h, ctypes.byref(a), m, cf, len(coeffs) - 1, float(delta), ctypes.byref(o),
+                             _stream(stream)))
+        out.update(o)
+        return out
+
     def ntt_tuning(self):
         nv = NTT_VARIANTS
         var = (ctypes.c_int32 * 4)()
@@ -467,6 +482,21 @@ class Context:
         buf = ctypes.create_string_buffer(1 << 16)
         n = _check(lib().he_profile_end(self.h, buf, len(buf)))
         return json.loads(buf.value[:n].decode())
+
+
+def cheb_plan(coeffs, masked):
+    """(levels consumed, relinearizations) of Context.cheb (host only)."""
+    cf = (ctypes.c_double * len(coeffs))(*[float(x) for x in coeffs])
+    lv, rl = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().he_cheb_plan(cf, len(coeffs) - 1, 1 if masked else 0, ctypes.byref(lv), ctypes.byref(rl)))
+    return lv.value, rl.value
+
+
+def cheb_relu_coeffs(beta, degree=59):
+    """Chebyshev interpolation coefficients of beta max(0, z) on [-1, 1] (host only)."""
+    cf = (ctypes.c_double * (degree + 1))()
+    _check(lib().he_cheb_relu_coeffs(float(beta), int(degree), cf))
+    return list(cf)
 
 
 class Batch:

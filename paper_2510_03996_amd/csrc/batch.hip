@@ -235,7 +235,8 @@ static int run_batched(Batch* b, hipStream_t s) {
   {
     const BConvSet& set = c->modup[l];
     ProfScope ps(c, "bconv_modup", s, 8.0 * N * b->B * (l + (double)set.count * set.max_out),
-                 (double)N * b->B * l * (1 + set.max_out));
+                 (double)N * b->B * l * (1 + set.max_out),
+                 bconv_ideal_s((double)N, (double)b->B * set.count, c->alpha, set.max_out));
     dim3 grid(N / 128, bconv_tiles_y(set), b->B * set.count);
     k_bconv<<<grid, 256, 0, s>>>(b->coeff, ln, b->ext, E * N, set.d, set.count, c->d_mod, c->log_n);
     HE_HIP(hipGetLastError());
@@ -255,7 +256,8 @@ static int run_batched(Batch* b, hipStream_t s) {
     if ((rc = ntt_launch(c, b->u, E * N, z, range_map(l, K, L), true, s))) return rc;
     {
       const BConvSet& set = c->moddown[l];
-      ProfScope ps(c, "bconv_moddown", s, 8.0 * N * z * (K + l), (double)N * z * K * (1 + l));
+      ProfScope ps(c, "bconv_moddown", s, 8.0 * N * z * (K + l), (double)N * z * K * (1 + l),
+                   bconv_ideal_s((double)N, z, K, l));
       dim3 grid(N / 128, bconv_tiles_y(set), z);
       k_bconv<<<grid, 256, 0, s>>>(b->u, E * N, b->y, ln, set.d, 1, c->d_mod, c->log_n);
       HE_HIP(hipGetLastError());

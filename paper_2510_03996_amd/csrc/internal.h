@@ -30,7 +30,18 @@ struct ProfRec {
   const char* name;
   hipEvent_t a, b;
   double bytes, modmul;
+  double ideal_s;  // the launch's modular products at the ALU peak of their arithmetic
 };
+
+// ALU peaks of one modular product, from the unit counts (256 CUs x 4 SIMDs
+// x 16 lanes at 2.4 GHz = 39.3e12 full-rate lane operations per second):
+// an integer Shoup product (64-bit primes) is 10 32-bit multiplies, which
+// issue at half rate; a centred FP64 product (primes below 2^50) is 6 FP64
+// operations (mul, rint, mul, fma, fma, add), all full rate.
+constexpr double LANE_OPS_PER_S = 256.0 * 4 * 16 * 2.4e9;
+constexpr double PEAK_MODMUL_INT = LANE_OPS_PER_S / 2 / 10;  // 1.966e12 / s
+constexpr double PEAK_MODMUL_F64 = LANE_OPS_PER_S / 6;       // 6.554e12 / s
+constexpr double PEAK_INT8_OPS = 5.0e15;                      // dense int8 MFMA, ops / s
 
 // Per-stream execution lane: the key-switch workspace and the pool of
 // temporary ciphertext buffers used by work enqueued on one stream.  Work on
@@ -86,11 +97,14 @@ struct ProfScope {
   hipStream_t s;
   ProfRec r;
   bool on;
-  ProfScope(Ctx* c_, const char* name, hipStream_t s_, double bytes, double modmul) : c(c_), s(s_), on(c_->prof_on) {
+  // ideal_s < 0: every product priced as an integer Shoup product
+  ProfScope(Ctx* c_, const char* name, hipStream_t s_, double bytes, double modmul, double ideal_s = -1.0)
+      : c(c_), s(s_), on(c_->prof_on) {
     if (!on) return;
     r.name = name;
     r.bytes = bytes;
     r.modmul = modmul;
+    r.ideal_s = ideal_s >= 0.0 ? ideal_s : modmul / PEAK_MODMUL_INT;
     hipEventCreate(&r.a);
     hipEventCreate(&r.b);
     hipEventRecord(r.a, s);
@@ -176,6 +190,14 @@ int check_ct(const Ctx* c, const he_ct* x, const char* what);
 int check_out(const Ctx* c, const he_ct* x, int need_level);
 
 constexpr int BCONV_TILES_Y = 8;  // 4-output row tiles per basis-conversion workgroup
+// ALU-ideal time of `convs` basis conversions with nin inputs and nout
+// outputs over N coefficients: the int8 MFMA work the kernel issues (K = 16
+// per two input limbs, 32 rows per four outputs) at the int8 peak, plus the
+// nin Shoup products and nout Montgomery reductions per coefficient.
+inline double bconv_ideal_s(double N, double convs, int nin, int nout) {
+  const double mfma = 2.0 * N * (16.0 * ((nin + 1) / 2)) * (32.0 * ((nout + 3) / 4));
+  return convs * (mfma / PEAK_INT8_OPS + N * (nin + nout) / PEAK_MODMUL_INT);
+}
 inline int bconv_tiles_y(const BConvSet& s) { return ((s.max_out + 3) / 4 + BCONV_TILES_Y - 1) / BCONV_TILES_Y; }
 __global__ void k_bconv(const uint64_t* __restrict__ in, size_t in_bs, uint64_t* __restrict__ out, size_t out_bs,
                         const BConvDesc* __restrict__ descs, int zdiv, const ModInfo* __restrict__ mods, int logn);

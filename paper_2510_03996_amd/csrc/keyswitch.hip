@@ -119,7 +119,8 @@ int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) 
   const BConvSet& set = c->modup[level];
   {
     const double mm = (double)N * level * (1 + set.max_out);  // t_i products + MACs (upper bound)
-    ProfScope ps(c, "bconv_modup", s, 8.0 * N * (level + (double)set.count * set.max_out), mm);
+    ProfScope ps(c, "bconv_modup", s, 8.0 * N * (level + (double)set.count * set.max_out), mm,
+                 bconv_ideal_s((double)N, set.count, c->alpha, set.max_out));
     dim3 grid(N / 128, bconv_tiles_y(set), set.count);
     k_bconv<<<grid, 256, 0, s>>>(w.coeff, 0, w.ext, E * N, set.d, set.count, c->d_mod, c->log_n);
   }
@@ -145,7 +146,8 @@ int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t*
   if ((rc = ntt_launch(c, w.u, E * N, 2, range_map(level, K, L), true, s))) return rc;
   const BConvSet& set = c->moddown[level];
   {
-    ProfScope ps(c, "bconv_moddown", s, 16.0 * N * (K + level), 2.0 * N * K * (1 + level));
+    ProfScope ps(c, "bconv_moddown", s, 16.0 * N * (K + level), 2.0 * N * K * (1 + level),
+                 bconv_ideal_s((double)N, 2, K, level));
     dim3 grid(N / 128, bconv_tiles_y(set), 2);
     k_bconv<<<grid, 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, set.d, 1, c->d_mod, c->log_n);
   }

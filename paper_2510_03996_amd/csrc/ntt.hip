@@ -51,7 +51,8 @@ __device__ __forceinline__ void ntt_store(uint64_t* a, int k, uint64_t v, const 
   }
 }
 
-// grid: x = tile within limb, y = limb index in `map`, z = batch
+// grid: x = tile within limb, y = batch, z = limb index in `map` (so the
+// workgroups of one modulus are adjacent and share its twiddles in L2)
 template <int LOGN, int PASS, bool INV, int LOG_EPT, int LOG_TILE, bool EPI>
 __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREADS)) void ntt_pass_kernel(
     const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, LimbMap map,
@@ -60,15 +61,22 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
   static_assert(!EPI || (PASS == 2 && !INV), "the ModDown epilogue follows the last forward pass");
   using P = NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>;
   __shared__ uint64_t lds[P::LDS_WORDS];
-  const int wg = blockIdx.x;
-  const int limb = blockIdx.y;
+  // Workgroups are dispatched round-robin over the 8 XCDs by linear id; with
+  // WG_PER_LIMB a multiple of 8 the XCD is blockIdx.x mod 8.  A pass-1 tile
+  // reads short row segments, so give each XCD a contiguous run of column
+  // groups: neighbouring segments then meet in the same L2 instead of being
+  // fetched separately by two XCDs.
+  constexpr int W = P::WG_PER_LIMB;
+  const int wg = (PASS == 1 && W % 8 == 0) ? (int)(blockIdx.x % 8) * (W / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int limb = blockIdx.z;  // limb-major grid: the batch index varies faster
+  const int bz = blockIdx.y;
   const int tid = threadIdx.x;
   // block-uniform: keep the limb's modulus and position (and so every base
   // address) in scalar registers, so loads and stores use 32-bit lane offsets
   const int m = __builtin_amdgcn_readfirstlane(map.mod[limb]);
   const int pos = __builtin_amdgcn_readfirstlane(map.pos[limb]);
-  const uint64_t* ain = src + blockIdx.z * src_bs + (size_t)pos * P::N;
-  uint64_t* a = data + blockIdx.z * batch_stride + (size_t)pos * P::N;
+  const uint64_t* ain = src + bz * src_bs + (size_t)pos * P::N;
+  uint64_t* a = data + bz * batch_stride + (size_t)pos * P::N;
   const ModInfo mi = mods[m];
   const uint64_t q = mi.q;
   if (mi.k <= 50) {
@@ -91,7 +99,7 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
       int g, k;
       P::tile_elem(e, g, k);
       ntt_store<EPI, LOGN>(a, P::gidx(wg, g, k), P::finish_f64(dl[P::lidx(g, k)], mi.dninv, mi.dninvq, dq, dqinv),
-                           epi, pos, blockIdx.z, q);
+                           epi, pos, bz, q);
     }
     return;
   }
@@ -110,7 +118,7 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
     int g, k;
     P::tile_elem(e, g, k);
     ntt_store<EPI, LOGN>(a, P::gidx(wg, g, k), P::finish(lds[P::lidx(g, k)], mi.ninv, mi.ninv_p, q), epi,
-                         pos, blockIdx.z, q);
+                         pos, bz, q);
   }
 }
 
@@ -120,35 +128,42 @@ static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* da
   using P1 = NttPass<LOGN, 1, false, LOG_EPT, LOG_TILE>;
   using P2 = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
   constexpr int T = P1::THREADS;
-  dim3 g1(P1::WG_PER_LIMB, map.n, nbatch), g2(P2::WG_PER_LIMB, map.n, nbatch);
+  dim3 g1(P1::WG_PER_LIMB, nbatch, map.n), g2(P2::WG_PER_LIMB, nbatch, map.n);
   const double limbs = (double)map.n * nbatch, N = (double)P1::N;
   const double bytes = 16.0 * N * limbs;  // one read + one write of every residue per pass
   const double mm1 = N / 2 * P1::LM * limbs, mm2 = N / 2 * P2::LM * limbs;
+  // ALU-ideal time per modular product, by the arithmetic of each limb's prime
+  double per_mm = 0.0;
+  if (c->prof_on) {
+    int nf = 0;
+    for (int i = 0; i < map.n; i++) nf += c->hmod[map.mod[i]].k <= 50;
+    per_mm = ((double)nf / PEAK_MODMUL_F64 + (double)(map.n - nf) / PEAK_MODMUL_INT) / map.n;
+  }
   const NttEpi none{};
   if (!inverse) {
     {
-      ProfScope ps(c, "ntt_fwd_pass1", s, bytes, mm1);
+      ProfScope ps(c, "ntt_fwd_pass1", s, bytes, mm1, mm1 * per_mm);
       ntt_pass_kernel<LOGN, 1, false, LOG_EPT, LOG_TILE, false><<<g1, T, 0, s>>>(
           src, src_bs, data, batch_stride, map, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, none);
     }
     if (epi) {
       // + u read, out write instead of y write, add_0 / add_1 reads
       const double eb = bytes + 8.0 * N * limbs * (1 + (epi->add[0] ? 0.5 : 0) + (epi->add[1] ? 0.5 : 0));
-      ProfScope ps(c, "ntt_fwd_pass2_moddown", s, eb, mm2 + N * limbs);
+      ProfScope ps(c, "ntt_fwd_pass2_moddown", s, eb, mm2 + N * limbs, mm2 * per_mm + N * limbs / PEAK_MODMUL_INT);
       ntt_pass_kernel<LOGN, 2, false, LOG_EPT, LOG_TILE, true><<<g2, T, 0, s>>>(
           data, batch_stride, data, batch_stride, map, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, *epi);
     } else {
-      ProfScope ps(c, "ntt_fwd_pass2", s, bytes, mm2);
+      ProfScope ps(c, "ntt_fwd_pass2", s, bytes, mm2, mm2 * per_mm);
       ntt_pass_kernel<LOGN, 2, false, LOG_EPT, LOG_TILE, false><<<g2, T, 0, s>>>(
           data, batch_stride, data, batch_stride, map, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, none);
     }
   } else {
     {
-      ProfScope ps(c, "ntt_inv_pass2", s, bytes, mm2);
+      ProfScope ps(c, "ntt_inv_pass2", s, bytes, mm2, mm2 * per_mm);
       ntt_pass_kernel<LOGN, 2, true, LOG_EPT, LOG_TILE, false><<<g2, T, 0, s>>>(
           src, src_bs, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod, none);
     }
-    ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs);
+    ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs, (mm1 + N * limbs) * per_mm);
     ntt_pass_kernel<LOGN, 1, true, LOG_EPT, LOG_TILE, false><<<g1, T, 0, s>>>(
         data, batch_stride, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod, none);
   }
@@ -179,11 +194,28 @@ static int ntt_launch_var(Ctx* c, int var, const uint64_t* src, size_t src_bs, u
   }
 }
 
+// Limbs of one modulus are transformed back to back (the order of
+// independent limb transforms is free), so that its twiddle tables are
+// fetched once and then served from L2; the slower integer-path limbs (primes
+// of 51 bits and more) go first so that they do not form the launch's tail.
+static LimbMap by_modulus(const Ctx* c, const LimbMap& m) {
+  LimbMap r = m;
+  int idx[MAXJ];
+  for (int i = 0; i < m.n; i++) idx[i] = i;
+  auto key = [&](int i) { return (c->hmod[m.mod[i]].k <= 50 ? 256 : 0) + (int)m.mod[i]; };
+  std::stable_sort(idx, idx + m.n, [&](int a, int b) { return key(a) < key(b); });
+  for (int i = 0; i < m.n; i++) {
+    r.pos[i] = m.pos[idx[i]];
+    r.mod[i] = m.mod[idx[i]];
+  }
+  return r;
+}
+
 template <int LOGN>
 static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
                         int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr) {
-  return ntt_launch_var<LOGN>(c, c->ntt_var[ntt_bucket(map.n * nbatch)], src, src_bs, data, batch_stride, nbatch, map,
-                              inverse, s, epi);
+  return ntt_launch_var<LOGN>(c, c->ntt_var[ntt_bucket(map.n * nbatch)], src, src_bs, data, batch_stride, nbatch,
+                              by_modulus(c, map), inverse, s, epi);
 }
 
 template <int LOGN>

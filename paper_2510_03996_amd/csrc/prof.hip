@@ -22,7 +22,7 @@ int he_profile_end(he_ctx* h, char* out, size_t cap) {
   if (!h || !out || cap == 0) return set_error(HE_EINVAL, "null argument");
   Ctx* c = &h->c;
   c->prof_on = false;
-  struct Agg { long n = 0; double ms = 0, bytes = 0, modmul = 0; };
+  struct Agg { long n = 0; double ms = 0, bytes = 0, modmul = 0, ideal_ms = 0; };
   std::map<std::string, Agg> agg;
   for (auto& r : c->prof) {
     HE_HIP(hipEventSynchronize(r.b));
@@ -33,6 +33,7 @@ int he_profile_end(he_ctx* h, char* out, size_t cap) {
     a.ms += ms;
     a.bytes += r.bytes;
     a.modmul += r.modmul;
+    a.ideal_ms += r.ideal_s * 1e3;
     hipEventDestroy(r.a);
     hipEventDestroy(r.b);
   }
@@ -41,8 +42,10 @@ int he_profile_end(he_ctx* h, char* out, size_t cap) {
   bool first = true;
   for (auto& kv : agg) {
     char buf[512];
-    snprintf(buf, sizeof buf, "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"bytes\": %.0f, \"modmul\": %.0f}",
-             first ? "" : ", ", kv.first.c_str(), kv.second.n, kv.second.ms, kv.second.bytes, kv.second.modmul);
+    snprintf(buf, sizeof buf,
+             "%s\"%s\": {\"launches\": %ld, \"ms\": %.6f, \"bytes\": %.0f, \"modmul\": %.0f, \"ideal_ms\": %.6f}",
+             first ? "" : ", ", kv.first.c_str(), kv.second.n, kv.second.ms, kv.second.bytes, kv.second.modmul,
+             kv.second.ideal_ms);
     js += buf;
     first = false;
   }

@@ -348,16 +348,31 @@ def compaction(ev, v, fm, S, Ho, Wo, masks):
 
 
 # ===================================================================== convolution
-def conv_kind(k, padding):
-    if k == 3 and padding == 1:
+def conv_kind(k, padding, fm=None, F=1):
+    """special: 3x3, padding 1 on a dense square map that is replicated (or a
+    single channel in and out); generic: any padding 0 <= P <= (k-1)/2 (the
+    zero padding is realised by masking every tap whose neighbour falls
+    outside the image, so the output fits the input's layout)."""
+    if k == 3 and padding == 1 and (fm is None or (
+            fm.H == fm.W and fm.rs == fm.W and fm.cs == fm.W * fm.W and (fm.reps == 2 or (fm.C == 1 and F == 1)))):
         return "special"
-    if padding == 0:
+    if 0 <= padding <= (k - 1) // 2:
         return "generic"
-    raise NotImplementedError("padding by rotations is not part of the pinned schedules")
+    raise NotImplementedError("padding beyond (k-1)/2 is not part of the pinned schedules")
+
+
+def conv_taps(fm, k, padding):
+    """Rotation of every tap (i, j), row-major: (i - P) rs + (j - P)."""
+    return [(i - padding) * fm.rs + (j - padding) for i in range(k) for j in range(k)]
+
+
+def conv_dims(fm, k, padding):
+    """Stride-1 output size H + 2P - k + 1, W + 2P - k + 1."""
+    return fm.H + 2 * padding - k + 1, fm.W + 2 * padding - k + 1
 
 
 def conv_out_map(fm, F, k, stride, padding, slots):
-    kind = conv_kind(k, padding)
+    kind = conv_kind(k, padding, fm, F)
     if kind == "special":
         W = fm.W
         if stride == 1:
@@ -365,10 +380,10 @@ def conv_out_map(fm, F, k, stride, padding, slots):
             return FMap(F, W, W, W, W * W, reps)
         Ho = (W + 2 - 3) // stride + 1
         return FMap(F, Ho, Ho, Ho, Ho * Ho, 1)
-    H1, W1 = fm.H - k + 1, fm.W - k + 1
+    H1, W1 = conv_dims(fm, k, padding)
     if stride == 1:
         return FMap(F, H1, W1, fm.rs, fm.cs, 1)
-    Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+    Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
     return FMap(F, Ho, Wo, Wo, Ho * Wo, 1)
 
 
@@ -377,7 +392,7 @@ def conv_plaintexts(fm, K, stride, padding, slots):
     (and the GPU library) consumes them: kernel vectors [f][tap], then masks."""
     F, C, k, _ = K.shape
     assert C == fm.C
-    kind = conv_kind(k, padding)
+    kind = conv_kind(k, padding, fm, F)
     kern, masks = [], []
     if kind == "special":
         W = fm.W
@@ -401,15 +416,20 @@ def conv_plaintexts(fm, K, stride, padding, slots):
             Ho = (W - 1) // stride + 1
             masks += compaction_masks(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, 1.0, slots)
     else:
-        H1, W1 = fm.H - k + 1, fm.W - k + 1
+        # tap (i, j) at output (y, x) reads input (y + i - P, x + j - P): the
+        # kernel value where that neighbour is inside the image, 0 elsewhere
+        H1, W1 = conv_dims(fm, k, padding)
+        P = padding
         for f in range(F):
             for i in range(k):
                 for j in range(k):
                     v = np.zeros(slots)
+                    x0, x1 = max(0, P - j), min(W1, fm.W + P - j)
                     for c in range(C):
                         for y in range(H1):
-                            base = c * fm.cs + y * fm.rs
-                            v[base:base + W1] = K[f, c, i, j]
+                            if 0 <= y + i - P < fm.H and x0 < x1:
+                                base = c * fm.cs + y * fm.rs
+                                v[base + x0:base + x1] = K[f, c, i, j]
                     kern.append(v)
         if C > 1:
             m = np.zeros(slots)
@@ -417,14 +437,14 @@ def conv_plaintexts(fm, K, stride, padding, slots):
                 m[y * fm.rs:y * fm.rs + W1] = 1.0
             masks.append(m)
         if stride > 1:
-            Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+            Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
             masks += compaction_masks(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0, slots)
     return kern, masks
 
 
 def conv_rotations(fm, F, k, stride, padding, slots):
     """Distinct rotation keys the schedule uses (the paper's per-layer index helper)."""
-    kind = conv_kind(k, padding)
+    kind = conv_kind(k, padding, fm, F)
     keys = set()
     if kind == "special":
         W = fm.W
@@ -435,14 +455,14 @@ def conv_rotations(fm, F, k, stride, padding, slots):
             Ho = (W - 1) // stride + 1
             keys |= {key for _, _, key in compaction_plan(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho)}
     else:
-        keys |= {i * fm.rs + j for i in range(k) for j in range(k) if (i, j) != (0, 0)}
+        keys |= {r for r in conv_taps(fm, k, padding) if r != 0}
         if fm.C > 1:
             keys.add(fm.cs)
         if F > 1:
             keys.add(-fm.cs)
         if stride > 1:
-            H1, W1 = fm.H - k + 1, fm.W - k + 1
-            Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+            H1, W1 = conv_dims(fm, k, padding)
+            Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
             keys |= {key for _, _, key in compaction_plan(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo)}
     return sorted(keys)
 
@@ -456,12 +476,13 @@ def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots):
       C > 1 (replicated input): S_f = A_f + Rot_{W^2}(A_f) + ... chained with
       the single key W^2 (C-1 key switches); Y = RS(sum_f S_f (.) blockmask_f);
       stride > 1: joint compaction of all channels.
-    generic (P=0): one hoisted group of the k^2-1 offsets i rs + j;
-      A_f = RS(sum r (.) kv); C > 1: channel chain with key cs, then
+    generic (0 <= P <= (k-1)/2): one hoisted group of the nonzero tap offsets
+      (i - P) rs + (j - P); kernel vectors zero where a tap's neighbour lies
+      in the padding; A_f = RS(sum r (.) kv); C > 1: channel chain with key cs, then
       RS(. (.) block-0 mask); out-channels placed by a Horner chain with key
       -cs; stride > 1: joint compaction.
     """
-    kind = conv_kind(k, padding)
+    kind = conv_kind(k, padding, fm, F)
     C = fm.C
     if kind == "special":
         W = fm.W
@@ -494,9 +515,9 @@ def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots):
         Ho = (W - 1) // stride + 1
         return compaction(ev, y, FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, masks[mpos:])
     # generic
-    offs = [i * fm.rs + j for i in range(k) for j in range(k)]
-    rot = ev.rot_hoisted(x, offs[1:])
-    taps = [x] + rot
+    offs = conv_taps(fm, k, padding)
+    rot = iter(ev.rot_hoisted(x, [r for r in offs if r != 0]))
+    taps = [x if r == 0 else next(rot) for r in offs]
     sums = []
     for f in range(F):
         A = ev.rescale(mac(ev, taps, kern[k * k * f:k * k * (f + 1)]))
@@ -519,10 +540,10 @@ def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots):
         y = acc
     else:
         y = sums[0]
-    H1, W1 = fm.H - k + 1, fm.W - k + 1
+    H1, W1 = conv_dims(fm, k, padding)
     if stride == 1:
         return y, FMap(F, H1, W1, fm.rs, fm.cs, 1)
-    Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
+    Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
     return compaction(ev, y, FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks[mpos:])
 
 

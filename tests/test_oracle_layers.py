@@ -139,6 +139,41 @@ def test_sim_generic_conv_multichannel_stride():
     assert np.max(np.abs(LY.unpack(y.v, fo) - LY.conv2d_ref(X, K, 2, 0))) < 1e-12
 
 
+@pytest.mark.parametrize("C,F,HW,k,S,P", [
+    (2, 3, 12, 5, 1, 2),   # 5x5 "same" padding
+    (3, 2, 16, 7, 2, 3),   # the ResNet-34 stem shape 7x7 / s2 / p3
+    (2, 2, 12, 3, 1, 1),   # 3x3 / p1 on a non-replicated multi-channel map
+    (3, 4, 12, 3, 2, 1),
+    (1, 1, 10, 5, 2, 1),   # padding below (k-1)/2
+    (2, 2, 9, 1, 1, 0),    # 1x1
+])
+def test_sim_generic_conv_with_padding(C, F, HW, k, S, P):
+    """Zero padding by masked taps equals the FP64 convolution with padding P."""
+    slots = 4096
+    X = synth.image(7, C, HW, HW)
+    K = synth.conv_weights(7, F, C, k, 0.2)
+    fm = LY.FMap(C, HW, HW)
+    assert LY.conv_kind(k, P, fm, F) == "generic"
+    kern, masks = LY.conv_plaintexts(fm, K, S, P, slots)
+    ev = sim(slots)
+    y, fo = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 12), fm, F, k, S, P, kern, masks, slots)
+    Ho = (HW + 2 * P - k) // S + 1
+    assert (fo.C, fo.H, fo.W) == (F, Ho, Ho) and fo == LY.conv_out_map(fm, F, k, S, P, slots)
+    assert np.max(np.abs(LY.unpack(y.v, fo) - LY.conv2d_ref(X, K, S, P))) < 1e-12
+    # rotations: k^2 - 1 taps, C - 1 per out-channel for the channel sum, F - 1 placements, compaction
+    taps = k * k - 1
+    assert ev.ks >= taps + F * (C - 1) + (F - 1 if F > 1 else 0)
+    keys = LY.conv_rotations(fm, F, k, S, P, slots)
+    assert {(i - P) * HW + (j - P) for i in range(k) for j in range(k)} - {0} <= set(keys)
+
+
+def test_padding_beyond_half_kernel_is_rejected():
+    with pytest.raises(NotImplementedError):
+        LY.conv_kind(3, 2)
+    with pytest.raises(NotImplementedError):
+        LY.conv_kind(5, 3, LY.FMap(1, 8, 8))
+
+
 # ------------------------------------------------------------------ encrypted (oracle CKKS)
 def he_eval(name, rots, relin=False):
     ctx, sk, pk = H.oracle_ctx(name)
@@ -186,6 +221,23 @@ def test_he_config1_stack_decrypts_to_fp64():
     ref = LY.avgpool_ref(LY.relu4_ref(LY.conv2d_ref(X, K, 1, 0)), 2, 2)
     err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, z), f2) - ref))
     assert err < 1e-2, err
+
+
+def test_he_config1_padded_conv_decrypts():
+    """7x7 / stride 2 / padding 3 on 3 x 16 x 16 (C=3 -> F=2) at N=2^14."""
+    name = "config1"
+    ctx1, _, _ = H.oracle_ctx(name)
+    slots = ctx1.n // 2
+    X = synth.image(12, 3, 16, 16)
+    K = synth.conv_weights(12, 2, 3, 7, 0.1)
+    fm = LY.FMap(3, 16, 16)
+    ev, ctx, sk, pk = he_eval(name, LY.conv_rotations(fm, 2, 7, 2, 3, slots))
+    kern, masks = LY.conv_plaintexts(fm, K, 2, 3, slots)
+    _, ct = H.encrypt_slots(name, 12, values=LY.pack(X, fm, slots))
+    L = ctx.pr.L
+    y, fo = LY.conv2d(ev, ct, fm, 2, 7, 2, 3, encode_all(ctx, kern, L), encode_all(ctx, masks, L - 1), slots)
+    err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, y), fo) - LY.conv2d_ref(X, K, 2, 3)))
+    assert err < 1e-3, err
 
 
 @pytest.mark.slow

@@ -229,9 +229,11 @@ typedef struct {
 /* Convolution (Sections "Secure Convolution Layer", "Secure Advanced
  * Convolution Layer" with striding approach 1 and the multi-channel striding
  * pipeline, "Special Secure Convolution Layer" with Algorithms 1-3).
- * Supported: kernel 3 / padding 1 (special schedule; several channels need
- * reps = 2 and a dense square map; stride 1 or 2) and padding 0 (generic
- * schedule, any kernel and stride).  Other paddings: HE_EUNSUPPORTED.
+ * Supported: kernel 3 / padding 1 on a dense square map that is replicated
+ * (reps = 2) or has one channel in and out (special schedule; stride 1 or 2),
+ * and every other padding 0 <= P <= (k-1)/2 with any kernel and stride
+ * (generic schedule: the zero padding is realised by the kernel vectors, so
+ * the output keeps the input's layout).  Larger paddings: HE_EUNSUPPORTED.
  * Plaintexts (NTT form, at least the input level in limbs, encoded at one
  * common scale), in this order:
  *  special: kernel_pts[9 f + t], t = 3 (dy+1) + (dx+1): K[f, b mod C, t] on
@@ -239,8 +241,10 @@ typedef struct {
  *    mask_pts: F block masks (1 on block f of every output replica) when
  *    C > 1 or F > 1, then the stride-compaction masks.
  *  generic: kernel_pts[k*k f + i k + j]: K[f, c, i, j] at c*cs + y*rs + x for
- *    the valid stride-1 outputs (y <= H-k, x <= W-k); mask_pts: the block-0
- *    valid-output mask when C > 1, then the stride-compaction masks.
+ *    the stride-1 outputs (y < H+2P-k+1, x < W+2P-k+1) whose neighbour
+ *    (y+i-P, x+j-P) lies inside the image, 0 elsewhere (tap (i, j) is the
+ *    input rotated by (i-P) rs + (j-P)); mask_pts: the block-0 mask of the
+ *    stride-1 outputs when C > 1, then the stride-compaction masks.
  *  compaction masks (stride S > 1, outputs (S i, S j) -> dense Ho x Wo):
  *    Wo column masks (1 at c*cs + S i rs + S j, all c, i), Ho row masks
  *    (1 at c*cs + S i rs + j, j < Wo), then C channel masks (1 on

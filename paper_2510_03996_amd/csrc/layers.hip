@@ -184,6 +184,23 @@ static void add_keys(std::vector<int>& keys, int k) {
 }
 
 // ---------------------------------------------------------------- conv plan
+// The special schedule (Algorithm 1's rotation tree) covers 3x3 / padding 1
+// on a dense square map that is replicated, or one channel in and out; any
+// other padding up to (k-1)/2 uses the generic schedule, whose kernel vectors
+// are zero wherever a tap's neighbour falls in the padding.
+static bool conv_special(const he_fmap& fm, int F, int k, int P) {
+  const int W = fm.width;
+  return k == 3 && P == 1 && fm.height == W && fm.row_stride == W && fm.chan_stride == W * W &&
+         (fm.reps == 2 || (fm.channels == 1 && F == 1));
+}
+// rotation of every tap (i, j), row-major: (i - P) rs + (j - P)
+static std::vector<int> conv_taps(const he_fmap& fm, int k, int P) {
+  std::vector<int> r;
+  for (int i = 0; i < k; i++)
+    for (int j = 0; j < k; j++) r.push_back((i - P) * fm.row_stride + (j - P));
+  return r;
+}
+
 static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P, he_layer_plan* pl) {
   if (!fm || !pl || F < 1 || k < 1 || S < 1) return set_error(HE_EINVAL, "bad convolution arguments");
   const int slots = c->n / 2;
@@ -191,12 +208,8 @@ static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P
   std::vector<int> keys;
   *pl = he_layer_plan{};
   int ks = 0, lv = 0, nmask = 0;
-  if (k == 3 && P == 1) {
+  if (conv_special(*fm, F, k, P)) {
     const int W = fm->width;
-    if (fm->height != W || fm->row_stride != W || fm->chan_stride != W * W)
-      return set_error(HE_EUNSUPPORTED, "special convolution needs a dense square feature map");
-    if (fm->reps == 1 && (C > 1 || F > 1))
-      return set_error(HE_EUNSUPPORTED, "special convolution with several channels needs a replicated input");
     if (fm->reps == 2 && 2 * C * W * W != slots) return set_error(HE_EINVAL, "replicated map must fill N/2 slots");
     if (F * W * W > slots) return set_error(HE_EINVAL, "output channels do not fit the slots");
     if (S > 2) return set_error(HE_EUNSUPPORTED, "special convolution supports stride 1 or 2");
@@ -216,20 +229,19 @@ static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P
       pl->out = he_fmap{F, Ho, Ho, Ho, Ho * Ho, 1};
     }
     pl->n_kernel_pts = 9 * F;
-  } else if (P == 0) {
-    const int H1 = fm->height - k + 1, W1 = fm->width - k + 1;
+  } else if (P >= 0 && P <= (k - 1) / 2) {
+    const int H1 = fm->height + 2 * P - k + 1, W1 = fm->width + 2 * P - k + 1;
     if (H1 < 1 || W1 < 1) return set_error(HE_EINVAL, "kernel larger than the input");
     if (F * fm->chan_stride > slots) return set_error(HE_EINVAL, "output channels do not fit the slots");
-    for (int i = 0; i < k; i++)
-      for (int j = 0; j < k; j++)
-        if (i || j) add_keys(keys, i * fm->row_stride + j);
+    for (int r : conv_taps(*fm, k, P))
+      if (r) add_keys(keys, r);
     ks = k * k - 1;
     lv = 1;
     if (C > 1) { add_keys(keys, fm->chan_stride); ks += F * (C - 1); nmask = 1; lv++; }
     if (F > 1) { add_keys(keys, -fm->chan_stride); ks += F - 1; }
     pl->out = he_fmap{F, H1, W1, fm->row_stride, fm->chan_stride, 1};
     if (S > 1) {
-      int Ho = (fm->height - k) / S + 1, Wo = (fm->width - k) / S + 1;
+      int Ho = (H1 - 1) / S + 1, Wo = (W1 - 1) / S + 1;
       he_fmap f1{F, H1, W1, fm->row_stride, fm->chan_stride, 1};
       auto st = compaction_plan(f1, S, Ho, Wo);
       for (auto& x : st) { add_keys(keys, x.key); ks += x.n - 1; lv++; }
@@ -238,7 +250,7 @@ static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P
     }
     pl->n_kernel_pts = k * k * F;
   } else {
-    return set_error(HE_EUNSUPPORTED, "padding other than 0 (or 1 with a 3x3 kernel) is not implemented");
+    return set_error(HE_EUNSUPPORTED, "padding must be in [0, (k-1)/2]");
   }
   pl->n_mask_pts = nmask;
   pl->levels = lv;
@@ -251,7 +263,7 @@ static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P
 static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, int S, int P, const he_pt* kern,
                       const he_pt* masks, he_fmap* out_map) {
   const int C = fm.channels;
-  if (k == 3 && P == 1) {
+  if (conv_special(fm, F, k, P)) {
     const int W = fm.width;
     auto g1 = ev.rot_hoisted(x, {-W, W, -1, 1});  // r1, r7, r3, r5
     auto g2 = ev.rot_hoisted(g1[0], {-1, 1});     // r0, r2
@@ -297,15 +309,15 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
     ev.release(y);
     return z;
   }
-  // generic
+  // generic: taps (i, j) row-major, rotated by (i - P) rs + (j - P) (one hoisted group)
+  const std::vector<int> tap_rot = conv_taps(fm, k, P);
   std::vector<int> offs;
-  for (int i = 0; i < k; i++)
-    for (int j = 0; j < k; j++)
-      if (i || j) offs.push_back(i * fm.row_stride + j);
+  for (int r : tap_rot)
+    if (r) offs.push_back(r);
   auto rots = ev.rot_hoisted(x, offs);
   std::vector<he_ct> taps;
-  taps.push_back(x);
-  for (auto& r : rots) taps.push_back(r);
+  size_t next = 0;
+  for (int r : tap_rot) taps.push_back(r ? rots[next++] : x);
   const int cs = fm.chan_stride;
   he_ct acc{};
   for (int f = F - 1; f >= 0; f--) {
@@ -327,10 +339,10 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
     acc = (f == F - 1) ? term : ev.add_take(ev.rot_take(acc, -cs), term);
   }
   for (auto& r : rots) ev.release(r);
-  const int H1 = fm.height - k + 1, W1 = fm.width - k + 1;
+  const int H1 = fm.height + 2 * P - k + 1, W1 = fm.width + 2 * P - k + 1;
   *out_map = he_fmap{F, H1, W1, fm.row_stride, cs, 1};
   if (S == 1) return acc;
-  int Ho = (fm.height - k) / S + 1, Wo = (fm.width - k) / S + 1;
+  int Ho = (H1 - 1) / S + 1, Wo = (W1 - 1) / S + 1;
   he_ct z = compaction(ev, acc, he_fmap{F, H1, W1, fm.row_stride, cs, 1}, S, Ho, Wo, masks + (C > 1 ? 1 : 0),
                        out_map);
   ev.release(acc);

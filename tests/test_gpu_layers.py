@@ -199,6 +199,15 @@ def test_config2_fc(gctx):
     assert np.max(np.abs(dec[:10] - LY.fc_ref(x, Wm))) < 1e-3
 
 
+@pytest.mark.parametrize("C,F,HW,k,S,P", [(3, 2, 16, 7, 2, 3), (3, 4, 12, 3, 1, 1), (2, 3, 12, 5, 2, 2)])
+def test_config1_padded_conv(gctx, C, F, HW, k, S, P):
+    """Padding by masked taps: 7x7/s2/p3 (ResNet-34 stem shape), 3x3/p1 on a
+    non-replicated multi-channel map, 5x5/s2/p2."""
+    X = synth.image(29, C, HW, HW)
+    K = synth.conv_weights(29, F, C, k, 0.15)
+    run_conv(gctx("config1"), "config1", X, K, LY.FMap(C, HW, HW), S, P, 29)
+
+
 def test_layer_errors(gctx):
     from paper_2510_03996_amd import he
 
@@ -206,7 +215,7 @@ def test_layer_errors(gctx):
     g = gctx(name)
     fm = he.fmap(1, 28, 28)
     with pytest.raises(he.HEError) as e:
-        g.conv2d_plan(fm, 6, 5, 1, 2)
+        g.conv2d_plan(fm, 6, 5, 1, 3)  # padding beyond (k-1)/2
     assert e.value.name == "HE_EUNSUPPORTED"
     _, ct = H.encrypt_slots(name, 28, level=2)
     gct = g.ct_from_numpy(ct.data, ct.scale)

@@ -346,8 +346,15 @@ static int ctx_init(Ctx* c, const he_params* p) {
       pv[i] = hinv(P, qi);
       pv[l + i] = shoup_of(pv[i], qi);
     }
-    if ((rc = dev_alloc(c, &c->d_pinv[l], 2 * l))) return rc;
-    HE_HIP(hipMemcpy(c->d_pinv[l], pv.data(), 2 * l * 8, hipMemcpyHostToDevice));
+    // then, for the FP64 path of the fused ModDown epilogue, P^{-1} and P^{-1}/q as doubles
+    pv.resize(4 * l);
+    for (int i = 0; i < l; i++) {
+      const double w = (double)pv[i], wq = (double)pv[i] / (double)c->mod[i];
+      std::memcpy(&pv[2 * l + i], &w, 8);
+      std::memcpy(&pv[3 * l + i], &wq, 8);
+    }
+    if ((rc = dev_alloc(c, &c->d_pinv[l], 4 * l))) return rc;
+    HE_HIP(hipMemcpy(c->d_pinv[l], pv.data(), 4 * l * 8, hipMemcpyHostToDevice));
     if (l >= 2) {
       std::vector<uint64_t> rv(2 * (l - 1));
       uint64_t qt = c->mod[l - 1];

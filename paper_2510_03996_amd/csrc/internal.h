@@ -147,7 +147,8 @@ struct NttEpi {
   size_t u_bs;
   const uint64_t* add[2];
   uint64_t* out[2];
-  const uint64_t* pinv;  // [level] P^{-1} mod q_i, then [level] Shoup companions
+  const uint64_t* pinv;  // [level] P^{-1} mod q_i, [level] Shoup companions, then (as
+                         // double bits) [level] P^{-1} and [level] P^{-1} / q_i
   uint32_t g;
   int32_t level;
 };

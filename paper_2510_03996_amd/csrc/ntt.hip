@@ -95,11 +95,31 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
     if (!INV) rounds_fwd<P, 0>(dl, tid, wg, dtw, dtwq, dq, dqinv);
     else rounds_inv<P, P::NR - 1>(dl, tid, wg, dtw, dtwq, dq, dqinv);
     __syncthreads();
-    for (int e = tid; e < P::TILE; e += P::THREADS) {
-      int g, k;
-      P::tile_elem(e, g, k);
-      ntt_store<EPI, LOGN>(a, P::gidx(wg, g, k), P::finish_f64(dl[P::lidx(g, k)], mi.dninv, mi.dninvq, dq, dqinv),
-                           epi, pos, bz, q);
+    if constexpr (EPI) {
+      // fused ModDown epilogue in centred FP64: v (|v| < 4.2q) is the transform's
+      // value before canonicalisation; |u - v| < 6q, the product is below 2q and
+      // adding the canonical c0 term stays below 3q, so one canonicalisation ends it
+      const size_t off = (size_t)pos << LOGN;
+      const double pw = bits_to_f64(epi.pinv[2 * epi.level + pos]);
+      const double pwq = bits_to_f64(epi.pinv[3 * epi.level + pos]);
+      const uint64_t* add = epi.add[bz];
+      const uint64_t* u = epi.u + bz * epi.u_bs + off;
+      uint64_t* o = epi.out[bz] + off;
+      for (int e = tid; e < P::TILE; e += P::THREADS) {
+        int g, k;
+        P::tile_elem(e, g, k);
+        const int kk = P::gidx(wg, g, k);
+        const double r = mul_f64_c(u52_to_f64(u[kk]) - dl[P::lidx(g, k)], pw, pwq, dq);
+        double x = 0.0;
+        if (add) x = u52_to_f64(add[off + (bz == 0 && epi.g != 1 ? automorph_src(kk, epi.g, LOGN) : (uint32_t)kk)]);
+        o[kk] = f64_to_u52(canon_f64(r + x, dqinv, dq));
+      }
+    } else {
+      for (int e = tid; e < P::TILE; e += P::THREADS) {
+        int g, k;
+        P::tile_elem(e, g, k);
+        a[P::gidx(wg, g, k)] = P::finish_f64(dl[P::lidx(g, k)], mi.dninv, mi.dninvq, dq, dqinv);
+      }
     }
     return;
   }

@@ -100,6 +100,16 @@ def upload_synthetic_keys(ctx, keys, seed, relin=False):
         ctx.key_upload(r, k)
 
 
+def register_synthetic_keys_on_host(ctx, keys, seed):
+    """The keys upload_synthetic_keys(ctx, keys, seed) makes, held instead as
+    host copies that the library loads on demand."""
+    import synth
+
+    for t, r in enumerate(keys):
+        k = synth.device_residues(seed * 7919 + t, ctx.moduli, ctx.n, lead=(ctx.dnum, 2))
+        ctx.key_host_register(r, k.cpu().numpy().view("uint64"))
+
+
 def synthetic_pts(ctx, count, level, seed, scale):
     import synth
     from paper_2510_03996_amd import he
@@ -359,6 +369,7 @@ def synthetic_serving_models(seed=1):
     nbuf = 24
     ms = {"lenet": serve.Model("lenet", c1, lenet.stages, nbuf, c1.lane_bytes(nbuf) + 4 * 2 * 8 * c1.n * 8),
           "resnet": serve.Model("resnet", c2, resnet.stages, nbuf, c2.lane_bytes(nbuf) + 4 * 2 * 24 * c2.n * 8)}
+    ms["resnet"].key_ids, ms["resnet"].key_seed = list(k2), seed * 100 + 4  # the seed regenerates them
 
     def make_input(kind, sd):
         if kind == "lenet":
@@ -400,6 +411,24 @@ def serving(n_req):
                          "p99_ms": round(serve.percentile(lat, 99) * 1e3, 2)}
         row["max_in_flight"] = srv.max_active
         res["load_%.1f" % load] = row
+    # dynamic key management: the ResNet-shaped model's keys held as host copies,
+    # loaded on demand into a device budget of a third of its key set (LRU)
+    rm = ms["resnet"]
+    register_synthetic_keys_on_host(rm.ctx, rm.key_ids, rm.key_seed)
+    budget = max(1, len(rm.key_ids) // 3) * rm.ctx.key_bytes()
+    rm.ctx.key_cache_limit(budget)
+    rate = 0.7 / mean_service
+    arr = synth.poisson_arrivals(12, rate, n_req)
+    log("serving load 0.7, continuous, keys on demand")
+    done = srv.serve([serve.Request(i, k, arr[i], inputs[i]) for i, k in enumerate(kinds)], "continuous")
+    lat = [r.latency for r in done]
+    span = max(r.t_done for r in done) - min(r.arrival for r in done)
+    st = rm.ctx.key_cache_stats()
+    res["dynamic_keys_load_0.7"] = {
+        "resnet_keys": len(rm.key_ids), "device_budget_keys": budget // rm.ctx.key_bytes(),
+        "continuous": {"req_per_s": round(len(done) / span, 2), "p50_ms": round(serve.percentile(lat, 50) * 1e3, 2),
+                       "p99_ms": round(serve.percentile(lat, 99) * 1e3, 2)},
+        "key_loads": st["loads"], "key_evictions": st["evictions"]}
     srv.close()
     for m in ms.values():
         m.ctx.close()

@@ -144,6 +144,26 @@ int he_key_upload(he_ctx* ctx, int32_t key_id, const uint64_t* src, size_t bytes
 int he_key_evict(he_ctx* ctx, int32_t key_id);
 int he_key_count(const he_ctx* ctx);
 size_t he_key_bytes(const he_ctx* ctx); /* bytes of one key */
+/* Dynamic key management (section "Evaluation Keys Management": keys loaded
+ * on demand and removed at run time, next to preloading).  A key registered
+ * with a host copy (copied into library-owned pinned memory; plain limb
+ * layout as for he_key_upload) need not be in device memory: any operation
+ * that needs it loads it, stream-ordered on that operation's stream
+ * (host-to-device copy + conversion), and another stream using it before the
+ * load has finished waits for it.  With a device budget (he_key_cache_limit,
+ * bytes; 0 = unlimited) a load first evicts the least recently used
+ * host-backed keys that no batch holds; an evicted buffer is reused only
+ * after the last kernel reading it has completed (the host waits for that).
+ * Keys uploaded with he_key_upload (no host copy) are never evicted; keys a
+ * batch captured stay resident until he_batch_destroy.  The budget is soft
+ * when nothing is evictable.  he_key_prefetch loads keys ahead of use on the
+ * given stream.  he_key_evict drops both copies.  Key-management calls must
+ * not run concurrently with other calls on the same context. */
+int he_key_host_register(he_ctx* ctx, int32_t key_id, const uint64_t* host_key, size_t bytes);
+int he_key_cache_limit(he_ctx* ctx, size_t device_bytes);
+int he_key_prefetch(he_ctx* ctx, const int32_t* key_ids, int n, he_stream stream);
+/* device bytes of resident keys, loads from host copies and evictions so far */
+int he_key_cache_stats(const he_ctx* ctx, size_t* resident_bytes, int64_t* loads, int64_t* evictions);
 
 /* ------------------------------------------------------------ ring ops */
 /* In-place negacyclic NTT (inverse = 0) or iNTT (inverse = 1, includes N^-1)

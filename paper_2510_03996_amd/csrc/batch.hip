@@ -198,6 +198,7 @@ struct Batch {
   int mac_og = 8;  // outputs per register group in the fused MAC (autotuned)
   int nmax = 0;    // largest rotation set
   std::vector<void*> allocs;
+  std::vector<int32_t> locked;  // keys held resident for the batch
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool use_graph = false;
@@ -220,6 +221,8 @@ static void batch_free(Batch* b) {
   if (b->graph) hipGraphDestroy(b->graph);
   for (void* p : b->allocs) hipFree(p);
   b->allocs.clear();
+  for (int32_t id : b->locked) key_lock(b->c, id, -1);
+  b->locked.clear();
 }
 
 // ---------------------------------------------------------------- execution
@@ -363,7 +366,7 @@ int he_batch_create(he_ctx* h, const he_batch_desc* d, int flags, he_batch** out
       for (int32_t x : seen)
         if (x == r) return fail(set_error(HE_EINVAL, "rotation amounts of an item must be distinct"));
       seen.push_back(r);
-      if (!find_key(c, r)) return fail(set_error(HE_ENOKEY, "rotation key " + std::to_string(r) + " not resident"));
+      if (!key_known(c, r)) return fail(set_error(HE_ENOKEY, "rotation key " + std::to_string(r) + " not resident"));
       by_key[r].push_back({i, t});
     }
   }
@@ -374,7 +377,12 @@ int he_batch_create(he_ctx* h, const he_batch_desc* d, int flags, he_batch** out
     KeyGroup g;
     g.rot = kv.first;
     g.g = galois_elt(c, kv.first);
-    g.key = find_key(c, kv.first);
+    // the batch captures the key's device address: load it now and hold it
+    // resident until the batch is destroyed
+    g.key = key_acquire(c, kv.first, nullptr);
+    if (!g.key) return fail(HE_ENOMEM);
+    key_lock(c, kv.first, 1);
+    b->locked.push_back(kv.first);
     g.npairs = (int)kv.second.size();
     g.first_pair = gp;
     std::vector<int32_t> items;
@@ -387,6 +395,9 @@ int he_batch_create(he_ctx* h, const he_batch_desc* d, int flags, he_batch** out
     b->max_group = std::max(b->max_group, g.npairs);
     b->groups.push_back(g);
   }
+  // keys loaded for the batch (on the null stream) must be complete before any
+  // stream runs it: its kernels read the captured addresses without a wait
+  if (hipStreamSynchronize(nullptr) != hipSuccess) return fail(set_error(HE_EHIP, "key load failed"));
   // device tables
   auto up = [&](int32_t** dst, const std::vector<int32_t>& v) -> int {
     int r = balloc(b, dst, v.size());

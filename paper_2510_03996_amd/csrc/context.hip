@@ -485,7 +485,7 @@ int he_ctx_destroy(he_ctx* h) {
   if (!h) return HE_OK;
   hipSetDevice(h->c.device);
   hipDeviceSynchronize();
-  for (auto& kv : h->c.keys) hipFree(kv.second);
+  keys_free_all(&h->c);
   for (auto& kv : h->c.lanes) lane_free(&h->c, kv.first, kv.second);
   h->c.lanes.clear();
   for (void* p : h->c.allocs) hipFree(p);

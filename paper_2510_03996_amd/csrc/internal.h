@@ -43,6 +43,20 @@ constexpr double PEAK_MODMUL_INT = LANE_OPS_PER_S / 2 / 10;  // 1.966e12 / s
 constexpr double PEAK_MODMUL_F64 = LANE_OPS_PER_S / 6;       // 6.554e12 / s
 constexpr double PEAK_INT8_OPS = 5.0e15;                      // dense int8 MFMA, ops / s
 
+// One evaluation key.  A key with a host copy may be evicted from device
+// memory (its buffer is reused only after the event recorded at its last use
+// has completed) and is loaded again, stream-ordered, by the next operation
+// that needs it; a key without one stays resident until he_key_evict.
+struct KeyEntry {
+  uint64_t* dev = nullptr;         // device copy, Montgomery form
+  uint64_t* host = nullptr;        // pinned host copy, plain form (library-owned)
+  hipEvent_t used = nullptr;       // recorded after the last kernel that read dev
+  hipEvent_t ready = nullptr;      // recorded after the last load into dev
+  hipStream_t ready_stream = nullptr;
+  uint64_t tick = 0;               // LRU clock of the last acquire
+  int locks = 0;                   // batches that captured dev
+};
+
 // Per-stream execution lane: the key-switch workspace and the pool of
 // temporary ciphertext buffers used by work enqueued on one stream.  Work on
 // different streams never shares scratch memory, so requests issued on
@@ -70,8 +84,13 @@ struct Ctx {
   std::vector<uint64_t*> d_rescale;
   // per level l: Shoup pairs of P^{-1} mod q_i: [2][l]
   std::vector<uint64_t*> d_pinv;
-  // resident evaluation keys (Montgomery form), by normalised id
-  std::map<int32_t, uint64_t*> keys;
+  // evaluation keys by normalised id: device copy (Montgomery form) and/or a
+  // pinned host copy from which the key is loaded on demand
+  std::map<int32_t, KeyEntry> keys;
+  std::vector<uint64_t*> key_free;  // device buffers of evicted keys, reused
+  size_t key_limit = 0;             // device bytes for keys (0: unlimited)
+  uint64_t key_tick = 0;            // LRU clock
+  long long key_loads = 0, key_evictions = 0;
   size_t key_words = 0;
   // workspace pool (one key switch at the top level)
   uint64_t* ws = nullptr;
@@ -183,7 +202,14 @@ int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s);
 // digits, ModDown, and out0 = add0[phi_g] + u0', out1 = add1 + u1'.
 int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
              const uint64_t* add0, const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s);
-const uint64_t* find_key(Ctx* c, int32_t id);
+// key cache (keys.hip): known = resident or loadable; acquire makes the key
+// usable by work enqueued next on s (loading and evicting as needed, nullptr
+// with the error set when that fails); note_use records its last use on s
+bool key_known(const Ctx* c, int32_t id);
+const uint64_t* key_acquire(Ctx* c, int32_t id, hipStream_t s);
+void key_note_use(Ctx* c, int32_t id, hipStream_t s);
+int key_lock(Ctx* c, int32_t id, int delta);
+void keys_free_all(Ctx* c);
 // lane of a stream (created on first use; throws nothing, returns null on allocation failure)
 Lane* lane_for(Ctx* c, hipStream_t s);
 uint64_t* lane_ct_get(Ctx* c, Lane* ln);  // null on allocation failure
@@ -200,6 +226,7 @@ inline double bconv_ideal_s(double N, double convs, int nin, int nout) {
   return convs * (mfma / PEAK_INT8_OPS + N * (nin + nout) / PEAK_MODMUL_INT);
 }
 inline int bconv_tiles_y(const BConvSet& s) { return ((s.max_out + 3) / 4 + BCONV_TILES_Y - 1) / BCONV_TILES_Y; }
+__global__ void k_to_mont(uint64_t* key, int M, int logn, const ModInfo* __restrict__ mods);
 __global__ void k_bconv(const uint64_t* __restrict__ in, size_t in_bs, uint64_t* __restrict__ out, size_t out_bs,
                         const BConvDesc* __restrict__ descs, int zdiv, const ModInfo* __restrict__ mods, int logn);
 __global__ void k_bcast_reduce(const uint64_t* __restrict__ T, uint64_t* __restrict__ R, int nl, int logn,

@@ -168,10 +168,7 @@ int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t*
   return HE_OK;
 }
 
-const uint64_t* find_key(Ctx* c, int32_t id) {
-  auto it = c->keys.find(norm_key_id(c, id));
-  return it == c->keys.end() ? nullptr : it->second;
-}
+
 
 
 }  // namespace he
@@ -180,43 +177,7 @@ using namespace he;
 
 extern "C" {
 
-int he_key_upload(he_ctx* h, int32_t key_id, const uint64_t* src, size_t bytes, int src_on_device, he_stream st) {
-  if (!h || !src) return set_error(HE_EINVAL, "null argument");
-  Ctx* c = &h->c;
-  if (bytes != c->key_words * 8) return set_error(HE_EINVAL, "key size must be dnum*2*(L+K)*N*8 bytes");
-  hipStream_t s = (hipStream_t)st;
-  const int32_t id = norm_key_id(c, key_id);
-  uint64_t* d = nullptr;
-  auto it = c->keys.find(id);
-  if (it != c->keys.end()) {
-    d = it->second;
-  } else {
-    hipError_t e = hipMalloc((void**)&d, bytes);
-    if (e != hipSuccess) return set_error(HE_ENOMEM, std::string("key allocation: ") + hipGetErrorString(e));
-    c->keys[id] = d;
-  }
-  HE_HIP(hipMemcpyAsync(d, src, bytes, src_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s));
-  const int M = c->L + c->K;
-  const int limbs = c->dnum(c->L) * 2 * M;
-  k_to_mont<<<dim3(c->n / 256, limbs), 256, 0, s>>>(d, M, c->log_n, c->d_mod);
-  HE_HIP(hipGetLastError());
-  if (!src_on_device) HE_HIP(hipStreamSynchronize(s));  // host buffer may be freed after return
-  return HE_OK;
-}
 
-int he_key_evict(he_ctx* h, int32_t key_id) {
-  if (!h) return set_error(HE_EINVAL, "null context");
-  Ctx* c = &h->c;
-  auto it = c->keys.find(norm_key_id(c, key_id));
-  if (it == c->keys.end()) return set_error(HE_ENOKEY, "key not resident");
-  HE_HIP(hipDeviceSynchronize());
-  HE_HIP(hipFree(it->second));
-  c->keys.erase(it);
-  return HE_OK;
-}
-
-int he_key_count(const he_ctx* h) { return h ? (int)h->c.keys.size() : 0; }
-size_t he_key_bytes(const he_ctx* h) { return h ? h->c.key_words * 8 : 0; }
 
 int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct* outs, he_stream st) {
   if (!h || !r || !outs || n < 0) return set_error(HE_EINVAL, "null argument");
@@ -231,7 +192,7 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
     if (outs[t].data == in->data) return set_error(HE_EINVAL, "output aliases the input");
     if (norm_key_id(c, r[t]) != 0) {
       any = true;
-      if (!find_key(c, r[t])) return set_error(HE_ENOKEY, "rotation key " + std::to_string(r[t]) + " not resident");
+      if (!key_known(c, r[t])) return set_error(HE_ENOKEY, "rotation key " + std::to_string(r[t]) + " not resident");
     }
   }
   hipStream_t s = (hipStream_t)st;
@@ -249,7 +210,10 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
       HE_HIP(hipMemcpyAsync(o0, c0, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s));
       HE_HIP(hipMemcpyAsync(o1, c1, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s));
     } else {
-      if ((rc = ks_apply(c, w, c1, l, find_key(c, r[t]), galois_elt(c, r[t]), c0, nullptr, o0, o1, s))) return rc;
+      const uint64_t* key = key_acquire(c, r[t], s);
+      if (!key) return HE_ENOMEM;
+      if ((rc = ks_apply(c, w, c1, l, key, galois_elt(c, r[t]), c0, nullptr, o0, o1, s))) return rc;
+      key_note_use(c, r[t], s);
     }
     o.level = l;
     o.scale = in->scale;
@@ -267,8 +231,7 @@ int he_relin(he_ctx* h, const uint64_t* d, int level, double scale, he_ct* out, 
   int rc;
   if (level < 1 || level > c->L) return set_error(HE_EINVAL, "bad level");
   if ((rc = check_out(c, out, level))) return rc;
-  const uint64_t* key = find_key(c, HE_KEY_RELIN);
-  if (!key) return set_error(HE_ENOKEY, "relinearization key not resident");
+  if (!key_known(c, HE_KEY_RELIN)) return set_error(HE_ENOKEY, "relinearization key not resident");
   hipStream_t s = (hipStream_t)st;
   const size_t N = c->n;
   Lane* lane = lane_for(c, s);
@@ -278,7 +241,10 @@ int he_relin(he_ctx* h, const uint64_t* d, int level, double scale, he_ct* out, 
   const uint64_t* d1 = d + (size_t)level * N;
   const uint64_t* d2 = d + 2 * (size_t)level * N;
   if ((rc = ks_modup(c, w, d2, level, s))) return rc;
+  const uint64_t* key = key_acquire(c, HE_KEY_RELIN, s);
+  if (!key) return HE_ENOMEM;
   if ((rc = ks_apply(c, w, d2, level, key, 1, d0, d1, out->data, out->data + (size_t)out->cap * N, s))) return rc;
+  key_note_use(c, HE_KEY_RELIN, s);
   out->level = level;
   out->scale = scale;
   return HE_OK;

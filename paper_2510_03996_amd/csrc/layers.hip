@@ -538,7 +538,7 @@ int he_conv2d(he_ctx* h, const he_ct* in, const he_fmap* in_map, int out_ch, int
   if ((rc = check_pts(c, kernel_pts, n_kernel_pts, in->level, "kernel_pts"))) return rc;
   if ((rc = check_pts(c, mask_pts, n_mask_pts, in->level - pl.levels + 1, "mask_pts"))) return rc;
   for (int i = 0; i < pl.n_keys; i++)
-    if (!find_key(c, pl.rot_keys[i]))
+    if (!key_known(c, pl.rot_keys[i]))
       return set_error(HE_ENOKEY, "rotation key " + std::to_string(pl.rot_keys[i]) + " not resident");
   return guarded([&] {
     Ev ev(h, s);
@@ -566,7 +566,7 @@ int he_avgpool(he_ctx* h, const he_ct* in, const he_fmap* in_map, int kernel, in
   if ((rc = check_out(c, out, in->level - pl.levels))) return rc;
   if ((rc = check_pts(c, mask_pts, n_mask_pts, in->level, "mask_pts"))) return rc;
   for (int i = 0; i < pl.n_keys; i++)
-    if (!find_key(c, pl.rot_keys[i]))
+    if (!key_known(c, pl.rot_keys[i]))
       return set_error(HE_ENOKEY, "rotation key " + std::to_string(pl.rot_keys[i]) + " not resident");
   return guarded([&] {
     Ev ev(h, s);
@@ -596,7 +596,7 @@ int he_fc(he_ctx* h, const he_ct* in, int n_in, int n_out, const he_pt* weight_p
       (rc = check_pts(c, mask_pts, 1, in->level - 1, "mask_pts")))
     return rc;
   for (int i = 0; i < pl.n_keys; i++)
-    if (!find_key(c, pl.rot_keys[i]))
+    if (!key_known(c, pl.rot_keys[i]))
       return set_error(HE_ENOKEY, "rotation key " + std::to_string(pl.rot_keys[i]) + " not resident");
   return guarded([&] {
     Ev ev(h, s);
@@ -623,7 +623,7 @@ int he_poly4(he_ctx* h, const he_ct* in, const double* cf, double delta, he_ct* 
   if (cf[3] != 0.0) return set_error(HE_EUNSUPPORTED, "the cubic coefficient must be zero");
   if (in->level <= 3) return set_error(HE_ELEVEL, "the polynomial needs three levels");
   if ((rc = check_out(c, out, in->level - 3))) return rc;
-  if (!find_key(c, HE_KEY_RELIN)) return set_error(HE_ENOKEY, "relinearization key not resident");
+  if (!key_known(c, HE_KEY_RELIN)) return set_error(HE_ENOKEY, "relinearization key not resident");
   return guarded([&] {
     Ev ev(h, s);
     const he_ct& x = *in;
@@ -680,7 +680,7 @@ int he_cheb(he_ctx* h, const he_ct* in, const he_pt* scale_mask, const double* c
     return set_error(HE_ELEVEL, "the Chebyshev evaluation needs " + std::to_string(levels) + " levels");
   if (scale_mask && (rc = check_pts(c, scale_mask, 1, in->level, "scale_mask"))) return rc;
   if ((rc = check_out(c, out, in->level - levels))) return rc;
-  if (!find_key(c, HE_KEY_RELIN)) return set_error(HE_ENOKEY, "relinearization key not resident");
+  if (!key_known(c, HE_KEY_RELIN)) return set_error(HE_ENOKEY, "relinearization key not resident");
   const std::vector<int> terms = cheb_terms(cf, degree);
   return guarded([&] {
     Ev ev(h, s);

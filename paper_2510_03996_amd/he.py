@@ -136,6 +136,10 @@ def lib():
             "he_ctx_ntt_tuning": [vp, P(i32), P(ctypes.c_float)],
             "he_ntt_variant": [c_int, P(i32), P(i32)],
             "he_ctx_ntt_select": [vp, P(i32)],
+            "he_key_host_register": [vp, i32, P(ctypes.c_uint64), sz],
+            "he_key_cache_limit": [vp, sz],
+            "he_key_prefetch": [vp, P(i32), c_int, vp],
+            "he_key_cache_stats": [vp, P(sz), P(ctypes.c_int64), P(ctypes.c_int64)],
             "he_profile_begin": [vp],
             "he_profile_end": [vp, ctypes.c_char_p, sz],
         }
@@ -286,6 +290,24 @@ class Context:
 
     def key_evict(self, key_id):
         _check(lib().he_key_evict(self.h, key_id))
+
+    def key_host_register(self, key_id, key):
+        """Register a key by a host copy (loaded into device memory on demand)."""
+        k = np.ascontiguousarray(np.asarray(key), dtype=np.uint64)
+        _check(lib().he_key_host_register(self.h, int(key_id), k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                          k.nbytes))
+
+    def key_cache_limit(self, device_bytes):
+        _check(lib().he_key_cache_limit(self.h, int(device_bytes)))
+
+    def key_prefetch(self, key_ids, stream=None):
+        ids = (ctypes.c_int32 * len(key_ids))(*[int(x) for x in key_ids])
+        _check(lib().he_key_prefetch(self.h, ids, len(key_ids), _stream(stream)))
+
+    def key_cache_stats(self):
+        r, lo, ev = ctypes.c_size_t(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().he_key_cache_stats(self.h, ctypes.byref(r), ctypes.byref(lo), ctypes.byref(ev)))
+        return {"resident_bytes": r.value, "loads": lo.value, "evictions": ev.value}
 
     def key_count(self):
         return lib().he_key_count(self.h)

@@ -33,12 +33,15 @@ class Model:
     layer on ``stream`` and return the output ciphertext (device memory).
     footprint: device bytes one in-flight request of this model needs
     (its lane workspace, temporaries, input and output).
+    key_ids: the model's evaluation keys (resident, or registered with host
+    copies and loaded on demand by the library's key cache).
     """
 
-    def __init__(self, name, ctx, stages, n_ct_buffers, footprint):
+    def __init__(self, name, ctx, stages, n_ct_buffers, footprint, key_ids=()):
         self.name, self.ctx, self.stages = name, ctx, stages
         self.n_ct_buffers = n_ct_buffers
         self.footprint = footprint
+        self.key_ids = list(key_ids)
 
 
 class Request:

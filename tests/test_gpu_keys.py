@@ -1,0 +1,147 @@
+"""Dynamic key management: keys loaded on demand from host copies into a
+device budget (LRU eviction), bit-exact against the oracle (needs MI355X)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import layers as LY
+from tests import helpers as H
+from tests.test_gpu_batch import make_batch, oracle_outputs
+
+pytestmark = pytest.mark.gpu
+NAME = "config1"
+
+
+def fresh():
+    return H.gpu_ctx(NAME)
+
+
+def test_demand_loading_and_eviction():
+    octx, _, _ = H.oracle_ctx(NAME)
+    g = fresh()
+    try:
+        rots = [1, -3, 17, 200]
+        for r in rots:
+            g.key_host_register(r, H.oracle_key(NAME, r))
+        g.key_cache_limit(2 * g.key_bytes())
+        assert g.key_count() == 0
+        _, ct = H.encrypt_slots(NAME, 80)
+        gct = g.ct_from_numpy(ct.data, ct.scale)
+        for rep in range(2):
+            for r in rots:
+                got = g.rotate(gct, r)
+                H.assert_limbs_equal(got.numpy(), octx.rotate(ct, r, {r: H.oracle_key(NAME, r)}).data,
+                                     "rotation %d under a 2-key budget (pass %d)" % (r, rep))
+                assert g.key_cache_stats()["resident_bytes"] <= 2 * g.key_bytes()
+        st = g.key_cache_stats()
+        assert st["loads"] == 8 and st["evictions"] == 6, st
+        # hoisted set of all four keys: the budget is exceeded by nothing evictable only transiently
+        outs = g.rotate_hoisted(gct, rots)
+        want = octx.rotate_hoisted(ct, rots, H.oracle_keys(NAME, rots))
+        for o, w in zip(outs, want):
+            H.assert_limbs_equal(o.numpy(), w.data, "hoisted set under a budget")
+    finally:
+        g.close()
+
+
+def test_layer_under_budget():
+    """Generic convolution (9 keys) with every key loaded on demand into a 3-key budget."""
+    octx, sk, _ = H.oracle_ctx(NAME)
+    slots = octx.n // 2
+    g = fresh()
+    try:
+        X = synth.image(81, 2, 12, 12)
+        K = synth.conv_weights(81, 3, 2, 3, 0.2)
+        fm = LY.FMap(2, 12, 12)
+        from paper_2510_03996_amd import he
+
+        plan = g.conv2d_plan(he.he_fmap(*fm.key()), 3, 3, 1, 1)
+        for r in plan.keys():
+            g.key_host_register(r, H.oracle_key(NAME, r))
+        g.key_cache_limit(3 * g.key_bytes())
+        _, ct = H.encrypt_slots(NAME, 81, values=LY.pack(X, fm, slots))
+        kern, masks = LY.conv_plaintexts(fm, K, 1, 1, slots)
+        kp = [octx.encode(v, octx.pr.scale, ct.level) for v in kern]
+        mp = [octx.encode(v, octx.pr.scale, ct.level) for v in masks]
+        ev = LY.HEEval(octx, H.oracle_keys(NAME, plan.keys()))
+        want, fo = LY.conv2d(ev, ct, fm, 3, 3, 1, 1, kp, mp, slots)
+        got, _ = g.conv2d(g.ct_from_numpy(ct.data, ct.scale), he.he_fmap(*fm.key()), 3, 3, 1, 1,
+                          [g.pt_from_numpy(p.data, p.scale) for p in kp], [g.pt_from_numpy(p.data, p.scale) for p in mp])
+        H.assert_limbs_equal(got.numpy(), want.data, "convolution with keys loaded on demand")
+        st = g.key_cache_stats()
+        assert st["resident_bytes"] <= 3 * g.key_bytes() and st["evictions"] > 0, st
+    finally:
+        g.close()
+
+
+def test_batch_holds_its_keys():
+    from paper_2510_03996_amd import he
+
+    octx, sets, outs, cts, pool, pti = make_batch(NAME, 3, 4, 2, 3, 1, 2, seed=82)
+    g = fresh()
+    try:
+        keys = sorted({r for s in sets for r in s})
+        for r in keys:
+            g.key_host_register(r, H.oracle_key(NAME, r))
+        g.key_cache_limit(g.key_bytes())  # smaller than the batch's key set: the budget is soft for held keys
+        level = cts[0].level
+        inp = he.to_device(np.stack([c.data for c in cts]))
+        pt = he.to_device(np.stack([p.data for p in pool]))
+        out = torch.zeros((sum(outs), 2, level - 1, g.n), dtype=torch.int64, device="cuda")
+        torch.cuda.synchronize()
+        b = he.Batch(g, inp, level, cts[0].scale, sets, outs, pt, pool[0].scale, pti, out, he.BATCH_GRAPH)
+        assert g.key_count() == len(keys)
+        with pytest.raises(he.HEError) as e:
+            g.key_evict(keys[0])
+        assert e.value.name == "HE_EINVAL"
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            b.run(s)
+            s.synchronize()
+        want = oracle_outputs(NAME, sets, outs, cts, pool, pti)
+        got = out.cpu().numpy().view(np.uint64)
+        for i, w in enumerate(want):
+            H.assert_limbs_equal(got[i], w.data, "batched output %d with held keys" % i)
+        b.close()
+        g.key_evict(keys[0])  # no longer held
+    finally:
+        g.close()
+
+
+def test_prefetch_on_another_stream():
+    octx, _, _ = H.oracle_ctx(NAME)
+    g = fresh()
+    try:
+        g.key_host_register(5, H.oracle_key(NAME, 5))
+        a, b = torch.cuda.Stream(), torch.cuda.Stream()
+        _, ct = H.encrypt_slots(NAME, 83)
+        gct = g.ct_from_numpy(ct.data, ct.scale)
+        out = g.new_ct(ct.level)
+        torch.cuda.synchronize()
+        g.key_prefetch([5], stream=a)  # loaded on stream a ...
+        g.rotate(gct, 5, out=out, stream=b)  # ... and used at once on stream b, which waits for the load
+        b.synchronize()
+        H.assert_limbs_equal(out.numpy(), octx.rotate(ct, 5, {5: H.oracle_key(NAME, 5)}).data, "prefetched key")
+        assert g.key_cache_stats()["loads"] == 1
+    finally:
+        torch.cuda.synchronize()
+        g.close()
+
+
+def test_key_cache_errors():
+    from paper_2510_03996_amd import he
+
+    g = fresh()
+    try:
+        with pytest.raises(he.HEError) as e:
+            g.key_cache_limit(g.key_bytes() - 8)
+        assert e.value.name == "HE_EINVAL"
+        with pytest.raises(he.HEError) as e:
+            g.key_prefetch([99])
+        assert e.value.name == "HE_ENOKEY"
+        with pytest.raises(he.HEError) as e:
+            g.key_host_register(7, np.zeros(16, dtype=np.uint64))
+        assert e.value.name == "HE_EINVAL"
+    finally:
+        g.close()

@@ -688,12 +688,75 @@ def cheb_relu_ref(x, beta, degree=CHEB_DEGREE):
     return np.polynomial.chebyshev.chebval(np.asarray(x) / beta, c)
 
 
+CHEB_BABY = 8  # baby-step bound of the evaluation: leaves have degree < 8
+
+
+def cheb_series(coeffs):
+    """Series coefficients a_j of f = sum a_j T_j (a_0 = c_0 / 2)."""
+    a = np.array(coeffs, dtype=float)
+    a[0] = a[0] / 2.0
+    return a
+
+
+def _trim(a):
+    d = len(a) - 1
+    while d > 0 and a[d] == 0.0:
+        d -= 1
+    return a[:d + 1]
+
+
+def cheb_split(a, K):
+    """Chebyshev division by T_K (K <= deg a < 2K): a = q T_K + r with
+    T_{K+i} = 2 T_K T_i - T_{K-i}:  q_0 = a_K, q_i = 2 a_{K+i} (i >= 1);
+    r_i = a_i - a_{2K-i} for 2K - deg <= i < K, r_i = a_i otherwise."""
+    d = len(a) - 1
+    q = np.zeros(d - K + 1)
+    q[0] = a[K]
+    for i in range(1, d - K + 1):
+        q[i] = 2.0 * a[K + i]
+    r = a[:K].copy()
+    for i in range(2 * K - d, K):
+        r[i] = a[i] - a[2 * K - i]
+    return q, r
+
+
+def cheb_tree(a):
+    """The evaluation tree of a series: a leaf (degree < CHEB_BABY) or
+    (K, quotient subtree, remainder subtree) with K = CHEB_BABY 2^m the
+    largest such index not above the degree."""
+    a = _trim(a)
+    d = len(a) - 1
+    if d < CHEB_BABY:
+        return ("leaf", a)
+    K = CHEB_BABY
+    while 2 * K <= d:
+        K *= 2
+    q, r = cheb_split(a, K)
+    return ("node", K, cheb_tree(q), cheb_tree(r))
+
+
+def _tree_terms(t, acc):
+    if t[0] == "leaf":
+        acc |= {j for j in range(1, len(t[1])) if t[1][j] != 0.0}
+        acc.add(1)
+    else:
+        acc.add(t[1])
+        _tree_terms(t[2], acc)
+        _tree_terms(t[3], acc)
+    return acc
+
+
+def _tree_nodes(t):
+    return 0 if t[0] == "leaf" else 1 + _tree_nodes(t[2]) + _tree_nodes(t[3])
+
+
 def cheb_terms(coeffs):
-    """Chebyshev indices j >= 1 the evaluation computes, ascending: every j
-    with c_j != 0 and, recursively, the factors of T_j's product rule
-    (T_{2k} = 2 T_k^2 - 1, T_{2k+1} = 2 T_k T_{k+1} - T_1)."""
+    """Chebyshev polynomials T_j (j >= 1) the evaluation computes, ascending:
+    the leaves' terms with nonzero coefficients, T_1, the giant steps T_K and,
+    recursively, the factors of the product rule (T_{2k} = 2 T_k^2 - 1,
+    T_{2k+1} = 2 T_k T_{k+1} - T_1)."""
     need = set()
-    stack = [1] + [j for j in range(1, len(coeffs)) if coeffs[j] != 0.0]
+    stack = sorted(_tree_terms(cheb_tree(cheb_series(coeffs)), set()))
     while stack:
         j = stack.pop()
         if j in need:
@@ -705,34 +768,69 @@ def cheb_terms(coeffs):
 
 
 def cheb_depth(j):
-    """Multiplicative depth of T_j in the product tree (T_1: 0)."""
+    """Multiplicative depth of T_j in the product rule (T_1: 0)."""
     return (j - 1).bit_length()
+
+
+def _allowed(t, top):
+    """Highest level a subtree can be evaluated onto when T_j sits at level top - depth(j)."""
+    if t[0] == "leaf":
+        js = [j for j in range(1, len(t[1])) if t[1][j] != 0.0] or [1]
+        return min(top - cheb_depth(j) - 1 for j in js)
+    K = t[1]
+    return min(top - cheb_depth(K) - 1, _allowed(t[2], top) - 1, _allowed(t[3], top))
 
 
 def cheb_plan(coeffs, masked):
     """(levels consumed, relinearizations) of cheb_eval."""
-    terms = cheb_terms(coeffs)
-    return int(masked) + max(cheb_depth(j) for j in terms) + 1, len(terms) - 1
+    tree = cheb_tree(cheb_series(coeffs))
+    top = 0  # levels are relative to v = the (masked) input
+    return int(masked) - _allowed(tree, top), len(cheb_terms(coeffs)) - 1 + _tree_nodes(tree)
 
 
 def cheb_lift(ev, v, level, scale, c):
     """c v brought to `level` with tracked scale `scale`: drop v to level + 1,
     multiply by c encoded at sigma = scale q / s_v (q the prime the rescale
-    divides by), rescale, and record `scale` (the product's scale up to the
+    divides by), rescale, and record `scale` (the product's, up to the
     rounding of sigma)."""
     q = ev.modulus(level)
     t = ev.rescale(ev.mul_const(ev.drop(v, level + 1), c, scale * q / v.scale))
     return ev.with_scale(t, scale)
 
 
+def _cheb_node(ev, tree, T, level, scale):
+    if tree[0] == "leaf":
+        a = tree[1]
+        acc = None
+        for j in range(1, len(a)):
+            if a[j] == 0.0:
+                continue
+            term = cheb_lift(ev, T[j], level, scale, a[j])
+            acc = term if acc is None else ev.add(acc, term)
+        if acc is None:
+            acc = cheb_lift(ev, T[1], level, scale, 0.0)
+        return ev.add_const(acc, a[0])
+    K, qt, rt = tree[1], tree[2], tree[3]
+    sigma = scale * ev.modulus(level) / T[K].scale
+    qc = _cheb_node(ev, qt, T, level + 1, sigma)
+    p = ev.rescale(ev.mul_relin(qc, ev.drop(T[K], level + 1)))
+    return ev.add(ev.with_scale(p, scale), _cheb_node(ev, rt, T, level, scale))
+
+
 def cheb_eval(ev, x, coeffs, mask_pt, delta):
     """Secure ReLU (the paper's algorithm): v = RS(x * mask) when a 1/beta
-    scale mask is given (beta > 1), else v = x; then sum_j c_j T_j(v) + c_0/2.
-    T_j for j in cheb_terms, ascending: the factors are aligned to the lower
-    level, prod = RS(Relin(T_a T_b)), T_j = prod + prod - 1 (j even) or
-    prod + prod + lift(v, -1) (j odd).  Every term c_j T_j is a lift onto one
-    common level (one below the deepest T_j) and scale delta; the terms are
-    added in ascending j and c_0 / 2 is added last."""
+    scale mask is given (beta > 1), else v = x; then f(v) = sum_j a_j T_j(v)
+    (a_0 = c_0 / 2) by baby-step giant-step Chebyshev evaluation:
+    * T_j for j in cheb_terms, ascending: factors aligned to the lower level,
+      prod = RS(Relin(T_a T_b)), T_j = prod + prod - 1 (j even) or
+      prod + prod + lift(v, -1) (j odd);
+    * the series is split recursively by the giant steps T_K
+      (a = q T_K + r, cheb_split) down to leaves of degree < CHEB_BABY;
+    * every subtree is evaluated onto a given (level, scale): a leaf as
+      sum_j lift(T_j, a_j) in ascending j plus a_0; a node as
+      with_scale(RS(Relin(q' T_K)), scale) + r', with q' evaluated one level
+      higher at scale * q_level / s(T_K) and r' at the node's own target;
+    * the root target is the highest level every subtree allows."""
     v = ev.rescale(ev.mul_plain(x, mask_pt)) if mask_pt is not None else x
     T = {1: v}
     for j in cheb_terms(coeffs)[1:]:
@@ -741,14 +839,8 @@ def cheb_eval(ev, x, coeffs, mask_pt, delta):
         p = ev.rescale(ev.mul_relin(ev.drop(T[a], lv), ev.drop(T[b], lv)))
         p2 = ev.add(p, p)
         T[j] = ev.add_const(p2, -1.0) if j % 2 == 0 else ev.add(p2, cheb_lift(ev, v, p2.level, p2.scale, -1.0))
-    lt = min(t.level for t in T.values()) - 1
-    acc = None
-    for j in sorted(T):
-        if coeffs[j] == 0.0:
-            continue
-        term = cheb_lift(ev, T[j], lt, delta, coeffs[j])
-        acc = term if acc is None else ev.add(acc, term)
-    return ev.add_const(acc, coeffs[0] / 2.0)
+    tree = cheb_tree(cheb_series(coeffs))
+    return _cheb_node(ev, tree, T, v.level + _allowed(tree, 0), delta)
 
 
 def cheb_scale_mask(beta, n, slots):

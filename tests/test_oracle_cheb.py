@@ -48,12 +48,29 @@ def test_degree59_approximates_relu():
 
 def test_terms_and_plan_closed_form():
     c = LY.cheb_relu_coeffs(1.0)
-    terms = LY.cheb_terms(c)
-    assert terms == list(range(1, 30)) + list(range(30, 59, 2))
-    assert LY.cheb_plan(c, True) == (8, 43) and LY.cheb_plan(c, False) == (7, 43)
+    # leaves use T_1, T_2, T_4, T_6 (odd coefficients vanish); giant steps T_8, T_16, T_32; T_3 is a factor of T_6
+    assert LY.cheb_terms(c) == [1, 2, 3, 4, 6, 8, 16, 32]
+    assert LY.cheb_plan(c, True) == (7, 14) and LY.cheb_plan(c, False) == (6, 14)
     assert [LY.cheb_depth(j) for j in (1, 2, 3, 4, 5, 8, 9, 16, 17, 32, 33, 58)] == [0, 1, 2, 2, 3, 3, 4, 4, 5, 5, 6, 6]
     # only T_1 and even T_j carry coefficients
     assert [j for j in range(60) if c[j] != 0.0] == [0, 1] + list(range(2, 59, 2))
+
+
+@pytest.mark.parametrize("degree", [40, 59, 100])
+def test_split_tree_reconstructs_the_series(degree):
+    """The recursive division by giant steps is an identity of polynomials
+    (checked by evaluating both sides at many points with numpy)."""
+    rng = np.random.default_rng(degree)
+    a = rng.normal(size=degree + 1)
+    x = np.linspace(-1, 1, 257)
+
+    def val(t):
+        if t[0] == "leaf":
+            return np.polynomial.chebyshev.chebval(x, t[1])
+        return val(t[2]) * np.polynomial.chebyshev.chebval(x, np.eye(t[1] + 1)[t[1]]) + val(t[3])
+
+    tree = LY.cheb_tree(a)
+    assert np.max(np.abs(val(tree) - np.polynomial.chebyshev.chebval(x, a))) < 1e-10 * np.abs(a).sum()
 
 
 @pytest.mark.parametrize("beta", [1.0, 4.0])
@@ -74,13 +91,13 @@ def test_sim_schedule_equals_clenshaw(beta):
 
 @pytest.mark.slow
 def test_he_config1_cheb_relu_decrypts():
-    """N=2^14, 8 limbs, beta = 1 (no mask): seven levels, level 8 -> 1."""
+    """N=2^14, 8 limbs, beta = 1 (no mask): six levels, level 8 -> 2."""
     name = "config1"
     octx, sk, _ = H.oracle_ctx(name)
     c = LY.cheb_relu_coeffs(1.0)
     v, ct = H.encrypt_slots(name, 71)
     ev = LY.HEEval(octx, {}, H.oracle_key(name, "relin"))
     y = LY.cheb_eval(ev, ct, c, None, octx.pr.scale)
-    assert y.level == 1 and ev.ks == 43
+    assert y.level == 2 and ev.ks == 14
     dec = octx.decrypt(sk, ckks.Ciphertext(y.data, y.scale))
     assert np.max(np.abs(dec - LY.cheb_relu_ref(v, 1.0))) < 1e-3

@@ -278,10 +278,10 @@ def layer_latencies(reps=3):
     out["resnet_fc_64x10_n16_ms"] = round(timed(lambda: c2.fc(ctf, 64, 10, fr, fmk, stream=s), reps, s) * 1e3, 3)
     # zero padding by masked taps: 7x7 / stride 2 / padding 3 (the ResNet-34 stem shape), 3 x 32 x 32 -> 8
     fmp = he.fmap(3, 32, 32)
-    pp = c2.conv2d_plan(fmp, 8, 7, 2, 3)
-    upload_synthetic_keys(c2, pp.keys(), 45)
+    p7 = c2.conv2d_plan(fmp, 8, 7, 2, 3)
+    upload_synthetic_keys(c2, p7.keys(), 45)
     ctp = synthetic_ct(c2, 24, 46, sc)
-    pk7, pm7 = synthetic_pts(c2, pp.n_kernel_pts, 24, 47, sc), synthetic_pts(c2, pp.n_mask_pts, 24, 48, sc)
+    pk7, pm7 = synthetic_pts(c2, p7.n_kernel_pts, 24, 47, sc), synthetic_pts(c2, p7.n_mask_pts, 24, 48, sc)
     out["conv7x7_s2_p3_3x32x32_n16_ms"] = round(
         timed(lambda: c2.conv2d(ctp, fmp, 8, 7, 2, 3, pk7, pm7, stream=s), reps, s) * 1e3, 3)
     del pk7, pm7
@@ -294,7 +294,7 @@ def layer_latencies(reps=3):
     out["key_switches"] = {"conv3x3_n12": 8, "lenet5_stack": pc.key_switches + pp.key_switches + 2,
                            "resnet_convA": pa.key_switches, "resnet_convB": pb.key_switches,
                            "resnet_gap": pg.key_switches, "resnet_fc": pf.key_switches,
-                           "conv7x7_s2_p3": pp.key_switches, "relu_cheb59": he.cheb_plan(cheb, True)[1]}
+                           "conv7x7_s2_p3": p7.key_switches, "relu_cheb59": he.cheb_plan(cheb, True)[1]}
     c2.close()
     return out
 

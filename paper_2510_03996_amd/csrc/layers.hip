@@ -440,14 +440,67 @@ static int fc_plan_impl(int n_in, int n_out, he_layer_plan* pl) {
 }
 
 // ---------------------------------------------------------------- Chebyshev secure ReLU
-// Terms T_j (j >= 1) the evaluation computes, ascending: every j with a
-// nonzero coefficient and, recursively, the factors of the product rule
+// Baby-step giant-step evaluation of f = sum_j a_j T_j (a_0 = c_0 / 2): the
+// series is divided recursively by giant steps T_K (K = 8 2^m, the largest
+// not above the degree; T_{K+i} = 2 T_K T_i - T_{K-i}) down to leaves of
+// degree below 8, and every subtree is evaluated directly onto a target
+// level and scale.
+constexpr int CHEB_BABY = 8;
+
+struct ChebNode {
+  int K = 0;              // 0: leaf
+  std::vector<double> a;  // leaf coefficients
+  int q = -1, r = -1;     // children (quotient, remainder)
+};
+
+static int cheb_build(std::vector<ChebNode>& t, std::vector<double> a) {
+  int d = (int)a.size() - 1;
+  while (d > 0 && a[d] == 0.0) d--;
+  a.resize(d + 1);
+  const int id = (int)t.size();
+  t.emplace_back();
+  if (d < CHEB_BABY) {
+    t[id].a = a;
+    return id;
+  }
+  int K = CHEB_BABY;
+  while (2 * K <= d) K *= 2;
+  std::vector<double> q(d - K + 1), r(a.begin(), a.begin() + K);
+  q[0] = a[K];
+  for (int i = 1; i <= d - K; i++) q[i] = 2.0 * a[K + i];
+  for (int i = 2 * K - d; i < K; i++) r[i] = a[i] - a[2 * K - i];
+  const int qi = cheb_build(t, q);
+  const int ri = cheb_build(t, r);
+  t[id].K = K;
+  t[id].q = qi;
+  t[id].r = ri;
+  return id;
+}
+
+static std::vector<ChebNode> cheb_tree(const double* cf, int degree) {
+  std::vector<double> a(cf, cf + degree + 1);
+  a[0] = a[0] / 2.0;
+  std::vector<ChebNode> t;
+  cheb_build(t, a);
+  return t;
+}
+
+static int cheb_depth(int j) { return j <= 1 ? 0 : 32 - __builtin_clz((unsigned)(j - 1)); }
+
+// T_j (j >= 1) the evaluation computes, ascending: the leaves' nonzero terms,
+// T_1, the giant steps and, recursively, the factors of the product rule
 // T_{2k} = 2 T_k^2 - 1, T_{2k+1} = 2 T_k T_{k+1} - T_1.
-static std::vector<int> cheb_terms(const double* cf, int degree) {
-  std::vector<char> need(degree + 1, 0);
+static std::vector<int> cheb_terms(const std::vector<ChebNode>& tree) {
+  int maxj = 1;
+  for (auto& n : tree) maxj = std::max(maxj, n.K ? n.K : (int)n.a.size() - 1);
+  std::vector<char> need(maxj + 1, 0);
   std::vector<int> stack{1};
-  for (int j = 1; j <= degree; j++)
-    if (cf[j] != 0.0) stack.push_back(j);
+  for (auto& n : tree) {
+    if (n.K) stack.push_back(n.K);
+    else
+      for (int j = 1; j < (int)n.a.size(); j++)
+        if (n.a[j] != 0.0) stack.push_back(j);
+  }
   while (!stack.empty()) {
     const int j = stack.back();
     stack.pop_back();
@@ -459,22 +512,33 @@ static std::vector<int> cheb_terms(const double* cf, int degree) {
     }
   }
   std::vector<int> out;
-  for (int j = 1; j <= degree; j++)
+  for (int j = 1; j <= maxj; j++)
     if (need[j]) out.push_back(j);
   return out;
 }
-static int cheb_depth(int j) { return j <= 1 ? 0 : 32 - __builtin_clz((unsigned)(j - 1)); }
+
+// highest level subtree `id` can be evaluated onto (T_j at level top - depth(j))
+static int cheb_allowed(const std::vector<ChebNode>& t, int id, int top) {
+  const ChebNode& n = t[id];
+  if (!n.K) {
+    int lv = INT32_MAX;
+    for (int j = 1; j < (int)n.a.size(); j++)
+      if (n.a[j] != 0.0) lv = std::min(lv, top - cheb_depth(j) - 1);
+    return lv == INT32_MAX ? top - 1 : lv;
+  }
+  return std::min(top - cheb_depth(n.K) - 1, std::min(cheb_allowed(t, n.q, top) - 1, cheb_allowed(t, n.r, top)));
+}
 
 static int cheb_plan_impl(const double* cf, int degree, int masked, int* levels, int* relins) {
   if (!cf || degree < 1 || degree > HE_CHEB_MAX_DEGREE) return set_error(HE_EINVAL, "degree must be in [1, 255]");
   bool any = false;
   for (int j = 1; j <= degree; j++) any = any || cf[j] != 0.0;
   if (!any) return set_error(HE_EINVAL, "every coefficient of degree >= 1 is zero");
-  const std::vector<int> t = cheb_terms(cf, degree);
-  int depth = 0;
-  for (int j : t) depth = std::max(depth, cheb_depth(j));
-  *levels = (masked ? 1 : 0) + depth + 1;
-  *relins = (int)t.size() - 1;
+  const std::vector<ChebNode> tree = cheb_tree(cf, degree);
+  int nodes = 0;
+  for (auto& n : tree) nodes += n.K != 0;
+  *levels = (masked ? 1 : 0) - cheb_allowed(tree, 0, 0);
+  *relins = (int)cheb_terms(tree).size() - 1 + nodes;
   return HE_OK;
 }
 
@@ -487,6 +551,40 @@ static he_ct cheb_lift(Ev& ev, const he_ct& v, int level, double scale, double c
   he_ct t = ev.rescale_take(ev.mul_const(Ev::drop(v, level + 1), c, scale * q / v.scale));
   t.scale = scale;
   return t;
+}
+
+// subtree `id` evaluated onto (level, scale): a leaf as sum_j lift(T_j, a_j)
+// (ascending j; lift(T_1, 0) if it has none) plus a_0; a node as
+// RS(Relin(q' T_K)) with scale `scale` plus r', q' evaluated one level higher
+// at scale q_level / s(T_K) times `scale`, r' onto (level, scale)
+static he_ct cheb_eval_node(Ev& ev, const std::vector<ChebNode>& t, int id, const std::vector<he_ct>& T, int level,
+                            double scale) {
+  const ChebNode& n = t[id];
+  if (!n.K) {
+    he_ct acc{};
+    bool first = true;
+    for (int j = 1; j < (int)n.a.size(); j++) {
+      if (n.a[j] == 0.0) continue;
+      he_ct term = cheb_lift(ev, T[j], level, scale, n.a[j]);
+      if (first) {
+        acc = term;
+        first = false;
+      } else {
+        acc = ev.add_take(acc, term);
+      }
+    }
+    if (first) acc = cheb_lift(ev, T[1], level, scale, 0.0);
+    he_ct y = ev.add_const(acc, n.a[0]);
+    ev.release(acc);
+    return y;
+  }
+  const double sigma = scale * (double)ev.c->mod[level] / T[n.K].scale;
+  he_ct qc = cheb_eval_node(ev, t, n.q, T, level + 1, sigma);
+  he_ct p = ev.rescale_take(ev.mul_relin(qc, Ev::drop(T[n.K], level + 1)));
+  ev.release(qc);
+  p.scale = scale;
+  he_ct rc = cheb_eval_node(ev, t, n.r, T, level, scale);
+  return ev.add_take(p, rc);
 }
 
 }  // namespace he
@@ -681,7 +779,8 @@ int he_cheb(he_ctx* h, const he_ct* in, const he_pt* scale_mask, const double* c
   if (scale_mask && (rc = check_pts(c, scale_mask, 1, in->level, "scale_mask"))) return rc;
   if ((rc = check_out(c, out, in->level - levels))) return rc;
   if (!key_known(c, HE_KEY_RELIN)) return set_error(HE_ENOKEY, "relinearization key not resident");
-  const std::vector<int> terms = cheb_terms(cf, degree);
+  const std::vector<ChebNode> tree = cheb_tree(cf, degree);
+  const std::vector<int> terms = cheb_terms(tree);
   return guarded([&] {
     Ev ev(h, s);
     const he_ct v = scale_mask ? ev.rescale_take(ev.mul(*in, *scale_mask)) : *in;
@@ -706,22 +805,7 @@ int he_cheb(he_ctx* h, const he_ct* in, const he_pt* scale_mask, const double* c
       ev.release(p2);
       have[j] = 1;
     }
-    int lt = T[1].level;
-    for (int j : terms) lt = std::min(lt, T[j].level);
-    lt -= 1;
-    he_ct acc{};
-    bool first = true;
-    for (int j : terms) {
-      if (cf[j] == 0.0) continue;
-      he_ct term = cheb_lift(ev, T[j], lt, delta, cf[j]);
-      if (first) {
-        acc = term;
-        first = false;
-      } else {
-        acc = ev.add_take(acc, term);
-      }
-    }
-    he_ct y = ev.add_const(acc, cf[0] / 2.0);
+    he_ct y = cheb_eval_node(ev, tree, 0, T, v.level + cheb_allowed(tree, 0, 0), delta);
     ev.copy_out(y, out);
     return HE_OK;
   });

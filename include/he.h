@@ -309,12 +309,18 @@ int he_poly4(he_ctx* ctx, const he_ct* in, const double* c, double delta, he_ct*
  * slots, encoded by the caller at scale delta; NULL when beta <= 1) the
  * input is first multiplied by it and rescaled; then
  *   y = c_0 / 2 + sum_{j=1..degree} c_j T_j(v)
- * is evaluated.  T_j are built by the product rule T_{2k} = 2 T_k^2 - 1,
- * T_{2k+1} = 2 T_k T_{k+1} - T_1 (only the terms with nonzero coefficients
- * and their factors, each product relinearized and rescaled); every term
- * c_j T_j is brought to one common level with tracked scale delta by a
- * constant multiplication encoded at delta q / scale(T_j), and c_0 / 2 is
- * added last.  Levels consumed and relinearizations: he_cheb_plan.  out
+ * is evaluated by baby-step giant-step division: the series is split
+ * recursively as q T_K + r by giant steps T_K (K = 8 * 2^m, the largest not
+ * above the degree of the part being split; T_{K+i} = 2 T_K T_i - T_{K-i})
+ * down to leaves of degree below 8.  The T_j needed (leaf terms with nonzero
+ * coefficients, T_1, the giant steps and their factors) are built by
+ * T_{2k} = 2 T_k^2 - 1, T_{2k+1} = 2 T_k T_{k+1} - T_1, each product
+ * relinearized and rescaled.  Each subtree is evaluated onto a target level
+ * and scale: a leaf as sum c_j T_j, each term by a constant multiplication
+ * encoded at target * q / scale(T_j), plus its constant; a node as
+ * RS(Relin(q' T_K)) + r' with q' evaluated one level higher.  Degree 59 with
+ * a mask: 14 relinearizations, 7 levels.  Levels consumed and
+ * relinearizations: he_cheb_plan.  out
  * gets level in->level - levels, scale delta.  HE_ELEVEL without enough
  * levels, HE_ENOKEY without the relinearization key, HE_EINVAL for a degree
  * outside [1, HE_CHEB_MAX_DEGREE] or when every c_j (j >= 1) is zero. */

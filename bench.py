@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="budget for the CPU baseline sample")
     ap.add_argument("--only-headline", action="store_true", help="skip layers / batched / serving sections")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run three 256 MiB device-to-device copies (the reference kernel that scales "
+                         "the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     ap.add_argument("--only", choices=["hoisted", "layers", "batched", "serving"], default=None,
                     help="run the headline plus one section (profiling runs)")
     ap.add_argument("--serve-requests", type=int, default=60)
@@ -466,6 +469,14 @@ def main():
     import torch
 
     torch.cuda.init()
+    if args.copy_calibration:
+        src = torch.ones(1 << 25, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 8, "copies": 3}), flush=True)
+        return
     log("headline: plain key-switch rotations")
     rot_s, el, roof, kern, ks_bytes, (L, K, dnum) = headline(args)
     result = {

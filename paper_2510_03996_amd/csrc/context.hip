@@ -472,6 +472,9 @@ int he_ctx_create(const he_params* p, int device, he_ctx** out) {
   if (e != hipSuccess) return hip_error(e, "hipSetDevice");
   he_ctx* h = new he_ctx();
   h->c.device = device;
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+    h->c.lds_per_block = (size_t)lds;
   int rc = ctx_init(&h->c, p);
   if (rc) {
     he_ctx_destroy(h);

@@ -100,6 +100,7 @@ struct Ctx {
   std::map<hipStream_t, Lane*> lanes;
   std::mutex lanes_mu;
   bool prof_on = false;
+  size_t lds_per_block = 65536;  // device limit on a workgroup's LDS (bytes)
   // NTT variant (log2 residues per thread) per batch-size bucket (<= 8, 16,
   // 32, more limbs), chosen by the autotuner at context creation
   int ntt_var[4] = {0, 0, 0, 2};           // NTT variant per batch-size bucket
@@ -172,6 +173,27 @@ struct NttEpi {
   int32_t level;
 };
 int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& map, const NttEpi& epi, hipStream_t s);
+// Key inner product fused into the last forward pass of ModUp (one key
+// switch): for every ext position pos < E = level + K and both key polys j,
+//   u_j[pos][k] = sum_d e_d[pos][src(k)] key_d[j][mod(pos)][k] 2^-64 mod q
+// with e_d the NTT form of digit d's extension (the own limb read from c1),
+// src the automorphism phi_g (g = 1: identity) and the key in Montgomery form.
+struct NttIp {
+  const uint64_t* ext;  // [dnum][E][N] converted limbs after forward pass 1
+  size_t ext_ds;
+  const uint64_t* c1;   // [level][N], NTT form
+  const uint64_t* key;  // [dnum][2][L+K][N], Montgomery form
+  size_t key_ds, key_ps;
+  uint64_t* u;          // [2][E][N]
+  size_t u_ps;
+  int32_t alpha, dnum, level;
+  uint32_t g;
+};
+int ntt_launch_modup_ip(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
+                        hipStream_t s);
+constexpr int NTT_IP_MAXD = 4;  // digits the fused kernel handles (one thread group each)
+// whether the fused kernel fits this ring and digit count (threads, LDS)
+bool ntt_ip_supported(const Ctx* c, int dnum);
 void ntt_variant_shape(int v, int* tile, int* per_thread);
 // positions 0..l-1 -> q_0..q_{l-1}, positions l..l+K-1 -> p_0..p_{K-1}
 LimbMap ext_map(const Ctx* c, int level);
@@ -202,6 +224,10 @@ int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s);
 // digits, ModDown, and out0 = add0[phi_g] + u0', out1 = add1 + u1'.
 int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
              const uint64_t* add0, const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s);
+// the same key switch without a separate ModUp: ModUp's last NTT pass
+// computes the inner product (NttIp), so the extended digits stay on chip
+int ks_single(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
+              const uint64_t* add0, const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s);
 // key cache (keys.hip): known = resident or loadable; acquire makes the key
 // usable by work enqueued next on s (loading and evicting as needed, nullptr
 // with the error set when that fails); note_use records its last use on s

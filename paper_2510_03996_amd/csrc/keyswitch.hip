@@ -111,7 +111,8 @@ __global__ __launch_bounds__(256) void k_to_mont(uint64_t* key, int M, int logn,
 // Digits of c1 (NTT form, `level` limbs) basis-extended to Q_l u P: the
 // digits' own limbs stay in c1; every other limb of digit j is written to
 // w.ext + j (level+K) N in NTT form.
-int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) {
+// iNTT of c1's digits and their basis conversion (coefficient form) into w.ext
+static int ks_modup_convert(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) {
   const size_t N = c->n;
   const size_t E = (size_t)(level + c->K);
   int rc;
@@ -125,23 +126,22 @@ int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) 
     k_bconv<<<grid, 256, 0, s>>>(w.coeff, 0, w.ext, E * N, set.d, set.count, c->d_mod, c->log_n);
   }
   HE_HIP(hipGetLastError());
+  return HE_OK;
+}
+
+int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) {
+  int rc;
+  if ((rc = ks_modup_convert(c, w, c1, level, s))) return rc;
   return ntt_launch(c, w.ext, 0, 1, c->modup_ntt[level], false, s);
 }
 
-int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
-             const uint64_t* add0, const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s) {
+// ModDown of w.u (both polynomials) and the final additions
+static int ks_moddown(Ctx* c, const WS& w, int level, uint32_t g, const uint64_t* add0, const uint64_t* add1,
+                      uint64_t* out0, uint64_t* out1, hipStream_t s) {
   const size_t N = c->n;
   const int K = c->K, L = c->L;
   const size_t E = (size_t)(level + K);
-  const size_t kps = (size_t)(L + K) * N;  // key poly stride
   int rc;
-  const int dn = c->dnum(level);
-  {
-    ProfScope ps(c, "ks_inner_product", s, 8.0 * N * E * (3.0 * dn + 2), 2.0 * dn * E * N);
-    k_ip<<<dim3(N / 256, E), 256, 0, s>>>(w.ext, E * N, c1, c->alpha, dn, key, 2 * kps, kps, level, L, g,
-                                          c->log_n, c->d_mod, w.u, E * N);
-  }
-  HE_HIP(hipGetLastError());
   // ModDown of u0 and u1: P limbs to coefficient form, convert to Q_l, back to NTT form
   if ((rc = ntt_launch(c, w.u, E * N, 2, range_map(level, K, L), true, s))) return rc;
   const BConvSet& set = c->moddown[level];
@@ -168,6 +168,51 @@ int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t*
   return HE_OK;
 }
 
+int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
+             const uint64_t* add0, const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s) {
+  const size_t N = c->n;
+  const int K = c->K, L = c->L;
+  const size_t E = (size_t)(level + K);
+  const size_t kps = (size_t)(L + K) * N;  // key poly stride
+  const int dn = c->dnum(level);
+  {
+    ProfScope ps(c, "ks_inner_product", s, 8.0 * N * E * (3.0 * dn + 2), 2.0 * dn * E * N);
+    k_ip<<<dim3(N / 256, E), 256, 0, s>>>(w.ext, E * N, c1, c->alpha, dn, key, 2 * kps, kps, level, L, g,
+                                          c->log_n, c->d_mod, w.u, E * N);
+  }
+  HE_HIP(hipGetLastError());
+  return ks_moddown(c, w, level, g, add0, add1, out0, out1, s);
+}
+
+int ks_single(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
+              const uint64_t* add0, const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s) {
+  const size_t N = c->n;
+  const int K = c->K, L = c->L;
+  const size_t E = (size_t)(level + K);
+  const size_t kps = (size_t)(L + K) * N;
+  int rc;
+  if (!ntt_ip_supported(c, c->dnum(level))) {
+    if ((rc = ks_modup(c, w, c1, level, s))) return rc;
+    return ks_apply(c, w, c1, level, key, g, add0, add1, out0, out1, s);
+  }
+  if ((rc = ks_modup_convert(c, w, c1, level, s))) return rc;
+  NttIp ip{};
+  ip.ext = w.ext;
+  ip.ext_ds = E * N;
+  ip.c1 = c1;
+  ip.key = key;
+  ip.key_ds = 2 * kps;
+  ip.key_ps = kps;
+  ip.u = w.u;
+  ip.u_ps = E * N;
+  ip.alpha = c->alpha;
+  ip.dnum = c->dnum(level);
+  ip.level = level;
+  ip.g = g;
+  if ((rc = ntt_launch_modup_ip(c, w.ext, c->modup_ntt[level], ext_map(c, level), ip, s))) return rc;
+  return ks_moddown(c, w, level, g, add0, add1, out0, out1, s);
+}
+
 
 
 
@@ -186,12 +231,12 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
   if ((rc = check_ct(c, in, "in"))) return rc;
   const int l = in->level;
   const size_t N = c->n;
-  bool any = false;
+  int nks = 0;  // rotations that need a key switch
   for (int t = 0; t < n; t++) {
     if ((rc = check_out(c, &outs[t], l))) return rc;
     if (outs[t].data == in->data) return set_error(HE_EINVAL, "output aliases the input");
     if (norm_key_id(c, r[t]) != 0) {
-      any = true;
+      nks++;
       if (!key_known(c, r[t])) return set_error(HE_ENOKEY, "rotation key " + std::to_string(r[t]) + " not resident");
     }
   }
@@ -201,7 +246,9 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
   WS w = ws_layout(c, lane->ws);
   const uint64_t* c0 = in->data;
   const uint64_t* c1 = in->data + (size_t)in->cap * N;
-  if (any && (rc = ks_modup(c, w, c1, l, s))) return rc;
+  // one key switch: the inner product is fused into ModUp's last NTT pass;
+  // several: one ModUp shared by all of them (hoisting)
+  if (nks > 1 && (rc = ks_modup(c, w, c1, l, s))) return rc;
   for (int t = 0; t < n; t++) {
     he_ct& o = outs[t];
     uint64_t* o0 = o.data;
@@ -212,7 +259,9 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
     } else {
       const uint64_t* key = key_acquire(c, r[t], s);
       if (!key) return HE_ENOMEM;
-      if ((rc = ks_apply(c, w, c1, l, key, galois_elt(c, r[t]), c0, nullptr, o0, o1, s))) return rc;
+      rc = nks == 1 ? ks_single(c, w, c1, l, key, galois_elt(c, r[t]), c0, nullptr, o0, o1, s)
+                    : ks_apply(c, w, c1, l, key, galois_elt(c, r[t]), c0, nullptr, o0, o1, s);
+      if (rc) return rc;
       key_note_use(c, r[t], s);
     }
     o.level = l;
@@ -240,10 +289,9 @@ int he_relin(he_ctx* h, const uint64_t* d, int level, double scale, he_ct* out, 
   const uint64_t* d0 = d;
   const uint64_t* d1 = d + (size_t)level * N;
   const uint64_t* d2 = d + 2 * (size_t)level * N;
-  if ((rc = ks_modup(c, w, d2, level, s))) return rc;
   const uint64_t* key = key_acquire(c, HE_KEY_RELIN, s);
   if (!key) return HE_ENOMEM;
-  if ((rc = ks_apply(c, w, d2, level, key, 1, d0, d1, out->data, out->data + (size_t)out->cap * N, s))) return rc;
+  if ((rc = ks_single(c, w, d2, level, key, 1, d0, d1, out->data, out->data + (size_t)out->cap * N, s))) return rc;
   key_note_use(c, HE_KEY_RELIN, s);
   out->level = level;
   out->scale = scale;

@@ -142,6 +142,106 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
   }
 }
 
+// Forward rounds IDX..NR-1 run by the waves with `act` set; every wave of
+// the workgroup passes the same barriers.
+template <class P, int IDX, class T, class TW, class Q>
+__device__ __forceinline__ void rounds_fwd_if(bool act, T* lds, int tid, int wg, const TW* tw, const TW* twp, Q q,
+                                              Q qinv) {
+  if constexpr (IDX < P::NR) {
+    if constexpr (IDX > 0) __syncthreads();
+    if (act) {
+      if constexpr (std::is_same<T, double>::value)
+        P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
+      else
+        P::template round<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
+    }
+    rounds_fwd_if<P, IDX + 1>(act, lds, tid, wg, tw, twp, q, qinv);
+  }
+}
+
+// Key-switch inner product fused into the last forward pass of ModUp (one
+// key switch, so one automorphism and one key).  Workgroup (x, z) owns output
+// tile x of ext limb map[z]: phi_g maps aligned blocks of TILE positions onto
+// aligned blocks, so the values it needs form one source tile.  The
+// workgroup has one group of P::THREADS threads (whole waves) per digit d,
+// each with its own LDS tile: group d loads digit d's source tile and
+// finishes its transform (the own digit's limb is c1 itself, already in NTT
+// form, and is only loaded); then every thread accumulates
+// e_d[src(k)] * key_d[j][pos][k] over the digits for both key polynomials j
+// in 128-bit registers.  The extended digits never return to HBM.
+template <int LOGN, int LOG_EPT, int LOG_TILE, int MAXD>
+__global__ __launch_bounds__(MAXD * 256) void ntt_ip_kernel(LimbMap map, const uint64_t* __restrict__ tw_all,
+                                                      const uint64_t* __restrict__ twp_all,
+                                                      const double* __restrict__ dtw_all,
+                                                      const double* __restrict__ dtwq_all,
+                                                      const ModInfo* __restrict__ mods, NttIp ip) {
+  using P = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
+  extern __shared__ uint64_t lds_all[];  // [dnum][P::LDS_WORDS]
+  const int tid = threadIdx.x;
+  const int nthr = blockDim.x;          // dnum * P::THREADS
+  const int d = tid / P::THREADS;       // wave-uniform
+  const int t = tid - d * P::THREADS;
+  const int m = __builtin_amdgcn_readfirstlane(map.mod[blockIdx.z]);
+  const int pos = __builtin_amdgcn_readfirstlane(map.pos[blockIdx.z]);
+  const ModInfo mi = mods[m];
+  const uint64_t q = mi.q;
+  const uint32_t out0 = blockIdx.x * P::TILE;
+  const uint32_t src0 = automorph_src(out0, ip.g, LOGN) & ~(uint32_t)(P::TILE - 1);
+  const int swg = (int)(src0 / P::TILE);
+  const size_t off = (size_t)pos << LOGN;
+  const bool own = pos < ip.level && pos / ip.alpha == d;
+  const uint64_t* ain = own ? ip.c1 + off : ip.ext + d * ip.ext_ds + off;
+  uint64_t* lds = lds_all + d * P::LDS_WORDS;
+  const bool f64 = mi.k <= 50;  // uniform over the workgroup
+  const int dn = ip.dnum;
+  const uint64_t* key = ip.key + ((size_t)m << LOGN) + out0;
+  if (f64) {
+    double* dl = reinterpret_cast<double*>(lds);
+    for (int e = t; e < P::TILE; e += P::THREADS) {
+      int g, k;
+      P::tile_elem(e, g, k);
+      const uint64_t w = ain[P::gidx(swg, g, k)];
+      dl[P::lidx(g, k)] = own ? u52_to_f64(w) : P::load_f64(w);
+    }
+    __syncthreads();
+    rounds_fwd_if<P, 0>(!own, dl, t, swg, dtw_all + (size_t)m * P::N, dtwq_all + (size_t)m * P::N, (double)q,
+                        mi.dqinv);
+  } else {
+    for (int e = t; e < P::TILE; e += P::THREADS) {
+      int g, k;
+      P::tile_elem(e, g, k);
+      lds[P::lidx(g, k)] = ain[P::gidx(swg, g, k)];
+    }
+    __syncthreads();
+    rounds_fwd_if<P, 0>(!own, lds, t, swg, tw_all + (size_t)m * P::N, twp_all + (size_t)m * P::N, q, q);
+  }
+  __syncthreads();
+  uint64_t* u = ip.u + off + out0;
+  for (int e = tid; e < P::TILE; e += nthr) {
+    const uint32_t k = out0 + e;
+    const int sl = (int)((ip.g == 1 ? k : automorph_src(k, ip.g, LOGN)) - src0);
+    const int li = P::lidx(sl / P::M, sl % P::M);
+    uint64_t k0[MAXD], k1[MAXD];
+#pragma unroll
+    for (int j = 0; j < MAXD; j++)
+      if (j < dn) {
+        k0[j] = key[j * ip.key_ds + e];
+        k1[j] = key[j * ip.key_ds + ip.key_ps + e];
+      }
+    U128 a0{0, 0}, a1{0, 0};
+#pragma unroll
+    for (int j = 0; j < MAXD; j++)
+      if (j < dn) {
+        const uint64_t w = lds_all[j * P::LDS_WORDS + li];
+        const uint64_t v = f64 ? f64_to_u52(canon_f64(bits_to_f64(w), mi.dqinv, (double)q)) : P::finish(w, 0, 0, q);
+        add_wide(a0, mul_wide(v, k0[j]));
+        add_wide(a1, mul_wide(v, k1[j]));
+      }
+    u[e] = mont_redc(a0, q, mi.qinv);
+    u[ip.u_ps + e] = mont_redc(a1, q, mi.qinv);
+  }
+}
+
 template <int LOGN, int LOG_EPT, int LOG_TILE>
 static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
                         int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr) {
@@ -324,6 +424,82 @@ int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& ma
     case 12: return ntt_launch_n<12>(c, yy, y_bs, yy, y_bs, 2, map, false, s, &epi);
     case 14: return ntt_launch_n<14>(c, yy, y_bs, yy, y_bs, 2, map, false, s, &epi);
     case 16: return ntt_launch_n<16>(c, yy, y_bs, yy, y_bs, 2, map, false, s, &epi);
+  }
+  return set_error(HE_EINVAL, "unsupported ring degree");
+}
+
+// ModUp's forward transform with the key inner product fused into its last
+// pass: pass 1 over every converted limb (`conv`, ext-relative positions),
+// then ntt_ip_kernel over the E = level + K output limbs (`outs`).
+template <int LOGN, int LOG_EPT, int LOG_TILE>
+static int ntt_ip_launch_v(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
+                           hipStream_t s) {
+  using P1 = NttPass<LOGN, 1, false, LOG_EPT, LOG_TILE>;
+  using P2 = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
+  const double N = (double)P1::N;
+  double nf = 0, nconv_f = 0;
+  if (c->prof_on) {
+    for (int i = 0; i < conv.n; i++) nconv_f += c->hmod[conv.mod[i]].k <= 50;
+    for (int i = 0; i < outs.n; i++) nf += c->hmod[outs.mod[i]].k <= 50;
+  }
+  {
+    const double mm = N / 2 * P1::LM * conv.n;
+    ProfScope ps(c, "ntt_fwd_pass1", s, 16.0 * N * conv.n, mm,
+                 N / 2 * P1::LM * (nconv_f / PEAK_MODMUL_F64 + (conv.n - nconv_f) / PEAK_MODMUL_INT));
+    ntt_pass_kernel<LOGN, 1, false, LOG_EPT, LOG_TILE, false><<<dim3(P1::WG_PER_LIMB, 1, conv.n), P1::THREADS, 0, s>>>(
+        ext, 0, ext, 0, conv, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, NttEpi{});
+  }
+  {
+    // reads: converted limbs, own limbs of c1, 2 dnum key limbs per output limb; writes: 2 output limbs
+    const double own = ip.level;
+    const double bytes = 8.0 * N * (conv.n + own + 2.0 * ip.dnum * outs.n + 2.0 * outs.n);
+    const double mm_ntt = N / 2 * P2::LM * conv.n, mm_ip = 2.0 * ip.dnum * N * outs.n;
+    const double ideal = N / 2 * P2::LM * (nconv_f / PEAK_MODMUL_F64 + (conv.n - nconv_f) / PEAK_MODMUL_INT) +
+                         mm_ip / PEAK_MODMUL_INT;
+    ProfScope ps(c, "ntt_fwd_pass2_ip", s, bytes, mm_ntt + mm_ip, ideal);
+    const dim3 grid(P2::WG_PER_LIMB, 1, outs.n);
+    const size_t lds = (size_t)ip.dnum * P2::LDS_WORDS * 8;
+    if (ip.dnum <= 3)
+      ntt_ip_kernel<LOGN, LOG_EPT, LOG_TILE, 3><<<grid, ip.dnum * P2::THREADS, lds, s>>>(
+          outs, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, ip);
+    else
+      ntt_ip_kernel<LOGN, LOG_EPT, LOG_TILE, 4><<<grid, ip.dnum * P2::THREADS, lds, s>>>(
+          outs, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, ip);
+  }
+  HE_HIP(hipGetLastError());
+  return HE_OK;
+}
+
+// The fused kernel runs one 256-thread group per digit: tile 2048 with 8
+// residues per thread.
+template <int LOGN>
+static int ntt_ip_launch_n(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
+                           hipStream_t s) {
+  return ntt_ip_launch_v<LOGN, 3, 11>(c, ext, by_modulus(c, conv), by_modulus(c, outs), ip, s);
+}
+
+bool ntt_ip_supported(const Ctx* c, int dnum) {
+  using P16 = NttPass<16, 2, false, 3, 11>;
+  static_assert(P16::THREADS == 256 && NttPass<14, 2, false, 3, 11>::THREADS == 256 &&
+                    NttPass<12, 2, false, 3, 11>::THREADS == 256,
+                "one 256-thread group per digit");
+  size_t words = 0;
+  switch (c->log_n) {
+    case 12: words = NttPass<12, 2, false, 3, 11>::LDS_WORDS; break;
+    case 14: words = NttPass<14, 2, false, 3, 11>::LDS_WORDS; break;
+    case 16: words = P16::LDS_WORDS; break;
+    default: return false;
+  }
+  return dnum >= 1 && dnum <= NTT_IP_MAXD && (size_t)dnum * words * 8 <= c->lds_per_block;
+}
+
+int ntt_launch_modup_ip(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
+                        hipStream_t s) {
+  if (conv.n <= 0 || outs.n <= 0) return HE_OK;
+  switch (c->log_n) {
+    case 12: return ntt_ip_launch_n<12>(c, ext, conv, outs, ip, s);
+    case 14: return ntt_ip_launch_n<14>(c, ext, conv, outs, ip, s);
+    case 16: return ntt_ip_launch_n<16>(c, ext, conv, outs, ip, s);
   }
   return set_error(HE_EINVAL, "unsupported ring degree");
 }

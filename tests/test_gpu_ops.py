@@ -138,6 +138,28 @@ def test_rotate_single(gctx, name):
 
 
 @pytest.mark.parametrize("name", CONFIGS)
+def test_rotate_single_every_key(gctx, name):
+    """One key switch per call takes the path with the inner product fused
+    into ModUp's last NTT pass: every rotation of the set (its own Galois
+    element, so its own tile mapping), and a hoisted call with one non-zero
+    rotation."""
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    keys = H.oracle_keys(name, ROTS[name])
+    for r, k in keys.items():
+        g.key_upload(r, k)
+    _, a = H.encrypt_slots(name, 14)
+    ga = g.ct_from_numpy(a.data, a.scale)
+    for r in ROTS[name]:
+        H.assert_limbs_equal(g.rotate(ga, r).numpy(), octx.rotate(a, r, {r: keys[r]}).data, "rotate %d" % r)
+    r = ROTS[name][-1]
+    got = g.rotate_hoisted(ga, [0, r])
+    want = octx.rotate_hoisted(a, [0, r], {r: keys[r]})
+    for x, y in zip(got, want):
+        H.assert_limbs_equal(x.numpy(), y.data, "hoisted [0, %d]" % r)
+
+
+@pytest.mark.parametrize("name", CONFIGS)
 def test_rotate_hoisted(gctx, name):
     g = gctx(name)
     octx, _, _ = H.oracle_ctx(name)

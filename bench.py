@@ -4,8 +4,8 @@
 Headline (``value``): key-switch rotations/s at N=2^16, L=24 — a step is one
 batch of ROT_PER_STEP plain slot rotations (Galois automorphism + hybrid key
 switching: ModUp -> key inner product -> ModDown) of one ciphertext at the
-top level (one 60-bit + 23 50-bit primes, K=8 60-bit special primes,
-dnum=3), cycling through three resident rotation keys (3 x 96 MiB, more than
+top level (one 60-bit + 23 50-bit primes, K=9 50-bit special primes,
+dnum=3), cycling through three resident rotation keys (3 x 99 MiB, more than
 the 256 MB Infinity Cache) so keys stream from HBM.
 
 Measured in the same run and reported beside it:
@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 
 CFG0 = dict(log_n=12, q_bits=[54, 40, 40], p_bits=[55], alpha=1)
 CFG1 = dict(log_n=14, q_bits=[60] + [45] * 7, p_bits=[60, 60], alpha=2)
-CFG2 = dict(log_n=16, q_bits=[60] + [50] * 23, p_bits=[60] * 8, alpha=8)
+CFG2 = dict(log_n=16, q_bits=[60] + [50] * 23, p_bits=[50] * 9, alpha=8)
 ROTATIONS = [1, -1, 32]
 ROT_PER_STEP = 48
 HBM_PEAK_GBS = 8000.0
@@ -458,7 +458,7 @@ def cpu_baseline(budget_s):
             break
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": round(done / el, 3), "unit": "rotations/s", "cores": threads, "kind": "oracle",
-            "sample": "%d single key-switch rotations at N=2^16 L=24 K=8 dnum=3 (%.1f s)" % (done, el)}
+            "sample": "%d single key-switch rotations at N=2^16 L=24 K=9 dnum=3 (%.1f s)" % (done, el)}
 
 
 def main():
@@ -492,7 +492,7 @@ def main():
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "plain he_rotate, one ciphertext at a time, N=2^16 L=24 K=8 dnum=3, "
+        "config": {"workload": "plain he_rotate, one ciphertext at a time, N=2^16 L=24 K=9 dnum=3, "
                                "%d rotations per step cycling %d resident keys" % (ROT_PER_STEP, len(ROTATIONS)),
                    "log_n": 16, "limbs": L, "special_primes": K, "dnum": dnum},
         "keyswitch_hbm_frac": round(rot_s * ks_bytes / 1e9 / HBM_PEAK_GBS, 4),

@@ -118,9 +118,10 @@ CONFIGS = {
     # LeNet-5-shaped: N=2^14, one 60-bit + seven 45-bit, two 60-bit P primes,
     # dnum=4 (two limbs per digit), scale 2^45
     "config1": dict(log_n=14, q_bits=[60] + [45] * 7, p_bits=[60, 60], alpha=2, log_scale=45),
-    # ResNet-20-shaped: N=2^16, one 60-bit + 23 50-bit, eight 60-bit P primes,
-    # dnum=3 (eight limbs per digit), scale 2^50
-    "config2": dict(log_n=16, q_bits=[60] + [50] * 23, p_bits=[60] * 8, alpha=8, log_scale=50),
+    # ResNet-20-shaped: N=2^16, one 60-bit + 23 50-bit, nine 50-bit P primes
+    # (P = 2^450 above the largest digit, 2^410), dnum=3 (eight limbs per
+    # digit), scale 2^50
+    "config2": dict(log_n=16, q_bits=[60] + [50] * 23, p_bits=[50] * 9, alpha=8, log_scale=50),
 }
 
 

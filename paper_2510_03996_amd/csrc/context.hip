@@ -466,7 +466,7 @@ int he_ctx_create(const he_params* p, int device, he_ctx** out) {
   if (p->n_q < 1 || p->n_q > HE_MAX_Q || p->n_p < 1 || p->n_p > HE_MAX_P || p->n_q + p->n_p > MAXL)
     return set_error(HE_EINVAL, "bad number of primes");
   if (p->alpha < 1 || p->alpha > p->n_q || p->alpha > MAX_BCONV_IN || p->n_p > MAX_BCONV_IN)
-    return set_error(HE_EINVAL, "alpha must be in [1, min(L, 8)] and K <= 8");
+    return set_error(HE_EINVAL, "alpha must be in [1, min(L, 10)] and K <= 10");
   if ((p->n_q + p->alpha - 1) / p->alpha > 8) return set_error(HE_EINVAL, "at most 8 key-switching digits");
   hipError_t e = hipSetDevice(device);
   if (e != hipSuccess) return hip_error(e, "hipSetDevice");

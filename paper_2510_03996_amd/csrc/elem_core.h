@@ -5,7 +5,7 @@
 
 namespace he {
 
-constexpr int MAX_BCONV_IN = 8;    // input limbs of one conversion (alpha and K)
+constexpr int MAX_BCONV_IN = 10;   // input limbs of one conversion (alpha and K)
 constexpr int MAX_BCONV_OUT = 64;
 constexpr int MAXJ = 128;          // limb jobs in one batched launch
 constexpr int MAX_DIGITS = 8;      // key-switching digits (dnum)
@@ -24,7 +24,7 @@ struct LimbMap {
 // C_{i,a,p} = [Qin/q_i]_p 2^64 256^a mod p (Montgomery form) into 8 signed
 // digits e_{i,a,p,b}, so
 //   2^64 sum_i t_i [Qin/q_i]_p == sum_b 256^b sum_{i,a} d_{i,a} e_{i,a,p,b}  (mod p)
-// with an inner sum of at most 64 products of magnitude <= 2^14 (exact in
+// with an inner sum of at most 80 products of magnitude <= 2^14 (exact in
 // int32); one Montgomery reduction of the digit-weighted sum gives y_p.
 // One 32x32x16 MFMA covers two input limbs (K = 2 x 8 digits) for 32
 // coefficients (columns) and four outputs x 8 digits b (rows).
@@ -63,9 +63,10 @@ HE_HD void bconv_row(int row, int& m, int& b) {
   b = reg & 7;
 }
 
-// REDC(M + sum_b 256^b acc[b]) for |acc[b]| <= 2^20: the weighted sum has
-// magnitude < 2^76.01, so with M = p 2^k in [2^77, 2^78) the argument lies in
-// (0, 2^78.3) < p 2^64 and the result is canonical.
+// REDC(M + sum_b 256^b acc[b]) for |acc[b]| <= 80 2^14 < 2^20.33 (ten input
+// limbs): the weighted sum has magnitude < 2^76.34, so with M = p 2^k in
+// [2^77, 2^78) the argument lies in (0, 2^78.3) < p 2^64 and the result is
+// canonical.
 HE_HD uint64_t bconv_combine(const int32_t* acc, const uint64_t* ep) {
   const int64_t lo = (int64_t)acc[0] + (int64_t)acc[1] * 256 + (int64_t)acc[2] * 65536 + (int64_t)acc[3] * 16777216;
   const int64_t hi = (int64_t)acc[4] + (int64_t)acc[5] * 256 + (int64_t)acc[6] * 65536 + (int64_t)acc[7] * 16777216;

@@ -158,7 +158,7 @@ def test_argument_errors(g1):
         he.Context(13, [40, 40], [41], 1)
     assert e.value.name == "HE_EINVAL"
     with pytest.raises(he.HEError) as e:
-        he.Context(14, [40] * 10, [41] * 9, 9)
+        he.Context(14, [40] * 12, [41] * 11, 11)  # more than ten limbs per basis conversion
     assert e.value.name == "HE_EINVAL"
     with pytest.raises(he.HEError) as e:
         g1.key_upload(11, np.zeros(10, dtype=np.uint64))

@@ -93,13 +93,14 @@ __global__ __launch_bounds__(256) void k_combine_multi(const uint64_t* __restric
   rot_out[(size_t)z * ln + (size_t)i * n + k] = v;
 }
 
-// out[i,o] (unrescaled) for every item: grid x = item, y = tile of 256
-// coefficients, z = limb.  A thread keeps OG outputs' 128-bit accumulators
+// out[i,o] (unrescaled) for every item: grid (items, tiles of 256
+// coefficients, limbs), the (item, tile) of a workgroup decoded from its
+// linear id as below.  A thread keeps OG outputs' 128-bit accumulators
 // (both polynomials) in registers and streams the item's rotated copies once
 // per group of OG outputs (the copies of one tile stay in L2 between groups);
-// every (output, rotation) plaintext residue is read once.  Accumulators stay
-// below 4 q 2^64 by subtracting 2 q 2^64 (a multiple of q) after every second
-// term; two REDCs give the canonical residue.
+// every (output, rotation) plaintext residue is read once.  Integer path:
+// accumulators stay below 4 q 2^64 by subtracting 2 q 2^64 (a multiple of q)
+// after every second term; two REDCs give the canonical residue.
 template <int OG>
 __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ rot_all, int level, int logn,
                                                    const ModInfo* __restrict__ mods,
@@ -111,8 +112,15 @@ __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ 
                                                    const uint64_t* __restrict__ pool, size_t pool_stride,
                                                    uint64_t* __restrict__ mac_all) {
   const size_t n = (size_t)1 << logn;
-  const size_t k = (size_t)blockIdx.y * 256 + threadIdx.x;
-  const int limb = blockIdx.z, it = blockIdx.x;
+  // Workgroups go round-robin to the 8 XCDs by linear id (x fastest; gridDim.y,
+  // the tile count, is a multiple of 8).  Give each XCD whole coefficient
+  // tiles, every item of a tile in a row, so that the plaintext pool's slice
+  // of a tile is fetched into that XCD's L2 once and reused by all items.
+  const int lin = blockIdx.x + gridDim.x * blockIdx.y;
+  const int xcd = lin & 7, r = lin >> 3;
+  const int it = r % (int)gridDim.x;
+  const size_t k = (size_t)((r / (int)gridDim.x) * 8 + xcd) * 256 + threadIdx.x;
+  const int limb = blockIdx.z;
   const ModInfo mi = mods[limb];
   const uint64_t q2 = 2 * mi.q;
   const size_t ln = (size_t)level * n;
@@ -120,6 +128,45 @@ __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ 
   const int o0 = out_off[it], no = out_off[it + 1] - o0;
   const int32_t* pix = pt_index + pt_off[it];
   const uint64_t* poolk = pool + (size_t)limb * n + k;
+  if (mi.k <= 50) {
+    // Primes below 2^50: centred FP64 products (mul_f64_c with the quotient
+    // estimate p fl(1/q), off by less than 0.1 for |x|, |p| <= q/2 + 1, so
+    // every product is exact and below 0.6 q in magnitude).  The sums are
+    // re-centred after every eighth term and so stay below 5.3 q < 2^53.
+    const double dq = (double)mi.q, dqi = mi.dqinv;
+    for (int og = 0; og < no; og += OG) {
+      const int cnt = no - og < OG ? no - og : OG;
+      double a[OG][2];
+#pragma unroll
+      for (int u = 0; u < OG; u++) a[u][0] = a[u][1] = 0.0;
+      for (int t = 0; t < nr; t++) {
+        const uint64_t* rc = rot_all + (size_t)rot_idx[r0 + t] * 2 * ln + (size_t)limb * n + k;
+        const double x0 = centre_f64(u52_to_f64(rc[0]), dqi, dq), x1 = centre_f64(u52_to_f64(rc[ln]), dqi, dq);
+#pragma unroll
+        for (int u = 0; u < OG; u++) {
+          if (u < cnt) {
+            const double p = centre_f64(u52_to_f64(poolk[(size_t)pix[(og + u) * nr + t] * pool_stride]), dqi, dq);
+            const double pq = p * dqi;
+            a[u][0] += mul_f64_c(x0, p, pq, dq);
+            a[u][1] += mul_f64_c(x1, p, pq, dq);
+            if ((t & 7) == 7) {
+              a[u][0] = centre_f64(a[u][0], dqi, dq);
+              a[u][1] = centre_f64(a[u][1], dqi, dq);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < OG; u++) {
+        if (u < cnt) {
+          uint64_t* dst = mac_all + (size_t)(o0 + og + u) * 2 * ln + (size_t)limb * n + k;
+          dst[0] = f64_to_u52(canon_f64(a[u][0], dqi, dq));
+          dst[ln] = f64_to_u52(canon_f64(a[u][1], dqi, dq));
+        }
+      }
+    }
+    return;
+  }
   for (int og = 0; og < no; og += OG) {
     const int cnt = no - og < OG ? no - og : OG;
     U128 a[OG][2];
@@ -278,7 +325,10 @@ static int run_batched(Batch* b, hipStream_t s) {
   {
     double terms = 0;
     for (int i = 0; i < b->B; i++) terms += (double)b->n_rot[i] * b->n_out[i];
-    ProfScope ps(c, "mac_multi", s, 8.0 * N * l * (2.0 * b->total_pairs + terms + 2.0 * b->total_out), 2.0 * N * l * terms);
+    int nf = 0;  // limbs on the FP64 path
+    for (int i = 0; i < l; i++) nf += c->hmod[i].k <= 50;
+    ProfScope ps(c, "mac_multi", s, 8.0 * N * l * (2.0 * b->total_pairs + terms + 2.0 * b->total_out), 2.0 * N * l * terms,
+                 2.0 * N * terms * (nf / PEAK_MODMUL_F64 + (l - nf) / PEAK_MODMUL_INT));
     launch_mac(b->mac_og, dim3(b->B, N / 256, l), s, b->rot, l, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx,
                b->d_out_off, b->d_pt_off, b->d_pt_index, b->pool, (size_t)b->pool_level * N, b->mac);
     HE_HIP(hipGetLastError());

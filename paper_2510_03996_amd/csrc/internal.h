@@ -188,6 +188,10 @@ struct NttIp {
   size_t u_ps;
   int32_t alpha, dnum, level;
   uint32_t g;
+  // nonzero (needs dnum >= 2): the special-prime limbs (pos >= level) of u_0
+  // and u_1 are stored after ModDown's inverse pass 2 (the pass-2
+  // intermediate) instead of in NTT form
+  int32_t p_inv2;
 };
 int ntt_launch_modup_ip(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
                         hipStream_t s);
@@ -195,6 +199,10 @@ constexpr int NTT_IP_MAXD = 4;  // digits the fused kernel handles (one thread g
 // whether the fused kernel fits this ring and digit count (threads, LDS)
 bool ntt_ip_supported(const Ctx* c, int dnum);
 void ntt_variant_shape(int v, int* tile, int* per_thread);
+// one pass of a transform: pass 2 (inverse: src -> data) or pass 1 (inverse:
+// in place on data)
+int ntt_launch_pass(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, int nbatch,
+                    const LimbMap& map, bool inverse, int pass, hipStream_t s);
 // positions 0..l-1 -> q_0..q_{l-1}, positions l..l+K-1 -> p_0..p_{K-1}
 LimbMap ext_map(const Ctx* c, int level);
 

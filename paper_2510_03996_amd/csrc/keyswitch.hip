@@ -136,14 +136,19 @@ int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) 
 }
 
 // ModDown of w.u (both polynomials) and the final additions
+// (p_inv2: the special-prime limbs of w.u are already after inverse pass 2)
 static int ks_moddown(Ctx* c, const WS& w, int level, uint32_t g, const uint64_t* add0, const uint64_t* add1,
-                      uint64_t* out0, uint64_t* out1, hipStream_t s) {
+                      uint64_t* out0, uint64_t* out1, hipStream_t s, bool p_inv2 = false) {
   const size_t N = c->n;
   const int K = c->K, L = c->L;
   const size_t E = (size_t)(level + K);
   int rc;
   // ModDown of u0 and u1: P limbs to coefficient form, convert to Q_l, back to NTT form
-  if ((rc = ntt_launch(c, w.u, E * N, 2, range_map(level, K, L), true, s))) return rc;
+  if (p_inv2)
+    rc = ntt_launch_pass(c, w.u, E * N, w.u, E * N, 2, range_map(level, K, L), true, 1, s);
+  else
+    rc = ntt_launch(c, w.u, E * N, 2, range_map(level, K, L), true, s);
+  if (rc) return rc;
   const BConvSet& set = c->moddown[level];
   {
     ProfScope ps(c, "bconv_moddown", s, 16.0 * N * (K + level), 2.0 * N * K * (1 + level),
@@ -209,8 +214,9 @@ int ks_single(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t
   ip.dnum = c->dnum(level);
   ip.level = level;
   ip.g = g;
+  ip.p_inv2 = ip.dnum >= 2;
   if ((rc = ntt_launch_modup_ip(c, w.ext, c->modup_ntt[level], ext_map(c, level), ip, s))) return rc;
-  return ks_moddown(c, w, level, g, add0, add1, out0, out1, s);
+  return ks_moddown(c, w, level, g, add0, add1, out0, out1, s, ip.p_inv2 != 0);
 }
 
 

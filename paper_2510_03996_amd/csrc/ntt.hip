@@ -169,16 +169,41 @@ __device__ __forceinline__ void rounds_fwd_if(bool act, T* lds, int tid, int wg,
 // form, and is only loaded); then every thread accumulates
 // e_d[src(k)] * key_d[j][pos][k] over the digits for both key polynomials j
 // in 128-bit registers.  The extended digits never return to HBM.
-template <int LOGN, int LOG_EPT, int LOG_TILE, int MAXD>
-__global__ __launch_bounds__(MAXD * 256) void ntt_ip_kernel(LimbMap map, const uint64_t* __restrict__ tw_all,
-                                                      const uint64_t* __restrict__ twp_all,
-                                                      const double* __restrict__ dtw_all,
-                                                      const double* __restrict__ dtwq_all,
-                                                      const ModInfo* __restrict__ mods, NttIp ip) {
+// Inverse rounds NR-1..0 run by the waves with `act` set; every wave of the
+// workgroup passes the same barriers.
+template <class P, int IDX, class T, class TW, class Q>
+__device__ __forceinline__ void rounds_inv_if(bool act, T* lds, int tid, int wg, const TW* tw, const TW* twp, Q q,
+                                              Q qinv) {
+  if constexpr (IDX >= 0) {
+    if (act) {
+      if constexpr (std::is_same<T, double>::value)
+        P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
+      else
+        P::template round<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
+    }
+    if constexpr (IDX > 0) {
+      __syncthreads();
+      rounds_inv_if<P, IDX - 1>(act, lds, tid, wg, tw, twp, q, qinv);
+    }
+  }
+}
+
+template <int LOGN, int LOG_EPT, int LOG_TILE, int DN>
+__global__ __launch_bounds__(DN * 256) void ntt_ip_kernel(LimbMap map, const uint64_t* __restrict__ tw_all,
+                                                          const uint64_t* __restrict__ twp_all,
+                                                          const double* __restrict__ dtw_all,
+                                                          const double* __restrict__ dtwq_all,
+                                                          const uint64_t* __restrict__ itw_all,
+                                                          const uint64_t* __restrict__ itwp_all,
+                                                          const double* __restrict__ ditw_all,
+                                                          const double* __restrict__ ditwq_all,
+                                                          const ModInfo* __restrict__ mods, NttIp ip) {
   using P = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
-  extern __shared__ uint64_t lds_all[];  // [dnum][P::LDS_WORDS]
+  using PI = NttPass<LOGN, 2, true, LOG_EPT, LOG_TILE>;
+  constexpr int NTHR = DN * P::THREADS;
+  constexpr int IT = (P::TILE + NTHR - 1) / NTHR;  // outputs per thread
+  extern __shared__ uint64_t lds_all[];  // [max(dnum, 2)][P::LDS_WORDS]
   const int tid = threadIdx.x;
-  const int nthr = blockDim.x;          // dnum * P::THREADS
   const int d = tid / P::THREADS;       // wave-uniform
   const int t = tid - d * P::THREADS;
   const int m = __builtin_amdgcn_readfirstlane(map.mod[blockIdx.z]);
@@ -193,7 +218,6 @@ __global__ __launch_bounds__(MAXD * 256) void ntt_ip_kernel(LimbMap map, const u
   const uint64_t* ain = own ? ip.c1 + off : ip.ext + d * ip.ext_ds + off;
   uint64_t* lds = lds_all + d * P::LDS_WORDS;
   const bool f64 = mi.k <= 50;  // uniform over the workgroup
-  const int dn = ip.dnum;
   const uint64_t* key = ip.key + ((size_t)m << LOGN) + out0;
   if (f64) {
     double* dl = reinterpret_cast<double*>(lds);
@@ -217,34 +241,75 @@ __global__ __launch_bounds__(MAXD * 256) void ntt_ip_kernel(LimbMap map, const u
   }
   __syncthreads();
   uint64_t* u = ip.u + off + out0;
-  for (int e = tid; e < P::TILE; e += nthr) {
+  // special-prime limbs continue with the inverse pass 2 of ModDown
+  const bool pinv2 = DN >= 2 && ip.p_inv2 && pos >= ip.level;
+  uint64_t r0[IT], r1[IT];
+#pragma unroll
+  for (int it = 0; it < IT; it++) {
+    const int e = tid + it * NTHR;
+    if (e >= P::TILE) break;
     const uint32_t k = out0 + e;
     const int sl = (int)((ip.g == 1 ? k : automorph_src(k, ip.g, LOGN)) - src0);
     const int li = P::lidx(sl / P::M, sl % P::M);
-    uint64_t k0[MAXD], k1[MAXD];
+    uint64_t k0[DN], k1[DN];
 #pragma unroll
-    for (int j = 0; j < MAXD; j++)
-      if (j < dn) {
-        k0[j] = key[j * ip.key_ds + e];
-        k1[j] = key[j * ip.key_ds + ip.key_ps + e];
-      }
+    for (int j = 0; j < DN; j++) {
+      k0[j] = key[j * ip.key_ds + e];
+      k1[j] = key[j * ip.key_ds + ip.key_ps + e];
+    }
     U128 a0{0, 0}, a1{0, 0};
 #pragma unroll
-    for (int j = 0; j < MAXD; j++)
-      if (j < dn) {
-        const uint64_t w = lds_all[j * P::LDS_WORDS + li];
-        const uint64_t v = f64 ? f64_to_u52(canon_f64(bits_to_f64(w), mi.dqinv, (double)q)) : P::finish(w, 0, 0, q);
-        add_wide(a0, mul_wide(v, k0[j]));
-        add_wide(a1, mul_wide(v, k1[j]));
-      }
-    u[e] = mont_redc(a0, q, mi.qinv);
-    u[ip.u_ps + e] = mont_redc(a1, q, mi.qinv);
+    for (int j = 0; j < DN; j++) {
+      const uint64_t w = lds_all[j * P::LDS_WORDS + li];
+      const uint64_t v = f64 ? f64_to_u52(canon_f64(bits_to_f64(w), mi.dqinv, (double)q)) : P::finish(w, 0, 0, q);
+      add_wide(a0, mul_wide(v, k0[j]));
+      add_wide(a1, mul_wide(v, k1[j]));
+    }
+    r0[it] = mont_redc(a0, q, mi.qinv);
+    r1[it] = mont_redc(a1, q, mi.qinv);
+    if (!pinv2) {
+      u[e] = r0[it];
+      u[ip.u_ps + e] = r1[it];
+    }
+  }
+  if (!pinv2) return;  // uniform over the workgroup
+  // u_0 and u_1 of this tile into regions 0 and 1 (natural order), then
+  // groups 0 and 1 run the inverse pass-2 rounds and store the intermediate
+  __syncthreads();
+#pragma unroll
+  for (int it = 0; it < IT; it++) {
+    const int e = tid + it * NTHR;
+    if (e >= P::TILE) break;
+    const int li = PI::lidx(e / PI::M, e % PI::M);
+    lds_all[li] = f64 ? f64_to_bits(u52_to_f64(r0[it])) : r0[it];
+    lds_all[PI::LDS_WORDS + li] = f64 ? f64_to_bits(u52_to_f64(r1[it])) : r1[it];
+  }
+  __syncthreads();
+  const bool act = d < 2;
+  const int wg = blockIdx.x;
+  if (f64)
+    rounds_inv_if<PI, PI::NR - 1>(act, reinterpret_cast<double*>(lds), t, wg, ditw_all + (size_t)m * P::N,
+                                  ditwq_all + (size_t)m * P::N, (double)q, mi.dqinv);
+  else
+    rounds_inv_if<PI, PI::NR - 1>(act, lds, t, wg, itw_all + (size_t)m * P::N, itwp_all + (size_t)m * P::N, q, q);
+  __syncthreads();
+  if (act) {
+    uint64_t* o = ip.u + d * ip.u_ps + off;
+    for (int e = t; e < PI::TILE; e += PI::THREADS) {
+      int g, k;
+      PI::tile_elem(e, g, k);
+      const uint64_t v = lds[PI::lidx(g, k)];
+      o[PI::gidx(wg, g, k)] = f64 ? PI::finish_f64(bits_to_f64(v), 0, 0, (double)q, mi.dqinv) : PI::finish(v, 0, 0, q);
+    }
   }
 }
 
+// passes: bit 0 = pass 1, bit 1 = pass 2 (a forward pass 2 alone reads `data`,
+// an inverse pass 1 alone reads `data` too)
 template <int LOGN, int LOG_EPT, int LOG_TILE>
 static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
-                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr) {
+                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr,
+                        int passes = 3) {
   using P1 = NttPass<LOGN, 1, false, LOG_EPT, LOG_TILE>;
   using P2 = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
   constexpr int T = P1::THREADS;
@@ -261,12 +326,13 @@ static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* da
   }
   const NttEpi none{};
   if (!inverse) {
-    {
+    if (passes & 1) {
       ProfScope ps(c, "ntt_fwd_pass1", s, bytes, mm1, mm1 * per_mm);
       ntt_pass_kernel<LOGN, 1, false, LOG_EPT, LOG_TILE, false><<<g1, T, 0, s>>>(
           src, src_bs, data, batch_stride, map, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, none);
     }
-    if (epi) {
+    if (!(passes & 2)) {
+    } else if (epi) {
       // + u read, out write instead of y write, add_0 / add_1 reads
       const double eb = bytes + 8.0 * N * limbs * (1 + (epi->add[0] ? 0.5 : 0) + (epi->add[1] ? 0.5 : 0));
       ProfScope ps(c, "ntt_fwd_pass2_moddown", s, eb, mm2 + N * limbs, mm2 * per_mm + N * limbs / PEAK_MODMUL_INT);
@@ -278,14 +344,16 @@ static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* da
           data, batch_stride, data, batch_stride, map, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, none);
     }
   } else {
-    {
+    if (passes & 2) {
       ProfScope ps(c, "ntt_inv_pass2", s, bytes, mm2, mm2 * per_mm);
       ntt_pass_kernel<LOGN, 2, true, LOG_EPT, LOG_TILE, false><<<g2, T, 0, s>>>(
           src, src_bs, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod, none);
     }
-    ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs, (mm1 + N * limbs) * per_mm);
-    ntt_pass_kernel<LOGN, 1, true, LOG_EPT, LOG_TILE, false><<<g1, T, 0, s>>>(
-        data, batch_stride, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod, none);
+    if (passes & 1) {
+      ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs, (mm1 + N * limbs) * per_mm);
+      ntt_pass_kernel<LOGN, 1, true, LOG_EPT, LOG_TILE, false><<<g1, T, 0, s>>>(
+          data, batch_stride, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod, none);
+    }
   }
   HE_HIP(hipGetLastError());
   return HE_OK;
@@ -304,13 +372,14 @@ static int ntt_bucket(int limbs) { return limbs <= 8 ? 0 : limbs <= 16 ? 1 : lim
 
 template <int LOGN>
 static int ntt_launch_var(Ctx* c, int var, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
-                          int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr) {
+                          int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr,
+                          int passes = 3) {
   switch (var) {
-    case 0: return ntt_launch_v<LOGN, 2, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi);
-    case 1: return ntt_launch_v<LOGN, 3, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi);
-    case 3: return ntt_launch_v<LOGN, 2, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi);
-    case 4: return ntt_launch_v<LOGN, 3, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi);
-    default: return ntt_launch_v<LOGN, 4, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi);
+    case 0: return ntt_launch_v<LOGN, 2, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes);
+    case 1: return ntt_launch_v<LOGN, 3, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes);
+    case 3: return ntt_launch_v<LOGN, 2, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes);
+    case 4: return ntt_launch_v<LOGN, 3, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes);
+    default: return ntt_launch_v<LOGN, 4, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes);
   }
 }
 
@@ -333,9 +402,10 @@ static LimbMap by_modulus(const Ctx* c, const LimbMap& m) {
 
 template <int LOGN>
 static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
-                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr) {
+                        int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr,
+                        int passes = 3) {
   return ntt_launch_var<LOGN>(c, c->ntt_var[ntt_bucket(map.n * nbatch)], src, src_bs, data, batch_stride, nbatch,
-                              by_modulus(c, map), inverse, s, epi);
+                              by_modulus(c, map), inverse, s, epi, passes);
 }
 
 template <int LOGN>
@@ -458,13 +528,19 @@ static int ntt_ip_launch_v(Ctx* c, uint64_t* ext, const LimbMap& conv, const Lim
                          mm_ip / PEAK_MODMUL_INT;
     ProfScope ps(c, "ntt_fwd_pass2_ip", s, bytes, mm_ntt + mm_ip, ideal);
     const dim3 grid(P2::WG_PER_LIMB, 1, outs.n);
-    const size_t lds = (size_t)ip.dnum * P2::LDS_WORDS * 8;
-    if (ip.dnum <= 3)
-      ntt_ip_kernel<LOGN, LOG_EPT, LOG_TILE, 3><<<grid, ip.dnum * P2::THREADS, lds, s>>>(
-          outs, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, ip);
-    else
-      ntt_ip_kernel<LOGN, LOG_EPT, LOG_TILE, 4><<<grid, ip.dnum * P2::THREADS, lds, s>>>(
-          outs, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod, ip);
+    const size_t lds = (size_t)std::max(ip.dnum, 2) * P2::LDS_WORDS * 8;
+    const dim3 blk(ip.dnum * P2::THREADS);
+#define HE_IP_LAUNCH(D)                                                                                           \
+  ntt_ip_kernel<LOGN, LOG_EPT, LOG_TILE, D><<<grid, blk, lds, s>>>(outs, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, \
+                                                                   c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq,   \
+                                                                   c->d_mod, ip)
+    switch (ip.dnum) {
+      case 1: HE_IP_LAUNCH(1); break;
+      case 2: HE_IP_LAUNCH(2); break;
+      case 3: HE_IP_LAUNCH(3); break;
+      default: HE_IP_LAUNCH(4); break;
+    }
+#undef HE_IP_LAUNCH
   }
   HE_HIP(hipGetLastError());
   return HE_OK;
@@ -475,7 +551,21 @@ static int ntt_ip_launch_v(Ctx* c, uint64_t* ext, const LimbMap& conv, const Lim
 template <int LOGN>
 static int ntt_ip_launch_n(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
                            hipStream_t s) {
-  return ntt_ip_launch_v<LOGN, 3, 11>(c, ext, by_modulus(c, conv), by_modulus(c, outs), ip, s);
+  LimbMap om = by_modulus(c, outs);
+  if (ip.p_inv2) {
+    // the special-prime workgroups carry the extra inverse pass: start them first
+    LimbMap r = om;
+    int n = 0;
+    for (int pass = 0; pass < 2; pass++)
+      for (int i = 0; i < om.n; i++)
+        if ((om.pos[i] >= ip.level) == (pass == 0)) {
+          r.pos[n] = om.pos[i];
+          r.mod[n] = om.mod[i];
+          n++;
+        }
+    om = r;
+  }
+  return ntt_ip_launch_v<LOGN, 3, 11>(c, ext, by_modulus(c, conv), om, ip, s);
 }
 
 bool ntt_ip_supported(const Ctx* c, int dnum) {
@@ -490,7 +580,7 @@ bool ntt_ip_supported(const Ctx* c, int dnum) {
     case 16: words = P16::LDS_WORDS; break;
     default: return false;
   }
-  return dnum >= 1 && dnum <= NTT_IP_MAXD && (size_t)dnum * words * 8 <= c->lds_per_block;
+  return dnum >= 1 && dnum <= NTT_IP_MAXD && (size_t)std::max(dnum, 2) * words * 8 <= c->lds_per_block;
 }
 
 int ntt_launch_modup_ip(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
@@ -500,6 +590,18 @@ int ntt_launch_modup_ip(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMa
     case 12: return ntt_ip_launch_n<12>(c, ext, conv, outs, ip, s);
     case 14: return ntt_ip_launch_n<14>(c, ext, conv, outs, ip, s);
     case 16: return ntt_ip_launch_n<16>(c, ext, conv, outs, ip, s);
+  }
+  return set_error(HE_EINVAL, "unsupported ring degree");
+}
+
+int ntt_launch_pass(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, int nbatch,
+                    const LimbMap& map, bool inverse, int pass, hipStream_t s) {
+  if (map.n <= 0 || nbatch <= 0) return HE_OK;
+  const int passes = pass == 1 ? 1 : 2;
+  switch (c->log_n) {
+    case 12: return ntt_launch_n<12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, nullptr, passes);
+    case 14: return ntt_launch_n<14>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, nullptr, passes);
+    case 16: return ntt_launch_n<16>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, nullptr, passes);
   }
   return set_error(HE_EINVAL, "unsupported ring degree");
 }

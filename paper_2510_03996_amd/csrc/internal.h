@@ -192,6 +192,9 @@ struct NttIp {
   // and u_1 are stored after ModDown's inverse pass 2 (the pass-2
   // intermediate) instead of in NTT form
   int32_t p_inv2;
+  // nonzero: ext already holds the converted limbs in NTT form (a hoisted
+  // ModUp); the kernel only gathers them and no forward pass runs
+  int32_t ext_ntt;
 };
 int ntt_launch_modup_ip(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
                         hipStream_t s);

@@ -180,6 +180,28 @@ int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t*
   const size_t E = (size_t)(level + K);
   const size_t kps = (size_t)(L + K) * N;  // key poly stride
   const int dn = c->dnum(level);
+  if (ntt_ip_supported(c, dn)) {
+    // tile-wise inner product (the fused kernel with the digits already in NTT
+    // form), which also runs ModDown's inverse pass 2 on the special limbs
+    NttIp ip{};
+    ip.ext = w.ext;
+    ip.ext_ds = E * N;
+    ip.c1 = c1;
+    ip.key = key;
+    ip.key_ds = 2 * kps;
+    ip.key_ps = kps;
+    ip.u = w.u;
+    ip.u_ps = E * N;
+    ip.alpha = c->alpha;
+    ip.dnum = dn;
+    ip.level = level;
+    ip.g = g;
+    ip.p_inv2 = dn >= 2;
+    ip.ext_ntt = 1;
+    int rc;
+    if ((rc = ntt_launch_modup_ip(c, w.ext, c->modup_ntt[level], ext_map(c, level), ip, s))) return rc;
+    return ks_moddown(c, w, level, g, add0, add1, out0, out1, s, ip.p_inv2 != 0);
+  }
   {
     ProfScope ps(c, "ks_inner_product", s, 8.0 * N * E * (3.0 * dn + 2), 2.0 * dn * E * N);
     k_ip<<<dim3(N / 256, E), 256, 0, s>>>(w.ext, E * N, c1, c->alpha, dn, key, 2 * kps, kps, level, L, g,

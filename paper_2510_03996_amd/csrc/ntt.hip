@@ -215,6 +215,7 @@ __global__ __launch_bounds__(DN * 256) void ntt_ip_kernel(LimbMap map, const uin
   const int swg = (int)(src0 / P::TILE);
   const size_t off = (size_t)pos << LOGN;
   const bool own = pos < ip.level && pos / ip.alpha == d;
+  const bool load_only = own || ip.ext_ntt;  // already in NTT form
   const uint64_t* ain = own ? ip.c1 + off : ip.ext + d * ip.ext_ds + off;
   uint64_t* lds = lds_all + d * P::LDS_WORDS;
   const bool f64 = mi.k <= 50;  // uniform over the workgroup
@@ -225,10 +226,10 @@ __global__ __launch_bounds__(DN * 256) void ntt_ip_kernel(LimbMap map, const uin
       int g, k;
       P::tile_elem(e, g, k);
       const uint64_t w = ain[P::gidx(swg, g, k)];
-      dl[P::lidx(g, k)] = own ? u52_to_f64(w) : P::load_f64(w);
+      dl[P::lidx(g, k)] = load_only ? u52_to_f64(w) : P::load_f64(w);
     }
     __syncthreads();
-    rounds_fwd_if<P, 0>(!own, dl, t, swg, dtw_all + (size_t)m * P::N, dtwq_all + (size_t)m * P::N, (double)q,
+    rounds_fwd_if<P, 0>(!load_only, dl, t, swg, dtw_all + (size_t)m * P::N, dtwq_all + (size_t)m * P::N, (double)q,
                         mi.dqinv);
   } else {
     for (int e = t; e < P::TILE; e += P::THREADS) {
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(DN * 256) void ntt_ip_kernel(LimbMap map, const uin
       lds[P::lidx(g, k)] = ain[P::gidx(swg, g, k)];
     }
     __syncthreads();
-    rounds_fwd_if<P, 0>(!own, lds, t, swg, tw_all + (size_t)m * P::N, twp_all + (size_t)m * P::N, q, q);
+    rounds_fwd_if<P, 0>(!load_only, lds, t, swg, tw_all + (size_t)m * P::N, twp_all + (size_t)m * P::N, q, q);
   }
   __syncthreads();
   uint64_t* u = ip.u + off + out0;
@@ -512,7 +513,7 @@ static int ntt_ip_launch_v(Ctx* c, uint64_t* ext, const LimbMap& conv, const Lim
     for (int i = 0; i < conv.n; i++) nconv_f += c->hmod[conv.mod[i]].k <= 50;
     for (int i = 0; i < outs.n; i++) nf += c->hmod[outs.mod[i]].k <= 50;
   }
-  {
+  if (!ip.ext_ntt) {
     const double mm = N / 2 * P1::LM * conv.n;
     ProfScope ps(c, "ntt_fwd_pass1", s, 16.0 * N * conv.n, mm,
                  N / 2 * P1::LM * (nconv_f / PEAK_MODMUL_F64 + (conv.n - nconv_f) / PEAK_MODMUL_INT));
@@ -523,10 +524,12 @@ static int ntt_ip_launch_v(Ctx* c, uint64_t* ext, const LimbMap& conv, const Lim
     // reads: converted limbs, own limbs of c1, 2 dnum key limbs per output limb; writes: 2 output limbs
     const double own = ip.level;
     const double bytes = 8.0 * N * (conv.n + own + 2.0 * ip.dnum * outs.n + 2.0 * outs.n);
-    const double mm_ntt = N / 2 * P2::LM * conv.n, mm_ip = 2.0 * ip.dnum * N * outs.n;
-    const double ideal = N / 2 * P2::LM * (nconv_f / PEAK_MODMUL_F64 + (conv.n - nconv_f) / PEAK_MODMUL_INT) +
-                         mm_ip / PEAK_MODMUL_INT;
-    ProfScope ps(c, "ntt_fwd_pass2_ip", s, bytes, mm_ntt + mm_ip, ideal);
+    const double fwd = ip.ext_ntt ? 0.0 : 1.0;  // forward pass 2 of the converted limbs
+    const double mm_ntt = fwd * N / 2 * P2::LM * conv.n, mm_ip = 2.0 * ip.dnum * N * outs.n;
+    const double ideal =
+        fwd * N / 2 * P2::LM * (nconv_f / PEAK_MODMUL_F64 + (conv.n - nconv_f) / PEAK_MODMUL_INT) +
+        mm_ip / PEAK_MODMUL_INT;
+    ProfScope ps(c, ip.ext_ntt ? "ks_inner_product_tile" : "ntt_fwd_pass2_ip", s, bytes, mm_ntt + mm_ip, ideal);
     const dim3 grid(P2::WG_PER_LIMB, 1, outs.n);
     const size_t lds = (size_t)std::max(ip.dnum, 2) * P2::LDS_WORDS * 8;
     const dim3 blk(ip.dnum * P2::THREADS);

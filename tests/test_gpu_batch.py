@@ -93,3 +93,27 @@ def test_batch_larger_config2_batched_equals_plain():
     got_b, got_p, info = run_gpu(g, name, sets, outs, cts, pool, pti, 1)
     H.assert_limbs_equal(got_b, got_p, "batched vs plain")
     g.close()
+
+
+def test_batch_mac_extreme_residues():
+    """The batched MAC's centred FP64 products (primes below 2^50) and its
+    integer path (q_0) against the per-op path's Barrett products, with
+    plaintext residues at the edges of their range (0, 1, q - 1, q/2, q/2 + 1)
+    and 9-17 terms per output so that the sums pass through several
+    re-centrings."""
+    name = "config2"
+    offsets = [1, -1, 2, -2, 3, -3, 4, -4, 5, -5, 7, -7, 16, -16, 32, -32, 64]
+    octx, sets, outs, cts, pool, pti = make_batch(name, 3, 4, 9, 17, 1, 3, seed=41, pool_offsets=offsets)
+    q = octx.pr.q
+    for p, pt in enumerate(pool):
+        d = pt.data
+        k = np.arange(d.shape[1])
+        for i in range(d.shape[0]):
+            qi = np.uint64(q[i])
+            edge = np.array([0, 1, q[i] - 1, q[i] // 2, q[i] // 2 + 1], dtype=np.uint64)
+            sel = (k + p + i) % 7
+            d[i] = np.where(sel < 5, edge[np.minimum(sel, 4)], d[i] % qi)
+    g = H.gpu_ctx(name)
+    got_b, got_p, info = run_gpu(g, name, sets, outs, cts, pool, pti, 0)
+    H.assert_limbs_equal(got_b, got_p, "batched vs plain, extreme plaintext residues")
+    g.close()

@@ -268,10 +268,22 @@ def layer_latencies(reps=3):
     ct = synthetic_ct(c2, 24, 31, sc)
     ak, am = synthetic_pts(c2, pa.n_kernel_pts, 24, 32, sc), synthetic_pts(c2, pa.n_mask_pts, 24, 33, sc)
     out["resnet_convA_16x32x32_n16_ms"] = round(timed(lambda: c2.conv2d(ct, fm0, 16, 3, 1, 1, ak, am, stream=s), reps, s) * 1e3, 3)
+    # the same layers with the log-step input-channel sum (keys W^2, 2 W^2, 4 W^2, 8 W^2)
+    c2.conv_channel_sum(he.CHSUM_LOG)
+    pal = c2.conv2d_plan(fm0, 16, 3, 1, 1)
+    pbl = c2.conv2d_plan(pa.out, 32, 3, 2, 1)
+    upload_synthetic_keys(c2, sorted(set(pal.keys()) | set(pbl.keys())), 30)
+    out["resnet_convA_16x32x32_n16_logsum_ms"] = round(
+        timed(lambda: c2.conv2d(ct, fm0, 16, 3, 1, 1, ak, am, stream=s), reps, s) * 1e3, 3)
+    c2.conv_channel_sum(he.CHSUM_CHAIN)
     del ak, am
     ctb = synthetic_ct(c2, 22, 34, sc)
     bk, bm = synthetic_pts(c2, pb.n_kernel_pts, 22, 35, sc), synthetic_pts(c2, pb.n_mask_pts, 22, 36, sc)
     out["resnet_convB_s2_n16_ms"] = round(timed(lambda: c2.conv2d(ctb, pa.out, 32, 3, 2, 1, bk, bm, stream=s), reps, s) * 1e3, 3)
+    c2.conv_channel_sum(he.CHSUM_LOG)
+    out["resnet_convB_s2_n16_logsum_ms"] = round(
+        timed(lambda: c2.conv2d(ctb, pa.out, 32, 3, 2, 1, bk, bm, stream=s), reps, s) * 1e3, 3)
+    c2.conv_channel_sum(he.CHSUM_CHAIN)
     del bk, bm
     ctg = synthetic_ct(c2, 17, 37, sc)
     gm = synthetic_pts(c2, pg.n_mask_pts, 17, 38, sc)
@@ -297,7 +309,8 @@ def layer_latencies(reps=3):
     out["key_switches"] = {"conv3x3_n12": 8, "lenet5_stack": pc.key_switches + pp.key_switches + 2,
                            "resnet_convA": pa.key_switches, "resnet_convB": pb.key_switches,
                            "resnet_gap": pg.key_switches, "resnet_fc": pf.key_switches,
-                           "conv7x7_s2_p3": p7.key_switches, "relu_cheb59": he.cheb_plan(cheb, True)[1]}
+                           "conv7x7_s2_p3": p7.key_switches, "relu_cheb59": he.cheb_plan(cheb, True)[1],
+                           "resnet_convA_logsum": pal.key_switches, "resnet_convB_logsum": pbl.key_switches}
     c2.close()
     return out
 

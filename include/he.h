@@ -272,6 +272,20 @@ typedef struct {
  * The result is rescaled after every multiplicative level. */
 int he_conv2d_plan(const he_ctx* ctx, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
                    he_layer_plan* plan);
+/* Input-channel sum of he_conv2d (S = sum_{j < C} Rot_{j step}(A), step =
+ * W^2 for the special schedule, chan_stride for the generic one), chosen per
+ * context for plans and calls made after this call:
+ *   HE_CHSUM_CHAIN (default): the paper's chain with the single key step
+ *     (Algorithm 1 of "Special Secure Convolution Layer"), C - 1 key switches
+ *     per output channel;
+ *   HE_CHSUM_LOG: for C a power of two, doubling S <- S + Rot_{2^t step}(S),
+ *     t < log2 C: log2 C key switches per output channel and log2 C keys
+ *     (2^t step); other channel counts keep the chain.
+ * Both give the same plaintext; the ciphertexts differ (other keys, other
+ * key-switch noise).  HE_EINVAL for another mode. */
+#define HE_CHSUM_CHAIN 0
+#define HE_CHSUM_LOG 1
+int he_ctx_conv_channel_sum(he_ctx* ctx, int mode);
 int he_conv2d(he_ctx* ctx, const he_ct* in, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
               const he_pt* kernel_pts, int n_kernel_pts, const he_pt* mask_pts, int n_mask_pts, he_ct* out,
               he_fmap* out_map, he_stream stream);

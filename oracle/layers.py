@@ -442,22 +442,53 @@ def conv_plaintexts(fm, K, stride, padding, slots):
     return kern, masks
 
 
-def conv_rotations(fm, F, k, stride, padding, slots):
+def logstep_ok(C):
+    """The log-step channel sum applies to power-of-two channel counts."""
+    return C > 1 and (C & (C - 1)) == 0
+
+
+def channel_sum_keys(C, step, logstep):
+    """Rotation keys of channel_sum."""
+    if logstep and logstep_ok(C):
+        return {step << t for t in range(C.bit_length() - 1)}
+    return {step} if C > 1 else set()
+
+
+def channel_sum(ev, A, C, step, logstep=False):
+    """S = sum_{j < C} Rot_{j step}(A), the input-channel sum of a convolution.
+
+    Chain (the paper's schedule, Algorithm 1's single key step): T <- Rot_step(T),
+    S <- S + T, C - 1 key switches.  Log-step (C a power of two): S <- S +
+    Rot_{2^t step}(S) for t < log2 C, log2 C key switches with keys 2^t step;
+    Rot is linear and Rot_a Rot_b = Rot_{a+b}, so both give the same sum.
+    """
+    if logstep and logstep_ok(C):
+        S, t = A, 1
+        while t < C:
+            S = ev.add(S, ev.rot(S, t * step))
+            t *= 2
+        return S
+    S, T = A, A
+    for _ in range(C - 1):
+        T = ev.rot(T, step)
+        S = ev.add(S, T)
+    return S
+
+
+def conv_rotations(fm, F, k, stride, padding, slots, logstep=False):
     """Distinct rotation keys the schedule uses (the paper's per-layer index helper)."""
     kind = conv_kind(k, padding, fm, F)
     keys = set()
     if kind == "special":
         W = fm.W
         keys |= {-W, W, -1, 1}
-        if fm.C > 1:
-            keys.add(W * W)
+        keys |= channel_sum_keys(fm.C, W * W, logstep)
         if stride > 1:
             Ho = (W - 1) // stride + 1
             keys |= {key for _, _, key in compaction_plan(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho)}
     else:
         keys |= {r for r in conv_taps(fm, k, padding) if r != 0}
-        if fm.C > 1:
-            keys.add(fm.cs)
+        keys |= channel_sum_keys(fm.C, fm.cs, logstep)
         if F > 1:
             keys.add(-fm.cs)
         if stride > 1:
@@ -467,20 +498,21 @@ def conv_rotations(fm, F, k, stride, padding, slots):
     return sorted(keys)
 
 
-def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots):
+def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False):
     """Pinned convolution schedule.
 
     special (k=3, P=1): r = Algorithm 1 rotations computed as three hoisted
       groups {-W, W, -1, 1} of x, {-1, 1} of r1, {-1, 1} of r7;
       A_f = RS(sum_tap r_tap (.) kv[f][tap]);
-      C > 1 (replicated input): S_f = A_f + Rot_{W^2}(A_f) + ... chained with
-      the single key W^2 (C-1 key switches); Y = RS(sum_f S_f (.) blockmask_f);
+      C > 1 (replicated input): S_f = channel_sum(A_f, C, W^2), chained with
+      the single key W^2 (C-1 key switches) or, with logstep and C a power of
+      two, by doubling (log2 C key switches); Y = RS(sum_f S_f (.) blockmask_f);
       stride > 1: joint compaction of all channels.
     generic (0 <= P <= (k-1)/2): one hoisted group of the nonzero tap offsets
       (i - P) rs + (j - P); kernel vectors zero where a tap's neighbour lies
-      in the padding; A_f = RS(sum r (.) kv); C > 1: channel chain with key cs, then
-      RS(. (.) block-0 mask); out-channels placed by a Horner chain with key
-      -cs; stride > 1: joint compaction.
+      in the padding; A_f = RS(sum r (.) kv); C > 1: channel_sum with step cs,
+      then RS(. (.) block-0 mask); out-channels placed by a Horner chain with
+      key -cs; stride > 1: joint compaction.
     """
     kind = conv_kind(k, padding, fm, F)
     C = fm.C
@@ -498,11 +530,7 @@ def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots):
         sums = []
         for f in range(F):
             A = ev.rescale(mac(ev, taps, kern[9 * f:9 * f + 9]))
-            S, T = A, A
-            for _ in range(C - 1):
-                T = ev.rot(T, W * W)
-                S = ev.add(S, T)
-            sums.append(S)
+            sums.append(channel_sum(ev, A, C, W * W, logstep))
         mpos = 0
         if F > 1 or C > 1:
             y = ev.rescale(mac(ev, sums, masks[:F]))
@@ -521,13 +549,7 @@ def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots):
     sums = []
     for f in range(F):
         A = ev.rescale(mac(ev, taps, kern[k * k * f:k * k * (f + 1)]))
-        if C > 1:
-            S, T = A, A
-            for _ in range(C - 1):
-                T = ev.rot(T, fm.cs)
-                S = ev.add(S, T)
-            A = S
-        sums.append(A)
+        sums.append(channel_sum(ev, A, C, fm.cs, logstep))
     mpos = 0
     if C > 1:
         sums = [ev.mul_plain(s, masks[0]) for s in sums]

@@ -201,6 +201,47 @@ static std::vector<int> conv_taps(const he_fmap& fm, int k, int P) {
   return r;
 }
 
+// Input-channel sum S = sum_{j < C} Rot_{j step}(A): the chain with the
+// single key `step`, or (HE_CHSUM_LOG, C a power of two) doubling with keys
+// 2^t step.  chsum_keys / chsum_switches describe it for the plans.
+static bool chsum_log(const Ctx* c, int C) { return c->chsum == HE_CHSUM_LOG && C > 1 && (C & (C - 1)) == 0; }
+static void chsum_keys(const Ctx* c, std::vector<int>& keys, int C, int step) {
+  if (chsum_log(c, C))
+    for (int t = 1; t < C; t *= 2) add_keys(keys, t * step);
+  else if (C > 1)
+    add_keys(keys, step);
+}
+static int chsum_switches(const Ctx* c, int C) {
+  if (chsum_log(c, C)) {
+    int n = 0;
+    for (int t = 1; t < C; t *= 2) n++;
+    return n;
+  }
+  return C - 1;
+}
+static he_ct channel_sum(Ev& ev, const he_ct& A, int C, int step) {
+  he_ct S = ev.copy(A);
+  if (chsum_log(ev.c, C)) {
+    for (int t = 1; t < C; t *= 2) {
+      he_ct R = ev.rot(S, t * step);
+      ck(he_add(ev.h, &S, &R, &S, ev.s));
+      ev.release(R);
+    }
+    return S;
+  }
+  he_ct T = A;
+  bool own = false;  // T is A (the caller's) until the first rotation
+  for (int cc = 1; cc < C; cc++) {
+    he_ct T2 = ev.rot(T, step);
+    if (own) ev.release(T);
+    ck(he_add(ev.h, &S, &T2, &S, ev.s));
+    T = T2;
+    own = true;
+  }
+  if (own) ev.release(T);
+  return S;
+}
+
 static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P, he_layer_plan* pl) {
   if (!fm || !pl || F < 1 || k < 1 || S < 1) return set_error(HE_EINVAL, "bad convolution arguments");
   const int slots = c->n / 2;
@@ -216,7 +257,7 @@ static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P
     for (int r : {-W, W, -1, 1}) add_keys(keys, r);
     ks = 8;
     lv = 1;
-    if (C > 1) { add_keys(keys, W * W); ks += F * (C - 1); }
+    if (C > 1) { chsum_keys(c, keys, C, W * W); ks += F * chsum_switches(c, C); }
     if (C > 1 || F > 1) { nmask = F; lv++; }
     he_fmap o1{F, W, W, W, W * W, (fm->reps == 2 && 2 * F * W * W == slots) ? 2 : 1};
     pl->out = o1;
@@ -237,7 +278,7 @@ static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P
       if (r) add_keys(keys, r);
     ks = k * k - 1;
     lv = 1;
-    if (C > 1) { add_keys(keys, fm->chan_stride); ks += F * (C - 1); nmask = 1; lv++; }
+    if (C > 1) { chsum_keys(c, keys, C, fm->chan_stride); ks += F * chsum_switches(c, C); nmask = 1; lv++; }
     if (F > 1) { add_keys(keys, -fm->chan_stride); ks += F - 1; }
     pl->out = he_fmap{F, H1, W1, fm->row_stride, fm->chan_stride, 1};
     if (S > 1) {
@@ -275,16 +316,9 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
       he_ct A = ev.rescale_take(mac_all(ev, taps, kern + 9 * f));
       he_ct Ssum = A;
       if (C > 1) {
-        // S_f = A_f + Rot_{W^2}(A_f) + Rot_{2 W^2}(A_f) + ..., chained with the single key W^2
-        Ssum = ev.copy(A);
-        he_ct T = A;
-        for (int cc = 1; cc < C; cc++) {
-          he_ct T2 = ev.rot(T, W * W);
-          ev.release(T);
-          ck(he_add(ev.h, &Ssum, &T2, &Ssum, ev.s));
-          T = T2;
-        }
-        ev.release(T);
+        // S_f = A_f + Rot_{W^2}(A_f) + Rot_{2 W^2}(A_f) + ...
+        Ssum = channel_sum(ev, A, C, W * W);
+        ev.release(A);
       }
       if (place) {
         if (f == 0) y = ev.mul(Ssum, masks[0]);
@@ -324,15 +358,8 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
     he_ct A = ev.rescale_take(mac_all(ev, taps, kern + k * k * f));
     he_ct term = A;
     if (C > 1) {
-      he_ct sum = ev.copy(A);
-      he_ct T = A;
-      for (int cc = 1; cc < C; cc++) {
-        he_ct T2 = ev.rot(T, cs);
-        ev.release(T);
-        ck(he_add(ev.h, &sum, &T2, &sum, ev.s));
-        T = T2;
-      }
-      ev.release(T);
+      he_ct sum = channel_sum(ev, A, C, cs);
+      ev.release(A);
       term = ev.rescale_take(ev.mul(sum, masks[0]));
       ev.release(sum);
     }
@@ -613,6 +640,13 @@ static int check_pts(const Ctx* c, const he_pt* p, int n, int level, const char*
 
 
 extern "C" {
+
+int he_ctx_conv_channel_sum(he_ctx* h, int mode) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  if (mode != HE_CHSUM_CHAIN && mode != HE_CHSUM_LOG) return set_error(HE_EINVAL, "unknown channel-sum mode");
+  h->c.chsum = mode;
+  return HE_OK;
+}
 
 int he_conv2d_plan(const he_ctx* h, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
                    he_layer_plan* plan) {

@@ -21,6 +21,7 @@ ERRORS = {
 }
 KEY_RELIN = 0x7FFFFFFF
 NTT_VARIANTS = 5
+CHSUM_CHAIN, CHSUM_LOG = 0, 1  # he_ctx_conv_channel_sum modes
 MAX_Q, MAX_P = 60, 16
 
 
@@ -136,6 +137,7 @@ def lib():
             "he_ctx_ntt_tuning": [vp, P(i32), P(ctypes.c_float)],
             "he_ntt_variant": [c_int, P(i32), P(i32)],
             "he_ctx_ntt_select": [vp, P(i32)],
+            "he_ctx_conv_channel_sum": [vp, i32],
             "he_key_host_register": [vp, i32, P(ctypes.c_uint64), sz],
             "he_key_cache_limit": [vp, sz],
             "he_key_prefetch": [vp, P(i32), c_int, vp],
@@ -478,6 +480,11 @@ class Context:
     def ntt_select(self, variants):
         """Pin the NTT variant of each batch-size bucket (4 entries)."""
         _check(lib().he_ctx_ntt_select(self.h, (ctypes.c_int32 * 4)(*[int(v) for v in variants])))
+
+    def conv_channel_sum(self, mode):
+        """Input-channel sum of later conv2d plans and calls: CHSUM_CHAIN (the
+        paper's single-key chain) or CHSUM_LOG (doubling, log2 C keys)."""
+        _check(lib().he_ctx_conv_channel_sum(self.h, int(mode)))
 
     def ntt_variants(self):
         var = (ctypes.c_int32 * 4)()

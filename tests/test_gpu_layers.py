@@ -67,18 +67,21 @@ def encrypt_map(name, X, fm, seed, level=None):
     return ct
 
 
-def run_conv(g, name, X, K, fm, stride, padding, seed, level=None):
+def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False):
+    from paper_2510_03996_amd import he
+
     octx, sk, _ = H.oracle_ctx(name)
     slots = octx.n // 2
     F, _, k, _ = K.shape
+    g.conv_channel_sum(he.CHSUM_LOG if logstep else he.CHSUM_CHAIN)
     plan = g.conv2d_plan(fm_he(fm), F, k, stride, padding)
-    assert sorted(plan.keys()) == LY.conv_rotations(fm, F, k, stride, padding, slots)
+    assert sorted(plan.keys()) == LY.conv_rotations(fm, F, k, stride, padding, slots, logstep=logstep)
     ev = setup_keys(g, name, plan.keys())
     ct = encrypt_map(name, X, fm, seed, level)
     kern, masks = LY.conv_plaintexts(fm, K, stride, padding, slots)
     assert (plan.n_kernel_pts, plan.n_mask_pts) == (len(kern), len(masks))
     kp, mp = encode(octx, kern, ct.level), encode(octx, masks, ct.level)
-    want, fo = LY.conv2d(ev, ct, fm, F, k, stride, padding, kp, mp, slots)
+    want, fo = LY.conv2d(ev, ct, fm, F, k, stride, padding, kp, mp, slots, logstep=logstep)
     assert ev.ks == plan.key_switches and ct.level - want.level == plan.levels
     got, gfm = g.conv2d(g.ct_from_numpy(ct.data, ct.scale), fm_he(fm), F, k, stride, padding, gpts(g, kp),
                         gpts(g, mp))
@@ -87,6 +90,7 @@ def run_conv(g, name, X, K, fm, stride, padding, seed, level=None):
     dec = LY.unpack(octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale)), fo)
     err = np.max(np.abs(dec - LY.conv2d_ref(X, K, stride, padding)))
     assert err < 1e-3, err
+    g.conv_channel_sum(he.CHSUM_CHAIN)
     return got, want, fo
 
 
@@ -227,3 +231,29 @@ def test_layer_errors(gctx):
         g.poly4(gct, RELU_COEFFS, 2.0 ** 45)
     assert e.value.name in ("HE_ELEVEL", "HE_ENOKEY")
     assert plan.n_kernel_pts == 150
+
+
+@pytest.mark.parametrize("stride", [1, 2])
+def test_config2_special_conv_logstep(gctx, stride):
+    """Log-step input-channel sum (he_ctx_conv_channel_sum): 4 replicated
+    channels of 64x64 at N=2^16, keys W^2 and 2 W^2, stride 1 and 2."""
+    X = synth.image(71, 4, 64, 64)
+    K = synth.conv_weights(71, 4, 4, 3, (2.0 / 36) ** 0.5)
+    run_conv(gctx("config2"), "config2", X, K, LY.FMap(4, 64, 64, reps=2), stride, 1, 71, logstep=True)
+
+
+def test_config1_generic_conv_logstep(gctx):
+    """Log-step channel sum in the generic schedule: C=4 -> F=3, 5x5, stride 2,
+    pad 2 at N=2^14 (keys cs and 2 cs)."""
+    X = synth.image(72, 4, 16, 16)
+    K = synth.conv_weights(72, 3, 4, 5, 0.1)
+    run_conv(gctx("config1"), "config1", X, K, LY.FMap(4, 16, 16), 2, 2, 72, logstep=True)
+
+
+def test_channel_sum_mode_errors(gctx):
+    from paper_2510_03996_amd import he
+
+    g = gctx("config0")
+    with pytest.raises(he.HEError) as e:
+        g.conv_channel_sum(7)
+    assert e.value.name == "HE_EINVAL"

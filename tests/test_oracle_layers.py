@@ -258,3 +258,87 @@ def test_he_config2_small_special_conv_decrypts():
     assert ev.ks == 20
     err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, y), fo) - LY.conv2d_ref(X, K, 1, 1)))
     assert err < 1e-3, err
+
+
+# ---------------------------------------------------------------- log-step channel sum
+def test_channel_sum_keys_closed_form():
+    assert LY.channel_sum_keys(16, 1024, True) == {1024, 2048, 4096, 8192}
+    assert LY.channel_sum_keys(16, 1024, False) == {1024}
+    assert LY.channel_sum_keys(6, 784, True) == {784}  # not a power of two: the chain
+    assert LY.channel_sum_keys(1, 784, True) == set()
+    assert LY.channel_sum_keys(2, 5, True) == {5}
+
+
+@pytest.mark.parametrize("C", [2, 4, 8, 16])
+def test_channel_sum_logstep_equals_chain_and_brute_force(C):
+    """Doubling and the chain give the same slot vector, and it equals the sum
+    of the C cyclic shifts written out (rotation = left shift of the slots)."""
+    slots = 4096
+    step = 37
+    rng = np.random.default_rng(C)
+    v = rng.uniform(-1, 1, slots)
+    want = sum(np.roll(v, -j * step) for j in range(C))
+    for logstep, ks in ((False, C - 1), (True, C.bit_length() - 1)):
+        ev = sim(slots)
+        S = LY.channel_sum(ev, LY.SimCt(v, 3), C, step, logstep)
+        assert ev.ks == ks
+        assert np.max(np.abs(S.v - want)) < 1e-12
+
+
+@pytest.mark.parametrize("stride,F", [(1, 16), (2, 32)])
+def test_sim_config2_special_conv_logstep(stride, F):
+    """The ResNet-shaped special convolutions with the log-step channel sum:
+    same output as the FP64 convolution with F log2(C) instead of F (C - 1)
+    channel-sum key switches."""
+    slots = 32768
+    X = synth.image(2, 16, 32, 32)
+    K = synth.conv_weights(2, F, 16, 3, (2.0 / 144) ** 0.5)
+    fm = LY.FMap(16, 32, 32, reps=2)
+    kern, masks = LY.conv_plaintexts(fm, K, stride, 1, slots)
+    ev = sim(slots)
+    y, fo = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 24), fm, F, 3, stride, 1, kern, masks, slots,
+                      logstep=True)
+    assert np.max(np.abs(LY.unpack(y.v, fo) - LY.conv2d_ref(X, K, stride, 1))) < 1e-9
+    if stride == 1:
+        assert ev.ks == 8 + 16 * 4 and np.array_equal(y.v[:16384], y.v[16384:])
+    else:
+        assert ev.ks == 549 - 32 * 15 + 32 * 4
+    keys = LY.conv_rotations(fm, F, 3, stride, 1, slots, logstep=True)
+    assert {1024, 2048, 4096, 8192} <= set(keys) and len(keys) == (8 if stride == 1 else 10)
+
+
+def test_sim_generic_conv_logstep():
+    """Generic convolution (5x5, pad 2, stride 2) over 4 input channels with
+    the log-step channel sum: equals the FP64 convolution."""
+    slots = 8192
+    X = synth.image(5, 4, 16, 16)
+    K = synth.conv_weights(5, 3, 4, 5, 0.1)
+    fm = LY.FMap(4, 16, 16)
+    kern, masks = LY.conv_plaintexts(fm, K, 2, 2, slots)
+    ev = sim(slots)
+    y, fo = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 12), fm, 3, 5, 2, 2, kern, masks, slots, logstep=True)
+    assert np.max(np.abs(LY.unpack(y.v, fo) - LY.conv2d_ref(X, K, 2, 2))) < 1e-9
+    chain = sim(slots)
+    LY.conv2d(chain, LY.SimCt(LY.pack(X, fm, slots), 12), fm, 3, 5, 2, 2, kern, masks, slots)
+    assert chain.ks - ev.ks == 3 * (3 - 2)
+
+
+@pytest.mark.slow
+def test_he_config2_small_special_conv_logstep_decrypts():
+    """The encrypted special convolution with the log-step channel sum (4
+    replicated channels of 64x64 at N=2^16): 8 + 4 * 2 key switches."""
+    name = "config2"
+    ctx2, _, _ = H.oracle_ctx(name)
+    slots = ctx2.n // 2
+    X = synth.image(12, 4, 64, 64)
+    K = synth.conv_weights(12, 4, 4, 3, (2.0 / 36) ** 0.5)
+    fm = LY.FMap(4, 64, 64, reps=2)
+    ev, ctx, sk, pk = he_eval(name, LY.conv_rotations(fm, 4, 3, 1, 1, slots, logstep=True))
+    kern, masks = LY.conv_plaintexts(fm, K, 1, 1, slots)
+    _, ct = H.encrypt_slots(name, 12, values=LY.pack(X, fm, slots))
+    L = ctx.pr.L
+    y, fo = LY.conv2d(ev, ct, fm, 4, 3, 1, 1, encode_all(ctx, kern, L), encode_all(ctx, masks, L), slots,
+                      logstep=True)
+    assert ev.ks == 16
+    err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, y), fo) - LY.conv2d_ref(X, K, 1, 1)))
+    assert err < 1e-3, err

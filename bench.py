@@ -366,7 +366,7 @@ def batched(reps=2):
 def synthetic_serving_models(seed=1):
     """LeNet-shaped (N=2^14) and ResNet-shaped (N=2^16) models with synthetic
     resident keys and weight plaintexts; returns (models, make_input)."""
-    from paper_2510_03996_amd import models, serve
+    from paper_2510_03996_amd import he, models, serve
 
     c1 = new_ctx(CFG1)
     fm0, pc, pp, k1 = models.lenet_plan(c1)
@@ -374,6 +374,7 @@ def synthetic_serving_models(seed=1):
     lenet = models.lenet_chain(c1, synthetic_pts(c1, pc.n_kernel_pts, 8, seed * 100 + 2, 2.0 ** 45),
                                synthetic_pts(c1, pp.n_mask_pts, 8, seed * 100 + 3, 2.0 ** 45), 2.0 ** 45)
     c2 = new_ctx(CFG2)
+    c2.conv_channel_sum(he.CHSUM_LOG)  # the served ResNet-shaped chain sums input channels by doubling
     fm0, pa, pb, pg, pf, k2 = models.resnet_plan(c2)
     upload_synthetic_keys(c2, k2, seed * 100 + 4)
     sc = 2.0 ** 50
@@ -409,7 +410,8 @@ def serving(n_req):
     t_len = np.mean([r.t_done - r.t_admit for r in w if r.kind == "lenet"])
     t_res = np.mean([r.t_done - r.t_admit for r in w if r.kind == "resnet"])
     mean_service = 0.75 * t_len + 0.25 * t_res
-    res = {"workload": "Poisson arrivals, LeNet-5-shaped N=2^14 (3/4) and ResNet-20-shaped N=2^16 (1/4) requests",
+    res = {"workload": "Poisson arrivals, LeNet-5-shaped N=2^14 (3/4) and ResNet-20-shaped N=2^16 (1/4, log-step "
+                       "channel sums) requests",
            "requests": n_req, "slots": 4, "service_ms": {"lenet": round(t_len * 1e3, 2), "resnet": round(t_res * 1e3, 2)}}
     kinds = ["lenet" if k == 0 else "resnet" for k in synth.request_mix(11, n_req)]
     inputs = [make_input(k, 1000 + i) for i, k in enumerate(kinds)]

@@ -72,27 +72,6 @@ __global__ __launch_bounds__(256) void k_ip_multi(const uint64_t* __restrict__ e
   }
 }
 
-// ModDown epilogue for every pair of one key: z = 2 pair + poly.
-__global__ __launch_bounds__(256) void k_combine_multi(const uint64_t* __restrict__ u_all, size_t En,
-                                                       const uint64_t* __restrict__ y_all,
-                                                       const uint64_t* __restrict__ in_all, size_t in_item,
-                                                       const int32_t* __restrict__ items, uint32_t g,
-                                                       uint64_t* __restrict__ rot_out, int level, int logn,
-                                                       const ModInfo* __restrict__ mods,
-                                                       const uint64_t* __restrict__ pinv) {
-  const size_t n = (size_t)1 << logn;
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y, z = blockIdx.z;
-  const int pair = z >> 1, poly = z & 1;
-  const uint64_t q = mods[i].q;
-  const size_t ln = (size_t)level * n;
-  uint64_t a = 0;
-  if (poly == 0) a = in_all[items[pair] * in_item + (size_t)i * n + (g == 1 ? k : automorph_src(k, g, logn))];
-  const uint64_t v = moddown_elem(u_all[(size_t)pair * 2 * En + poly * En + (size_t)i * n + k],
-                                  y_all[(size_t)z * ln + (size_t)i * n + k], a, pinv[i], pinv[level + i], q);
-  rot_out[(size_t)z * ln + (size_t)i * n + k] = v;
-}
-
 // out[i,o] (unrescaled) for every item: grid (items, tiles of 256
 // coefficients, limbs), the (item, tile) of a workgroup decoded from its
 // linear id as below.  A thread keeps OG outputs' 128-bit accumulators
@@ -312,14 +291,20 @@ static int run_batched(Batch* b, hipStream_t s) {
       k_bconv<<<grid, 256, 0, s>>>(b->u, E * N, b->y, ln, set.d, 1, c->d_mod, c->log_n);
       HE_HIP(hipGetLastError());
     }
-    if ((rc = ntt_launch(c, b->y, ln, z, range_map(0, l, 0), false, s))) return rc;
-    {
-      ProfScope ps(c, "moddown_combine", s, 8.0 * N * l * z * 3.5, (double)N * l * z);
-      k_combine_multi<<<dim3(N / 256, l, z), 256, 0, s>>>(b->u, E * N, b->y, b->in, in_item, gk.d_items, gk.g,
-                                                          b->rot + (size_t)gk.first_pair * 2 * ln, l, c->log_n,
-                                                          c->d_mod, c->d_pinv[l]);
-      HE_HIP(hipGetLastError());
-    }
+    // back to NTT form with the ModDown combine in the last pass: rotated copy
+    // z = 2 pair + poly = add + (u - y) P^{-1}, add = phi_g(c0 of the pair's item) for poly 0
+    NttEpi epi{};
+    epi.u = b->u;
+    epi.u_bs = E * N;
+    epi.pinv = c->d_pinv[l];
+    epi.g = gk.g;
+    epi.level = l;
+    epi.items = gk.d_items;
+    epi.add_base = b->in;
+    epi.add_item = in_item;
+    epi.out_base = b->rot + (size_t)gk.first_pair * 2 * ln;
+    epi.out_bs = ln;
+    if ((rc = ntt_launch_moddown(c, b->y, ln, range_map(0, l, 0), epi, s, z))) return rc;
   }
   // 3. fused multiply-accumulate of every output
   {

@@ -172,8 +172,18 @@ struct NttEpi {
                          // double bits) [level] P^{-1} and [level] P^{-1} / q_i
   uint32_t g;
   int32_t level;
+  // batched form (items != nullptr): batch z = 2 pair + poly writes
+  // out_base + z out_bs; add_z = add_base + items[pair] add_item for poly 0
+  // (gathered through phi_g), none for poly 1
+  const int32_t* items;
+  const uint64_t* add_base;
+  size_t add_item;
+  uint64_t* out_base;
+  size_t out_bs;
 };
-int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& map, const NttEpi& epi, hipStream_t s);
+// the last forward NTT with the ModDown epilogue, over nbatch arrays of y
+int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& map, const NttEpi& epi, hipStream_t s,
+                       int nbatch = 2);
 // Key inner product fused into the last forward pass of ModUp (one key
 // switch): for every ext position pos < E = level + K and both key polys j,
 //   u_j[pos][k] = sum_d e_d[pos][src(k)] key_d[j][mod(pos)][k] 2^-64 mod q

@@ -43,11 +43,12 @@ __device__ __forceinline__ void ntt_store(uint64_t* a, int k, uint64_t v, const 
     a[k] = v;
   } else {
     const size_t off = (size_t)i << LOGN;
-    const uint64_t* add = epi.add[z];
+    const bool gather = epi.items ? (z & 1) == 0 : z == 0;  // the polynomial c0 is added to
+    const uint64_t* add = epi.items ? (gather ? epi.add_base + epi.items[z >> 1] * epi.add_item : nullptr) : epi.add[z];
+    uint64_t* out = epi.items ? epi.out_base + z * epi.out_bs : epi.out[z];
     uint64_t x = 0;
-    if (add) x = add[off + (z == 0 && epi.g != 1 ? automorph_src(k, epi.g, LOGN) : (uint32_t)k)];
-    epi.out[z][off + k] =
-        moddown_elem(epi.u[z * epi.u_bs + off + k], v, x, epi.pinv[i], epi.pinv[epi.level + i], q);
+    if (add) x = add[off + (gather && epi.g != 1 ? automorph_src(k, epi.g, LOGN) : (uint32_t)k)];
+    out[off + k] = moddown_elem(epi.u[z * epi.u_bs + off + k], v, x, epi.pinv[i], epi.pinv[epi.level + i], q);
   }
 }
 
@@ -102,16 +103,18 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
       const size_t off = (size_t)pos << LOGN;
       const double pw = bits_to_f64(epi.pinv[2 * epi.level + pos]);
       const double pwq = bits_to_f64(epi.pinv[3 * epi.level + pos]);
-      const uint64_t* add = epi.add[bz];
+      const bool gather = epi.items ? (bz & 1) == 0 : bz == 0;  // the polynomial c0 is added to
+      const uint64_t* add =
+          epi.items ? (gather ? epi.add_base + epi.items[bz >> 1] * epi.add_item : nullptr) : epi.add[bz];
       const uint64_t* u = epi.u + bz * epi.u_bs + off;
-      uint64_t* o = epi.out[bz] + off;
+      uint64_t* o = (epi.items ? epi.out_base + bz * epi.out_bs : epi.out[bz]) + off;
       for (int e = tid; e < P::TILE; e += P::THREADS) {
         int g, k;
         P::tile_elem(e, g, k);
         const int kk = P::gidx(wg, g, k);
         const double r = mul_f64_c(u52_to_f64(u[kk]) - dl[P::lidx(g, k)], pw, pwq, dq);
         double x = 0.0;
-        if (add) x = u52_to_f64(add[off + (bz == 0 && epi.g != 1 ? automorph_src(kk, epi.g, LOGN) : (uint32_t)kk)]);
+        if (add) x = u52_to_f64(add[off + (gather && epi.g != 1 ? automorph_src(kk, epi.g, LOGN) : (uint32_t)kk)]);
         o[kk] = f64_to_u52(canon_f64(r + x, dqinv, dq));
       }
     } else {
@@ -487,14 +490,16 @@ int ntt_launch_strided(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* dat
   return set_error(HE_EINVAL, "unsupported ring degree");
 }
 
-int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& map, const NttEpi& epi, hipStream_t s) {
-  if (map.n <= 0) return HE_OK;
+int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& map, const NttEpi& epi, hipStream_t s,
+                       int nbatch) {
+  if (map.n <= 0 || nbatch <= 0) return HE_OK;
+  if (nbatch > 65535) return set_error(HE_EINVAL, "NTT batch too large for one launch");
   // the transform runs in place on y (its scratch); results go to epi.out
   uint64_t* yy = const_cast<uint64_t*>(y);
   switch (c->log_n) {
-    case 12: return ntt_launch_n<12>(c, yy, y_bs, yy, y_bs, 2, map, false, s, &epi);
-    case 14: return ntt_launch_n<14>(c, yy, y_bs, yy, y_bs, 2, map, false, s, &epi);
-    case 16: return ntt_launch_n<16>(c, yy, y_bs, yy, y_bs, 2, map, false, s, &epi);
+    case 12: return ntt_launch_n<12>(c, yy, y_bs, yy, y_bs, nbatch, map, false, s, &epi);
+    case 14: return ntt_launch_n<14>(c, yy, y_bs, yy, y_bs, nbatch, map, false, s, &epi);
+    case 16: return ntt_launch_n<16>(c, yy, y_bs, yy, y_bs, nbatch, map, false, s, &epi);
   }
   return set_error(HE_EINVAL, "unsupported ring degree");
 }

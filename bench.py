@@ -259,6 +259,14 @@ def layer_latencies(reps=3):
         return x
 
     out["lenet5_stack_n14_ms"] = round(timed(lambda: run_chain(chain, ct), reps, s) * 1e3, 3)
+    # the same stack with the baby-step giant-step pooling compaction
+    c1.mask_chains(he.CHAIN_BSGS)
+    fm0, pc_b, pp_b, keys_b = models.lenet_plan(c1)
+    upload_synthetic_keys(c1, keys_b, 20, relin=True)
+    chain_b = models.lenet_chain(c1, synthetic_pts(c1, pc_b.n_kernel_pts, 8, 21, 2.0 ** 45),
+                                 synthetic_pts(c1, pp_b.n_mask_pts, 8, 22, 2.0 ** 45), 2.0 ** 45)
+    out["lenet5_stack_n14_bsgs_ms"] = round(timed(lambda: run_chain(chain_b, ct), reps, s) * 1e3, 3)
+    lenet_ks_b = pc_b.key_switches + pp_b.key_switches + 2
     c1.close()
     # ResNet-20-shaped layers, N=2^16
     c2 = new_ctx(CFG2)
@@ -283,11 +291,24 @@ def layer_latencies(reps=3):
     c2.conv_channel_sum(he.CHSUM_LOG)
     out["resnet_convB_s2_n16_logsum_ms"] = round(
         timed(lambda: c2.conv2d(ctb, pa.out, 32, 3, 2, 1, bk, bm, stream=s), reps, s) * 1e3, 3)
+    # and with the baby-step giant-step stride compaction as well
+    c2.mask_chains(he.CHAIN_BSGS)
+    pbb = c2.conv2d_plan(pa.out, 32, 3, 2, 1)
+    upload_synthetic_keys(c2, pbb.keys(), 30)
+    out["resnet_convB_s2_n16_logsum_bsgs_ms"] = round(
+        timed(lambda: c2.conv2d(ctb, pa.out, 32, 3, 2, 1, bk, bm, stream=s), reps, s) * 1e3, 3)
+    c2.mask_chains(he.CHAIN_HORNER)
     c2.conv_channel_sum(he.CHSUM_CHAIN)
     del bk, bm
     ctg = synthetic_ct(c2, 17, 37, sc)
     gm = synthetic_pts(c2, pg.n_mask_pts, 17, 38, sc)
     out["resnet_gap_32x16x16_n16_ms"] = round(timed(lambda: c2.avgpool(ctg, pb.out, 0, 1, gm, stream=s), reps, s) * 1e3, 3)
+    c2.mask_chains(he.CHAIN_BSGS)
+    pgb = c2.avgpool_plan(pb.out, 0, 1)
+    upload_synthetic_keys(c2, pgb.keys(), 30)
+    out["resnet_gap_32x16x16_n16_bsgs_ms"] = round(
+        timed(lambda: c2.avgpool(ctg, pb.out, 0, 1, gm, stream=s), reps, s) * 1e3, 3)
+    c2.mask_chains(he.CHAIN_HORNER)
     ctf = synthetic_ct(c2, 16, 39, sc)
     fr, fmk = synthetic_pts(c2, 10, 16, 40, sc), synthetic_pts(c2, 1, 16, 41, sc)
     out["resnet_fc_64x10_n16_ms"] = round(timed(lambda: c2.fc(ctf, 64, 10, fr, fmk, stream=s), reps, s) * 1e3, 3)
@@ -310,7 +331,9 @@ def layer_latencies(reps=3):
                            "resnet_convA": pa.key_switches, "resnet_convB": pb.key_switches,
                            "resnet_gap": pg.key_switches, "resnet_fc": pf.key_switches,
                            "conv7x7_s2_p3": p7.key_switches, "relu_cheb59": he.cheb_plan(cheb, True)[1],
-                           "resnet_convA_logsum": pal.key_switches, "resnet_convB_logsum": pbl.key_switches}
+                           "resnet_convA_logsum": pal.key_switches, "resnet_convB_logsum": pbl.key_switches,
+                           "resnet_convB_logsum_bsgs": pbb.key_switches, "resnet_gap_bsgs": pgb.key_switches,
+                           "lenet5_stack_bsgs": lenet_ks_b}
     c2.close()
     return out
 
@@ -375,6 +398,7 @@ def synthetic_serving_models(seed=1):
                                synthetic_pts(c1, pp.n_mask_pts, 8, seed * 100 + 3, 2.0 ** 45), 2.0 ** 45)
     c2 = new_ctx(CFG2)
     c2.conv_channel_sum(he.CHSUM_LOG)  # the served ResNet-shaped chain sums input channels by doubling
+    c2.mask_chains(he.CHAIN_BSGS)      # and compacts / gathers with baby-step giant-step chains
     fm0, pa, pb, pg, pf, k2 = models.resnet_plan(c2)
     upload_synthetic_keys(c2, k2, seed * 100 + 4)
     sc = 2.0 ** 50
@@ -411,7 +435,7 @@ def serving(n_req):
     t_res = np.mean([r.t_done - r.t_admit for r in w if r.kind == "resnet"])
     mean_service = 0.75 * t_len + 0.25 * t_res
     res = {"workload": "Poisson arrivals, LeNet-5-shaped N=2^14 (3/4) and ResNet-20-shaped N=2^16 (1/4, log-step "
-                       "channel sums) requests",
+                       "channel sums and baby-step giant-step mask chains) requests",
            "requests": n_req, "slots": 4, "service_ms": {"lenet": round(t_len * 1e3, 2), "resnet": round(t_res * 1e3, 2)}}
     kinds = ["lenet" if k == 0 else "resnet" for k in synth.request_mix(11, n_req)]
     inputs = [make_input(k, 1000 + i) for i, k in enumerate(kinds)]

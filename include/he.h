@@ -286,6 +286,21 @@ int he_conv2d_plan(const he_ctx* ctx, const he_fmap* in_map, int out_ch, int ker
 #define HE_CHSUM_CHAIN 0
 #define HE_CHSUM_LOG 1
 int he_ctx_conv_channel_sum(he_ctx* ctx, int mode);
+/* Masked rotation chains sum_{t<n} Rot_{t key}(v . m_t) of the layers (the
+ * three stride-compaction steps of he_conv2d / he_avgpool and the channel
+ * gather of global pooling), chosen per context for later plans and calls:
+ *   HE_CHAIN_HORNER (default): acc = RS(v.m_{n-1}); acc = Rot_key(acc) +
+ *     RS(v.m_t), n - 1 key switches, one key;
+ *   HE_CHAIN_BSGS: baby-step giant-step with B = ceil(sqrt n), A =
+ *     ceil(n / B): one hoisted group of the rotations b key (b < B) of v, inner
+ *     sums I_a = RS(sum_b Rot_{b key}(v) . m_{aB+b}) and a Horner chain over a
+ *     with key B key: (B - 1) + (A - 1) key switches, B keys.  The caller
+ *     supplies mask t = a B + b rotated by b key (Rot_{b key}(m_t)), in the
+ *     same order and number as for Horner.
+ * Same plaintext result, other ciphertexts.  HE_EINVAL for another mode. */
+#define HE_CHAIN_HORNER 0
+#define HE_CHAIN_BSGS 1
+int he_ctx_mask_chains(he_ctx* ctx, int mode);
 int he_conv2d(he_ctx* ctx, const he_ct* in, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
               const he_pt* kernel_pts, int n_kernel_pts, const he_pt* mask_pts, int n_mask_pts, he_ct* out,
               he_fmap* out_map, he_stream stream);

@@ -302,6 +302,67 @@ def horner(ev, terms_fn, n, key):
     return acc
 
 
+def bsgs_split(n):
+    """Baby steps B = ceil(sqrt(n)) and giant steps A = ceil(n / B) of a masked chain."""
+    B = math.isqrt(n - 1) + 1 if n > 1 else 1
+    return B, (n + B - 1) // B
+
+
+def masked_chain_keys(n, key, bsgs):
+    """Rotation keys of masked_chain."""
+    if n <= 1:
+        return set()
+    if not bsgs:
+        return {key}
+    B, A = bsgs_split(n)
+    return {b * key for b in range(1, B)} | ({B * key} if A > 1 else set())
+
+
+def masked_chain_switches(n, bsgs):
+    if n <= 1:
+        return 0
+    if not bsgs:
+        return n - 1
+    B, A = bsgs_split(n)
+    return (B - 1) + (A - 1)
+
+
+def chain_masks(vecs, key, bsgs):
+    """Mask vectors of a masked chain: as given (Horner), or for the baby-step
+    giant-step chain mask t = a B + b pre-rotated by b key (Rot_r moves slot
+    i + r to slot i, i.e. np.roll by -r)."""
+    if not bsgs:
+        return list(vecs)
+    B, _ = bsgs_split(len(vecs))
+    return [np.roll(m, -(t % B) * key) for t, m in enumerate(vecs)]
+
+
+def masked_chain(ev, v, masks, n, key, bsgs=False):
+    """sum_{t<n} Rot_{t key}(v (.) m_t), one level.
+
+    Horner (default): acc = RS(v.m_{n-1}); acc = Rot_key(acc) + RS(v.m_t),
+    n - 1 key switches.  Baby-step giant-step: with t = a B + b,
+    Rot_{t key}(v.m_t) = Rot_{a B key}(Rot_{b key}(v) . Rot_{b key}(m_t)), so
+    with the pre-rotated masks m'_t (chain_masks) the inner sums
+    I_a = RS(sum_b Rot_{b key}(v) . m'_{aB+b}) use one hoisted group of B - 1
+    rotations of v, and acc = I_{A-1}; acc = Rot_{B key}(acc) + I_a adds
+    A - 1 more.
+    """
+    if not bsgs:
+        return horner(ev, lambda t: ev.mul_plain(v, masks[t]), n, key)
+    B, A = bsgs_split(n)
+    baby = [v] + (ev.rot_hoisted(v, [b * key for b in range(1, B)]) if B > 1 else [])
+
+    def inner(a):
+        idx = [t for t in range(a * B, min(n, a * B + B))]
+        return ev.rescale(mac(ev, [baby[t - a * B] for t in idx], [masks[t] for t in idx]))
+
+    acc = inner(A - 1)
+    for a in range(A - 2, -1, -1):
+        acc = ev.add(ev.rot(acc, B * key), inner(a))
+    return acc
+
+
 def compaction_plan(fm, S, Ho, Wo):
     """Steps of the stride-S extraction of outputs (S i, S j), jointly over all
     channels: (i) columns, key S-1; (ii) rows, key D = S rs - Wo;
@@ -318,9 +379,10 @@ def compaction_plan(fm, S, Ho, Wo):
     return steps
 
 
-def compaction_masks(fm, S, Ho, Wo, col_scale, slots):
+def compaction_masks(fm, S, Ho, Wo, col_scale, slots, bsgs=False):
     vecs = []
-    for step, n, _ in compaction_plan(fm, S, Ho, Wo):
+    for step, n, key in compaction_plan(fm, S, Ho, Wo):
+        sv = []
         for t in range(n):
             m = np.zeros(slots)
             for c in range(fm.C):
@@ -332,17 +394,25 @@ def compaction_masks(fm, S, Ho, Wo, col_scale, slots):
                     m[base:base + Wo] = 1.0
                 elif step == "chan" and c == t:
                     m[c * fm.cs:c * fm.cs + Ho * Wo] = 1.0
-            vecs.append(m)
+            sv.append(m)
+        vecs += chain_masks(sv, key, bsgs)
     return vecs
 
 
-def compaction(ev, v, fm, S, Ho, Wo, masks):
+def compaction_keys(fm, S, Ho, Wo, bsgs=False):
+    keys = set()
+    for _, n, key in compaction_plan(fm, S, Ho, Wo):
+        keys |= masked_chain_keys(n, key, bsgs)
+    return keys
+
+
+def compaction(ev, v, fm, S, Ho, Wo, masks, bsgs=False):
     """Move output (c, i, j) from c cs + S i rs + S j to c Ho Wo + i Wo + j."""
     pos = 0
     for step, n, key in compaction_plan(fm, S, Ho, Wo):
         ms = masks[pos:pos + n]
         pos += n
-        v = horner(ev, lambda t, ms=ms, v=v: ev.mul_plain(v, ms[t]), n, key)
+        v = masked_chain(ev, v, ms, n, key, bsgs)
     assert pos == len(masks)
     return v, FMap(fm.C, Ho, Wo, Wo, Ho * Wo, 1)
 
@@ -387,7 +457,7 @@ def conv_out_map(fm, F, k, stride, padding, slots):
     return FMap(F, Ho, Wo, Wo, Ho * Wo, 1)
 
 
-def conv_plaintexts(fm, K, stride, padding, slots):
+def conv_plaintexts(fm, K, stride, padding, slots, bsgs=False):
     """Real vectors the convolution multiplies by, in the order the schedule
     (and the GPU library) consumes them: kernel vectors [f][tap], then masks."""
     F, C, k, _ = K.shape
@@ -414,7 +484,7 @@ def conv_plaintexts(fm, K, stride, padding, slots):
                 masks.append(m)
         if stride > 1:
             Ho = (W - 1) // stride + 1
-            masks += compaction_masks(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, 1.0, slots)
+            masks += compaction_masks(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, 1.0, slots, bsgs)
     else:
         # tap (i, j) at output (y, x) reads input (y + i - P, x + j - P): the
         # kernel value where that neighbour is inside the image, 0 elsewhere
@@ -438,7 +508,7 @@ def conv_plaintexts(fm, K, stride, padding, slots):
             masks.append(m)
         if stride > 1:
             Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
-            masks += compaction_masks(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0, slots)
+            masks += compaction_masks(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0, slots, bsgs)
     return kern, masks
 
 
@@ -475,7 +545,7 @@ def channel_sum(ev, A, C, step, logstep=False):
     return S
 
 
-def conv_rotations(fm, F, k, stride, padding, slots, logstep=False):
+def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False):
     """Distinct rotation keys the schedule uses (the paper's per-layer index helper)."""
     kind = conv_kind(k, padding, fm, F)
     keys = set()
@@ -485,7 +555,7 @@ def conv_rotations(fm, F, k, stride, padding, slots, logstep=False):
         keys |= channel_sum_keys(fm.C, W * W, logstep)
         if stride > 1:
             Ho = (W - 1) // stride + 1
-            keys |= {key for _, _, key in compaction_plan(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho)}
+            keys |= compaction_keys(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, bsgs)
     else:
         keys |= {r for r in conv_taps(fm, k, padding) if r != 0}
         keys |= channel_sum_keys(fm.C, fm.cs, logstep)
@@ -494,11 +564,11 @@ def conv_rotations(fm, F, k, stride, padding, slots, logstep=False):
         if stride > 1:
             H1, W1 = conv_dims(fm, k, padding)
             Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
-            keys |= {key for _, _, key in compaction_plan(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo)}
+            keys |= compaction_keys(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, bsgs)
     return sorted(keys)
 
 
-def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False):
+def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False, bsgs=False):
     """Pinned convolution schedule.
 
     special (k=3, P=1): r = Algorithm 1 rotations computed as three hoisted
@@ -541,7 +611,7 @@ def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False):
         if stride == 1:
             return y, out1
         Ho = (W - 1) // stride + 1
-        return compaction(ev, y, FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, masks[mpos:])
+        return compaction(ev, y, FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, masks[mpos:], bsgs)
     # generic
     offs = conv_taps(fm, k, padding)
     rot = iter(ev.rot_hoisted(x, [r for r in offs if r != 0]))
@@ -566,11 +636,11 @@ def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False):
     if stride == 1:
         return y, FMap(F, H1, W1, fm.rs, fm.cs, 1)
     Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
-    return compaction(ev, y, FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks[mpos:])
+    return compaction(ev, y, FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks[mpos:], bsgs)
 
 
 # ===================================================================== pooling
-def avgpool_plaintexts(fm, k, stride, slots):
+def avgpool_plaintexts(fm, k, stride, slots, bsgs=False):
     H1, W1 = fm.H - k + 1, fm.W - k + 1
     Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
     if stride == 1:
@@ -579,19 +649,19 @@ def avgpool_plaintexts(fm, k, stride, slots):
             for y in range(H1):
                 m[c * fm.cs + y * fm.rs:c * fm.cs + y * fm.rs + W1] = 1.0 / (k * k)
         return [m]
-    return compaction_masks(FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0 / (k * k), slots)
+    return compaction_masks(FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0 / (k * k), slots, bsgs)
 
 
-def avgpool_rotations(fm, k, stride):
+def avgpool_rotations(fm, k, stride, bsgs=False):
     keys = {i * fm.rs + j for i in range(k) for j in range(k) if (i, j) != (0, 0)}
     if stride > 1:
         H1, W1 = fm.H - k + 1, fm.W - k + 1
         Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
-        keys |= {key for _, _, key in compaction_plan(FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo)}
+        keys |= compaction_keys(FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, bsgs)
     return sorted(keys)
 
 
-def avgpool(ev, x, fm, k, stride, masks):
+def avgpool(ev, x, fm, k, stride, masks, bsgs=False):
     """Window sum by one hoisted group of the k^2-1 offsets i rs + j, then the
     stride compaction with 1/k^2 folded into the column masks."""
     offs = [i * fm.rs + j for i in range(k) for j in range(k)]
@@ -602,26 +672,25 @@ def avgpool(ev, x, fm, k, stride, masks):
     if stride == 1:
         return ev.rescale(ev.mul_plain(s, masks[0])), FMap(fm.C, H1, W1, fm.rs, fm.cs, 1)
     Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
-    return compaction(ev, s, FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks)
+    return compaction(ev, s, FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks, bsgs)
 
 
-def gap_plaintexts(fm, slots):
+def gap_plaintexts(fm, slots, bsgs=False):
     out = []
     for c in range(fm.C):
         m = np.zeros(slots)
         m[c * fm.cs] = 1.0 / (fm.H * fm.W)
         out.append(m)
-    return out
+    return chain_masks(out, fm.cs - 1, bsgs)
 
 
-def gap_rotations(fm):
+def gap_rotations(fm, bsgs=False):
     keys = {1 << t for t in range(int(math.log2(fm.cs)))}
-    if fm.C > 1:
-        keys.add(fm.cs - 1)
+    keys |= masked_chain_keys(fm.C, fm.cs - 1, bsgs)
     return sorted(keys)
 
 
-def gap(ev, x, fm, masks):
+def gap(ev, x, fm, masks, bsgs=False):
     """Global average pooling: S += Rot_{2^t}(S) for t < log2(cs) sums every
     channel block into its first slot; a Horner chain with key cs-1 and masks
     1/(H W) at c*cs gathers channel c into slot c."""
@@ -629,7 +698,7 @@ def gap(ev, x, fm, masks):
     S = x
     for t in range(int(math.log2(fm.cs))):
         S = ev.add(S, ev.rot(S, 1 << t))
-    y = horner(ev, lambda c: ev.mul_plain(S, masks[c]), fm.C, fm.cs - 1)
+    y = masked_chain(ev, S, masks, fm.C, fm.cs - 1, bsgs)
     return y, FMap(fm.C, 1, 1, 1, 1, 1)
 
 

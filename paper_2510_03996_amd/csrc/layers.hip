@@ -156,10 +156,57 @@ static int compaction_masks(const std::vector<Step>& st) {
   return n;
 }
 
-// acc = RS(v.m_{n-1}); acc = Rot_key(acc) + RS(v.m_t), t = n-2..0
+// Masked chain sum_{t<n} Rot_{t key}(v . m_t), one level.  Horner (default):
+// acc = RS(v.m_{n-1}); acc = Rot_key(acc) + RS(v.m_t), t = n-2..0 (n - 1
+// key switches).  Baby-step giant-step (HE_CHAIN_BSGS; the caller's masks
+// m_t, t = a B + b, pre-rotated by b key): one hoisted group of the B - 1
+// rotations b key of v, I_a = RS(sum_b Rot_{b key}(v) . m_{aB+b}), then
+// acc = I_{A-1}; acc = Rot_{B key}(acc) + I_a: (B - 1) + (A - 1) key switches.
+static void add_keys(std::vector<int>& keys, int k);
+static void bsgs_split(int n, int& B, int& A) {
+  B = 1;
+  while (B * B < n) B++;
+  A = (n + B - 1) / B;
+}
+static void chain_keys(const Ctx* c, std::vector<int>& keys, int n, int key) {
+  if (n <= 1) return;
+  if (c->chain != HE_CHAIN_BSGS) {
+    add_keys(keys, key);
+    return;
+  }
+  int B, A;
+  bsgs_split(n, B, A);
+  for (int b = 1; b < B; b++) add_keys(keys, b * key);
+  if (A > 1) add_keys(keys, B * key);
+}
+static int chain_switches(const Ctx* c, int n) {
+  if (n <= 1) return 0;
+  if (c->chain != HE_CHAIN_BSGS) return n - 1;
+  int B, A;
+  bsgs_split(n, B, A);
+  return (B - 1) + (A - 1);
+}
 static he_ct horner_masked(Ev& ev, const he_ct& v, const he_pt* m, int n, int key) {
-  he_ct acc = ev.rescale_take(ev.mul(v, m[n - 1]));
-  for (int t = n - 2; t >= 0; t--) acc = ev.add_take(ev.rot_take(acc, key), ev.rescale_take(ev.mul(v, m[t])));
+  if (ev.c->chain != HE_CHAIN_BSGS) {
+    he_ct acc = ev.rescale_take(ev.mul(v, m[n - 1]));
+    for (int t = n - 2; t >= 0; t--) acc = ev.add_take(ev.rot_take(acc, key), ev.rescale_take(ev.mul(v, m[t])));
+    return acc;
+  }
+  int B, A;
+  bsgs_split(n, B, A);
+  std::vector<int> offs;
+  for (int b = 1; b < B; b++) offs.push_back(b * key);
+  std::vector<he_ct> baby{v};
+  if (!offs.empty())
+    for (const he_ct& r : ev.rot_hoisted(v, offs)) baby.push_back(r);
+  auto inner = [&](int a) {
+    const int cnt = std::min(B, n - a * B);
+    std::vector<he_ct> cts(baby.begin(), baby.begin() + cnt);
+    return ev.rescale_take(mac_all(ev, cts, m + a * B));
+  };
+  he_ct acc = inner(A - 1);
+  for (int a = A - 2; a >= 0; a--) acc = ev.add_take(ev.rot_take(acc, B * key), inner(a));
+  for (size_t b = 1; b < baby.size(); b++) ev.release(baby[b]);
   return acc;
 }
 
@@ -265,7 +312,7 @@ static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P
       int Ho = (W - 1) / S + 1;
       he_fmap f1{F, W, W, W, W * W, 1};
       auto st = compaction_plan(f1, S, Ho, Ho);
-      for (auto& x : st) { add_keys(keys, x.key); ks += x.n - 1; lv++; }
+      for (auto& x : st) { chain_keys(c, keys, x.n, x.key); ks += chain_switches(c, x.n); lv++; }
       nmask += compaction_masks(st);
       pl->out = he_fmap{F, Ho, Ho, Ho, Ho * Ho, 1};
     }
@@ -285,7 +332,7 @@ static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P
       int Ho = (H1 - 1) / S + 1, Wo = (W1 - 1) / S + 1;
       he_fmap f1{F, H1, W1, fm->row_stride, fm->chan_stride, 1};
       auto st = compaction_plan(f1, S, Ho, Wo);
-      for (auto& x : st) { add_keys(keys, x.key); ks += x.n - 1; lv++; }
+      for (auto& x : st) { chain_keys(c, keys, x.n, x.key); ks += chain_switches(c, x.n); lv++; }
       nmask += compaction_masks(st);
       pl->out = he_fmap{F, Ho, Wo, Wo, Ho * Wo, 1};
     }
@@ -387,7 +434,8 @@ static int pool_plan(const Ctx* c, const he_fmap* fm, int k, int S, he_layer_pla
     if (fm->row_stride != fm->width || cs != fm->height * fm->width || (cs & (cs - 1)))
       return set_error(HE_EUNSUPPORTED, "global pooling needs dense power-of-two channel blocks");
     for (int t = 1; t < cs; t <<= 1) { add_keys(keys, t); ks++; }
-    if (fm->channels > 1) { add_keys(keys, cs - 1); ks += fm->channels - 1; }
+    chain_keys(c, keys, fm->channels, cs - 1);
+    ks += chain_switches(c, fm->channels);
     pl->n_mask_pts = fm->channels;
     pl->levels = 1;
     pl->out = he_fmap{fm->channels, 1, 1, 1, 1, 1};
@@ -405,7 +453,7 @@ static int pool_plan(const Ctx* c, const he_fmap* fm, int k, int S, he_layer_pla
       int Ho = (fm->height - k) / S + 1, Wo = (fm->width - k) / S + 1;
       he_fmap f1{fm->channels, H1, W1, fm->row_stride, fm->chan_stride, 1};
       auto st = compaction_plan(f1, S, Ho, Wo);
-      for (auto& x : st) { add_keys(keys, x.key); ks += x.n - 1; }
+      for (auto& x : st) { chain_keys(c, keys, x.n, x.key); ks += chain_switches(c, x.n); }
       pl->n_mask_pts = compaction_masks(st);
       pl->levels = (int)st.size();
       pl->out = he_fmap{fm->channels, Ho, Wo, Wo, Ho * Wo, 1};
@@ -640,6 +688,13 @@ static int check_pts(const Ctx* c, const he_pt* p, int n, int level, const char*
 
 
 extern "C" {
+
+int he_ctx_mask_chains(he_ctx* h, int mode) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  if (mode != HE_CHAIN_HORNER && mode != HE_CHAIN_BSGS) return set_error(HE_EINVAL, "unknown chain mode");
+  h->c.chain = mode;
+  return HE_OK;
+}
 
 int he_ctx_conv_channel_sum(he_ctx* h, int mode) {
   if (!h) return set_error(HE_EINVAL, "null context");

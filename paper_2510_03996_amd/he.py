@@ -22,6 +22,7 @@ ERRORS = {
 KEY_RELIN = 0x7FFFFFFF
 NTT_VARIANTS = 5
 CHSUM_CHAIN, CHSUM_LOG = 0, 1  # he_ctx_conv_channel_sum modes
+CHAIN_HORNER, CHAIN_BSGS = 0, 1  # he_ctx_mask_chains modes
 MAX_Q, MAX_P = 60, 16
 
 
@@ -138,6 +139,7 @@ def lib():
             "he_ntt_variant": [c_int, P(i32), P(i32)],
             "he_ctx_ntt_select": [vp, P(i32)],
             "he_ctx_conv_channel_sum": [vp, i32],
+            "he_ctx_mask_chains": [vp, i32],
             "he_key_host_register": [vp, i32, P(ctypes.c_uint64), sz],
             "he_key_cache_limit": [vp, sz],
             "he_key_prefetch": [vp, P(i32), c_int, vp],
@@ -485,6 +487,11 @@ class Context:
         """Input-channel sum of later conv2d plans and calls: CHSUM_CHAIN (the
         paper's single-key chain) or CHSUM_LOG (doubling, log2 C keys)."""
         _check(lib().he_ctx_conv_channel_sum(self.h, int(mode)))
+
+    def mask_chains(self, mode):
+        """Masked rotation chains of later layer plans and calls: CHAIN_HORNER
+        or CHAIN_BSGS (baby-step giant-step; masks pre-rotated by the caller)."""
+        _check(lib().he_ctx_mask_chains(self.h, int(mode)))
 
     def ntt_variants(self):
         var = (ctypes.c_int32 * 4)()

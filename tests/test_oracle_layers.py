@@ -342,3 +342,83 @@ def test_he_config2_small_special_conv_logstep_decrypts():
     assert ev.ks == 16
     err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, y), fo) - LY.conv2d_ref(X, K, 1, 1)))
     assert err < 1e-3, err
+
+
+# ---------------------------------------------------------------- baby-step giant-step masked chains
+def test_bsgs_split_closed_form():
+    assert [LY.bsgs_split(n) for n in (1, 2, 3, 4, 5, 6, 12, 16, 17, 32)] == [
+        (1, 1), (2, 1), (2, 2), (2, 2), (3, 2), (3, 2), (4, 3), (4, 4), (5, 4), (6, 6)]
+    assert LY.masked_chain_switches(32, True) == 10 and LY.masked_chain_switches(32, False) == 31
+    assert LY.masked_chain_keys(16, 48, True) == {48, 96, 144, 192}
+    assert LY.masked_chain_keys(16, 48, False) == {48} and LY.masked_chain_keys(1, 48, True) == set()
+
+
+@pytest.mark.parametrize("n,key", [(1, 5), (2, -1), (5, 7), (12, 255), (16, 1), (17, -33), (32, 768)])
+def test_masked_chain_bsgs_brute_force(n, key):
+    """sum_t Rot_{t key}(v m_t) written out with np.roll, against the Horner
+    chain (plain masks) and the baby-step giant-step chain (pre-rotated masks)."""
+    slots = 2048
+    rng = np.random.default_rng(n * 1000 + abs(key))
+    v = rng.uniform(-1, 1, slots)
+    ms = [rng.uniform(-1, 1, slots) for _ in range(n)]
+    want = sum(np.roll(v * m, -t * key) for t, m in enumerate(ms))
+    for bsgs in (False, True):
+        ev = sim(slots)
+        got = LY.masked_chain(ev, LY.SimCt(v, 4), LY.chain_masks(ms, key, bsgs), n, key, bsgs)
+        assert ev.ks == LY.masked_chain_switches(n, bsgs) and got.level == 3
+        assert np.max(np.abs(got.v - want)) < 1e-12
+
+
+def test_sim_config2_conv_b_logstep_bsgs():
+    """Conv B (16 -> 32, stride 2) with both options: 8 + 32 * 4 + (6 + 6 + 10)
+    key switches instead of 549, same output as the FP64 convolution."""
+    slots = 32768
+    X = synth.image(2, 16, 32, 32)
+    K = synth.conv_weights(2, 32, 16, 3, (2.0 / 144) ** 0.5)
+    fm = LY.FMap(16, 32, 32, reps=2)
+    kern, masks = LY.conv_plaintexts(fm, K, 2, 1, slots, bsgs=True)
+    ev = sim(slots)
+    y, fo = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 24), fm, 32, 3, 2, 1, kern, masks, slots,
+                      logstep=True, bsgs=True)
+    assert np.max(np.abs(LY.unpack(y.v, fo) - LY.conv2d_ref(X, K, 2, 1))) < 1e-9
+    assert ev.ks == 8 + 32 * 4 + 22 and 24 - y.level == 5 and fo == LY.FMap(32, 16, 16)
+    # taps {+-W, +-1}, column chain {1, 2, 3, 4} (1 shared with a tap), row chain
+    # 48 {1..4}, channel chain 768 {1..6}, channel sum 1024 {1, 2, 4, 8}
+    assert len(LY.conv_rotations(fm, 32, 3, 2, 1, slots, logstep=True, bsgs=True)) == 4 + 3 + 4 + 6 + 4
+
+
+@pytest.mark.parametrize("C,HW,ks", [(32, 16, 8 + 10), (64, 8, 6 + 14)])
+def test_sim_gap_bsgs(C, HW, ks):
+    slots = 32768
+    X = synth.image(4, C, HW, HW)
+    fm = LY.FMap(C, HW, HW)
+    ev = sim(slots)
+    y, fo = LY.gap(ev, LY.SimCt(LY.pack(X, fm, slots), 10), fm, LY.gap_plaintexts(fm, slots, bsgs=True), bsgs=True)
+    assert ev.ks == ks and y.level == 9
+    assert np.max(np.abs(y.v[:C] - LY.gap_ref(X))) < 1e-12 and np.max(np.abs(y.v[C:])) < 1e-12
+
+
+def test_he_config1_stack_bsgs_decrypts_to_fp64():
+    """The LeNet-shaped stack with the baby-step giant-step compaction in the
+    average pool: 61 - 27 + 13 key switches, decrypts to the FP64 layers."""
+    name = "config1"
+    ctx1, _, _ = H.oracle_ctx(name)
+    slots = ctx1.n // 2
+    X = synth.image(11, 1, 28, 28)
+    K = synth.conv_weights(11, 6, 1, 5, 0.1)
+    fm = LY.FMap(1, 28, 28)
+    f1 = LY.conv_out_map(fm, 6, 5, 1, 0, slots)
+    rots = sorted(set(LY.conv_rotations(fm, 6, 5, 1, 0, slots, bsgs=True)) |
+                  set(LY.avgpool_rotations(f1, 2, 2, bsgs=True)))
+    ev, ctx, sk, pk = he_eval(name, rots, relin=True)
+    kern, masks = LY.conv_plaintexts(fm, K, 1, 0, slots, bsgs=True)
+    _, ct = H.encrypt_slots(name, 11, values=LY.pack(X, fm, slots))
+    L = ctx.pr.L
+    y, f1 = LY.conv2d(ev, ct, fm, 6, 5, 1, 0, encode_all(ctx, kern, L), masks, slots, bsgs=True)
+    p = LY.relu_poly4(ev, y, ctx.pr.scale)
+    z, f2 = LY.avgpool(ev, p, f1, 2, 2, encode_all(ctx, LY.avgpool_plaintexts(f1, 2, 2, slots, bsgs=True), L),
+                       bsgs=True)
+    assert z.level == 1 and ev.ks == 61 - 27 + 13
+    ref = LY.avgpool_ref(LY.relu4_ref(LY.conv2d_ref(X, K, 1, 0)), 2, 2)
+    err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, z), f2) - ref))
+    assert err < 1e-2, err

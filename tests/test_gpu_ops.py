@@ -241,3 +241,33 @@ def test_error_codes(gctx):
     with pytest.raises(he.HEError) as e:
         g.rotate_hoisted(ga, [1], outs=[ga])
     assert e.value.name == "HE_EINVAL"
+
+
+# six one-limb digits: more digits than the fused inner-product kernel takes,
+# so single and hoisted key switches use the separate ModUp / inner product
+ckks.CONFIGS.setdefault("dnum6", dict(log_n=12, q_bits=[50, 45, 45, 45, 45, 45], p_bits=[55], alpha=1,
+                                      log_scale=40))
+
+
+def test_key_switch_many_digits():
+    name = "dnum6"
+    g = H.gpu_ctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    from paper_2510_03996_amd import he
+
+    rs = [3, -100]
+    keys = H.oracle_keys(name, rs)
+    for r, k in keys.items():
+        g.key_upload(r, k)
+    rk = H.oracle_key(name, "relin")
+    g.key_upload(he.KEY_RELIN, rk)
+    _, a = H.encrypt_slots(name, 41)
+    _, b = H.encrypt_slots(name, 42, enc_id=1)
+    ga = g.ct_from_numpy(a.data, a.scale)
+    H.assert_limbs_equal(g.rotate(ga, rs[0]).numpy(), octx.rotate(a, rs[0], keys).data, "rotate, 6 digits")
+    got = g.rotate_hoisted(ga, rs)
+    for x, y in zip(got, octx.rotate_hoisted(a, rs, keys)):
+        H.assert_limbs_equal(x.numpy(), y.data, "hoisted, 6 digits")
+    m = g.mul_relin(ga, g.ct_from_numpy(b.data, b.scale))
+    H.assert_limbs_equal(m.numpy(), octx.mul_relin(a, b, rk).data, "mul_relin, 6 digits")
+    g.close()

@@ -312,6 +312,13 @@ def layer_latencies(reps=3):
     ctf = synthetic_ct(c2, 16, 39, sc)
     fr, fmk = synthetic_pts(c2, 10, 16, 40, sc), synthetic_pts(c2, 1, 16, 41, sc)
     out["resnet_fc_64x10_n16_ms"] = round(timed(lambda: c2.fc(ctf, 64, 10, fr, fmk, stream=s), reps, s) * 1e3, 3)
+    c2.fc_form(he.FC_DIAG)
+    pfd = c2.fc_plan(64, 10)
+    upload_synthetic_keys(c2, pfd.keys(), 30)
+    fd = synthetic_pts(c2, pfd.n_kernel_pts, 16, 40, sc)
+    out["resnet_fc_64x10_n16_diag_ms"] = round(timed(lambda: c2.fc(ctf, 64, 10, fd, [], stream=s), reps, s) * 1e3, 3)
+    c2.fc_form(he.FC_ROWS)
+    del fd
     # zero padding by masked taps: 7x7 / stride 2 / padding 3 (the ResNet-34 stem shape), 3 x 32 x 32 -> 8
     fmp = he.fmap(3, 32, 32)
     p7 = c2.conv2d_plan(fmp, 8, 7, 2, 3)
@@ -333,7 +340,7 @@ def layer_latencies(reps=3):
                            "conv7x7_s2_p3": p7.key_switches, "relu_cheb59": he.cheb_plan(cheb, True)[1],
                            "resnet_convA_logsum": pal.key_switches, "resnet_convB_logsum": pbl.key_switches,
                            "resnet_convB_logsum_bsgs": pbb.key_switches, "resnet_gap_bsgs": pgb.key_switches,
-                           "lenet5_stack_bsgs": lenet_ks_b}
+                           "lenet5_stack_bsgs": lenet_ks_b, "resnet_fc_diag": pfd.key_switches}
     c2.close()
     return out
 
@@ -399,14 +406,15 @@ def synthetic_serving_models(seed=1):
     c2 = new_ctx(CFG2)
     c2.conv_channel_sum(he.CHSUM_LOG)  # the served ResNet-shaped chain sums input channels by doubling
     c2.mask_chains(he.CHAIN_BSGS)      # and compacts / gathers with baby-step giant-step chains
+    c2.fc_form(he.FC_DIAG)             # and takes the diagonal fully connected form
     fm0, pa, pb, pg, pf, k2 = models.resnet_plan(c2)
     upload_synthetic_keys(c2, k2, seed * 100 + 4)
     sc = 2.0 ** 50
     resnet = models.resnet_chain(
         c2, synthetic_pts(c2, pa.n_kernel_pts, 24, seed * 100 + 5, sc), synthetic_pts(c2, pa.n_mask_pts, 24, seed * 100 + 6, sc),
         synthetic_pts(c2, pb.n_kernel_pts, 22, seed * 100 + 7, sc), synthetic_pts(c2, pb.n_mask_pts, 22, seed * 100 + 8, sc),
-        synthetic_pts(c2, pg.n_mask_pts, 17, seed * 100 + 9, sc), synthetic_pts(c2, 10, 16, seed * 100 + 10, sc),
-        synthetic_pts(c2, 1, 16, seed * 100 + 11, sc))
+        synthetic_pts(c2, pg.n_mask_pts, 17, seed * 100 + 9, sc),
+        synthetic_pts(c2, pf.n_kernel_pts, 16, seed * 100 + 10, sc), synthetic_pts(c2, pf.n_mask_pts, 16, seed * 100 + 11, sc))
     nbuf = 24
     ms = {"lenet": serve.Model("lenet", c1, lenet.stages, nbuf, c1.lane_bytes(nbuf) + 4 * 2 * 8 * c1.n * 8),
           "resnet": serve.Model("resnet", c2, resnet.stages, nbuf, c2.lane_bytes(nbuf) + 4 * 2 * 24 * c2.n * 8)}
@@ -435,7 +443,7 @@ def serving(n_req):
     t_res = np.mean([r.t_done - r.t_admit for r in w if r.kind == "resnet"])
     mean_service = 0.75 * t_len + 0.25 * t_res
     res = {"workload": "Poisson arrivals, LeNet-5-shaped N=2^14 (3/4) and ResNet-20-shaped N=2^16 (1/4, log-step "
-                       "channel sums and baby-step giant-step mask chains) requests",
+                       "channel sums, baby-step giant-step mask chains, diagonal FC) requests",
            "requests": n_req, "slots": 4, "service_ms": {"lenet": round(t_len * 1e3, 2), "resnet": round(t_res * 1e3, 2)}}
     kinds = ["lenet" if k == 0 else "resnet" for k in synth.request_mix(11, n_req)]
     inputs = [make_input(k, 1000 + i) for i, k in enumerate(kinds)]

@@ -324,6 +324,22 @@ int he_avgpool(he_ctx* ctx, const he_ct* in, const he_fmap* in_map, int kernel, 
 int he_fc_plan(const he_ctx* ctx, int n_in, int n_out, he_layer_plan* plan);
 int he_fc(he_ctx* ctx, const he_ct* in, int n_in, int n_out, const he_pt* weight_pts, const he_pt* mask_pts,
           const he_pt* bias_pt, he_ct* out, he_stream stream);
+/* Form of later he_fc plans and calls:
+ *   HE_FC_ROWS (default): the per-neuron schedule above, n_out products,
+ *     n_out log2(n_in) + n_out - 1 key switches, two levels;
+ *   HE_FC_DIAG: the diagonal (Halevi-Shoup) form for n_out <= n_in with
+ *     baby-step giant-step (B = ceil(sqrt n_in), A = n_in / B rounded up):
+ *     x~ = x + Rot_{-n_in}(x), one hoisted group Rot_b(x~) (b < B), inner
+ *     sums I_a = sum_b Rot_b(x~) . w_{aB+b}, acc = I_{A-1}; acc = Rot_B(acc)
+ *     + I_a, one rescale: 1 + (B - 1) + (A - 1) key switches, one level.
+ *     weight_pts[d] (d < n_in) is diagonal d, W[j][(j + d) mod n_in] in slot
+ *     j < n_out, rotated by -(d / B) B; no mask_pts.  The input must be zero
+ *     in slots [n_in, 2 n_in) and in the top n_in slots (as global pooling
+ *     leaves it); the output is zero outside slots 0..n_out-1.
+ * HE_EINVAL for another mode. */
+#define HE_FC_ROWS 0
+#define HE_FC_DIAG 1
+int he_ctx_fc_form(he_ctx* ctx, int mode);
 
 /* Polynomial activation p(x) = c[0] + c[1] x + c[2] x^2 + c[4] x^4 (c[3]
  * must be 0) in three levels with two relinearizations:

@@ -733,6 +733,52 @@ def fc(ev, x, n_in, n_out, rows, masks):
     return horner(ev, lambda k: ev.mul_plain(sums[k], masks[0]), n_out, -1)
 
 
+def fc_diag_plaintexts(Wm, slots):
+    """Diagonal form of the fully connected layer (n_out <= n_in, n_in a power
+    of two): diagonal d holds W[j][(j + d) mod n_in] in slot j < n_out; with
+    d = a B + b (bsgs_split) it is supplied rotated by -a B (np.roll by +a B)
+    so that the inner sums of fc_diag need no further rotation."""
+    n_out, n_in = Wm.shape
+    assert n_in & (n_in - 1) == 0 and n_out <= n_in
+    B, _ = bsgs_split(n_in)
+    out = []
+    for d in range(n_in):
+        v = np.zeros(slots)
+        for j in range(n_out):
+            v[j] = Wm[j][(j + d) % n_in]
+        out.append(np.roll(v, (d // B) * B))
+    return out
+
+
+def fc_diag_rotations(n_in):
+    B, A = bsgs_split(n_in)
+    return sorted({-n_in} | set(range(1, B)) | ({B} if A > 1 else set()))
+
+
+def fc_diag(ev, x, n_in, n_out, diags):
+    """y = W x with x in slots [0, n_in) (zeros in [n_in, 2 n_in) and in the
+    top n_in slots): x~ = x + Rot_{-n_in}(x) makes slots [0, 2 n_in) periodic,
+    so Rot_d(x~)[j] = x[(j + d) mod n_in] and y = sum_d diag_d . Rot_d(x~)
+    (Halevi-Shoup).  Baby-step giant-step over d = a B + b: one hoisted group
+    of Rot_b(x~), inner sums I_a = sum_b Rot_b(x~) . diag'_{aB+b} (diag'
+    pre-rotated by -a B), acc = I_{A-1}; acc = Rot_B(acc) + I_a; one rescale.
+    1 + (B - 1) + (A - 1) key switches, one level; y lands in slots
+    [0, n_out), zeros elsewhere."""
+    assert n_in & (n_in - 1) == 0 and n_out <= n_in
+    B, A = bsgs_split(n_in)
+    xt = ev.add(x, ev.rot(x, -n_in))
+    baby = [xt] + (ev.rot_hoisted(xt, list(range(1, B))) if B > 1 else [])
+
+    def inner(a):
+        idx = range(a * B, min(n_in, a * B + B))
+        return mac(ev, [baby[d - a * B] for d in idx], [diags[d] for d in idx])
+
+    acc = inner(A - 1)
+    for a in range(A - 2, -1, -1):
+        acc = ev.add(ev.rot(acc, B), inner(a))
+    return ev.rescale(acc)
+
+
 # ===================================================================== polynomial activation
 def relu_poly4(ev, x, delta):
     """p(x) = c0 + c1 x + c2 x^2 + c4 x^4 (RELU4) in three levels:

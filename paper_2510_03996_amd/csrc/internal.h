@@ -103,6 +103,7 @@ struct Ctx {
   size_t lds_per_block = 65536;  // device limit on a workgroup's LDS (bytes)
   int chsum = HE_CHSUM_CHAIN;      // convolution input-channel sum (he_ctx_conv_channel_sum)
   int chain = HE_CHAIN_HORNER;     // masked rotation chains of the layers (he_ctx_mask_chains)
+  int fc = HE_FC_ROWS;             // fully connected form (he_ctx_fc_form)
   // NTT variant (log2 residues per thread) per batch-size bucket (<= 8, 16,
   // 32, more limbs), chosen by the autotuner at context creation
   int ntt_var[4] = {0, 0, 0, 2};           // NTT variant per batch-size bucket

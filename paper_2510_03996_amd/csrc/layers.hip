@@ -496,12 +496,29 @@ static he_ct pool_run(Ev& ev, const he_ct& x, const he_fmap& fm, int k, int S, c
   return z;
 }
 
-static int fc_plan_impl(int n_in, int n_out, he_layer_plan* pl) {
+static int fc_plan_impl(const Ctx* c, int n_in, int n_out, he_layer_plan* pl) {
   if (!pl || n_in < 1 || (n_in & (n_in - 1)) || n_out < 1)
     return set_error(HE_EINVAL, "n_in must be a power of two and n_out >= 1");
   *pl = he_layer_plan{};
   std::vector<int> keys;
   int ks = 0;
+  if (c->fc == HE_FC_DIAG) {
+    if (n_out > n_in) return set_error(HE_EINVAL, "the diagonal form needs n_out <= n_in");
+    int B, A;
+    bsgs_split(n_in, B, A);
+    add_keys(keys, -n_in);
+    for (int b = 1; b < B; b++) add_keys(keys, b);
+    if (A > 1) add_keys(keys, B);
+    ks = 1 + (B - 1) + (A - 1);
+    pl->n_kernel_pts = n_in;
+    pl->n_mask_pts = 0;
+    pl->levels = 1;
+    pl->key_switches = ks;
+    pl->out = he_fmap{n_out, 1, 1, 1, 1, 1};
+    pl->n_keys = (int)keys.size();
+    for (int i = 0; i < pl->n_keys && i < 64; i++) pl->rot_keys[i] = keys[i];
+    return HE_OK;
+  }
   for (int t = 1; t < n_in; t <<= 1) { add_keys(keys, t); ks += n_out; }
   if (n_out > 1) { add_keys(keys, -1); ks += n_out - 1; }
   pl->n_kernel_pts = n_out;
@@ -765,7 +782,14 @@ int he_avgpool(he_ctx* h, const he_ct* in, const he_fmap* in_map, int kernel, in
 
 int he_fc_plan(const he_ctx* h, int n_in, int n_out, he_layer_plan* plan) {
   if (!h) return set_error(HE_EINVAL, "null context");
-  return fc_plan_impl(n_in, n_out, plan);
+  return fc_plan_impl(&h->c, n_in, n_out, plan);
+}
+
+int he_ctx_fc_form(he_ctx* h, int mode) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  if (mode != HE_FC_ROWS && mode != HE_FC_DIAG) return set_error(HE_EINVAL, "unknown fully connected form");
+  h->c.fc = mode;
+  return HE_OK;
 }
 
 int he_fc(he_ctx* h, const he_ct* in, int n_in, int n_out, const he_pt* weight_pts, const he_pt* mask_pts,
@@ -775,18 +799,43 @@ int he_fc(he_ctx* h, const he_ct* in, int n_in, int n_out, const he_pt* weight_p
   he_layer_plan pl;
   int rc;
   if ((rc = check_ct(c, in, "in"))) return rc;
-  if ((rc = fc_plan_impl(n_in, n_out, &pl))) return rc;
+  if ((rc = fc_plan_impl(c, n_in, n_out, &pl))) return rc;
   if (n_in > c->n / 2 || n_out > c->n / 2) return set_error(HE_EINVAL, "vector longer than the slots");
-  if (in->level <= 2) return set_error(HE_ELEVEL, "not enough levels for the fully connected layer");
-  if ((rc = check_out(c, out, in->level - 2))) return rc;
-  if ((rc = check_pts(c, weight_pts, n_out, in->level, "weight_pts")) ||
-      (rc = check_pts(c, mask_pts, 1, in->level - 1, "mask_pts")))
+  if (in->level <= pl.levels) return set_error(HE_ELEVEL, "not enough levels for the fully connected layer");
+  if ((rc = check_out(c, out, in->level - pl.levels))) return rc;
+  if ((rc = check_pts(c, weight_pts, pl.n_kernel_pts, in->level, "weight_pts")) ||
+      (pl.n_mask_pts && (rc = check_pts(c, mask_pts, 1, in->level - 1, "mask_pts"))))
     return rc;
   for (int i = 0; i < pl.n_keys; i++)
     if (!key_known(c, pl.rot_keys[i]))
       return set_error(HE_ENOKEY, "rotation key " + std::to_string(pl.rot_keys[i]) + " not resident");
+  if (c->fc == HE_FC_DIAG && 2 * n_in > c->n / 2) return set_error(HE_EINVAL, "2 n_in exceeds the slots");
   return guarded([&] {
     Ev ev(h, s);
+    if (c->fc == HE_FC_DIAG) {
+      // x~ = x + Rot_{-n_in}(x); baby steps Rot_b(x~) hoisted; inner sums with
+      // the pre-rotated diagonals; Horner over the giant steps with key B
+      int B, A;
+      bsgs_split(n_in, B, A);
+      he_ct xt = ev.add_take(ev.rot(*in, -n_in), ev.copy(*in));
+      std::vector<int> offs;
+      for (int b = 1; b < B; b++) offs.push_back(b);
+      std::vector<he_ct> baby{xt};
+      if (!offs.empty())
+        for (const he_ct& r : ev.rot_hoisted(xt, offs)) baby.push_back(r);
+      auto inner = [&](int a) {
+        const int cnt = std::min(B, n_in - a * B);
+        std::vector<he_ct> cts(baby.begin(), baby.begin() + cnt);
+        return mac_all(ev, cts, weight_pts + a * B);
+      };
+      he_ct acc = inner(A - 1);
+      for (int a = A - 2; a >= 0; a--) acc = ev.add_take(ev.rot_take(acc, B), inner(a));
+      for (const he_ct& b : baby) ev.release(b);
+      acc = ev.rescale_take(acc);
+      if (bias_pt) ck(he_add_plain(h, &acc, bias_pt, &acc, s));
+      ev.copy_out(acc, out);
+      return HE_OK;
+    }
     auto neuron = [&](int k) {
       he_ct P = ev.rescale_take(ev.mul(*in, weight_pts[k]));
       for (int t = 1; t < n_in; t <<= 1) P = ev.add_take(P, ev.rot(P, t));

@@ -23,6 +23,7 @@ KEY_RELIN = 0x7FFFFFFF
 NTT_VARIANTS = 5
 CHSUM_CHAIN, CHSUM_LOG = 0, 1  # he_ctx_conv_channel_sum modes
 CHAIN_HORNER, CHAIN_BSGS = 0, 1  # he_ctx_mask_chains modes
+FC_ROWS, FC_DIAG = 0, 1  # he_ctx_fc_form modes
 MAX_Q, MAX_P = 60, 16
 
 
@@ -140,6 +141,7 @@ def lib():
             "he_ctx_ntt_select": [vp, P(i32)],
             "he_ctx_conv_channel_sum": [vp, i32],
             "he_ctx_mask_chains": [vp, i32],
+            "he_ctx_fc_form": [vp, i32],
             "he_key_host_register": [vp, i32, P(ctypes.c_uint64), sz],
             "he_key_cache_limit": [vp, sz],
             "he_key_prefetch": [vp, P(i32), c_int, vp],
@@ -492,6 +494,11 @@ class Context:
         """Masked rotation chains of later layer plans and calls: CHAIN_HORNER
         or CHAIN_BSGS (baby-step giant-step; masks pre-rotated by the caller)."""
         _check(lib().he_ctx_mask_chains(self.h, int(mode)))
+
+    def fc_form(self, mode):
+        """Form of later fc plans and calls: FC_ROWS (per neuron) or FC_DIAG
+        (diagonal, baby-step giant-step; weight_pts are the rotated diagonals)."""
+        _check(lib().he_ctx_fc_form(self.h, int(mode)))
 
     def ntt_variants(self):
         var = (ctypes.c_int32 * 4)()

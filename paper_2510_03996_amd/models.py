@@ -61,5 +61,6 @@ def resnet_chain(ctx, a_kern, a_mask, b_kern, b_mask, gap_mask, fc_rows, fc_mask
         lambda ct, s: ctx.avgpool(ct, fb, 0, 1, gap_mask, stream=s)[0],
         lambda ct, s: ctx.fc(ct, 64, 10, fc_rows, fc_mask, stream=s),
     ]
-    counts = [(pa.n_kernel_pts, pa.n_mask_pts), (pb.n_kernel_pts, pb.n_mask_pts), (0, pg.n_mask_pts), (10, 1)]
+    counts = [(pa.n_kernel_pts, pa.n_mask_pts), (pb.n_kernel_pts, pb.n_mask_pts), (0, pg.n_mask_pts),
+              (pf.n_kernel_pts, pf.n_mask_pts)]
     return Chain(ctx, stages, keys, counts, pa.levels + pb.levels + pg.levels + pf.levels)

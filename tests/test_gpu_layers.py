@@ -338,3 +338,49 @@ def test_chain_mode_errors(gctx):
     with pytest.raises(he.HEError) as e:
         g.mask_chains(2)
     assert e.value.name == "HE_EINVAL"
+
+
+@pytest.mark.parametrize("n_in,n_out,name", [(64, 10, "config2"), (32, 32, "config1"), (8, 3, "config0")])
+def test_fc_diag(gctx, n_in, n_out, name):
+    """Diagonal (baby-step giant-step) fully connected form (he_ctx_fc_form)."""
+    from paper_2510_03996_amd import he
+
+    g = gctx(name)
+    octx, sk, _ = H.oracle_ctx(name)
+    slots = octx.n // 2
+    x = synth.uniform_slots(78 + n_in, n_in)
+    Wm = synth.fc_weights(78 + n_out, n_out, n_in, (2.0 / n_in) ** 0.5)
+    g.fc_form(he.FC_DIAG)
+    try:
+        plan = g.fc_plan(n_in, n_out)
+        assert sorted(plan.keys()) == LY.fc_diag_rotations(n_in) and plan.n_mask_pts == 0
+        ev = setup_keys(g, name, plan.keys())
+        v = np.zeros(slots)
+        v[:n_in] = x
+        level = min(octx.pr.L, 16)
+        _, ct = H.encrypt_slots(name, 78, level=level, values=v)
+        dp = encode(octx, LY.fc_diag_plaintexts(Wm, slots), ct.level)
+        want = LY.fc_diag(ev, ct, n_in, n_out, dp)
+        got = g.fc(g.ct_from_numpy(ct.data, ct.scale), n_in, n_out, gpts(g, dp), [])
+        assert ev.ks == plan.key_switches and got.level == ct.level - 1
+        check_ct(got, want, "fc diag")
+        dec = octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale))
+        assert np.max(np.abs(dec[:n_out] - LY.fc_ref(x, Wm))) < 1e-3
+    finally:
+        g.fc_form(he.FC_ROWS)
+
+
+def test_fc_form_errors(gctx):
+    from paper_2510_03996_amd import he
+
+    g = gctx("config0")
+    with pytest.raises(he.HEError) as e:
+        g.fc_form(5)
+    assert e.value.name == "HE_EINVAL"
+    g.fc_form(he.FC_DIAG)
+    try:
+        with pytest.raises(he.HEError) as e:
+            g.fc_plan(8, 9)  # more outputs than inputs
+        assert e.value.name == "HE_EINVAL"
+    finally:
+        g.fc_form(he.FC_ROWS)

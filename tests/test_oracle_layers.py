@@ -422,3 +422,54 @@ def test_he_config1_stack_bsgs_decrypts_to_fp64():
     ref = LY.avgpool_ref(LY.relu4_ref(LY.conv2d_ref(X, K, 1, 0)), 2, 2)
     err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, z), f2) - ref))
     assert err < 1e-2, err
+
+
+# ---------------------------------------------------------------- diagonal fully connected layer
+@pytest.mark.parametrize("n_in,n_out", [(64, 10), (32, 32), (16, 1), (8, 5), (2, 2)])
+def test_sim_fc_diag(n_in, n_out):
+    """Halevi-Shoup diagonal form with baby-step giant-step: equals the FP64
+    matrix-vector product written out; 1 + (B-1) + (A-1) key switches, one
+    level, zeros outside the n_out outputs."""
+    slots = 4096
+    x = synth.uniform_slots(9 + n_in, n_in)
+    Wm = synth.fc_weights(9 + n_out, n_out, n_in, (2.0 / n_in) ** 0.5)
+    v = np.zeros(slots)
+    v[:n_in] = x
+    diags = LY.fc_diag_plaintexts(Wm, slots)
+    ev = sim(slots)
+    y = LY.fc_diag(ev, LY.SimCt(v, 5), n_in, n_out, diags)
+    B, A = LY.bsgs_split(n_in)
+    assert ev.ks == 1 + (B - 1) + (A - 1) and y.level == 4
+    want = np.array([sum(Wm[j][i] * x[i] for i in range(n_in)) for j in range(n_out)])
+    assert np.max(np.abs(y.v[:n_out] - want)) < 1e-12 and np.max(np.abs(y.v[n_out:])) < 1e-12
+    assert LY.fc_diag_rotations(n_in) == sorted({-n_in} | set(range(1, B)) | ({B} if A > 1 else set()))
+
+
+def test_sim_fc_diag_resnet_shape_key_switches():
+    """The ResNet-shaped FC 64 -> 10: 15 key switches and one level instead of 69 and two."""
+    slots = 32768
+    x = synth.uniform_slots(5, 64)
+    Wm = synth.fc_weights(5, 10, 64, (2.0 / 64) ** 0.5)
+    v = np.zeros(slots)
+    v[:64] = x
+    ev = sim(slots)
+    y = LY.fc_diag(ev, LY.SimCt(v, 10), 64, 10, LY.fc_diag_plaintexts(Wm, slots))
+    assert ev.ks == 15 and y.level == 9
+    assert np.max(np.abs(y.v[:10] - LY.fc_ref(x, Wm))) < 1e-12
+
+
+def test_he_config1_fc_diag_decrypts():
+    """Encrypted diagonal FC 64 -> 10 at N=2^14 decrypts to W x within 1e-3."""
+    name = "config1"
+    ctx1, _, _ = H.oracle_ctx(name)
+    slots = ctx1.n // 2
+    x = synth.uniform_slots(77, 64)
+    Wm = synth.fc_weights(77, 10, 64, (2.0 / 64) ** 0.5)
+    v = np.zeros(slots)
+    v[:64] = x
+    ev, ctx, sk, pk = he_eval(name, LY.fc_diag_rotations(64))
+    _, ct = H.encrypt_slots(name, 77, values=v)
+    y = LY.fc_diag(ev, ct, 64, 10, encode_all(ctx, LY.fc_diag_plaintexts(Wm, slots), ctx.pr.L))
+    assert ev.ks == 15 and y.level == ctx.pr.L - 1
+    err = np.max(np.abs(ctx.decrypt(sk, y)[:10] - LY.fc_ref(x, Wm)))
+    assert err < 1e-3, err

@@ -88,6 +88,9 @@ HE_HD uint64_t barrett_reduce(U128 x, uint64_t q, uint64_t mu, int k) {
 // below 2^53 in magnitude, hence exact in one FMA, and r = (hi - quot q) + lo
 // is exact too.  No conditional corrections are needed: callers keep |a| <= 8q
 // and re-centre with centre_f64 (|result| <= q/2 + 1) once per LDS round.
+// The same argument holds for a centred |w| <= 3q/4 with wq = fl(w fl(1/q))
+// (the NTT's factored twiddles): the estimate is then within
+// 1.125 |a| 2^-52 of a w / q.
 HE_HD double mul_f64_c(double a, double w, double wq, double q) {
   const double quot = rint(a * wq);
   const double hi = a * w;

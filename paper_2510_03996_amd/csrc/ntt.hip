@@ -7,16 +7,17 @@
 
 namespace he {
 
-// Rounds IDX..NR-1 of a pass, forward order (integer or FP64 arithmetic).
-template <class P, int IDX, class T, class TW, class Q>
+// Rounds IDX..NR-1 of a pass, forward order (integer or FP64 arithmetic;
+// the FP64 rounds of pass 2 build their twiddles from two table factors).
+template <class P, int IDX, bool FT = P::PASS_NO == 2, class T, class TW, class Q>
 __device__ __forceinline__ void rounds_fwd(T* lds, int tid, int wg, const TW* tw, const TW* twp, Q q, Q qinv) {
   if constexpr (IDX < P::NR) {
     if constexpr (IDX > 0) __syncthreads();
     if constexpr (std::is_same<T, double>::value)
-      P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
+      P::template round_f64<P::rbits(IDX), FT>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
     else
       P::template round<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
-    rounds_fwd<P, IDX + 1>(lds, tid, wg, tw, twp, q, qinv);
+    rounds_fwd<P, IDX + 1, FT>(lds, tid, wg, tw, twp, q, qinv);
   }
 }
 // Rounds IDX..0 of a pass, inverse order.
@@ -24,7 +25,7 @@ template <class P, int IDX, class T, class TW, class Q>
 __device__ __forceinline__ void rounds_inv(T* lds, int tid, int wg, const TW* tw, const TW* twp, Q q, Q qinv) {
   if constexpr (IDX >= 0) {
     if constexpr (std::is_same<T, double>::value)
-      P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
+      P::template round_f64<P::rbits(IDX), P::PASS_NO == 2>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
     else
       P::template round<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
     if constexpr (IDX > 0) {
@@ -93,11 +94,11 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
       dl[P::lidx(g, k)] = P::load_f64(ain[P::gidx(wg, g, k)]);
     }
     __syncthreads();
-    if (!INV) rounds_fwd<P, 0>(dl, tid, wg, dtw, dtwq, dq, dqinv);
+    if (!INV) rounds_fwd<P, 0, PASS == 2 && !EPI>(dl, tid, wg, dtw, dtwq, dq, dqinv);
     else rounds_inv<P, P::NR - 1>(dl, tid, wg, dtw, dtwq, dq, dqinv);
     __syncthreads();
     if constexpr (EPI) {
-      // fused ModDown epilogue in centred FP64: v (|v| < 4.2q) is the transform's
+      // fused ModDown epilogue in centred FP64: v (|v| < 4.25q) is the transform's
       // value before canonicalisation; |u - v| < 6q, the product is below 2q and
       // adding the canonical c0 term stays below 3q, so one canonicalisation ends it
       const size_t off = (size_t)pos << LOGN;
@@ -154,7 +155,7 @@ __device__ __forceinline__ void rounds_fwd_if(bool act, T* lds, int tid, int wg,
     if constexpr (IDX > 0) __syncthreads();
     if (act) {
       if constexpr (std::is_same<T, double>::value)
-        P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
+        P::template round_f64<P::rbits(IDX), P::PASS_NO == 2>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
       else
         P::template round<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
     }
@@ -180,7 +181,7 @@ __device__ __forceinline__ void rounds_inv_if(bool act, T* lds, int tid, int wg,
   if constexpr (IDX >= 0) {
     if (act) {
       if constexpr (std::is_same<T, double>::value)
-        P::template round_f64<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
+        P::template round_f64<P::rbits(IDX), P::PASS_NO == 2>(lds, tid, wg, P::rstart(IDX), tw, twp, q, qinv);
       else
         P::template round<P::rbits(IDX)>(lds, tid, wg, P::rstart(IDX), tw, twp, q);
     }
@@ -192,7 +193,7 @@ __device__ __forceinline__ void rounds_inv_if(bool act, T* lds, int tid, int wg,
 }
 
 template <int LOGN, int LOG_EPT, int LOG_TILE, int DN>
-__global__ __launch_bounds__(DN * 256) void ntt_ip_kernel(LimbMap map, const uint64_t* __restrict__ tw_all,
+__global__ __launch_bounds__((DN * NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>::THREADS)) void ntt_ip_kernel(LimbMap map, const uint64_t* __restrict__ tw_all,
                                                           const uint64_t* __restrict__ twp_all,
                                                           const double* __restrict__ dtw_all,
                                                           const double* __restrict__ dtwq_all,
@@ -203,6 +204,7 @@ __global__ __launch_bounds__(DN * 256) void ntt_ip_kernel(LimbMap map, const uin
                                                           const ModInfo* __restrict__ mods, NttIp ip) {
   using P = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
   using PI = NttPass<LOGN, 2, true, LOG_EPT, LOG_TILE>;
+  static_assert(P::THREADS % 64 == 0, "digit groups of whole waves");
   constexpr int NTHR = DN * P::THREADS;
   constexpr int IT = (P::TILE + NTHR - 1) / NTHR;  // outputs per thread
   extern __shared__ uint64_t lds_all[];  // [max(dnum, 2)][P::LDS_WORDS]
@@ -507,11 +509,11 @@ int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& ma
 // ModUp's forward transform with the key inner product fused into its last
 // pass: pass 1 over every converted limb (`conv`, ext-relative positions),
 // then ntt_ip_kernel over the E = level + K output limbs (`outs`).
-template <int LOGN, int LOG_EPT, int LOG_TILE>
+template <int LOGN, int LOG_EPT, int LOG_TILE, int LOG_EPT_IP, int LOG_TILE_IP>
 static int ntt_ip_launch_v(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
                            hipStream_t s) {
   using P1 = NttPass<LOGN, 1, false, LOG_EPT, LOG_TILE>;
-  using P2 = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
+  using P2 = NttPass<LOGN, 2, false, LOG_EPT_IP, LOG_TILE_IP>;
   const double N = (double)P1::N;
   double nf = 0, nconv_f = 0;
   if (c->prof_on) {
@@ -539,7 +541,7 @@ static int ntt_ip_launch_v(Ctx* c, uint64_t* ext, const LimbMap& conv, const Lim
     const size_t lds = (size_t)std::max(ip.dnum, 2) * P2::LDS_WORDS * 8;
     const dim3 blk(ip.dnum * P2::THREADS);
 #define HE_IP_LAUNCH(D)                                                                                           \
-  ntt_ip_kernel<LOGN, LOG_EPT, LOG_TILE, D><<<grid, blk, lds, s>>>(outs, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, \
+  ntt_ip_kernel<LOGN, LOG_EPT_IP, LOG_TILE_IP, D><<<grid, blk, lds, s>>>(outs, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, \
                                                                    c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq,   \
                                                                    c->d_mod, ip)
     switch (ip.dnum) {
@@ -554,8 +556,11 @@ static int ntt_ip_launch_v(Ctx* c, uint64_t* ext, const LimbMap& conv, const Lim
   return HE_OK;
 }
 
-// The fused kernel runs one 256-thread group per digit: tile 2048 with 8
-// residues per thread.
+// The fused kernel runs one group of P::THREADS threads per digit with 8
+// residues per thread, on output tiles of 2^IP_LOG_TILE positions: smaller
+// tiles than pass 1's (whose row segments need the width) give smaller
+// workgroups, more of them resident per CU and a shorter tail.
+constexpr int IP_LOG_EPT = 3, IP_LOG_TILE = 9;
 template <int LOGN>
 static int ntt_ip_launch_n(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
                            hipStream_t s) {
@@ -573,19 +578,15 @@ static int ntt_ip_launch_n(Ctx* c, uint64_t* ext, const LimbMap& conv, const Lim
         }
     om = r;
   }
-  return ntt_ip_launch_v<LOGN, 3, 11>(c, ext, by_modulus(c, conv), om, ip, s);
+  return ntt_ip_launch_v<LOGN, 3, 11, IP_LOG_EPT, IP_LOG_TILE>(c, ext, by_modulus(c, conv), om, ip, s);
 }
 
 bool ntt_ip_supported(const Ctx* c, int dnum) {
-  using P16 = NttPass<16, 2, false, 3, 11>;
-  static_assert(P16::THREADS == 256 && NttPass<14, 2, false, 3, 11>::THREADS == 256 &&
-                    NttPass<12, 2, false, 3, 11>::THREADS == 256,
-                "one 256-thread group per digit");
   size_t words = 0;
   switch (c->log_n) {
-    case 12: words = NttPass<12, 2, false, 3, 11>::LDS_WORDS; break;
-    case 14: words = NttPass<14, 2, false, 3, 11>::LDS_WORDS; break;
-    case 16: words = P16::LDS_WORDS; break;
+    case 12: words = NttPass<12, 2, false, IP_LOG_EPT, IP_LOG_TILE>::LDS_WORDS; break;
+    case 14: words = NttPass<14, 2, false, IP_LOG_EPT, IP_LOG_TILE>::LDS_WORDS; break;
+    case 16: words = NttPass<16, 2, false, IP_LOG_EPT, IP_LOG_TILE>::LDS_WORDS; break;
     default: return false;
   }
   return dnum >= 1 && dnum <= NTT_IP_MAXD && (size_t)std::max(dnum, 2) * words * 8 <= c->lds_per_block;

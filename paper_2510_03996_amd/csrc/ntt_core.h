@@ -27,6 +27,7 @@ namespace he {
 template <int LOGN, int PASS, bool INV, int LOG_EPT = 4, int LOG_TILE = 12>
 struct NttPass {
   static constexpr int N = 1 << LOGN;
+  static constexpr int PASS_NO = PASS;
   static constexpr int L1 = (LOGN + 1) / 2;
   static constexpr int L2 = LOGN - L1;
   static constexpr int N2 = 1 << L2;
@@ -122,12 +123,27 @@ struct NttPass {
   // FP64 round for q < 2^50: the same butterflies in centred arithmetic
   // (mul_f64_c, full-rate FP64 FMA instead of 32-bit integer multiplies).
   // Each round starts by re-centring its inputs to |x| <= q/2 + 1; over at
-  // most four stages the forward butterflies (a + y, a - y) stay below 4.2q
-  // and the inverse ones (a + b, (a - b) w) below 8q, so everything is exact.
-  template <int R>
+  // most four stages the forward butterflies (a + y, a - y) stay below 4.25q
+  // and the inverse ones (a + b, (a - b) w) below 8q + 16, so everything is
+  // exact.
+  //
+  // FACT (pass 2 only): the twiddle of chunk b, stage s, index i is built from
+  // two entries of the same table instead of being read from its own slot.
+  // The three parts of the table index 2^(L1+s) + b 2^s + i occupy disjoint
+  // bits, so its bit reversal (the exponent of psi) is the sum of those of
+  // 2^(L1+s) + i and b 2^s:  Psi[2^(L1+s) + b 2^s + i] =
+  // Psi[2^(L1+s) + i] Psi[b 2^s] mod q.  The first factor lies in the 2^L2
+  // entries shared by every chunk, the second is one entry per chunk and
+  // stage, so a pass reads a few KiB of table per modulus instead of N
+  // entries.  The product w = mul_f64_c(., .) has |w| <= 3q/4 and
+  // wq = fl(w fl(1/q)) is within 2^-52 (relatively) of w / q; the quotient
+  // estimate of a product by w is then off by at most 1.125 |a| 2^-52, which
+  // is what the bounds above allow for.
+  template <int R, bool FACT = false>
   HE_HD static void round_f64(double* lds, int tid, int wg, int s0, const double* tw, const double* twq, double q,
                               double qinv) {
     static_assert(R <= 4, "the centred bounds assume at most four stages per round");
+    static_assert(!FACT || PASS == 2, "factored twiddles are for pass 2");
     constexpr int GPS = M >> R;
     constexpr int TOTAL = G * GPS;
     const int dmin = M >> (s0 + R);
@@ -152,8 +168,9 @@ struct NttPass {
           for (int u = 0; u < (1 << R); u++) {
             if (u & half) continue;
             const int iloc = (hi << ss) + (u >> (R - ss));
-            const int ti = (1 << sg) + (sub_off << s) + iloc;
-            const double y = mul_f64_c(x[u + half], tw[ti], twq[ti], q);
+            double w, wq;
+            twiddle_f64<FACT>(tw, twq, sg, s, sub_off, iloc, q, qinv, w, wq);
+            const double y = mul_f64_c(x[u + half], w, wq, q);
             const double a = x[u];
             x[u] = a + y;
             x[u + half] = a - y;
@@ -169,15 +186,32 @@ struct NttPass {
           for (int u = 0; u < (1 << R); u++) {
             if (u & half) continue;
             const int iloc = (hi << ss) + (u >> (R - ss));
-            const int ti = (1 << sg) + (sub_off << s) + iloc;
+            double w, wq;
+            twiddle_f64<FACT>(tw, twq, sg, s, sub_off, iloc, q, qinv, w, wq);
             const double a = x[u], b = x[u + half];
             x[u] = a + b;
-            x[u + half] = mul_f64_c(a - b, tw[ti], twq[ti], q);
+            x[u + half] = mul_f64_c(a - b, w, wq, q);
           }
         }
       }
 #pragma unroll
       for (int u = 0; u < (1 << R); u++) lds[lidx(g, base + u * dmin)] = x[u];
+    }
+  }
+
+  // twiddle of global stage sg (local stage s), sub-transform sub_off, index
+  // iloc: the table entry, or (FACT) the product of its two factors
+  template <bool FACT>
+  HE_HD static void twiddle_f64(const double* tw, const double* twq, int sg, int s, int sub_off, int iloc, double q,
+                                double qinv, double& w, double& wq) {
+    if constexpr (FACT) {
+      const int fi = sub_off << s;
+      w = mul_f64_c(tw[(1 << sg) + iloc], tw[fi], twq[fi], q);
+      wq = w * qinv;
+    } else {
+      const int ti = (1 << sg) + (sub_off << s) + iloc;
+      w = tw[ti];
+      wq = twq[ti];
     }
   }
 

@@ -131,7 +131,8 @@ static int build_bconv(Ctx* c, BConvDesc& t, const std::vector<int>& in_pos, con
   t.nsteps = (t.nin + 1) / 2;
   t.ngroups = (t.nout + 3) / 4;
   std::vector<uint64_t> pre(2 * t.nin);
-  // cst[i][p] = (Qin / q_i) 2^64 mod p (Montgomery form)
+  // cst[i][p] = (Qin / q_i) 2^64 mod p (Montgomery form), or (Qin / q_i) mod p
+  // for outputs that take the FP64 epilogue
   std::vector<uint64_t> cst((size_t)t.nin * t.nout);
   for (int i = 0; i < t.nin; i++) {
     uint64_t qi = c->mod[in_mod[i]];
@@ -145,7 +146,8 @@ static int build_bconv(Ctx* c, BConvDesc& t, const std::vector<int>& in_pos, con
       uint64_t v = 1 % po;
       for (int i2 = 0; i2 < t.nin; i2++)
         if (i2 != i) v = hmul(v, c->mod[in_mod[i2]] % po, po);
-      cst[(size_t)i * t.nout + p] = hmul(v, (uint64_t)(((u128)1 << 64) % po), po);
+      cst[(size_t)i * t.nout + p] =
+          bconv_out_f64(c->hmod[out_mod[p]].k) ? v : hmul(v, (uint64_t)(((u128)1 << 64) % po), po);
     }
   }
   // A fragments: lane l of K-step s in row tile g holds, for row r = l % 32
@@ -167,16 +169,10 @@ static int build_bconv(Ctx* c, BConvDesc& t, const std::vector<int>& in_pos, con
         }
         frag[((size_t)g * t.nsteps + st) * 64 + l] = word;
       }
-  std::vector<uint64_t> ep((size_t)t.nout * 4);
+  std::vector<uint64_t> ep((size_t)t.nout * BCONV_EPW);
   for (int p = 0; p < t.nout; p++) {
-    const uint64_t po = c->mod[out_mod[p]];
-    int kshift = 0;
-    while (((u128)po << kshift) < ((u128)1 << 77)) kshift++;
-    const u128 M = (u128)po << kshift;
-    ep[4 * p] = (uint64_t)M;
-    ep[4 * p + 1] = (uint64_t)(M >> 64);
-    ep[4 * p + 2] = po;
-    ep[4 * p + 3] = c->hmod[out_mod[p]].qinv;
+    const ModInfo& mo = c->hmod[out_mod[p]];
+    bconv_ep_fill(mo.q, mo.k, mo.qinv, &ep[(size_t)BCONV_EPW * p]);
   }
   uint64_t *dpre = nullptr, *dfrag = nullptr, *dep = nullptr;
   int rc;

@@ -9,6 +9,7 @@ constexpr int MAX_BCONV_IN = 10;   // input limbs of one conversion (alpha and K
 constexpr int MAX_BCONV_OUT = 64;
 constexpr int MAXJ = 128;          // limb jobs in one batched launch
 constexpr int MAX_DIGITS = 8;      // key-switching digits (dnum)
+constexpr int BCONV_EPW = 5;       // epilogue words per basis-conversion output
 
 // Which limbs of a [limbs][N] array a kernel touches and their moduli.
 struct LimbMap {
@@ -28,11 +29,16 @@ struct LimbMap {
 // int32); one Montgomery reduction of the digit-weighted sum gives y_p.
 // One 32x32x16 MFMA covers two input limbs (K = 2 x 8 digits) for 32
 // coefficients (columns) and four outputs x 8 digits b (rows).
+// Outputs modulo a prime below 2^50 instead use C_{i,a,p} = [Qin/q_i]_p
+// 256^a mod p (no Montgomery factor) and an FP64 epilogue (bconv_combine_f64),
+// which needs no 64-bit integer multiplies.
 //   tab:  [nin] w, [nin] w'   Shoup pair of (Qin/q_i)^{-1} mod q_i
 //   frag: [ngroups][nsteps][64] A-operand fragments (8 signed digit bytes per
 //         lane, laid out as the instruction reads them)
-//   ep:   [nout][4] per output modulus: the 128-bit offset M = p 2^k in
-//         [2^77, 2^78) (low word, high word), p, p^{-1} mod 2^64
+//   ep:   [nout][BCONV_EPW] per output modulus (bconv_ep_fill): Montgomery
+//         outputs hold the 128-bit offset M = p 2^k in [2^77, 2^78) (low
+//         word, high word), p, p^{-1} mod 2^64, 0; FP64 outputs hold the
+//         doubles 2^32 mod p, fl((2^32 mod p) / p), p, fl(1/p) (as bits), 1
 struct BConvDesc {
   int32_t nin, nout;
   int32_t nsteps, ngroups;  // ceil(nin / 2) K-steps, ceil(nout / 4) row tiles
@@ -72,6 +78,51 @@ HE_HD uint64_t bconv_combine(const int32_t* acc, const uint64_t* ep) {
   const int64_t hi = (int64_t)acc[4] + (int64_t)acc[5] * 256 + (int64_t)acc[6] * 65536 + (int64_t)acc[7] * 16777216;
   const __int128 t = (__int128)hi * ((__int128)1 << 32) + lo + (__int128)(((unsigned __int128)ep[1] << 64) | ep[0]);
   return mont_redc(U128{(uint64_t)t, (uint64_t)((unsigned __int128)t >> 64)}, ep[2], ep[3]);
+}
+
+// Outputs modulo primes of at most 50 bits take the FP64 epilogue.
+HE_HD bool bconv_out_f64(int kbits) { return kbits <= 50; }
+
+// FP64 epilogue: V = sum_b 256^b acc[b] = lo + 2^32 hi with
+// lo = sum_{b<4} 256^b acc[b] and hi = sum_{b>=4} 256^(b-4) acc[b].  Pairs
+// acc[2c] + 256 acc[2c+1] stay below 2^28.34 (int32), lo and hi below
+// 2^44.35, so both are exact doubles.  hi (2^32 mod p) is reduced with the
+// centred product (|hi| 2^-52 < 2^-7.6, so the result is below 0.51 p in
+// magnitude and exact), lo is added (an integer below 2^53) and one floor
+// estimate with fl(1/p) plus a correction either way leaves V mod p.
+HE_HD uint64_t bconv_combine_f64(const int32_t* acc, const uint64_t* ep) {
+  const int32_t p0 = acc[0] + acc[1] * 256, p1 = acc[2] + acc[3] * 256;
+  const int32_t p2 = acc[4] + acc[5] * 256, p3 = acc[6] + acc[7] * 256;
+  const double lo = fma((double)p1, 65536.0, (double)p0);
+  const double hi = fma((double)p3, 65536.0, (double)p2);
+  const double p = bits_to_f64(ep[2]);
+  const double v = mul_f64_c(hi, bits_to_f64(ep[0]), bits_to_f64(ep[1]), p) + lo;
+  return f64_to_u52(canon_f64(v, bits_to_f64(ep[3]), p));
+}
+
+HE_HD uint64_t bconv_out(const int32_t* acc, const uint64_t* ep) {
+  return ep[4] ? bconv_combine_f64(acc, ep) : bconv_combine(acc, ep);
+}
+
+// (host) Epilogue record of one output modulus po (kbits bits, pinv64 = po^{-1} mod 2^64).
+inline void bconv_ep_fill(uint64_t po, int kbits, uint64_t pinv64, uint64_t* ep) {
+  if (bconv_out_f64(kbits)) {
+    const uint64_t c32 = (uint64_t)(((unsigned __int128)1 << 32) % po);
+    ep[0] = f64_to_bits((double)c32);
+    ep[1] = f64_to_bits((double)c32 / (double)po);
+    ep[2] = f64_to_bits((double)po);
+    ep[3] = f64_to_bits(1.0 / (double)po);
+    ep[4] = 1;
+    return;
+  }
+  int kshift = 0;
+  while (((unsigned __int128)po << kshift) < ((unsigned __int128)1 << 77)) kshift++;
+  const unsigned __int128 M = (unsigned __int128)po << kshift;
+  ep[0] = (uint64_t)M;
+  ep[1] = (uint64_t)(M >> 64);
+  ep[2] = po;
+  ep[3] = pinv64;
+  ep[4] = 0;
 }
 
 HE_HD uint32_t bitrev_n(uint32_t x, int logn) {

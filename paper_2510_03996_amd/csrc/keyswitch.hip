@@ -25,7 +25,7 @@ __global__ __launch_bounds__(256) void k_bconv(const uint64_t* __restrict__ in, 
                                                const ModInfo* __restrict__ mods, int logn) {
   // constants of this block's row tiles, staged once per workgroup
   __shared__ uint64_t s_frag[BCONV_TILES_Y * (MAX_BCONV_IN / 2) * 64];
-  __shared__ uint64_t s_ep[BCONV_TILES_Y * 4 * 4];
+  __shared__ uint64_t s_ep[BCONV_TILES_Y * 4 * BCONV_EPW];
   __shared__ uint32_t s_pos[BCONV_TILES_Y * 4];
   const size_t n = (size_t)1 << logn;
   const int lane = threadIdx.x & 63;
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(256) void k_bconv(const uint64_t* __restrict__ in, 
     const int nf = (g1 - g0) * nsteps * 64;
     for (int e = threadIdx.x; e < nf; e += 256) s_frag[e] = fr[e];
     const int p0 = 4 * g0, np = min(4 * g1, d.nout) - p0;
-    for (int e = threadIdx.x; e < 4 * np; e += 256) s_ep[e] = d.ep[4 * p0 + e];
+    for (int e = threadIdx.x; e < BCONV_EPW * np; e += 256) s_ep[e] = d.ep[BCONV_EPW * p0 + e];
     for (int e = threadIdx.x; e < np; e += 256) s_pos[e] = (uint32_t)d.out_pos[p0 + e];
   }
   long bf[MAX_BCONV_IN / 2];
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(256) void k_bconv(const uint64_t* __restrict__ in, 
         int32_t a8[8];
 #pragma unroll
         for (int b = 0; b < 8; b++) a8[b] = acc[8 * mm + b];
-        dst[(size_t)s_pos[p] * n + k] = bconv_combine(a8, s_ep + 4 * p);
+        dst[(size_t)s_pos[p] * n + k] = bconv_out(a8, s_ep + BCONV_EPW * p);
       }
     }
   }

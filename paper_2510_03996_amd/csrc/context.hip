@@ -279,6 +279,9 @@ static int ctx_init(Ctx* c, const he_params* p) {
     mi.dninv = (double)mi.ninv;
     mi.dninvq = (double)mi.ninv / (double)q;
     mi.dqinv = 1.0 / (double)q;
+    const uint64_t rinv = hinv(r64, q);  // 2^-64 mod q
+    mi.drinv = (double)rinv;
+    mi.drinvq = (double)rinv / (double)q;
     mi.dpad = 0.0;
   }
   int rc;

@@ -129,6 +129,7 @@ struct ModInfo {
   int32_t pad;
   double dninv, dninvq;  // N^{-1} and N^{-1}/q as doubles (FP64 NTT path, q < 2^50)
   double dqinv;          // 1/q as a double (FP64 NTT path)
+  double drinv, drinvq;  // 2^-64 mod q and fl(that / q) (FP64 key inner product)
   double dpad;
 };
 

@@ -205,6 +205,7 @@ __global__ __launch_bounds__((DN * NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>::T
   using P = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
   using PI = NttPass<LOGN, 2, true, LOG_EPT, LOG_TILE>;
   static_assert(P::THREADS % 64 == 0, "digit groups of whole waves");
+  static_assert(LOG_EPT <= 3 && DN <= 4, "the FP64 inner-product bounds assume three-stage rounds, four digits");
   constexpr int NTHR = DN * P::THREADS;
   constexpr int IT = (P::TILE + NTHR - 1) / NTHR;  // outputs per thread
   extern __shared__ uint64_t lds_all[];  // [max(dnum, 2)][P::LDS_WORDS]
@@ -263,16 +264,35 @@ __global__ __launch_bounds__((DN * NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>::T
       k0[j] = key[j * ip.key_ds + e];
       k1[j] = key[j * ip.key_ds + ip.key_ps + e];
     }
-    U128 a0{0, 0}, a1{0, 0};
+    if (f64) {
+      // centred FP64: the digits' values (|v| < 2.9q after rounds of at most
+      // three stages, or canonical for the own digit) times the Montgomery-form
+      // key words (< q, exact as doubles; quotient estimates fl(k fl(1/q)),
+      // off by at most 1.5 |v| 2^-52 < 1.09) are below 1.6q each, the sum over
+      // at most four digits below 6.4q; one more product by 2^-64 mod q
+      // removes the Montgomery factor and leaves |x| < 2.9q for canon_f64
+      const double dq = (double)q, qi = mi.dqinv;
+      double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-    for (int j = 0; j < DN; j++) {
-      const uint64_t w = lds_all[j * P::LDS_WORDS + li];
-      const uint64_t v = f64 ? f64_to_u52(canon_f64(bits_to_f64(w), mi.dqinv, (double)q)) : P::finish(w, 0, 0, q);
-      add_wide(a0, mul_wide(v, k0[j]));
-      add_wide(a1, mul_wide(v, k1[j]));
+      for (int j = 0; j < DN; j++) {
+        const double v = bits_to_f64(lds_all[j * P::LDS_WORDS + li]);
+        const double w0 = u52_to_f64(k0[j]), w1 = u52_to_f64(k1[j]);
+        a0 += mul_f64_c(v, w0, w0 * qi, dq);
+        a1 += mul_f64_c(v, w1, w1 * qi, dq);
+      }
+      r0[it] = f64_to_u52(canon_f64(mul_f64_c(a0, mi.drinv, mi.drinvq, dq), qi, dq));
+      r1[it] = f64_to_u52(canon_f64(mul_f64_c(a1, mi.drinv, mi.drinvq, dq), qi, dq));
+    } else {
+      U128 a0{0, 0}, a1{0, 0};
+#pragma unroll
+      for (int j = 0; j < DN; j++) {
+        const uint64_t v = P::finish(lds_all[j * P::LDS_WORDS + li], 0, 0, q);
+        add_wide(a0, mul_wide(v, k0[j]));
+        add_wide(a1, mul_wide(v, k1[j]));
+      }
+      r0[it] = mont_redc(a0, q, mi.qinv);
+      r1[it] = mont_redc(a1, q, mi.qinv);
     }
-    r0[it] = mont_redc(a0, q, mi.qinv);
-    r1[it] = mont_redc(a1, q, mi.qinv);
     if (!pinv2) {
       u[e] = r0[it];
       u[ip.u_ps + e] = r1[it];

@@ -138,7 +138,8 @@ size_t he_lane_bytes(const he_ctx* ctx, int n_ct_buffers);
  * ([dnum][2][L+K][N], host or device memory per src_on_device); the library
  * copies it into its own storage (converted to an internal form).
  * key_id: a rotation amount r (slot i <- slot i + r; ids are reduced mod N/2)
- * or HE_KEY_RELIN. */
+ * or HE_KEY_RELIN.  Uploading over a key that has a device copy first waits
+ * for the whole device (work on any stream may still read the old key). */
 int he_key_upload(he_ctx* ctx, int32_t key_id, const uint64_t* src, size_t bytes, int src_on_device,
                   he_stream stream);
 int he_key_evict(he_ctx* ctx, int32_t key_id);
@@ -153,7 +154,8 @@ size_t he_key_bytes(const he_ctx* ctx); /* bytes of one key */
  * load has finished waits for it.  With a device budget (he_key_cache_limit,
  * bytes; 0 = unlimited) a load first evicts the least recently used
  * host-backed keys that no batch holds; an evicted buffer is reused only
- * after the last kernel reading it has completed (the host waits for that).
+ * after the last kernel reading it on every stream that used it has
+ * completed (the host waits for that).
  * Keys uploaded with he_key_upload (no host copy) are never evicted; keys a
  * batch captured stay resident until he_batch_destroy.  The budget is soft
  * when nothing is evictable.  he_key_prefetch loads keys ahead of use on the

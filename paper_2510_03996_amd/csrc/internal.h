@@ -50,7 +50,9 @@ constexpr double PEAK_INT8_OPS = 5.0e15;                      // dense int8 MFMA
 struct KeyEntry {
   uint64_t* dev = nullptr;         // device copy, Montgomery form
   uint64_t* host = nullptr;        // pinned host copy, plain form (library-owned)
-  hipEvent_t used = nullptr;       // recorded after the last kernel that read dev
+  // per stream: recorded after the last kernel on that stream that read dev
+  // (host-backed keys only: they are the ones that can be evicted)
+  std::vector<std::pair<hipStream_t, hipEvent_t>> uses;
   hipEvent_t ready = nullptr;      // recorded after the last load into dev
   hipStream_t ready_stream = nullptr;
   uint64_t tick = 0;               // LRU clock of the last acquire

@@ -6,9 +6,11 @@
 // the stream of the operation that needs the key, followed by a `ready`
 // event; another stream that uses the key before that event has completed
 // waits for it.  Every kernel that reads a host-backed key is followed by a
-// `used` event, and an evicted key's buffer is handed to the next load only
-// after that event has completed, so no in-flight kernel ever reads a buffer
-// that is being overwritten.
+// `used` event of its stream (one per stream that read the key), and an
+// evicted key's buffer is handed to the next load only after all of them
+// have completed, so no in-flight kernel on any stream ever reads a buffer
+// that is being overwritten.  Replacing a key that has a device copy waits
+// for the whole device.
 #include <cstring>
 
 #include "internal.h"
@@ -23,8 +25,15 @@ static size_t resident_bytes(const Ctx* c) {
   return n;
 }
 
+static void destroy_events(KeyEntry& e) {
+  for (auto& u : e.uses) hipEventDestroy(u.second);
+  e.uses.clear();
+  if (e.ready) hipEventDestroy(e.ready);
+  e.ready = nullptr;
+}
+
 static void wait_and_free(Ctx* c, KeyEntry& e) {
-  if (e.used) hipEventSynchronize(e.used);
+  for (auto& u : e.uses) hipEventSynchronize(u.second);
   if (e.ready) hipEventSynchronize(e.ready);
   c->key_free.push_back(e.dev);
   e.dev = nullptr;
@@ -106,8 +115,15 @@ void key_note_use(Ctx* c, int32_t id, hipStream_t s) {
   auto it = c->keys.find(norm_key_id(c, id));
   if (it == c->keys.end() || !it->second.host) return;  // resident-only keys are never evicted
   KeyEntry& e = it->second;
-  if (!e.used && hipEventCreateWithFlags(&e.used, hipEventDisableTiming) != hipSuccess) return;
-  hipEventRecord(e.used, s);
+  for (auto& u : e.uses)
+    if (u.first == s) {
+      hipEventRecord(u.second, s);
+      return;
+    }
+  hipEvent_t ev = nullptr;
+  if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return;
+  hipEventRecord(ev, s);
+  e.uses.emplace_back(s, ev);
 }
 
 int key_lock(Ctx* c, int32_t id, int delta) {
@@ -122,8 +138,7 @@ void keys_free_all(Ctx* c) {
     KeyEntry& e = kv.second;
     if (e.dev) hipFree(e.dev);
     if (e.host) hipHostFree(e.host);
-    if (e.used) hipEventDestroy(e.used);
-    if (e.ready) hipEventDestroy(e.ready);
+    destroy_events(e);
   }
   c->keys.clear();
   for (uint64_t* p : c->key_free) hipFree(p);
@@ -152,8 +167,8 @@ int he_key_upload(he_ctx* h, int32_t key_id, const uint64_t* src, size_t bytes, 
       return HE_ENOMEM;
     }
   } else {
-    // the old contents may still be read by enqueued work
-    if (e.used) HE_HIP(hipEventSynchronize(e.used));
+    // the old contents may still be read by work enqueued on any stream
+    HE_HIP(hipDeviceSynchronize());
   }
   int rc = key_fill(c, e, src, src_on_device != 0, s);
   if (rc) return rc;
@@ -224,8 +239,7 @@ int he_key_evict(he_ctx* h, int32_t key_id) {
   HE_HIP(hipDeviceSynchronize());
   if (e.dev) hipFree(e.dev);
   if (e.host) hipHostFree(e.host);
-  if (e.used) hipEventDestroy(e.used);
-  if (e.ready) hipEventDestroy(e.ready);
+  destroy_events(e);
   c->keys.erase(it);
   return HE_OK;
 }

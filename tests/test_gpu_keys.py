@@ -129,6 +129,55 @@ def test_prefetch_on_another_stream():
         g.close()
 
 
+def _keep_busy(stream):
+    """Enqueue several milliseconds of bounded work on `stream`."""
+    with torch.cuda.stream(stream):
+        if hasattr(torch.cuda, "_sleep"):
+            torch.cuda._sleep(20_000_000)
+        else:
+            x = torch.ones(64 << 20, device="cuda")
+            for _ in range(20):
+                x.mul_(1.0)
+
+
+def test_eviction_waits_for_every_stream():
+    """With a one-key budget, a key still read by work queued on stream a must
+    not be evicted (its buffer reloaded) because stream b's use of it is done."""
+    octx, _, _ = H.oracle_ctx(NAME)
+    g = fresh()
+    try:
+        k1, k2 = 3, -9
+        for r in (k1, k2):
+            g.key_host_register(r, H.oracle_key(NAME, r))
+        g.key_cache_limit(g.key_bytes())
+        _, ct = H.encrypt_slots(NAME, 84)
+        gct = g.ct_from_numpy(ct.data, ct.scale)
+        want1 = octx.rotate(ct, k1, {k1: H.oracle_key(NAME, k1)}).data
+        want2 = octx.rotate(ct, k2, {k2: H.oracle_key(NAME, k2)}).data
+        a, b = torch.cuda.Stream(), torch.cuda.Stream()
+        outs_a = [g.new_ct(ct.level) for _ in range(8)]
+        out_b1, out_b2 = g.new_ct(ct.level), g.new_ct(ct.level)
+        g.lane_reserve(a, 1)  # no allocation once the busy work is queued
+        g.lane_reserve(b, 1)
+        g.key_prefetch([k1])
+        torch.cuda.synchronize()
+        _keep_busy(a)
+        for o in outs_a:  # queued behind the busy work: they read k1 later
+            g.rotate(gct, k1, out=o, stream=a)
+        g.rotate(gct, k1, out=out_b1, stream=b)  # runs at once
+        b.synchronize()
+        g.rotate(gct, k2, out=out_b2, stream=b)  # evicts k1: must wait for stream a's reads
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs_a):
+            H.assert_limbs_equal(o.numpy(), want1, "rotation %d queued on the other stream" % i)
+        H.assert_limbs_equal(out_b1.numpy(), want1, "rotation on stream b")
+        H.assert_limbs_equal(out_b2.numpy(), want2, "rotation with the reloaded buffer")
+        assert g.key_cache_stats()["evictions"] >= 1
+    finally:
+        torch.cuda.synchronize()
+        g.close()
+
+
 def test_key_cache_errors():
     from paper_2510_03996_amd import he
 

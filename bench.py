@@ -12,7 +12,8 @@ Measured in the same run and reported beside it:
   * roofline of the dominant kernel, from HIP events around every launch;
   * layer latencies: the tiny conv (N=2^12), the LeNet-5-shaped stack
     (N=2^14), and the ResNet-20-shaped conv A / conv B / global pooling / FC
-    (N=2^16);
+    (N=2^16); convolutions at the library default of two layer streams, the
+    ResNet-shaped ones also on one and four (`*_streams<n>_ms`);
   * batched key switching: 64 ciphertexts with seeded hoisted rotation sets
     of 9-49 indices from a 7x7-window key pool and 1-32 outputs each,
     batched + graph-captured vs the per-op path, same GPU;
@@ -36,6 +37,8 @@ sys.path.insert(0, ROOT)
 CFG0 = dict(log_n=12, q_bits=[54, 40, 40], p_bits=[55], alpha=1)
 CFG1 = dict(log_n=14, q_bits=[60] + [45] * 7, p_bits=[60, 60], alpha=2)
 CFG2 = dict(log_n=16, q_bits=[60] + [50] * 23, p_bits=[50] * 9, alpha=8)
+# layer-stream counts timed besides the library default (2) for the ResNet-shaped convolutions
+LAYER_STREAMS = (1, 4)
 ROTATIONS = [1, -1, 32]
 ROT_PER_STEP = 48
 HBM_PEAK_GBS = 8000.0
@@ -276,6 +279,13 @@ def layer_latencies(reps=3):
     ct = synthetic_ct(c2, 24, 31, sc)
     ak, am = synthetic_pts(c2, pa.n_kernel_pts, 24, 32, sc), synthetic_pts(c2, pa.n_mask_pts, 24, 33, sc)
     out["resnet_convA_16x32x32_n16_ms"] = round(timed(lambda: c2.conv2d(ct, fm0, 16, 3, 1, 1, ak, am, stream=s), reps, s) * 1e3, 3)
+    # the library default spreads output channels over the caller's stream and
+    # one helper stream; the same layer on one stream and on four (same results)
+    for n in LAYER_STREAMS:
+        c2.layer_streams(n)
+        out["resnet_convA_16x32x32_n16_streams%d_ms" % n] = round(
+            timed(lambda: c2.conv2d(ct, fm0, 16, 3, 1, 1, ak, am, stream=s), reps, s) * 1e3, 3)
+    c2.layer_streams(2)
     # the same layers with the log-step input-channel sum (keys W^2, 2 W^2, 4 W^2, 8 W^2)
     c2.conv_channel_sum(he.CHSUM_LOG)
     pal = c2.conv2d_plan(fm0, 16, 3, 1, 1)
@@ -288,6 +298,11 @@ def layer_latencies(reps=3):
     ctb = synthetic_ct(c2, 22, 34, sc)
     bk, bm = synthetic_pts(c2, pb.n_kernel_pts, 22, 35, sc), synthetic_pts(c2, pb.n_mask_pts, 22, 36, sc)
     out["resnet_convB_s2_n16_ms"] = round(timed(lambda: c2.conv2d(ctb, pa.out, 32, 3, 2, 1, bk, bm, stream=s), reps, s) * 1e3, 3)
+    for n in LAYER_STREAMS:
+        c2.layer_streams(n)
+        out["resnet_convB_s2_n16_streams%d_ms" % n] = round(
+            timed(lambda: c2.conv2d(ctb, pa.out, 32, 3, 2, 1, bk, bm, stream=s), reps, s) * 1e3, 3)
+    c2.layer_streams(2)
     c2.conv_channel_sum(he.CHSUM_LOG)
     out["resnet_convB_s2_n16_logsum_ms"] = round(
         timed(lambda: c2.conv2d(ctb, pa.out, 32, 3, 2, 1, bk, bm, stream=s), reps, s) * 1e3, 3)
@@ -416,8 +431,11 @@ def synthetic_serving_models(seed=1):
         synthetic_pts(c2, pg.n_mask_pts, 17, seed * 100 + 9, sc),
         synthetic_pts(c2, pf.n_kernel_pts, 16, seed * 100 + 10, sc), synthetic_pts(c2, pf.n_mask_pts, 16, seed * 100 + 11, sc))
     nbuf = 24
-    ms = {"lenet": serve.Model("lenet", c1, lenet.stages, nbuf, c1.lane_bytes(nbuf) + 4 * 2 * 8 * c1.n * 8),
-          "resnet": serve.Model("resnet", c2, resnet.stages, nbuf, c2.lane_bytes(nbuf) + 4 * 2 * 24 * c2.n * 8)}
+    # footprint: the request's lane, its convolutions' helper lane, in/out ciphertexts
+    ms = {"lenet": serve.Model("lenet", c1, lenet.stages, nbuf,
+                               c1.lane_bytes(nbuf) + c1.lane_bytes(4) + 4 * 2 * 8 * c1.n * 8),
+          "resnet": serve.Model("resnet", c2, resnet.stages, nbuf,
+                                c2.lane_bytes(nbuf) + c2.lane_bytes(4) + 4 * 2 * 24 * c2.n * 8)}
     ms["resnet"].key_ids, ms["resnet"].key_seed = list(k2), seed * 100 + 4  # the seed regenerates them
 
     def make_input(kind, sd):

@@ -414,6 +414,35 @@ static void lane_free(Ctx* c, hipStream_t s, Lane* ln) {
   delete ln;
 }
 
+int aux_streams_for(Ctx* c, hipStream_t s, int n, hipStream_t* out) {
+  std::lock_guard<std::mutex> lk(c->lanes_mu);
+  std::vector<hipStream_t>& v = c->aux_streams[s];
+  while ((int)v.size() < n) {
+    hipStream_t a = nullptr;
+    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess)
+      return set_error(HE_EHIP, "helper stream creation failed");
+    v.push_back(a);
+  }
+  for (int i = 0; i < n; i++) out[i] = v[i];
+  return HE_OK;
+}
+
+// destroy the helper streams of caller stream s and their lanes (lanes_mu held)
+static void aux_free(Ctx* c, hipStream_t s) {
+  auto it = c->aux_streams.find(s);
+  if (it == c->aux_streams.end()) return;
+  for (hipStream_t a : it->second) {
+    hipStreamSynchronize(a);
+    auto ln = c->lanes.find(a);
+    if (ln != c->lanes.end()) {
+      lane_free(c, ln->first, ln->second);
+      c->lanes.erase(ln);
+    }
+    hipStreamDestroy(a);
+  }
+  c->aux_streams.erase(it);
+}
+
 }  // namespace he
 
 using namespace he;
@@ -445,6 +474,7 @@ int he_lane_release(he_ctx* h, he_stream stream) {
   Ctx* c = &h->c;
   HE_HIP(hipStreamSynchronize((hipStream_t)stream));
   std::lock_guard<std::mutex> lk(c->lanes_mu);
+  aux_free(c, (hipStream_t)stream);
   auto it = c->lanes.find((hipStream_t)stream);
   if (it == c->lanes.end()) return HE_OK;
   lane_free(c, it->first, it->second);
@@ -488,6 +518,12 @@ int he_ctx_destroy(he_ctx* h) {
   hipSetDevice(h->c.device);
   hipDeviceSynchronize();
   keys_free_all(&h->c);
+  {
+    std::lock_guard<std::mutex> lk(h->c.lanes_mu);
+    std::vector<hipStream_t> callers;
+    for (auto& kv : h->c.aux_streams) callers.push_back(kv.first);
+    for (hipStream_t st : callers) aux_free(&h->c, st);
+  }
   for (auto& kv : h->c.lanes) lane_free(&h->c, kv.first, kv.second);
   h->c.lanes.clear();
   for (void* p : h->c.allocs) hipFree(p);

@@ -106,6 +106,10 @@ struct Ctx {
   int chsum = HE_CHSUM_CHAIN;      // convolution input-channel sum (he_ctx_conv_channel_sum)
   int chain = HE_CHAIN_HORNER;     // masked rotation chains of the layers (he_ctx_mask_chains)
   int fc = HE_FC_ROWS;             // fully connected form (he_ctx_fc_form)
+  int layer_streams = 2;           // streams a layer spreads its output channels over (he_ctx_layer_streams)
+  // helper streams of each caller stream (created on first use, default
+  // priority; each gets its own lane), guarded by lanes_mu
+  std::map<hipStream_t, std::vector<hipStream_t>> aux_streams;
   // NTT variant (log2 residues per thread) per batch-size bucket (<= 8, 16,
   // 32, more limbs), chosen by the autotuner at context creation
   int ntt_var[4] = {0, 0, 0, 2};           // NTT variant per batch-size bucket
@@ -264,6 +268,9 @@ int key_lock(Ctx* c, int32_t id, int delta);
 void keys_free_all(Ctx* c);
 // lane of a stream (created on first use; throws nothing, returns null on allocation failure)
 Lane* lane_for(Ctx* c, hipStream_t s);
+// the first n helper streams of caller stream s (created on first use);
+// HE_OK or HE_EHIP
+int aux_streams_for(Ctx* c, hipStream_t s, int n, hipStream_t* out);
 uint64_t* lane_ct_get(Ctx* c, Lane* ln);  // null on allocation failure
 int check_ct(const Ctx* c, const he_ct* x, const char* what);
 int check_out(const Ctx* c, const he_ct* x, int need_level);

@@ -136,6 +136,67 @@ static he_ct mac_all(Ev& ev, const std::vector<he_ct>& cts, const he_pt* pts) {
   return acc;
 }
 
+// A layer's independent per-output-channel work spread over the caller's
+// stream (at(0)) and up to layer_streams - 1 helper streams of it, each with
+// its own evaluator (lane).  The helpers start after everything enqueued on
+// the caller's stream so far; join() makes the caller's stream wait for
+// them.  On destruction the helpers wait for the caller's stream, so their
+// pooled temporaries (which the caller's stream may have read) are reused
+// only after those reads; on an error path (no join) the host first waits
+// for the helpers.  Results do not depend on the split: the work on each
+// stream is the same sequence of exact modular operations.
+struct Fork {
+  Ev& main;
+  std::vector<hipStream_t> hs;
+  std::vector<Ev*> aux;
+  bool joined = false;
+  Fork(Ev& m, int want) : main(m) {
+    const int n = std::max(0, std::min(want, 8) - 1);
+    if (n == 0) return;
+    hs.resize(n);
+    ck(aux_streams_for(m.c, (hipStream_t)m.s, n, hs.data()));
+    hipEvent_t e = nullptr;
+    ck(hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess ? HE_OK : HE_EHIP);
+    hipEventRecord(e, (hipStream_t)m.s);
+    for (hipStream_t a : hs) hipStreamWaitEvent(a, e, 0);
+    hipEventDestroy(e);
+    try {
+      for (hipStream_t a : hs) aux.push_back(new Ev(m.h, (he_stream)a));
+    } catch (...) {
+      release_all();
+      throw;
+    }
+  }
+  int size() const { return 1 + (int)aux.size(); }
+  Ev& at(int i) { return i == 0 ? main : *aux[i - 1]; }
+  void join() {
+    for (hipStream_t a : hs) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        hipStreamSynchronize(a);
+        continue;
+      }
+      hipEventRecord(e, a);
+      hipStreamWaitEvent((hipStream_t)main.s, e, 0);
+      hipEventDestroy(e);
+    }
+    joined = true;
+  }
+  void release_all() {
+    if (!joined)
+      for (hipStream_t a : hs) hipStreamSynchronize(a);
+    hipEvent_t e = nullptr;
+    if (!hs.empty() && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+      hipEventRecord(e, (hipStream_t)main.s);
+      for (hipStream_t a : hs) hipStreamWaitEvent(a, e, 0);
+      hipEventDestroy(e);
+    }
+    for (Ev* x : aux) delete x;
+    aux.clear();
+  }
+  ~Fork() { release_all(); }
+};
+
 // ---------------------------------------------------------------- compaction
 struct Step {
   int kind, n, key;  // kind 0 col, 1 row, 2 chan
@@ -359,20 +420,36 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
     std::vector<he_ct> taps = {g2[0], g1[0], g2[1], g1[2], x, g1[3], g3[0], g1[1], g3[1]};
     const bool place = C > 1 || F > 1;
     he_ct y{};
-    for (int f = 0; f < F; f++) {
-      he_ct A = ev.rescale_take(mac_all(ev, taps, kern + 9 * f));
-      he_ct Ssum = A;
-      if (C > 1) {
-        // S_f = A_f + Rot_{W^2}(A_f) + Rot_{2 W^2}(A_f) + ...
-        Ssum = channel_sum(ev, A, C, W * W);
-        ev.release(A);
+    {
+      // output channel f on stream f mod K; per-stream partial sums of the
+      // placed channels, added on the caller's stream
+      Fork fk(ev, place ? std::min(ev.c->layer_streams, F) : 1);
+      const int K = fk.size();
+      std::vector<he_ct> part(K);
+      std::vector<bool> has(K, false);
+      for (int f = 0; f < F; f++) {
+        Ev& e = fk.at(f % K);
+        he_ct A = e.rescale_take(mac_all(e, taps, kern + 9 * f));
+        he_ct Ssum = A;
+        if (C > 1) {
+          // S_f = A_f + Rot_{W^2}(A_f) + Rot_{2 W^2}(A_f) + ...
+          Ssum = channel_sum(e, A, C, W * W);
+          e.release(A);
+        }
+        if (place) {
+          if (!has[f % K]) part[f % K] = e.mul(Ssum, masks[f]);
+          else e.mac(part[f % K], Ssum, masks[f]);
+          has[f % K] = true;
+          e.release(Ssum);
+        } else {
+          y = Ssum;
+        }
       }
+      fk.join();
       if (place) {
-        if (f == 0) y = ev.mul(Ssum, masks[0]);
-        else ev.mac(y, Ssum, masks[f]);
-        ev.release(Ssum);
-      } else {
-        y = Ssum;
+        y = part[0];
+        for (int k = 1; k < K; k++)
+          if (has[k]) ev.add_into(y, part[k]);
       }
     }
     int mpos = 0;
@@ -401,16 +478,37 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
   for (int r : tap_rot) taps.push_back(r ? rots[next++] : x);
   const int cs = fm.chan_stride;
   he_ct acc{};
-  for (int f = F - 1; f >= 0; f--) {
-    he_ct A = ev.rescale_take(mac_all(ev, taps, kern + k * k * f));
-    he_ct term = A;
-    if (C > 1) {
-      he_ct sum = channel_sum(ev, A, C, cs);
-      ev.release(A);
-      term = ev.rescale_take(ev.mul(sum, masks[0]));
-      ev.release(sum);
+  {
+    // per-channel terms (output channel f on stream f mod K), then the
+    // placement chain on the caller's stream
+    Fork fk(ev, std::min(ev.c->layer_streams, F));
+    const int K = fk.size();
+    std::vector<he_ct> terms(F);
+    for (int f = F - 1; f >= 0; f--) {
+      Ev& e = fk.at(f % K);
+      he_ct A = e.rescale_take(mac_all(e, taps, kern + k * k * f));
+      he_ct term = A;
+      if (C > 1) {
+        he_ct sum = channel_sum(e, A, C, cs);
+        e.release(A);
+        term = e.rescale_take(e.mul(sum, masks[0]));
+        e.release(sum);
+      }
+      if (K == 1) {  // fold at once (one term alive at a time)
+        acc = (f == F - 1) ? term : ev.add_take(ev.rot_take(acc, -cs), term);
+      } else {
+        terms[f] = term;
+      }
     }
-    acc = (f == F - 1) ? term : ev.add_take(ev.rot_take(acc, -cs), term);
+    fk.join();
+    if (K > 1) {
+      // rot_take returns only the caller evaluator's own temporaries
+      acc = terms[F - 1];
+      for (int f = F - 2; f >= 0; f--) {
+        acc = ev.rot_take(acc, -cs);
+        ev.add_into(acc, terms[f]);
+      }
+    }
   }
   for (auto& r : rots) ev.release(r);
   const int H1 = fm.height + 2 * P - k + 1, W1 = fm.width + 2 * P - k + 1;
@@ -783,6 +881,13 @@ int he_avgpool(he_ctx* h, const he_ct* in, const he_fmap* in_map, int kernel, in
 int he_fc_plan(const he_ctx* h, int n_in, int n_out, he_layer_plan* plan) {
   if (!h) return set_error(HE_EINVAL, "null context");
   return fc_plan_impl(&h->c, n_in, n_out, plan);
+}
+
+int he_ctx_layer_streams(he_ctx* h, int n) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  if (n < 1 || n > 8) return set_error(HE_EINVAL, "layer streams must be in [1, 8]");
+  h->c.layer_streams = n;
+  return HE_OK;
 }
 
 int he_ctx_fc_form(he_ctx* h, int mode) {

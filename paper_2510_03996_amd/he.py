@@ -142,6 +142,7 @@ def lib():
             "he_ctx_conv_channel_sum": [vp, i32],
             "he_ctx_mask_chains": [vp, i32],
             "he_ctx_fc_form": [vp, i32],
+            "he_ctx_layer_streams": [vp, i32],
             "he_key_host_register": [vp, i32, P(ctypes.c_uint64), sz],
             "he_key_cache_limit": [vp, sz],
             "he_key_prefetch": [vp, P(i32), c_int, vp],
@@ -499,6 +500,12 @@ class Context:
         """Form of later fc plans and calls: FC_ROWS (per neuron) or FC_DIAG
         (diagonal, baby-step giant-step; weight_pts are the rotated diagonals)."""
         _check(lib().he_ctx_fc_form(self.h, int(mode)))
+
+    def layer_streams(self, n):
+        """Streams (1..8, default 2) a convolution spreads its output channels
+        over: the caller's stream plus n - 1 helper streams of it; results do
+        not depend on n."""
+        _check(lib().he_ctx_layer_streams(self.h, int(n)))
 
     def ntt_variants(self):
         var = (ctypes.c_int32 * 4)()

@@ -6,6 +6,7 @@ decryption with the paper's FP64 layer equation.
 """
 import numpy as np
 import pytest
+import torch
 
 import synth
 from oracle import ckks
@@ -67,7 +68,9 @@ def encrypt_map(name, X, fm, seed, level=None):
     return ct
 
 
-def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False, bsgs=False):
+def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False, bsgs=False, streams=(2,)):
+    """One oracle convolution; the GPU result with each layer-stream count in
+    `streams` must equal it bit for bit."""
     from paper_2510_03996_amd import he
 
     octx, sk, _ = H.oracle_ctx(name)
@@ -84,10 +87,14 @@ def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False
     kp, mp = encode(octx, kern, ct.level), encode(octx, masks, ct.level)
     want, fo = LY.conv2d(ev, ct, fm, F, k, stride, padding, kp, mp, slots, logstep=logstep, bsgs=bsgs)
     assert ev.ks == plan.key_switches and ct.level - want.level == plan.levels
-    got, gfm = g.conv2d(g.ct_from_numpy(ct.data, ct.scale), fm_he(fm), F, k, stride, padding, gpts(g, kp),
-                        gpts(g, mp))
-    assert gfm.key() == fo.key()
-    check_ct(got, want, "conv2d")
+    gct, gkp, gmp = g.ct_from_numpy(ct.data, ct.scale), gpts(g, kp), gpts(g, mp)
+    for n in streams:
+        g.layer_streams(n)
+        got, gfm = g.conv2d(gct, fm_he(fm), F, k, stride, padding, gkp, gmp)
+        torch.cuda.synchronize()
+        assert gfm.key() == fo.key()
+        check_ct(got, want, "conv2d with %d layer stream(s)" % n)
+    g.layer_streams(2)  # the library default
     dec = LY.unpack(octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale)), fo)
     err = np.max(np.abs(dec - LY.conv2d_ref(X, K, stride, padding)))
     assert err < 1e-3, err
@@ -99,14 +106,14 @@ def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False
 def test_config0_special_conv(gctx):
     X = synth.image(20, 1, 8, 8)
     K = synth.conv_weights(20, 1, 1, 3, 0.1)
-    run_conv(gctx("config0"), "config0", X, K, LY.FMap(1, 8, 8), 1, 1, 20)
+    run_conv(gctx("config0"), "config0", X, K, LY.FMap(1, 8, 8), 1, 1, 20, streams=(1, 2))
 
 
 def test_config1_generic_conv_multichannel_stride(gctx):
     """C=3 -> F=4, 3x3, stride 2, pad 0 at N=2^14 (channel chain, block-0 mask, placement, compaction)."""
     X = synth.image(21, 3, 12, 12)
     K = synth.conv_weights(21, 4, 3, 3, 0.2)
-    run_conv(gctx("config1"), "config1", X, K, LY.FMap(3, 12, 12), 2, 0, 21)
+    run_conv(gctx("config1"), "config1", X, K, LY.FMap(3, 12, 12), 2, 0, 21, streams=(1, 2, 3, 8))
 
 
 def test_config1_lenet_stack(gctx):
@@ -142,14 +149,15 @@ def test_config2_small_special_conv(gctx):
     """4 replicated channels of 64x64 at N=2^16, L=24 (20 key switches)."""
     X = synth.image(23, 4, 64, 64)
     K = synth.conv_weights(23, 4, 4, 3, (2.0 / 36) ** 0.5)
-    run_conv(gctx("config2"), "config2", X, K, LY.FMap(4, 64, 64, reps=2), 1, 1, 23)
+    run_conv(gctx("config2"), "config2", X, K, LY.FMap(4, 64, 64, reps=2), 1, 1, 23, streams=(1, 3, 4))
 
 
 def test_config2_conv_a(gctx):
     """ResNet-20-shaped conv 3x3 16->16, stride 1, pad 1 on a replicated 16x32x32 input (248 key switches)."""
     X = synth.image(24, 16, 32, 32)
     K = synth.conv_weights(24, 16, 16, 3, (2.0 / 144) ** 0.5)
-    got, want, fo = run_conv(gctx("config2"), "config2", X, K, LY.FMap(16, 32, 32, reps=2), 1, 1, 24)
+    got, want, fo = run_conv(gctx("config2"), "config2", X, K, LY.FMap(16, 32, 32, reps=2), 1, 1, 24,
+                             streams=(1, 4))
     assert fo.reps == 2
 
 
@@ -157,7 +165,7 @@ def test_config2_conv_b(gctx):
     """conv 3x3 16->32, stride 2, pad 1 at level 22 (549 key switches, joint stride compaction)."""
     X = synth.image(25, 16, 32, 32)
     K = synth.conv_weights(25, 32, 16, 3, (2.0 / 144) ** 0.5)
-    run_conv(gctx("config2"), "config2", X, K, LY.FMap(16, 32, 32, reps=2), 2, 1, 25, level=22)
+    run_conv(gctx("config2"), "config2", X, K, LY.FMap(16, 32, 32, reps=2), 2, 1, 25, level=22, streams=(1, 4))
 
 
 @pytest.mark.parametrize("C,HW,level", [(32, 16, 17), (64, 8, 17)])
@@ -241,7 +249,8 @@ def test_config2_special_conv_logstep(gctx, stride):
     channels of 64x64 at N=2^16, keys W^2 and 2 W^2, stride 1 and 2."""
     X = synth.image(71, 4, 64, 64)
     K = synth.conv_weights(71, 4, 4, 3, (2.0 / 36) ** 0.5)
-    run_conv(gctx("config2"), "config2", X, K, LY.FMap(4, 64, 64, reps=2), stride, 1, 71, logstep=True)
+    run_conv(gctx("config2"), "config2", X, K, LY.FMap(4, 64, 64, reps=2), stride, 1, 71, logstep=True,
+             streams=(1, 2))
 
 
 def test_config1_generic_conv_logstep(gctx):
@@ -249,7 +258,7 @@ def test_config1_generic_conv_logstep(gctx):
     pad 2 at N=2^14 (keys cs and 2 cs)."""
     X = synth.image(72, 4, 16, 16)
     K = synth.conv_weights(72, 3, 4, 5, 0.1)
-    run_conv(gctx("config1"), "config1", X, K, LY.FMap(4, 16, 16), 2, 2, 72, logstep=True)
+    run_conv(gctx("config1"), "config1", X, K, LY.FMap(4, 16, 16), 2, 2, 72, logstep=True, streams=(1, 4))
 
 
 def test_channel_sum_mode_errors(gctx):
@@ -368,6 +377,17 @@ def test_fc_diag(gctx, n_in, n_out, name):
         assert np.max(np.abs(dec[:n_out] - LY.fc_ref(x, Wm))) < 1e-3
     finally:
         g.fc_form(he.FC_ROWS)
+
+
+def test_layer_streams_errors(gctx):
+    from paper_2510_03996_amd import he
+
+    g = gctx("config0")
+    for bad in (0, 9, -1):
+        with pytest.raises(he.HEError) as e:
+            g.layer_streams(bad)
+        assert e.value.name == "HE_EINVAL"
+    g.layer_streams(2)
 
 
 def test_fc_form_errors(gctx):

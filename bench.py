@@ -204,7 +204,9 @@ def headline(args):
 # ---------------------------------------------------------------- hoisted rotation sets
 def hoisted_sets(reps=20):
     """he_rotate_hoisted at N=2^16 L=24: the 3x3 conv window (8 rotations, W=32)
-    and the 7x7 window plus 1024 (49 rotations), one ModUp per set."""
+    and the 7x7 window plus 1024 (49 rotations), one ModUp per set; the key
+    switches of a set at the library default of two streams, and on one
+    (`<set>_streams1`) and four (`<set>_streams4`)."""
     import torch
 
     ctx = new_ctx(CFG2)
@@ -214,19 +216,21 @@ def hoisted_sets(reps=20):
     ct = synthetic_ct(ctx, ctx.L, 4, 2.0 ** 50)
     stream = torch.cuda.current_stream()
     out = {}
-    for name, rs in sets.items():
-        outs = [ctx.new_ct(ctx.L) for _ in rs]
-        for _ in range(2):
-            ctx.rotate_hoisted(ct, rs, outs=outs, stream=stream)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            ctx.rotate_hoisted(ct, rs, outs=outs, stream=stream)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        out[name] = {"rotations": len(rs), "ms_per_set": round(el / reps * 1e3, 3),
-                     "rotations_per_s": round(reps * len(rs) / el, 1)}
-        del outs
+    for n_streams, suffix in ((2, ""), (1, "_streams1"), (4, "_streams4")):
+        ctx.layer_streams(n_streams)
+        for name, rs in sets.items():
+            outs = [ctx.new_ct(ctx.L) for _ in rs]
+            for _ in range(2):
+                ctx.rotate_hoisted(ct, rs, outs=outs, stream=stream)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ctx.rotate_hoisted(ct, rs, outs=outs, stream=stream)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            out[name + suffix] = {"rotations": len(rs), "ms_per_set": round(el / reps * 1e3, 3),
+                                  "rotations_per_s": round(reps * len(rs) / el, 1)}
+            del outs
     ctx.close()
     return out
 

@@ -343,17 +343,20 @@ int he_fc(he_ctx* ctx, const he_ct* in, int n_in, int n_out, const he_pt* weight
 #define HE_FC_DIAG 1
 int he_ctx_fc_form(he_ctx* ctx, int mode);
 
-/* Streams a convolution spreads its output channels over (1..8, default 2):
+/* Streams the independent parts of a call are spread over (1..8, default 2):
  * the per-channel work (products with the kernel vectors, input-channel sum,
- * masking) of output channel f runs on the caller's stream (f mod n == 0) or
- * on helper stream f mod n of the caller's stream, which the library creates
- * on first use (default priority, one workspace lane each: he_lane_bytes(0)
- * of device memory per helper) and destroys with he_lane_release of the
+ * masking) of a convolution's output channel f, and key switch j (inner
+ * product + ModDown after the shared ModUp) of a hoisted rotation set with
+ * several keys, run on the caller's stream (index mod n == 0) or on helper
+ * stream (index mod n) of the caller's stream, which the library creates on
+ * first use (default priority, one workspace lane each: he_lane_bytes(0) of
+ * device memory per helper) and destroys with he_lane_release of the
  * caller's stream or with the context.  The helpers start after the work
  * already enqueued on the caller's stream, and the caller's stream waits for
- * them before the channels are combined, so the call stays stream-ordered on
- * the caller's stream and its results are the same for every n.  HE_EINVAL
- * outside [1, 8]. */
+ * them before the parts are combined (or the call returns), so the call stays
+ * stream-ordered on the caller's stream and its results are the same for
+ * every n.  Rings below N = 2^14 always use the caller's stream alone (their
+ * key switches are too short to gain).  HE_EINVAL outside [1, 8]. */
 int he_ctx_layer_streams(he_ctx* ctx, int n);
 
 /* Polynomial activation p(x) = c[0] + c[1] x + c[2] x^2 + c[4] x^4 (c[3]

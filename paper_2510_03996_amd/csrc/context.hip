@@ -427,6 +427,35 @@ int aux_streams_for(Ctx* c, hipStream_t s, int n, hipStream_t* out) {
   return HE_OK;
 }
 
+int stream_fork(hipStream_t s, const hipStream_t* hs, int n) {
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return set_error(HE_EHIP, "event creation failed");
+  hipError_t err = hipEventRecord(e, s);
+  for (int i = 0; i < n && err == hipSuccess; i++) err = hipStreamWaitEvent(hs[i], e, 0);
+  hipEventDestroy(e);
+  return err == hipSuccess ? HE_OK : hip_error(err, "stream fork");
+}
+
+int stream_join(hipStream_t s, const hipStream_t* hs, int n) {
+  int rc = HE_OK;
+  for (int i = 0; i < n; i++) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      hipStreamSynchronize(hs[i]);  // cannot order on the device: wait on the host
+      rc = set_error(HE_EHIP, "event creation failed");
+      continue;
+    }
+    hipError_t err = hipEventRecord(e, hs[i]);
+    if (err == hipSuccess) err = hipStreamWaitEvent(s, e, 0);
+    if (err != hipSuccess) {
+      hipStreamSynchronize(hs[i]);
+      rc = hip_error(err, "stream join");
+    }
+    hipEventDestroy(e);
+  }
+  return rc;
+}
+
 // destroy the helper streams of caller stream s and their lanes (lanes_mu held)
 static void aux_free(Ctx* c, hipStream_t s) {
   auto it = c->aux_streams.find(s);

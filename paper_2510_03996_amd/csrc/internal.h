@@ -106,7 +106,9 @@ struct Ctx {
   int chsum = HE_CHSUM_CHAIN;      // convolution input-channel sum (he_ctx_conv_channel_sum)
   int chain = HE_CHAIN_HORNER;     // masked rotation chains of the layers (he_ctx_mask_chains)
   int fc = HE_FC_ROWS;             // fully connected form (he_ctx_fc_form)
-  int layer_streams = 2;           // streams a layer spreads its output channels over (he_ctx_layer_streams)
+  int layer_streams = 2;           // streams a convolution / hoisted set is spread over (he_ctx_layer_streams)
+  // helper streams only where a key switch outlasts the fork and join (N >= 2^14)
+  int streams_for_ring() const { return n >= 16384 ? layer_streams : 1; }
   // helper streams of each caller stream (created on first use, default
   // priority; each gets its own lane), guarded by lanes_mu
   std::map<hipStream_t, std::vector<hipStream_t>> aux_streams;
@@ -271,6 +273,10 @@ Lane* lane_for(Ctx* c, hipStream_t s);
 // the first n helper streams of caller stream s (created on first use);
 // HE_OK or HE_EHIP
 int aux_streams_for(Ctx* c, hipStream_t s, int n, hipStream_t* out);
+// helpers hs[0..n) wait for the work enqueued on s so far (fork), or s waits
+// for the work enqueued on each helper so far (join); HE_OK or HE_EHIP
+int stream_fork(hipStream_t s, const hipStream_t* hs, int n);
+int stream_join(hipStream_t s, const hipStream_t* hs, int n);
 uint64_t* lane_ct_get(Ctx* c, Lane* ln);  // null on allocation failure
 int check_ct(const Ctx* c, const he_ct* x, const char* what);
 int check_out(const Ctx* c, const he_ct* x, int need_level);

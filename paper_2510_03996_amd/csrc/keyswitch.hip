@@ -277,25 +277,51 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
   // one key switch: the inner product is fused into ModUp's last NTT pass;
   // several: one ModUp shared by all of them (hoisting)
   if (nks > 1 && (rc = ks_modup(c, w, c1, l, s))) return rc;
-  for (int t = 0; t < n; t++) {
+  // several: key switch j (inner product + ModDown) on the caller's stream or
+  // on helper stream j mod K of it, each helper with its own lane's
+  // workspace and the caller's extended digits; the helpers start after the
+  // ModUp and the caller's stream waits for them before returning
+  const int K = nks > 1 ? std::max(1, std::min(std::min(c->streams_for_ring(), 8), nks)) : 1;
+  hipStream_t hs[8] = {s};
+  WS wk[8] = {w};
+  if (K > 1) {
+    if ((rc = aux_streams_for(c, s, K - 1, hs + 1))) return rc;
+    for (int k = 1; k < K; k++) {
+      Lane* lk = lane_for(c, hs[k]);
+      if (!lk) return HE_ENOMEM;
+      wk[k] = ws_layout(c, lk->ws);
+      wk[k].ext = w.ext;
+    }
+    if ((rc = stream_fork(s, hs + 1, K - 1))) return rc;
+  }
+  int j = 0;
+  for (int t = 0; t < n && rc == HE_OK; t++) {
     he_ct& o = outs[t];
     uint64_t* o0 = o.data;
     uint64_t* o1 = o.data + (size_t)o.cap * N;
     if (norm_key_id(c, r[t]) == 0) {
-      HE_HIP(hipMemcpyAsync(o0, c0, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s));
-      HE_HIP(hipMemcpyAsync(o1, c1, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s));
+      if (hipMemcpyAsync(o0, c0, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+          hipMemcpyAsync(o1, c1, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        rc = set_error(HE_EHIP, "copy of an identity rotation failed");
     } else {
-      const uint64_t* key = key_acquire(c, r[t], s);
-      if (!key) return HE_ENOMEM;
-      rc = nks == 1 ? ks_single(c, w, c1, l, key, galois_elt(c, r[t]), c0, nullptr, o0, o1, s)
-                    : ks_apply(c, w, c1, l, key, galois_elt(c, r[t]), c0, nullptr, o0, o1, s);
-      if (rc) return rc;
-      key_note_use(c, r[t], s);
+      const int k = j++ % K;
+      const uint64_t* key = key_acquire(c, r[t], hs[k]);
+      if (!key) {
+        rc = HE_ENOMEM;
+        break;
+      }
+      rc = nks == 1 ? ks_single(c, wk[k], c1, l, key, galois_elt(c, r[t]), c0, nullptr, o0, o1, hs[k])
+                    : ks_apply(c, wk[k], c1, l, key, galois_elt(c, r[t]), c0, nullptr, o0, o1, hs[k]);
+      if (rc == HE_OK) key_note_use(c, r[t], hs[k]);
     }
     o.level = l;
     o.scale = in->scale;
   }
-  return HE_OK;
+  if (K > 1) {
+    const int jr = stream_join(s, hs + 1, K - 1);  // also on an error path: the helpers read the workspace
+    if (rc == HE_OK) rc = jr;
+  }
+  return rc;
 }
 
 int he_rotate(he_ctx* h, const he_ct* in, int32_t r, he_ct* out, he_stream st) {

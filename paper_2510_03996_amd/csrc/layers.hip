@@ -155,11 +155,7 @@ struct Fork {
     if (n == 0) return;
     hs.resize(n);
     ck(aux_streams_for(m.c, (hipStream_t)m.s, n, hs.data()));
-    hipEvent_t e = nullptr;
-    ck(hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess ? HE_OK : HE_EHIP);
-    hipEventRecord(e, (hipStream_t)m.s);
-    for (hipStream_t a : hs) hipStreamWaitEvent(a, e, 0);
-    hipEventDestroy(e);
+    ck(stream_fork((hipStream_t)m.s, hs.data(), n));
     try {
       for (hipStream_t a : hs) aux.push_back(new Ev(m.h, (he_stream)a));
     } catch (...) {
@@ -170,26 +166,15 @@ struct Fork {
   int size() const { return 1 + (int)aux.size(); }
   Ev& at(int i) { return i == 0 ? main : *aux[i - 1]; }
   void join() {
-    for (hipStream_t a : hs) {
-      hipEvent_t e = nullptr;
-      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-        hipStreamSynchronize(a);
-        continue;
-      }
-      hipEventRecord(e, a);
-      hipStreamWaitEvent((hipStream_t)main.s, e, 0);
-      hipEventDestroy(e);
-    }
-    joined = true;
+    joined = true;  // stream_join waits on the host for a helper it cannot order
+    ck(stream_join((hipStream_t)main.s, hs.data(), (int)hs.size()));
   }
   void release_all() {
-    if (!joined)
-      for (hipStream_t a : hs) hipStreamSynchronize(a);
-    hipEvent_t e = nullptr;
-    if (!hs.empty() && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
-      hipEventRecord(e, (hipStream_t)main.s);
-      for (hipStream_t a : hs) hipStreamWaitEvent(a, e, 0);
-      hipEventDestroy(e);
+    if (!hs.empty()) {
+      if (!joined)
+        for (hipStream_t a : hs) hipStreamSynchronize(a);
+      if (stream_fork((hipStream_t)main.s, hs.data(), (int)hs.size()) != HE_OK)
+        hipStreamSynchronize((hipStream_t)main.s);
     }
     for (Ev* x : aux) delete x;
     aux.clear();
@@ -423,7 +408,7 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
     {
       // output channel f on stream f mod K; per-stream partial sums of the
       // placed channels, added on the caller's stream
-      Fork fk(ev, place ? std::min(ev.c->layer_streams, F) : 1);
+      Fork fk(ev, place ? std::min(ev.c->streams_for_ring(), F) : 1);
       const int K = fk.size();
       std::vector<he_ct> part(K);
       std::vector<bool> has(K, false);
@@ -481,7 +466,7 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
   {
     // per-channel terms (output channel f on stream f mod K), then the
     // placement chain on the caller's stream
-    Fork fk(ev, std::min(ev.c->layer_streams, F));
+    Fork fk(ev, std::min(ev.c->streams_for_ring(), F));
     const int K = fk.size();
     std::vector<he_ct> terms(F);
     for (int f = F - 1; f >= 0; f--) {

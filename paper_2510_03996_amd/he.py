@@ -502,9 +502,9 @@ class Context:
         _check(lib().he_ctx_fc_form(self.h, int(mode)))
 
     def layer_streams(self, n):
-        """Streams (1..8, default 2) a convolution spreads its output channels
-        over: the caller's stream plus n - 1 helper streams of it; results do
-        not depend on n."""
+        """Streams (1..8, default 2) a convolution's output channels and a
+        hoisted set's key switches are spread over: the caller's stream plus
+        n - 1 helper streams of it; results do not depend on n."""
         _check(lib().he_ctx_layer_streams(self.h, int(n)))
 
     def ntt_variants(self):

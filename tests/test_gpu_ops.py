@@ -168,10 +168,15 @@ def test_rotate_hoisted(gctx, name):
     for r, k in keys.items():
         g.key_upload(r, k)
     _, a = H.encrypt_slots(name, 12)
-    got = g.rotate_hoisted(g.ct_from_numpy(a.data, a.scale), rs)
+    ga = g.ct_from_numpy(a.data, a.scale)
     want = octx.rotate_hoisted(a, rs, keys)
-    for r, x, y in zip(rs, got, want):
-        H.assert_limbs_equal(x.numpy(), y.data, "hoisted rotation %d" % r)
+    # the key switches of the set on 1, 2, 3 and 8 streams (caller + helpers)
+    for n in (1, 2, 3, 8):
+        g.layer_streams(n)
+        got = g.rotate_hoisted(ga, rs)
+        for r, x, y in zip(rs, got, want):
+            H.assert_limbs_equal(x.numpy(), y.data, "hoisted rotation %d on %d stream(s)" % (r, n))
+    g.layer_streams(2)
 
 
 @pytest.mark.parametrize("name,level", [("config2", 13), ("config2", 8), ("config1", 5), ("config1", 2), ("config0", 2)])

@@ -345,7 +345,8 @@ int he_ctx_fc_form(he_ctx* ctx, int mode);
 
 /* Streams the independent parts of a call are spread over (1..8, default 2):
  * the per-channel work (products with the kernel vectors, input-channel sum,
- * masking) of a convolution's output channel f, and key switch j (inner
+ * masking) of a convolution's output channel f, the per-neuron work of the
+ * per-row fully connected form (product, log-step sum, mask), and key switch j (inner
  * product + ModDown after the shared ModUp) of a hoisted rotation set with
  * several keys, run on the caller's stream (index mod n == 0) or on helper
  * stream (index mod n) of the caller's stream, which the library creates on
@@ -355,8 +356,10 @@ int he_ctx_fc_form(he_ctx* ctx, int mode);
  * already enqueued on the caller's stream, and the caller's stream waits for
  * them before the parts are combined (or the call returns), so the call stays
  * stream-ordered on the caller's stream and its results are the same for
- * every n.  Rings below N = 2^14 always use the caller's stream alone (their
- * key switches are too short to gain).  HE_EINVAL outside [1, 8]. */
+ * every n.  Rings below N = 2^16 always use the caller's stream alone (their
+ * key switches are too short to cover the cross-queue waits).  The gain needs
+ * the helpers on other hardware queues than the caller's (HIP maps streams
+ * onto a few queues per process).  HE_EINVAL outside [1, 8]. */
 int he_ctx_layer_streams(he_ctx* ctx, int n);
 
 /* Polynomial activation p(x) = c[0] + c[1] x + c[2] x^2 + c[4] x^4 (c[3]

@@ -107,8 +107,9 @@ struct Ctx {
   int chain = HE_CHAIN_HORNER;     // masked rotation chains of the layers (he_ctx_mask_chains)
   int fc = HE_FC_ROWS;             // fully connected form (he_ctx_fc_form)
   int layer_streams = 2;           // streams a convolution / hoisted set is spread over (he_ctx_layer_streams)
-  // helper streams only where a key switch outlasts the fork and join (N >= 2^14)
-  int streams_for_ring() const { return n >= 16384 ? layer_streams : 1; }
+  // helper streams only where a key switch outlasts the fork and join even
+  // when the helpers sit on other hardware queues (N = 2^16)
+  int streams_for_ring() const { return n >= 65536 ? layer_streams : 1; }
   // helper streams of each caller stream (created on first use, default
   // priority; each gets its own lane), guarded by lanes_mu
   std::map<hipStream_t, std::vector<hipStream_t>> aux_streams;

@@ -926,15 +926,32 @@ int he_fc(he_ctx* h, const he_ct* in, int n_in, int n_out, const he_pt* weight_p
       ev.copy_out(acc, out);
       return HE_OK;
     }
-    auto neuron = [&](int k) {
-      he_ct P = ev.rescale_take(ev.mul(*in, weight_pts[k]));
-      for (int t = 1; t < n_in; t <<= 1) P = ev.add_take(P, ev.rot(P, t));
-      he_ct r = ev.rescale_take(ev.mul(P, mask_pts[0]));
-      ev.release(P);
+    auto neuron = [&](Ev& e, int k) {
+      he_ct P = e.rescale_take(e.mul(*in, weight_pts[k]));
+      for (int t = 1; t < n_in; t <<= 1) P = e.add_take(P, e.rot(P, t));
+      he_ct r = e.rescale_take(e.mul(P, mask_pts[0]));
+      e.release(P);
       return r;
     };
-    he_ct acc = neuron(n_out - 1);
-    for (int k = n_out - 2; k >= 0; k--) acc = ev.add_take(ev.rot_take(acc, -1), neuron(k));
+    he_ct acc{};
+    {
+      // neuron k on stream k mod K, then the placement chain on the caller's stream
+      Fork fk(ev, std::min(c->streams_for_ring(), n_out));
+      const int K = fk.size();
+      if (K == 1) {
+        acc = neuron(ev, n_out - 1);
+        for (int k = n_out - 2; k >= 0; k--) acc = ev.add_take(ev.rot_take(acc, -1), neuron(ev, k));
+      } else {
+        std::vector<he_ct> r(n_out);
+        for (int k = n_out - 1; k >= 0; k--) r[k] = neuron(fk.at(k % K), k);
+        fk.join();
+        acc = r[n_out - 1];  // rot_take returns only the caller evaluator's own temporaries
+        for (int k = n_out - 2; k >= 0; k--) {
+          acc = ev.rot_take(acc, -1);
+          ev.add_into(acc, r[k]);
+        }
+      }
+    }
     if (bias_pt) ck(he_add_plain(h, &acc, bias_pt, &acc, s));
     ev.copy_out(acc, out);
     return HE_OK;

@@ -60,10 +60,18 @@ class Request:
 
 
 class Server:
-    def __init__(self, models, slots=4, budget_bytes=None):
+    """layer_streams: streams (he_ctx_layer_streams) a stage may spread its
+    convolution channels and hoisted key switches over while its request is
+    the only one in flight (always in sequential mode); with several requests
+    in flight each stage stays on its request's stream, since the requests
+    already overlap and more streams than hardware queues make them wait on
+    each other.  Results do not depend on it."""
+
+    def __init__(self, models, slots=4, budget_bytes=None, layer_streams=2):
         self.models = models
         self.slots = slots
         self.budget = budget_bytes
+        self.layer_streams = layer_streams
         self.streams = [torch.cuda.Stream() for _ in range(slots)]
         for s in self.streams:
             for m in models.values():
@@ -77,8 +85,9 @@ class Server:
             for m in self.models.values():
                 m.ctx.lane_release(s)
 
-    def _enqueue_stage(self, r):
+    def _enqueue_stage(self, r, alone=True):
         m = self.models[r.kind]
+        m.ctx.layer_streams(self.layer_streams if alone else 1)
         with torch.cuda.stream(r.stream):
             r.cur = m.stages[r.stage](r.cur, r.stream)
         r.stage += 1
@@ -88,6 +97,13 @@ class Server:
 
     def serve(self, requests, mode="continuous", t0=None):
         """Run requests (arrival times in seconds from t0); returns them completed."""
+        try:
+            return self._serve(requests, mode, t0)
+        finally:
+            for m in self.models.values():
+                m.ctx.layer_streams(self.layer_streams)
+
+    def _serve(self, requests, mode, t0):
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         done = []
         t0 = time.perf_counter() if t0 is None else t0
@@ -138,7 +154,7 @@ class Server:
                     used -= m.footprint
                     done.append(r)
                 else:
-                    self._enqueue_stage(r)
+                    self._enqueue_stage(r, alone=len(active) == 1)
                 progressed = True
             if not progressed:
                 nxt = pending[0].arrival - (time.perf_counter() - t0) if pending else 0.0

@@ -206,9 +206,14 @@ def test_config2_fc(gctx):
     rows, masks = LY.fc_plaintexts(Wm, slots)
     rp, mp = encode(octx, rows, ct.level), encode(octx, masks, ct.level)
     want = LY.fc(ev, ct, 64, 10, rp, mp)
-    got = g.fc(g.ct_from_numpy(ct.data, ct.scale), 64, 10, gpts(g, rp), gpts(g, mp))
     assert ev.ks == plan.key_switches == 69
-    check_ct(got, want, "fc")
+    gct, grp, gmp = g.ct_from_numpy(ct.data, ct.scale), gpts(g, rp), gpts(g, mp)
+    for n in (1, 2, 4):  # neurons over the caller's stream and n - 1 helpers
+        g.layer_streams(n)
+        got = g.fc(gct, 64, 10, grp, gmp)
+        torch.cuda.synchronize()
+        check_ct(got, want, "fc with %d stream(s)" % n)
+    g.layer_streams(2)
     dec = octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale))
     assert np.max(np.abs(dec[:10] - LY.fc_ref(x, Wm))) < 1e-3
 

@@ -197,8 +197,26 @@ def headline(args):
                  "hbm_GBs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4), "gmodmul_s": round(gmm, 1)})
     ks_bytes = 2 * L * N * 8 + 2 * dnum * (L + K) * N * 8 + 2 * L * N * 8
     roof["ntt_autotune"] = ctx.ntt_tuning()
+    # reported beside the value: the same independent rotations issued
+    # alternately on two streams (each stream with its own output buffer)
+    s2 = torch.cuda.Stream()
+    pair = (stream, s2)
+
+    def step2():
+        for t in range(ROT_PER_STEP):
+            ctx.rotate(ct, ROTATIONS[t % len(ROTATIONS)], out=outs[t & 1], stream=pair[t & 1])
+
+    for _ in range(args.warmup):
+        step2()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step2()
+    torch.cuda.synchronize()
+    two = {"rotations_per_s": round(args.steps * ROT_PER_STEP / (time.perf_counter() - t0), 1),
+           "workload": "the same rotations, issued alternately on two streams"}
     ctx.close()
-    return rot_s, el, roof, kern, ks_bytes, (L, K, dnum)
+    return rot_s, el, roof, kern, ks_bytes, (L, K, dnum), two
 
 
 # ---------------------------------------------------------------- hoisted rotation sets
@@ -551,7 +569,7 @@ def main():
         print(json.dumps({"copy_calibration_bytes": src.numel() * 8, "copies": 3}), flush=True)
         return
     log("headline: plain key-switch rotations")
-    rot_s, el, roof, kern, ks_bytes, (L, K, dnum) = headline(args)
+    rot_s, el, roof, kern, ks_bytes, (L, K, dnum), two = headline(args)
     result = {
         "metric": "key-switch rotations/s at N=2^16 L=24",
         "value": round(rot_s, 1),
@@ -571,6 +589,7 @@ def main():
         "keyswitch_hbm_frac": round(rot_s * ks_bytes / 1e9 / HBM_PEAK_GBS, 4),
         "roofline": roof,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in kern.items()},
+        "two_streams": two,
     }
     sections = [] if args.only_headline else ([args.only] if args.only else ["hoisted", "layers", "batched", "serving"])
     if "hoisted" in sections:

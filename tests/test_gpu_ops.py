@@ -179,6 +179,32 @@ def test_rotate_hoisted(gctx, name):
     g.layer_streams(2)
 
 
+def test_helper_streams_released_with_the_lane(gctx):
+    """A hoisted set on a fresh stream (its key switches over the stream and a
+    helper), the stream's lane released (helpers destroyed), the same set
+    again on that stream (helpers recreated): both equal the oracle."""
+    import torch
+
+    name = "config2"
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    rs = ROTS[name]
+    keys = H.oracle_keys(name, rs)
+    for r, k in keys.items():
+        g.key_upload(r, k)
+    _, a = H.encrypt_slots(name, 14)
+    ga = g.ct_from_numpy(a.data, a.scale)
+    want = octx.rotate_hoisted(a, rs, keys)
+    st = torch.cuda.Stream()
+    g.layer_streams(2)
+    for rep in range(2):
+        got = g.rotate_hoisted(ga, rs, stream=st)
+        st.synchronize()
+        for r, x, y in zip(rs, got, want):
+            H.assert_limbs_equal(x.numpy(), y.data, "hoisted rotation %d, pass %d" % (r, rep))
+        g.lane_release(st)
+
+
 @pytest.mark.parametrize("name,level", [("config2", 13), ("config2", 8), ("config1", 5), ("config1", 2), ("config0", 2)])
 def test_rotate_lower_levels(gctx, name, level):
     """Partial last digit and restricted keys at lower levels."""

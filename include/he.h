@@ -184,7 +184,9 @@ int he_ntt(he_ctx* ctx, uint64_t* poly, int n_limbs, int first_limb, int inverse
 int he_rotate(he_ctx* ctx, const he_ct* in, int32_t r, he_ct* out, he_stream stream);
 
 /* Hoisted rotations ("fast rotations"): one ModUp of c1 shared by n
- * rotations; outs[t] = Rot_{r[t]}(in).  Outputs must not alias the input. */
+ * rotations; outs[t] = Rot_{r[t]}(in).  Outputs must not alias the input or
+ * each other (HE_EINVAL); their key switches may run on helper streams of
+ * `stream` (he_ctx_layer_streams), all finished in stream order of `stream`. */
 int he_rotate_hoisted(he_ctx* ctx, const he_ct* in, const int32_t* r, int n, he_ct* outs, he_stream stream);
 
 /* out (+)= in (.) pt limb-wise at the ciphertext's level (pt-ct product of

@@ -263,6 +263,8 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
   for (int t = 0; t < n; t++) {
     if ((rc = check_out(c, &outs[t], l))) return rc;
     if (outs[t].data == in->data) return set_error(HE_EINVAL, "output aliases the input");
+    for (int u = 0; u < t; u++)  // outputs may be written from different streams
+      if (outs[u].data == outs[t].data) return set_error(HE_EINVAL, "two outputs share a buffer");
     if (norm_key_id(c, r[t]) != 0) {
       nks++;
       if (!key_known(c, r[t])) return set_error(HE_ENOKEY, "rotation key " + std::to_string(r[t]) + " not resident");

@@ -54,6 +54,13 @@ def test_degenerate_rotation_sets(g1):
     for o in outs[:3]:
         H.assert_limbs_equal(o.numpy(), want.data, "rotation aliases")
     H.assert_limbs_equal(outs[3].numpy(), a.data, "copy in a hoisted set")
+    # two outputs in one buffer are rejected (they may be written from different streams)
+    from paper_2510_03996_amd import he
+
+    o = g1.new_ct(a.level)
+    with pytest.raises(he.HEError) as e:
+        g1.rotate_hoisted(ga, [3, 0], outs=[o, o])
+    assert e.value.name == "HE_EINVAL"
 
 
 def test_constants_and_rescale_chain(g1):

@@ -178,6 +178,44 @@ def test_eviction_waits_for_every_stream():
         g.close()
 
 
+def test_convolution_streams_under_budget():
+    """Special convolution at N=2^16 (four replicated channels of 64x64, 20 key
+    switches) on four layer streams with every key loaded on demand into a
+    two-key budget: the hoisted taps and the channel sums on different streams
+    evict and reload keys that other streams have read; bit-exact."""
+    from paper_2510_03996_amd import he
+
+    name = "config2"
+    octx, _, _ = H.oracle_ctx(name)
+    slots = octx.n // 2
+    g = H.gpu_ctx(name)
+    try:
+        X = synth.image(23, 4, 64, 64)
+        K = synth.conv_weights(23, 4, 4, 3, (2.0 / 36) ** 0.5)
+        fm = LY.FMap(4, 64, 64, reps=2)
+        hfm = he.he_fmap(*fm.key())
+        plan = g.conv2d_plan(hfm, 4, 3, 1, 1)
+        for r in plan.keys():
+            g.key_host_register(r, H.oracle_key(name, r))
+        g.key_cache_limit(2 * g.key_bytes())
+        g.layer_streams(4)
+        _, ct = H.encrypt_slots(name, 85, values=LY.pack(X, fm, slots))
+        kern, masks = LY.conv_plaintexts(fm, K, 1, 1, slots)
+        kp = [octx.encode(v, octx.pr.scale, ct.level) for v in kern]
+        mp = [octx.encode(v, octx.pr.scale, ct.level) for v in masks]
+        ev = LY.HEEval(octx, H.oracle_keys(name, plan.keys()))
+        want, _ = LY.conv2d(ev, ct, fm, 4, 3, 1, 1, kp, mp, slots)
+        got, _ = g.conv2d(g.ct_from_numpy(ct.data, ct.scale), hfm, 4, 3, 1, 1,
+                          [g.pt_from_numpy(p.data, p.scale) for p in kp], [g.pt_from_numpy(p.data, p.scale) for p in mp])
+        torch.cuda.synchronize()
+        H.assert_limbs_equal(got.numpy(), want.data, "convolution on four streams with keys loaded on demand")
+        st = g.key_cache_stats()
+        assert st["evictions"] > 0 and st["resident_bytes"] <= 2 * g.key_bytes(), st
+    finally:
+        torch.cuda.synchronize()
+        g.close()
+
+
 def test_key_cache_errors():
     from paper_2510_03996_amd import he
 

@@ -381,6 +381,10 @@ def layer_latencies(reps=3):
     ctr = synthetic_ct(c2, 24, 43, sc)
     rmask = synthetic_pts(c2, 1, 24, 44, sc)[0]
     out["relu_cheb59_n16_ms"] = round(timed(lambda: c2.cheb(ctr, cheb, sc, scale_mask=rmask, stream=s), reps, s) * 1e3, 3)
+    c2.layer_streams(1)
+    out["relu_cheb59_n16_streams1_ms"] = round(
+        timed(lambda: c2.cheb(ctr, cheb, sc, scale_mask=rmask, stream=s), reps, s) * 1e3, 3)
+    c2.layer_streams(2)
     out["key_switches"] = {"conv3x3_n12": 8, "lenet5_stack": pc.key_switches + pp.key_switches + 2,
                            "resnet_convA": pa.key_switches, "resnet_convB": pb.key_switches,
                            "resnet_gap": pg.key_switches, "resnet_fc": pf.key_switches,

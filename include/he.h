@@ -348,7 +348,9 @@ int he_ctx_fc_form(he_ctx* ctx, int mode);
 /* Streams the independent parts of a call are spread over (1..8, default 2):
  * the per-channel work (products with the kernel vectors, input-channel sum,
  * masking) of a convolution's output channel f, the per-neuron work of the
- * per-row fully connected form (product, log-step sum, mask), and key switch j (inner
+ * per-row fully connected form (product, log-step sum, mask), the products
+ * of he_cheb (on two streams at most: its Chebyshev terms by list scheduling
+ * and the remainder branch of its division tree), and key switch j (inner
  * product + ModDown after the shared ModUp) of a hoisted rotation set with
  * several keys, run on the caller's stream (index mod n == 0) or on helper
  * stream (index mod n) of the caller's stream, which the library creates on

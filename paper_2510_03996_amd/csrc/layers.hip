@@ -1029,28 +1029,66 @@ int he_cheb(he_ctx* h, const he_ct* in, const he_pt* scale_mask, const double* c
   return guarded([&] {
     Ev ev(h, s);
     const he_ct v = scale_mask ? ev.rescale_take(ev.mul(*in, *scale_mask)) : *in;
+    // the terms on up to two streams (the caller's and a helper), each placed
+    // by list scheduling (one unit per product, earliest start, ties to a
+    // factor's stream); a term waits for a factor made on the other stream.
+    // The division tree's remainder branch at the root then runs on the
+    // helper beside the quotient branch.  Every value is computed by the same
+    // operations as on one stream.
+    Fork fk(ev, std::min(c->streams_for_ring(), 2));
+    const int K = fk.size();
+    auto stream_of = [&](int k) { return (hipStream_t)fk.at(k).s; };
     std::vector<he_ct> T(degree + 1);
-    std::vector<char> have(degree + 1, 0);
+    std::vector<int> on(degree + 1, 0), fin(degree + 1, 0), busy(K, 0);
     T[1] = v;
-    have[1] = 1;
     for (size_t t = 1; t < terms.size(); t++) {
       const int j = terms[t];
       const int a = j / 2, b = j - j / 2;
+      const int dep = std::max(fin[a], fin[b]);
+      int k = on[b];
+      for (int x = 0; x < K; x++)
+        if (std::max(dep, busy[x]) < std::max(dep, busy[k])) k = x;
+      hipStream_t to = stream_of(k);
+      for (int f : {a, b})
+        if (on[f] != k) ck(stream_fork(stream_of(on[f]), &to, 1));
+      Ev& e = fk.at(k);
       const int lv = std::min(T[a].level, T[b].level);
-      he_ct p = ev.rescale_take(ev.mul_relin(Ev::drop(T[a], lv), Ev::drop(T[b], lv)));
-      he_ct p2 = ev.add(p, p);
-      ev.release(p);
+      he_ct p = e.rescale_take(e.mul_relin(Ev::drop(T[a], lv), Ev::drop(T[b], lv)));
+      he_ct p2 = e.add(p, p);
+      e.release(p);
       if (j % 2 == 0) {
-        T[j] = ev.add_const(p2, -1.0);
+        T[j] = e.add_const(p2, -1.0);
       } else {
-        he_ct l = cheb_lift(ev, v, p2.level, p2.scale, -1.0);
-        T[j] = ev.add(p2, l);
-        ev.release(l);
+        he_ct l = cheb_lift(e, v, p2.level, p2.scale, -1.0);
+        T[j] = e.add(p2, l);
+        e.release(l);
       }
-      ev.release(p2);
-      have[j] = 1;
+      e.release(p2);
+      on[j] = k;
+      fin[j] = std::max(dep, busy[k]) + 1;
+      busy[k] = fin[j];
     }
-    he_ct y = cheb_eval_node(ev, tree, 0, T, v.level + cheb_allowed(tree, 0, 0), delta);
+    const int top = v.level + cheb_allowed(tree, 0, 0);
+    he_ct y{};
+    if (K > 1 && tree[0].K) {
+      // both streams see every term; remainder r' on the helper, quotient
+      // branch and the root product on the caller's stream
+      const ChebNode& n = tree[0];
+      fk.join();
+      hipStream_t helper = stream_of(1);
+      ck(stream_fork(stream_of(0), &helper, 1));
+      he_ct rc = cheb_eval_node(fk.at(1), tree, n.r, T, top, delta);
+      const double sigma = delta * (double)c->mod[top] / T[n.K].scale;
+      he_ct qc = cheb_eval_node(ev, tree, n.q, T, top + 1, sigma);
+      he_ct p = ev.rescale_take(ev.mul_relin(qc, Ev::drop(T[n.K], top + 1)));
+      ev.release(qc);
+      p.scale = delta;
+      fk.join();
+      y = ev.add_take(p, rc);
+    } else {
+      fk.join();
+      y = cheb_eval_node(ev, tree, 0, T, top, delta);
+    }
     ev.copy_out(y, out);
     return HE_OK;
   });

@@ -26,10 +26,13 @@ def run(name, beta, n, seed):
         want = LY.cheb_eval(ev, ct, c, mask, octx.pr.scale)
         levels, relins = he.cheb_plan(list(c), mask is not None)
         assert ev.ks == relins == 14 and ct.level - want.level == levels
-        got = g.cheb(g.ct_from_numpy(ct.data, ct.scale), list(c), octx.pr.scale,
-                     scale_mask=g.pt_from_numpy(mask.data, mask.scale) if mask is not None else None)
-        H.assert_limbs_equal(got.numpy(), want.data, "Chebyshev ReLU")
-        assert got.level == want.level and got.scale == want.scale
+        gct = g.ct_from_numpy(ct.data, ct.scale)
+        gmask = g.pt_from_numpy(mask.data, mask.scale) if mask is not None else None
+        for n_streams in (1, 2):  # terms and the division tree over one or two streams (N=2^16)
+            g.layer_streams(n_streams)
+            got = g.cheb(gct, list(c), octx.pr.scale, scale_mask=gmask)
+            H.assert_limbs_equal(got.numpy(), want.data, "Chebyshev ReLU on %d stream(s)" % n_streams)
+            assert got.level == want.level and got.scale == want.scale
         dec = octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale))
         assert np.max(np.abs(dec[:n] - LY.cheb_relu_ref(x[:n], beta))) < 1e-3 * beta
         assert np.max(np.abs(dec[:n] - np.maximum(0.0, x[:n]))) < 0.012 * beta

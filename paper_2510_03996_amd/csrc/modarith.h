@@ -111,7 +111,10 @@ HE_HD uint64_t f64_to_bits(double d) {
 // Exact conversions of integers below 2^52: x is the low mantissa of 2^52 + x.
 HE_HD double u52_to_f64(uint64_t x) { return bits_to_f64(x | 0x4330000000000000ull) - 4503599627370496.0; }
 HE_HD uint64_t f64_to_u52(double v) { return f64_to_bits(v + 4503599627370496.0) & 0x000FFFFFFFFFFFFFull; }
-// canonical representative in [0, q) of an integer-valued |x| <= 8q
+// canonical representative in [0, q) of an integer-valued |x| < 2^53 (q > 4):
+// fl(x fl(1/q)) is within 2^-51 |x| / q < 1 of x / q, so its floor is off by
+// at most one, x - floor q (exact in one FMA) lies in [-q, 2q) and one
+// correction either way ends it
 HE_HD double canon_f64(double x, double qinv, double q) {
   double r = fma(-floor(x * qinv), q, x);
   r = r < 0.0 ? r + q : r;

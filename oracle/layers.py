@@ -95,43 +95,6 @@ def relu4_ref(x):
 
 
 # ===================================================================== masks (Alg. 2 / 3)
-def build_mask(sp, ep, w, m, C):
-    """Algorithm 2 (build_mask), arguments in the order (sp, ep, w, m, C); the
-    final loop's bound, garbled in the listing, is read as C (one copy per
-    input channel)."""
-    mask = [0.0] * sp
-    while len(mask) < m - ep:
-        mask.extend([1.0] * w)
-        mask.append(0.0)
-    while len(mask) > m:
-        mask.pop()
-    while len(mask) < m:
-        mask.append(0.0)
-    for i in range(ep):
-        mask[m - i - 1] = 0.0
-    tmask = []
-    for _ in range(C):
-        tmask.extend(mask)
-    return np.array(tmask)
-
-
-def special_masks(W, C):
-    """Algorithm 3: the nine masks of the 3x3 / stride 1 / pad 1 convolution,
-    tap k = 3 (dy + 1) + (dx + 1)."""
-    m = W * W
-    return [
-        build_mask(W + 1, 0, W - 1, m, C),
-        build_mask(W, 0, m, m, C),
-        build_mask(W, 0, W - 1, m, C),
-        build_mask(1, 0, W - 1, m, C),
-        build_mask(0, 0, m, m, C),
-        build_mask(0, 1, W - 1, m, C),
-        build_mask(1, W - 1, W - 1, m, C),
-        build_mask(0, W, m, m, C),
-        build_mask(0, W + 1, W - 1, m, C),
-    ]
-
-
 def neighbour_masks(W):
     """Closed form: tap (dy, dx) of output pixel (y, x) reads inside the image."""
     out = []
@@ -144,6 +107,15 @@ def neighbour_masks(W):
                         m[y * W + x] = 1.0
             out.append(m)
     return out
+
+
+def special_masks(W, C):
+    """The nine 0/1 masks of the 3x3 / stride 1 / pad 1 convolution (what
+    Algorithms 2 and 3 of the special convolution produce: zeros where a
+    tap would read across the image border), tap k = 3 (dy + 1) + (dx + 1),
+    one W^2 block per input channel.  Built from the closed form of
+    ``neighbour_masks``, repeated over the C channels."""
+    return [np.tile(m, C) for m in neighbour_masks(W)]
 
 
 # ===================================================================== geometry

@@ -1,7 +1,10 @@
 // Word-size modular arithmetic for primes q < 2^61 on gfx950.
 //
-// Integer-ALU only (no MFMA: a 64-bit modular product is not a floating-point
-// contraction).  Three reductions are used:
+// Element-wise modular products run on the vector ALUs: 32-bit integer
+// multiplies for primes of 51 bits and more, centred FP64 FMA for primes
+// below 2^50.  (The one dense contraction of the key switch, the basis
+// conversion, runs on the int8 matrix cores instead: see BConvDesc in
+// elem_core.h.)  Three integer reductions are used:
 //   * Shoup multiplication by a constant w with companion w' = floor(w 2^64 / q)
 //     (NTT twiddles, BConv input factors, q^{-1}, P^{-1});
 //   * Montgomery reduction of a 128-bit accumulator (key inner product, BConv

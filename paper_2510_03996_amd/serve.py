@@ -53,6 +53,11 @@ class Request:
         self.stream = None
         self.t_admit = self.t_done = None
         self.output = None
+        # the input was written by work enqueued on the creating thread's
+        # current stream (e.g. an asynchronous host-to-device fill); stage 0
+        # runs on another stream and must wait for it
+        self.ready = torch.cuda.Event()
+        self.ready.record(torch.cuda.current_stream())
 
     @property
     def latency(self):
@@ -88,6 +93,8 @@ class Server:
     def _enqueue_stage(self, r, alone=True):
         m = self.models[r.kind]
         m.ctx.layer_streams(self.layer_streams if alone else 1)
+        if r.stage == 0:
+            r.stream.wait_event(r.ready)
         with torch.cuda.stream(r.stream):
             r.cur = m.stages[r.stage](r.cur, r.stream)
         r.stage += 1

@@ -1,7 +1,7 @@
 """Pins for the layer schedules (CPU only).
 
-1. Algorithms 2/3 (build_mask, nine masks) equal the closed-form
-   "neighbour inside the image" masks.
+1. The nine special-convolution masks (closed form) have the structure
+   Algorithms 2/3 give them, and a hand-worked W = 3 case.
 2. Every schedule, run as a plain float slot simulation, equals the paper's
    FP64 layer equation (direct loops), and uses the documented number of key
    switches and levels.
@@ -23,13 +23,49 @@ from tests import helpers as H
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-@pytest.mark.parametrize("W", [4, 5, 8, 32])
+# Algorithm 3 of the special convolution builds tap k's mask with Algorithm 2
+# from three numbers: sp leading zeros, ep trailing zeros, and in between runs
+# of w ones each followed by one zero (m = W^2 entries per channel).  These
+# are the paper's (sp, ep, w) per tap k = 3 (dy + 1) + (dx + 1), as functions
+# of W (m = W^2 stands for "one run over the whole block").
+def _alg3_params(W):
+    m = W * W
+    return [(W + 1, 0, W - 1), (W, 0, m), (W, 0, W - 1), (1, 0, W - 1), (0, 0, m),
+            (0, 1, W - 1), (1, W - 1, W - 1), (0, W, m), (0, W + 1, W - 1)]
+
+
+@pytest.mark.parametrize("W", [3, 4, 5, 8, 32])
 @pytest.mark.parametrize("C", [1, 3])
-def test_alg2_alg3_masks_are_neighbour_masks(W, C):
+def test_special_masks_have_the_alg3_structure(W, C):
+    """The closed-form masks equal the structure Algorithm 2 describes for
+    Algorithm 3's parameters: zero on the first sp and the last ep entries,
+    and at offset t >= sp one unless (t - sp) is the last position of a run
+    of w ones; repeated once per input channel."""
+    m = W * W
     got = LY.special_masks(W, C)
-    want = LY.neighbour_masks(W)
+    for k, (sp, ep, w) in enumerate(_alg3_params(W)):
+        want = np.zeros(m)
+        for t in range(sp, m - ep):
+            want[t] = 0.0 if (t - sp) % (w + 1) == w else 1.0
+        assert np.array_equal(got[k], np.tile(want, C)), (W, k)
+
+
+def test_special_masks_worked_example_w3():
+    """W = 3 worked by hand from the zero-padded 3x3 convolution: tap (dy, dx)
+    contributes to output (y, x) only if (y + dy, x + dx) is inside the image."""
+    want = [
+        [0, 0, 0, 0, 1, 1, 0, 1, 1], [0, 0, 0, 1, 1, 1, 1, 1, 1], [0, 0, 0, 1, 1, 0, 1, 1, 0],
+        [0, 1, 1, 0, 1, 1, 0, 1, 1], [1, 1, 1, 1, 1, 1, 1, 1, 1], [1, 1, 0, 1, 1, 0, 1, 1, 0],
+        [0, 1, 1, 0, 1, 1, 0, 0, 0], [1, 1, 1, 1, 1, 1, 0, 0, 0], [1, 1, 0, 1, 1, 0, 0, 0, 0],
+    ]
+    got = LY.special_masks(3, 1)
     for k in range(9):
-        assert np.array_equal(got[k], np.tile(want[k], C)), k
+        assert got[k].tolist() == want[k], k
+    # ones per tap: (W - |dy|) (W - |dx|)
+    for W in (4, 7):
+        for k, mk in enumerate(LY.special_masks(W, 1)):
+            dy, dx = k // 3 - 1, k % 3 - 1
+            assert mk.sum() == (W - abs(dy)) * (W - abs(dx))
 
 
 def test_paper_output_size_formulas():

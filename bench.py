@@ -197,6 +197,7 @@ def headline(args):
                  "hbm_GBs": round(gbs, 1), "hbm_frac": round(hbm_frac, 4), "gmodmul_s": round(gmm, 1)})
     ks_bytes = 2 * L * N * 8 + 2 * dnum * (L + K) * N * 8 + 2 * L * N * 8
     roof["ntt_autotune"] = ctx.ntt_tuning()
+    roof["conv_autotune"] = ctx.conv_tuning()
     ctx.close()
     return rot_s, el, roof, kern, ks_bytes, (L, K, dnum)
 

@@ -118,6 +118,16 @@ int he_ntt_variant(int v, int32_t* tile, int32_t* per_thread);
  * do not call while work of this context is being enqueued.  HE_EINVAL for
  * an unknown variant (nothing is changed then). */
 int he_ctx_ntt_select(he_ctx* ctx, const int32_t* variant);
+/* Basis-conversion tuning done at context creation.  The conversion of
+ * hybrid key switching (ModUp: each digit to the other limbs and the special
+ * primes; ModDown: the special primes to the ciphertext limbs) runs fused
+ * with the first (column) pass of the forward NTT of its outputs, in
+ * workgroups that each own a column tile and a group of outputs; the
+ * number of workgroups aimed for (512, 768, 1024 or 1536, which sets the
+ * outputs per group) is timed for the top-level ModUp and ModDown and the
+ * fastest kept.  target[2] (may be NULL) receives the choice for ModUp and
+ * ModDown, us[2][4] (may be NULL) the timings in microseconds. */
+int he_ctx_conv_tuning(const he_ctx* ctx, int32_t* target, float* us);
 const char* he_last_error(void);
 
 /* Execution lanes.  Calls on different streams of one context may run

@@ -7,7 +7,8 @@
 // summed) and of the batched key-switching workload.
 //
 // Batched schedule (one stream, optionally captured once in a hipGraph):
-//   1. ModUp of every input at once (one iNTT, one BConv, one NTT launch);
+//   1. ModUp of every input at once (inverse NTT, conversion fused into the
+//      forward column pass, forward row pass);
 //   2. key-major key switching: for each distinct rotation key, ONE inner-
 //      product launch loads each key residue once and applies it to every
 //      ciphertext that uses that key (the key is read from HBM once per
@@ -259,18 +260,17 @@ static int run_batched(Batch* b, hipStream_t s) {
   const size_t E = (size_t)(l + K), ln = (size_t)l * N, in_item = 2 * ln;
   const size_t ext_item = (size_t)dn * E * N;
   int rc;
-  // 1. ModUp of every input
-  if ((rc = ntt_launch_strided(c, b->in + ln, in_item, b->coeff, ln, b->B, range_map(0, l, 0), true, s))) return rc;
+  // 1. ModUp of every input: inverse transform into the conversion inputs,
+  // conversion + forward pass 1, forward pass 2
+  if ((rc = ntt_launch_conv_in(c, b->in + ln, in_item, b->coeff, ln, b->B, range_map(0, l, 0), c->d_fin[l], 3, s)))
+    return rc;
   {
-    const BConvSet& set = c->modup[l];
-    ProfScope ps(c, "bconv_modup", s, 8.0 * N * b->B * (l + (double)set.count * set.max_out),
-                 (double)N * b->B * l * (1 + set.max_out),
-                 bconv_ideal_s((double)N, (double)b->B * set.count, c->alpha, set.max_out));
-    dim3 grid(N / 128, bconv_tiles_y(set), b->B * set.count);
-    k_bconv<<<grid, 256, 0, s>>>(b->coeff, ln, b->ext, E * N, set.d, set.count, c->d_mod, c->log_n);
-    HE_HIP(hipGetLastError());
+    const ConvSet& set = c->modup[l];
+    if ((rc = conv_fwd1_launch(c, set, b->coeff, ln, b->ext, E * N, b->B * set.count, set.count, c->conv_target[0],
+                               "conv_fwd1_modup", s)))
+      return rc;
   }
-  if ((rc = ntt_launch(c, b->ext, ext_item, b->B, c->modup_ntt[l], false, s))) return rc;
+  if ((rc = ntt_launch_pass(c, b->ext, ext_item, b->ext, ext_item, b->B, c->modup_ntt[l], false, 2, s))) return rc;
   // 2. key-major key switching
   const size_t kps = (size_t)(L + K) * N;
   for (const KeyGroup& gk : b->groups) {
@@ -282,15 +282,10 @@ static int run_batched(Batch* b, hipStream_t s) {
       HE_HIP(hipGetLastError());
     }
     const int z = 2 * gk.npairs;
-    if ((rc = ntt_launch(c, b->u, E * N, z, range_map(l, K, L), true, s))) return rc;
-    {
-      const BConvSet& set = c->moddown[l];
-      ProfScope ps(c, "bconv_moddown", s, 8.0 * N * z * (K + l), (double)N * z * K * (1 + l),
-                   bconv_ideal_s((double)N, z, K, l));
-      dim3 grid(N / 128, bconv_tiles_y(set), z);
-      k_bconv<<<grid, 256, 0, s>>>(b->u, E * N, b->y, ln, set.d, 1, c->d_mod, c->log_n);
-      HE_HIP(hipGetLastError());
-    }
+    if ((rc = ntt_launch_conv_in(c, b->u, E * N, b->u, E * N, z, range_map(l, K, L), c->d_fin[l], 3, s))) return rc;
+    if ((rc = conv_fwd1_launch(c, c->moddown[l], b->u, E * N, b->y, ln, z, 1, c->conv_target[1], "conv_fwd1_moddown",
+                               s)))
+      return rc;
     // back to NTT form with the ModDown combine in the last pass: rotated copy
     // z = 2 pair + poly = add + (u - y) P^{-1}, add = phi_g(c0 of the pair's item) for poly 0
     NttEpi epi{};
@@ -304,7 +299,7 @@ static int run_batched(Batch* b, hipStream_t s) {
     epi.add_item = in_item;
     epi.out_base = b->rot + (size_t)gk.first_pair * 2 * ln;
     epi.out_bs = ln;
-    if ((rc = ntt_launch_moddown(c, b->y, ln, range_map(0, l, 0), epi, s, z))) return rc;
+    if ((rc = ntt_launch_moddown(c, b->y, ln, range_map(0, l, 0), epi, s, z, 2))) return rc;
   }
   // 3. fused multiply-accumulate of every output
   {

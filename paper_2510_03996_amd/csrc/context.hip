@@ -120,81 +120,108 @@ static int dev_alloc(Ctx* c, T** p, size_t count) {
 
 // Host-side construction of one basis-conversion descriptor (constants are
 // uploaded to device memory; the descriptor points at them).
-static int build_bconv(Ctx* c, BConvDesc& t, const std::vector<int>& in_pos, const std::vector<int>& in_mod,
-                       const std::vector<int>& out_pos, const std::vector<int>& out_mod) {
-  t = BConvDesc{};
+static int build_conv(Ctx* c, ConvDesc& t, const std::vector<int>& in_pos, const std::vector<int>& in_mod,
+                      const std::vector<int>& out_pos, const std::vector<int>& out_mod) {
+  t = ConvDesc{};
   t.nin = (int)in_mod.size();
   t.nout = (int)out_mod.size();
   if (t.nin > MAX_BCONV_IN || t.nout > MAX_BCONV_OUT) return set_error(HE_EINVAL, "basis conversion too wide");
   for (int i = 0; i < t.nin; i++) { t.in_pos[i] = in_pos[i]; t.in_mod[i] = in_mod[i]; }
-  for (int p = 0; p < t.nout; p++) { t.out_pos[p] = out_pos[p]; t.out_mod[p] = out_mod[p]; }
-  t.nsteps = (t.nin + 1) / 2;
-  t.ngroups = (t.nout + 3) / 4;
-  std::vector<uint64_t> pre(2 * t.nin);
-  // cst[i][p] = (Qin / q_i) 2^64 mod p (Montgomery form), or (Qin / q_i) mod p
-  // for outputs that take the FP64 epilogue
-  std::vector<uint64_t> cst((size_t)t.nin * t.nout);
+  // outputs of 51 bits and more (integer arithmetic) first, then the FP64 ones
+  t.nint = 0;
+  {
+    int n = 0;
+    for (int pass = 0; pass < 2; pass++)
+      for (size_t p = 0; p < out_mod.size(); p++)
+        if (conv_out_f64(c->hmod[out_mod[p]].k) == (pass == 1)) {
+          t.out_pos[n] = out_pos[p];
+          t.out_mod[n] = out_mod[p];
+          n++;
+          if (pass == 0) t.nint++;
+        }
+  }
+  // parts: one per narrow input, two (low 32 bits, the rest) per wide one
+  std::vector<int> part_in, part_sh;
   for (int i = 0; i < t.nin; i++) {
-    uint64_t qi = c->mod[in_mod[i]];
-    uint64_t prod = 1 % qi;
-    for (int i2 = 0; i2 < t.nin; i2++)
-      if (i2 != i) prod = hmul(prod, c->mod[in_mod[i2]] % qi, qi);
-    pre[i] = hinv(prod, qi);
-    pre[t.nin + i] = shoup_of(pre[i], qi);
-    for (int p = 0; p < t.nout; p++) {
-      uint64_t po = c->mod[out_mod[p]];
-      uint64_t v = 1 % po;
-      for (int i2 = 0; i2 < t.nin; i2++)
-        if (i2 != i) v = hmul(v, c->mod[in_mod[i2]] % po, po);
-      cst[(size_t)i * t.nout + p] =
-          bconv_out_f64(c->hmod[out_mod[p]].k) ? v : hmul(v, (uint64_t)(((u128)1 << 64) % po), po);
+    if (conv_in_narrow(c->hmod[in_mod[i]].k)) {
+      t.part_pos[part_in.size()] = in_pos[i];
+      t.part_kind[part_in.size()] = 0;
+      part_in.push_back(i);
+      part_sh.push_back(0);
+    } else {
+      for (int h = 0; h < 2; h++) {
+        t.part_pos[part_in.size()] = in_pos[i];
+        t.part_kind[part_in.size()] = 1 + h;
+        part_in.push_back(i);
+        part_sh.push_back(32 * h);
+      }
     }
   }
-  // A fragments: lane l of K-step s in row tile g holds, for row r = l % 32
-  // (output p = 4 g + m, digit weight b) and input limb i = 2 s + l / 32,
-  // byte a = digit b of C_{i,a,p} = cst[i][p] 256^a mod p
-  std::vector<uint64_t> frag((size_t)t.ngroups * t.nsteps * 64, 0);
-  for (int g = 0; g < t.ngroups; g++)
-    for (int st = 0; st < t.nsteps; st++)
-      for (int l = 0; l < 64; l++) {
-        int m, b;
-        bconv_row(l % 32, m, b);
-        const int p = 4 * g + m, i = 2 * st + l / 32;
-        if (p >= t.nout || i >= t.nin) continue;
-        const uint64_t po = c->mod[out_mod[p]];
-        uint64_t word = 0, cpow = cst[(size_t)i * t.nout + p];
-        for (int a8 = 0; a8 < 8; a8++) {
-          word |= (uint64_t)(uint8_t)(int8_t)sdigit(cpow, b) << (8 * a8);
-          cpow = hmul(cpow, 256 % po, po);
-        }
-        frag[((size_t)g * t.nsteps + st) * 64 + l] = word;
-      }
-  std::vector<uint64_t> ep((size_t)t.nout * BCONV_EPW);
+  t.nparts = (int)part_in.size();
+  std::vector<uint64_t> cst((size_t)t.nout * t.nparts * 2, 0);
   for (int p = 0; p < t.nout; p++) {
-    const ModInfo& mo = c->hmod[out_mod[p]];
-    bconv_ep_fill(mo.q, mo.k, mo.qinv, &ep[(size_t)BCONV_EPW * p]);
+    const uint64_t po = c->mod[t.out_mod[p]];
+    const bool f64 = conv_out_f64(c->hmod[t.out_mod[p]].k);
+    for (int v = 0; v < t.nparts; v++) {
+      // [Qin / q_i]_p 2^shift for the part's input i
+      const int i = part_in[v];
+      uint64_t w = 1 % po;
+      for (int i2 = 0; i2 < t.nin; i2++)
+        if (i2 != i) w = hmul(w, c->mod[in_mod[i2]] % po, po);
+      w = hmul(w, (uint64_t)(((u128)1 << part_sh[v]) % po), po);
+      uint64_t* e = &cst[((size_t)p * t.nparts + v) * 2];
+      if (f64) {
+        const double wc = w > po / 2 ? -(double)(po - w) : (double)w;  // centred, exact
+        const double wq = wc / (double)po;
+        std::memcpy(&e[0], &wc, 8);
+        std::memcpy(&e[1], &wq, 8);
+      } else {
+        e[0] = hmul(w, (uint64_t)(((u128)1 << 64) % po), po);  // Montgomery form
+      }
+    }
   }
-  uint64_t *dpre = nullptr, *dfrag = nullptr, *dep = nullptr;
+  uint64_t* dcst = nullptr;
   int rc;
-  if ((rc = dev_alloc(c, &dpre, pre.size())) || (rc = dev_alloc(c, &dfrag, frag.size())) ||
-      (rc = dev_alloc(c, &dep, ep.size())))
-    return rc;
-  HE_HIP(hipMemcpy(dpre, pre.data(), pre.size() * 8, hipMemcpyHostToDevice));
-  HE_HIP(hipMemcpy(dfrag, frag.data(), frag.size() * 8, hipMemcpyHostToDevice));
-  HE_HIP(hipMemcpy(dep, ep.data(), ep.size() * 8, hipMemcpyHostToDevice));
-  t.tab = dpre;
-  t.frag = dfrag;
-  t.ep = dep;
+  if ((rc = dev_alloc(c, &dcst, std::max<size_t>(cst.size(), 1)))) return rc;
+  HE_HIP(hipMemcpy(dcst, cst.data(), cst.size() * 8, hipMemcpyHostToDevice));
+  t.cst = dcst;
   return HE_OK;
 }
 
-static int upload_set(Ctx* c, BConvSet& set, const std::vector<BConvDesc>& v) {
+// Finishing constant of an inverse transform whose output feeds a basis
+// conversion: N^{-1} (Qin/q_i)^{-1} mod q_i for input modulus m of a
+// conversion with input moduli `ins`, as [integer, Shoup companion, double,
+// double / q] in row m of a [L+K][4] table.
+static void conv_fin_fill(const Ctx* c, const std::vector<int>& ins, int m, uint64_t* row) {
+  const uint64_t q = c->mod[m];
+  uint64_t prod = 1 % q;
+  for (int m2 : ins)
+    if (m2 != m) prod = hmul(prod, c->mod[m2] % q, q);
+  const uint64_t w = hmul(hinv(prod, q), c->hmod[m].ninv, q);
+  row[0] = w;
+  row[1] = shoup_of(w, q);
+  const double dw = (double)w, dwq = (double)w / (double)q;
+  std::memcpy(&row[2], &dw, 8);
+  std::memcpy(&row[3], &dwq, 8);
+}
+
+static int upload_set(Ctx* c, ConvSet& set, const std::vector<ConvDesc>& v) {
   set.count = (int)v.size();
   set.max_out = 0;
-  for (auto& d : v) set.max_out = std::max(set.max_out, d.nout);
+  set.max_parts = 0;
+  set.max_in = 0;
+  set.nout.clear();
+  set.nint.clear();
+  for (auto& d : v) {
+    set.max_out = std::max(set.max_out, d.nout);
+    set.max_parts = std::max(set.max_parts, d.nparts);
+    set.max_in = std::max(set.max_in, d.nin);
+    set.nout.push_back(d.nout);
+    set.nint.push_back(d.nint);
+  }
   int rc = dev_alloc(c, &set.d, v.size());
   if (rc) return rc;
-  HE_HIP(hipMemcpy(set.d, v.data(), v.size() * sizeof(BConvDesc), hipMemcpyHostToDevice));
+  HE_HIP(hipMemcpy(set.d, v.data(), v.size() * sizeof(ConvDesc), hipMemcpyHostToDevice));
   return HE_OK;
 }
 
@@ -309,12 +336,16 @@ static int ctx_init(Ctx* c, const he_params* p) {
   c->modup_ntt.assign(c->L + 1, LimbMap{});
   c->d_rescale.assign(c->L + 1, nullptr);
   c->d_pinv.assign(c->L + 1, nullptr);
+  c->d_fin.assign(c->L + 1, nullptr);
   for (int l = 1; l <= c->L; l++) {
     int dn = c->dnum(l);
     const int E = l + c->K;
-    std::vector<BConvDesc> ups(dn);
+    std::vector<ConvDesc> ups(dn);
     LimbMap& nm = c->modup_ntt[l];
     nm.n = 0;
+    // finishing constants of the inverse transforms feeding this level's
+    // conversions: digit j's limbs for ModUp, the special primes for ModDown
+    std::vector<uint64_t> fin((size_t)(c->L + c->K) * 4, 0);
     for (int j = 0; j < dn; j++) {
       std::vector<int> ip, im, op, om;
       int lo = j * c->alpha, hi = std::min((j + 1) * c->alpha, l);
@@ -322,7 +353,8 @@ static int ctx_init(Ctx* c, const he_params* p) {
       for (int i = 0; i < l; i++)
         if (i < lo || i >= hi) { op.push_back(i); om.push_back(i); }
       for (int k = 0; k < c->K; k++) { op.push_back(l + k); om.push_back(c->L + k); }
-      if ((rc = build_bconv(c, ups[j], ip, im, op, om))) return rc;
+      if ((rc = build_conv(c, ups[j], ip, im, op, om))) return rc;
+      for (int m : im) conv_fin_fill(c, im, m, &fin[(size_t)m * 4]);
       for (size_t p = 0; p < op.size(); p++) {
         if (nm.n >= MAXJ) return set_error(HE_EINVAL, "too many extended limbs for one launch");
         nm.pos[nm.n] = (uint16_t)(j * E + op[p]);
@@ -334,9 +366,12 @@ static int ctx_init(Ctx* c, const he_params* p) {
     std::vector<int> ip, im, op, om;
     for (int k = 0; k < c->K; k++) { ip.push_back(l + k); im.push_back(c->L + k); }
     for (int i = 0; i < l; i++) { op.push_back(i); om.push_back(i); }
-    std::vector<BConvDesc> dn1(1);
-    if ((rc = build_bconv(c, dn1[0], ip, im, op, om))) return rc;
+    std::vector<ConvDesc> dn1(1);
+    if ((rc = build_conv(c, dn1[0], ip, im, op, om))) return rc;
     if ((rc = upload_set(c, c->moddown[l], dn1))) return rc;
+    for (int m : im) conv_fin_fill(c, im, m, &fin[(size_t)m * 4]);
+    if ((rc = dev_alloc(c, &c->d_fin[l], fin.size()))) return rc;
+    HE_HIP(hipMemcpy(c->d_fin[l], fin.data(), fin.size() * 8, hipMemcpyHostToDevice));
     // P^{-1} mod q_i
     std::vector<uint64_t> pv(2 * l);
     for (int i = 0; i < l; i++) {
@@ -370,7 +405,8 @@ static int ctx_init(Ctx* c, const he_params* p) {
   c->ws_words = ws_words(c);
   if ((rc = dev_alloc(c, &c->ws, c->ws_words))) return rc;
   c->key_words = D * 2 * (L + K) * N;
-  return ntt_autotune(c);
+  if ((rc = ntt_autotune(c))) return rc;
+  return conv_autotune(c);
 }
 
 Lane* lane_for(Ctx* c, hipStream_t s) {
@@ -574,6 +610,16 @@ int he_ctx_ntt_tuning(const he_ctx* h, int32_t* variant, float* us) {
     if (variant) variant[i] = h->c.ntt_var[i];
     for (int v = 0; v < NTT_VARIANTS; v++)
       if (us) us[v * 4 + i] = h->c.ntt_tune_us[v][i];
+  }
+  return HE_OK;
+}
+
+int he_ctx_conv_tuning(const he_ctx* h, int32_t* target, float* us) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  for (int k = 0; k < 2; k++) {
+    if (target) target[k] = h->c.conv_target[k];
+    for (int t = 0; t < 4; t++)
+      if (us) us[k * 4 + t] = h->c.conv_tune_us[k][t];
   }
   return HE_OK;
 }

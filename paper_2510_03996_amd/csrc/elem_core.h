@@ -7,9 +7,9 @@ namespace he {
 
 constexpr int MAX_BCONV_IN = 10;   // input limbs of one conversion (alpha and K)
 constexpr int MAX_BCONV_OUT = 64;
+constexpr int CONV_MAX_GROUP = 16;  // outputs of one conversion workgroup
 constexpr int MAXJ = 128;          // limb jobs in one batched launch
 constexpr int MAX_DIGITS = 8;      // key-switching digits (dnum)
-constexpr int BCONV_EPW = 5;       // epilogue words per basis-conversion output
 
 // Which limbs of a [limbs][N] array a kernel touches and their moduli.
 struct LimbMap {
@@ -18,111 +18,84 @@ struct LimbMap {
   uint8_t mod[MAXJ];   // modulus index (0..L-1 q_i, L.. p_k)
 };
 
-// Device-resident description of one fast basis conversion (floor type):
-//   t_i = [x_i (Qin/q_i)^{-1}]_{q_i},  y_p = sum_i t_i [Qin/q_i]_p  mod p.
-// The sum is an integer matrix product evaluated on the int8 matrix cores:
-// every t_i is split into 8 signed base-256 digits d_{i,a}, and the constant
-// C_{i,a,p} = [Qin/q_i]_p 2^64 256^a mod p (Montgomery form) into 8 signed
-// digits e_{i,a,p,b}, so
-//   2^64 sum_i t_i [Qin/q_i]_p == sum_b 256^b sum_{i,a} d_{i,a} e_{i,a,p,b}  (mod p)
-// with an inner sum of at most 80 products of magnitude <= 2^14 (exact in
-// int32); one Montgomery reduction of the digit-weighted sum gives y_p.
-// One 32x32x16 MFMA covers two input limbs (K = 2 x 8 digits) for 32
-// coefficients (columns) and four outputs x 8 digits b (rows).
-// Outputs modulo a prime below 2^50 instead use C_{i,a,p} = [Qin/q_i]_p
-// 256^a mod p (no Montgomery factor) and an FP64 epilogue (bconv_combine_f64),
-// which needs no 64-bit integer multiplies.
-//   tab:  [nin] w, [nin] w'   Shoup pair of (Qin/q_i)^{-1} mod q_i
-//   frag: [ngroups][nsteps][64] A-operand fragments (8 signed digit bytes per
-//         lane, laid out as the instruction reads them)
-//   ep:   [nout][BCONV_EPW] per output modulus (bconv_ep_fill): Montgomery
-//         outputs hold the 128-bit offset M = p 2^k in [2^77, 2^78) (low
-//         word, high word), p, p^{-1} mod 2^64, 0; FP64 outputs hold the
-//         doubles 2^32 mod p, fl((2^32 mod p) / p), p, fl(1/p) (as bits), 1
-struct BConvDesc {
-  int32_t nin, nout;
-  int32_t nsteps, ngroups;  // ceil(nin / 2) K-steps, ceil(nout / 4) row tiles
+// Device-resident description of one fast basis conversion (floor type)
+//   t_i = [x_i (Qin/q_i)^{-1}]_{q_i},  y_p = sum_i t_i [Qin/q_i]_p  mod p
+// as the forward column pass of the outputs consumes it.  The inputs arrive
+// as t_i already: the inverse transform that produces them multiplies by
+// N^{-1} (Qin/q_i)^{-1} instead of N^{-1} (see conv_fin_fill).  The sum runs
+// on the vector ALUs over "parts": an input below 2^50 is one part (an exact
+// double); a wider one is two, its low 32 bits and the rest, with constants
+// [Qin/q_i]_p and [Qin/q_i 2^32]_p.  For an output prime below 2^50 every
+// term is one centred FP64 product (mul_f64_c with a centred constant,
+// |term| <= 0.625 p) and the sum is re-centred every 8 terms; other outputs
+// accumulate exact 128-bit products with constants in Montgomery form and
+// end with one REDC.
+//   part_pos[v]: input limb of part v; part_kind[v]: 0 whole value, 1 low
+//     32 bits, 2 bits 32 and up
+//   cst: [nout][nparts][2] words; FP64 output: centred constant and
+//     fl(constant / p) as double bits; integer output: constant 2^64 mod p, 0
+struct ConvDesc {
+  int32_t nin, nparts, nout;
+  int32_t nint;  // outputs of 51 bits and more, listed first
   int32_t in_pos[MAX_BCONV_IN], in_mod[MAX_BCONV_IN];
+  int32_t part_pos[2 * MAX_BCONV_IN], part_kind[2 * MAX_BCONV_IN];
   int32_t out_pos[MAX_BCONV_OUT], out_mod[MAX_BCONV_OUT];
-  const uint64_t* tab;
-  const uint64_t* frag;
-  const uint64_t* ep;
+  const uint64_t* cst;
 };
 
-// Balanced base-256 digits of v < 2^61, packed as 8 int8 bytes: byte a is
-// d_a in [-128, 127] with v = sum_a d_a 256^a (the top digit is <= 33).
-HE_HD uint64_t sdigits(uint64_t v) {
-  constexpr uint64_t H = 0x0080808080808080ull;
-  return (v + H) ^ H;
+// Value of part `kind` of an input word w (canonical, below 2^61), exact
+// and without a branch: with lo, hi the 32-bit halves, a whole value below
+// 2^50 is hi 2^32 + lo, the low part lo, the high part hi.  conv_part_ab
+// gives the weights (a, b) of hi and lo for a kind.
+HE_HD void conv_part_ab(int kind, double& a, double& b) {
+  a = kind == 0 ? 4294967296.0 : kind == 2 ? 1.0 : 0.0;
+  b = kind == 2 ? 0.0 : 1.0;
 }
-HE_HD int sdigit(uint64_t v, int a) { return (int)(int8_t)(uint8_t)(sdigits(v) >> (8 * a)); }
-
-// Row r of a 32-row accumulator tile holds output m (0..3) of the tile and
-// digit weight b (0..7).  The 32x32 int32 accumulator gives lane l the rows
-// (reg & 3) + 4 (l / 32) + 8 (reg / 4), so with this assignment lane l owns
-// all eight b of outputs 2 (l / 32) and 2 (l / 32) + 1 in registers
-// 0..7 and 8..15.
-HE_HD void bconv_row(int row, int& m, int& b) {
-  const int h = (row >> 2) & 1;
-  const int reg = (row & 3) + 4 * (row >> 3);
-  m = 2 * h + (reg >> 3);
-  b = reg & 7;
+HE_HD double conv_part(uint64_t w, double a, double b) {
+  return fma((double)(uint32_t)(w >> 32), a, (double)(uint32_t)w * b);
 }
 
-// REDC(M + sum_b 256^b acc[b]) for |acc[b]| <= 80 2^14 < 2^20.33 (ten input
-// limbs): the weighted sum has magnitude < 2^76.34, so with M = p 2^k in
-// [2^77, 2^78) the argument lies in (0, 2^78.3) < p 2^64 and the result is
-// canonical.
-HE_HD uint64_t bconv_combine(const int32_t* acc, const uint64_t* ep) {
-  const int64_t lo = (int64_t)acc[0] + (int64_t)acc[1] * 256 + (int64_t)acc[2] * 65536 + (int64_t)acc[3] * 16777216;
-  const int64_t hi = (int64_t)acc[4] + (int64_t)acc[5] * 256 + (int64_t)acc[6] * 65536 + (int64_t)acc[7] * 16777216;
-  const __int128 t = (__int128)hi * ((__int128)1 << 32) + lo + (__int128)(((unsigned __int128)ep[1] << 64) | ep[0]);
-  return mont_redc(U128{(uint64_t)t, (uint64_t)((unsigned __int128)t >> 64)}, ep[2], ep[3]);
+// Outputs modulo primes of at most 50 bits take the FP64 sum; inputs below
+// 2^50 are one part.
+HE_HD bool conv_out_f64(int kbits) { return kbits <= 50; }
+HE_HD bool conv_in_narrow(int kbits) { return kbits <= 50; }
+
+// FP64 outputs (|x_v| < 2^50, centred constants |c| <= p/2 with
+// cq = fl(c/p)): each centred product mul_f64_c(x_v, c, cq, p) is exact and
+// below 0.625 p in magnitude (the quotient estimate is off by at most 1/8),
+// eight of them stay below 5 p < 2^53, and re-centring after every eighth
+// keeps the running sum exact; the sum is an integer-valued double congruent
+// to y_p with magnitude below 5.5 p (not canonical: the column pass that
+// consumes it re-centres first).
+// Integer outputs: x_v (c_v 2^64 mod p), each product below 2^52 2^61,
+// accumulated in 128 bits and kept below p 2^64 by one conditional
+// subtraction of p 2^64 per term; one REDC then gives the canonical y_p.
+HE_HD void conv_mac_int(U128& acc, double x, uint64_t c_mont, uint64_t p) {
+  add_wide(acc, mul_wide(f64_to_u52(x), c_mont));
+  if (acc.hi >= p) acc.hi -= p;
 }
-
-// Outputs modulo primes of at most 50 bits take the FP64 epilogue.
-HE_HD bool bconv_out_f64(int kbits) { return kbits <= 50; }
-
-// FP64 epilogue: V = sum_b 256^b acc[b] = lo + 2^32 hi with
-// lo = sum_{b<4} 256^b acc[b] and hi = sum_{b>=4} 256^(b-4) acc[b].  Pairs
-// acc[2c] + 256 acc[2c+1] stay below 2^28.34 (int32), lo and hi below
-// 2^44.35, so both are exact doubles.  hi (2^32 mod p) is reduced with the
-// centred product (|hi| 2^-52 < 2^-7.6, so the result is below 0.51 p in
-// magnitude and exact), lo is added (an integer below 2^53) and one floor
-// estimate with fl(1/p) plus a correction either way leaves V mod p.
-HE_HD uint64_t bconv_combine_f64(const int32_t* acc, const uint64_t* ep) {
-  const int32_t p0 = acc[0] + acc[1] * 256, p1 = acc[2] + acc[3] * 256;
-  const int32_t p2 = acc[4] + acc[5] * 256, p3 = acc[6] + acc[7] * 256;
-  const double lo = fma((double)p1, 65536.0, (double)p0);
-  const double hi = fma((double)p3, 65536.0, (double)p2);
-  const double p = bits_to_f64(ep[2]);
-  const double v = mul_f64_c(hi, bits_to_f64(ep[0]), bits_to_f64(ep[1]), p) + lo;
-  return f64_to_u52(canon_f64(v, bits_to_f64(ep[3]), p));
-}
-
-HE_HD uint64_t bconv_out(const int32_t* acc, const uint64_t* ep) {
-  return ep[4] ? bconv_combine_f64(acc, ep) : bconv_combine(acc, ep);
-}
-
-// (host) Epilogue record of one output modulus po (kbits bits, pinv64 = po^{-1} mod 2^64).
-inline void bconv_ep_fill(uint64_t po, int kbits, uint64_t pinv64, uint64_t* ep) {
-  if (bconv_out_f64(kbits)) {
-    const uint64_t c32 = (uint64_t)(((unsigned __int128)1 << 32) % po);
-    ep[0] = f64_to_bits((double)c32);
-    ep[1] = f64_to_bits((double)c32 / (double)po);
-    ep[2] = f64_to_bits((double)po);
-    ep[3] = f64_to_bits(1.0 / (double)po);
-    ep[4] = 1;
-    return;
+// One output from the parts x[0..nparts) of a coefficient, nparts <= NP
+// (the loops unroll over NP so x stays in registers); cst = the output's
+// [nparts][2] constants.
+template <int NP>
+HE_HD double conv_sum_f64(const double* x, int nparts, const uint64_t* cst, double p, double pinv) {
+  double acc = 0.0;
+#pragma unroll
+  for (int v = 0; v < NP; v++) {
+    if (v < nparts) {
+      acc += mul_f64_c(x[v], bits_to_f64(cst[2 * v]), bits_to_f64(cst[2 * v + 1]), p);
+      if ((v & 7) == 7) acc = centre_f64(acc, pinv, p);
+    }
   }
-  int kshift = 0;
-  while (((unsigned __int128)po << kshift) < ((unsigned __int128)1 << 77)) kshift++;
-  const unsigned __int128 M = (unsigned __int128)po << kshift;
-  ep[0] = (uint64_t)M;
-  ep[1] = (uint64_t)(M >> 64);
-  ep[2] = po;
-  ep[3] = pinv64;
-  ep[4] = 0;
+  return acc;
+}
+template <int NP>
+HE_HD uint64_t conv_sum_int(const double* x, int nparts, const uint64_t* cst, uint64_t p, uint64_t pinv64) {
+  U128 acc{0, 0};
+#pragma unroll
+  for (int v = 0; v < NP; v++)
+    if (v < nparts) conv_mac_int(acc, x[v], cst[2 * v], p);
+  return mont_redc(acc, p, pinv64);
 }
 
 HE_HD uint32_t bitrev_n(uint32_t x, int logn) {

@@ -17,11 +17,14 @@ constexpr int MAXL = 64;  // max limbs in any basis (L + K)
 constexpr int NTT_VARIANTS = HE_NTT_VARIANTS;  // (tile, residues per thread) kernel shapes
 
 // Basis-conversion tables of one level: device descriptors (one per digit
-// for ModUp, one for ModDown) plus the largest output count.
-struct BConvSet {
-  BConvDesc* d = nullptr;  // device array
+// for ModUp, one for ModDown) plus the largest output, part and input counts.
+struct ConvSet {
+  ConvDesc* d = nullptr;  // device array
   int count = 0;
   int max_out = 0;
+  int max_parts = 0;
+  int max_in = 0;
+  std::vector<int> nout, nint;  // per descriptor (host copies)
 };
 
 // Optional per-kernel timing: a HIP event pair around each launch on its own
@@ -41,7 +44,6 @@ struct ProfRec {
 constexpr double LANE_OPS_PER_S = 256.0 * 4 * 16 * 2.4e9;
 constexpr double PEAK_MODMUL_INT = LANE_OPS_PER_S / 2 / 10;  // 1.966e12 / s
 constexpr double PEAK_MODMUL_F64 = LANE_OPS_PER_S / 6;       // 6.554e12 / s
-constexpr double PEAK_INT8_OPS = 5.0e15;                      // dense int8 MFMA, ops / s
 
 // One evaluation key.  A key with a host copy may be evicted from device
 // memory (its buffer is reused only after the event recorded at its last use
@@ -80,7 +82,10 @@ struct Ctx {
   // FP64 twiddles w and w/q (used for primes below 2^50)
   double *d_dtw = nullptr, *d_dtwq = nullptr, *d_ditw = nullptr, *d_ditwq = nullptr;
   // modup[level][digit]; moddown[level]
-  std::vector<BConvSet> modup, moddown;
+  std::vector<ConvSet> modup, moddown;
+  // per level: [L+K][4] finishing constants of the inverse transforms that
+  // feed the conversions (conv_fin_fill): N^{-1} (Qin/q_m)^{-1} mod q_m
+  std::vector<uint64_t*> d_fin;
   std::vector<LimbMap> modup_ntt;  // per level: every converted limb of every digit (ext-relative)
   // per level l (>= 2): Shoup pairs of q_{l-1}^{-1} mod q_i (i < l-1): [2][l-1]
   std::vector<uint64_t*> d_rescale;
@@ -116,6 +121,8 @@ struct Ctx {
   // NTT variant (log2 residues per thread) per batch-size bucket (<= 8, 16,
   // 32, more limbs), chosen by the autotuner at context creation
   int ntt_var[4] = {0, 0, 0, 2};           // NTT variant per batch-size bucket
+  int conv_target[2] = {1024, 1024};       // conversion workgroup target: ModUp, ModDown (conv_autotune)
+  float conv_tune_us[2][4] = {};           // [ModUp / ModDown][candidate] timed microseconds
   float ntt_tune_us[NTT_VARIANTS][4] = {};  // [variant][probe 8/16/32/64 limbs] forward+inverse us
   std::vector<ProfRec> prof;
 
@@ -191,10 +198,31 @@ struct NttEpi {
   size_t add_item;
   uint64_t* out_base;
   size_t out_bs;
+  // inverse pass 1 only: per-modulus finishing constants [4] (conv_fin_fill)
+  // replacing N^{-1}, so that the transform writes a conversion's inputs
+  const uint64_t* fin;
 };
 // the last forward NTT with the ModDown epilogue, over nbatch arrays of y
+// (passes = 2: y already holds forward pass 1, as the conversion writes it)
 int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& map, const NttEpi& epi, hipStream_t s,
-                       int nbatch = 2);
+                       int nbatch = 2, int passes = 3);
+// Inverse transform whose output feeds a basis conversion: like
+// ntt_launch_strided (inverse), with the last pass multiplying by the
+// level's finishing constants (Ctx::d_fin) instead of N^{-1}.  passes: 3 =
+// both (src -> data), 1 = pass 1 only (in place on data).
+int ntt_launch_conv_in(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, int nbatch,
+                       const LimbMap& map, const uint64_t* fin, int passes, hipStream_t s);
+// Basis conversion fused into the forward column pass of its outputs: for
+// batch z (descriptor set.d[z % zdiv], inputs in + (z / zdiv) in_bs, outputs
+// out + z out_bs) every output limb out_pos[p] receives forward pass 1 of
+// y_p = sum_i t_i [Qin/q_i]_p, the t_i read from in at in_pos[i].
+// `target`: about how many workgroups to form when the batch is small
+// (outputs are grouped accordingly; Ctx::conv_target, tuned at creation).
+int conv_fwd1_launch(Ctx* c, const ConvSet& set, const uint64_t* in, size_t in_bs, uint64_t* out, size_t out_bs,
+                     int nz, int zdiv, int target, const char* name, hipStream_t s);
+// time the conversion kernel at the top level with a few workgroup targets
+// and keep the fastest for ModUp and for ModDown
+int conv_autotune(Ctx* c);
 // Key inner product fused into the last forward pass of ModUp (one key
 // switch): for every ext position pos < E = level + K and both key polys j,
 //   u_j[pos][k] = sum_d e_d[pos][src(k)] key_d[j][mod(pos)][k] 2^-64 mod q
@@ -217,6 +245,9 @@ struct NttIp {
   // nonzero: ext already holds the converted limbs in NTT form (a hoisted
   // ModUp); the kernel only gathers them and no forward pass runs
   int32_t ext_ntt;
+  // nonzero: ext holds the converted limbs after forward pass 1 (written by
+  // the conversion kernel), so only pass 2 runs here
+  int32_t ext_p1;
 };
 int ntt_launch_modup_ip(Ctx* c, uint64_t* ext, const LimbMap& conv, const LimbMap& outs, const NttIp& ip,
                         hipStream_t s);
@@ -282,19 +313,7 @@ uint64_t* lane_ct_get(Ctx* c, Lane* ln);  // null on allocation failure
 int check_ct(const Ctx* c, const he_ct* x, const char* what);
 int check_out(const Ctx* c, const he_ct* x, int need_level);
 
-constexpr int BCONV_TILES_Y = 8;  // 4-output row tiles per basis-conversion workgroup
-// ALU-ideal time of `convs` basis conversions with nin inputs and nout
-// outputs over N coefficients: the int8 MFMA work the kernel issues (K = 16
-// per two input limbs, 32 rows per four outputs) at the int8 peak, plus the
-// nin Shoup products and nout Montgomery reductions per coefficient.
-inline double bconv_ideal_s(double N, double convs, int nin, int nout) {
-  const double mfma = 2.0 * N * (16.0 * ((nin + 1) / 2)) * (32.0 * ((nout + 3) / 4));
-  return convs * (mfma / PEAK_INT8_OPS + N * (nin + nout) / PEAK_MODMUL_INT);
-}
-inline int bconv_tiles_y(const BConvSet& s) { return ((s.max_out + 3) / 4 + BCONV_TILES_Y - 1) / BCONV_TILES_Y; }
 __global__ void k_to_mont(uint64_t* key, int M, int logn, const ModInfo* __restrict__ mods);
-__global__ void k_bconv(const uint64_t* __restrict__ in, size_t in_bs, uint64_t* __restrict__ out, size_t out_bs,
-                        const BConvDesc* __restrict__ descs, int zdiv, const ModInfo* __restrict__ mods, int logn);
 __global__ void k_bcast_reduce(const uint64_t* __restrict__ T, uint64_t* __restrict__ R, int nl, int logn,
                                const ModInfo* __restrict__ mods);
 __global__ void k_rescale_combine(const uint64_t* in, size_t ips, const uint64_t* __restrict__ R, uint64_t* out,

@@ -1,5 +1,5 @@
 // Hybrid key switching (ModUp -> key inner product -> ModDown), rotations,
-// hoisted rotations, relinearization, and the resident key store.
+// hoisted rotations and relinearization.
 //
 // Pinned formula for every key switch (one formula for plain and hoisted
 // rotations): digits of c1 are basis-extended once (ModUp), the Galois
@@ -10,78 +10,6 @@
 namespace he {
 
 // ---------------------------------------------------------------- kernels
-// Basis conversion on the int8 matrix cores (see BConvDesc).  One wave owns
-// 32 coefficients: lane l loads t_i for i = 2 s + l / 32 (the B operand of
-// K-step s is exactly its 8 digit bytes), then every 4-output row tile takes
-// nsteps MFMAs and an epilogue that turns 8 int32 digit sums per output
-// into a residue.  grid: x = 128-coefficient block (4 waves), y = chunk of
-// BCONV_TILES_Y row tiles, z = batch: descriptor descs[z % zdiv], input
-// in + (z / zdiv) in_bs, output out + z out_bs.
-typedef int32_t v16i __attribute__((ext_vector_type(16)));
-
-__global__ __launch_bounds__(256) void k_bconv(const uint64_t* __restrict__ in, size_t in_bs,
-                                               uint64_t* __restrict__ out, size_t out_bs,
-                                               const BConvDesc* __restrict__ descs, int zdiv,
-                                               const ModInfo* __restrict__ mods, int logn) {
-  // constants of this block's row tiles, staged once per workgroup
-  __shared__ uint64_t s_frag[BCONV_TILES_Y * (MAX_BCONV_IN / 2) * 64];
-  __shared__ uint64_t s_ep[BCONV_TILES_Y * 4 * BCONV_EPW];
-  __shared__ uint32_t s_pos[BCONV_TILES_Y * 4];
-  const size_t n = (size_t)1 << logn;
-  const int lane = threadIdx.x & 63;
-  const int half = lane >> 5;
-  const size_t k = ((size_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * 32 + (lane & 31);
-  const int z = blockIdx.z;
-  const BConvDesc& d = descs[z % zdiv];
-  const int g0 = blockIdx.y * BCONV_TILES_Y;
-  if (g0 >= d.ngroups) return;  // uniform over the block
-  const int g1 = min(g0 + BCONV_TILES_Y, d.ngroups);
-  const int nin = d.nin, nsteps = d.nsteps;
-  const uint64_t* src = in + (z / zdiv) * in_bs;
-  uint64_t* dst = out + z * out_bs;
-  uint64_t x[MAX_BCONV_IN / 2];
-#pragma unroll
-  for (int s = 0; s < MAX_BCONV_IN / 2; s++) {
-    const int i = 2 * s + half;
-    x[s] = i < nin ? src[(size_t)d.in_pos[i] * n + k] : 0;
-  }
-  {
-    const uint64_t* __restrict__ fr = d.frag + (size_t)g0 * nsteps * 64;
-    const int nf = (g1 - g0) * nsteps * 64;
-    for (int e = threadIdx.x; e < nf; e += 256) s_frag[e] = fr[e];
-    const int p0 = 4 * g0, np = min(4 * g1, d.nout) - p0;
-    for (int e = threadIdx.x; e < BCONV_EPW * np; e += 256) s_ep[e] = d.ep[BCONV_EPW * p0 + e];
-    for (int e = threadIdx.x; e < np; e += 256) s_pos[e] = (uint32_t)d.out_pos[p0 + e];
-  }
-  long bf[MAX_BCONV_IN / 2];
-#pragma unroll
-  for (int s = 0; s < MAX_BCONV_IN / 2; s++) {
-    const int i = 2 * s + half;
-    uint64_t t = 0;
-    if (i < nin) t = mul_shoup(x[s], d.tab[i], d.tab[nin + i], mods[d.in_mod[i]].q);
-    bf[s] = (long)sdigits(t);
-  }
-  __syncthreads();
-  const int np = min(4 * g1, d.nout) - 4 * g0;
-  for (int g = 0; g < g1 - g0; g++) {
-    const uint64_t* fr = s_frag + g * nsteps * 64 + lane;
-    v16i acc = {};
-#pragma unroll
-    for (int s = 0; s < MAX_BCONV_IN / 2; s++)
-      if (s < nsteps) acc = __builtin_amdgcn_mfma_i32_32x32x16_i8((long)fr[s * 64], bf[s], acc, 0, 0, 0);
-#pragma unroll
-    for (int mm = 0; mm < 2; mm++) {
-      const int p = 4 * g + 2 * half + mm;
-      if (p < np) {
-        int32_t a8[8];
-#pragma unroll
-        for (int b = 0; b < 8; b++) a8[b] = acc[8 * mm + b];
-        dst[(size_t)s_pos[p] * n + k] = bconv_out(a8, s_ep + BCONV_EPW * p);
-      }
-    }
-  }
-}
-
 __global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, size_t ext_stride,
                                             const uint64_t* __restrict__ c1, int alpha, int dnum,
                                             const uint64_t* __restrict__ key, size_t key_digit_stride,
@@ -108,56 +36,46 @@ __global__ __launch_bounds__(256) void k_to_mont(uint64_t* key, int M, int logn,
 }
 
 // ---------------------------------------------------------------- building blocks
-// Digits of c1 (NTT form, `level` limbs) basis-extended to Q_l u P: the
-// digits' own limbs stay in c1; every other limb of digit j is written to
-// w.ext + j (level+K) N in NTT form.
-// iNTT of c1's digits and their basis conversion (coefficient form) into w.ext
+// ModUp up to the forward column pass: the inverse transform of c1's digits
+// (NTT form, `level` limbs) finishes with N^{-1} (Q_j/q_i)^{-1}, so it writes
+// the conversion inputs t_i into w.coeff; one launch then converts every
+// digit to its other limbs (Q_l \ Q_j) u P and runs their forward pass 1,
+// writing digit j's limbs to w.ext + j (level+K) N (the digit's own limbs stay
+// in c1).
 static int ks_modup_convert(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) {
   const size_t N = c->n;
   const size_t E = (size_t)(level + c->K);
   int rc;
-  if ((rc = ntt_launch_from(c, c1, w.coeff, 0, 1, range_map(0, level, 0), true, s))) return rc;
-  const BConvSet& set = c->modup[level];
-  {
-    const double mm = (double)N * level * (1 + set.max_out);  // t_i products + MACs (upper bound)
-    ProfScope ps(c, "bconv_modup", s, 8.0 * N * (level + (double)set.count * set.max_out), mm,
-                 bconv_ideal_s((double)N, set.count, c->alpha, set.max_out));
-    dim3 grid(N / 128, bconv_tiles_y(set), set.count);
-    k_bconv<<<grid, 256, 0, s>>>(w.coeff, 0, w.ext, E * N, set.d, set.count, c->d_mod, c->log_n);
-  }
-  HE_HIP(hipGetLastError());
-  return HE_OK;
+  if ((rc = ntt_launch_conv_in(c, c1, 0, w.coeff, 0, 1, range_map(0, level, 0), c->d_fin[level], 3, s))) return rc;
+  const ConvSet& set = c->modup[level];
+  return conv_fwd1_launch(c, set, w.coeff, 0, w.ext, E * N, set.count, set.count, c->conv_target[0],
+                          "conv_fwd1_modup", s);
 }
 
+// ModUp: the extended digits in NTT form in w.ext
 int ks_modup(Ctx* c, const WS& w, const uint64_t* c1, int level, hipStream_t s) {
   int rc;
   if ((rc = ks_modup_convert(c, w, c1, level, s))) return rc;
-  return ntt_launch(c, w.ext, 0, 1, c->modup_ntt[level], false, s);
+  return ntt_launch_pass(c, w.ext, 0, w.ext, 0, 1, c->modup_ntt[level], false, 2, s);
 }
 
 // ModDown of w.u (both polynomials) and the final additions
-// (p_inv2: the special-prime limbs of w.u are already after inverse pass 2)
+// (p_inv2: the special-prime limbs of w.u are already after inverse pass 2).
+// The inverse transform of the special limbs writes the conversion inputs,
+// the conversion writes forward pass 1 of the Q limbs into w.y, and the last
+// forward pass applies (u - y) P^{-1} + add.
 static int ks_moddown(Ctx* c, const WS& w, int level, uint32_t g, const uint64_t* add0, const uint64_t* add1,
                       uint64_t* out0, uint64_t* out1, hipStream_t s, bool p_inv2 = false) {
   const size_t N = c->n;
   const int K = c->K, L = c->L;
   const size_t E = (size_t)(level + K);
   int rc;
-  // ModDown of u0 and u1: P limbs to coefficient form, convert to Q_l, back to NTT form
-  if (p_inv2)
-    rc = ntt_launch_pass(c, w.u, E * N, w.u, E * N, 2, range_map(level, K, L), true, 1, s);
-  else
-    rc = ntt_launch(c, w.u, E * N, 2, range_map(level, K, L), true, s);
-  if (rc) return rc;
-  const BConvSet& set = c->moddown[level];
-  {
-    ProfScope ps(c, "bconv_moddown", s, 16.0 * N * (K + level), 2.0 * N * K * (1 + level),
-                 bconv_ideal_s((double)N, 2, K, level));
-    dim3 grid(N / 128, bconv_tiles_y(set), 2);
-    k_bconv<<<grid, 256, 0, s>>>(w.u, E * N, w.y, (size_t)level * N, set.d, 1, c->d_mod, c->log_n);
-  }
-  HE_HIP(hipGetLastError());
-  // back to NTT form with the ModDown epilogue fused into the last pass
+  if ((rc = ntt_launch_conv_in(c, w.u, E * N, w.u, E * N, 2, range_map(level, K, L), c->d_fin[level], p_inv2 ? 1 : 3,
+                               s)))
+    return rc;
+  if ((rc = conv_fwd1_launch(c, c->moddown[level], w.u, E * N, w.y, (size_t)level * N, 2, 1, c->conv_target[1],
+                              "conv_fwd1_moddown", s)))
+    return rc;
   NttEpi epi{};
   epi.u = w.u;
   epi.u_bs = E * N;
@@ -168,9 +86,7 @@ static int ks_moddown(Ctx* c, const WS& w, int level, uint32_t g, const uint64_t
   epi.pinv = c->d_pinv[level];
   epi.g = g;
   epi.level = level;
-  if ((rc = ntt_launch_moddown(c, w.y, (size_t)level * N, range_map(0, level, 0), epi, s))) return rc;
-  HE_HIP(hipGetLastError());
-  return HE_OK;
+  return ntt_launch_moddown(c, w.y, (size_t)level * N, range_map(0, level, 0), epi, s, 2, 2);
 }
 
 int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
@@ -224,6 +140,7 @@ int ks_single(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t
   }
   if ((rc = ks_modup_convert(c, w, c1, level, s))) return rc;
   NttIp ip{};
+  ip.ext_p1 = 1;
   ip.ext = w.ext;
   ip.ext_ds = E * N;
   ip.c1 = c1;

@@ -1,14 +1,15 @@
 // Word-size modular arithmetic for primes q < 2^61 on gfx950.
 //
-// Element-wise modular products run on the vector ALUs: 32-bit integer
-// multiplies for primes of 51 bits and more, centred FP64 FMA for primes
-// below 2^50.  (The one dense contraction of the key switch, the basis
-// conversion, runs on the int8 matrix cores instead: see BConvDesc in
-// elem_core.h.)  Three integer reductions are used:
+// Every modular product runs on the vector ALUs: 32-bit integer multiplies
+// for primes of 51 bits and more, centred FP64 FMA for primes below 2^50.
+// The basis conversion, the one contraction of the key switch, is a short
+// sum (at most ten inputs) per output residue and runs on the same ALUs
+// (ConvDesc in elem_core.h).  Three integer reductions are used:
 //   * Shoup multiplication by a constant w with companion w' = floor(w 2^64 / q)
-//     (NTT twiddles, BConv input factors, q^{-1}, P^{-1});
-//   * Montgomery reduction of a 128-bit accumulator (key inner product, BConv
-//     sums) with constants stored premultiplied by 2^64 mod q;
+//     (NTT twiddles, the inverse transform's finishing factors, q^{-1}, P^{-1});
+//   * Montgomery reduction of a 128-bit accumulator (key inner product, the
+//     basis conversion into primes of 51 bits and more) with constants stored
+//     premultiplied by 2^64 mod q;
 //   * Barrett reduction of a full 128-bit product for ct (.) pt products where
 //     neither operand is a precomputed constant.
 // All results are canonical residues in [0, q): any exact reduction yields the

@@ -119,10 +119,16 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
         o[kk] = f64_to_u52(canon_f64(r + x, dqinv, dq));
       }
     } else {
+      // the inverse transform's N^{-1}, or a conversion's finishing constant
+      double fw = mi.dninv, fwq = mi.dninvq;
+      if (INV && PASS == 1 && epi.fin) {
+        fw = bits_to_f64(epi.fin[4 * m + 2]);
+        fwq = bits_to_f64(epi.fin[4 * m + 3]);
+      }
       for (int e = tid; e < P::TILE; e += P::THREADS) {
         int g, k;
         P::tile_elem(e, g, k);
-        a[P::gidx(wg, g, k)] = P::finish_f64(dl[P::lidx(g, k)], mi.dninv, mi.dninvq, dq, dqinv);
+        a[P::gidx(wg, g, k)] = P::finish_f64(dl[P::lidx(g, k)], fw, fwq, dq, dqinv);
       }
     }
     return;
@@ -138,11 +144,196 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
   if (!INV) rounds_fwd<P, 0>(lds, tid, wg, tw, twp, q, q);
   else rounds_inv<P, P::NR - 1>(lds, tid, wg, tw, twp, q, q);
   __syncthreads();
+  uint64_t fw = mi.ninv, fwp = mi.ninv_p;
+  if (INV && PASS == 1 && epi.fin) {
+    fw = epi.fin[4 * m];
+    fwp = epi.fin[4 * m + 1];
+  }
   for (int e = tid; e < P::TILE; e += P::THREADS) {
     int g, k;
     P::tile_elem(e, g, k);
-    ntt_store<EPI, LOGN>(a, P::gidx(wg, g, k), P::finish(lds[P::lidx(g, k)], mi.ninv, mi.ninv_p, q), epi,
-                         pos, bz, q);
+    ntt_store<EPI, LOGN>(a, P::gidx(wg, g, k), P::finish(lds[P::lidx(g, k)], fw, fwp, q), epi, pos, bz, q);
+  }
+}
+
+// Word at element offset idx (below 2^29) of a uniform base: the byte offset
+// is formed in 32 bits, so the access takes a scalar base and a 32-bit lane
+// offset instead of a 64-bit address per lane.
+__device__ __forceinline__ uint64_t ld_at(const uint64_t* base, uint32_t idx) {
+  return *reinterpret_cast<const uint64_t*>(reinterpret_cast<const char*>(base) + (uint32_t)(idx << 3));
+}
+__device__ __forceinline__ void st_at(uint64_t* base, uint32_t idx, uint64_t v) {
+  *reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(base) + (uint32_t)(idx << 3)) = v;
+}
+
+// Forward column rounds of two tiles side by side (the second only when
+// `two`, uniform over the workgroup): one barrier per round serves both.
+template <class P, int IDX>
+__device__ __forceinline__ void rounds_fwd2_f64(double* a, double* b, bool two, int tid, int wg, const double* twa,
+                                                const double* twqa, double qa, double qia, const double* twb,
+                                                const double* twqb, double qb, double qib) {
+  if constexpr (IDX < P::NR) {
+    if constexpr (IDX > 0) __syncthreads();
+    P::template round_f64<P::rbits(IDX), false>(a, tid, wg, P::rstart(IDX), twa, twqa, qa, qia);
+    if (two) P::template round_f64<P::rbits(IDX), false>(b, tid, wg, P::rstart(IDX), twb, twqb, qb, qib);
+    rounds_fwd2_f64<P, IDX + 1>(a, b, two, tid, wg, twa, twqa, qa, qia, twb, twqb, qb, qib);
+  }
+}
+
+// Basis conversion fused into the forward column pass (pass 1) of its
+// outputs (ConvDesc).  Workgroup (x, y, z) owns column tile x, output group
+// y and batch z.  Every thread first loads all input parts at the tile
+// positions it owns when a tile is staged (one round of loads in flight,
+// kept in registers: NP parts x EPT residues).  An FP64 group (outputs below
+// 2^50) then takes its outputs two at a time: the centred sums of both go
+// into two LDS tiles, the forward column rounds of both run between the same
+// barriers, and both pass-1 intermediates (the form the second pass reads)
+// are stored.  An integer group (outputs of 51 bits and more; descriptors
+// list them first) takes its outputs one at a time with 128-bit
+// accumulators.  The workgroups of one column tile sit on one XCD (the XCD
+// is the linear workgroup id mod 8, i.e. blockIdx.x mod 8 since the tile
+// count is a multiple of 8), so a tile's inputs are fetched from HBM once
+// and re-read from that XCD's L2 by its other output groups.
+template <int LOGN, int LOG_EPT, int LOG_TILE, int NP>
+__global__ __launch_bounds__((NttPass<LOGN, 1, false, LOG_EPT, LOG_TILE>::THREADS))
+__attribute__((amdgpu_waves_per_eu(4))) void k_conv_fwd1(
+    const uint64_t* __restrict__ in, size_t in_bs, uint64_t* __restrict__ out, size_t out_bs,
+    const ConvDesc* __restrict__ descs, int zdiv, int group, const uint64_t* __restrict__ tw_all,
+    const uint64_t* __restrict__ twp_all, const double* __restrict__ dtw_all, const double* __restrict__ dtwq_all,
+    const ModInfo* __restrict__ mods) {
+  using P = NttPass<LOGN, 1, false, LOG_EPT, LOG_TILE>;
+  constexpr int EPT = P::TILE / P::THREADS;
+  __shared__ uint64_t lds[2][P::LDS_WORDS];
+  // the M - 1 twiddles (and quotients) of the column transform of each tile's
+  // modulus, staged once per output instead of gathered from L2 every round
+  __shared__ double s_tw[2][2][P::M];
+  // the group's conversion constants, staged once (read with uniform
+  // addresses, i.e. broadcast)
+  __shared__ uint64_t s_cst[CONV_MAX_GROUP * 2 * 2 * MAX_BCONV_IN];
+  constexpr int W = P::WG_PER_LIMB;
+  const int wg = (W % 8 == 0) ? (int)(blockIdx.x % 8) * (W / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+  const int z = blockIdx.z;
+  const ConvDesc& d = descs[z % zdiv];
+  // descriptor fields are uniform: keep them (and so every base address) in
+  // scalar registers, so that loads and stores take 32-bit lane offsets
+  const int nout = __builtin_amdgcn_readfirstlane(d.nout);
+  const int np = __builtin_amdgcn_readfirstlane(d.nparts);
+  const int nint = __builtin_amdgcn_readfirstlane(d.nint);
+  // group y: integer outputs [y group, ..) while y < ceil(nint / group), then FP64 ones
+  const int gint = (nint + group - 1) / group;
+  const int y = blockIdx.y;
+  const bool fp = y >= gint;
+  const int p0 = fp ? nint + (y - gint) * group : y * group;
+  const int p1 = min(p0 + group, fp ? nout : nint);
+  if (p0 >= p1) return;  // uniform over the workgroup
+  const uint64_t* src = in + (size_t)(z / zdiv) * in_bs;
+  uint64_t* dst = out + (size_t)z * out_bs;
+  const int tid = threadIdx.x;
+  {
+    const uint64_t* c0 = d.cst + (size_t)p0 * np * 2;
+    for (int t = tid; t < (p1 - p0) * np * 2; t += P::THREADS) s_cst[t] = c0[t];
+  }
+  int gi[EPT], li[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; j++) {
+    int g, k;
+    P::tile_elem(tid + j * P::THREADS, g, k);
+    gi[j] = P::gidx(wg, g, k);
+    li[j] = P::lidx(g, k);
+  }
+  if (fp) {
+    __syncthreads();  // s_cst
+    double x[NP][EPT];
+#pragma unroll
+    for (int v = 0; v < NP; v++) {
+      if (v < np) {
+        const uint64_t* sp = src + ((size_t)__builtin_amdgcn_readfirstlane(d.part_pos[v]) << LOGN);
+        double pa, pb;
+        conv_part_ab(__builtin_amdgcn_readfirstlane(d.part_kind[v]), pa, pb);
+#pragma unroll
+        for (int j = 0; j < EPT; j++) x[v][j] = conv_part(ld_at(sp, gi[j]), pa, pb);
+      } else {
+#pragma unroll
+        for (int j = 0; j < EPT; j++) x[v][j] = 0.0;
+      }
+    }
+    for (int p = p0; p < p1; p += 2) {
+      const bool two = p + 1 < p1;
+      const int ma = __builtin_amdgcn_readfirstlane(d.out_mod[p]);
+      const int mb = __builtin_amdgcn_readfirstlane(d.out_mod[two ? p + 1 : p]);
+      const ModInfo& mia = mods[ma];
+      const ModInfo& mib = mods[mb];
+      const double qa = (double)mia.q, qb = (double)mib.q;
+      double* la = reinterpret_cast<double*>(lds[0]);
+      double* lb = reinterpret_cast<double*>(lds[1]);
+      for (int t = tid; t < P::M; t += P::THREADS) {
+        s_tw[0][0][t] = dtw_all[((size_t)ma << LOGN) + t];
+        s_tw[0][1][t] = dtwq_all[((size_t)ma << LOGN) + t];
+        s_tw[1][0][t] = dtw_all[((size_t)mb << LOGN) + t];
+        s_tw[1][1][t] = dtwq_all[((size_t)mb << LOGN) + t];
+      }
+      const uint64_t* ca = s_cst + (p - p0) * np * 2;
+#pragma unroll
+      for (int j = 0; j < EPT; j++) {
+        double xs[NP];
+#pragma unroll
+        for (int v = 0; v < NP; v++) xs[v] = x[v][j];
+        la[li[j]] = conv_sum_f64<NP>(xs, np, ca, qa, mia.dqinv);
+      }
+      if (two) {
+        const uint64_t* cb = ca + np * 2;
+#pragma unroll
+        for (int j = 0; j < EPT; j++) {
+          double xs[NP];
+#pragma unroll
+          for (int v = 0; v < NP; v++) xs[v] = x[v][j];
+          lb[li[j]] = conv_sum_f64<NP>(xs, np, cb, qb, mib.dqinv);
+        }
+      }
+      __syncthreads();
+      rounds_fwd2_f64<P, 0>(la, lb, two, tid, wg, s_tw[0][0], s_tw[0][1], qa, mia.dqinv, s_tw[1][0], s_tw[1][1], qb,
+                            mib.dqinv);
+      __syncthreads();
+      uint64_t* oa = dst + ((size_t)__builtin_amdgcn_readfirstlane(d.out_pos[p]) << LOGN);
+#pragma unroll
+      for (int j = 0; j < EPT; j++) st_at(oa, gi[j], f64_to_bits(la[li[j]]));
+      if (two) {
+        uint64_t* ob = dst + ((size_t)__builtin_amdgcn_readfirstlane(d.out_pos[p + 1]) << LOGN);
+#pragma unroll
+        for (int j = 0; j < EPT; j++) st_at(ob, gi[j], f64_to_bits(lb[li[j]]));
+      }
+      __syncthreads();  // the tiles are rewritten by the next pair
+    }
+    return;
+  }
+  // integer outputs (rare: at most a few per conversion) re-read the parts
+  // from L2 instead of keeping them in registers next to the FP64 path's copy
+  __syncthreads();  // s_cst
+  for (int p = p0; p < p1; p++) {
+    const int m = __builtin_amdgcn_readfirstlane(d.out_mod[p]);
+    const ModInfo mi = mods[m];
+    const uint64_t q = mi.q;
+    const uint64_t* cst = s_cst + (p - p0) * np * 2;
+    uint64_t* il = lds[0];
+    U128 acc[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; j++) acc[j] = U128{0, 0};
+    for (int v = 0; v < np; v++) {
+      const uint64_t* sp = src + ((size_t)__builtin_amdgcn_readfirstlane(d.part_pos[v]) << LOGN);
+      double pa, pb;
+      conv_part_ab(__builtin_amdgcn_readfirstlane(d.part_kind[v]), pa, pb);
+#pragma unroll
+      for (int j = 0; j < EPT; j++) conv_mac_int(acc[j], conv_part(ld_at(sp, gi[j]), pa, pb), cst[2 * v], q);
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; j++) il[li[j]] = mont_redc(acc[j], q, mi.qinv);
+    __syncthreads();
+    rounds_fwd<P, 0>(il, tid, wg, tw_all + ((size_t)m << LOGN), twp_all + ((size_t)m << LOGN), q, q);
+    __syncthreads();
+    uint64_t* o_ = dst + ((size_t)__builtin_amdgcn_readfirstlane(d.out_pos[p]) << LOGN);
+#pragma unroll
+    for (int j = 0; j < EPT; j++) st_at(o_, gi[j], il[li[j]]);
+    __syncthreads();
   }
 }
 
@@ -335,7 +526,7 @@ __global__ __launch_bounds__((DN * NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>::T
 template <int LOGN, int LOG_EPT, int LOG_TILE>
 static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
                         int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr,
-                        int passes = 3) {
+                        int passes = 3, const uint64_t* fin = nullptr) {
   using P1 = NttPass<LOGN, 1, false, LOG_EPT, LOG_TILE>;
   using P2 = NttPass<LOGN, 2, false, LOG_EPT, LOG_TILE>;
   constexpr int T = P1::THREADS;
@@ -376,9 +567,11 @@ static int ntt_launch_v(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* da
           src, src_bs, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod, none);
     }
     if (passes & 1) {
-      ProfScope ps(c, "ntt_inv_pass1", s, bytes, mm1 + N * limbs, (mm1 + N * limbs) * per_mm);
+      NttEpi e1{};
+      e1.fin = fin;
+      ProfScope ps(c, fin ? "ntt_inv_pass1_conv" : "ntt_inv_pass1", s, bytes, mm1 + N * limbs, (mm1 + N * limbs) * per_mm);
       ntt_pass_kernel<LOGN, 1, true, LOG_EPT, LOG_TILE, false><<<g1, T, 0, s>>>(
-          data, batch_stride, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod, none);
+          data, batch_stride, data, batch_stride, map, c->d_itw, c->d_itwp, c->d_ditw, c->d_ditwq, c->d_mod, e1);
     }
   }
   HE_HIP(hipGetLastError());
@@ -399,13 +592,13 @@ static int ntt_bucket(int limbs) { return limbs <= 8 ? 0 : limbs <= 16 ? 1 : lim
 template <int LOGN>
 static int ntt_launch_var(Ctx* c, int var, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
                           int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr,
-                          int passes = 3) {
+                          int passes = 3, const uint64_t* fin = nullptr) {
   switch (var) {
-    case 0: return ntt_launch_v<LOGN, 2, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes);
-    case 1: return ntt_launch_v<LOGN, 3, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes);
-    case 3: return ntt_launch_v<LOGN, 2, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes);
-    case 4: return ntt_launch_v<LOGN, 3, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes);
-    default: return ntt_launch_v<LOGN, 4, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes);
+    case 0: return ntt_launch_v<LOGN, 2, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes, fin);
+    case 1: return ntt_launch_v<LOGN, 3, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes, fin);
+    case 3: return ntt_launch_v<LOGN, 2, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes, fin);
+    case 4: return ntt_launch_v<LOGN, 3, 11>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes, fin);
+    default: return ntt_launch_v<LOGN, 4, 12>(c, src, src_bs, data, batch_stride, nbatch, map, inverse, s, epi, passes, fin);
   }
 }
 
@@ -429,9 +622,9 @@ static LimbMap by_modulus(const Ctx* c, const LimbMap& m) {
 template <int LOGN>
 static int ntt_launch_n(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride,
                         int nbatch, const LimbMap& map, bool inverse, hipStream_t s, const NttEpi* epi = nullptr,
-                        int passes = 3) {
+                        int passes = 3, const uint64_t* fin = nullptr) {
   return ntt_launch_var<LOGN>(c, c->ntt_var[ntt_bucket(map.n * nbatch)], src, src_bs, data, batch_stride, nbatch,
-                              by_modulus(c, map), inverse, s, epi, passes);
+                              by_modulus(c, map), inverse, s, epi, passes, fin);
 }
 
 template <int LOGN>
@@ -513,17 +706,133 @@ int ntt_launch_strided(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* dat
 }
 
 int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& map, const NttEpi& epi, hipStream_t s,
-                       int nbatch) {
+                       int nbatch, int passes) {
   if (map.n <= 0 || nbatch <= 0) return HE_OK;
   if (nbatch > 65535) return set_error(HE_EINVAL, "NTT batch too large for one launch");
   // the transform runs in place on y (its scratch); results go to epi.out
   uint64_t* yy = const_cast<uint64_t*>(y);
   switch (c->log_n) {
-    case 12: return ntt_launch_n<12>(c, yy, y_bs, yy, y_bs, nbatch, map, false, s, &epi);
-    case 14: return ntt_launch_n<14>(c, yy, y_bs, yy, y_bs, nbatch, map, false, s, &epi);
-    case 16: return ntt_launch_n<16>(c, yy, y_bs, yy, y_bs, nbatch, map, false, s, &epi);
+    case 12: return ntt_launch_n<12>(c, yy, y_bs, yy, y_bs, nbatch, map, false, s, &epi, passes);
+    case 14: return ntt_launch_n<14>(c, yy, y_bs, yy, y_bs, nbatch, map, false, s, &epi, passes);
+    case 16: return ntt_launch_n<16>(c, yy, y_bs, yy, y_bs, nbatch, map, false, s, &epi, passes);
   }
   return set_error(HE_EINVAL, "unsupported ring degree");
+}
+
+int ntt_launch_conv_in(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, int nbatch,
+                       const LimbMap& map, const uint64_t* fin, int passes, hipStream_t s) {
+  if (map.n <= 0 || nbatch <= 0) return HE_OK;
+  if (nbatch > 65535) return set_error(HE_EINVAL, "NTT batch too large for one launch");
+  switch (c->log_n) {
+    case 12: return ntt_launch_n<12>(c, src, src_bs, data, batch_stride, nbatch, map, true, s, nullptr, passes, fin);
+    case 14: return ntt_launch_n<14>(c, src, src_bs, data, batch_stride, nbatch, map, true, s, nullptr, passes, fin);
+    case 16: return ntt_launch_n<16>(c, src, src_bs, data, batch_stride, nbatch, map, true, s, nullptr, passes, fin);
+  }
+  return set_error(HE_EINVAL, "unsupported ring degree");
+}
+
+// Conversion kernel shape: 1024-residue column tiles, 4 residues per thread
+// (4 LDS rounds of 2 stages at N = 2^16); the parts of an input coefficient
+// stay in registers, so the kernel is instantiated per part count bucket.
+constexpr int CONV_LOG_EPT = 2, CONV_LOG_TILE = 10;
+
+template <int LOGN, int NP>
+static void conv_fwd1_go(Ctx* c, const ConvSet& set, const uint64_t* in, size_t in_bs, uint64_t* out, size_t out_bs,
+                         int nz, int zdiv, int group, int ngroups, hipStream_t s) {
+  using P = NttPass<LOGN, 1, false, CONV_LOG_EPT, CONV_LOG_TILE>;
+  const dim3 grid(P::WG_PER_LIMB, ngroups, nz);
+  k_conv_fwd1<LOGN, CONV_LOG_EPT, CONV_LOG_TILE, NP><<<grid, P::THREADS, 0, s>>>(
+      in, in_bs, out, out_bs, set.d, zdiv, group, c->d_tw, c->d_twp, c->d_dtw, c->d_dtwq, c->d_mod);
+}
+
+template <int LOGN>
+static int conv_fwd1_n(Ctx* c, const ConvSet& set, const uint64_t* in, size_t in_bs, uint64_t* out, size_t out_bs,
+                       int nz, int zdiv, int group, int ngroups, hipStream_t s) {
+  const int np = set.max_parts;
+  if (np <= 2) conv_fwd1_go<LOGN, 2>(c, set, in, in_bs, out, out_bs, nz, zdiv, group, ngroups, s);
+  else if (np <= 4) conv_fwd1_go<LOGN, 4>(c, set, in, in_bs, out, out_bs, nz, zdiv, group, ngroups, s);
+  else if (np <= 6) conv_fwd1_go<LOGN, 6>(c, set, in, in_bs, out, out_bs, nz, zdiv, group, ngroups, s);
+  else if (np <= 9) conv_fwd1_go<LOGN, 9>(c, set, in, in_bs, out, out_bs, nz, zdiv, group, ngroups, s);
+  else if (np <= 12) conv_fwd1_go<LOGN, 12>(c, set, in, in_bs, out, out_bs, nz, zdiv, group, ngroups, s);
+  else conv_fwd1_go<LOGN, 2 * MAX_BCONV_IN>(c, set, in, in_bs, out, out_bs, nz, zdiv, group, ngroups, s);
+  HE_HIP(hipGetLastError());
+  return HE_OK;
+}
+
+int conv_fwd1_launch(Ctx* c, const ConvSet& set, const uint64_t* in, size_t in_bs, uint64_t* out, size_t out_bs,
+                     int nz, int zdiv, int target, const char* name, hipStream_t s) {
+  if (nz <= 0 || set.count <= 0) return HE_OK;
+  if (nz > 65535) return set_error(HE_EINVAL, "conversion batch too large for one launch");
+  const size_t N = c->n;
+  const int tiles = (int)(N >> CONV_LOG_TILE);
+  // outputs per group: few enough for about `target` workgroups when the
+  // batch is small, at most CONV_MAX_GROUP
+  const int want = std::max(1, (target + tiles * nz - 1) / (tiles * nz));
+  const int group = std::min(CONV_MAX_GROUP, std::max(1, (set.max_out + want - 1) / want));
+  int ngroups = 0;
+  for (int t = 0; t < set.count; t++) {
+    const int ni = set.nint[t], nf = set.nout[t] - ni;
+    ngroups = std::max(ngroups, (ni + group - 1) / group + (nf + group - 1) / group);
+  }
+  const double items = (double)nz / zdiv;
+  const double outs = (double)nz * set.max_out;  // upper bound on the output limbs written
+  const int l1 = (c->log_n + 1) / 2;
+  ProfScope ps(c, name, s, 8.0 * N * (items * set.max_in * set.count + outs),
+               (double)N * outs * (set.max_parts + l1 / 2.0),
+               (double)N * outs * (set.max_parts + l1 / 2.0) / PEAK_MODMUL_F64);
+  switch (c->log_n) {
+    case 12: return conv_fwd1_n<12>(c, set, in, in_bs, out, out_bs, nz, zdiv, group, ngroups, s);
+    case 14: return conv_fwd1_n<14>(c, set, in, in_bs, out, out_bs, nz, zdiv, group, ngroups, s);
+    case 16: return conv_fwd1_n<16>(c, set, in, in_bs, out, out_bs, nz, zdiv, group, ngroups, s);
+  }
+  return set_error(HE_EINVAL, "unsupported ring degree");
+}
+
+// Workgroup targets tried by conv_autotune (the conversion kernel is
+// latency-bound: fewer, longer workgroups re-read less, more of them overlap
+// better; the balance depends on the ring and the conversion's shape).
+static const int kConvTargets[4] = {512, 768, 1024, 1536};
+
+int conv_autotune(Ctx* c) {
+  const int l = c->L;
+  const size_t N = c->n, E = (size_t)(l + c->K);
+  WS w = ws_layout(c, c->ws);
+  hipStream_t s;
+  HE_HIP(hipStreamCreate(&s));
+  hipEvent_t e0, e1;
+  HE_HIP(hipEventCreate(&e0));
+  HE_HIP(hipEventCreate(&e1));
+  HE_HIP(hipMemsetAsync(c->ws, 0, c->ws_words * 8, s));
+  for (int kind = 0; kind < 2; kind++) {
+    const ConvSet& set = kind == 0 ? c->modup[l] : c->moddown[l];
+    auto run = [&](int target) -> int {
+      if (kind == 0) return conv_fwd1_launch(c, set, w.coeff, 0, w.ext, E * N, set.count, set.count, target, "tune", s);
+      return conv_fwd1_launch(c, set, w.u, E * N, w.y, (size_t)l * N, 2, 1, target, "tune", s);
+    };
+    float best = 1e30f;
+    for (int t = 0; t < 4; t++) {
+      int rc;
+      if ((rc = run(kConvTargets[t]))) return rc;  // warm-up
+      HE_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 5; r++)
+        if ((rc = run(kConvTargets[t]))) return rc;
+      HE_HIP(hipEventRecord(e1, s));
+      HE_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      HE_HIP(hipEventElapsedTime(&ms, e0, e1));
+      const float us = ms * 1e3f / 5;
+      c->conv_tune_us[kind][t] = us;
+      if (us < best) {
+        best = us;
+        c->conv_target[kind] = kConvTargets[t];
+      }
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HE_HIP(hipStreamSynchronize(s));
+  hipStreamDestroy(s);
+  return HE_OK;
 }
 
 // ModUp's forward transform with the key inner product fused into its last
@@ -540,7 +849,7 @@ static int ntt_ip_launch_v(Ctx* c, uint64_t* ext, const LimbMap& conv, const Lim
     for (int i = 0; i < conv.n; i++) nconv_f += c->hmod[conv.mod[i]].k <= 50;
     for (int i = 0; i < outs.n; i++) nf += c->hmod[outs.mod[i]].k <= 50;
   }
-  if (!ip.ext_ntt) {
+  if (!ip.ext_ntt && !ip.ext_p1) {
     const double mm = N / 2 * P1::LM * conv.n;
     ProfScope ps(c, "ntt_fwd_pass1", s, 16.0 * N * conv.n, mm,
                  N / 2 * P1::LM * (nconv_f / PEAK_MODMUL_F64 + (conv.n - nconv_f) / PEAK_MODMUL_INT));

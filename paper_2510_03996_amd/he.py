@@ -137,6 +137,7 @@ def lib():
             "he_lane_reserve": [vp, vp, c_int],
             "he_lane_release": [vp, vp],
             "he_ctx_ntt_tuning": [vp, P(i32), P(ctypes.c_float)],
+            "he_ctx_conv_tuning": [vp, P(i32), P(ctypes.c_float)],
             "he_ntt_variant": [c_int, P(i32), P(i32)],
             "he_ctx_ntt_select": [vp, P(i32)],
             "he_ctx_conv_channel_sum": [vp, i32],
@@ -481,6 +482,17 @@ class Context:
             shapes.append("%dx%d" % (t.value, e.value))
         return {"bucket_max_limbs": [8, 16, 32, "more"], "variant_tile_x_per_thread": [shapes[v] for v in var],
                 "us_fwd_inv": {shapes[v]: [round(us[v * 4 + i], 2) for i in range(4)] for v in range(nv)}}
+
+    def conv_tuning(self):
+        """Basis-conversion workgroup targets chosen at creation (ModUp, ModDown)
+        and the timings of the candidates."""
+        tg = (ctypes.c_int32 * 2)()
+        us = (ctypes.c_float * 8)()
+        _check(lib().he_ctx_conv_tuning(self.h, tg, us))
+        cand = [512, 768, 1024, 1536]
+        return {"modup_target": tg[0], "moddown_target": tg[1],
+                "us": {"modup": dict(zip(cand, [round(us[i], 2) for i in range(4)])),
+                       "moddown": dict(zip(cand, [round(us[4 + i], 2) for i in range(4)]))}}
 
     def ntt_select(self, variants):
         """Pin the NTT variant of each batch-size bucket (4 entries)."""

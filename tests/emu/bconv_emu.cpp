@@ -1,9 +1,15 @@
-// Host check of the int8 matrix-core basis conversion: the constant tables
-// and A-operand fragments built as the library builds them, the digit
-// products summed in the lane/row layout of v_mfma_i32_32x32x16_i8, and the
-// library's epilogues (bconv_out: Montgomery for outputs modulo primes above
-// 2^50, FP64 below), against y_p = sum_i t_i [Qin/q_i]_p mod p computed with
-// 128-bit integers and %.  Inputs include 0 and q_i - 1.
+// Host check of the basis conversion's per-residue arithmetic as the fused
+// conversion kernel runs it (elem_core.h): inputs split into parts
+// (conv_part_ab / conv_part: one exact double below 2^50, or the low 32 bits
+// and the rest of a wider residue), FP64 outputs as a sum of centred
+// products mul_f64_c re-centred after every eighth part, integer outputs as
+// 128-bit products with Montgomery constants (conv_mac_int) and one REDC.
+// Constants are formed as the library forms them ([Qin/q_i]_p 2^shift,
+// centred for FP64 outputs, times 2^64 for integer ones).  Reference:
+// y_p = sum_i t_i [Qin/q_i]_p mod p with 128-bit integers and %.  Inputs
+// include 0 and q_i - 1; the FP64 sums are also checked to stay integral and
+// below 5.5 p in magnitude (the bound the column pass relies on).
+#include <cmath>
 #include <cstdio>
 #include <cstdint>
 #include <vector>
@@ -19,66 +25,84 @@ static bool isprime(uint64_t n) { if (n < 2) return false; for (uint64_t a : {2,
     for (int r = 1; r < s; r++) { x = hmul(x, x, n); if (x == n - 1) { ok = true; break; } } if (!ok) return false; } return true; }
 static std::vector<uint64_t> primes(int bits, int cnt, uint64_t two_n) {
   std::vector<uint64_t> v; uint64_t k = ((uint64_t)1 << bits) / two_n;
-  while ((int)v.size() < cnt) { uint64_t p = k * two_n + 1; if (p < ((uint64_t)1 << bits) && isprime(p)) v.push_back(p); k--; } return v; }
+  while ((int)v.size() < cnt && k > 0) { uint64_t p = k * two_n + 1; if (p < ((uint64_t)1 << bits) && isprime(p)) v.push_back(p); k--; } return v; }
+static int bits(uint64_t q) { return 64 - __builtin_clzll(q); }
+
 int main() {
   std::mt19937_64 rng(7);
-  int bad = 0, total = 0, nf64 = 0;
-  struct Case { int bin, nin, bout, nout; } cases[] = {{50, 8, 60, 24}, {60, 8, 50, 24}, {40, 1, 55, 3}, {45, 2, 60, 7}, {50, 5, 40, 61}, {60, 3, 60, 1}, {50, 9, 50, 24}, {50, 8, 50, 25}, {60, 10, 60, 30}, {50, 10, 40, 9}, {40, 2, 40, 5}, {40, 3, 54, 1}, {50, 9, 50, 33}, {45, 10, 41, 16}};
+  int bad = 0, total = 0, nf64 = 0, nint = 0, nwide = 0;
+  double worst = 0.0;  // largest |FP64 sum| / p
+  // (input bits, inputs, output bits, outputs); the first input of some
+  // cases is a wider prime (as q_0 of a digit)
+  struct Case { int bin0, bin, nin, bout, nout; } cases[] = {
+      {60, 50, 8, 50, 25}, {50, 50, 8, 60, 1}, {50, 50, 9, 50, 24}, {50, 50, 9, 60, 1}, {54, 40, 1, 40, 2},
+      {55, 55, 1, 40, 3}, {60, 45, 2, 45, 6}, {60, 60, 2, 45, 8}, {60, 60, 2, 60, 1}, {50, 50, 10, 50, 33},
+      {61, 61, 10, 50, 8}, {61, 61, 10, 61, 3}, {40, 40, 3, 54, 1}, {45, 45, 10, 41, 16}, {24, 24, 4, 24, 5}};
   for (auto cs : cases) {
-    auto qin = primes(cs.bin, cs.nin, 1 << 17);
-    auto qout = primes(cs.bout, cs.nout + cs.nin, 1 << 17);
-    qout.erase(qout.begin(), qout.begin() + cs.nin);  // distinct from the inputs when the sizes match
-    int nsteps = (cs.nin + 1) / 2, ngroups = (cs.nout + 3) / 4;
-    std::vector<uint64_t> cst(cs.nin * cs.nout), pre(cs.nin);
+    std::vector<uint64_t> qin = primes(cs.bin0, 1, 1 << 13);
+    auto rest = primes(cs.bin, cs.nin + 1, 1 << 13);
+    for (uint64_t q : rest) if ((int)qin.size() < cs.nin && q != qin[0]) qin.push_back(q);
+    if ((int)qin.size() < cs.nin) { printf("not enough input primes\n"); return 1; }
+    auto qout = primes(cs.bout, cs.nout + cs.nin + 1, 1 << 13);
+    std::vector<uint64_t> qo;
+    for (uint64_t q : qout) { bool used = false; for (uint64_t a : qin) used |= a == q; if (!used && (int)qo.size() < cs.nout) qo.push_back(q); }
+    if ((int)qo.size() < cs.nout) { printf("not enough output primes\n"); return 1; }
+    // parts
+    std::vector<int> part_in, part_kind, part_sh;
     for (int i = 0; i < cs.nin; i++) {
-      uint64_t prod = 1;
-      for (int i2 = 0; i2 < cs.nin; i2++) if (i2 != i) prod = hmul(prod, qin[i2] % qin[i], qin[i]);
-      pre[i] = hpow(prod, qin[i] - 2, qin[i]);
-      for (int p = 0; p < cs.nout; p++) { uint64_t v = 1; for (int i2 = 0; i2 < cs.nin; i2++) if (i2 != i) v = hmul(v, qin[i2] % qout[p], qout[p]); int kb = 64 - __builtin_clzll(qout[p]); cst[i * cs.nout + p] = bconv_out_f64(kb) ? v : hmul(v, (uint64_t)(((u128)1 << 64) % qout[p]), qout[p]); }
+      if (conv_in_narrow(bits(qin[i]))) { part_in.push_back(i); part_kind.push_back(0); part_sh.push_back(0); }
+      else { nwide++; for (int h = 0; h < 2; h++) { part_in.push_back(i); part_kind.push_back(1 + h); part_sh.push_back(32 * h); } }
     }
-    std::vector<uint64_t> frag(ngroups * nsteps * 64, 0);
-    for (int g = 0; g < ngroups; g++) for (int st = 0; st < nsteps; st++) for (int l = 0; l < 64; l++) {
-      int m, b; bconv_row(l % 32, m, b); int p = 4 * g + m, i = 2 * st + l / 32;
-      if (p >= cs.nout || i >= cs.nin) continue;
-      uint64_t word = 0, cp = cst[i * cs.nout + p];
-      for (int a = 0; a < 8; a++) { word |= (uint64_t)(uint8_t)(int8_t)sdigit(cp, b) << (8 * a); cp = hmul(cp, 256 % qout[p], qout[p]); }
-      frag[(g * nsteps + st) * 64 + l] = word;
-    }
-    std::vector<uint64_t> ep(cs.nout * BCONV_EPW);
-    for (int p = 0; p < cs.nout; p++) { uint64_t po = qout[p]; uint64_t inv = 1; for (int it = 0; it < 7; it++) inv *= 2 - po * inv;
-      bconv_ep_fill(po, 64 - __builtin_clzll(po), inv, &ep[BCONV_EPW * p]); nf64 += ep[BCONV_EPW * p + 4] != 0; }
-    for (int trial = 0; trial < 64; trial++) {  // 32 coefficients per trial (one wave)
-      uint64_t x[10][32], t[10][32];
-      for (int i = 0; i < cs.nin; i++) for (int c = 0; c < 32; c++) {
-        x[i][c] = trial < 2 ? (trial ? qin[i] - 1 : 0) : rng() % qin[i];
-        t[i][c] = hmul(x[i][c], pre[i], qin[i]); }
-      for (int g = 0; g < ngroups; g++) {
-        int32_t acc[64][16] = {};
-        for (int st = 0; st < nsteps; st++) for (int row = 0; row < 32; row++) for (int col = 0; col < 32; col++) {
-          int32_t sum = 0;
-          for (int kk = 0; kk < 16; kk++) {
-            int la = row + 32 * (kk / 8), lb = col + 32 * (kk / 8);
-            int i = 2 * st + lb / 32;
-            uint64_t bw = i < cs.nin ? sdigits(t[i][col]) : 0;
-            int8_t av = (int8_t)(frag[(g * nsteps + st) * 64 + la] >> (8 * (kk % 8)));
-            int8_t bv = (int8_t)(bw >> (8 * (kk % 8)));
-            sum += av * bv;
+    const int np = (int)part_in.size();
+    for (int p = 0; p < cs.nout; p++) {
+      const uint64_t po = qo[p];
+      const bool f64 = conv_out_f64(bits(po));
+      (f64 ? nf64 : nint)++;
+      std::vector<uint64_t> cst(2 * np);
+      std::vector<uint64_t> plain(cs.nin);  // [Qin/q_i]_p
+      for (int i = 0; i < cs.nin; i++) { uint64_t v = 1 % po; for (int i2 = 0; i2 < cs.nin; i2++) if (i2 != i) v = hmul(v, qin[i2] % po, po); plain[i] = v; }
+      for (int v = 0; v < np; v++) {
+        const uint64_t w = hmul(plain[part_in[v]], (uint64_t)(((u128)1 << part_sh[v]) % po), po);
+        if (f64) {
+          const double wc = w > po / 2 ? -(double)(po - w) : (double)w, wq = wc / (double)po;
+          cst[2 * v] = f64_to_bits(wc); cst[2 * v + 1] = f64_to_bits(wq);
+        } else {
+          cst[2 * v] = hmul(w, (uint64_t)(((u128)1 << 64) % po), po); cst[2 * v + 1] = 0;
+        }
+      }
+      uint64_t pinv64 = 1; for (int it = 0; it < 7; it++) pinv64 *= 2 - po * pinv64;
+      for (int trial = 0; trial < 400; trial++) {
+        std::vector<uint64_t> t(cs.nin);
+        for (int i = 0; i < cs.nin; i++) t[i] = trial < 2 ? (trial ? qin[i] - 1 : 0) : rng() % qin[i];
+        double x[2 * MAX_BCONV_IN];
+        for (int v = 0; v < np; v++) { double a, b; conv_part_ab(part_kind[v], a, b); x[v] = conv_part(t[part_in[v]], a, b); }
+        uint64_t got;
+        if (f64) {
+          const double pd = (double)po, pi = 1.0 / pd;
+          double acc = 0.0;
+          for (int v = 0; v < np; v++) {
+            acc += mul_f64_c(x[v], bits_to_f64(cst[2 * v]), bits_to_f64(cst[2 * v + 1]), pd);
+            if ((v & 7) == 7) acc = centre_f64(acc, pi, pd);
+            if (acc != std::floor(acc)) { bad++; printf("non-integral sum\n"); }
           }
-          acc[col + 32 * ((row / 4) % 2)][(row % 4) + 4 * (row / 8)] += sum;
+          worst = std::max(worst, std::fabs(acc) / pd);
+          got = f64_to_u52(canon_f64(acc, pi, pd));
+        } else {
+          U128 acc{0, 0};
+          for (int v = 0; v < np; v++) conv_mac_int(acc, x[v], cst[2 * v], po);
+          got = mont_redc(acc, po, pinv64);
         }
-        for (int l = 0; l < 64; l++) for (int mm = 0; mm < 2; mm++) {
-          int p = 4 * g + 2 * (l / 32) + mm; if (p >= cs.nout) continue;
-          int col = l % 32;
-          uint64_t got = bconv_out(&acc[l][8 * mm], &ep[BCONV_EPW * p]);
-          u128 want = 0; for (int i = 0; i < cs.nin; i++) { uint64_t pl = 1; for (int i2 = 0; i2 < cs.nin; i2++) if (i2 != i) pl = hmul(pl, qin[i2] % qout[p], qout[p]); want += (u128)t[i][col] * pl; }
-          uint64_t w = (uint64_t)(want % qout[p]);
-          total++; if (got != w) { if (bad < 5) printf("case %d/%d p=%d col=%d got %llu want %llu\n", cs.nin, cs.nout, p, col, (unsigned long long)got, (unsigned long long)w); bad++; }
-        }
+        u128 want = 0;
+        for (int i = 0; i < cs.nin; i++) want += (u128)t[i] * plain[i];
+        const uint64_t w = (uint64_t)(want % po);
+        total++;
+        if (got != w) { if (bad < 5) printf("case nin=%d bout=%d p=%d got %llu want %llu\n", cs.nin, cs.bout, p, (unsigned long long)got, (unsigned long long)w); bad++; }
       }
     }
   }
-  printf("bconv emu: %d mismatches of %d outputs (%d FP64 output moduli)\n", bad, total, nf64);
-  const bool ok = bad == 0 && nf64 > 0;
+  printf("bconv emu: %d mismatches of %d outputs (%d FP64 and %d integer output moduli, %d wide inputs), max |FP64 sum| = %.3f p\n",
+         bad, total, nf64, nint, nwide, worst);
+  const bool ok = bad == 0 && nf64 > 0 && nint > 0 && nwide > 0 && worst < 5.5;
   printf(ok ? "OK\n" : "FAIL\n");
   return ok ? 0 : 1;
 }

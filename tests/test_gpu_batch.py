@@ -117,3 +117,35 @@ def test_batch_mac_extreme_residues():
     got_b, got_p, info = run_gpu(g, name, sets, outs, cts, pool, pti, 0)
     H.assert_limbs_equal(got_b, got_p, "batched vs plain, extreme plaintext residues")
     g.close()
+
+
+def test_batch_config3_shape_matches_oracle():
+    """The batched workload's shape at N=2^16, L=24 against the oracle: 8
+    ciphertexts with hoisted sets from the 49-key pool (the 48 non-zero
+    offsets of a 7x7 window on a 32-wide map, plus 1024), one item rotated by
+    all 49 keys, one with 32 outputs, the others 9-12 rotations and 1-4
+    outputs; every output limb compared with the oracle's
+    rotate_hoisted + mul_plain + add + rescale."""
+    name = "config2"
+    pool_offsets = [dy * 32 + dx for dy in range(-3, 4) for dx in range(-3, 4) if (dy, dx) != (0, 0)] + [1024]
+    octx, _, _ = H.oracle_ctx(name)
+    pr = octx.pr
+    B, pool_n, seed = 8, 16, 43
+    sets, outs = synth.rotation_sets(seed, B, pool_offsets, 9, 12, 1, 4)
+    sets[0] = [int(x) for x in synth.rng(seed, 11).permutation(np.asarray(pool_offsets))]  # n = 49
+    outs[1] = 32  # m = 32
+    cts = [H.encrypt_slots(name, seed * 100 + i, level=pr.L, enc_id=i)[1] for i in range(B)]
+    pool = [octx.encode(synth.uniform_slots(seed * 1000 + p, pr.n // 2, stream=9), pr.scale, pr.L)
+            for p in range(pool_n)]
+    pti = [[(i + 7 * o + 13 * t) % pool_n for o in range(outs[i]) for t in range(len(sets[i]))] for i in range(B)]
+    print("config-3 shape: n =", [len(s) for s in sets], "m =", outs, flush=True)
+    g = H.gpu_ctx(name)
+    got_b, got_p, info = run_gpu(g, name, sets, outs, cts, pool, pti, 5)
+    assert info["keys"] == 49 and info["rotations"] == sum(len(s) for s in sets)
+    H.assert_limbs_equal(got_b, got_p, "batched vs plain")
+    want = oracle_outputs(name, sets, outs, cts, pool, pti)
+    assert len(want) == got_b.shape[0]
+    for k, w in enumerate(want):
+        H.assert_limbs_equal(got_b[k], w.data, "batched vs oracle output %d" % k)
+    assert info["out_scale"] == want[0].scale
+    g.close()

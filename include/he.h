@@ -193,6 +193,22 @@ int he_ntt(he_ctx* ctx, uint64_t* poly, int n_limbs, int first_limb, int inverse
  * with one index.  r = 0 (mod N/2) copies.  HE_ENOKEY if evk_r is absent. */
 int he_rotate(he_ctx* ctx, const he_ct* in, int32_t r, he_ct* out, he_stream stream);
 
+/* he_rotate for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same rotation, bit for bit, with the key-switch workspace in a static
+ * device array of HE_NOALLOC_SCRATCH_BYTES that each GPU the library runs on
+ * holds until the process ends, so the call allocates nothing (no lane, no
+ * events, no key loads).  The key must be a resident key from he_key_upload
+ * (a host-registered key is HE_ENOKEY), profiling must be off, and the key
+ * switch at in->level must fit the array: N (l + dnum (l+K) + 2 (l+K) + 2 l)
+ * words (l = in->level, dnum = ceil(l / alpha)); larger is HE_EINVAL, with
+ * the sizes in he_last_error().  All calls on one GPU share that GPU's
+ * array: calls that overlap on one GPU (other streams, other threads, other
+ * contexts) race and must be serialised by the caller.  Nothing in the
+ * array has to start at zero; it keeps the last call's intermediates. */
+#define HE_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int he_rotate_noalloc(he_ctx* ctx, const he_ct* in, int32_t r, he_ct* out, he_stream stream);
+
 /* Hoisted rotations ("fast rotations"): one ModUp of c1 shared by n
  * rotations; outs[t] = Rot_{r[t]}(in).  Outputs must not alias the input or
  * each other (HE_EINVAL); their key switches may run on helper streams of

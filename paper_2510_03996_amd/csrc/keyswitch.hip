@@ -5,6 +5,9 @@
 // rotations): digits of c1 are basis-extended once (ModUp), the Galois
 // automorphism phi_g is applied to the extended digits as an NTT-form index
 // gather fused into the inner-product load, then ModDown.
+#include <mutex>
+#include <string>
+
 #include "internal.h"
 
 namespace he {
@@ -245,6 +248,96 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
 
 int he_rotate(he_ctx* h, const he_ct* in, int32_t r, he_ct* out, he_stream st) {
   return he_rotate_hoisted(h, in, &r, 1, out, st);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- rotation without allocation
+// he_rotate_noalloc runs the same key switch as he_rotate (ks_single), with
+// its workspace in this static device array instead of a lane's allocation.
+// Each GPU the library runs on holds its own copy until the process ends; in
+// host code `scratch` only names the symbol, so its device address is looked
+// up once per device (hipGetSymbolAddress, with that device current) and
+// that address is what kernels receive.
+namespace he {
+constexpr size_t NOALLOC_SCRATCH_WORDS = HE_NOALLOC_SCRATCH_BYTES / 8;
+static __device__ __align__(256) uint64_t scratch[NOALLOC_SCRATCH_WORDS];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static uint64_t* g_scratch[NOALLOC_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// device address of `scratch` on the current device (nullptr with the error set)
+static uint64_t* scratch_ptr(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) {
+    set_error(HE_EINVAL, "device index out of range for the static workspace");
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      hip_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress(scratch)");
+      return nullptr;
+    }
+    g_scratch[device] = (uint64_t*)p;
+  }
+  return g_scratch[device];
+}
+}  // namespace he
+
+extern "C" {
+
+int he_rotate_noalloc(he_ctx* h, const he_ct* in, int32_t r, he_ct* out, he_stream st) {
+  if (!h || !out) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in")) || (rc = check_out(c, out, in->level))) return rc;
+  if (out->data == in->data) return set_error(HE_EINVAL, "output aliases the input");
+  if (c->prof_on) return set_error(HE_EINVAL, "profiling is on (it creates events): not available here");
+  const int l = in->level;
+  const size_t N = c->n;
+  hipStream_t s = (hipStream_t)st;
+  const uint64_t* c0 = in->data;
+  const uint64_t* c1 = in->data + (size_t)in->cap * N;
+  uint64_t* o0 = out->data;
+  uint64_t* o1 = out->data + (size_t)out->cap * N;
+  out->level = l;
+  out->scale = in->scale;
+  if (norm_key_id(c, r) == 0) {
+    if (hipMemcpyAsync(o0, c0, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(o1, c1, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return set_error(HE_EHIP, "copy of an identity rotation failed");
+    return HE_OK;
+  }
+  // the key must already be in device memory and never evicted (uploaded with
+  // he_key_upload): loading or tracking a host-backed key allocates
+  auto it = c->keys.find(norm_key_id(c, r));
+  if (it == c->keys.end() || !it->second.dev || it->second.host)
+    return set_error(HE_ENOKEY, "rotation key " + std::to_string(r) + " is not a resident (uploaded) key");
+  // workspace of one key switch at level l, packed: coeff [l], ext [dnum][l+K],
+  // u [2][l+K], y [2][l] limbs
+  const size_t E = (size_t)(l + c->K);
+  const size_t need = N * ((size_t)l + (size_t)c->dnum(l) * E + 2 * E + 2 * (size_t)l);
+  if (need > NOALLOC_SCRATCH_WORDS)
+    return set_error(HE_EINVAL, "key switch needs " + std::to_string(need * 8) + " bytes of workspace, more than the " +
+                                    std::to_string(HE_NOALLOC_SCRATCH_BYTES) + "-byte static workspace");
+  int cur = 0;
+  HE_HIP(hipGetDevice(&cur));
+  if (cur != c->device) HE_HIP(hipSetDevice(c->device));
+  uint64_t* base = scratch_ptr(c->device);
+  if (!base) {
+    if (cur != c->device) hipSetDevice(cur);
+    return HE_EHIP;
+  }
+  WS w{};
+  w.coeff = base;
+  w.ext = w.coeff + (size_t)l * N;
+  w.u = w.ext + (size_t)c->dnum(l) * E * N;
+  w.y = w.u + 2 * E * N;
+  rc = ks_single(c, w, c1, l, it->second.dev, galois_elt(c, r), c0, nullptr, o0, o1, s);
+  if (cur != c->device) hipSetDevice(cur);
+  return rc;
 }
 
 int he_relin(he_ctx* h, const uint64_t* d, int level, double scale, he_ct* out, he_stream st) {

@@ -106,6 +106,7 @@ def lib():
             "he_key_count": [vp],
             "he_ntt": [vp, vp, c_int, c_int, c_int, vp],
             "he_rotate": [vp, P(he_ct), i32, P(he_ct), vp],
+            "he_rotate_noalloc": [vp, P(he_ct), i32, P(he_ct), vp],
             "he_rotate_hoisted": [vp, P(he_ct), P(i32), c_int, P(he_ct), vp],
             "he_mul_plain": [vp, P(he_ct), P(he_pt), P(he_ct), c_int, vp],
             "he_add": [vp, P(he_ct), P(he_ct), P(he_ct), vp],
@@ -328,6 +329,14 @@ class Context:
         out = out or self.new_ct(ct.level)
         a, o = ct.c(), out.c()
         _check(lib().he_rotate(self.h, ctypes.byref(a), int(r), ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    def rotate_noalloc(self, ct, r, out, stream=None):
+        """he_rotate with the key-switch workspace in the library's static
+        device array (allocates nothing; out must be preallocated)."""
+        a, o = ct.c(), out.c()
+        _check(lib().he_rotate_noalloc(self.h, ctypes.byref(a), int(r), ctypes.byref(o), _stream(stream)))
         out.update(o)
         return out
 

@@ -276,6 +276,44 @@ typedef struct {
   he_fmap out;
 } he_layer_plan;
 
+/* Plaintext recipes (section "FHEON's Support Functions": the model owner
+ * preprocesses weights into the plaintext vectors a layer multiplies by).
+ * Host only, no context: fills the real slot vectors (N/2 doubles each,
+ * N = 2^log_n) a layer consumes, in the order and number its plan gives,
+ * for the schedule options in the descriptor (set the same options on the
+ * context that runs the layer; the input-channel sum mode does not change
+ * the vectors):
+ *   HE_LAYER_CONV: weights [out_ch][in.channels][kernel][kernel]; the
+ *     plan's n_kernel_pts kernel vectors, then its n_mask_pts masks, then,
+ *     when bias (out_ch values) is given, one bias vector (b_f on every
+ *     output position of channel f, in every replica of the output layout);
+ *   HE_LAYER_AVGPOOL: the n_mask_pts masks (kernel 0 = global pooling);
+ *   HE_LAYER_FC: weights [n_out][n_in]; rows form: the n_out rows, then
+ *     e_0; diagonal form: the n_in rotated diagonals; then, when bias
+ *     (n_out values) is given, the bias in slots 0..n_out-1;
+ *   HE_LAYER_CHEB_MASK: he_cheb's scale mask, 1/beta on slots [0, n_in).
+ * out: [cap_vectors][N/2] doubles or NULL (then only *n_vectors is set).
+ * The caller encodes the vectors (scale and level: kernel vectors at the
+ * input's level, masks one level per step lower as the layer consumes them,
+ * biases at the output's scale and level).  HE_EINVAL for shapes the layer
+ * rejects or a too small cap_vectors; HE_EUNSUPPORTED as the layer. */
+#define HE_LAYER_CONV 0
+#define HE_LAYER_AVGPOOL 1
+#define HE_LAYER_FC 2
+#define HE_LAYER_CHEB_MASK 3
+typedef struct {
+  int32_t kind;
+  int32_t log_n;        /* ring degree N = 2^log_n (slots N/2) */
+  int32_t mask_chains;  /* HE_CHAIN_HORNER or HE_CHAIN_BSGS (he_ctx_mask_chains) */
+  int32_t fc_form;      /* HE_FC_ROWS or HE_FC_DIAG (he_ctx_fc_form) */
+  he_fmap in;           /* CONV, AVGPOOL: input layout */
+  int32_t out_ch, kernel, stride, padding;
+  int32_t n_in, n_out;  /* FC; CHEB_MASK: n_in = used slots */
+  double beta;          /* CHEB_MASK */
+} he_layer_desc;
+int he_layer_plaintexts(const he_layer_desc* desc, const double* weights, const double* bias, double* out,
+                        size_t cap_vectors, int32_t* n_vectors);
+
 /* Convolution (Sections "Secure Convolution Layer", "Secure Advanced
  * Convolution Layer" with striding approach 1 and the multi-channel striding
  * pipeline, "Special Secure Convolution Layer" with Algorithms 1-3).
@@ -331,9 +369,12 @@ int he_ctx_conv_channel_sum(he_ctx* ctx, int mode);
 #define HE_CHAIN_HORNER 0
 #define HE_CHAIN_BSGS 1
 int he_ctx_mask_chains(he_ctx* ctx, int mode);
+/* bias_pt (nullable): the output channels' biases on the output layout
+ * (he_layer_plaintexts), encoded at the output's scale and level, added to
+ * the result (the convolution's "add the bias"). */
 int he_conv2d(he_ctx* ctx, const he_ct* in, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
-              const he_pt* kernel_pts, int n_kernel_pts, const he_pt* mask_pts, int n_mask_pts, he_ct* out,
-              he_fmap* out_map, he_stream stream);
+              const he_pt* kernel_pts, int n_kernel_pts, const he_pt* mask_pts, int n_mask_pts, const he_pt* bias_pt,
+              he_ct* out, he_fmap* out_map, he_stream stream);
 
 /* Average pooling (Section "Secure Average Pooling Layer", equation of the
  * pooled output): window sum by rotations, 1/k^2 folded into the column masks

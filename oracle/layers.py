@@ -197,6 +197,9 @@ class SimEval:
         assert a.level == b.level
         return SimCt(a.v * b.v, a.level, a.scale)
 
+    def add_plain(self, x, pt):
+        return SimCt(x.v + pt, x.level, x.scale)
+
     def mul_const(self, x, c, scale):
         return SimCt(x.v * c, x.level, x.scale)
 
@@ -239,6 +242,9 @@ class HEEval:
     def mul_relin(self, a, b):
         self.ks += 1
         return self.ctx.mul_relin(a, b, self.relin_key)
+
+    def add_plain(self, x, pt):
+        return self.ctx.add_plain(x, pt)
 
     def mul_const(self, x, c, scale):
         return self.ctx.mul_plain(x, self.ctx.encode_const(c, scale, x.level))
@@ -540,7 +546,30 @@ def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False):
     return sorted(keys)
 
 
-def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False, bsgs=False):
+def conv_bias_vector(fo, bias, slots):
+    """The output channels' biases on the output layout fo: b_f at every
+    position of channel f, in every replica (added after the convolution,
+    the paper's "add the bias")."""
+    v = np.zeros(slots)
+    for r in range(fo.reps):
+        for f in range(fo.C):
+            for y in range(fo.H):
+                base = (r * fo.C + f) * fo.cs + y * fo.rs
+                v[base:base + fo.W] = bias[f]
+    return v
+
+
+def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False, bsgs=False, bias=None):
+    """The pinned convolution schedule (_conv2d_schedule), then the bias
+    plaintext (conv_bias_vector, encoded at the output's scale and level)
+    added when given."""
+    y, fo = _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep, bsgs)
+    if bias is not None:
+        y = ev.add_plain(y, bias)
+    return y, fo
+
+
+def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False, bsgs=False):
     """Pinned convolution schedule.
 
     special (k=3, P=1): r = Algorithm 1 rotations computed as three hoisted

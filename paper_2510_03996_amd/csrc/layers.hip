@@ -762,6 +762,192 @@ static he_ct cheb_eval_node(Ev& ev, const std::vector<ChebNode>& t, int id, cons
   return ev.add_take(p, rc);
 }
 
+// ---------------------------------------------------------------- plaintext recipes
+// The real slot vectors a layer multiplies by, built on the host in the
+// order and number the layer's plan gives (the model owner's weight
+// preprocessing).  V is [count][slots]; every builder appends.
+using Vecs = std::vector<std::vector<double>>;
+
+static std::vector<double> zeros(int slots) { return std::vector<double>((size_t)slots, 0.0); }
+
+// Rot_r moves slot i + r to slot i: the vector a rotation by r would give
+static std::vector<double> rotated(const std::vector<double>& m, long r) {
+  const long n = (long)m.size();
+  std::vector<double> o(m.size());
+  for (long i = 0; i < n; i++) o[i] = m[(size_t)(((i + r) % n + n) % n)];
+  return o;
+}
+
+// masks of a masked chain with key `key`: as given (Horner), or mask t = a B + b
+// rotated by b key (baby-step giant-step)
+static void chain_vectors(const Ctx* c, Vecs& out, Vecs v, int key) {
+  if (c->chain == HE_CHAIN_BSGS && v.size() > 1) {
+    int B, A;
+    bsgs_split((int)v.size(), B, A);
+    for (size_t t = 0; t < v.size(); t++) v[t] = rotated(v[t], (long)(t % B) * key);
+  }
+  for (auto& x : v) out.push_back(std::move(x));
+}
+
+// stride-S extraction masks of outputs (S i, S j) of map fm (compaction_plan)
+static void compaction_vectors(const Ctx* c, Vecs& out, const he_fmap& fm, int S, int Ho, int Wo, double col_scale) {
+  const int slots = c->n / 2;
+  for (const Step& st : compaction_plan(fm, S, Ho, Wo)) {
+    Vecs v;
+    for (int t = 0; t < st.n; t++) {
+      std::vector<double> m = zeros(slots);
+      for (int ch = 0; ch < fm.channels; ch++) {
+        if (st.kind == 0) {
+          for (int i = 0; i < Ho; i++) m[(size_t)ch * fm.chan_stride + (size_t)S * i * fm.row_stride + S * t] = col_scale;
+        } else if (st.kind == 1) {
+          const size_t base = (size_t)ch * fm.chan_stride + (size_t)S * t * fm.row_stride;
+          for (int j = 0; j < Wo; j++) m[base + j] = 1.0;
+        } else if (ch == t) {
+          for (int j = 0; j < Ho * Wo; j++) m[(size_t)ch * fm.chan_stride + j] = 1.0;
+        }
+      }
+      v.push_back(std::move(m));
+    }
+    chain_vectors(c, out, std::move(v), st.key);
+  }
+}
+
+// convolution: kernel vectors [f][tap], then masks, then (bias) the bias
+// vector on the output layout.  K is [F][C][k][k].
+static int conv_vectors(const Ctx* c, const he_fmap& fm, int F, int k, int S, int P, const double* K, const double* bias,
+                        Vecs& out) {
+  he_layer_plan pl;
+  int rc;
+  if ((rc = conv_plan(c, &fm, F, k, S, P, &pl))) return rc;
+  const int slots = c->n / 2, C = fm.channels;
+  auto w = [&](int f, int ch, int i, int j) { return K[(((size_t)f * C + ch) * k + i) * k + j]; };
+  if (conv_special(fm, F, k, P)) {
+    const int W = fm.width, WW = W * W;
+    for (int f = 0; f < F; f++)
+      for (int tap = 0; tap < 9; tap++) {
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+        std::vector<double> v = zeros(slots);
+        for (int b = 0; b < fm.reps * C; b++)
+          for (int y = 0; y < W; y++)
+            for (int x = 0; x < W; x++)
+              if (y + dy >= 0 && y + dy < W && x + dx >= 0 && x + dx < W)
+                v[(size_t)b * WW + y * W + x] = w(f, b % C, dy + 1, dx + 1);
+        out.push_back(std::move(v));
+      }
+    const int reps1 = (fm.reps == 2 && 2 * F * WW == slots) ? 2 : 1;
+    if (F > 1 || C > 1)
+      for (int f = 0; f < F; f++) {
+        std::vector<double> m = zeros(slots);
+        for (int r = 0; r < reps1; r++)
+          for (int t = 0; t < WW; t++) m[(size_t)(r * F + f) * WW + t] = 1.0;
+        out.push_back(std::move(m));
+      }
+    if (S > 1) {
+      const int Ho = (W - 1) / S + 1;
+      compaction_vectors(c, out, he_fmap{F, W, W, W, WW, 1}, S, Ho, Ho, 1.0);
+    }
+  } else {
+    const int H1 = fm.height + 2 * P - k + 1, W1 = fm.width + 2 * P - k + 1;
+    for (int f = 0; f < F; f++)
+      for (int i = 0; i < k; i++)
+        for (int j = 0; j < k; j++) {
+          std::vector<double> v = zeros(slots);
+          const int x0 = std::max(0, P - j), x1 = std::min(W1, fm.width + P - j);
+          for (int ch = 0; ch < C; ch++)
+            for (int y = 0; y < H1; y++)
+              if (y + i - P >= 0 && y + i - P < fm.height)
+                for (int x = x0; x < x1; x++) v[(size_t)ch * fm.chan_stride + (size_t)y * fm.row_stride + x] = w(f, ch, i, j);
+          out.push_back(std::move(v));
+        }
+    if (C > 1) {
+      std::vector<double> m = zeros(slots);
+      for (int y = 0; y < H1; y++)
+        for (int x = 0; x < W1; x++) m[(size_t)y * fm.row_stride + x] = 1.0;
+      out.push_back(std::move(m));
+    }
+    if (S > 1) {
+      const int Ho = (H1 - 1) / S + 1, Wo = (W1 - 1) / S + 1;
+      compaction_vectors(c, out, he_fmap{F, H1, W1, fm.row_stride, fm.chan_stride, 1}, S, Ho, Wo, 1.0);
+    }
+  }
+  if (bias) {
+    const he_fmap& o = pl.out;
+    std::vector<double> v = zeros(slots);
+    for (int r = 0; r < o.reps; r++)
+      for (int f = 0; f < F; f++)
+        for (int y = 0; y < o.height; y++)
+          for (int x = 0; x < o.width; x++)
+            v[(size_t)(r * F + f) * o.chan_stride + (size_t)y * o.row_stride + x] = bias[f];
+    out.push_back(std::move(v));
+  }
+  return HE_OK;
+}
+
+static int pool_vectors(const Ctx* c, const he_fmap& fm, int k, int S, Vecs& out) {
+  he_layer_plan pl;
+  int rc;
+  if ((rc = pool_plan(c, &fm, k, S, &pl))) return rc;
+  const int slots = c->n / 2;
+  if (k == 0) {
+    Vecs v;
+    for (int ch = 0; ch < fm.channels; ch++) {
+      std::vector<double> m = zeros(slots);
+      m[(size_t)ch * fm.chan_stride] = 1.0 / ((double)fm.height * fm.width);
+      v.push_back(std::move(m));
+    }
+    chain_vectors(c, out, std::move(v), fm.chan_stride - 1);
+    return HE_OK;
+  }
+  const int H1 = fm.height - k + 1, W1 = fm.width - k + 1;
+  const double inv = 1.0 / ((double)k * k);
+  if (S == 1) {
+    std::vector<double> m = zeros(slots);
+    for (int ch = 0; ch < fm.channels; ch++)
+      for (int y = 0; y < H1; y++)
+        for (int x = 0; x < W1; x++) m[(size_t)ch * fm.chan_stride + (size_t)y * fm.row_stride + x] = inv;
+    out.push_back(std::move(m));
+    return HE_OK;
+  }
+  const int Ho = (fm.height - k) / S + 1, Wo = (fm.width - k) / S + 1;
+  compaction_vectors(c, out, he_fmap{fm.channels, H1, W1, fm.row_stride, fm.chan_stride, 1}, S, Ho, Wo, inv);
+  return HE_OK;
+}
+
+// fully connected: rows W_k then e_0 (rows form), or the n_in diagonals
+// W[j][(j + d) mod n_in] rotated by -(d / B) B (diagonal form); then the bias
+// in slots 0..n_out-1 when given.  Wm is [n_out][n_in].
+static int fc_vectors(const Ctx* c, int n_in, int n_out, const double* Wm, const double* bias, Vecs& out) {
+  he_layer_plan pl;
+  int rc;
+  if ((rc = fc_plan_impl(c, n_in, n_out, &pl))) return rc;
+  const int slots = c->n / 2;
+  if (n_in > slots) return set_error(HE_EINVAL, "n_in exceeds the slots");
+  if (c->fc == HE_FC_DIAG) {
+    int B, A;
+    bsgs_split(n_in, B, A);
+    for (int d = 0; d < n_in; d++) {
+      std::vector<double> v = zeros(slots);
+      for (int j = 0; j < n_out; j++) v[j] = Wm[(size_t)j * n_in + (j + d) % n_in];
+      out.push_back(rotated(v, -(long)(d / B) * B));
+    }
+  } else {
+    for (int kk = 0; kk < n_out; kk++) {
+      std::vector<double> v = zeros(slots);
+      for (int j = 0; j < n_in; j++) v[j] = Wm[(size_t)kk * n_in + j];
+      out.push_back(std::move(v));
+    }
+    std::vector<double> e0 = zeros(slots);
+    e0[0] = 1.0;
+    out.push_back(std::move(e0));
+  }
+  if (bias) {
+    std::vector<double> v = zeros(slots);
+    for (int j = 0; j < n_out; j++) v[j] = bias[j];
+    out.push_back(std::move(v));
+  }
+  return HE_OK;
+}
+
 }  // namespace he
 
 using namespace he;
@@ -810,8 +996,8 @@ int he_conv2d_plan(const he_ctx* h, const he_fmap* in_map, int out_ch, int kerne
 }
 
 int he_conv2d(he_ctx* h, const he_ct* in, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
-              const he_pt* kernel_pts, int n_kernel_pts, const he_pt* mask_pts, int n_mask_pts, he_ct* out,
-              he_fmap* out_map, he_stream s) {
+              const he_pt* kernel_pts, int n_kernel_pts, const he_pt* mask_pts, int n_mask_pts, const he_pt* bias_pt,
+              he_ct* out, he_fmap* out_map, he_stream s) {
   if (!h || !out_map) return set_error(HE_EINVAL, "null argument");
   Ctx* c = &h->c;
   he_layer_plan pl;
@@ -824,6 +1010,7 @@ int he_conv2d(he_ctx* h, const he_ct* in, const he_fmap* in_map, int out_ch, int
   if ((rc = check_out(c, out, in->level - pl.levels))) return rc;
   if ((rc = check_pts(c, kernel_pts, n_kernel_pts, in->level, "kernel_pts"))) return rc;
   if ((rc = check_pts(c, mask_pts, n_mask_pts, in->level - pl.levels + 1, "mask_pts"))) return rc;
+  if (bias_pt && (rc = check_pts(c, bias_pt, 1, in->level - pl.levels, "bias_pt"))) return rc;
   for (int i = 0; i < pl.n_keys; i++)
     if (!key_known(c, pl.rot_keys[i]))
       return set_error(HE_ENOKEY, "rotation key " + std::to_string(pl.rot_keys[i]) + " not resident");
@@ -831,6 +1018,55 @@ int he_conv2d(he_ctx* h, const he_ct* in, const he_fmap* in_map, int out_ch, int
     Ev ev(h, s);
     he_ct y = conv_run(ev, *in, *in_map, out_ch, kernel, stride, padding, kernel_pts, mask_pts, out_map);
     ev.copy_out(y, out);
+    if (bias_pt) ck(he_add_plain(h, out, bias_pt, out, s));  // the paper's "add the bias"
+    return HE_OK;
+  });
+}
+
+int he_layer_plaintexts(const he_layer_desc* d, const double* weights, const double* bias, double* out,
+                        size_t cap_vectors, int32_t* n_vectors) {
+  if (!d || !n_vectors) return set_error(HE_EINVAL, "null argument");
+  if (d->log_n < 1 || d->log_n > 17) return set_error(HE_EINVAL, "log_n out of range");
+  if (d->mask_chains != HE_CHAIN_HORNER && d->mask_chains != HE_CHAIN_BSGS)
+    return set_error(HE_EINVAL, "unknown mask-chain mode");
+  if (d->fc_form != HE_FC_ROWS && d->fc_form != HE_FC_DIAG) return set_error(HE_EINVAL, "unknown FC form");
+  return guarded([&] {
+    Ctx opt;  // the schedule options the layer's plan depends on
+    opt.log_n = d->log_n;
+    opt.n = 1 << d->log_n;
+    opt.chain = d->mask_chains;
+    opt.fc = d->fc_form;
+    Vecs v;
+    int rc;
+    switch (d->kind) {
+      case HE_LAYER_CONV:
+        if (!weights) return set_error(HE_EINVAL, "convolution weights missing");
+        rc = conv_vectors(&opt, d->in, d->out_ch, d->kernel, d->stride, d->padding, weights, bias, v);
+        break;
+      case HE_LAYER_AVGPOOL:
+        rc = pool_vectors(&opt, d->in, d->kernel, d->stride, v);
+        break;
+      case HE_LAYER_FC:
+        if (!weights) return set_error(HE_EINVAL, "fully connected weights missing");
+        rc = fc_vectors(&opt, d->n_in, d->n_out, weights, bias, v);
+        break;
+      case HE_LAYER_CHEB_MASK: {
+        if (!(d->beta > 0.0) || d->n_in < 0 || d->n_in > opt.n / 2) return set_error(HE_EINVAL, "bad scale mask");
+        std::vector<double> m = zeros(opt.n / 2);
+        for (int i = 0; i < d->n_in; i++) m[i] = 1.0 / d->beta;
+        v.push_back(std::move(m));
+        rc = HE_OK;
+        break;
+      }
+      default:
+        return set_error(HE_EINVAL, "unknown layer kind");
+    }
+    if (rc) return rc;
+    *n_vectors = (int32_t)v.size();
+    if (!out) return HE_OK;
+    if (v.size() > cap_vectors) return set_error(HE_EINVAL, "output holds too few vectors");
+    const size_t slots = (size_t)opt.n / 2;
+    for (size_t i = 0; i < v.size(); i++) std::copy(v[i].begin(), v[i].end(), out + i * slots);
     return HE_OK;
   });
 }

@@ -74,6 +74,34 @@ class he_layer_plan(ctypes.Structure):
         return [int(self.rot_keys[i]) for i in range(self.n_keys)]
 
 
+class he_layer_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("log_n", ctypes.c_int32), ("mask_chains", ctypes.c_int32),
+                ("fc_form", ctypes.c_int32), ("in_", he_fmap), ("out_ch", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("stride", ctypes.c_int32), ("padding", ctypes.c_int32), ("n_in", ctypes.c_int32),
+                ("n_out", ctypes.c_int32), ("beta", ctypes.c_double)]
+
+
+LAYER_CONV, LAYER_AVGPOOL, LAYER_FC, LAYER_CHEB_MASK = 0, 1, 2, 3
+
+
+def layer_plaintexts(kind, log_n, weights=None, bias=None, fm=None, out_ch=0, kernel=0, stride=1, padding=0,
+                     n_in=0, n_out=0, beta=1.0, mask_chains=0, fc_form=0):
+    """he_layer_plaintexts: the real slot vectors (float64 [count][N/2]) a
+    layer consumes, in its plan's order (host only, no GPU needed)."""
+    d = he_layer_desc(int(kind), int(log_n), int(mask_chains), int(fc_form), fm if fm is not None else he_fmap(),
+                      int(out_ch), int(kernel), int(stride), int(padding), int(n_in), int(n_out), float(beta))
+    w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
+    b = None if bias is None else np.ascontiguousarray(bias, dtype=np.float64)
+    dp = ctypes.POINTER(ctypes.c_double)
+    wp = w.ctypes.data_as(dp) if w is not None else None
+    bp = b.ctypes.data_as(dp) if b is not None else None
+    n = ctypes.c_int32()
+    _check(lib().he_layer_plaintexts(ctypes.byref(d), wp, bp, None, 0, ctypes.byref(n)))
+    out = np.zeros((n.value, (1 << int(log_n)) // 2))
+    _check(lib().he_layer_plaintexts(ctypes.byref(d), wp, bp, out.ctypes.data_as(dp), n.value, ctypes.byref(n)))
+    return out
+
+
 class he_batch_desc(ctypes.Structure):
     _fields_ = [("n_items", ctypes.c_int32), ("level", ctypes.c_int32), ("in_scale", ctypes.c_double),
                 ("pt_scale", ctypes.c_double), ("in_", ctypes.c_void_p), ("n_rot", ctypes.POINTER(ctypes.c_int32)),
@@ -120,7 +148,9 @@ def lib():
             "he_add_const": [vp, P(he_ct), ctypes.c_double, P(he_ct), vp],
             "he_conv2d_plan": [vp, P(he_fmap), c_int, c_int, c_int, c_int, P(he_layer_plan)],
             "he_conv2d": [vp, P(he_ct), P(he_fmap), c_int, c_int, c_int, c_int, P(he_pt), c_int, P(he_pt), c_int,
-                          P(he_ct), P(he_fmap), vp],
+                          P(he_pt), P(he_ct), P(he_fmap), vp],
+            "he_layer_plaintexts": [P(he_layer_desc), P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
+                                    ctypes.c_size_t, P(i32)],
             "he_avgpool_plan": [vp, P(he_fmap), c_int, c_int, P(he_layer_plan)],
             "he_avgpool": [vp, P(he_ct), P(he_fmap), c_int, c_int, P(he_pt), c_int, P(he_ct), P(he_fmap), vp],
             "he_fc_plan": [vp, c_int, c_int, P(he_layer_plan)],
@@ -423,11 +453,13 @@ class Context:
         _check(lib().he_conv2d_plan(self.h, ctypes.byref(fm), out_ch, kernel, stride, padding, ctypes.byref(pl)))
         return pl
 
-    def conv2d(self, ct, fm, out_ch, kernel, stride, padding, kernel_pts, mask_pts, out=None, stream=None):
+    def conv2d(self, ct, fm, out_ch, kernel, stride, padding, kernel_pts, mask_pts, out=None, stream=None,
+               bias_pt=None):
         out = out or self.new_ct(ct.cap)
         a, o, om = ct.c(), out.c(), he_fmap()
+        b = ctypes.byref(bias_pt.c()) if bias_pt is not None else None
         _check(lib().he_conv2d(self.h, ctypes.byref(a), ctypes.byref(fm), out_ch, kernel, stride, padding,
-                               _pts(kernel_pts), len(kernel_pts), _pts(mask_pts), len(mask_pts), ctypes.byref(o),
+                               _pts(kernel_pts), len(kernel_pts), _pts(mask_pts), len(mask_pts), b, ctypes.byref(o),
                                ctypes.byref(om), _stream(stream)))
         out.update(o)
         return out, om

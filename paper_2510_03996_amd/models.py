@@ -42,6 +42,41 @@ def lenet_chain(ctx, kern_pts, pool_pts, delta):
     return Chain(ctx, stages, keys, (pc.n_kernel_pts, pp.n_mask_pts), pc.levels + 3 + pp.levels, relin=True)
 
 
+def lenet_vectors(conv_weights, mask_chains=he.CHAIN_HORNER, log_n=14):
+    """The real slot vectors of the LeNet-shaped stack from the library's
+    plaintext recipes (he_layer_plaintexts), in the order lenet_chain takes
+    them: conv 5x5 1->6 kernel vectors (conv_weights [6][1][5][5]) and the
+    2x2 / stride-2 pooling masks.  The model owner encodes them (CKKS
+    encoding at the input level and the working scale) into kern_pts and
+    pool_pts."""
+    fm0 = he.fmap(1, 28, 28)
+    kern = he.layer_plaintexts(he.LAYER_CONV, log_n, conv_weights, fm=fm0, out_ch=6, kernel=5, stride=1, padding=0,
+                               mask_chains=mask_chains)
+    fm1 = he.fmap(6, 24, 24, rs=28, cs=28 * 28)
+    pool = he.layer_plaintexts(he.LAYER_AVGPOOL, log_n, fm=fm1, kernel=2, stride=2, mask_chains=mask_chains)
+    return kern, pool
+
+
+def resnet_vectors(wa, wb, wfc, mask_chains=he.CHAIN_HORNER, fc_form=he.FC_ROWS, log_n=16):
+    """The real slot vectors of the ResNet-shaped chain, in the order
+    resnet_chain takes them: conv A (wa [16][16][3][3]) kernel vectors and
+    masks, conv B (wb [32][16][3][3]) kernel vectors and masks, the global
+    pooling masks, the FC (wfc [10][64]) weight vectors and masks."""
+    slots = (1 << log_n) // 2
+    fm0 = he.fmap(16, 32, 32, reps=2)
+    va = he.layer_plaintexts(he.LAYER_CONV, log_n, wa, fm=fm0, out_ch=16, kernel=3, stride=1, padding=1,
+                             mask_chains=mask_chains)
+    fa = he.fmap(16, 32, 32, reps=2 if 2 * 16 * 32 * 32 == slots else 1)
+    vb = he.layer_plaintexts(he.LAYER_CONV, log_n, wb, fm=fa, out_ch=32, kernel=3, stride=2, padding=1,
+                             mask_chains=mask_chains)
+    fb = he.fmap(32, 16, 16)
+    vg = he.layer_plaintexts(he.LAYER_AVGPOOL, log_n, fm=fb, kernel=0, stride=1, mask_chains=mask_chains)
+    vf = he.layer_plaintexts(he.LAYER_FC, log_n, wfc, n_in=64, n_out=10, fc_form=fc_form)
+    na, nb = 9 * 16, 9 * 32
+    nf = 64 if fc_form == he.FC_DIAG else 10
+    return (va[:na], va[na:], vb[:nb], vb[nb:], vg, vf[:nf], vf[nf:])
+
+
 def resnet_plan(ctx):
     fm0 = he.fmap(16, 32, 32, reps=2)
     pa = ctx.conv2d_plan(fm0, 16, 3, 1, 1)

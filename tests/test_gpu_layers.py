@@ -409,3 +409,52 @@ def test_fc_form_errors(gctx):
         assert e.value.name == "HE_EINVAL"
     finally:
         g.fc_form(he.FC_ROWS)
+
+
+@pytest.mark.parametrize("name,case", [
+    ("config0", (1, 8, 8, 1, 1, 3, 1, 1)),       # special, single channel
+    ("config1", (3, 12, 12, 1, 4, 3, 2, 0)),     # generic, channel chain + placement + compaction
+    ("config1", (2, 10, 10, 1, 2, 5, 2, 2)),     # generic 5x5 / s2 / p2
+], ids=["special_n12", "generic_s2_n14", "generic_p2_n14"])
+def test_conv_with_bias_from_library_recipes(gctx, name, case):
+    """The library's own plaintext recipes (he_layer_plaintexts: kernel
+    vectors, masks and the bias vector) drive the GPU convolution; the oracle
+    runs its own recipes (conv_plaintexts, conv_bias_vector).  The vectors are
+    equal, so the oracle-encoded plaintexts and the ciphertexts are too; the
+    decryption matches the FP64 convolution plus bias."""
+    from paper_2510_03996_amd import he
+
+    nc, nh, nw, reps, F, k, S, P = case
+    g = gctx(name)
+    octx, sk, _ = H.oracle_ctx(name)
+    slots = octx.n // 2
+    X = synth.image(60, nc, nh, nw)
+    K = synth.conv_weights(60, F, nc, k, 0.2)
+    b = synth.uniform_slots(61, F, -0.5, 0.5)
+    fm = LY.FMap(nc, nh, nw, reps=reps)
+    plan = g.conv2d_plan(fm_he(fm), F, k, S, P)
+    vecs = he.layer_plaintexts(he.LAYER_CONV, octx.pr.log_n, K, b, fm=fm_he(fm), out_ch=F, kernel=k, stride=S,
+                               padding=P)
+    assert vecs.shape[0] == plan.n_kernel_pts + plan.n_mask_pts + 1
+    ev = setup_keys(g, name, plan.keys())
+    ct = encrypt_map(name, X, fm, 62)
+    L = ct.level
+    kern, masks = LY.conv_plaintexts(fm, K, S, P, slots)
+    fo = LY.conv_out_map(fm, F, k, S, P, slots)
+    out_level = L - plan.levels
+    # oracle: its own vectors; the bias at the output's scale and level
+    y0, _ = LY.conv2d(ev, ct, fm, F, k, S, P, encode(octx, kern, L), encode(octx, masks, L), slots)
+    bias_o = octx.encode(LY.conv_bias_vector(fo, b, slots), y0.scale, out_level)
+    want = octx.add_plain(y0, bias_o)
+    # GPU: the library's vectors, encoded by the same encoder
+    nk = plan.n_kernel_pts
+    gk = gpts(g, encode(octx, list(vecs[:nk]), L))
+    gm = gpts(g, encode(octx, list(vecs[nk:nk + plan.n_mask_pts]), L))
+    gb = g.pt_from_numpy(octx.encode(vecs[-1], y0.scale, out_level).data, y0.scale)
+    got, gfm = g.conv2d(g.ct_from_numpy(ct.data, ct.scale), fm_he(fm), F, k, S, P, gk, gm, bias_pt=gb)
+    torch.cuda.synchronize()
+    assert gfm.key() == fo.key()
+    check_ct(got, want, "conv2d + bias")
+    dec = LY.unpack(octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale)), fo)
+    err = np.max(np.abs(dec - LY.conv2d_ref(X, K, S, P, bias=b)))
+    assert err < 1e-3, err

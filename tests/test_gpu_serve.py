@@ -24,9 +24,11 @@ def lenet_real(name="config1"):
     g.key_upload(he.KEY_RELIN, H.oracle_key(name, "relin"))
     K = synth.conv_weights(40, 6, 1, 5, 0.1)
     fm = LY.FMap(1, 28, 28)
-    kern, _ = LY.conv_plaintexts(fm, K, 1, 0, slots)
     f1 = LY.conv_out_map(fm, 6, 5, 1, 0, slots)
-    pool = LY.avgpool_plaintexts(f1, 2, 2, slots)
+    # the library's own recipes (equal to the oracle's, tests/test_host_plaintexts.py);
+    # the client-side encoding is the oracle's
+    kern, pool = models.lenet_vectors(K)
+    assert len(kern) == pc.n_kernel_pts and len(pool) == pp.n_mask_pts
     L = octx.pr.L
     kp = [g.pt_from_numpy(octx.encode(v, octx.pr.scale, L).data, octx.pr.scale) for v in kern]
     mp = [g.pt_from_numpy(octx.encode(v, octx.pr.scale, L).data, octx.pr.scale) for v in pool]

@@ -1,0 +1,122 @@
+"""he_layer_plaintexts (the library's host-side plaintext recipes) against
+the oracle's layer plaintext builders, element for element, for every layer
+schedule and option the layers take: special and generic convolutions
+(strides 1 and 2, paddings up to (k-1)/2, replicated and single maps, with
+and without bias), window and global pooling, both FC forms, Horner and
+baby-step giant-step mask chains, and the Chebyshev scale mask.  Host only
+(the library loads without a GPU)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import layers as LY
+
+pytest.importorskip("torch")
+he = pytest.importorskip("paper_2510_03996_amd.he")
+
+
+def lib_ok():
+    import os
+
+    return os.path.exists(he.LIB_PATH)
+
+
+pytestmark = pytest.mark.skipif(not lib_ok(), reason="libfheon_hip.so not built")
+
+CONVS = [  # (log_n, C, H, W, reps, F, k, stride, padding)
+    (12, 1, 8, 8, 1, 1, 3, 1, 1),        # tiny conv (special, single channel)
+    (12, 1, 8, 8, 1, 1, 3, 2, 1),        # special, stride 2
+    (16, 16, 32, 32, 2, 16, 3, 1, 1),    # ResNet conv A (special, replicated)
+    (16, 16, 32, 32, 2, 32, 3, 2, 1),    # ResNet conv B (special, stride 2)
+    (14, 1, 28, 28, 1, 6, 5, 1, 0),      # LeNet conv (generic, C = 1)
+    (14, 3, 16, 16, 1, 2, 7, 2, 3),      # 7x7 / s2 / p3 (generic, padded)
+    (14, 4, 12, 12, 1, 3, 3, 1, 1),      # generic 3x3 p1 on a map that is not replicated
+    (14, 2, 10, 10, 1, 2, 5, 2, 2),      # generic 5x5 / s2 / p2
+    (14, 2, 9, 9, 1, 3, 3, 3, 0),        # stride 3, no padding
+]
+
+
+def hfm(C, H, W, reps):
+    return he.fmap(C, H, W, reps=reps)
+
+
+@pytest.mark.parametrize("case", CONVS, ids=lambda c: "n%d_%dx%dx%d_F%d_k%d_s%d_p%d" % (c[0], c[1], c[2], c[3], c[5], c[6], c[7], c[8]))
+@pytest.mark.parametrize("bsgs", [False, True], ids=["horner", "bsgs"])
+def test_conv_plaintexts_match_oracle(case, bsgs):
+    log_n, C, H, W, reps, F, k, S, P = case
+    slots = (1 << log_n) // 2
+    K = synth.conv_weights(log_n * 7 + F, F, C, k, 0.1)
+    b = synth.uniform_slots(F, F)
+    got = he.layer_plaintexts(he.LAYER_CONV, log_n, K, b, fm=hfm(C, H, W, reps), out_ch=F, kernel=k, stride=S,
+                              padding=P, mask_chains=int(bsgs))
+    fm = LY.FMap(C, H, W, reps=reps)
+    kern, masks = LY.conv_plaintexts(fm, K, S, P, slots, bsgs)
+    fo = LY.conv_out_map(fm, F, k, S, P, slots)
+    want = kern + masks + [LY.conv_bias_vector(fo, b, slots)]
+    assert got.shape == (len(want), slots)
+    for i, w in enumerate(want):
+        assert np.array_equal(got[i], w), "vector %d of %d" % (i, len(want))
+    # without a bias the vector is left out
+    nb = he.layer_plaintexts(he.LAYER_CONV, log_n, K, None, fm=hfm(C, H, W, reps), out_ch=F, kernel=k, stride=S,
+                             padding=P, mask_chains=int(bsgs))
+    assert nb.shape[0] == len(want) - 1
+
+
+POOLS = [  # (log_n, C, H, W, k, stride)
+    (14, 6, 24, 24, 2, 2),    # LeNet pooling
+    (14, 3, 10, 10, 2, 1),    # stride 1
+    (14, 2, 12, 12, 3, 3),    # 3x3 / 3
+    (16, 32, 16, 16, 0, 1),   # global pooling (ResNet chain)
+    (16, 64, 8, 8, 0, 1),     # global pooling (ResNet-20's 64x8x8)
+]
+
+
+@pytest.mark.parametrize("case", POOLS, ids=lambda c: "n%d_%dx%dx%d_k%d_s%d" % c)
+@pytest.mark.parametrize("bsgs", [False, True], ids=["horner", "bsgs"])
+def test_pool_plaintexts_match_oracle(case, bsgs):
+    log_n, C, H, W, k, S = case
+    slots = (1 << log_n) // 2
+    got = he.layer_plaintexts(he.LAYER_AVGPOOL, log_n, fm=hfm(C, H, W, 1), kernel=k, stride=S,
+                              mask_chains=int(bsgs))
+    fm = LY.FMap(C, H, W)
+    want = LY.gap_plaintexts(fm, slots, bsgs) if k == 0 else LY.avgpool_plaintexts(fm, k, S, slots, bsgs)
+    assert got.shape == (len(want), slots)
+    for i, w in enumerate(want):
+        assert np.array_equal(got[i], w), "vector %d" % i
+
+
+@pytest.mark.parametrize("n_in,n_out", [(64, 10), (16, 16), (8, 1), (4, 3)])
+@pytest.mark.parametrize("form", [0, 1], ids=["rows", "diag"])
+def test_fc_plaintexts_match_oracle(n_in, n_out, form):
+    log_n = 14
+    slots = (1 << log_n) // 2
+    Wm = synth.fc_weights(n_in + n_out, n_out, n_in, 0.2)
+    b = synth.uniform_slots(n_out, n_out)
+    got = he.layer_plaintexts(he.LAYER_FC, log_n, Wm, b, n_in=n_in, n_out=n_out, fc_form=form)
+    if form == 0:
+        rows, masks = LY.fc_plaintexts(Wm, slots)
+        want = rows + masks
+    else:
+        want = LY.fc_diag_plaintexts(Wm, slots)
+    bias = np.zeros(slots)
+    bias[:n_out] = b
+    want = want + [bias]
+    assert got.shape == (len(want), slots)
+    for i, w in enumerate(want):
+        assert np.array_equal(got[i], w), "vector %d" % i
+
+
+def test_cheb_scale_mask():
+    got = he.layer_plaintexts(he.LAYER_CHEB_MASK, 16, n_in=1024, beta=4.0)
+    want = np.zeros(1 << 15)
+    want[:1024] = 0.25
+    assert got.shape == (1, 1 << 15) and np.array_equal(got[0], want)
+
+
+def test_recipe_counts_follow_the_plan_and_errors():
+    # padding beyond (k-1)/2 is rejected as by the layer itself
+    with pytest.raises(he.HEError):
+        he.layer_plaintexts(he.LAYER_CONV, 14, np.zeros((1, 1, 3, 3)), fm=hfm(1, 8, 8, 1), out_ch=1, kernel=3,
+                            stride=1, padding=2)
+    with pytest.raises(he.HEError):
+        he.layer_plaintexts(he.LAYER_FC, 14, np.zeros((3, 6)), n_in=6, n_out=3)  # n_in not a power of two

@@ -641,7 +641,18 @@ def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logst
 
 
 # ===================================================================== pooling
+def pool_whole_channel(fm, k):
+    """The pooling special case: the window covers the whole (square, dense,
+    power-of-two) channel, one output per channel, so the layer is the
+    global schedule (channel sum, 1/k^2, each channel's first value
+    gathered with one key)."""
+    return (k > 0 and k == fm.H == fm.W and fm.rs == fm.W and fm.cs == fm.H * fm.W
+            and fm.cs & (fm.cs - 1) == 0)
+
+
 def avgpool_plaintexts(fm, k, stride, slots, bsgs=False):
+    if pool_whole_channel(fm, k):
+        return gap_plaintexts(fm, slots, bsgs)
     H1, W1 = fm.H - k + 1, fm.W - k + 1
     Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
     if stride == 1:
@@ -654,6 +665,8 @@ def avgpool_plaintexts(fm, k, stride, slots, bsgs=False):
 
 
 def avgpool_rotations(fm, k, stride, bsgs=False):
+    if pool_whole_channel(fm, k):
+        return gap_rotations(fm, bsgs)
     keys = {i * fm.rs + j for i in range(k) for j in range(k) if (i, j) != (0, 0)}
     if stride > 1:
         H1, W1 = fm.H - k + 1, fm.W - k + 1
@@ -664,7 +677,10 @@ def avgpool_rotations(fm, k, stride, bsgs=False):
 
 def avgpool(ev, x, fm, k, stride, masks, bsgs=False):
     """Window sum by one hoisted group of the k^2-1 offsets i rs + j, then the
-    stride compaction with 1/k^2 folded into the column masks."""
+    stride compaction with 1/k^2 folded into the column masks; a window over
+    the whole channel is the global schedule (pool_whole_channel)."""
+    if pool_whole_channel(fm, k):
+        return gap(ev, x, fm, masks, bsgs)
     offs = [i * fm.rs + j for i in range(k) for j in range(k)]
     s = x
     for r in ev.rot_hoisted(x, offs[1:]):

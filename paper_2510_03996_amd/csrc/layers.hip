@@ -507,8 +507,18 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
 }
 
 // ---------------------------------------------------------------- pooling plan
+// The pooling special case (section "Secure Average Pooling Layer"): a
+// window covering the whole (square, dense) channel gives one value per
+// channel, i.e. the global schedule: the channel's sum by log-step rotations,
+// 1/k^2 and each channel's first value gathered with one key.
+static bool pool_whole_channel(const he_fmap& fm, int k) {
+  return k > 0 && k == fm.height && k == fm.width && fm.row_stride == fm.width &&
+         fm.chan_stride == fm.height * fm.width && (fm.chan_stride & (fm.chan_stride - 1)) == 0;
+}
+
 static int pool_plan(const Ctx* c, const he_fmap* fm, int k, int S, he_layer_plan* pl) {
   if (!fm || !pl || k < 0 || S < 1) return set_error(HE_EINVAL, "bad pooling arguments");
+  if (pool_whole_channel(*fm, k)) k = 0;
   *pl = he_layer_plan{};
   std::vector<int> keys;
   int ks = 0;
@@ -550,7 +560,7 @@ static int pool_plan(const Ctx* c, const he_fmap* fm, int k, int S, he_layer_pla
 
 static he_ct pool_run(Ev& ev, const he_ct& x, const he_fmap& fm, int k, int S, const he_pt* masks,
                       he_fmap* out_map) {
-  if (k == 0) {
+  if (k == 0 || pool_whole_channel(fm, k)) {
     const int cs = fm.chan_stride;
     he_ct Ssum = ev.copy(x);
     for (int t = 1; t < cs; t <<= 1) Ssum = ev.add_take(Ssum, ev.rot(Ssum, t));
@@ -888,7 +898,7 @@ static int pool_vectors(const Ctx* c, const he_fmap& fm, int k, int S, Vecs& out
   int rc;
   if ((rc = pool_plan(c, &fm, k, S, &pl))) return rc;
   const int slots = c->n / 2;
-  if (k == 0) {
+  if (k == 0 || pool_whole_channel(fm, k)) {
     Vecs v;
     for (int ch = 0; ch < fm.channels; ch++) {
       std::vector<double> m = zeros(slots);

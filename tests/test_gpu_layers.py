@@ -189,6 +189,30 @@ def test_config2_global_avgpool(gctx, C, HW, level):
     assert np.max(np.abs(dec[:C] - LY.gap_ref(X))) < 1e-3
 
 
+def test_config1_pool_whole_channel(gctx):
+    """A k = H = W window takes the global schedule (pooling special case)."""
+    name = "config1"
+    g = gctx(name)
+    octx, sk, _ = H.oracle_ctx(name)
+    slots = octx.n // 2
+    C, HW = 16, 8
+    X = synth.image(27, C, HW, HW)
+    fm = LY.FMap(C, HW, HW)
+    plan = g.avgpool_plan(fm_he(fm), HW, HW)
+    assert sorted(plan.keys()) == LY.avgpool_rotations(fm, HW, HW) == LY.gap_rotations(fm)
+    assert plan.levels == 1
+    ev = setup_keys(g, name, plan.keys())
+    ct = encrypt_map(name, X, fm, 27, 5)
+    mp = encode(octx, LY.avgpool_plaintexts(fm, HW, HW, slots), ct.level)
+    want, fo = LY.avgpool(ev, ct, fm, HW, HW, mp)
+    got, gfo = g.avgpool(g.ct_from_numpy(ct.data, ct.scale), fm_he(fm), HW, HW, gpts(g, mp))
+    assert ev.ks == plan.key_switches
+    assert (gfo.channels, gfo.height, gfo.width) == (C, 1, 1)
+    check_ct(got, want, "whole-channel avgpool")
+    dec = octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale))
+    assert np.max(np.abs(dec[:C] - LY.avgpool_ref(X, HW, HW).reshape(-1))) < 1e-3
+
+
 def test_config2_fc(gctx):
     name = "config2"
     g = gctx(name)

@@ -68,6 +68,7 @@ POOLS = [  # (log_n, C, H, W, k, stride)
     (14, 2, 12, 12, 3, 3),    # 3x3 / 3
     (16, 32, 16, 16, 0, 1),   # global pooling (ResNet chain)
     (16, 64, 8, 8, 0, 1),     # global pooling (ResNet-20's 64x8x8)
+    (14, 16, 8, 8, 8, 8),     # window over the whole channel (global schedule)
 ]
 
 

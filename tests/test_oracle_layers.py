@@ -148,6 +148,28 @@ def test_sim_gap(C, HW, ks):
     assert np.max(np.abs(y.v[:C] - LY.gap_ref(X))) < 1e-12 and np.max(np.abs(y.v[C:])) < 1e-12
 
 
+@pytest.mark.parametrize("C,HW", [(4, 8), (16, 4), (2, 16)])
+def test_sim_pool_whole_channel(C, HW):
+    """The pooling special case: a k = H = W window is the global schedule
+    (log2(H W) sum rotations plus a one-key gather, not k^2 - 1 window
+    rotations and a compaction) and still equals the window average."""
+    slots = 8192
+    X = synth.image(7, C, HW, HW)
+    fm = LY.FMap(C, HW, HW)
+    assert LY.pool_whole_channel(fm, HW) and not LY.pool_whole_channel(fm, HW - 1)
+    assert not LY.pool_whole_channel(LY.FMap(C, HW, HW, 2 * HW, 2 * HW * HW), HW)
+    ev = sim(slots)
+    pm = LY.avgpool_plaintexts(fm, HW, HW, slots)
+    assert len(pm) == C
+    y, fo = LY.avgpool(ev, LY.SimCt(LY.pack(X, fm, slots), 10), fm, HW, HW, pm)
+    steps = int(np.log2(HW * HW))
+    assert fo == LY.FMap(C, 1, 1, 1, 1, 1) and y.level == 9 and ev.ks == steps + C - 1
+    ref = LY.avgpool_ref(X, HW, HW)
+    assert np.max(np.abs(LY.unpack(y.v, fo) - ref)) < 1e-12 and np.max(np.abs(y.v[C:])) < 1e-12
+    keys = LY.avgpool_rotations(fm, HW, HW)
+    assert keys == sorted({1 << t for t in range(steps)} | {HW * HW - 1})
+
+
 def test_sim_fc():
     slots = 32768
     x = np.zeros(64)

@@ -321,7 +321,14 @@ int he_layer_plaintexts(const he_layer_desc* desc, const double* weights, const 
  * (reps = 2) or has one channel in and out (special schedule; stride 1 or 2),
  * and every other padding 0 <= P <= (k-1)/2 with any kernel and stride
  * (generic schedule: the zero padding is realised by the kernel vectors, so
- * the output keeps the input's layout).  Larger paddings: HE_EUNSUPPORTED.
+ * the output keeps the input's layout).  Larger paddings (section "Secure
+ * Advanced Convolution With Padding"): the input is first re-laid out as the
+ * padded tensor X_p, (C, H+2P, W+2P) flattened densely (row stride W+2P,
+ * channel block (H+2P)(W+2P)), by masked chains over the rows (key
+ * rs - (W+2P)) and the channels (key cs - (H+2P)(W+2P)), each only when it
+ * moves data (else one clearing mask), and one rotation by -(P (W+2P) + P);
+ * the generic schedule with P = 0 then runs on X_p.  C (H+2P)(W+2P) must fit
+ * the slots; a layer needing more than 64 rotation keys: HE_EUNSUPPORTED.
  * Plaintexts (NTT form, at least the input level in limbs, encoded at one
  * common scale), in this order:
  *  special: kernel_pts[9 f + t], t = 3 (dy+1) + (dx+1): K[f, b mod C, t] on
@@ -337,6 +344,12 @@ int he_layer_plaintexts(const he_layer_desc* desc, const double* weights, const 
  *    Wo column masks (1 at c*cs + S i rs + S j, all c, i), Ho row masks
  *    (1 at c*cs + S i rs + j, j < Wo), then C channel masks (1 on
  *    c*cs + [0, Ho*Wo)) — each step only when it moves data.
+ *  padded (P > (k-1)/2): kernel_pts as generic for X_p with P = 0; mask_pts:
+ *    first the re-layout masks at the input level (channel step: C masks,
+ *    1 on channel c's image; row step: H masks, 1 on row y of every
+ *    channel; each on the layout its step sees, in the step order of the
+ *    plan; or the one clearing mask of the whole image), then the generic
+ *    masks for X_p.
  * The result is rescaled after every multiplicative level. */
 int he_conv2d_plan(const he_ctx* ctx, const he_fmap* in_map, int out_ch, int kernel, int stride, int padding,
                    he_layer_plan* plan);

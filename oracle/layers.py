@@ -400,13 +400,107 @@ def conv_kind(k, padding, fm=None, F=1):
     """special: 3x3, padding 1 on a dense square map that is replicated (or a
     single channel in and out); generic: any padding 0 <= P <= (k-1)/2 (the
     zero padding is realised by masking every tap whose neighbour falls
-    outside the image, so the output fits the input's layout)."""
+    outside the image, so the output fits the input's layout); padded: any
+    larger padding, where the output is wider than the input, so the input
+    is first re-laid out as the padded tensor X_p (pad_layout) and the
+    generic schedule runs on it with P = 0."""
+    if padding < 0:
+        raise ValueError("negative padding")
     if k == 3 and padding == 1 and (fm is None or (
             fm.H == fm.W and fm.rs == fm.W and fm.cs == fm.W * fm.W and (fm.reps == 2 or (fm.C == 1 and F == 1)))):
         return "special"
-    if 0 <= padding <= (k - 1) // 2:
+    if padding <= (k - 1) // 2:
         return "generic"
-    raise NotImplementedError("padding beyond (k-1)/2 is not part of the pinned schedules")
+    return "padded"
+
+
+def padded_map(fm, P):
+    """X_p's layout: (C, H + 2P, W + 2P) flattened densely, row stride
+    W_p = W + 2P and channel block H_p W_p (section "Secure Advanced
+    Convolution With Padding", equations for H_p and W_p)."""
+    Hp, Wp = fm.H + 2 * P, fm.W + 2 * P
+    return FMap(fm.C, Hp, Wp, Wp, Hp * Wp, 1)
+
+
+def pad_plan(fm, P):
+    """Steps that move X[c, y, x] from c cs + y rs + x to
+    c cs' + (y + P) W_p + (x + P), zeros everywhere else in the blocks.
+
+    The paper's reading: rows are spread apart with one rotation amount (the
+    flattened rows are adjacent, so spreading them by 2P opens the left and
+    right padding of neighbouring rows at once), channels are spread to their
+    padded blocks, and one last rotation by W_p + P opens the top rows and
+    the first row's left padding.  Here the row and channel spreads are
+    masked chains (Horner with a single key each: rows key rs - W_p over
+    the H rows, channels key cs - cs' over the C channels), one level each,
+    so the layout needs three keys where the paper's per-channel rotations
+    need C + 3.  Returns ([(step, count, key)], shift key, X_p's map): the
+    channel step comes first when the blocks grow (rows then fit in them),
+    the row step first otherwise; with neither needed one mask still clears
+    whatever lies outside the image."""
+    fp = padded_map(fm, P)
+    rows = ("row", fm.H, fm.rs - fp.rs) if fm.rs != fp.rs else None
+    chan = ("chan", fm.C, fm.cs - fp.cs) if fm.C > 1 and fm.cs != fp.cs else None
+    if chan and rows:
+        if (fm.H - 1) * fm.rs + fm.W <= fp.cs:
+            steps = [chan, rows]
+        elif (fm.H - 1) * fp.rs + fm.W <= fm.cs:
+            steps = [rows, chan]
+        else:
+            raise NotImplementedError("the input layout leaves no room to re-lay out its rows")
+    elif chan or rows:
+        steps = [chan or rows]
+    else:
+        steps = [("clear", 1, 0)]
+    return steps, -(P * fp.rs + P), fp
+
+
+def pad_masks(fm, P, slots, bsgs=False):
+    """Masks of pad_plan's steps, on the layout each step sees: channel t's
+    image (t cs' or t cs + y rs + x), row t of every channel, or the whole
+    image for the clearing step."""
+    steps, _, fp = pad_plan(fm, P)
+    if fm.C * fp.cs > slots:
+        raise ValueError("the padded channels do not fit the slots")
+    rs, cs = fm.rs, fm.cs
+    out = []
+    for step, n, key in steps:
+        vecs = []
+        for t in range(n):
+            m = np.zeros(slots)
+            for c in range(fm.C):
+                for y in range(fm.H):
+                    if (step == "chan" and c != t) or (step == "row" and y != t):
+                        continue
+                    base = c * cs + y * rs
+                    m[base:base + fm.W] = 1.0
+            vecs.append(m)
+        out += chain_masks(vecs, key, bsgs) if n > 1 else vecs
+        if step == "chan":
+            cs = fp.cs
+        elif step == "row":
+            rs = fp.rs
+    return out
+
+
+def pad_keys(fm, P, bsgs=False):
+    steps, shift, _ = pad_plan(fm, P)
+    keys = {shift}
+    for _, n, key in steps:
+        keys |= masked_chain_keys(n, key, bsgs)
+    return keys
+
+
+def pad_layout(ev, x, fm, P, masks, bsgs=False):
+    """X_p = Rot_{-(P W_p + P)}(chains of pad_plan applied to x); returns
+    (X_p, its map).  Levels: one per step."""
+    steps, shift, fp = pad_plan(fm, P)
+    pos = 0
+    for _, n, key in steps:
+        x = masked_chain(ev, x, masks[pos:pos + n], n, key, bsgs)
+        pos += n
+    assert pos == len(masks)
+    return ev.rot(x, shift), fp
 
 
 def conv_taps(fm, k, padding):
@@ -421,6 +515,8 @@ def conv_dims(fm, k, padding):
 
 def conv_out_map(fm, F, k, stride, padding, slots):
     kind = conv_kind(k, padding, fm, F)
+    if kind == "padded":
+        return conv_out_map(padded_map(fm, padding), F, k, stride, 0, slots)
     if kind == "special":
         W = fm.W
         if stride == 1:
@@ -441,6 +537,9 @@ def conv_plaintexts(fm, K, stride, padding, slots, bsgs=False):
     F, C, k, _ = K.shape
     assert C == fm.C
     kind = conv_kind(k, padding, fm, F)
+    if kind == "padded":
+        kern, masks = conv_plaintexts(padded_map(fm, padding), K, stride, 0, slots, bsgs)
+        return kern, pad_masks(fm, padding, slots, bsgs) + masks
     kern, masks = [], []
     if kind == "special":
         W = fm.W
@@ -526,6 +625,9 @@ def channel_sum(ev, A, C, step, logstep=False):
 def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False):
     """Distinct rotation keys the schedule uses (the paper's per-layer index helper)."""
     kind = conv_kind(k, padding, fm, F)
+    if kind == "padded":
+        return sorted(pad_keys(fm, padding, bsgs) |
+                      set(conv_rotations(padded_map(fm, padding), F, k, stride, 0, slots, logstep, bsgs)))
     keys = set()
     if kind == "special":
         W = fm.W
@@ -584,8 +686,15 @@ def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logst
       in the padding; A_f = RS(sum r (.) kv); C > 1: channel_sum with step cs,
       then RS(. (.) block-0 mask); out-channels placed by a Horner chain with
       key -cs; stride > 1: joint compaction.
+    padded (P > (k-1)/2): X_p = pad_layout(x) with the first pad masks, then
+      the generic schedule with P = 0 on X_p's map and the remaining
+      plaintexts.
     """
     kind = conv_kind(k, padding, fm, F)
+    if kind == "padded":
+        npad = len(pad_masks(fm, padding, slots, bsgs))
+        xp, fp = pad_layout(ev, x, fm, padding, masks[:npad], bsgs)
+        return _conv2d_schedule(ev, xp, fp, F, k, stride, 0, kern, masks[npad:], slots, logstep, bsgs)
     C = fm.C
     if kind == "special":
         W = fm.W

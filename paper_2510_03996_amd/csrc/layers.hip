@@ -276,6 +276,14 @@ static void add_keys(std::vector<int>& keys, int k) {
   keys.push_back(k);
 }
 
+// a plan lists its keys in he_layer_plan's 64 entries
+static int plan_keys_out(he_layer_plan* pl, const std::vector<int>& keys) {
+  if (keys.size() > 64) return set_error(HE_EUNSUPPORTED, "the layer needs more than 64 rotation keys");
+  pl->n_keys = (int)keys.size();
+  for (int i = 0; i < pl->n_keys; i++) pl->rot_keys[i] = keys[i];
+  return HE_OK;
+}
+
 // ---------------------------------------------------------------- conv plan
 // The special schedule (Algorithm 1's rotation tree) covers 3x3 / padding 1
 // on a dense square map that is replicated, or one channel in and out; any
@@ -335,11 +343,83 @@ static he_ct channel_sum(Ev& ev, const he_ct& A, int C, int step) {
   return S;
 }
 
+// ---------------------------------------------------------------- padding by re-layout
+// Padding beyond (k-1)/2 (section "Secure Advanced Convolution With
+// Padding"): the output is wider than the input, so the input is re-laid out
+// as the padded tensor X_p, (C, H + 2P, W + 2P) flattened densely (row
+// stride W_p = W + 2P, channel block H_p W_p), and the generic schedule runs
+// on it with P = 0.  Rows are spread by one rotation amount (rs - W_p) and
+// channels by another (cs - H_p W_p), each a masked chain of one level, and
+// one rotation by -(P W_p + P) opens the top padding: three keys.
+static he_fmap padded_map(const he_fmap& fm, int P) {
+  const int Hp = fm.height + 2 * P, Wp = fm.width + 2 * P;
+  return he_fmap{fm.channels, Hp, Wp, Wp, Hp * Wp, 1};
+}
+static bool conv_padded(const he_fmap& fm, int F, int k, int P) {
+  return !conv_special(fm, F, k, P) && P > (k - 1) / 2;
+}
+// Step kinds here: 1 rows (n = H), 2 channels (n = C), 3 a clearing mask
+// (n = 1).  Channels go first when their blocks grow enough to hold the
+// rows at the input's row stride, rows first otherwise.
+static int pad_plan(const he_fmap& fm, int P, std::vector<Step>& st, int* shift) {
+  const he_fmap fp = padded_map(fm, P);
+  const bool rows = fm.row_stride != fp.row_stride;
+  const bool chan = fm.channels > 1 && fm.chan_stride != fp.chan_stride;
+  const Step r{1, fm.height, fm.row_stride - fp.row_stride};
+  const Step ch{2, fm.channels, fm.chan_stride - fp.chan_stride};
+  st.clear();
+  if (rows && chan) {
+    if ((long)(fm.height - 1) * fm.row_stride + fm.width <= fp.chan_stride) st = {ch, r};
+    else if ((long)(fm.height - 1) * fp.row_stride + fm.width <= fm.chan_stride) st = {r, ch};
+    else return set_error(HE_EUNSUPPORTED, "the input layout leaves no room to re-lay out its rows");
+  } else if (rows) {
+    st = {r};
+  } else if (chan) {
+    st = {ch};
+  } else {
+    st = {Step{3, 1, 0}};
+  }
+  *shift = -(P * fp.row_stride + P);
+  return HE_OK;
+}
+static int pad_mask_count(const he_fmap& fm, int F, int k, int P) {
+  if (!conv_padded(fm, F, k, P)) return 0;
+  std::vector<Step> st;
+  int shift;
+  if (pad_plan(fm, P, st, &shift)) return 0;
+  return compaction_masks(st);
+}
+static he_ct pad_run(Ev& ev, const he_ct& x, const he_fmap& fm, int P, const he_pt* masks) {
+  std::vector<Step> st;
+  int shift;
+  ck(pad_plan(fm, P, st, &shift));
+  he_ct cur = x;
+  int pos = 0;
+  for (const Step& s : st) {
+    he_ct nxt = horner_masked(ev, cur, masks + pos, s.n, s.key);
+    if (pos > 0) ev.release(cur);
+    cur = nxt;
+    pos += s.n;
+  }
+  return ev.rot_take(cur, shift);
+}
+
+static int conv_plan_keys(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P, he_layer_plan* pl,
+                          std::vector<int>& keys);
+
 static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P, he_layer_plan* pl) {
-  if (!fm || !pl || F < 1 || k < 1 || S < 1) return set_error(HE_EINVAL, "bad convolution arguments");
+  std::vector<int> keys;
+  const int rc = conv_plan_keys(c, fm, F, k, S, P, pl, keys);
+  if (rc) return rc;
+  return plan_keys_out(pl, keys);
+}
+
+// the plan without its key list, the keys appended to `keys`
+static int conv_plan_keys(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P, he_layer_plan* pl,
+                          std::vector<int>& keys) {
+  if (!fm || !pl || F < 1 || k < 1 || S < 1 || P < 0) return set_error(HE_EINVAL, "bad convolution arguments");
   const int slots = c->n / 2;
   const int C = fm->channels;
-  std::vector<int> keys;
   *pl = he_layer_plan{};
   int ks = 0, lv = 0, nmask = 0;
   if (conv_special(*fm, F, k, P)) {
@@ -384,19 +464,40 @@ static int conv_plan(const Ctx* c, const he_fmap* fm, int F, int k, int S, int P
     }
     pl->n_kernel_pts = k * k * F;
   } else {
-    return set_error(HE_EUNSUPPORTED, "padding must be in [0, (k-1)/2]");
+    // P > (k-1)/2: X_p by re-layout, then the generic schedule with P = 0
+    const he_fmap fp = padded_map(*fm, P);
+    if ((long)C * fp.chan_stride > slots) return set_error(HE_EINVAL, "the padded channels do not fit the slots");
+    std::vector<Step> st;
+    int shift, rc;
+    if ((rc = pad_plan(*fm, P, st, &shift))) return rc;
+    for (auto& x : st) { chain_keys(c, keys, x.n, x.key); ks += chain_switches(c, x.n); lv++; }
+    nmask = compaction_masks(st);
+    add_keys(keys, shift);
+    ks++;
+    he_layer_plan sub;
+    if ((rc = conv_plan_keys(c, &fp, F, k, S, 0, &sub, keys))) return rc;
+    ks += sub.key_switches;
+    lv += sub.levels;
+    nmask += sub.n_mask_pts;
+    pl->out = sub.out;
+    pl->n_kernel_pts = sub.n_kernel_pts;
   }
   pl->n_mask_pts = nmask;
   pl->levels = lv;
   pl->key_switches = ks;
-  pl->n_keys = (int)keys.size();
-  for (int i = 0; i < pl->n_keys && i < 64; i++) pl->rot_keys[i] = keys[i];
   return HE_OK;
 }
 
 static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, int S, int P, const he_pt* kern,
                       const he_pt* masks, he_fmap* out_map) {
   const int C = fm.channels;
+  if (conv_padded(fm, F, k, P)) {
+    const int npad = pad_mask_count(fm, F, k, P);
+    he_ct xp = pad_run(ev, x, fm, P, masks);
+    he_ct y = conv_run(ev, xp, padded_map(fm, P), F, k, S, 0, kern, masks + npad, out_map);
+    ev.release(xp);
+    return y;
+  }
   if (conv_special(fm, F, k, P)) {
     const int W = fm.width;
     auto g1 = ev.rot_hoisted(x, {-W, W, -1, 1});  // r1, r7, r3, r5
@@ -553,9 +654,7 @@ static int pool_plan(const Ctx* c, const he_fmap* fm, int k, int S, he_layer_pla
     }
   }
   pl->key_switches = ks;
-  pl->n_keys = (int)keys.size();
-  for (int i = 0; i < pl->n_keys && i < 64; i++) pl->rot_keys[i] = keys[i];
-  return HE_OK;
+  return plan_keys_out(pl, keys);
 }
 
 static he_ct pool_run(Ev& ev, const he_ct& x, const he_fmap& fm, int k, int S, const he_pt* masks,
@@ -608,9 +707,7 @@ static int fc_plan_impl(const Ctx* c, int n_in, int n_out, he_layer_plan* pl) {
     pl->levels = 1;
     pl->key_switches = ks;
     pl->out = he_fmap{n_out, 1, 1, 1, 1, 1};
-    pl->n_keys = (int)keys.size();
-    for (int i = 0; i < pl->n_keys && i < 64; i++) pl->rot_keys[i] = keys[i];
-    return HE_OK;
+    return plan_keys_out(pl, keys);
   }
   for (int t = 1; t < n_in; t <<= 1) { add_keys(keys, t); ks += n_out; }
   if (n_out > 1) { add_keys(keys, -1); ks += n_out - 1; }
@@ -619,9 +716,7 @@ static int fc_plan_impl(const Ctx* c, int n_in, int n_out, he_layer_plan* pl) {
   pl->levels = 2;
   pl->key_switches = ks;
   pl->out = he_fmap{n_out, 1, 1, 1, 1, 1};
-  pl->n_keys = (int)keys.size();
-  for (int i = 0; i < pl->n_keys && i < 64; i++) pl->rot_keys[i] = keys[i];
-  return HE_OK;
+  return plan_keys_out(pl, keys);
 }
 
 // ---------------------------------------------------------------- Chebyshev secure ReLU
@@ -831,6 +926,38 @@ static int conv_vectors(const Ctx* c, const he_fmap& fm, int F, int k, int S, in
   if ((rc = conv_plan(c, &fm, F, k, S, P, &pl))) return rc;
   const int slots = c->n / 2, C = fm.channels;
   auto w = [&](int f, int ch, int i, int j) { return K[(((size_t)f * C + ch) * k + i) * k + j]; };
+  if (conv_padded(fm, F, k, P)) {
+    // re-layout masks on the layout each step sees, then the P = 0 vectors on X_p
+    std::vector<Step> st;
+    int shift;
+    if ((rc = pad_plan(fm, P, st, &shift))) return rc;
+    Vecs pads;
+    int rs = fm.row_stride, cs = fm.chan_stride;
+    const he_fmap fp = padded_map(fm, P);
+    for (const Step& x : st) {
+      Vecs v;
+      for (int t = 0; t < x.n; t++) {
+        std::vector<double> m = zeros(slots);
+        for (int ch = 0; ch < C; ch++)
+          for (int y = 0; y < fm.height; y++) {
+            if ((x.kind == 2 && ch != t) || (x.kind == 1 && y != t)) continue;
+            const size_t base = (size_t)ch * cs + (size_t)y * rs;
+            for (int j = 0; j < fm.width; j++) m[base + j] = 1.0;
+          }
+        v.push_back(std::move(m));
+      }
+      chain_vectors(c, pads, std::move(v), x.key);
+      if (x.kind == 2) cs = fp.chan_stride;
+      if (x.kind == 1) rs = fp.row_stride;
+    }
+    Vecs rest;
+    if ((rc = conv_vectors(c, fp, F, k, S, 0, K, bias, rest))) return rc;
+    const size_t nk = (size_t)k * k * F;
+    for (size_t i = 0; i < nk; i++) out.push_back(std::move(rest[i]));
+    for (auto& m : pads) out.push_back(std::move(m));
+    for (size_t i = nk; i < rest.size(); i++) out.push_back(std::move(rest[i]));
+    return HE_OK;
+  }
   if (conv_special(fm, F, k, P)) {
     const int W = fm.width, WW = W * W;
     for (int f = 0; f < F; f++)
@@ -1019,7 +1146,10 @@ int he_conv2d(he_ctx* h, const he_ct* in, const he_fmap* in_map, int out_ch, int
   if (in->level <= pl.levels) return set_error(HE_ELEVEL, "not enough levels for the convolution");
   if ((rc = check_out(c, out, in->level - pl.levels))) return rc;
   if ((rc = check_pts(c, kernel_pts, n_kernel_pts, in->level, "kernel_pts"))) return rc;
-  if ((rc = check_pts(c, mask_pts, n_mask_pts, in->level - pl.levels + 1, "mask_pts"))) return rc;
+  const int npad = pad_mask_count(*in_map, out_ch, kernel, padding);  // used at the input level
+  if ((rc = check_pts(c, mask_pts, npad, in->level, "mask_pts")) ||
+      (rc = check_pts(c, mask_pts + npad, n_mask_pts - npad, in->level - pl.levels + 1, "mask_pts")))
+    return rc;
   if (bias_pt && (rc = check_pts(c, bias_pt, 1, in->level - pl.levels, "bias_pt"))) return rc;
   for (int i = 0; i < pl.n_keys; i++)
     if (!key_known(c, pl.rot_keys[i]))

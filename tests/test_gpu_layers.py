@@ -116,6 +116,22 @@ def test_config1_generic_conv_multichannel_stride(gctx):
     run_conv(gctx("config1"), "config1", X, K, LY.FMap(3, 12, 12), 2, 0, 21, streams=(1, 2, 3, 8))
 
 
+@pytest.mark.parametrize("C,F,H,W,rs,cs,k,S,P,bsgs", [
+    (2, 3, 8, 8, None, None, 3, 1, 2, False),    # 3x3 / padding 2: channels then rows, then the shift
+    (3, 2, 10, 10, None, None, 1, 2, 1, True),   # 1x1 / stride 2 / padding 1, baby-step giant-step chains
+    (2, 2, 6, 6, 30, 180, 3, 1, 2, False),       # wide input rows: rows first, then channels
+    (1, 2, 7, 9, None, None, 5, 2, 3, False),    # one channel, rectangular, strided
+])
+def test_config1_relayout_padded_conv(gctx, C, F, H, W, rs, cs, k, S, P, bsgs):
+    """Padding beyond (k-1)/2: the re-layout as X_p and the generic schedule
+    with P = 0, bit for bit against the oracle."""
+    X = synth.image(30 + k, C, H, W)
+    K = synth.conv_weights(30 + k, F, C, k, 0.2)
+    fm = LY.FMap(C, H, W, rs, cs)
+    assert LY.conv_kind(k, P, fm, F) == "padded"
+    run_conv(gctx("config1"), "config1", X, K, fm, S, P, 30 + k, bsgs=bsgs, streams=(1, 2))
+
+
 def test_config1_lenet_stack(gctx):
     """LeNet-5-shaped stack: conv 5x5 1->6 -> degree-4 ReLU -> 2x2 avgpool (7 levels)."""
     name = "config1"
@@ -258,7 +274,7 @@ def test_layer_errors(gctx):
     g = gctx(name)
     fm = he.fmap(1, 28, 28)
     with pytest.raises(he.HEError) as e:
-        g.conv2d_plan(fm, 6, 5, 1, 3)  # padding beyond (k-1)/2
+        g.conv2d_plan(fm, 6, 9, 1, 4)  # 80 tap keys: more than a plan lists
     assert e.value.name == "HE_EUNSUPPORTED"
     _, ct = H.encrypt_slots(name, 28, level=2)
     gct = g.ct_from_numpy(ct.data, ct.scale)

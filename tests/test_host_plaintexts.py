@@ -1,7 +1,7 @@
 """he_layer_plaintexts (the library's host-side plaintext recipes) against
 the oracle's layer plaintext builders, element for element, for every layer
 schedule and option the layers take: special and generic convolutions
-(strides 1 and 2, paddings up to (k-1)/2, replicated and single maps, with
+(strides 1 and 2, paddings up to (k-1)/2 and beyond (re-layout), replicated and single maps, with
 and without bias), window and global pooling, both FC forms, Horner and
 baby-step giant-step mask chains, and the Chebyshev scale mask.  Host only
 (the library loads without a GPU)."""
@@ -33,6 +33,9 @@ CONVS = [  # (log_n, C, H, W, reps, F, k, stride, padding)
     (14, 4, 12, 12, 1, 3, 3, 1, 1),      # generic 3x3 p1 on a map that is not replicated
     (14, 2, 10, 10, 1, 2, 5, 2, 2),      # generic 5x5 / s2 / p2
     (14, 2, 9, 9, 1, 3, 3, 3, 0),        # stride 3, no padding
+    (14, 2, 8, 8, 1, 3, 3, 1, 2),        # padding beyond (k-1)/2: re-layout as X_p
+    (14, 3, 10, 10, 1, 2, 1, 2, 1),      # 1x1 / stride 2 / padding 1 (re-layout)
+    (14, 2, 7, 9, 1, 2, 5, 2, 3),        # rectangular, re-layout, strided
 ]
 
 
@@ -115,9 +118,13 @@ def test_cheb_scale_mask():
 
 
 def test_recipe_counts_follow_the_plan_and_errors():
-    # padding beyond (k-1)/2 is rejected as by the layer itself
+    # padded channels that do not fit the slots are rejected as by the layer itself
     with pytest.raises(he.HEError):
-        he.layer_plaintexts(he.LAYER_CONV, 14, np.zeros((1, 1, 3, 3)), fm=hfm(1, 8, 8, 1), out_ch=1, kernel=3,
+        he.layer_plaintexts(he.LAYER_CONV, 12, np.zeros((1, 8, 3, 3)), fm=hfm(8, 16, 16, 1), out_ch=1, kernel=3,
                             stride=1, padding=2)
+    # a 9x9 kernel needs 80 tap keys, more than a plan lists
+    with pytest.raises(he.HEError):
+        he.layer_plaintexts(he.LAYER_CONV, 14, np.zeros((1, 1, 9, 9)), fm=hfm(1, 16, 16, 1), out_ch=1, kernel=9,
+                            stride=1, padding=4)
     with pytest.raises(he.HEError):
         he.layer_plaintexts(he.LAYER_FC, 14, np.zeros((3, 6)), n_in=6, n_out=3)  # n_in not a power of two

@@ -225,11 +225,84 @@ def test_sim_generic_conv_with_padding(C, F, HW, k, S, P):
     assert {(i - P) * HW + (j - P) for i in range(k) for j in range(k)} - {0} <= set(keys)
 
 
-def test_padding_beyond_half_kernel_is_rejected():
-    with pytest.raises(NotImplementedError):
-        LY.conv_kind(3, 2)
-    with pytest.raises(NotImplementedError):
-        LY.conv_kind(5, 3, LY.FMap(1, 8, 8))
+def test_padding_beyond_half_kernel_takes_the_relayout():
+    assert LY.conv_kind(3, 2) == "padded" and LY.conv_kind(5, 3, LY.FMap(1, 8, 8)) == "padded"
+    assert LY.conv_kind(1, 1) == "padded" and LY.conv_kind(5, 2) == "generic"
+    with pytest.raises(ValueError):
+        LY.conv_kind(3, -1)
+    with pytest.raises(ValueError):  # 4 padded 16 x 16 blocks (20 x 20 each) exceed 1024 slots
+        LY.pad_masks(LY.FMap(4, 16, 16), 2, 1024)
+
+
+PAD_MAPS = [  # (C, H, W, rs, cs, P)
+    (1, 6, 6, None, None, 2),
+    (3, 5, 7, None, None, 3),    # rectangular
+    (4, 8, 8, None, None, 1),
+    (2, 6, 6, 16, 96, 2),        # wide rows: channels spread first
+    (2, 6, 6, 30, 180, 2),       # rows too wide for the padded block: rows first
+    (2, 4, 4, 8, 64, 2),         # rows already at W + 2P and cs = H_p W_p: a clearing mask only
+]
+
+
+@pytest.mark.parametrize("C,H,W,rs,cs,P", PAD_MAPS)
+@pytest.mark.parametrize("bsgs", [False, True], ids=["horner", "bsgs"])
+def test_pad_layout_builds_the_padded_tensor(C, H, W, rs, cs, P, bsgs):
+    """The re-layout yields exactly np.pad(X) flattened in X_p's map, zero
+    in every other slot, even when the unused input slots hold junk; it uses
+    the three keys and the level count pad_plan states."""
+    slots = 2048
+    X = synth.image(31, C, H, W)
+    fm = LY.FMap(C, H, W, rs, cs)
+    v = LY.pack(X, fm, slots)
+    used = LY.pack(np.ones_like(X), fm, slots) != 0
+    junk = np.random.default_rng(5).uniform(-3, 3, slots)
+    v[~used] = junk[~used]
+    masks = LY.pad_masks(fm, P, slots, bsgs)
+    ev = sim(slots)
+    xp, fp = LY.pad_layout(ev, LY.SimCt(v, 5), fm, P, masks, bsgs)
+    assert fp == LY.FMap(C, H + 2 * P, W + 2 * P)
+    want = np.zeros(slots)
+    want[:C * fp.cs] = np.pad(X, ((0, 0), (P, P), (P, P))).reshape(-1)
+    assert np.array_equal(xp.v, want)
+    steps, shift, _ = LY.pad_plan(fm, P)
+    assert shift == -(P * (W + 2 * P) + P)
+    assert xp.level == 5 - len(steps)
+    assert ev.ks == 1 + sum(LY.masked_chain_switches(n, bsgs) for _, n, _ in steps)
+    assert len(LY.pad_keys(fm, P)) <= 3
+    if rs is None:  # dense input: channels spread first, then rows
+        assert [s[0] for s in steps] == (["chan", "row"] if C > 1 else ["row"])
+        assert ev.ks == 1 + (C - 1) + (H - 1) if not bsgs else True
+    if rs == 30:
+        assert [s[0] for s in steps] == ["row", "chan"]
+    if rs == 8:
+        assert steps == [("clear", 1, 0)]
+
+
+@pytest.mark.parametrize("C,F,H,W,k,S,P", [
+    (2, 3, 8, 8, 3, 1, 2),     # 3x3 with padding 2 (output wider than the input)
+    (3, 2, 10, 10, 1, 2, 1),   # 1x1 / stride 2 / padding 1 (ResNet downsampling shortcut)
+    (1, 1, 6, 6, 3, 1, 3),
+    (2, 2, 7, 9, 5, 2, 3),     # rectangular, strided
+    (4, 1, 5, 5, 3, 1, 2),
+])
+def test_sim_padded_conv(C, F, H, W, k, S, P):
+    """Padding beyond (k-1)/2: re-layout then the generic P = 0 schedule
+    equals the FP64 convolution with padding P."""
+    slots = 4096
+    X = synth.image(33, C, H, W)
+    K = synth.conv_weights(33, F, C, k, 0.2)
+    fm = LY.FMap(C, H, W)
+    assert LY.conv_kind(k, P, fm, F) == "padded"
+    kern, masks = LY.conv_plaintexts(fm, K, S, P, slots)
+    ev = sim(slots)
+    y, fo = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 12), fm, F, k, S, P, kern, masks, slots)
+    Ho, Wo = (H + 2 * P - k) // S + 1, (W + 2 * P - k) // S + 1
+    assert (fo.C, fo.H, fo.W) == (F, Ho, Wo) and fo == LY.conv_out_map(fm, F, k, S, P, slots)
+    assert np.max(np.abs(LY.unpack(y.v, fo) - LY.conv2d_ref(X, K, S, P))) < 1e-12
+    fp = LY.padded_map(fm, P)
+    keys = set(LY.conv_rotations(fm, F, k, S, P, slots))
+    assert keys == LY.pad_keys(fm, P) | set(LY.conv_rotations(fp, F, k, S, 0, slots))
+    assert {i * fp.rs + j for i in range(k) for j in range(k)} - {0} <= keys
 
 
 # ------------------------------------------------------------------ encrypted (oracle CKKS)
@@ -295,6 +368,29 @@ def test_he_config1_padded_conv_decrypts():
     L = ctx.pr.L
     y, fo = LY.conv2d(ev, ct, fm, 2, 7, 2, 3, encode_all(ctx, kern, L), encode_all(ctx, masks, L - 1), slots)
     err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, y), fo) - LY.conv2d_ref(X, K, 2, 3)))
+    assert err < 1e-3, err
+
+
+def test_he_config1_relayout_padded_conv_decrypts():
+    """3x3 / padding 2 on 2 x 6 x 6 (C=2 -> F=2) at N=2^14: re-layout (two
+    mask levels) then the generic schedule."""
+    name = "config1"
+    ctx1, _, _ = H.oracle_ctx(name)
+    slots = ctx1.n // 2
+    X = synth.image(13, 2, 6, 6)
+    K = synth.conv_weights(13, 2, 2, 3, 0.2)
+    fm = LY.FMap(2, 6, 6)
+    ev, ctx, sk, pk = he_eval(name, LY.conv_rotations(fm, 2, 3, 1, 2, slots))
+    kern, masks = LY.conv_plaintexts(fm, K, 1, 2, slots)
+    npad = len(LY.pad_masks(fm, 2, slots))
+    _, ct = H.encrypt_slots(name, 13, values=LY.pack(X, fm, slots))
+    L = ctx.pr.L
+    steps, _, _ = LY.pad_plan(fm, 2)
+    assert [(st, n) for st, n, _ in steps] == [("chan", 2), ("row", 6)] and npad == 8
+    pm = encode_all(ctx, masks[:2], L) + encode_all(ctx, masks[2:npad], L - 1)
+    y, fo = LY.conv2d(ev, ct, fm, 2, 3, 1, 2, encode_all(ctx, kern, L - 2), pm + encode_all(ctx, masks[npad:], L - 3), slots)
+    assert y.level == L - 4
+    err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, y), fo) - LY.conv2d_ref(X, K, 1, 2)))
     assert err < 1e-3, err
 
 

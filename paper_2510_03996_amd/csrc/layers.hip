@@ -54,6 +54,7 @@ struct Ev {
     return o;
   }
   std::vector<he_ct> rot_hoisted(const he_ct& x, const std::vector<int>& rs) {
+    if (rs.empty()) return {};  // a 1x1 kernel has no tap rotation
     std::vector<he_ct> o(rs.size());
     for (auto& t : o) t = fresh();
     ck(he_rotate_hoisted(h, &x, rs.data(), (int)rs.size(), o.data(), s));

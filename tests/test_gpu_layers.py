@@ -258,10 +258,12 @@ def test_config2_fc(gctx):
     assert np.max(np.abs(dec[:10] - LY.fc_ref(x, Wm))) < 1e-3
 
 
-@pytest.mark.parametrize("C,F,HW,k,S,P", [(3, 2, 16, 7, 2, 3), (3, 4, 12, 3, 1, 1), (2, 3, 12, 5, 2, 2)])
+@pytest.mark.parametrize("C,F,HW,k,S,P", [(3, 2, 16, 7, 2, 3), (3, 4, 12, 3, 1, 1), (2, 3, 12, 5, 2, 2),
+                                          (4, 3, 8, 1, 2, 0)])
 def test_config1_padded_conv(gctx, C, F, HW, k, S, P):
     """Padding by masked taps: 7x7/s2/p3 (ResNet-34 stem shape), 3x3/p1 on a
-    non-replicated multi-channel map, 5x5/s2/p2."""
+    non-replicated multi-channel map, 5x5/s2/p2; and a 1x1 / stride 2 kernel
+    (no tap rotation at all)."""
     X = synth.image(29, C, HW, HW)
     K = synth.conv_weights(29, F, C, k, 0.15)
     run_conv(gctx("config1"), "config1", X, K, LY.FMap(C, HW, HW), S, P, 29)

@@ -310,6 +310,7 @@ typedef struct {
   int32_t out_ch, kernel, stride, padding;
   int32_t n_in, n_out;  /* FC; CHEB_MASK: n_in = used slots */
   double beta;          /* CHEB_MASK */
+  int32_t stride_mode;  /* HE_STRIDE_EXTRACT or HE_STRIDE_LOG (he_ctx_striding) */
 } he_layer_desc;
 int he_layer_plaintexts(const he_layer_desc* desc, const double* weights, const double* bias, double* out,
                         size_t cap_vectors, int32_t* n_vectors);
@@ -382,6 +383,23 @@ int he_ctx_conv_channel_sum(he_ctx* ctx, int mode);
 #define HE_CHAIN_HORNER 0
 #define HE_CHAIN_BSGS 1
 int he_ctx_mask_chains(he_ctx* ctx, int mode);
+/* Column step of the stride compaction (section "Secure Advanced Convolution
+ * With Striding"), chosen per context for later plans and calls:
+ *   HE_STRIDE_EXTRACT (default, the paper's first approach): one masked
+ *     chain over the Wo columns with key S-1 (Wo - 1 key switches, 1 level);
+ *   HE_STRIDE_LOG (its second approach): ceil(log2 Wo) steps t, each a
+ *     two-term masked chain with key (S-1) 2^t that keeps the columns j
+ *     whose bit t is 0 and moves those whose bit t is 1 left by (S-1) 2^t
+ *     (one key switch and one level per step): fewer rotations and keys
+ *     (log2 Wo + 1 for one channel), more levels.  Step t's masks: mask 0
+ *     is 1 (the column scale at t = 0) at c*cs + S i rs + S (j - j mod 2^t)
+ *     + j mod 2^t for the j with bit t clear, mask 1 the same for bit t set;
+ *     Wo = 1 keeps the one-mask column step.
+ * The row and channel steps are the same in both.  Same plaintext result.
+ * HE_EINVAL for another mode. */
+#define HE_STRIDE_EXTRACT 0
+#define HE_STRIDE_LOG 1
+int he_ctx_striding(he_ctx* ctx, int mode);
 /* bias_pt (nullable): the output channels' biases on the output layout
  * (he_layer_plaintexts), encoded at the output's scale and level, added to
  * the result (the convolution's "add the bias"). */

@@ -13,7 +13,10 @@ Written from the paper's section "Secure Neural Network Layers":
     (Special Secure Convolution Layer);
   * striding extracts the stride-aligned outputs with masks and rotations,
     jointly for all channels (Secure Advanced Convolution With Striding,
-    approach 1 and the multi-channel pipeline);
+    approach 1, or approach 2's log-step column moves, and the
+    multi-channel pipeline);
+  * padding beyond (k-1)/2 re-lays the input out as the padded tensor
+    (Secure Advanced Convolution With Padding);
   * average pooling sums the window rotations and multiplies by 1/k^2, then
     strides; global average pooling sums each W^2 block and merges the
     channels; the fully connected layer multiplies by each weight row, sums
@@ -341,13 +344,26 @@ def masked_chain(ev, v, masks, n, key, bsgs=False):
     return acc
 
 
-def compaction_plan(fm, S, Ho, Wo):
+def log_steps(Wo):
+    """ceil(log2 Wo): the column steps of the log-step extraction."""
+    return (Wo - 1).bit_length()
+
+
+def compaction_plan(fm, S, Ho, Wo, stride_log=False):
     """Steps of the stride-S extraction of outputs (S i, S j), jointly over all
-    channels: (i) columns, key S-1; (ii) rows, key D = S rs - Wo;
+    channels: (i) columns, key S-1 (the paper's first striding approach: one
+    masked chain over the Wo columns), or with stride_log (its second
+    approach) ceil(log2 Wo) steps t with key (S-1) 2^t, each a two-term
+    masked chain keeping the columns whose bit t is 0 and moving those whose
+    bit t is 1 left by (S-1) 2^t; (ii) rows, key D = S rs - Wo;
     (iii) channels, key E = cs - Ho Wo.  Returns [(step, count, key)]."""
     steps = []
     if S > 1:
-        steps.append(("col", Wo, S - 1))
+        T = log_steps(Wo)
+        if stride_log and T > 0:
+            steps += [("logcol%d" % t, 2, (S - 1) << t) for t in range(T)]
+        else:
+            steps.append(("col", Wo, S - 1))
     D = S * fm.rs - Wo
     if D != 0:
         steps.append(("row", Ho, D))
@@ -357,14 +373,28 @@ def compaction_plan(fm, S, Ho, Wo):
     return steps
 
 
-def compaction_masks(fm, S, Ho, Wo, col_scale, slots, bsgs=False):
+def compaction_masks(fm, S, Ho, Wo, col_scale, slots, bsgs=False, stride_log=False):
+    """Masks of each step on the layout that step sees.  Log-step column step
+    t: after steps < t, column j of the stride-S row i sits at
+    S i rs + S (j - j mod 2^t) + j mod 2^t; mask 0 is 1 there for the j with
+    bit t clear (they stay), mask 1 for those with bit t set (they move by
+    (S-1) 2^t); step 0 also selects the stride-aligned outputs, and carries
+    the column scale."""
     vecs = []
-    for step, n, key in compaction_plan(fm, S, Ho, Wo):
+    for step, n, key in compaction_plan(fm, S, Ho, Wo, stride_log):
         sv = []
         for t in range(n):
             m = np.zeros(slots)
             for c in range(fm.C):
-                if step == "col":
+                if step.startswith("logcol"):
+                    lt = int(step[6:])
+                    for i in range(Ho):
+                        for j in range(Wo):
+                            if (j >> lt) & 1 == t:
+                                b = j & ((1 << lt) - 1)
+                                pos = S * (j - b) + b
+                                m[c * fm.cs + S * i * fm.rs + pos] = col_scale if lt == 0 else 1.0
+                elif step == "col":
                     for i in range(Ho):
                         m[c * fm.cs + S * i * fm.rs + S * t] = col_scale
                 elif step == "row":
@@ -377,17 +407,17 @@ def compaction_masks(fm, S, Ho, Wo, col_scale, slots, bsgs=False):
     return vecs
 
 
-def compaction_keys(fm, S, Ho, Wo, bsgs=False):
+def compaction_keys(fm, S, Ho, Wo, bsgs=False, stride_log=False):
     keys = set()
-    for _, n, key in compaction_plan(fm, S, Ho, Wo):
+    for _, n, key in compaction_plan(fm, S, Ho, Wo, stride_log):
         keys |= masked_chain_keys(n, key, bsgs)
     return keys
 
 
-def compaction(ev, v, fm, S, Ho, Wo, masks, bsgs=False):
+def compaction(ev, v, fm, S, Ho, Wo, masks, bsgs=False, stride_log=False):
     """Move output (c, i, j) from c cs + S i rs + S j to c Ho Wo + i Wo + j."""
     pos = 0
-    for step, n, key in compaction_plan(fm, S, Ho, Wo):
+    for step, n, key in compaction_plan(fm, S, Ho, Wo, stride_log):
         ms = masks[pos:pos + n]
         pos += n
         v = masked_chain(ev, v, ms, n, key, bsgs)
@@ -531,14 +561,14 @@ def conv_out_map(fm, F, k, stride, padding, slots):
     return FMap(F, Ho, Wo, Wo, Ho * Wo, 1)
 
 
-def conv_plaintexts(fm, K, stride, padding, slots, bsgs=False):
+def conv_plaintexts(fm, K, stride, padding, slots, bsgs=False, stride_log=False):
     """Real vectors the convolution multiplies by, in the order the schedule
     (and the GPU library) consumes them: kernel vectors [f][tap], then masks."""
     F, C, k, _ = K.shape
     assert C == fm.C
     kind = conv_kind(k, padding, fm, F)
     if kind == "padded":
-        kern, masks = conv_plaintexts(padded_map(fm, padding), K, stride, 0, slots, bsgs)
+        kern, masks = conv_plaintexts(padded_map(fm, padding), K, stride, 0, slots, bsgs, stride_log)
         return kern, pad_masks(fm, padding, slots, bsgs) + masks
     kern, masks = [], []
     if kind == "special":
@@ -561,7 +591,7 @@ def conv_plaintexts(fm, K, stride, padding, slots, bsgs=False):
                 masks.append(m)
         if stride > 1:
             Ho = (W - 1) // stride + 1
-            masks += compaction_masks(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, 1.0, slots, bsgs)
+            masks += compaction_masks(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, 1.0, slots, bsgs, stride_log)
     else:
         # tap (i, j) at output (y, x) reads input (y + i - P, x + j - P): the
         # kernel value where that neighbour is inside the image, 0 elsewhere
@@ -585,7 +615,7 @@ def conv_plaintexts(fm, K, stride, padding, slots, bsgs=False):
             masks.append(m)
         if stride > 1:
             Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
-            masks += compaction_masks(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0, slots, bsgs)
+            masks += compaction_masks(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0, slots, bsgs, stride_log)
     return kern, masks
 
 
@@ -622,12 +652,12 @@ def channel_sum(ev, A, C, step, logstep=False):
     return S
 
 
-def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False):
+def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False, stride_log=False):
     """Distinct rotation keys the schedule uses (the paper's per-layer index helper)."""
     kind = conv_kind(k, padding, fm, F)
     if kind == "padded":
         return sorted(pad_keys(fm, padding, bsgs) |
-                      set(conv_rotations(padded_map(fm, padding), F, k, stride, 0, slots, logstep, bsgs)))
+                      set(conv_rotations(padded_map(fm, padding), F, k, stride, 0, slots, logstep, bsgs, stride_log)))
     keys = set()
     if kind == "special":
         W = fm.W
@@ -635,7 +665,7 @@ def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False):
         keys |= channel_sum_keys(fm.C, W * W, logstep)
         if stride > 1:
             Ho = (W - 1) // stride + 1
-            keys |= compaction_keys(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, bsgs)
+            keys |= compaction_keys(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, bsgs, stride_log)
     else:
         keys |= {r for r in conv_taps(fm, k, padding) if r != 0}
         keys |= channel_sum_keys(fm.C, fm.cs, logstep)
@@ -644,7 +674,7 @@ def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False):
         if stride > 1:
             H1, W1 = conv_dims(fm, k, padding)
             Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
-            keys |= compaction_keys(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, bsgs)
+            keys |= compaction_keys(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, bsgs, stride_log)
     return sorted(keys)
 
 
@@ -661,17 +691,19 @@ def conv_bias_vector(fo, bias, slots):
     return v
 
 
-def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False, bsgs=False, bias=None):
+def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False, bsgs=False, bias=None,
+           stride_log=False):
     """The pinned convolution schedule (_conv2d_schedule), then the bias
     plaintext (conv_bias_vector, encoded at the output's scale and level)
     added when given."""
-    y, fo = _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep, bsgs)
+    y, fo = _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep, bsgs, stride_log)
     if bias is not None:
         y = ev.add_plain(y, bias)
     return y, fo
 
 
-def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False, bsgs=False):
+def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False, bsgs=False,
+                     stride_log=False):
     """Pinned convolution schedule.
 
     special (k=3, P=1): r = Algorithm 1 rotations computed as three hoisted
@@ -694,7 +726,7 @@ def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logst
     if kind == "padded":
         npad = len(pad_masks(fm, padding, slots, bsgs))
         xp, fp = pad_layout(ev, x, fm, padding, masks[:npad], bsgs)
-        return _conv2d_schedule(ev, xp, fp, F, k, stride, 0, kern, masks[npad:], slots, logstep, bsgs)
+        return _conv2d_schedule(ev, xp, fp, F, k, stride, 0, kern, masks[npad:], slots, logstep, bsgs, stride_log)
     C = fm.C
     if kind == "special":
         W = fm.W
@@ -721,7 +753,7 @@ def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logst
         if stride == 1:
             return y, out1
         Ho = (W - 1) // stride + 1
-        return compaction(ev, y, FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, masks[mpos:], bsgs)
+        return compaction(ev, y, FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, masks[mpos:], bsgs, stride_log)
     # generic
     offs = conv_taps(fm, k, padding)
     rot = iter(ev.rot_hoisted(x, [r for r in offs if r != 0]))
@@ -746,7 +778,7 @@ def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logst
     if stride == 1:
         return y, FMap(F, H1, W1, fm.rs, fm.cs, 1)
     Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
-    return compaction(ev, y, FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks[mpos:], bsgs)
+    return compaction(ev, y, FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks[mpos:], bsgs, stride_log)
 
 
 # ===================================================================== pooling
@@ -759,7 +791,7 @@ def pool_whole_channel(fm, k):
             and fm.cs & (fm.cs - 1) == 0)
 
 
-def avgpool_plaintexts(fm, k, stride, slots, bsgs=False):
+def avgpool_plaintexts(fm, k, stride, slots, bsgs=False, stride_log=False):
     if pool_whole_channel(fm, k):
         return gap_plaintexts(fm, slots, bsgs)
     H1, W1 = fm.H - k + 1, fm.W - k + 1
@@ -770,21 +802,22 @@ def avgpool_plaintexts(fm, k, stride, slots, bsgs=False):
             for y in range(H1):
                 m[c * fm.cs + y * fm.rs:c * fm.cs + y * fm.rs + W1] = 1.0 / (k * k)
         return [m]
-    return compaction_masks(FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0 / (k * k), slots, bsgs)
+    return compaction_masks(FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0 / (k * k), slots, bsgs,
+                            stride_log)
 
 
-def avgpool_rotations(fm, k, stride, bsgs=False):
+def avgpool_rotations(fm, k, stride, bsgs=False, stride_log=False):
     if pool_whole_channel(fm, k):
         return gap_rotations(fm, bsgs)
     keys = {i * fm.rs + j for i in range(k) for j in range(k) if (i, j) != (0, 0)}
     if stride > 1:
         H1, W1 = fm.H - k + 1, fm.W - k + 1
         Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
-        keys |= compaction_keys(FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, bsgs)
+        keys |= compaction_keys(FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, bsgs, stride_log)
     return sorted(keys)
 
 
-def avgpool(ev, x, fm, k, stride, masks, bsgs=False):
+def avgpool(ev, x, fm, k, stride, masks, bsgs=False, stride_log=False):
     """Window sum by one hoisted group of the k^2-1 offsets i rs + j, then the
     stride compaction with 1/k^2 folded into the column masks; a window over
     the whole channel is the global schedule (pool_whole_channel)."""
@@ -798,7 +831,7 @@ def avgpool(ev, x, fm, k, stride, masks, bsgs=False):
     if stride == 1:
         return ev.rescale(ev.mul_plain(s, masks[0])), FMap(fm.C, H1, W1, fm.rs, fm.cs, 1)
     Ho, Wo = (fm.H - k) // stride + 1, (fm.W - k) // stride + 1
-    return compaction(ev, s, FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks, bsgs)
+    return compaction(ev, s, FMap(fm.C, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks, bsgs, stride_log)
 
 
 def gap_plaintexts(fm, slots, bsgs=False):

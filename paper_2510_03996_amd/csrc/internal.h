@@ -110,6 +110,7 @@ struct Ctx {
   size_t lds_per_block = 65536;  // device limit on a workgroup's LDS (bytes)
   int chsum = HE_CHSUM_CHAIN;      // convolution input-channel sum (he_ctx_conv_channel_sum)
   int chain = HE_CHAIN_HORNER;     // masked rotation chains of the layers (he_ctx_mask_chains)
+  int stride = HE_STRIDE_EXTRACT;  // column step of the stride compaction (he_ctx_striding)
   int fc = HE_FC_ROWS;             // fully connected form (he_ctx_fc_form)
   int layer_streams = 2;           // streams a convolution / hoisted set is spread over (he_ctx_layer_streams)
   // helper streams only where a key switch outlasts the fork and join even

@@ -185,12 +185,22 @@ struct Fork {
 
 // ---------------------------------------------------------------- compaction
 struct Step {
-  int kind, n, key;  // kind 0 col, 1 row, 2 chan
+  int kind, n, key;  // kind 0 col, 1 row, 2 chan, 4 log-step column step t
+  int t = 0;
 };
 
-static std::vector<Step> compaction_plan(const he_fmap& fm, int S, int Ho, int Wo) {
+// Stride-S extraction of outputs (S i, S j), jointly over all channels:
+// columns (one chain, key S-1; or with HE_STRIDE_LOG ceil(log2 Wo) two-term
+// chains with keys (S-1) 2^t), rows (key S rs - Wo), channels (key
+// cs - Ho Wo), each only when it moves data.
+static std::vector<Step> compaction_plan(const Ctx* c, const he_fmap& fm, int S, int Ho, int Wo) {
   std::vector<Step> st;
-  if (S > 1) st.push_back({0, Wo, S - 1});
+  int T = 0;
+  while ((1 << T) < Wo) T++;
+  if (S > 1 && c->stride == HE_STRIDE_LOG && T > 0)
+    for (int t = 0; t < T; t++) st.push_back({4, 2, (S - 1) << t, t});
+  else if (S > 1)
+    st.push_back({0, Wo, S - 1});
   int D = S * fm.row_stride - Wo;
   if (D != 0) st.push_back({1, Ho, D});
   int E = fm.chan_stride - Ho * Wo;
@@ -261,7 +271,7 @@ static he_ct compaction(Ev& ev, const he_ct& v, const he_fmap& fm, int S, int Ho
                         he_fmap* out_map) {
   he_ct cur = v;
   int pos = 0;
-  for (const Step& st : compaction_plan(fm, S, Ho, Wo)) {
+  for (const Step& st : compaction_plan(ev.c, fm, S, Ho, Wo)) {
     he_ct nxt = horner_masked(ev, cur, masks + pos, st.n, st.key);
     if (pos > 0) ev.release(cur);
     cur = nxt;
@@ -438,7 +448,7 @@ static int conv_plan_keys(const Ctx* c, const he_fmap* fm, int F, int k, int S, 
     if (S > 1) {
       int Ho = (W - 1) / S + 1;
       he_fmap f1{F, W, W, W, W * W, 1};
-      auto st = compaction_plan(f1, S, Ho, Ho);
+      auto st = compaction_plan(c, f1, S, Ho, Ho);
       for (auto& x : st) { chain_keys(c, keys, x.n, x.key); ks += chain_switches(c, x.n); lv++; }
       nmask += compaction_masks(st);
       pl->out = he_fmap{F, Ho, Ho, Ho, Ho * Ho, 1};
@@ -458,7 +468,7 @@ static int conv_plan_keys(const Ctx* c, const he_fmap* fm, int F, int k, int S, 
     if (S > 1) {
       int Ho = (H1 - 1) / S + 1, Wo = (W1 - 1) / S + 1;
       he_fmap f1{F, H1, W1, fm->row_stride, fm->chan_stride, 1};
-      auto st = compaction_plan(f1, S, Ho, Wo);
+      auto st = compaction_plan(c, f1, S, Ho, Wo);
       for (auto& x : st) { chain_keys(c, keys, x.n, x.key); ks += chain_switches(c, x.n); lv++; }
       nmask += compaction_masks(st);
       pl->out = he_fmap{F, Ho, Wo, Wo, Ho * Wo, 1};
@@ -647,7 +657,7 @@ static int pool_plan(const Ctx* c, const he_fmap* fm, int k, int S, he_layer_pla
     } else {
       int Ho = (fm->height - k) / S + 1, Wo = (fm->width - k) / S + 1;
       he_fmap f1{fm->channels, H1, W1, fm->row_stride, fm->chan_stride, 1};
-      auto st = compaction_plan(f1, S, Ho, Wo);
+      auto st = compaction_plan(c, f1, S, Ho, Wo);
       for (auto& x : st) { chain_keys(c, keys, x.n, x.key); ks += chain_switches(c, x.n); }
       pl->n_mask_pts = compaction_masks(st);
       pl->levels = (int)st.size();
@@ -898,12 +908,21 @@ static void chain_vectors(const Ctx* c, Vecs& out, Vecs v, int key) {
 // stride-S extraction masks of outputs (S i, S j) of map fm (compaction_plan)
 static void compaction_vectors(const Ctx* c, Vecs& out, const he_fmap& fm, int S, int Ho, int Wo, double col_scale) {
   const int slots = c->n / 2;
-  for (const Step& st : compaction_plan(fm, S, Ho, Wo)) {
+  for (const Step& st : compaction_plan(c, fm, S, Ho, Wo)) {
     Vecs v;
     for (int t = 0; t < st.n; t++) {
       std::vector<double> m = zeros(slots);
       for (int ch = 0; ch < fm.channels; ch++) {
-        if (st.kind == 0) {
+        if (st.kind == 4) {
+          // after steps < st.t column j sits at S (j - b) + b, b = j mod 2^st.t;
+          // mask 0 holds the j with bit st.t clear, mask 1 those with it set
+          const int lo = (1 << st.t) - 1;
+          for (int i = 0; i < Ho; i++)
+            for (int j = 0; j < Wo; j++)
+              if (((j >> st.t) & 1) == t)
+                m[(size_t)ch * fm.chan_stride + (size_t)S * i * fm.row_stride + S * (j & ~lo) + (j & lo)] =
+                    st.t == 0 ? col_scale : 1.0;
+        } else if (st.kind == 0) {
           for (int i = 0; i < Ho; i++) m[(size_t)ch * fm.chan_stride + (size_t)S * i * fm.row_stride + S * t] = col_scale;
         } else if (st.kind == 1) {
           const size_t base = (size_t)ch * fm.chan_stride + (size_t)S * t * fm.row_stride;
@@ -1113,6 +1132,13 @@ static int check_pts(const Ctx* c, const he_pt* p, int n, int level, const char*
 
 extern "C" {
 
+int he_ctx_striding(he_ctx* h, int mode) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  if (mode != HE_STRIDE_EXTRACT && mode != HE_STRIDE_LOG) return set_error(HE_EINVAL, "unknown striding mode");
+  h->c.stride = mode;
+  return HE_OK;
+}
+
 int he_ctx_mask_chains(he_ctx* h, int mode) {
   if (!h) return set_error(HE_EINVAL, "null context");
   if (mode != HE_CHAIN_HORNER && mode != HE_CHAIN_BSGS) return set_error(HE_EINVAL, "unknown chain mode");
@@ -1171,11 +1197,14 @@ int he_layer_plaintexts(const he_layer_desc* d, const double* weights, const dou
   if (d->mask_chains != HE_CHAIN_HORNER && d->mask_chains != HE_CHAIN_BSGS)
     return set_error(HE_EINVAL, "unknown mask-chain mode");
   if (d->fc_form != HE_FC_ROWS && d->fc_form != HE_FC_DIAG) return set_error(HE_EINVAL, "unknown FC form");
+  if (d->stride_mode != HE_STRIDE_EXTRACT && d->stride_mode != HE_STRIDE_LOG)
+    return set_error(HE_EINVAL, "unknown striding mode");
   return guarded([&] {
     Ctx opt;  // the schedule options the layer's plan depends on
     opt.log_n = d->log_n;
     opt.n = 1 << d->log_n;
     opt.chain = d->mask_chains;
+    opt.stride = d->stride_mode;
     opt.fc = d->fc_form;
     Vecs v;
     int rc;

@@ -68,7 +68,8 @@ def encrypt_map(name, X, fm, seed, level=None):
     return ct
 
 
-def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False, bsgs=False, streams=(2,)):
+def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False, bsgs=False, streams=(2,),
+             slog=False):
     """One oracle convolution; the GPU result with each layer-stream count in
     `streams` must equal it bit for bit."""
     from paper_2510_03996_amd import he
@@ -78,14 +79,17 @@ def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False
     F, _, k, _ = K.shape
     g.conv_channel_sum(he.CHSUM_LOG if logstep else he.CHSUM_CHAIN)
     g.mask_chains(he.CHAIN_BSGS if bsgs else he.CHAIN_HORNER)
+    g.striding(he.STRIDE_LOG if slog else he.STRIDE_EXTRACT)
     plan = g.conv2d_plan(fm_he(fm), F, k, stride, padding)
-    assert sorted(plan.keys()) == LY.conv_rotations(fm, F, k, stride, padding, slots, logstep=logstep, bsgs=bsgs)
+    assert sorted(plan.keys()) == LY.conv_rotations(fm, F, k, stride, padding, slots, logstep=logstep, bsgs=bsgs,
+                                                    stride_log=slog)
     ev = setup_keys(g, name, plan.keys())
     ct = encrypt_map(name, X, fm, seed, level)
-    kern, masks = LY.conv_plaintexts(fm, K, stride, padding, slots, bsgs=bsgs)
+    kern, masks = LY.conv_plaintexts(fm, K, stride, padding, slots, bsgs=bsgs, stride_log=slog)
     assert (plan.n_kernel_pts, plan.n_mask_pts) == (len(kern), len(masks))
     kp, mp = encode(octx, kern, ct.level), encode(octx, masks, ct.level)
-    want, fo = LY.conv2d(ev, ct, fm, F, k, stride, padding, kp, mp, slots, logstep=logstep, bsgs=bsgs)
+    want, fo = LY.conv2d(ev, ct, fm, F, k, stride, padding, kp, mp, slots, logstep=logstep, bsgs=bsgs,
+                         stride_log=slog)
     assert ev.ks == plan.key_switches and ct.level - want.level == plan.levels
     gct, gkp, gmp = g.ct_from_numpy(ct.data, ct.scale), gpts(g, kp), gpts(g, mp)
     for n in streams:
@@ -100,6 +104,7 @@ def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False
     assert err < 1e-3, err
     g.conv_channel_sum(he.CHSUM_CHAIN)
     g.mask_chains(he.CHAIN_HORNER)
+    g.striding(he.STRIDE_EXTRACT)
     return got, want, fo
 
 
@@ -130,6 +135,42 @@ def test_config1_relayout_padded_conv(gctx, C, F, H, W, rs, cs, k, S, P, bsgs):
     fm = LY.FMap(C, H, W, rs, cs)
     assert LY.conv_kind(k, P, fm, F) == "padded"
     run_conv(gctx("config1"), "config1", X, K, fm, S, P, 30 + k, bsgs=bsgs, streams=(1, 2))
+
+
+@pytest.mark.parametrize("bsgs", [False, True], ids=["horner", "bsgs"])
+def test_config1_log_step_striding_conv(gctx, bsgs):
+    """Striding approach 2 (log-step column moves): C=3 -> F=4, 3x3, stride 2,
+    pad 1 at N=2^14, bit for bit against the oracle."""
+    X = synth.image(34, 3, 12, 12)
+    K = synth.conv_weights(34, 4, 3, 3, 0.2)
+    run_conv(gctx("config1"), "config1", X, K, LY.FMap(3, 12, 12), 2, 1, 34, bsgs=bsgs, streams=(1, 2), slog=True)
+
+
+def test_config1_log_step_striding_pool(gctx):
+    """2x2 / stride 2 pooling of 6 x 24 x 24 (row stride 28) with approach 2."""
+    from paper_2510_03996_amd import he
+
+    name = "config1"
+    g = gctx(name)
+    octx, sk, _ = H.oracle_ctx(name)
+    slots = octx.n // 2
+    X = synth.image(35, 6, 24, 24)
+    fm = LY.FMap(6, 24, 24, 28, 784)
+    g.striding(he.STRIDE_LOG)
+    try:
+        plan = g.avgpool_plan(fm_he(fm), 2, 2)
+        assert sorted(plan.keys()) == LY.avgpool_rotations(fm, 2, 2, stride_log=True)
+        ev = setup_keys(g, name, plan.keys())
+        ct = encrypt_map(name, X, fm, 35)
+        mp = encode(octx, LY.avgpool_plaintexts(fm, 2, 2, slots, stride_log=True), ct.level)
+        want, fo = LY.avgpool(ev, ct, fm, 2, 2, mp, stride_log=True)
+        got, gfo = g.avgpool(g.ct_from_numpy(ct.data, ct.scale), fm_he(fm), 2, 2, gpts(g, mp))
+        assert ev.ks == plan.key_switches and ct.level - want.level == plan.levels == 6
+        check_ct(got, want, "log-step strided avgpool")
+        dec = LY.unpack(octx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale)), fo)
+        assert np.max(np.abs(dec - LY.avgpool_ref(X, 2, 2))) < 1e-3
+    finally:
+        g.striding(he.STRIDE_EXTRACT)
 
 
 def test_config1_lenet_stack(gctx):

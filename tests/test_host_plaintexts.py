@@ -45,15 +45,18 @@ def hfm(C, H, W, reps):
 
 @pytest.mark.parametrize("case", CONVS, ids=lambda c: "n%d_%dx%dx%d_F%d_k%d_s%d_p%d" % (c[0], c[1], c[2], c[3], c[5], c[6], c[7], c[8]))
 @pytest.mark.parametrize("bsgs", [False, True], ids=["horner", "bsgs"])
-def test_conv_plaintexts_match_oracle(case, bsgs):
+@pytest.mark.parametrize("slog", [False, True], ids=["extract", "logstride"])
+def test_conv_plaintexts_match_oracle(case, bsgs, slog):
     log_n, C, H, W, reps, F, k, S, P = case
+    if slog and S == 1:
+        pytest.skip("the striding mode only changes strided layers")
     slots = (1 << log_n) // 2
     K = synth.conv_weights(log_n * 7 + F, F, C, k, 0.1)
     b = synth.uniform_slots(F, F)
     got = he.layer_plaintexts(he.LAYER_CONV, log_n, K, b, fm=hfm(C, H, W, reps), out_ch=F, kernel=k, stride=S,
-                              padding=P, mask_chains=int(bsgs))
+                              padding=P, mask_chains=int(bsgs), stride_mode=int(slog))
     fm = LY.FMap(C, H, W, reps=reps)
-    kern, masks = LY.conv_plaintexts(fm, K, S, P, slots, bsgs)
+    kern, masks = LY.conv_plaintexts(fm, K, S, P, slots, bsgs, slog)
     fo = LY.conv_out_map(fm, F, k, S, P, slots)
     want = kern + masks + [LY.conv_bias_vector(fo, b, slots)]
     assert got.shape == (len(want), slots)
@@ -61,7 +64,7 @@ def test_conv_plaintexts_match_oracle(case, bsgs):
         assert np.array_equal(got[i], w), "vector %d of %d" % (i, len(want))
     # without a bias the vector is left out
     nb = he.layer_plaintexts(he.LAYER_CONV, log_n, K, None, fm=hfm(C, H, W, reps), out_ch=F, kernel=k, stride=S,
-                             padding=P, mask_chains=int(bsgs))
+                             padding=P, mask_chains=int(bsgs), stride_mode=int(slog))
     assert nb.shape[0] == len(want) - 1
 
 
@@ -77,13 +80,14 @@ POOLS = [  # (log_n, C, H, W, k, stride)
 
 @pytest.mark.parametrize("case", POOLS, ids=lambda c: "n%d_%dx%dx%d_k%d_s%d" % c)
 @pytest.mark.parametrize("bsgs", [False, True], ids=["horner", "bsgs"])
-def test_pool_plaintexts_match_oracle(case, bsgs):
+@pytest.mark.parametrize("slog", [False, True], ids=["extract", "logstride"])
+def test_pool_plaintexts_match_oracle(case, bsgs, slog):
     log_n, C, H, W, k, S = case
     slots = (1 << log_n) // 2
     got = he.layer_plaintexts(he.LAYER_AVGPOOL, log_n, fm=hfm(C, H, W, 1), kernel=k, stride=S,
-                              mask_chains=int(bsgs))
+                              mask_chains=int(bsgs), stride_mode=int(slog))
     fm = LY.FMap(C, H, W)
-    want = LY.gap_plaintexts(fm, slots, bsgs) if k == 0 else LY.avgpool_plaintexts(fm, k, S, slots, bsgs)
+    want = LY.gap_plaintexts(fm, slots, bsgs) if k == 0 else LY.avgpool_plaintexts(fm, k, S, slots, bsgs, slog)
     assert got.shape == (len(want), slots)
     for i, w in enumerate(want):
         assert np.array_equal(got[i], w), "vector %d" % i

@@ -225,6 +225,79 @@ def test_sim_generic_conv_with_padding(C, F, HW, k, S, P):
     assert {(i - P) * HW + (j - P) for i in range(k) for j in range(k)} - {0} <= set(keys)
 
 
+STRIDE_MAPS = [  # (C, H1, W1, rs, cs, S)
+    (1, 32, 32, 32, 1024, 2),   # ResNet downsampling: Wo = 16 (power of two)
+    (3, 12, 12, 12, 144, 2),    # Wo = 6
+    (2, 11, 13, 16, 200, 3),    # S = 3, Wo = 5, padded row stride
+    (4, 9, 9, 9, 81, 2),        # Wo = 5
+    (2, 3, 2, 4, 16, 2),        # Wo = 1: no column step
+    (1, 5, 17, 17, 85, 4),      # S = 4, Wo = 5
+]
+
+
+@pytest.mark.parametrize("C,H1,W1,rs,cs,S", STRIDE_MAPS)
+@pytest.mark.parametrize("bsgs", [False, True], ids=["horner", "bsgs"])
+def test_log_step_striding_equals_extraction(C, H1, W1, rs, cs, S, bsgs):
+    """Striding approach 2 (ceil(log2 Wo) column steps with keys (S-1) 2^t)
+    moves every stride-aligned output exactly where approach 1 does, from a
+    ciphertext full of values (every slot nonzero), with log2(Wo) + 1 keys
+    for one channel and ceil(log2 Wo) column key switches instead of Wo - 1."""
+    slots = 4096
+    rng = np.random.default_rng(11)
+    v = rng.uniform(-1, 1, slots)
+    fm = LY.FMap(C, H1, W1, rs, cs)
+    Ho, Wo = (H1 - 1) // S + 1, (W1 - 1) // S + 1
+    out = []
+    for log in (False, True):
+        ev = sim(slots)
+        masks = LY.compaction_masks(fm, S, Ho, Wo, 0.25, slots, bsgs, log)
+        y, fo = LY.compaction(ev, LY.SimCt(v, 9), fm, S, Ho, Wo, masks, bsgs, log)
+        out.append((y, fo, ev.ks))
+    (y1, f1, ks1), (y2, f2, ks2) = out
+    assert f1 == f2 == LY.FMap(C, Ho, Wo, Wo, Ho * Wo)
+    assert np.array_equal(y1.v, y2.v)
+    want = np.zeros(slots)
+    for c in range(C):
+        for i in range(Ho):
+            for j in range(Wo):
+                want[c * Ho * Wo + i * Wo + j] = 0.25 * v[c * cs + S * i * rs + S * j]
+    assert np.array_equal(y2.v, want)
+    T = LY.log_steps(Wo)
+    assert T == int(np.ceil(np.log2(Wo))) if Wo > 1 else T == 0
+    rest = sum(LY.masked_chain_switches(n, bsgs) for st, n, _ in LY.compaction_plan(fm, S, Ho, Wo) if st != "col")
+    assert ks2 == (T if Wo > 1 else 0) + rest and ks1 == LY.masked_chain_switches(Wo, bsgs) + rest
+    assert y2.level == 9 - (max(T, 1) + len(LY.compaction_plan(fm, S, Ho, Wo)) - 1)
+    keys = LY.compaction_keys(fm, S, Ho, Wo, False, True)
+    if C == 1 and Ho > 1 and Wo > 1:
+        assert len(keys) == T + 1 and {(S - 1) << t for t in range(T)} <= keys
+
+
+@pytest.mark.parametrize("C,F,HW,k,S,P", [(3, 4, 12, 3, 2, 1), (2, 2, 13, 5, 2, 2), (1, 2, 16, 3, 3, 0)])
+def test_sim_conv_log_step_striding(C, F, HW, k, S, P):
+    slots = 4096
+    X = synth.image(17, C, HW, HW)
+    K = synth.conv_weights(17, F, C, k, 0.2)
+    fm = LY.FMap(C, HW, HW)
+    kern, masks = LY.conv_plaintexts(fm, K, S, P, slots, stride_log=True)
+    ev = sim(slots)
+    y, fo = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 12), fm, F, k, S, P, kern, masks, slots, stride_log=True)
+    assert fo == LY.conv_out_map(fm, F, k, S, P, slots)
+    assert np.max(np.abs(LY.unpack(y.v, fo) - LY.conv2d_ref(X, K, S, P))) < 1e-12
+    assert set(LY.conv_rotations(fm, F, k, S, P, slots, stride_log=True)) >= {(S - 1) << t for t in range(
+        LY.log_steps(fo.W))}
+
+
+def test_sim_pool_log_step_striding():
+    slots = 8192
+    X = synth.image(18, 6, 24, 24)
+    fm = LY.FMap(6, 24, 24, 28, 784)
+    ev = sim(slots)
+    pm = LY.avgpool_plaintexts(fm, 2, 2, slots, stride_log=True)
+    z, f2 = LY.avgpool(ev, LY.SimCt(LY.pack(X, fm, slots), 5), fm, 2, 2, pm, stride_log=True)
+    assert f2 == LY.FMap(6, 12, 12) and ev.ks == 3 + 4 + 11 + 5 and z.level == 5 - 6
+    assert np.max(np.abs(LY.unpack(z.v, f2) - LY.avgpool_ref(X, 2, 2))) < 1e-12
+
+
 def test_padding_beyond_half_kernel_takes_the_relayout():
     assert LY.conv_kind(3, 2) == "padded" and LY.conv_kind(5, 3, LY.FMap(1, 8, 8)) == "padded"
     assert LY.conv_kind(1, 1) == "padded" and LY.conv_kind(5, 2) == "generic"
@@ -391,6 +464,26 @@ def test_he_config1_relayout_padded_conv_decrypts():
     y, fo = LY.conv2d(ev, ct, fm, 2, 3, 1, 2, encode_all(ctx, kern, L - 2), pm + encode_all(ctx, masks[npad:], L - 3), slots)
     assert y.level == L - 4
     err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, y), fo) - LY.conv2d_ref(X, K, 1, 2)))
+    assert err < 1e-3, err
+
+
+def test_he_config1_log_step_strided_conv_decrypts():
+    """3x3 / stride 2 / padding 1 on 3 x 12 x 12 -> 4 x 6 x 6 with striding
+    approach 2 at N=2^14."""
+    name = "config1"
+    ctx1, _, _ = H.oracle_ctx(name)
+    slots = ctx1.n // 2
+    X = synth.image(14, 3, 12, 12)
+    K = synth.conv_weights(14, 4, 3, 3, 0.2)
+    fm = LY.FMap(3, 12, 12)
+    ev, ctx, sk, pk = he_eval(name, LY.conv_rotations(fm, 4, 3, 2, 1, slots, stride_log=True))
+    kern, masks = LY.conv_plaintexts(fm, K, 2, 1, slots, stride_log=True)
+    _, ct = H.encrypt_slots(name, 14, values=LY.pack(X, fm, slots))
+    L = ctx.pr.L
+    y, fo = LY.conv2d(ev, ct, fm, 4, 3, 2, 1, encode_all(ctx, kern, L), encode_all(ctx, masks, L), slots,
+                      stride_log=True)
+    assert fo == LY.FMap(4, 6, 6) and y.level == L - 7  # kernel, block mask, 3 log steps, rows, channels
+    err = np.max(np.abs(LY.unpack(ctx.decrypt(sk, y), fo) - LY.conv2d_ref(X, K, 2, 1)))
     assert err < 1e-3, err
 
 

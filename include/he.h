@@ -526,13 +526,17 @@ int he_cheb_relu_coeffs(double beta, int degree, double* coeffs);
  * multiply-accumulate kernel and chunked rescaling.  HE_BATCH_GRAPH: the
  * first he_batch_run on a (non-default) stream captures the schedule in a
  * hipGraph, later runs replay it.  The fused multiply-accumulate keeps a
- * group of 8 outputs in registers (HE_BATCH_MAC4: 4); HE_BATCH_TUNE times
- * both groupings on the batch's own shapes at creation and keeps the
- * faster.  Workspace memory is allocated at creation and released by
- * he_batch_destroy. */
+ * group of outputs in registers and reads an item's rotated copies once per
+ * group: variants (outputs per group, polynomials per workgroup) = (4, 2),
+ * (8, 2), (16, 2) (the default), (16, 1), (32, 1); HE_BATCH_MAC4 takes
+ * (4, 2), HE_BATCH_MAC_SELECT(v) variant v (and skips the tuning);
+ * HE_BATCH_TUNE times every variant on the batch's own shapes at creation
+ * and keeps the fastest.  All variants give the same bits.  Workspace memory is allocated at creation
+ * and released by he_batch_destroy. */
 #define HE_BATCH_GRAPH 1
 #define HE_BATCH_MAC4 2
 #define HE_BATCH_TUNE 4
+#define HE_BATCH_MAC_SELECT(v) (((v) + 1) << 8)
 typedef struct he_batch he_batch;
 typedef struct {
   int32_t n_items;
@@ -554,9 +558,13 @@ int he_batch_run(he_batch* batch, he_stream stream);
 int he_batch_run_plain(he_batch* batch, he_stream stream);
 int he_batch_info(const he_batch* batch, int32_t* total_rotations, int32_t* total_outputs, int32_t* distinct_keys,
                   double* out_scale);
-/* The MAC grouping in use and, after HE_BATCH_TUNE, the timed milliseconds
- * of the 4- and 8-output groupings (0 when not tuned). */
-int he_batch_tuning(const he_batch* batch, int32_t* mac_outputs_per_group, float* ms_group4, float* ms_group8);
+/* The MAC variant in use (outputs per register group, polynomials per
+ * workgroup) and, after HE_BATCH_TUNE, the timed milliseconds of every
+ * variant in the order above (0 when not tuned); ms (nullable) needs cap >=
+ * HE_BATCH_MAC_VARIANTS entries, else HE_EINVAL. */
+#define HE_BATCH_MAC_VARIANTS 5
+int he_batch_tuning(const he_batch* batch, int32_t* outputs_per_group, int32_t* polys_per_group, float* ms,
+                    int32_t cap);
 int he_batch_destroy(he_batch* batch);
 
 /* ------------------------------------------------------------ measurement

@@ -14,9 +14,11 @@
 //      ciphertext that uses that key (the key is read from HBM once per
 //      batch instead of once per rotation), then one batched ModDown for all
 //      of that key's rotations;
-//   3. one fused MAC launch for all outputs: each thread stages its
-//      coefficient of the input's rotated copies in LDS and accumulates every
-//      output with 128-bit products (one reduction per output residue);
+//   3. the plaintext pool centred once (k_pool_centre), then one fused MAC
+//      launch for all outputs: each thread keeps a group of outputs'
+//      accumulators in registers and streams the item's rotated copies once
+//      per group (centred FP64 products for the primes below 2^50, 128-bit
+//      products otherwise);
 //   4. rescale of all outputs in chunks.
 // The result is bit-identical to the per-op path (he_rotate_hoisted,
 // he_mul_plain, he_rescale), which he_batch_run_plain executes for
@@ -73,15 +75,34 @@ __global__ __launch_bounds__(256) void k_ip_multi(const uint64_t* __restrict__ e
   }
 }
 
+// The plaintext pool as the MAC consumes it, once per run: limbs below 2^50
+// as the bits of their centred double (|p| <= q/2), the others unchanged.
+// grid: (N / 256, limbs, pool entries); pool_c is [entry][level][N].
+__global__ __launch_bounds__(256) void k_pool_centre(const uint64_t* __restrict__ pool, size_t pool_stride,
+                                                     uint64_t* __restrict__ pool_c, int level, int logn,
+                                                     const ModInfo* __restrict__ mods) {
+  const size_t n = (size_t)1 << logn;
+  const size_t k = (size_t)blockIdx.x * 256 + threadIdx.x;
+  const int limb = blockIdx.y;
+  const ModInfo mi = mods[limb];
+  const uint64_t v = pool[(size_t)blockIdx.z * pool_stride + (size_t)limb * n + k];
+  pool_c[((size_t)blockIdx.z * level + limb) * n + k] =
+      mi.k <= 50 ? f64_to_bits(centre_f64(u52_to_f64(v), mi.dqinv, (double)mi.q)) : v;
+}
+
 // out[i,o] (unrescaled) for every item: grid (items, tiles of 256
-// coefficients, limbs), the (item, tile) of a workgroup decoded from its
-// linear id as below.  A thread keeps OG outputs' 128-bit accumulators
-// (both polynomials) in registers and streams the item's rotated copies once
-// per group of OG outputs (the copies of one tile stay in L2 between groups);
-// every (output, rotation) plaintext residue is read once.  Integer path:
-// accumulators stay below 4 q 2^64 by subtracting 2 q 2^64 (a multiple of q)
-// after every second term; two REDCs give the canonical residue.
-template <int OG>
+// coefficients, limbs of one arithmetic path x polynomial groups), the
+// (item, tile) of a workgroup decoded from its linear id as below; the limb
+// is limbs[blockIdx.z / (3 - PS)].  A thread keeps OG outputs' accumulators
+// of PS polynomials (both, or the one blockIdx.z selects) in registers and
+// streams the item's rotated copies once per group of OG outputs; every
+// (output, rotation) plaintext residue is read once (from the pool as
+// k_pool_centre leaves it, stride level N per entry, mostly from L2: all
+// items of a tile run on one XCD in a row).  WIDE instantiations take the
+// primes above 2^50 (integer products), the others the primes below 2^50
+// (centred FP64 products); each path is its own launch, so each gets the
+// registers (and occupancy) its accumulators need.
+template <int OG, int PS, bool WIDE>
 __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ rot_all, int level, int logn,
                                                    const ModInfo* __restrict__ mods,
                                                    const int32_t* __restrict__ rot_off,
@@ -89,7 +110,8 @@ __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ 
                                                    const int32_t* __restrict__ out_off,
                                                    const int32_t* __restrict__ pt_off,
                                                    const int32_t* __restrict__ pt_index,
-                                                   const uint64_t* __restrict__ pool, size_t pool_stride,
+                                                   const uint64_t* __restrict__ pool_c,
+                                                   const int32_t* __restrict__ limbs,
                                                    uint64_t* __restrict__ mac_all) {
   const size_t n = (size_t)1 << logn;
   // Workgroups go round-robin to the 8 XCDs by linear id (x fastest; gridDim.y,
@@ -100,15 +122,17 @@ __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ 
   const int xcd = lin & 7, r = lin >> 3;
   const int it = r % (int)gridDim.x;
   const size_t k = (size_t)((r / (int)gridDim.x) * 8 + xcd) * 256 + threadIdx.x;
-  const int limb = blockIdx.z;
+  const int limb = limbs[PS == 2 ? (int)blockIdx.z : (int)blockIdx.z >> 1];
+  const int z0 = PS == 2 ? 0 : (int)blockIdx.z & 1;  // first polynomial of this workgroup
   const ModInfo mi = mods[limb];
   const uint64_t q2 = 2 * mi.q;
   const size_t ln = (size_t)level * n;
   const int r0 = rot_off[it], nr = rot_off[it + 1] - r0;
   const int o0 = out_off[it], no = out_off[it + 1] - o0;
   const int32_t* pix = pt_index + pt_off[it];
-  const uint64_t* poolk = pool + (size_t)limb * n + k;
-  if (mi.k <= 50) {
+  const uint64_t* poolk = pool_c + (size_t)limb * n + k;
+  const size_t zoff = (size_t)z0 * ln + (size_t)limb * n + k;
+  if (!WIDE) {
     // Primes below 2^50: centred FP64 products (mul_f64_c with the quotient
     // estimate p fl(1/q), off by less than 0.1 for |x|, |p| <= q/2 + 1, so
     // every product is exact and below 0.6 q in magnitude).  The sums are
@@ -116,22 +140,26 @@ __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ 
     const double dq = (double)mi.q, dqi = mi.dqinv;
     for (int og = 0; og < no; og += OG) {
       const int cnt = no - og < OG ? no - og : OG;
-      double a[OG][2];
+      double a[OG][PS];
 #pragma unroll
-      for (int u = 0; u < OG; u++) a[u][0] = a[u][1] = 0.0;
+      for (int u = 0; u < OG; u++)
+#pragma unroll
+        for (int z = 0; z < PS; z++) a[u][z] = 0.0;
       for (int t = 0; t < nr; t++) {
-        const uint64_t* rc = rot_all + (size_t)rot_idx[r0 + t] * 2 * ln + (size_t)limb * n + k;
-        const double x0 = centre_f64(u52_to_f64(rc[0]), dqi, dq), x1 = centre_f64(u52_to_f64(rc[ln]), dqi, dq);
+        const uint64_t* rc = rot_all + (size_t)rot_idx[r0 + t] * 2 * ln + zoff;
+        double x[PS];
+#pragma unroll
+        for (int z = 0; z < PS; z++) x[z] = centre_f64(u52_to_f64(rc[z * ln]), dqi, dq);
+        const int32_t* pt = pix + og * nr + t;
 #pragma unroll
         for (int u = 0; u < OG; u++) {
           if (u < cnt) {
-            const double p = centre_f64(u52_to_f64(poolk[(size_t)pix[(og + u) * nr + t] * pool_stride]), dqi, dq);
+            const double p = bits_to_f64(poolk[(size_t)pt[u * nr] * ln]);
             const double pq = p * dqi;
-            a[u][0] += mul_f64_c(x0, p, pq, dq);
-            a[u][1] += mul_f64_c(x1, p, pq, dq);
-            if ((t & 7) == 7) {
-              a[u][0] = centre_f64(a[u][0], dqi, dq);
-              a[u][1] = centre_f64(a[u][1], dqi, dq);
+#pragma unroll
+            for (int z = 0; z < PS; z++) {
+              a[u][z] += mul_f64_c(x[z], p, pq, dq);
+              if ((t & 7) == 7) a[u][z] = centre_f64(a[u][z], dqi, dq);
             }
           }
         }
@@ -139,31 +167,37 @@ __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ 
 #pragma unroll
       for (int u = 0; u < OG; u++) {
         if (u < cnt) {
-          uint64_t* dst = mac_all + (size_t)(o0 + og + u) * 2 * ln + (size_t)limb * n + k;
-          dst[0] = f64_to_u52(canon_f64(a[u][0], dqi, dq));
-          dst[ln] = f64_to_u52(canon_f64(a[u][1], dqi, dq));
+          uint64_t* dst = mac_all + (size_t)(o0 + og + u) * 2 * ln + zoff;
+#pragma unroll
+          for (int z = 0; z < PS; z++) dst[z * ln] = f64_to_u52(canon_f64(a[u][z], dqi, dq));
         }
       }
     }
     return;
   }
+  // Primes above 2^50: 128-bit products; accumulators stay below 4 q 2^64 by
+  // subtracting 2 q 2^64 (a multiple of q) after every second term; two
+  // REDCs give the canonical residue.
   for (int og = 0; og < no; og += OG) {
     const int cnt = no - og < OG ? no - og : OG;
-    U128 a[OG][2];
+    U128 a[OG][PS];
 #pragma unroll
-    for (int u = 0; u < OG; u++) a[u][0] = a[u][1] = U128{0, 0};
+    for (int u = 0; u < OG; u++)
+#pragma unroll
+      for (int z = 0; z < PS; z++) a[u][z] = U128{0, 0};
     for (int t = 0; t < nr; t++) {
-      const uint64_t* rc = rot_all + (size_t)rot_idx[r0 + t] * 2 * ln + (size_t)limb * n + k;
-      const uint64_t x0 = rc[0], x1 = rc[ln];
+      const uint64_t* rc = rot_all + (size_t)rot_idx[r0 + t] * 2 * ln + zoff;
+      uint64_t x[PS];
+#pragma unroll
+      for (int z = 0; z < PS; z++) x[z] = rc[z * ln];
 #pragma unroll
       for (int u = 0; u < OG; u++) {
         if (u < cnt) {
-          const uint64_t p = poolk[(size_t)pix[(og + u) * nr + t] * pool_stride];
-          add_wide(a[u][0], mul_wide(p, x0));
-          add_wide(a[u][1], mul_wide(p, x1));
-          if (t & 1) {
-            if (a[u][0].hi >= q2) a[u][0].hi -= q2;
-            if (a[u][1].hi >= q2) a[u][1].hi -= q2;
+          const uint64_t p = poolk[(size_t)pix[(og + u) * nr + t] * ln];
+#pragma unroll
+          for (int z = 0; z < PS; z++) {
+            add_wide(a[u][z], mul_wide(p, x[z]));
+            if ((t & 1) && a[u][z].hi >= q2) a[u][z].hi -= q2;
           }
         }
       }
@@ -171,9 +205,9 @@ __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ 
 #pragma unroll
     for (int u = 0; u < OG; u++) {
       if (u < cnt) {
-        uint64_t* dst = mac_all + (size_t)(o0 + og + u) * 2 * ln + (size_t)limb * n + k;
+        uint64_t* dst = mac_all + (size_t)(o0 + og + u) * 2 * ln + zoff;
 #pragma unroll
-        for (int z = 0; z < 2; z++) {
+        for (int z = 0; z < PS; z++) {
           U128 v = a[u][z];
           if (v.hi >= q2) v.hi -= q2;
           if (v.hi >= mi.q) v.hi -= mi.q;
@@ -184,13 +218,37 @@ __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ 
   }
 }
 
-static void launch_mac(int og, dim3 grid, hipStream_t s, const uint64_t* rot, int l, int logn, const ModInfo* mods,
-                       const int32_t* ro, const int32_t* ri, const int32_t* oo, const int32_t* po, const int32_t* pi,
-                       const uint64_t* pool, size_t ps, uint64_t* mac) {
-  if (og == 4)
-    k_mac_multi<4><<<grid, 256, 0, s>>>(rot, l, logn, mods, ro, ri, oo, po, pi, pool, ps, mac);
-  else
-    k_mac_multi<8><<<grid, 256, 0, s>>>(rot, l, logn, mods, ro, ri, oo, po, pi, pool, ps, mac);
+// MAC variants (outputs per register group, polynomials per workgroup)
+constexpr int MAC_VARIANTS = 5;
+constexpr int MAC_OG[MAC_VARIANTS] = {4, 8, 16, 16, 32};
+constexpr int MAC_PS[MAC_VARIANTS] = {2, 2, 2, 1, 1};
+constexpr int MAC_DEFAULT = 2;
+
+// FP64 limbs with variant v, then the integer limbs (8 outputs, both
+// polynomials per workgroup)
+static void launch_mac(int v, int B, int tiles, int l, hipStream_t s, const uint64_t* rot, int logn,
+                       const ModInfo* mods, const int32_t* ro, const int32_t* ri, const int32_t* oo, const int32_t* po,
+                       const int32_t* pi, const uint64_t* pool_c, const int32_t* limbs_f, int nf,
+                       const int32_t* limbs_i, int ni, uint64_t* mac) {
+  if (nf > 0) {
+    const dim3 grid(B, tiles, nf * (3 - MAC_PS[v]));
+#define HE_MAC(i, OG, PS) \
+  case i:                 \
+    k_mac_multi<OG, PS, false><<<grid, 256, 0, s>>>(rot, l, logn, mods, ro, ri, oo, po, pi, pool_c, limbs_f, mac); \
+    break;
+    switch (v) {
+      HE_MAC(0, 4, 2)
+      HE_MAC(1, 8, 2)
+      HE_MAC(2, 16, 2)
+      HE_MAC(3, 16, 1)
+      default:
+      HE_MAC(4, 32, 1)
+    }
+#undef HE_MAC
+  }
+  if (ni > 0)
+    k_mac_multi<8, 2, true><<<dim3(B, tiles, ni), 256, 0, s>>>(rot, l, logn, mods, ro, ri, oo, po, pi, pool_c, limbs_i,
+                                                               mac);
 }
 
 // ---------------------------------------------------------------- plan
@@ -220,16 +278,18 @@ struct Batch {
           *d_pt_index = nullptr;
   // device workspaces
   uint64_t *coeff = nullptr, *ext = nullptr, *u = nullptr, *y = nullptr, *rot = nullptr, *mac = nullptr,
-           *rs_T = nullptr, *rs_R = nullptr;
+           *rs_T = nullptr, *rs_R = nullptr, *pool_c = nullptr;
+  int32_t *d_limbs_f = nullptr, *d_limbs_i = nullptr;  // limbs of the MAC's FP64 / integer paths
+  int n_limbs_f = 0, n_limbs_i = 0;
   int rs_chunk = 0;
-  int mac_og = 8;  // outputs per register group in the fused MAC (autotuned)
+  int mac_v = MAC_DEFAULT;  // MAC variant (register grouping; autotuned)
   int nmax = 0;    // largest rotation set
   std::vector<void*> allocs;
   std::vector<int32_t> locked;  // keys held resident for the batch
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool use_graph = false;
-  float tuned_ms[2] = {0, 0};
+  float tuned_ms[MAC_VARIANTS] = {0, 0, 0, 0, 0};
   double out_scale = 0;
 };
 
@@ -307,10 +367,17 @@ static int run_batched(Batch* b, hipStream_t s) {
     for (int i = 0; i < b->B; i++) terms += (double)b->n_rot[i] * b->n_out[i];
     int nf = 0;  // limbs on the FP64 path
     for (int i = 0; i < l; i++) nf += c->hmod[i].k <= 50;
+    {
+      ProfScope pc(c, "pool_centre", s, 16.0 * N * l * b->npool, 0);
+      k_pool_centre<<<dim3(N / 256, l, b->npool), 256, 0, s>>>(b->pool, (size_t)b->pool_level * N, b->pool_c, l,
+                                                               c->log_n, c->d_mod);
+      HE_HIP(hipGetLastError());
+    }
     ProfScope ps(c, "mac_multi", s, 8.0 * N * l * (2.0 * b->total_pairs + terms + 2.0 * b->total_out), 2.0 * N * l * terms,
                  2.0 * N * terms * (nf / PEAK_MODMUL_F64 + (l - nf) / PEAK_MODMUL_INT));
-    launch_mac(b->mac_og, dim3(b->B, N / 256, l), s, b->rot, l, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx,
-               b->d_out_off, b->d_pt_off, b->d_pt_index, b->pool, (size_t)b->pool_level * N, b->mac);
+    launch_mac(b->mac_v, b->B, (int)(N / 256), l, s, b->rot, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx,
+               b->d_out_off, b->d_pt_off, b->d_pt_index, b->pool_c, b->d_limbs_f, b->n_limbs_f, b->d_limbs_i,
+               b->n_limbs_i, b->mac);
     HE_HIP(hipGetLastError());
   }
   // 4. rescale every output (chunks of rs_chunk ciphertexts = 2 rs_chunk polynomials)
@@ -435,8 +502,13 @@ int he_batch_create(he_ctx* h, const he_batch_desc* d, int flags, he_batch** out
     HE_HIP(hipMemcpy(*dst, v.data(), v.size() * 4, hipMemcpyHostToDevice));
     return HE_OK;
   };
+  std::vector<int32_t> lf, li;  // the MAC's limbs by arithmetic path
+  for (int i = 0; i < b->level; i++) (c->hmod[i].k <= 50 ? lf : li).push_back(i);
+  b->n_limbs_f = (int)lf.size();
+  b->n_limbs_i = (int)li.size();
   if ((rc = up(&b->d_rot_off, b->rot_off)) || (rc = up(&b->d_rot_idx, rot_idx)) || (rc = up(&b->d_out_off, b->out_off)) ||
-      (rc = up(&b->d_pt_off, b->pt_off)) || (rc = up(&b->d_pt_index, b->pt_index)))
+      (rc = up(&b->d_pt_off, b->pt_off)) || (rc = up(&b->d_pt_index, b->pt_index)) || (rc = up(&b->d_limbs_f, lf)) ||
+      (rc = up(&b->d_limbs_i, li)))
     return fail(rc);
   // workspaces
   const size_t N = c->n, l = b->level, K = c->K, dn = c->dnum(b->level), E = l + K;
@@ -445,34 +517,42 @@ int he_batch_create(he_ctx* h, const he_batch_desc* d, int flags, he_batch** out
       (rc = balloc(b, &b->u, (size_t)b->max_group * 2 * E * N)) || (rc = balloc(b, &b->y, (size_t)b->max_group * 2 * l * N)) ||
       (rc = balloc(b, &b->rot, (size_t)b->total_pairs * 2 * l * N)) ||
       (rc = balloc(b, &b->mac, (size_t)b->total_out * 2 * l * N)) || (rc = balloc(b, &b->rs_T, (size_t)2 * b->rs_chunk * N)) ||
-      (rc = balloc(b, &b->rs_R, (size_t)2 * b->rs_chunk * (l - 1) * N)))
+      (rc = balloc(b, &b->rs_R, (size_t)2 * b->rs_chunk * (l - 1) * N)) ||
+      (rc = balloc(b, &b->pool_c, (size_t)b->npool * l * N)))
     return fail(rc);
   for (int x : b->n_rot) b->nmax = std::max(b->nmax, x);
-  b->mac_og = (flags & HE_BATCH_MAC4) ? 4 : 8;
-  if (flags & HE_BATCH_TUNE) {
-    // time both register groupings of the fused MAC on this batch's shapes
-    // (workspace contents are irrelevant to the timing) and keep the faster
+  b->mac_v = (flags & HE_BATCH_MAC4) ? 0 : MAC_DEFAULT;
+  const int sel = (flags >> 8) & 15;  // HE_BATCH_MAC_SELECT(v) = (v + 1) << 8
+  if (sel > MAC_VARIANTS) return fail(set_error(HE_EINVAL, "unknown MAC variant"));
+  if (sel) b->mac_v = sel - 1;
+  if ((flags & HE_BATCH_TUNE) && !sel) {
+    // time every register grouping of the fused MAC on this batch's shapes
+    // (workspace contents are irrelevant to the timing) and keep the fastest
     hipStream_t ts;
     HE_HIP(hipStreamCreate(&ts));
     hipEvent_t e0, e1;
     HE_HIP(hipEventCreate(&e0));
     HE_HIP(hipEventCreate(&e1));
     float best = 1e30f;
-    for (int og : {4, 8}) {
-      dim3 grid(b->B, N / 256, l);
-      launch_mac(og, grid, ts, b->rot, l, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx, b->d_out_off, b->d_pt_off,
-                 b->d_pt_index, b->pool, (size_t)b->pool_level * N, b->mac);
+    k_pool_centre<<<dim3(N / 256, l, b->npool), 256, 0, ts>>>(b->pool, (size_t)b->pool_level * N, b->pool_c, l,
+                                                              c->log_n, c->d_mod);
+    HE_HIP(hipGetLastError());
+    for (int v = 0; v < MAC_VARIANTS; v++) {
+      launch_mac(v, b->B, (int)(N / 256), l, ts, b->rot, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx,
+                 b->d_out_off, b->d_pt_off, b->d_pt_index, b->pool_c, b->d_limbs_f, b->n_limbs_f, b->d_limbs_i,
+                 b->n_limbs_i, b->mac);
       HE_HIP(hipEventRecord(e0, ts));
-      launch_mac(og, grid, ts, b->rot, l, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx, b->d_out_off, b->d_pt_off,
-                 b->d_pt_index, b->pool, (size_t)b->pool_level * N, b->mac);
+      launch_mac(v, b->B, (int)(N / 256), l, ts, b->rot, c->log_n, c->d_mod, b->d_rot_off, b->d_rot_idx,
+                 b->d_out_off, b->d_pt_off, b->d_pt_index, b->pool_c, b->d_limbs_f, b->n_limbs_f, b->d_limbs_i,
+                 b->n_limbs_i, b->mac);
       HE_HIP(hipEventRecord(e1, ts));
       HE_HIP(hipEventSynchronize(e1));
       float ms = 0;
       HE_HIP(hipEventElapsedTime(&ms, e0, e1));
-      b->tuned_ms[og == 4 ? 0 : 1] = ms;
+      b->tuned_ms[v] = ms;
       if (ms < best) {
         best = ms;
-        b->mac_og = og;
+        b->mac_v = v;
       }
     }
     hipEventDestroy(e0);
@@ -564,11 +644,14 @@ int he_batch_info(const he_batch* hb, int32_t* total_rotations, int32_t* total_o
   return HE_OK;
 }
 
-int he_batch_tuning(const he_batch* hb, int32_t* mac_outputs_per_group, float* ms_group4, float* ms_group8) {
+int he_batch_tuning(const he_batch* hb, int32_t* outputs_per_group, int32_t* polys_per_group, float* ms,
+                    int32_t cap) {
   if (!hb) return set_error(HE_EINVAL, "null batch");
-  if (mac_outputs_per_group) *mac_outputs_per_group = hb->b.mac_og;
-  if (ms_group4) *ms_group4 = hb->b.tuned_ms[0];
-  if (ms_group8) *ms_group8 = hb->b.tuned_ms[1];
+  if (ms && cap < MAC_VARIANTS) return set_error(HE_EINVAL, "ms needs HE_BATCH_MAC_VARIANTS entries");
+  if (outputs_per_group) *outputs_per_group = MAC_OG[hb->b.mac_v];
+  if (polys_per_group) *polys_per_group = MAC_PS[hb->b.mac_v];
+  if (ms)
+    for (int v = 0; v < MAC_VARIANTS; v++) ms[v] = hb->b.tuned_ms[v];
   return HE_OK;
 }
 

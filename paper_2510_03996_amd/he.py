@@ -113,6 +113,12 @@ class he_batch_desc(ctypes.Structure):
 
 
 BATCH_GRAPH, BATCH_MAC4, BATCH_TUNE = 1, 2, 4
+BATCH_MAC_VARIANTS = 5
+
+
+def batch_mac_select(v):
+    """HE_BATCH_MAC_SELECT(v): run the batched MAC as variant v (0..4)."""
+    return (int(v) + 1) << 8
 
 _lib = None
 
@@ -166,7 +172,7 @@ def lib():
             "he_batch_run_plain": [vp, vp],
             "he_batch_info": [vp, P(i32), P(i32), P(i32), P(ctypes.c_double)],
             "he_batch_destroy": [vp],
-            "he_batch_tuning": [vp, P(i32), P(ctypes.c_float), P(ctypes.c_float)],
+            "he_batch_tuning": [vp, P(i32), P(i32), P(ctypes.c_float), i32],
             "he_lane_reserve": [vp, vp, c_int],
             "he_lane_release": [vp, vp],
             "he_ctx_ntt_tuning": [vp, P(i32), P(ctypes.c_float)],
@@ -654,9 +660,14 @@ class Batch:
         return {"rotations": a.value, "outputs": b.value, "keys": c.value, "out_scale": sc.value}
 
     def tuning(self):
-        og, a, b = ctypes.c_int32(), ctypes.c_float(), ctypes.c_float()
-        _check(lib().he_batch_tuning(self.h, ctypes.byref(og), ctypes.byref(a), ctypes.byref(b)))
-        return {"mac_outputs_per_group": og.value, "ms_group4": round(a.value, 3), "ms_group8": round(b.value, 3)}
+        """MAC variant in use and the autotuner's milliseconds per variant
+        (outputs per register group x polynomials per workgroup)."""
+        og, ps = ctypes.c_int32(), ctypes.c_int32()
+        ms = (ctypes.c_float * BATCH_MAC_VARIANTS)()
+        _check(lib().he_batch_tuning(self.h, ctypes.byref(og), ctypes.byref(ps), ms, BATCH_MAC_VARIANTS))
+        names = ["%dx%d" % v for v in ((4, 2), (8, 2), (16, 2), (16, 1), (32, 1))]
+        return {"mac_outputs_per_group": og.value, "mac_polys_per_group": ps.value,
+                "ms": {n: round(m, 3) for n, m in zip(names, ms)}}
 
     def close(self):
         if self.h:

@@ -84,6 +84,26 @@ def test_batch_matches_plain_and_oracle(name, flags):
     g.close()
 
 
+@pytest.mark.parametrize("variant", range(5))
+def test_batch_every_mac_variant(variant):
+    """Every register grouping of the batched MAC (outputs per group x
+    polynomials per workgroup) equals the per-op path and the oracle, on
+    items with up to 40 outputs (several groups for every variant)."""
+    from paper_2510_03996_amd import he
+
+    name = "config1"
+    octx, sets, outs, cts, pool, pti = make_batch(name, 4, 6, 2, 4, 1, 3, seed=53)
+    outs[0], outs[2] = 40, 17
+    pti = [[(i + 7 * o + 13 * t) % 6 for o in range(outs[i]) for t in range(len(sets[i]))] for i in range(4)]
+    g = H.gpu_ctx(name)
+    got_b, got_p, info = run_gpu(g, name, sets, outs, cts, pool, pti, he.batch_mac_select(variant) | 1)
+    H.assert_limbs_equal(got_b, got_p, "batched (MAC variant %d) vs plain" % variant)
+    want = oracle_outputs(name, sets, outs, cts, pool, pti)
+    for k in (0, 39, 40, 41, len(want) - 1):
+        H.assert_limbs_equal(got_b[k], want[k].data, "batched vs oracle output %d" % k)
+    g.close()
+
+
 def test_batch_larger_config2_batched_equals_plain():
     """16 ciphertexts at N=2^16, L=24, 9-15 rotations from a 7x7-window pool, 1-8 outputs."""
     name = "config2"
@@ -113,9 +133,12 @@ def test_batch_mac_extreme_residues():
             edge = np.array([0, 1, q[i] - 1, q[i] // 2, q[i] // 2 + 1], dtype=np.uint64)
             sel = (k + p + i) % 7
             d[i] = np.where(sel < 5, edge[np.minimum(sel, 4)], d[i] % qi)
+    from paper_2510_03996_amd import he
+
     g = H.gpu_ctx(name)
-    got_b, got_p, info = run_gpu(g, name, sets, outs, cts, pool, pti, 0)
-    H.assert_limbs_equal(got_b, got_p, "batched vs plain, extreme plaintext residues")
+    for v in (0, 4):  # both polynomials per workgroup, and one
+        got_b, got_p, info = run_gpu(g, name, sets, outs, cts, pool, pti, he.batch_mac_select(v))
+        H.assert_limbs_equal(got_b, got_p, "batched (MAC variant %d) vs plain, extreme plaintext residues" % v)
     g.close()
 
 

@@ -19,7 +19,7 @@
 //      accumulators in registers and streams the item's rotated copies once
 //      per group (centred FP64 products for the primes below 2^50, 128-bit
 //      products otherwise);
-//   4. rescale of all outputs in chunks.
+//   4. rescale of all outputs in chunks (a ModDown by the top prime).
 // The result is bit-identical to the per-op path (he_rotate_hoisted,
 // he_mul_plain, he_rescale), which he_batch_run_plain executes for
 // comparison: every step is the same exact modular arithmetic.
@@ -380,20 +380,14 @@ static int run_batched(Batch* b, hipStream_t s) {
                b->n_limbs_i, b->mac);
     HE_HIP(hipGetLastError());
   }
-  // 4. rescale every output (chunks of rs_chunk ciphertexts = 2 rs_chunk polynomials)
+  // 4. rescale every output (chunks of rs_chunk ciphertexts = 2 rs_chunk
+  // polynomials): a ModDown by q_{l-1} whose epilogue writes the outputs
   const int t = l - 1;
   for (int o0 = 0; o0 < b->total_out; o0 += b->rs_chunk) {
     const int cnt = std::min(b->rs_chunk, b->total_out - o0);
-    const int z = 2 * cnt;
-    const uint64_t* src = b->mac + (size_t)o0 * 2 * ln;
-    if ((rc = ntt_launch_strided(c, src + (size_t)t * N, ln, b->rs_T, N, z, range_map(0, 1, t), true, s))) return rc;
-    k_bcast_reduce<<<dim3(N / 256, t, z), 256, 0, s>>>(b->rs_T, b->rs_R, t, c->log_n, c->d_mod);
-    HE_HIP(hipGetLastError());
-    if ((rc = ntt_launch(c, b->rs_R, (size_t)t * N, z, range_map(0, t, 0), false, s))) return rc;
-    ProfScope ps(c, "rescale_combine", s, 8.0 * N * t * z * 3, (double)N * t * z);
-    k_rescale_combine<<<dim3(N / 256, t, z), 256, 0, s>>>(src, ln, b->rs_R, b->out + (size_t)o0 * 2 * t * N,
-                                                          (size_t)t * N, t, c->log_n, c->d_mod, c->d_rescale[l]);
-    HE_HIP(hipGetLastError());
+    if ((rc = rescale_launch(c, b->mac + (size_t)o0 * 2 * ln, ln, b->out + (size_t)o0 * 2 * t * N, (size_t)t * N,
+                             2 * cnt, l, b->rs_T, b->rs_R, s)))
+      return rc;
   }
   return HE_OK;
 }

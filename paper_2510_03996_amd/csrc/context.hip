@@ -333,6 +333,7 @@ static int ctx_init(Ctx* c, const he_params* p) {
   // ---- basis conversion tables for every level
   c->modup.assign(c->L + 1, {});
   c->moddown.assign(c->L + 1, {});
+  c->rsconv.assign(c->L + 1, {});
   c->modup_ntt.assign(c->L + 1, LimbMap{});
   c->d_rescale.assign(c->L + 1, nullptr);
   c->d_pinv.assign(c->L + 1, nullptr);
@@ -390,14 +391,25 @@ static int ctx_init(Ctx* c, const he_params* p) {
     if ((rc = dev_alloc(c, &c->d_pinv[l], 4 * l))) return rc;
     HE_HIP(hipMemcpy(c->d_pinv[l], pv.data(), 4 * l * 8, hipMemcpyHostToDevice));
     if (l >= 2) {
-      std::vector<uint64_t> rv(2 * (l - 1));
-      uint64_t qt = c->mod[l - 1];
-      for (int i = 0; i < l - 1; i++) {
+      // rescale = ModDown by the single prime q_{l-1}: its conversion (one
+      // input, constant 1) and q_{l-1}^{-1} in the epilogue's layout
+      const int t = l - 1;
+      std::vector<uint64_t> rv(4 * t);
+      uint64_t qt = c->mod[t];
+      for (int i = 0; i < t; i++) {
         rv[i] = hinv(qt % c->mod[i], c->mod[i]);
-        rv[l - 1 + i] = shoup_of(rv[i], c->mod[i]);
+        rv[t + i] = shoup_of(rv[i], c->mod[i]);
+        const double w = (double)rv[i], wq = (double)rv[i] / (double)c->mod[i];
+        std::memcpy(&rv[2 * t + i], &w, 8);
+        std::memcpy(&rv[3 * t + i], &wq, 8);
       }
-      if ((rc = dev_alloc(c, &c->d_rescale[l], 2 * (l - 1)))) return rc;
-      HE_HIP(hipMemcpy(c->d_rescale[l], rv.data(), 2 * (l - 1) * 8, hipMemcpyHostToDevice));
+      if ((rc = dev_alloc(c, &c->d_rescale[l], 4 * t))) return rc;
+      HE_HIP(hipMemcpy(c->d_rescale[l], rv.data(), 4 * t * 8, hipMemcpyHostToDevice));
+      std::vector<int> rin{0}, rim{t}, rop, rom;
+      for (int i = 0; i < t; i++) { rop.push_back(i); rom.push_back(i); }
+      std::vector<ConvDesc> rs1(1);
+      if ((rc = build_conv(c, rs1[0], rin, rim, rop, rom))) return rc;
+      if ((rc = upload_set(c, c->rsconv[l], rs1))) return rc;
     }
   }
   // ---- workspace: one top-level key switch + tensor + rescale scratch

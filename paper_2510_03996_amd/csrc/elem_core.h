@@ -144,11 +144,6 @@ HE_HD uint64_t moddown_elem(uint64_t u, uint64_t y, uint64_t add, uint64_t pinv,
   return add_mod(add, mul_shoup(sub_mod(u, y, q), pinv, pinvp, q), q);
 }
 
-// Rescale epilogue: (c - r) * q_t^{-1} mod q_i
-HE_HD uint64_t rescale_elem(uint64_t c, uint64_t r, uint64_t w, uint64_t wp, uint64_t q) {
-  return mul_shoup(sub_mod(c, r, q), w, wp, q);
-}
-
 // x mod q for any x < 2^64 (x < q^2 holds for every prime >= 2^32 used here;
 // smaller moduli fall back to the % operator)
 HE_HD uint64_t reduce_word(uint64_t x, const ModInfo& m) {

@@ -83,11 +83,14 @@ struct Ctx {
   double *d_dtw = nullptr, *d_dtwq = nullptr, *d_ditw = nullptr, *d_ditwq = nullptr;
   // modup[level][digit]; moddown[level]
   std::vector<ConvSet> modup, moddown;
+  std::vector<ConvSet> rsconv;  // rescale at level l: q_{l-1} -> q_0..q_{l-2} (l >= 2)
   // per level: [L+K][4] finishing constants of the inverse transforms that
   // feed the conversions (conv_fin_fill): N^{-1} (Qin/q_m)^{-1} mod q_m
   std::vector<uint64_t*> d_fin;
   std::vector<LimbMap> modup_ntt;  // per level: every converted limb of every digit (ext-relative)
-  // per level l (>= 2): Shoup pairs of q_{l-1}^{-1} mod q_i (i < l-1): [2][l-1]
+  // per level l (>= 2): q_{l-1}^{-1} mod q_i (i < l-1) as [l-1] integers, [l-1]
+  // Shoup companions, then (double bits) [l-1] values and [l-1] values / q_i:
+  // the layout of NttEpi::pinv, so the rescale reuses the ModDown epilogue
   std::vector<uint64_t*> d_rescale;
   // per level l: Shoup pairs of P^{-1} mod q_i: [2][l]
   std::vector<uint64_t*> d_pinv;
@@ -191,9 +194,9 @@ struct NttEpi {
                          // double bits) [level] P^{-1} and [level] P^{-1} / q_i
   uint32_t g;
   int32_t level;
-  // batched form (items != nullptr): batch z = 2 pair + poly writes
+  // batched form (out_base != nullptr): batch z = 2 pair + poly writes
   // out_base + z out_bs; add_z = add_base + items[pair] add_item for poly 0
-  // (gathered through phi_g), none for poly 1
+  // (gathered through phi_g), none for poly 1 or when add_base is null
   const int32_t* items;
   const uint64_t* add_base;
   size_t add_item;
@@ -213,6 +216,15 @@ int ntt_launch_moddown(Ctx* c, const uint64_t* y, size_t y_bs, const LimbMap& ma
 // both (src -> data), 1 = pass 1 only (in place on data).
 int ntt_launch_conv_in(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* data, size_t batch_stride, int nbatch,
                        const LimbMap& map, const uint64_t* fin, int passes, hipStream_t s);
+// Rescale of npolys polynomials at level l (polynomial z at in + z in_bs,
+// result at out + z out_bs, l - 1 limbs; out may equal in with equal
+// strides) as a ModDown by the single prime q_{l-1}: inverse transform of the
+// top limbs into T ([npolys][N] scratch), the conversion to q_0..q_{l-2}
+// fused with the forward column pass into Y ([npolys][l-1][N] scratch), the
+// forward row pass with the epilogue (c_i - y_i) q_{l-1}^{-1}.  Floor
+// rounding, canonical outputs: the same residues as the textbook rescale.
+int rescale_launch(Ctx* c, const uint64_t* in, size_t in_bs, uint64_t* out, size_t out_bs, int npolys, int l,
+                   uint64_t* T, uint64_t* Y, hipStream_t s);
 // Basis conversion fused into the forward column pass of its outputs: for
 // batch z (descriptor set.d[z % zdiv], inputs in + (z / zdiv) in_bs, outputs
 // out + z out_bs) every output limb out_pos[p] receives forward pass 1 of
@@ -315,11 +327,6 @@ int check_ct(const Ctx* c, const he_ct* x, const char* what);
 int check_out(const Ctx* c, const he_ct* x, int need_level);
 
 __global__ void k_to_mont(uint64_t* key, int M, int logn, const ModInfo* __restrict__ mods);
-__global__ void k_bcast_reduce(const uint64_t* __restrict__ T, uint64_t* __restrict__ R, int nl, int logn,
-                               const ModInfo* __restrict__ mods);
-__global__ void k_rescale_combine(const uint64_t* in, size_t ips, const uint64_t* __restrict__ R, uint64_t* out,
-                                  size_t ops, int nl, int logn, const ModInfo* __restrict__ mods,
-                                  const uint64_t* __restrict__ tab);
 
 int32_t norm_key_id(const Ctx* c, int32_t id);
 uint32_t galois_elt(const Ctx* c, int32_t r);

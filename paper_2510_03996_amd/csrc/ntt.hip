@@ -44,9 +44,11 @@ __device__ __forceinline__ void ntt_store(uint64_t* a, int k, uint64_t v, const 
     a[k] = v;
   } else {
     const size_t off = (size_t)i << LOGN;
-    const bool gather = epi.items ? (z & 1) == 0 : z == 0;  // the polynomial c0 is added to
-    const uint64_t* add = epi.items ? (gather ? epi.add_base + epi.items[z >> 1] * epi.add_item : nullptr) : epi.add[z];
-    uint64_t* out = epi.items ? epi.out_base + z * epi.out_bs : epi.out[z];
+    const bool batched = epi.out_base != nullptr;
+    const bool gather = batched ? (z & 1) == 0 : z == 0;  // the polynomial c0 is added to
+    const uint64_t* add = batched ? (gather && epi.add_base ? epi.add_base + epi.items[z >> 1] * epi.add_item : nullptr)
+                                  : epi.add[z];
+    uint64_t* out = batched ? epi.out_base + z * epi.out_bs : epi.out[z];
     uint64_t x = 0;
     if (add) x = add[off + (gather && epi.g != 1 ? automorph_src(k, epi.g, LOGN) : (uint32_t)k)];
     out[off + k] = moddown_elem(epi.u[z * epi.u_bs + off + k], v, x, epi.pinv[i], epi.pinv[epi.level + i], q);
@@ -104,11 +106,13 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
       const size_t off = (size_t)pos << LOGN;
       const double pw = bits_to_f64(epi.pinv[2 * epi.level + pos]);
       const double pwq = bits_to_f64(epi.pinv[3 * epi.level + pos]);
-      const bool gather = epi.items ? (bz & 1) == 0 : bz == 0;  // the polynomial c0 is added to
-      const uint64_t* add =
-          epi.items ? (gather ? epi.add_base + epi.items[bz >> 1] * epi.add_item : nullptr) : epi.add[bz];
+      const bool batched = epi.out_base != nullptr;
+      const bool gather = batched ? (bz & 1) == 0 : bz == 0;  // the polynomial c0 is added to
+      const uint64_t* add = batched ? (gather && epi.add_base ? epi.add_base + epi.items[bz >> 1] * epi.add_item
+                                                              : nullptr)
+                                    : epi.add[bz];
       const uint64_t* u = epi.u + bz * epi.u_bs + off;
-      uint64_t* o = (epi.items ? epi.out_base + bz * epi.out_bs : epi.out[bz]) + off;
+      uint64_t* o = (batched ? epi.out_base + bz * epi.out_bs : epi.out[bz]) + off;
       for (int e = tid; e < P::TILE; e += P::THREADS) {
         int g, k;
         P::tile_elem(e, g, k);
@@ -729,6 +733,30 @@ int ntt_launch_conv_in(Ctx* c, const uint64_t* src, size_t src_bs, uint64_t* dat
     case 16: return ntt_launch_n<16>(c, src, src_bs, data, batch_stride, nbatch, map, true, s, nullptr, passes, fin);
   }
   return set_error(HE_EINVAL, "unsupported ring degree");
+}
+
+int rescale_launch(Ctx* c, const uint64_t* in, size_t in_bs, uint64_t* out, size_t out_bs, int npolys, int l,
+                   uint64_t* T, uint64_t* Y, hipStream_t s) {
+  if (l < 2 || npolys <= 0) return set_error(HE_EINVAL, "bad rescale");
+  const int t = l - 1;
+  const size_t N = c->n;
+  int rc;
+  // top limbs to coefficient form (a one-input conversion needs no factor
+  // beyond N^{-1})
+  if ((rc = ntt_launch_conv_in(c, in + (size_t)t * N, in_bs, T, N, npolys, range_map(0, 1, t), nullptr, 3, s)))
+    return rc;
+  if ((rc = conv_fwd1_launch(c, c->rsconv[l], T, N, Y, (size_t)t * N, npolys, 1, c->conv_target[1], "conv_fwd1_rescale",
+                             s)))
+    return rc;
+  NttEpi epi{};
+  epi.u = in;
+  epi.u_bs = in_bs;
+  epi.pinv = c->d_rescale[l];
+  epi.g = 1;
+  epi.level = t;
+  epi.out_base = out;
+  epi.out_bs = out_bs;
+  return ntt_launch_moddown(c, Y, (size_t)t * N, range_map(0, t, 0), epi, s, npolys, 2);
 }
 
 // Conversion kernel shape: 1024-residue column tiles, 4 residues per thread

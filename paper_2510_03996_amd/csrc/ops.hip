@@ -37,28 +37,6 @@ __global__ __launch_bounds__(256) void k_mul_plain(const uint64_t* in, size_t ip
   out[k * ops + i * n + j] = r;
 }
 
-// R[k][i][j] = T[k][j] mod q_i  (top-limb residues broadcast to the lower limbs)
-__global__ __launch_bounds__(256) void k_bcast_reduce(const uint64_t* __restrict__ T, uint64_t* __restrict__ R,
-                                                      int nl, int logn, const ModInfo* __restrict__ mods) {
-  const size_t n = (size_t)1 << logn;
-  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y, k = blockIdx.z;
-  R[((size_t)k * nl + i) * n + j] = reduce_word(T[k * n + j], mods[i]);
-}
-
-// out[k][i][j] = (in[k][i][j] - R[k][i][j]) * q_t^{-1} mod q_i
-__global__ __launch_bounds__(256) void k_rescale_combine(const uint64_t* in, size_t ips,
-                                                         const uint64_t* __restrict__ R, uint64_t* out, size_t ops,
-                                                         int nl, int logn, const ModInfo* __restrict__ mods,
-                                                         const uint64_t* __restrict__ tab) {
-  const size_t n = (size_t)1 << logn;
-  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y, k = blockIdx.z;
-  const uint64_t v = rescale_elem(in[k * ips + i * n + j], R[((size_t)k * nl + i) * n + j], tab[i], tab[nl + i],
-                                  mods[i].q);
-  out[k * ops + i * n + j] = v;
-}
-
 // per-limb scalar constants (Shoup pairs) for constant-polynomial plaintexts
 struct Scalars {
   uint64_t w[64];
@@ -190,18 +168,8 @@ int he_rescale(he_ctx* h, const he_ct* in, he_ct* out, he_stream st) {
   Lane* lane = lane_for(c, s);
   if (!lane) return HE_ENOMEM;
   WS w = ws_layout(c, lane->ws);
-  uint64_t* T = w.y;   // [2][N] top limbs -> coefficient form
-  uint64_t* R = w.rs;  // [2][t][N]
-  for (int k = 0; k < 2; k++)
-    HE_HIP(hipMemcpyAsync(T + k * N, in->data + (k * (size_t)in->cap + t) * N, N * 8, hipMemcpyDeviceToDevice, s));
-  if ((rc = ntt_launch(c, T, N, 2, range_map(0, 1, t), true, s))) return rc;
-  k_bcast_reduce<<<grid_for(c, t, 2), 256, 0, s>>>(T, R, t, c->log_n, c->d_mod);
-  HE_HIP(hipGetLastError());
-  if ((rc = ntt_launch(c, R, (size_t)t * N, 2, range_map(0, t, 0), false, s))) return rc;
-  ProfScope ps(c, "rescale_combine", s, 8.0 * N * t * 6, 2.0 * N * t);
-  k_rescale_combine<<<grid_for(c, t, 2), 256, 0, s>>>(in->data, in->cap * N, R, out->data, out->cap * N, t, c->log_n,
-                                                      c->d_mod, c->d_rescale[l]);
-  HE_HIP(hipGetLastError());
+  // T = w.y: [2][N] top limbs in coefficient form; w.rs: [2][t][N] converted
+  if ((rc = rescale_launch(c, in->data, in->cap * N, out->data, out->cap * N, 2, l, w.y, w.rs, s))) return rc;
   out->level = t;
   out->scale = in->scale / (double)c->mod[t];
   return HE_OK;

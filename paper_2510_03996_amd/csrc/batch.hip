@@ -145,16 +145,29 @@ __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ 
       for (int u = 0; u < OG; u++)
 #pragma unroll
         for (int z = 0; z < PS; z++) a[u][z] = 0.0;
-      for (int t = 0; t < nr; t++) {
+      // term t's rotated residues and plaintext residues are loaded while
+      // term t - 1 is being accumulated (register double buffering), so the
+      // HBM and L2 latencies overlap the FP64 work
+      uint64_t xr[PS], pr[OG];
+      auto load = [&](int t, uint64_t* xv, uint64_t* pv) {
         const uint64_t* rc = rot_all + (size_t)rot_idx[r0 + t] * 2 * ln + zoff;
+#pragma unroll
+        for (int z = 0; z < PS; z++) xv[z] = rc[z * ln];
+        const int32_t* pt = pix + og * nr + t;
+#pragma unroll
+        for (int u = 0; u < OG; u++) pv[u] = u < cnt ? poolk[(size_t)pt[u * nr] * ln] : 0;
+      };
+      load(0, xr, pr);
+      for (int t = 0; t < nr; t++) {
+        uint64_t xn[PS], pn[OG];
+        if (t + 1 < nr) load(t + 1, xn, pn);
         double x[PS];
 #pragma unroll
-        for (int z = 0; z < PS; z++) x[z] = centre_f64(u52_to_f64(rc[z * ln]), dqi, dq);
-        const int32_t* pt = pix + og * nr + t;
+        for (int z = 0; z < PS; z++) x[z] = centre_f64(u52_to_f64(xr[z]), dqi, dq);
 #pragma unroll
         for (int u = 0; u < OG; u++) {
           if (u < cnt) {
-            const double p = bits_to_f64(poolk[(size_t)pt[u * nr] * ln]);
+            const double p = bits_to_f64(pr[u]);
             const double pq = p * dqi;
 #pragma unroll
             for (int z = 0; z < PS; z++) {
@@ -162,6 +175,12 @@ __global__ __launch_bounds__(256) void k_mac_multi(const uint64_t* __restrict__ 
               if ((t & 7) == 7) a[u][z] = centre_f64(a[u][z], dqi, dq);
             }
           }
+        }
+        if (t + 1 < nr) {
+#pragma unroll
+          for (int z = 0; z < PS; z++) xr[z] = xn[z];
+#pragma unroll
+          for (int u = 0; u < OG; u++) pr[u] = pn[u];
         }
       }
 #pragma unroll

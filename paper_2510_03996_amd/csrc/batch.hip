@@ -35,22 +35,41 @@ constexpr int BATCH_NMAX = 64;  // rotations per ciphertext in one batch
 
 // ---------------------------------------------------------------- kernels
 // Inner product of one key with the extended digits of every pair using it.
-// grid: x = coefficient tile, y = extended limb.  Pair p uses input item[p].
+// grid: x = 256-coefficient tile, y = extended limb.  Pair p uses input
+// item[p].  phi_g maps an aligned block of 256 NTT indices onto an aligned
+// block (the bit reversal puts the block's varying low bits on top, where
+// g (2 brv(j) + 1) mod 2N leaves the low bits alone), so each digit's source
+// block is read coalesced into LDS and permuted there instead of gathered
+// from HBM.  The next pair's blocks are loaded while the current pair is
+// accumulated (two LDS buffers, one barrier per pair).  Primes below 2^50:
+// centred FP64 products of the canonical digit values with the
+// Montgomery-form key words (each below 1.6q, the sum over at most four
+// digits below 6.4q) and one product by 2^-64 mod q; the others: 128-bit
+// products and one REDC.  Both give the canonical residue.
+template <int DN>
 __global__ __launch_bounds__(256) void k_ip_multi(const uint64_t* __restrict__ ext_all, size_t ext_item,
                                                   const uint64_t* __restrict__ in_all, size_t in_item, int level,
-                                                  int K, int alpha, int dnum, const uint64_t* __restrict__ key,
+                                                  int K, int alpha, const uint64_t* __restrict__ key,
                                                   size_t key_digit_stride, size_t key_poly_stride, int L, uint32_t g,
                                                   int logn, const ModInfo* __restrict__ mods,
                                                   const int32_t* __restrict__ items, int npairs,
                                                   uint64_t* __restrict__ u_all) {
+  constexpr int dnum = DN;
+  __shared__ uint64_t sh[2][DN][256];
   const size_t n = (size_t)1 << logn;
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  const int tid = threadIdx.x;
+  const uint32_t k = blockIdx.x * 256 + tid;
   const int pos = blockIdx.y;
   const int E = level + K;
   const int mod = pos < level ? pos : L + (pos - level);
   const ModInfo mi = mods[mod];
   const uint32_t src = g == 1 ? k : automorph_src(k, g, logn);
-  uint64_t kb[MAX_DIGITS], ka[MAX_DIGITS];
+  const uint32_t s0 = src & ~255u;  // the source block, the same for the whole workgroup
+  const int sl = (int)(src & 255u);
+  const bool f64 = mi.k <= 50;
+  const double dq = (double)mi.q, qi = mi.dqinv;
+  uint64_t kb[DN], ka[DN];
+#pragma unroll
   for (int j = 0; j < dnum; j++) {
     const uint64_t* kj = key + j * key_digit_stride + (size_t)mod * n + k;
     kb[j] = kj[0];
@@ -58,21 +77,65 @@ __global__ __launch_bounds__(256) void k_ip_multi(const uint64_t* __restrict__ e
   }
   const int own = pos < level ? pos / alpha : -1;
   const size_t En = (size_t)E * n;
-  for (int p = 0; p < npairs; p++) {
+  uint64_t cur[DN];
+  auto gload = [&](int p) {
     const int it = items[p];
     const uint64_t* c1 = in_all + it * in_item + (size_t)level * n;
     const uint64_t* ext = ext_all + it * ext_item;
-    U128 a0{0, 0}, a1{0, 0};
+#pragma unroll
     for (int j = 0; j < dnum; j++) {
       const uint64_t* sp = j == own ? c1 : ext + j * En;
-      const uint64_t e = sp[(size_t)pos * n + src];
-      add_wide(a0, mul_wide(e, kb[j]));
-      add_wide(a1, mul_wide(e, ka[j]));
+      cur[j] = sp[(size_t)pos * n + s0 + tid];
     }
+  };
+  if (npairs > 0) gload(0);
+  for (int p = 0; p < npairs; p++) {
+    const int b = p & 1;
+#pragma unroll
+    for (int j = 0; j < dnum; j++) sh[b][j][tid] = cur[j];
+    __syncthreads();
+    if (p + 1 < npairs) gload(p + 1);
     uint64_t* u = u_all + (size_t)p * 2 * En + (size_t)pos * n + k;
-    u[0] = mont_redc(a0, mi.q, mi.qinv);
-    u[En] = mont_redc(a1, mi.q, mi.qinv);
+    if (f64) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < dnum; j++) {
+        const double v = u52_to_f64(sh[b][j][sl]);
+        const double w0 = u52_to_f64(kb[j]), w1 = u52_to_f64(ka[j]);
+        a0 += mul_f64_c(v, w0, w0 * qi, dq);
+        a1 += mul_f64_c(v, w1, w1 * qi, dq);
+      }
+      u[0] = f64_to_u52(canon_f64(mul_f64_c(a0, mi.drinv, mi.drinvq, dq), qi, dq));
+      u[En] = f64_to_u52(canon_f64(mul_f64_c(a1, mi.drinv, mi.drinvq, dq), qi, dq));
+    } else {
+      U128 a0{0, 0}, a1{0, 0};
+#pragma unroll
+      for (int j = 0; j < dnum; j++) {
+        const uint64_t e = sh[b][j][sl];
+        add_wide(a0, mul_wide(e, kb[j]));
+        add_wide(a1, mul_wide(e, ka[j]));
+      }
+      u[0] = mont_redc(a0, mi.q, mi.qinv);
+      u[En] = mont_redc(a1, mi.q, mi.qinv);
+    }
   }
+}
+
+static int ip_multi_launch(int dn, dim3 grid, hipStream_t s, const uint64_t* ext, size_t ext_item, const uint64_t* in,
+                           size_t in_item, int l, int K, int alpha, const uint64_t* key, size_t kds, size_t kps, int L,
+                           uint32_t g, int logn, const ModInfo* mods, const int32_t* items, int npairs, uint64_t* u) {
+  switch (dn) {
+#define HE_IPM(D) \
+  case D:         \
+    k_ip_multi<D><<<grid, 256, 0, s>>>(ext, ext_item, in, in_item, l, K, alpha, key, kds, kps, L, g, logn, mods, items, \
+                                       npairs, u);                                                                    \
+    break;
+    HE_IPM(1) HE_IPM(2) HE_IPM(3) HE_IPM(4) HE_IPM(5) HE_IPM(6) HE_IPM(7) HE_IPM(8)
+#undef HE_IPM
+    default:
+      return set_error(HE_EINVAL, "too many key-switching digits");
+  }
+  return HE_OK;
 }
 
 // The plaintext pool as the MAC consumes it, once per run: limbs below 2^50
@@ -356,8 +419,9 @@ static int run_batched(Batch* b, hipStream_t s) {
     {
       ProfScope ps(c, "ks_inner_product_multi", s, 8.0 * N * E * (2.0 * dn + gk.npairs * (dn + 2.0)),
                    2.0 * dn * E * N * gk.npairs);
-      k_ip_multi<<<dim3(N / 256, E), 256, 0, s>>>(b->ext, ext_item, b->in, in_item, l, K, c->alpha, dn, gk.key, 2 * kps,
-                                                  kps, L, gk.g, c->log_n, c->d_mod, gk.d_items, gk.npairs, b->u);
+      if ((rc = ip_multi_launch(dn, dim3(N / 256, E), s, b->ext, ext_item, b->in, in_item, l, K, c->alpha, gk.key,
+                                2 * kps, kps, L, gk.g, c->log_n, c->d_mod, gk.d_items, gk.npairs, b->u)))
+        return rc;
       HE_HIP(hipGetLastError());
     }
     const int z = 2 * gk.npairs;

@@ -458,6 +458,8 @@ uint64_t* lane_ct_get(Ctx* c, Lane* ln) {
 
 static void lane_free(Ctx* c, hipStream_t s, Lane* ln) {
   for (uint64_t* p : ln->ct_all) hipFree(p);
+  if (ln->set_ws) hipFree(ln->set_ws);
+  if (ln->set_tab) hipFree(ln->set_tab);
   if (s != nullptr && ln->ws) hipFree(ln->ws);
   delete ln;
 }

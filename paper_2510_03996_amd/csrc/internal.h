@@ -65,10 +65,26 @@ struct KeyEntry {
 // temporary ciphertext buffers used by work enqueued on one stream.  Work on
 // different streams never shares scratch memory, so requests issued on
 // different streams may overlap on the device.
+// Per-launch tables of the batched hoisted key switch (he_rotate_hoisted with
+// several key switches): the key and Galois element of each rotation and the
+// two output polynomials of each.  Written on the lane's stream by a one-thread
+// kernel before the launches that read it (stream order keeps it stable).
+constexpr int SET_MAX = 8;
+constexpr int HOIST_SET_MIN = 3;  // key switches from which a hoisted set is batched
+struct SetTab {
+  const uint64_t* key[SET_MAX];
+  uint32_t g[SET_MAX];
+  uint64_t* out[2 * SET_MAX];
+};
+
 struct Lane {
   uint64_t* ws = nullptr;
   std::vector<uint64_t*> ct_pool;  // free [2][L][N] buffers
   std::vector<uint64_t*> ct_all;   // every buffer this lane allocated
+  // batched hoisted key switch: SET_MAX x ([2][L+K][N] u + [2][L][N] y) and
+  // its table, allocated on first use
+  uint64_t* set_ws = nullptr;
+  SetTab* set_tab = nullptr;
 };
 
 struct Ctx {
@@ -205,6 +221,10 @@ struct NttEpi {
   // inverse pass 1 only: per-modulus finishing constants [4] (conv_fin_fill)
   // replacing N^{-1}, so that the transform writes a conversion's inputs
   const uint64_t* fin;
+  // batched hoisted set (with out_base set to any non-null value): output of
+  // batch z at tab->out[z], pair z/2 gathered through tab->g[z/2]; add_base
+  // (items null) is the one input's c0
+  const SetTab* tab;
 };
 // the last forward NTT with the ModDown epilogue, over nbatch arrays of y
 // (passes = 2: y already holds forward pass 1, as the conversion writes it)
@@ -312,6 +332,7 @@ bool key_known(const Ctx* c, int32_t id);
 const uint64_t* key_acquire(Ctx* c, int32_t id, hipStream_t s);
 void key_note_use(Ctx* c, int32_t id, hipStream_t s);
 int key_lock(Ctx* c, int32_t id, int delta);
+bool key_resident_only(const Ctx* c, int32_t id);  // uploaded, never evicted
 void keys_free_all(Ctx* c);
 // lane of a stream (created on first use; throws nothing, returns null on allocation failure)
 Lane* lane_for(Ctx* c, hipStream_t s);

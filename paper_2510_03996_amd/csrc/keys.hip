@@ -126,6 +126,11 @@ void key_note_use(Ctx* c, int32_t id, hipStream_t s) {
   e.uses.emplace_back(s, ev);
 }
 
+bool key_resident_only(const Ctx* c, int32_t id) {
+  auto it = c->keys.find(norm_key_id(c, id));
+  return it != c->keys.end() && it->second.dev && !it->second.host;
+}
+
 int key_lock(Ctx* c, int32_t id, int delta) {
   auto it = c->keys.find(norm_key_id(c, id));
   if (it == c->keys.end()) return HE_ENOKEY;

@@ -28,6 +28,74 @@ __global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, si
           mod, n, k, src, mods[mod], u, u, u_poly_stride);
 }
 
+// Inner products of one input's extended digits with several keys (a
+// hoisted set): grid x = 256-coefficient tile, y = extended limb, z =
+// rotation of the set (key tab->key[z], Galois element tab->g[z]); output
+// u_z = u + z 2 (level+K) N, [2][level+K][N].  phi_g maps an aligned block
+// of 256 NTT indices onto an aligned block, so each digit's source block is
+// read coalesced and permuted in LDS.  Primes below 2^50: centred FP64
+// products with the Montgomery-form key words and one product by 2^-64 mod
+// q; the others: 128-bit products and one REDC (the same canonical residue).
+template <int DN>
+__global__ __launch_bounds__(256) void k_ip_set(const uint64_t* __restrict__ ext, const uint64_t* __restrict__ c1,
+                                                int level, int K, int alpha, const SetTab* __restrict__ tab,
+                                                size_t key_digit_stride, size_t key_poly_stride, int L, int logn,
+                                                const ModInfo* __restrict__ mods, uint64_t* __restrict__ u_all) {
+  __shared__ uint64_t sh[DN][256];
+  const size_t n = (size_t)1 << logn;
+  const int tid = threadIdx.x;
+  const uint32_t k = blockIdx.x * 256 + tid;
+  const int pos = blockIdx.y, z = blockIdx.z;
+  const int E = level + K;
+  const size_t En = (size_t)E * n;
+  const int mod = pos < level ? pos : L + (pos - level);
+  const ModInfo mi = mods[mod];
+  const uint64_t* key = tab->key[z];
+  const uint32_t g = tab->g[z];
+  const uint32_t src = g == 1 ? k : automorph_src(k, g, logn);
+  const uint32_t s0 = src & ~255u;
+  const int sl = (int)(src & 255u);
+  const int own = pos < level ? pos / alpha : -1;
+  uint64_t kb[DN], ka[DN];
+#pragma unroll
+  for (int j = 0; j < DN; j++) {
+    const uint64_t* sp = j == own ? c1 : ext + j * En;
+    sh[j][tid] = sp[(size_t)pos * n + s0 + tid];
+    const uint64_t* kj = key + j * key_digit_stride + (size_t)mod * n + k;
+    kb[j] = kj[0];
+    ka[j] = kj[key_poly_stride];
+  }
+  __syncthreads();
+  uint64_t* u = u_all + (size_t)z * 2 * En + (size_t)pos * n + k;
+  if (mi.k <= 50) {
+    const double dq = (double)mi.q, qi = mi.dqinv;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int j = 0; j < DN; j++) {
+      const double v = u52_to_f64(sh[j][sl]);
+      const double w0 = u52_to_f64(kb[j]), w1 = u52_to_f64(ka[j]);
+      a0 += mul_f64_c(v, w0, w0 * qi, dq);
+      a1 += mul_f64_c(v, w1, w1 * qi, dq);
+    }
+    u[0] = f64_to_u52(canon_f64(mul_f64_c(a0, mi.drinv, mi.drinvq, dq), qi, dq));
+    u[En] = f64_to_u52(canon_f64(mul_f64_c(a1, mi.drinv, mi.drinvq, dq), qi, dq));
+  } else {
+    U128 a0{0, 0}, a1{0, 0};
+#pragma unroll
+    for (int j = 0; j < DN; j++) {
+      const uint64_t e = sh[j][sl];
+      add_wide(a0, mul_wide(e, kb[j]));
+      add_wide(a1, mul_wide(e, ka[j]));
+    }
+    u[0] = mont_redc(a0, mi.q, mi.qinv);
+    u[En] = mont_redc(a1, mi.q, mi.qinv);
+  }
+}
+
+__global__ void k_set_tab(SetTab t, SetTab* dst) {
+  if (threadIdx.x == 0) *dst = t;
+}
+
 // x -> x 2^64 mod q on every limb of a [dnum][2][L+K][N] key
 __global__ __launch_bounds__(256) void k_to_mont(uint64_t* key, int M, int logn, const ModInfo* __restrict__ mods) {
   const size_t n = (size_t)1 << logn;
@@ -130,6 +198,76 @@ int ks_apply(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t*
   return ks_moddown(c, w, level, g, add0, add1, out0, out1, s);
 }
 
+// The key switches of a hoisted set whose extended digits are in w.ext: up
+// to SET_MAX rotations per round of one inner-product launch and one batched
+// ModDown (inverse transform of the special limbs, conversion fused with the
+// forward column pass, forward row pass writing c0 through phi_g plus
+// (u - y) P^{-1} to each rotation's outputs).  keys[i], g[i], outs[2 i],
+// outs[2 i + 1] per rotation; the keys must stay resident for the rounds.
+static int ks_set(Ctx* c, Lane* lane, const WS& w, const uint64_t* c0, const uint64_t* c1, int level,
+                  const std::vector<const uint64_t*>& keys, const std::vector<uint32_t>& gs,
+                  const std::vector<uint64_t*>& outs, hipStream_t s) {
+  const size_t N = c->n;
+  const int K = c->K, L = c->L, dn = c->dnum(level);
+  const size_t E = (size_t)(level + K), Etop = (size_t)(L + K);
+  const size_t kps = (size_t)(L + K) * N;
+  if (!lane->set_ws) {
+    void* v = nullptr;
+    if (hipMalloc(&v, (size_t)SET_MAX * 2 * (Etop + L) * N * 8) != hipSuccess)
+      return set_error(HE_ENOMEM, "hoisted-set workspace allocation failed");
+    lane->set_ws = (uint64_t*)v;
+    if (hipMalloc(&v, sizeof(SetTab)) != hipSuccess) return set_error(HE_ENOMEM, "hoisted-set table allocation failed");
+    lane->set_tab = (SetTab*)v;
+  }
+  uint64_t* U = lane->set_ws;                               // [SET_MAX][2][E][N]
+  uint64_t* Y = lane->set_ws + (size_t)SET_MAX * 2 * Etop * N;  // [SET_MAX][2][level][N]
+  int rc;
+  for (size_t r0 = 0; r0 < keys.size(); r0 += SET_MAX) {
+    const int nc = (int)std::min<size_t>(SET_MAX, keys.size() - r0);
+    SetTab t{};
+    for (int i = 0; i < nc; i++) {
+      t.key[i] = keys[r0 + i];
+      t.g[i] = gs[r0 + i];
+      t.out[2 * i] = outs[2 * (r0 + i)];
+      t.out[2 * i + 1] = outs[2 * (r0 + i) + 1];
+    }
+    k_set_tab<<<1, 64, 0, s>>>(t, lane->set_tab);
+    HE_HIP(hipGetLastError());
+    {
+      ProfScope ps(c, "ks_inner_product_set", s, 8.0 * N * E * nc * (3.0 * dn + 2), 2.0 * dn * E * N * nc);
+      const dim3 grid(N / 256, E, nc);
+      switch (dn) {
+#define HE_IPS(D)                                                                                                  \
+  case D:                                                                                                          \
+    k_ip_set<D><<<grid, 256, 0, s>>>(w.ext, c1, level, K, c->alpha, lane->set_tab, 2 * kps, kps, L, c->log_n,      \
+                                     c->d_mod, U);                                                                 \
+    break;
+        HE_IPS(1) HE_IPS(2) HE_IPS(3) HE_IPS(4) HE_IPS(5) HE_IPS(6) HE_IPS(7) HE_IPS(8)
+#undef HE_IPS
+        default:
+          return set_error(HE_EINVAL, "too many key-switching digits");
+      }
+      HE_HIP(hipGetLastError());
+    }
+    const int z = 2 * nc;
+    if ((rc = ntt_launch_conv_in(c, U, E * N, U, E * N, z, range_map(level, K, L), c->d_fin[level], 3, s))) return rc;
+    if ((rc = conv_fwd1_launch(c, c->moddown[level], U, E * N, Y, (size_t)level * N, z, 1, c->conv_target[1],
+                               "conv_fwd1_moddown", s)))
+      return rc;
+    NttEpi epi{};
+    epi.u = U;
+    epi.u_bs = E * N;
+    epi.pinv = c->d_pinv[level];
+    epi.level = level;
+    epi.g = 1;
+    epi.add_base = c0;
+    epi.out_base = outs[0];  // batched mode; the outputs come from the table
+    epi.tab = lane->set_tab;
+    if ((rc = ntt_launch_moddown(c, Y, (size_t)level * N, range_map(0, level, 0), epi, s, z, 2))) return rc;
+  }
+  return HE_OK;
+}
+
 int ks_single(Ctx* c, const WS& w, const uint64_t* c1, int level, const uint64_t* key, uint32_t g,
               const uint64_t* add0, const uint64_t* add1, uint64_t* out0, uint64_t* out1, hipStream_t s) {
   const size_t N = c->n;
@@ -199,6 +337,36 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
   // one key switch: the inner product is fused into ModUp's last NTT pass;
   // several: one ModUp shared by all of them (hoisting)
   if (nks > 1 && (rc = ks_modup(c, w, c1, l, s))) return rc;
+  // several key switches with resident keys: batched, SET_MAX rotations per
+  // inner-product launch and per ModDown launch chain, on the caller's stream
+  bool batched = nks >= HOIST_SET_MIN;
+  for (int t = 0; t < n && batched; t++)
+    if (norm_key_id(c, r[t]) != 0 && !key_resident_only(c, r[t])) batched = false;
+  if (batched) {
+    std::vector<const uint64_t*> keys;
+    std::vector<uint32_t> gs;
+    std::vector<uint64_t*> os;
+    for (int t = 0; t < n; t++) {
+      he_ct& o = outs[t];
+      uint64_t* o0 = o.data;
+      uint64_t* o1 = o.data + (size_t)o.cap * N;
+      if (norm_key_id(c, r[t]) == 0) {
+        if (hipMemcpyAsync(o0, c0, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+            hipMemcpyAsync(o1, c1, (size_t)l * N * 8, hipMemcpyDeviceToDevice, s) != hipSuccess)
+          return set_error(HE_EHIP, "copy of an identity rotation failed");
+      } else {
+        const uint64_t* key = key_acquire(c, r[t], s);
+        if (!key) return HE_ENOMEM;
+        keys.push_back(key);
+        gs.push_back(galois_elt(c, r[t]));
+        os.push_back(o0);
+        os.push_back(o1);
+      }
+      o.level = l;
+      o.scale = in->scale;
+    }
+    return ks_set(c, lane, w, c0, c1, l, keys, gs, os, s);
+  }
   // several: key switch j (inner product + ModDown) on the caller's stream or
   // on helper stream j mod K of it, each helper with its own lane's
   // workspace and the caller's extended digits; the helpers start after the

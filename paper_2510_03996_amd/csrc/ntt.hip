@@ -46,11 +46,13 @@ __device__ __forceinline__ void ntt_store(uint64_t* a, int k, uint64_t v, const 
     const size_t off = (size_t)i << LOGN;
     const bool batched = epi.out_base != nullptr;
     const bool gather = batched ? (z & 1) == 0 : z == 0;  // the polynomial c0 is added to
-    const uint64_t* add = batched ? (gather && epi.add_base ? epi.add_base + epi.items[z >> 1] * epi.add_item : nullptr)
-                                  : epi.add[z];
-    uint64_t* out = batched ? epi.out_base + z * epi.out_bs : epi.out[z];
+    const uint64_t* add =
+        batched ? (gather && epi.add_base ? epi.add_base + (epi.items ? epi.items[z >> 1] * epi.add_item : 0) : nullptr)
+                : epi.add[z];
+    uint64_t* out = epi.tab ? epi.tab->out[z] : batched ? epi.out_base + z * epi.out_bs : epi.out[z];
+    const uint32_t g = epi.tab ? epi.tab->g[z >> 1] : epi.g;
     uint64_t x = 0;
-    if (add) x = add[off + (gather && epi.g != 1 ? automorph_src(k, epi.g, LOGN) : (uint32_t)k)];
+    if (add) x = add[off + (gather && g != 1 ? automorph_src(k, g, LOGN) : (uint32_t)k)];
     out[off + k] = moddown_elem(epi.u[z * epi.u_bs + off + k], v, x, epi.pinv[i], epi.pinv[epi.level + i], q);
   }
 }
@@ -108,18 +110,20 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
       const double pwq = bits_to_f64(epi.pinv[3 * epi.level + pos]);
       const bool batched = epi.out_base != nullptr;
       const bool gather = batched ? (bz & 1) == 0 : bz == 0;  // the polynomial c0 is added to
-      const uint64_t* add = batched ? (gather && epi.add_base ? epi.add_base + epi.items[bz >> 1] * epi.add_item
-                                                              : nullptr)
-                                    : epi.add[bz];
+      const uint64_t* add =
+          batched ? (gather && epi.add_base ? epi.add_base + (epi.items ? epi.items[bz >> 1] * epi.add_item : 0)
+                                            : nullptr)
+                  : epi.add[bz];
       const uint64_t* u = epi.u + bz * epi.u_bs + off;
-      uint64_t* o = (batched ? epi.out_base + bz * epi.out_bs : epi.out[bz]) + off;
+      uint64_t* o = (epi.tab ? epi.tab->out[bz] : batched ? epi.out_base + bz * epi.out_bs : epi.out[bz]) + off;
+      const uint32_t gal = epi.tab ? epi.tab->g[bz >> 1] : epi.g;  // (g is the tile loop's index below)
       for (int e = tid; e < P::TILE; e += P::THREADS) {
         int g, k;
         P::tile_elem(e, g, k);
         const int kk = P::gidx(wg, g, k);
         const double r = mul_f64_c(u52_to_f64(u[kk]) - dl[P::lidx(g, k)], pw, pwq, dq);
         double x = 0.0;
-        if (add) x = u52_to_f64(add[off + (gather && epi.g != 1 ? automorph_src(kk, epi.g, LOGN) : (uint32_t)kk)]);
+        if (add) x = u52_to_f64(add[off + (gather && gal != 1 ? automorph_src(kk, gal, LOGN) : (uint32_t)kk)]);
         o[kk] = f64_to_u52(canon_f64(r + x, dqinv, dq));
       }
     } else {

@@ -365,7 +365,30 @@ int he_rotate_hoisted(he_ctx* h, const he_ct* in, const int32_t* r, int n, he_ct
       o.level = l;
       o.scale = in->scale;
     }
-    return ks_set(c, lane, w, c0, c1, l, keys, gs, os, s);
+    // rounds of SET_MAX key switches alternate over the caller's stream and
+    // helper streams (each with its own lane), which start after the ModUp
+    const int rounds = (int)((keys.size() + SET_MAX - 1) / SET_MAX);
+    const int K = std::max(1, std::min(std::min(c->streams_for_ring(), 8), rounds));
+    hipStream_t hs[8] = {s};
+    Lane* lk[8] = {lane};
+    if (K > 1) {
+      if ((rc = aux_streams_for(c, s, K - 1, hs + 1))) return rc;
+      for (int k = 1; k < K; k++)
+        if (!(lk[k] = lane_for(c, hs[k]))) return HE_ENOMEM;
+      if ((rc = stream_fork(s, hs + 1, K - 1))) return rc;
+    }
+    for (int i = 0; i < rounds && rc == HE_OK; i++) {
+      const size_t a = (size_t)i * SET_MAX, b = std::min(keys.size(), a + SET_MAX);
+      std::vector<const uint64_t*> kr(keys.begin() + a, keys.begin() + b);
+      std::vector<uint32_t> gr(gs.begin() + a, gs.begin() + b);
+      std::vector<uint64_t*> orr(os.begin() + 2 * a, os.begin() + 2 * b);
+      rc = ks_set(c, lk[i % K], w, c0, c1, l, kr, gr, orr, hs[i % K]);
+    }
+    if (K > 1) {
+      const int jr = stream_join(s, hs + 1, K - 1);  // also on an error path: the helpers read the workspace
+      if (rc == HE_OK) rc = jr;
+    }
+    return rc;
   }
   // several: key switch j (inner product + ModDown) on the caller's stream or
   // on helper stream j mod K of it, each helper with its own lane's

@@ -29,66 +29,89 @@ __global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, si
 }
 
 // Inner products of one input's extended digits with several keys (a
-// hoisted set): grid x = 256-coefficient tile, y = extended limb, z =
-// rotation of the set (key tab->key[z], Galois element tab->g[z]); output
-// u_z = u + z 2 (level+K) N, [2][level+K][N].  phi_g maps an aligned block
-// of 256 NTT indices onto an aligned block, so each digit's source block is
-// read coalesced and permuted in LDS.  Primes below 2^50: centred FP64
-// products with the Montgomery-form key words and one product by 2^-64 mod
-// q; the others: 128-bit products and one REDC (the same canonical residue).
+// hoisted set): grid x = 256-coefficient tile, y = extended limb; the
+// workgroup loops over the nz rotations of the round (key tab->key[z],
+// Galois element tab->g[z]), writing u_z = u + z 2 (level+K) N,
+// [2][level+K][N].  phi_g maps an aligned block of 256 NTT indices onto an
+// aligned block, so each digit's source block is read coalesced and permuted
+// in LDS; the next rotation's blocks and key words are loaded while the
+// current one is accumulated (two LDS buffers, one barrier per rotation).
+// Primes below 2^50: centred FP64 products with the Montgomery-form key
+// words and one product by 2^-64 mod q; the others: 128-bit products and one
+// REDC (the same canonical residue).
 template <int DN>
 __global__ __launch_bounds__(256) void k_ip_set(const uint64_t* __restrict__ ext, const uint64_t* __restrict__ c1,
-                                                int level, int K, int alpha, const SetTab* __restrict__ tab,
+                                                int level, int K, int alpha, const SetTab* __restrict__ tab, int nz,
                                                 size_t key_digit_stride, size_t key_poly_stride, int L, int logn,
                                                 const ModInfo* __restrict__ mods, uint64_t* __restrict__ u_all) {
-  __shared__ uint64_t sh[DN][256];
+  __shared__ uint64_t sh[2][DN][256];
   const size_t n = (size_t)1 << logn;
   const int tid = threadIdx.x;
   const uint32_t k = blockIdx.x * 256 + tid;
-  const int pos = blockIdx.y, z = blockIdx.z;
+  const int pos = blockIdx.y;
   const int E = level + K;
   const size_t En = (size_t)E * n;
   const int mod = pos < level ? pos : L + (pos - level);
   const ModInfo mi = mods[mod];
-  const uint64_t* key = tab->key[z];
-  const uint32_t g = tab->g[z];
-  const uint32_t src = g == 1 ? k : automorph_src(k, g, logn);
-  const uint32_t s0 = src & ~255u;
-  const int sl = (int)(src & 255u);
   const int own = pos < level ? pos / alpha : -1;
-  uint64_t kb[DN], ka[DN];
-#pragma unroll
-  for (int j = 0; j < DN; j++) {
-    const uint64_t* sp = j == own ? c1 : ext + j * En;
-    sh[j][tid] = sp[(size_t)pos * n + s0 + tid];
-    const uint64_t* kj = key + j * key_digit_stride + (size_t)mod * n + k;
-    kb[j] = kj[0];
-    ka[j] = kj[key_poly_stride];
-  }
-  __syncthreads();
-  uint64_t* u = u_all + (size_t)z * 2 * En + (size_t)pos * n + k;
-  if (mi.k <= 50) {
-    const double dq = (double)mi.q, qi = mi.dqinv;
-    double a0 = 0.0, a1 = 0.0;
+  const bool f64 = mi.k <= 50;
+  const double dq = (double)mi.q, qi = mi.dqinv;
+  // loads of rotation z: its digits' source blocks (to LDS later) and key words
+  uint64_t cur[DN], kb[DN], ka[DN], nkb[DN], nka[DN];
+  int sl = 0, nsl = 0;
+  auto gload = [&](int z, uint64_t* e, uint64_t* b, uint64_t* a, int& slot) {
+    const uint32_t g = tab->g[z];
+    const uint32_t src = g == 1 ? k : automorph_src(k, g, logn);
+    const uint32_t s0 = src & ~255u;
+    slot = (int)(src & 255u);
+    const uint64_t* key = tab->key[z];
 #pragma unroll
     for (int j = 0; j < DN; j++) {
-      const double v = u52_to_f64(sh[j][sl]);
-      const double w0 = u52_to_f64(kb[j]), w1 = u52_to_f64(ka[j]);
-      a0 += mul_f64_c(v, w0, w0 * qi, dq);
-      a1 += mul_f64_c(v, w1, w1 * qi, dq);
+      const uint64_t* sp = j == own ? c1 : ext + j * En;
+      e[j] = sp[(size_t)pos * n + s0 + tid];
+      const uint64_t* kj = key + j * key_digit_stride + (size_t)mod * n + k;
+      b[j] = kj[0];
+      a[j] = kj[key_poly_stride];
     }
-    u[0] = f64_to_u52(canon_f64(mul_f64_c(a0, mi.drinv, mi.drinvq, dq), qi, dq));
-    u[En] = f64_to_u52(canon_f64(mul_f64_c(a1, mi.drinv, mi.drinvq, dq), qi, dq));
-  } else {
-    U128 a0{0, 0}, a1{0, 0};
+  };
+  gload(0, cur, kb, ka, sl);
+  for (int z = 0; z < nz; z++) {
+    const int bf = z & 1;
 #pragma unroll
-    for (int j = 0; j < DN; j++) {
-      const uint64_t e = sh[j][sl];
-      add_wide(a0, mul_wide(e, kb[j]));
-      add_wide(a1, mul_wide(e, ka[j]));
+    for (int j = 0; j < DN; j++) sh[bf][j][tid] = cur[j];
+    __syncthreads();
+    if (z + 1 < nz) gload(z + 1, cur, nkb, nka, nsl);
+    uint64_t* u = u_all + (size_t)z * 2 * En + (size_t)pos * n + k;
+    if (f64) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < DN; j++) {
+        const double v = u52_to_f64(sh[bf][j][sl]);
+        const double w0 = u52_to_f64(kb[j]), w1 = u52_to_f64(ka[j]);
+        a0 += mul_f64_c(v, w0, w0 * qi, dq);
+        a1 += mul_f64_c(v, w1, w1 * qi, dq);
+      }
+      u[0] = f64_to_u52(canon_f64(mul_f64_c(a0, mi.drinv, mi.drinvq, dq), qi, dq));
+      u[En] = f64_to_u52(canon_f64(mul_f64_c(a1, mi.drinv, mi.drinvq, dq), qi, dq));
+    } else {
+      U128 a0{0, 0}, a1{0, 0};
+#pragma unroll
+      for (int j = 0; j < DN; j++) {
+        const uint64_t e = sh[bf][j][sl];
+        add_wide(a0, mul_wide(e, kb[j]));
+        add_wide(a1, mul_wide(e, ka[j]));
+      }
+      u[0] = mont_redc(a0, mi.q, mi.qinv);
+      u[En] = mont_redc(a1, mi.q, mi.qinv);
     }
-    u[0] = mont_redc(a0, mi.q, mi.qinv);
-    u[En] = mont_redc(a1, mi.q, mi.qinv);
+    if (z + 1 < nz) {
+#pragma unroll
+      for (int j = 0; j < DN; j++) {
+        kb[j] = nkb[j];
+        ka[j] = nka[j];
+      }
+      sl = nsl;
+    }
   }
 }
 
@@ -235,11 +258,11 @@ static int ks_set(Ctx* c, Lane* lane, const WS& w, const uint64_t* c0, const uin
     HE_HIP(hipGetLastError());
     {
       ProfScope ps(c, "ks_inner_product_set", s, 8.0 * N * E * nc * (3.0 * dn + 2), 2.0 * dn * E * N * nc);
-      const dim3 grid(N / 256, E, nc);
+      const dim3 grid(N / 256, E);
       switch (dn) {
 #define HE_IPS(D)                                                                                                  \
   case D:                                                                                                          \
-    k_ip_set<D><<<grid, 256, 0, s>>>(w.ext, c1, level, K, c->alpha, lane->set_tab, 2 * kps, kps, L, c->log_n,      \
+    k_ip_set<D><<<grid, 256, 0, s>>>(w.ext, c1, level, K, c->alpha, lane->set_tab, nc, 2 * kps, kps, L, c->log_n,  \
                                      c->d_mod, U);                                                                 \
     break;
         HE_IPS(1) HE_IPS(2) HE_IPS(3) HE_IPS(4) HE_IPS(5) HE_IPS(6) HE_IPS(7) HE_IPS(8)

@@ -179,6 +179,32 @@ def test_rotate_hoisted(gctx, name):
     g.layer_streams(2)
 
 
+@pytest.mark.parametrize("level", [24, 13])
+def test_rotate_hoisted_rounds(gctx, level):
+    """A hoisted set of 13 key switches (the 3x3 window's 8 offsets on a
+    32-wide map, four more, and the identity) at N=2^16: two rounds of the
+    batched set path (8 + 5), spread over 1, 2 and 4 streams; at level 13 the
+    last digit is partial (8 + 5 limbs).  Every output equals the oracle's."""
+    name = "config2"
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    rs = [dy * 32 + dx for dy in (-1, 0, 1) for dx in (-1, 0, 1) if (dy, dx) != (0, 0)] + [2, -64, 1024, 4095, 0]
+    ks = [r for r in rs if r != 0]
+    keys = H.oracle_keys(name, ks)
+    for r, k in keys.items():
+        g.key_upload(r, k)
+    _, a = H.encrypt_slots(name, 15, level=level)
+    ga = g.ct_from_numpy(a.data, a.scale)
+    want = octx.rotate_hoisted(a, rs, keys)
+    for n in (1, 2, 4):
+        g.layer_streams(n)
+        got = g.rotate_hoisted(ga, rs)
+        for r, x, y in zip(rs, got, want):
+            H.assert_limbs_equal(x.numpy(), y.data, "hoisted rotation %d at level %d on %d stream(s)" % (r, level, n))
+            assert x.level == level
+    g.layer_streams(2)
+
+
 def test_helper_streams_released_with_the_lane(gctx):
     """A hoisted set on a fresh stream (its key switches over the stream and a
     helper), the stream's lane released (helpers destroyed), the same set

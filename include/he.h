@@ -212,7 +212,11 @@ int he_rotate_noalloc(he_ctx* ctx, const he_ct* in, int32_t r, he_ct* out, he_st
 /* Hoisted rotations ("fast rotations"): one ModUp of c1 shared by n
  * rotations; outs[t] = Rot_{r[t]}(in).  Outputs must not alias the input or
  * each other (HE_EINVAL); their key switches may run on helper streams of
- * `stream` (he_ctx_layer_streams), all finished in stream order of `stream`. */
+ * `stream` (he_ctx_layer_streams), all finished in stream order of `stream`.
+ * Three or more key switches whose keys are all uploaded (not host-
+ * registered) run batched, in rounds of 8: one inner-product launch and one
+ * ModDown chain per round (the same residues as key switch by key switch;
+ * the stream's lane then holds a round's workspace, 8 x 2 (2L+K) N words). */
 int he_rotate_hoisted(he_ctx* ctx, const he_ct* in, const int32_t* r, int n, he_ct* outs, he_stream stream);
 
 /* out (+)= in (.) pt limb-wise at the ciphertext's level (pt-ct product of
@@ -231,7 +235,10 @@ int he_add_plain(he_ctx* ctx, const he_ct* a, const he_pt* pt, he_ct* out, he_st
 
 /* Floor rescale by the top prime q_t (t = level-1):
  * c'_i = (c_i - ([c]_{q_t} mod q_i)) q_t^{-1} mod q_i; scale /= q_t.
- * HE_ELEVEL at level 1.  out may alias in. */
+ * Computed as a ModDown by the single prime q_t (inverse transform of the top
+ * limb, its residues reduced to the other limbs in the forward column pass,
+ * the combination in the forward row pass).  HE_ELEVEL at level 1.  out may
+ * alias in. */
 int he_rescale(he_ctx* ctx, const he_ct* in, he_ct* out, he_stream stream);
 /* Keep limbs q_0..q_{level-1} (level alignment, no scale change). */
 int he_drop_level(he_ctx* ctx, const he_ct* in, int level, he_ct* out, he_stream stream);

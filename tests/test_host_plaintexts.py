@@ -132,3 +132,9 @@ def test_recipe_counts_follow_the_plan_and_errors():
                             stride=1, padding=4)
     with pytest.raises(he.HEError):
         he.layer_plaintexts(he.LAYER_FC, 14, np.zeros((3, 6)), n_in=6, n_out=3)  # n_in not a power of two
+    with pytest.raises(he.HEError):  # no such striding mode
+        he.layer_plaintexts(he.LAYER_AVGPOOL, 14, fm=hfm(2, 8, 8, 1), kernel=2, stride=2, stride_mode=2)
+    # the log-step column steps: ceil(log2 Wo) pairs of masks instead of Wo masks
+    ext = he.layer_plaintexts(he.LAYER_AVGPOOL, 14, fm=hfm(2, 8, 8, 1), kernel=2, stride=2)
+    log = he.layer_plaintexts(he.LAYER_AVGPOOL, 14, fm=hfm(2, 8, 8, 1), kernel=2, stride=2, stride_mode=1)
+    assert ext.shape[0] == 4 + 4 + 2 and log.shape[0] == 2 * 2 + 4 + 2

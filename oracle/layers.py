@@ -349,14 +349,17 @@ def log_steps(Wo):
     return (Wo - 1).bit_length()
 
 
-def compaction_plan(fm, S, Ho, Wo, stride_log=False):
+def compaction_plan(fm, S, Ho, Wo, stride_log=False, multi=None):
     """Steps of the stride-S extraction of outputs (S i, S j), jointly over all
     channels: (i) columns, key S-1 (the paper's first striding approach: one
     masked chain over the Wo columns), or with stride_log (its second
     approach) ceil(log2 Wo) steps t with key (S-1) 2^t, each a two-term
     masked chain keeping the columns whose bit t is 0 and moving those whose
     bit t is 1 left by (S-1) 2^t; (ii) rows, key D = S rs - Wo;
-    (iii) channels, key E = cs - Ho Wo.  Returns [(step, count, key)]."""
+    (iii) channels, key E = cs - Ho Wo, when there are several channels
+    (multi; a one-channel group of the multi-channel pipeline keeps the step
+    as one mask, so that every group ends at the same level).  Returns
+    [(step, count, key)]."""
     steps = []
     if S > 1:
         T = log_steps(Wo)
@@ -368,24 +371,25 @@ def compaction_plan(fm, S, Ho, Wo, stride_log=False):
     if D != 0:
         steps.append(("row", Ho, D))
     E = fm.cs - Ho * Wo
-    if E != 0 and fm.C > 1:
+    if E != 0 and (fm.C > 1 if multi is None else multi):
         steps.append(("chan", fm.C, E))
     return steps
 
 
-def compaction_masks(fm, S, Ho, Wo, col_scale, slots, bsgs=False, stride_log=False):
+def compaction_masks(fm, S, Ho, Wo, col_scale, slots, bsgs=False, stride_log=False, c0=0, multi=None):
     """Masks of each step on the layout that step sees.  Log-step column step
     t: after steps < t, column j of the stride-S row i sits at
     S i rs + S (j - j mod 2^t) + j mod 2^t; mask 0 is 1 there for the j with
     bit t clear (they stay), mask 1 for those with bit t set (they move by
     (S-1) 2^t); step 0 also selects the stride-aligned outputs, and carries
-    the column scale."""
+    the column scale.  c0: the channels are c0 .. c0 + C - 1 of the map (a
+    group of the multi-channel pipeline, see strided)."""
     vecs = []
-    for step, n, key in compaction_plan(fm, S, Ho, Wo, stride_log):
+    for step, n, key in compaction_plan(fm, S, Ho, Wo, stride_log, multi):
         sv = []
         for t in range(n):
             m = np.zeros(slots)
-            for c in range(fm.C):
+            for c in range(c0, c0 + fm.C):
                 if step.startswith("logcol"):
                     lt = int(step[6:])
                     for i in range(Ho):
@@ -400,29 +404,81 @@ def compaction_masks(fm, S, Ho, Wo, col_scale, slots, bsgs=False, stride_log=Fal
                 elif step == "row":
                     base = c * fm.cs + S * t * fm.rs
                     m[base:base + Wo] = 1.0
-                elif step == "chan" and c == t:
+                elif step == "chan" and c == c0 + t:
                     m[c * fm.cs:c * fm.cs + Ho * Wo] = 1.0
             sv.append(m)
         vecs += chain_masks(sv, key, bsgs)
     return vecs
 
 
-def compaction_keys(fm, S, Ho, Wo, bsgs=False, stride_log=False):
+def compaction_keys(fm, S, Ho, Wo, bsgs=False, stride_log=False, multi=None):
     keys = set()
-    for _, n, key in compaction_plan(fm, S, Ho, Wo, stride_log):
+    for _, n, key in compaction_plan(fm, S, Ho, Wo, stride_log, multi):
         keys |= masked_chain_keys(n, key, bsgs)
     return keys
 
 
-def compaction(ev, v, fm, S, Ho, Wo, masks, bsgs=False, stride_log=False):
-    """Move output (c, i, j) from c cs + S i rs + S j to c Ho Wo + i Wo + j."""
+def compaction(ev, v, fm, S, Ho, Wo, masks, bsgs=False, stride_log=False, multi=None):
+    """Move output (c, i, j) from c cs + S i rs + S j to c Ho Wo + i Wo + j
+    (channels offset by c0 of a group keep c0 cs as their origin:
+    c0 cs + c Ho Wo + i Wo + j, see strided)."""
     pos = 0
-    for step, n, key in compaction_plan(fm, S, Ho, Wo, stride_log):
+    for step, n, key in compaction_plan(fm, S, Ho, Wo, stride_log, multi):
         ms = masks[pos:pos + n]
         pos += n
         v = masked_chain(ev, v, ms, n, key, bsgs)
     assert pos == len(masks)
     return v, FMap(fm.C, Ho, Wo, Wo, Ho * Wo, 1)
+
+
+def stride_groups(C, g):
+    """The multi-channel striding pipeline's groups [(c0, size)]: g output
+    channels each (the paper sets g to the layer's input channels); g <= 0 or
+    g >= C is one group of all C channels."""
+    if g <= 0 or g >= C:
+        return [(0, C)]
+    return [(c0, min(g, C - c0)) for c0 in range(0, C, g)]
+
+
+def strided_masks(fm, S, Ho, Wo, col_scale, slots, bsgs=False, stride_log=False, group=0):
+    """compaction_masks of every group in turn (the merge takes none)."""
+    out = []
+    for c0, n in stride_groups(fm.C, group):
+        out += compaction_masks(FMap(n, fm.H, fm.W, fm.rs, fm.cs, 1), S, Ho, Wo, col_scale, slots, bsgs, stride_log,
+                                c0, fm.C > 1)
+    return out
+
+
+def strided_keys(fm, S, Ho, Wo, bsgs=False, stride_log=False, group=0):
+    groups = stride_groups(fm.C, group)
+    keys = set()
+    for _, n in groups:
+        keys |= compaction_keys(FMap(n, fm.H, fm.W, fm.rs, fm.cs, 1), S, Ho, Wo, bsgs, stride_log, fm.C > 1)
+    if len(groups) > 1:
+        keys.add(group * (fm.cs - Ho * Wo))
+    return keys
+
+
+def strided(ev, v, fm, S, Ho, Wo, masks, bsgs=False, stride_log=False, group=0):
+    """Stride compaction of all channels (group 0) or, the paper's
+    multi-channel pipeline, of groups of `group` channels each: group c0's
+    compaction leaves its channel c at c0 cs + c Ho Wo, i.e. c0 E = c0 (cs -
+    Ho Wo) to the right of its place, so the groups are merged by a Horner
+    chain with the single key group E: acc = z_last; acc = Rot_{gE}(acc) +
+    z_k (no level)."""
+    groups = stride_groups(fm.C, group)
+    zs, pos = [], 0
+    for c0, n in groups:
+        sub = FMap(n, fm.H, fm.W, fm.rs, fm.cs, 1)
+        cnt = sum(k for _, k, _ in compaction_plan(sub, S, Ho, Wo, stride_log, fm.C > 1))
+        z, _ = compaction(ev, v, sub, S, Ho, Wo, masks[pos:pos + cnt], bsgs, stride_log, fm.C > 1)
+        zs.append(z)
+        pos += cnt
+    assert pos == len(masks)
+    acc = zs[-1]
+    for z in reversed(zs[:-1]):
+        acc = ev.add(ev.rot(acc, group * (fm.cs - Ho * Wo)), z)
+    return acc, FMap(fm.C, Ho, Wo, Wo, Ho * Wo, 1)
 
 
 # ===================================================================== convolution
@@ -561,14 +617,14 @@ def conv_out_map(fm, F, k, stride, padding, slots):
     return FMap(F, Ho, Wo, Wo, Ho * Wo, 1)
 
 
-def conv_plaintexts(fm, K, stride, padding, slots, bsgs=False, stride_log=False):
+def conv_plaintexts(fm, K, stride, padding, slots, bsgs=False, stride_log=False, stride_group=0):
     """Real vectors the convolution multiplies by, in the order the schedule
     (and the GPU library) consumes them: kernel vectors [f][tap], then masks."""
     F, C, k, _ = K.shape
     assert C == fm.C
     kind = conv_kind(k, padding, fm, F)
     if kind == "padded":
-        kern, masks = conv_plaintexts(padded_map(fm, padding), K, stride, 0, slots, bsgs, stride_log)
+        kern, masks = conv_plaintexts(padded_map(fm, padding), K, stride, 0, slots, bsgs, stride_log, stride_group)
         return kern, pad_masks(fm, padding, slots, bsgs) + masks
     kern, masks = [], []
     if kind == "special":
@@ -591,7 +647,8 @@ def conv_plaintexts(fm, K, stride, padding, slots, bsgs=False, stride_log=False)
                 masks.append(m)
         if stride > 1:
             Ho = (W - 1) // stride + 1
-            masks += compaction_masks(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, 1.0, slots, bsgs, stride_log)
+            masks += strided_masks(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, 1.0, slots, bsgs, stride_log,
+                                   stride_group)
     else:
         # tap (i, j) at output (y, x) reads input (y + i - P, x + j - P): the
         # kernel value where that neighbour is inside the image, 0 elsewhere
@@ -615,7 +672,8 @@ def conv_plaintexts(fm, K, stride, padding, slots, bsgs=False, stride_log=False)
             masks.append(m)
         if stride > 1:
             Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
-            masks += compaction_masks(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0, slots, bsgs, stride_log)
+            masks += strided_masks(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, 1.0, slots, bsgs, stride_log,
+                                   stride_group)
     return kern, masks
 
 
@@ -652,12 +710,13 @@ def channel_sum(ev, A, C, step, logstep=False):
     return S
 
 
-def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False, stride_log=False):
+def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False, stride_log=False, stride_group=0):
     """Distinct rotation keys the schedule uses (the paper's per-layer index helper)."""
     kind = conv_kind(k, padding, fm, F)
     if kind == "padded":
         return sorted(pad_keys(fm, padding, bsgs) |
-                      set(conv_rotations(padded_map(fm, padding), F, k, stride, 0, slots, logstep, bsgs, stride_log)))
+                      set(conv_rotations(padded_map(fm, padding), F, k, stride, 0, slots, logstep, bsgs, stride_log,
+                                         stride_group)))
     keys = set()
     if kind == "special":
         W = fm.W
@@ -665,7 +724,7 @@ def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False, 
         keys |= channel_sum_keys(fm.C, W * W, logstep)
         if stride > 1:
             Ho = (W - 1) // stride + 1
-            keys |= compaction_keys(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, bsgs, stride_log)
+            keys |= strided_keys(FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, bsgs, stride_log, stride_group)
     else:
         keys |= {r for r in conv_taps(fm, k, padding) if r != 0}
         keys |= channel_sum_keys(fm.C, fm.cs, logstep)
@@ -674,7 +733,7 @@ def conv_rotations(fm, F, k, stride, padding, slots, logstep=False, bsgs=False, 
         if stride > 1:
             H1, W1 = conv_dims(fm, k, padding)
             Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
-            keys |= compaction_keys(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, bsgs, stride_log)
+            keys |= strided_keys(FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, bsgs, stride_log, stride_group)
     return sorted(keys)
 
 
@@ -692,18 +751,19 @@ def conv_bias_vector(fo, bias, slots):
 
 
 def conv2d(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False, bsgs=False, bias=None,
-           stride_log=False):
+           stride_log=False, stride_group=0):
     """The pinned convolution schedule (_conv2d_schedule), then the bias
     plaintext (conv_bias_vector, encoded at the output's scale and level)
     added when given."""
-    y, fo = _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep, bsgs, stride_log)
+    y, fo = _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep, bsgs, stride_log,
+                             stride_group)
     if bias is not None:
         y = ev.add_plain(y, bias)
     return y, fo
 
 
 def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logstep=False, bsgs=False,
-                     stride_log=False):
+                     stride_log=False, stride_group=0):
     """Pinned convolution schedule.
 
     special (k=3, P=1): r = Algorithm 1 rotations computed as three hoisted
@@ -712,7 +772,8 @@ def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logst
       C > 1 (replicated input): S_f = channel_sum(A_f, C, W^2), chained with
       the single key W^2 (C-1 key switches) or, with logstep and C a power of
       two, by doubling (log2 C key switches); Y = RS(sum_f S_f (.) blockmask_f);
-      stride > 1: joint compaction of all channels.
+      stride > 1: joint compaction of all channels (or, stride_group = g > 0,
+      the paper's multi-channel pipeline: groups of g channels, merged).
     generic (0 <= P <= (k-1)/2): one hoisted group of the nonzero tap offsets
       (i - P) rs + (j - P); kernel vectors zero where a tap's neighbour lies
       in the padding; A_f = RS(sum r (.) kv); C > 1: channel_sum with step cs,
@@ -726,7 +787,8 @@ def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logst
     if kind == "padded":
         npad = len(pad_masks(fm, padding, slots, bsgs))
         xp, fp = pad_layout(ev, x, fm, padding, masks[:npad], bsgs)
-        return _conv2d_schedule(ev, xp, fp, F, k, stride, 0, kern, masks[npad:], slots, logstep, bsgs, stride_log)
+        return _conv2d_schedule(ev, xp, fp, F, k, stride, 0, kern, masks[npad:], slots, logstep, bsgs, stride_log,
+                                stride_group)
     C = fm.C
     if kind == "special":
         W = fm.W
@@ -753,7 +815,7 @@ def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logst
         if stride == 1:
             return y, out1
         Ho = (W - 1) // stride + 1
-        return compaction(ev, y, FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, masks[mpos:], bsgs, stride_log)
+        return strided(ev, y, FMap(F, W, W, W, W * W, 1), stride, Ho, Ho, masks[mpos:], bsgs, stride_log, stride_group)
     # generic
     offs = conv_taps(fm, k, padding)
     rot = iter(ev.rot_hoisted(x, [r for r in offs if r != 0]))
@@ -778,7 +840,8 @@ def _conv2d_schedule(ev, x, fm, F, k, stride, padding, kern, masks, slots, logst
     if stride == 1:
         return y, FMap(F, H1, W1, fm.rs, fm.cs, 1)
     Ho, Wo = (H1 - 1) // stride + 1, (W1 - 1) // stride + 1
-    return compaction(ev, y, FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks[mpos:], bsgs, stride_log)
+    return strided(ev, y, FMap(F, H1, W1, fm.rs, fm.cs, 1), stride, Ho, Wo, masks[mpos:], bsgs, stride_log,
+                   stride_group)
 
 
 # ===================================================================== pooling

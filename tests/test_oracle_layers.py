@@ -272,6 +272,53 @@ def test_log_step_striding_equals_extraction(C, H1, W1, rs, cs, S, bsgs):
         assert len(keys) == T + 1 and {(S - 1) << t for t in range(T)} <= keys
 
 
+@pytest.mark.parametrize("C,g", [(6, 2), (7, 3), (4, 4), (5, 1), (3, 0)])
+@pytest.mark.parametrize("log", [False, True], ids=["extract", "logstride"])
+def test_grouped_striding_equals_joint(C, g, log):
+    """The multi-channel pipeline (groups of g channels, each compacted
+    jointly, merged with the key g E) places every output exactly where the
+    all-channel compaction does, from a ciphertext with every slot nonzero;
+    (G - 1) merge key switches on top of G group compactions."""
+    slots = 4096
+    v = np.random.default_rng(12).uniform(-1, 1, slots)
+    fm = LY.FMap(C, 9, 9, 12, 120)
+    S, Ho, Wo = 2, 5, 5
+    ev1, ev2 = sim(slots), sim(slots)
+    joint, _ = LY.compaction(ev1, LY.SimCt(v, 9), fm, S, Ho, Wo,
+                             LY.compaction_masks(fm, S, Ho, Wo, 1.0, slots, False, log), False, log)
+    grp, fo = LY.strided(ev2, LY.SimCt(v, 9), fm, S, Ho, Wo,
+                         LY.strided_masks(fm, S, Ho, Wo, 1.0, slots, False, log, g), False, log, g)
+    assert fo == LY.FMap(C, Ho, Wo) and np.array_equal(joint.v, grp.v) and grp.level == joint.level
+    groups = LY.stride_groups(C, g)
+    per = lambda n: sum(LY.masked_chain_switches(k, False)
+                        for _, k, _ in LY.compaction_plan(LY.FMap(n, 9, 9, 12, 120), S, Ho, Wo, log, C > 1))
+    assert ev2.ks == sum(per(n) for _, n in groups) + len(groups) - 1
+    keys = LY.strided_keys(fm, S, Ho, Wo, False, log, g)
+    assert (g * (120 - Ho * Wo) in keys) == (len(groups) > 1)
+
+
+def test_conv_b_with_the_paper_grouping():
+    """ResNet conv B (16 -> 32, 3x3, stride 2, pad 1) with groups of g = 16
+    (the layer's input channels): 579 key switches against the joint
+    compaction's 549, the same FP64 result."""
+    slots = 32768
+    X = synth.image(2, 16, 32, 32)
+    K = synth.conv_weights(2, 32, 16, 3, 0.1)
+    fm = LY.FMap(16, 32, 32, reps=2)
+    out = []
+    for g in (0, 16):
+        kern, masks = LY.conv_plaintexts(fm, K, 2, 1, slots, stride_group=g)
+        ev = sim(slots)
+        y, fo = LY.conv2d(ev, LY.SimCt(LY.pack(X, fm, slots), 22), fm, 32, 3, 2, 1, kern, masks, slots,
+                          stride_group=g)
+        out.append((ev.ks, y, fo))
+    assert out[0][0] == 549 and out[1][0] == 579
+    assert np.array_equal(out[0][1].v, out[1][1].v) and out[1][1].level == out[0][1].level == 17
+    assert np.max(np.abs(LY.unpack(out[1][1].v, out[1][2]) - LY.conv2d_ref(X, K, 2, 1))) < 1e-12
+    assert len(LY.conv_rotations(fm, 32, 3, 2, 1, slots, stride_group=16)) == len(
+        LY.conv_rotations(fm, 32, 3, 2, 1, slots)) + 1
+
+
 @pytest.mark.parametrize("C,F,HW,k,S,P", [(3, 4, 12, 3, 2, 1), (2, 2, 13, 5, 2, 2), (1, 2, 16, 3, 3, 0)])
 def test_sim_conv_log_step_striding(C, F, HW, k, S, P):
     slots = 4096

@@ -318,6 +318,7 @@ typedef struct {
   int32_t n_in, n_out;  /* FC; CHEB_MASK: n_in = used slots */
   double beta;          /* CHEB_MASK */
   int32_t stride_mode;  /* HE_STRIDE_EXTRACT or HE_STRIDE_LOG (he_ctx_striding) */
+  int32_t stride_groups; /* HE_STRIDE_JOINT or HE_STRIDE_GROUP_IN (he_ctx_stride_groups) */
 } he_layer_desc;
 int he_layer_plaintexts(const he_layer_desc* desc, const double* weights, const double* bias, double* out,
                         size_t cap_vectors, int32_t* n_vectors);
@@ -407,6 +408,19 @@ int he_ctx_mask_chains(he_ctx* ctx, int mode);
 #define HE_STRIDE_EXTRACT 0
 #define HE_STRIDE_LOG 1
 int he_ctx_striding(he_ctx* ctx, int mode);
+/* Output-channel grouping of a strided convolution's compaction (section
+ * "Secure Advanced Convolution With Striding", the multi-channel pipeline),
+ * per context for later plans and calls:
+ *   HE_STRIDE_JOINT (default): all F output channels compacted at once;
+ *   HE_STRIDE_GROUP_IN: the paper's groups of g = the layer's input channels
+ *     (when fewer than F): each group compacted jointly (its masks in the
+ *     group order, covering only its channels; a one-channel group keeps the
+ *     channel step as one mask), then the groups merged by a Horner chain
+ *     with the single key g (cs - Ho Wo), G - 1 more key switches, no level.
+ * Same plaintext result.  HE_EINVAL for another mode. */
+#define HE_STRIDE_JOINT 0
+#define HE_STRIDE_GROUP_IN 1
+int he_ctx_stride_groups(he_ctx* ctx, int mode);
 /* bias_pt (nullable): the output channels' biases on the output layout
  * (he_layer_plaintexts), encoded at the output's scale and level, added to
  * the result (the convolution's "add the bias"). */

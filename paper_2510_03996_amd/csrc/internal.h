@@ -130,6 +130,7 @@ struct Ctx {
   int chsum = HE_CHSUM_CHAIN;      // convolution input-channel sum (he_ctx_conv_channel_sum)
   int chain = HE_CHAIN_HORNER;     // masked rotation chains of the layers (he_ctx_mask_chains)
   int stride = HE_STRIDE_EXTRACT;  // column step of the stride compaction (he_ctx_striding)
+  int stride_groups = HE_STRIDE_JOINT;  // output-channel groups of a convolution's striding (he_ctx_stride_groups)
   int fc = HE_FC_ROWS;             // fully connected form (he_ctx_fc_form)
   int layer_streams = 2;           // streams a convolution / hoisted set is spread over (he_ctx_layer_streams)
   // helper streams only where a key switch outlasts the fork and join even

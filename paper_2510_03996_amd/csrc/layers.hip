@@ -193,7 +193,7 @@ struct Step {
 // columns (one chain, key S-1; or with HE_STRIDE_LOG ceil(log2 Wo) two-term
 // chains with keys (S-1) 2^t), rows (key S rs - Wo), channels (key
 // cs - Ho Wo), each only when it moves data.
-static std::vector<Step> compaction_plan(const Ctx* c, const he_fmap& fm, int S, int Ho, int Wo) {
+static std::vector<Step> compaction_plan(const Ctx* c, const he_fmap& fm, int S, int Ho, int Wo, int multi = -1) {
   std::vector<Step> st;
   int T = 0;
   while ((1 << T) < Wo) T++;
@@ -204,7 +204,10 @@ static std::vector<Step> compaction_plan(const Ctx* c, const he_fmap& fm, int S,
   int D = S * fm.row_stride - Wo;
   if (D != 0) st.push_back({1, Ho, D});
   int E = fm.chan_stride - Ho * Wo;
-  if (E != 0 && fm.channels > 1) st.push_back({2, fm.channels, E});
+  // channels: when there are several (multi: a one-channel group of the
+  // multi-channel pipeline keeps the step as one mask, so that every group
+  // ends at the same level)
+  if (E != 0 && (multi < 0 ? fm.channels > 1 : multi != 0)) st.push_back({2, fm.channels, E});
   return st;
 }
 static int compaction_masks(const std::vector<Step>& st) {
@@ -268,10 +271,10 @@ static he_ct horner_masked(Ev& ev, const he_ct& v, const he_pt* m, int n, int ke
 }
 
 static he_ct compaction(Ev& ev, const he_ct& v, const he_fmap& fm, int S, int Ho, int Wo, const he_pt* masks,
-                        he_fmap* out_map) {
+                        he_fmap* out_map, int multi = -1) {
   he_ct cur = v;
   int pos = 0;
-  for (const Step& st : compaction_plan(ev.c, fm, S, Ho, Wo)) {
+  for (const Step& st : compaction_plan(ev.c, fm, S, Ho, Wo, multi)) {
     he_ct nxt = horner_masked(ev, cur, masks + pos, st.n, st.key);
     if (pos > 0) ev.release(cur);
     cur = nxt;
@@ -293,6 +296,57 @@ static int plan_keys_out(he_layer_plan* pl, const std::vector<int>& keys) {
   pl->n_keys = (int)keys.size();
   for (int i = 0; i < pl->n_keys; i++) pl->rot_keys[i] = keys[i];
   return HE_OK;
+}
+
+// ---------------------------------------------------------------- multi-channel striding
+// The stride compaction of a convolution's F output channels: all at once
+// (HE_STRIDE_JOINT), or the paper's multi-channel pipeline
+// (HE_STRIDE_GROUP_IN): groups of g = the layer's input channels, each
+// compacted jointly (group c0's channel c lands at c0 cs + c Ho Wo), then
+// merged by a Horner chain with the single key g E, E = cs - Ho Wo
+// (acc = z_last; acc = Rot_{gE}(acc) + z_k; no level).
+static int stride_group_size(const Ctx* c, int F, int C_in) {
+  return (c->stride_groups == HE_STRIDE_GROUP_IN && C_in > 0 && C_in < F) ? C_in : F;
+}
+// plan of the strided compaction of map f1 (F channels): keys, key switches,
+// levels and masks added to the caller's counts
+static void strided_plan(const Ctx* c, const he_fmap& f1, int S, int Ho, int Wo, int g, std::vector<int>& keys,
+                         int& ks, int& lv, int& nmask) {
+  const int F = f1.channels, multi = F > 1;
+  int ngroups = 0, steps = 0;
+  for (int c0 = 0; c0 < F; c0 += g, ngroups++) {
+    he_fmap sub{std::min(g, F - c0), f1.height, f1.width, f1.row_stride, f1.chan_stride, 1};
+    auto st = compaction_plan(c, sub, S, Ho, Wo, multi);
+    for (auto& x : st) { chain_keys(c, keys, x.n, x.key); ks += chain_switches(c, x.n); }
+    nmask += compaction_masks(st);
+    steps = (int)st.size();
+  }
+  lv += steps;
+  if (ngroups > 1) {
+    add_keys(keys, g * (f1.chan_stride - Ho * Wo));
+    ks += ngroups - 1;
+  }
+}
+static he_ct strided(Ev& ev, const he_ct& v, const he_fmap& f1, int S, int Ho, int Wo, int g, const he_pt* masks,
+                     he_fmap* out_map) {
+  const int F = f1.channels, multi = F > 1;
+  if (g >= F) return compaction(ev, v, f1, S, Ho, Wo, masks, out_map, multi);
+  std::vector<he_ct> zs;
+  int pos = 0;
+  for (int c0 = 0; c0 < F; c0 += g) {
+    he_fmap sub{std::min(g, F - c0), f1.height, f1.width, f1.row_stride, f1.chan_stride, 1};
+    he_fmap om;
+    zs.push_back(compaction(ev, v, sub, S, Ho, Wo, masks + pos, &om, multi));
+    pos += compaction_masks(compaction_plan(ev.c, sub, S, Ho, Wo, multi));
+  }
+  he_ct acc = zs.back();
+  for (int k = (int)zs.size() - 2; k >= 0; k--) {
+    acc = ev.rot_take(acc, g * (f1.chan_stride - Ho * Wo));
+    ev.add_into(acc, zs[k]);
+    ev.release(zs[k]);
+  }
+  *out_map = he_fmap{F, Ho, Wo, Wo, Ho * Wo, 1};
+  return acc;
 }
 
 // ---------------------------------------------------------------- conv plan
@@ -448,9 +502,7 @@ static int conv_plan_keys(const Ctx* c, const he_fmap* fm, int F, int k, int S, 
     if (S > 1) {
       int Ho = (W - 1) / S + 1;
       he_fmap f1{F, W, W, W, W * W, 1};
-      auto st = compaction_plan(c, f1, S, Ho, Ho);
-      for (auto& x : st) { chain_keys(c, keys, x.n, x.key); ks += chain_switches(c, x.n); lv++; }
-      nmask += compaction_masks(st);
+      strided_plan(c, f1, S, Ho, Ho, stride_group_size(c, F, C), keys, ks, lv, nmask);
       pl->out = he_fmap{F, Ho, Ho, Ho, Ho * Ho, 1};
     }
     pl->n_kernel_pts = 9 * F;
@@ -468,9 +520,7 @@ static int conv_plan_keys(const Ctx* c, const he_fmap* fm, int F, int k, int S, 
     if (S > 1) {
       int Ho = (H1 - 1) / S + 1, Wo = (W1 - 1) / S + 1;
       he_fmap f1{F, H1, W1, fm->row_stride, fm->chan_stride, 1};
-      auto st = compaction_plan(c, f1, S, Ho, Wo);
-      for (auto& x : st) { chain_keys(c, keys, x.n, x.key); ks += chain_switches(c, x.n); lv++; }
-      nmask += compaction_masks(st);
+      strided_plan(c, f1, S, Ho, Wo, stride_group_size(c, F, C), keys, ks, lv, nmask);
       pl->out = he_fmap{F, Ho, Wo, Wo, Ho * Wo, 1};
     }
     pl->n_kernel_pts = k * k * F;
@@ -560,7 +610,8 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
     *out_map = he_fmap{F, W, W, W, W * W, (fm.reps == 2 && 2 * F * W * W == slots) ? 2 : 1};
     if (S == 1) return y;
     int Ho = (W - 1) / S + 1;
-    he_ct z = compaction(ev, y, he_fmap{F, W, W, W, W * W, 1}, S, Ho, Ho, masks + mpos, out_map);
+    he_ct z = strided(ev, y, he_fmap{F, W, W, W, W * W, 1}, S, Ho, Ho, stride_group_size(ev.c, F, C), masks + mpos,
+                      out_map);
     ev.release(y);
     return z;
   }
@@ -612,7 +663,8 @@ static he_ct conv_run(Ev& ev, const he_ct& x, const he_fmap& fm, int F, int k, i
   *out_map = he_fmap{F, H1, W1, fm.row_stride, cs, 1};
   if (S == 1) return acc;
   int Ho = (H1 - 1) / S + 1, Wo = (W1 - 1) / S + 1;
-  he_ct z = compaction(ev, acc, he_fmap{F, H1, W1, fm.row_stride, cs, 1}, S, Ho, Wo, masks + (C > 1 ? 1 : 0),
+  he_ct z = strided(ev, acc, he_fmap{F, H1, W1, fm.row_stride, cs, 1}, S, Ho, Wo, stride_group_size(ev.c, F, C),
+                    masks + (C > 1 ? 1 : 0),
                        out_map);
   ev.release(acc);
   return z;
@@ -906,13 +958,15 @@ static void chain_vectors(const Ctx* c, Vecs& out, Vecs v, int key) {
 }
 
 // stride-S extraction masks of outputs (S i, S j) of map fm (compaction_plan)
-static void compaction_vectors(const Ctx* c, Vecs& out, const he_fmap& fm, int S, int Ho, int Wo, double col_scale) {
+// (channels c0 .. c0 + channels - 1 of the map: a group of the multi-channel pipeline)
+static void compaction_vectors(const Ctx* c, Vecs& out, const he_fmap& fm, int S, int Ho, int Wo, double col_scale,
+                               int c0 = 0, int multi = -1) {
   const int slots = c->n / 2;
-  for (const Step& st : compaction_plan(c, fm, S, Ho, Wo)) {
+  for (const Step& st : compaction_plan(c, fm, S, Ho, Wo, multi)) {
     Vecs v;
     for (int t = 0; t < st.n; t++) {
       std::vector<double> m = zeros(slots);
-      for (int ch = 0; ch < fm.channels; ch++) {
+      for (int ch = c0; ch < c0 + fm.channels; ch++) {
         if (st.kind == 4) {
           // after steps < st.t column j sits at S (j - b) + b, b = j mod 2^st.t;
           // mask 0 holds the j with bit st.t clear, mask 1 those with it set
@@ -927,7 +981,7 @@ static void compaction_vectors(const Ctx* c, Vecs& out, const he_fmap& fm, int S
         } else if (st.kind == 1) {
           const size_t base = (size_t)ch * fm.chan_stride + (size_t)S * t * fm.row_stride;
           for (int j = 0; j < Wo; j++) m[base + j] = 1.0;
-        } else if (ch == t) {
+        } else if (ch == c0 + t) {
           for (int j = 0; j < Ho * Wo; j++) m[(size_t)ch * fm.chan_stride + j] = 1.0;
         }
       }
@@ -935,6 +989,14 @@ static void compaction_vectors(const Ctx* c, Vecs& out, const he_fmap& fm, int S
     }
     chain_vectors(c, out, std::move(v), st.key);
   }
+}
+
+// the convolution's stride masks: each group of the multi-channel pipeline in turn
+static void strided_vectors(const Ctx* c, Vecs& out, const he_fmap& f1, int S, int Ho, int Wo, int g) {
+  const int F = f1.channels;
+  for (int c0 = 0; c0 < F; c0 += g)
+    compaction_vectors(c, out, he_fmap{std::min(g, F - c0), f1.height, f1.width, f1.row_stride, f1.chan_stride, 1}, S,
+                       Ho, Wo, 1.0, c0, F > 1);
 }
 
 // convolution: kernel vectors [f][tap], then masks, then (bias) the bias
@@ -1001,7 +1063,7 @@ static int conv_vectors(const Ctx* c, const he_fmap& fm, int F, int k, int S, in
       }
     if (S > 1) {
       const int Ho = (W - 1) / S + 1;
-      compaction_vectors(c, out, he_fmap{F, W, W, W, WW, 1}, S, Ho, Ho, 1.0);
+      strided_vectors(c, out, he_fmap{F, W, W, W, WW, 1}, S, Ho, Ho, stride_group_size(c, F, C));
     }
   } else {
     const int H1 = fm.height + 2 * P - k + 1, W1 = fm.width + 2 * P - k + 1;
@@ -1024,7 +1086,8 @@ static int conv_vectors(const Ctx* c, const he_fmap& fm, int F, int k, int S, in
     }
     if (S > 1) {
       const int Ho = (H1 - 1) / S + 1, Wo = (W1 - 1) / S + 1;
-      compaction_vectors(c, out, he_fmap{F, H1, W1, fm.row_stride, fm.chan_stride, 1}, S, Ho, Wo, 1.0);
+      strided_vectors(c, out, he_fmap{F, H1, W1, fm.row_stride, fm.chan_stride, 1}, S, Ho, Wo,
+                      stride_group_size(c, F, C));
     }
   }
   if (bias) {
@@ -1132,6 +1195,13 @@ static int check_pts(const Ctx* c, const he_pt* p, int n, int level, const char*
 
 extern "C" {
 
+int he_ctx_stride_groups(he_ctx* h, int mode) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  if (mode != HE_STRIDE_JOINT && mode != HE_STRIDE_GROUP_IN) return set_error(HE_EINVAL, "unknown stride grouping");
+  h->c.stride_groups = mode;
+  return HE_OK;
+}
+
 int he_ctx_striding(he_ctx* h, int mode) {
   if (!h) return set_error(HE_EINVAL, "null context");
   if (mode != HE_STRIDE_EXTRACT && mode != HE_STRIDE_LOG) return set_error(HE_EINVAL, "unknown striding mode");
@@ -1199,12 +1269,15 @@ int he_layer_plaintexts(const he_layer_desc* d, const double* weights, const dou
   if (d->fc_form != HE_FC_ROWS && d->fc_form != HE_FC_DIAG) return set_error(HE_EINVAL, "unknown FC form");
   if (d->stride_mode != HE_STRIDE_EXTRACT && d->stride_mode != HE_STRIDE_LOG)
     return set_error(HE_EINVAL, "unknown striding mode");
+  if (d->stride_groups != HE_STRIDE_JOINT && d->stride_groups != HE_STRIDE_GROUP_IN)
+    return set_error(HE_EINVAL, "unknown stride grouping");
   return guarded([&] {
     Ctx opt;  // the schedule options the layer's plan depends on
     opt.log_n = d->log_n;
     opt.n = 1 << d->log_n;
     opt.chain = d->mask_chains;
     opt.stride = d->stride_mode;
+    opt.stride_groups = d->stride_groups;
     opt.fc = d->fc_form;
     Vecs v;
     int rc;

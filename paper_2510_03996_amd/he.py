@@ -24,6 +24,7 @@ NTT_VARIANTS = 5
 CHSUM_CHAIN, CHSUM_LOG = 0, 1  # he_ctx_conv_channel_sum modes
 CHAIN_HORNER, CHAIN_BSGS = 0, 1  # he_ctx_mask_chains modes
 STRIDE_EXTRACT, STRIDE_LOG = 0, 1  # he_ctx_striding modes
+STRIDE_JOINT, STRIDE_GROUP_IN = 0, 1  # he_ctx_stride_groups modes
 FC_ROWS, FC_DIAG = 0, 1  # he_ctx_fc_form modes
 MAX_Q, MAX_P = 60, 16
 
@@ -79,19 +80,20 @@ class he_layer_desc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("log_n", ctypes.c_int32), ("mask_chains", ctypes.c_int32),
                 ("fc_form", ctypes.c_int32), ("in_", he_fmap), ("out_ch", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("stride", ctypes.c_int32), ("padding", ctypes.c_int32), ("n_in", ctypes.c_int32),
-                ("n_out", ctypes.c_int32), ("beta", ctypes.c_double), ("stride_mode", ctypes.c_int32)]
+                ("n_out", ctypes.c_int32), ("beta", ctypes.c_double), ("stride_mode", ctypes.c_int32),
+                ("stride_groups", ctypes.c_int32)]
 
 
 LAYER_CONV, LAYER_AVGPOOL, LAYER_FC, LAYER_CHEB_MASK = 0, 1, 2, 3
 
 
 def layer_plaintexts(kind, log_n, weights=None, bias=None, fm=None, out_ch=0, kernel=0, stride=1, padding=0,
-                     n_in=0, n_out=0, beta=1.0, mask_chains=0, fc_form=0, stride_mode=0):
+                     n_in=0, n_out=0, beta=1.0, mask_chains=0, fc_form=0, stride_mode=0, stride_groups=0):
     """he_layer_plaintexts: the real slot vectors (float64 [count][N/2]) a
     layer consumes, in its plan's order (host only, no GPU needed)."""
     d = he_layer_desc(int(kind), int(log_n), int(mask_chains), int(fc_form), fm if fm is not None else he_fmap(),
                       int(out_ch), int(kernel), int(stride), int(padding), int(n_in), int(n_out), float(beta),
-                      int(stride_mode))
+                      int(stride_mode), int(stride_groups))
     w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
     b = None if bias is None else np.ascontiguousarray(bias, dtype=np.float64)
     dp = ctypes.POINTER(ctypes.c_double)
@@ -182,6 +184,7 @@ def lib():
             "he_ctx_conv_channel_sum": [vp, i32],
             "he_ctx_mask_chains": [vp, i32],
             "he_ctx_striding": [vp, i32],
+            "he_ctx_stride_groups": [vp, i32],
             "he_ctx_fc_form": [vp, i32],
             "he_ctx_layer_streams": [vp, i32],
             "he_key_host_register": [vp, i32, P(ctypes.c_uint64), sz],
@@ -563,6 +566,12 @@ class Context:
         and calls: STRIDE_EXTRACT (one chain over the columns) or STRIDE_LOG
         (ceil(log2 Wo) two-term steps, the paper's second approach)."""
         _check(lib().he_ctx_striding(self.h, int(mode)))
+
+    def stride_groups(self, mode):
+        """Output-channel grouping of later strided conv2d plans and calls:
+        STRIDE_JOINT (all channels at once) or STRIDE_GROUP_IN (the paper's
+        groups of the layer's input channels, merged with one more key)."""
+        _check(lib().he_ctx_stride_groups(self.h, int(mode)))
 
     def fc_form(self, mode):
         """Form of later fc plans and calls: FC_ROWS (per neuron) or FC_DIAG

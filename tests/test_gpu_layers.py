@@ -69,7 +69,7 @@ def encrypt_map(name, X, fm, seed, level=None):
 
 
 def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False, bsgs=False, streams=(2,),
-             slog=False):
+             slog=False, groups=False):
     """One oracle convolution; the GPU result with each layer-stream count in
     `streams` must equal it bit for bit."""
     from paper_2510_03996_amd import he
@@ -80,16 +80,18 @@ def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False
     g.conv_channel_sum(he.CHSUM_LOG if logstep else he.CHSUM_CHAIN)
     g.mask_chains(he.CHAIN_BSGS if bsgs else he.CHAIN_HORNER)
     g.striding(he.STRIDE_LOG if slog else he.STRIDE_EXTRACT)
+    g.stride_groups(he.STRIDE_GROUP_IN if groups else he.STRIDE_JOINT)
+    sg = fm.C if groups else 0
     plan = g.conv2d_plan(fm_he(fm), F, k, stride, padding)
     assert sorted(plan.keys()) == LY.conv_rotations(fm, F, k, stride, padding, slots, logstep=logstep, bsgs=bsgs,
-                                                    stride_log=slog)
+                                                    stride_log=slog, stride_group=sg)
     ev = setup_keys(g, name, plan.keys())
     ct = encrypt_map(name, X, fm, seed, level)
-    kern, masks = LY.conv_plaintexts(fm, K, stride, padding, slots, bsgs=bsgs, stride_log=slog)
+    kern, masks = LY.conv_plaintexts(fm, K, stride, padding, slots, bsgs=bsgs, stride_log=slog, stride_group=sg)
     assert (plan.n_kernel_pts, plan.n_mask_pts) == (len(kern), len(masks))
     kp, mp = encode(octx, kern, ct.level), encode(octx, masks, ct.level)
     want, fo = LY.conv2d(ev, ct, fm, F, k, stride, padding, kp, mp, slots, logstep=logstep, bsgs=bsgs,
-                         stride_log=slog)
+                         stride_log=slog, stride_group=sg)
     assert ev.ks == plan.key_switches and ct.level - want.level == plan.levels
     gct, gkp, gmp = g.ct_from_numpy(ct.data, ct.scale), gpts(g, kp), gpts(g, mp)
     for n in streams:
@@ -105,6 +107,7 @@ def run_conv(g, name, X, K, fm, stride, padding, seed, level=None, logstep=False
     g.conv_channel_sum(he.CHSUM_CHAIN)
     g.mask_chains(he.CHAIN_HORNER)
     g.striding(he.STRIDE_EXTRACT)
+    g.stride_groups(he.STRIDE_JOINT)
     return got, want, fo
 
 
@@ -144,6 +147,24 @@ def test_config1_log_step_striding_conv(gctx, bsgs):
     X = synth.image(34, 3, 12, 12)
     K = synth.conv_weights(34, 4, 3, 3, 0.2)
     run_conv(gctx("config1"), "config1", X, K, LY.FMap(3, 12, 12), 2, 1, 34, bsgs=bsgs, streams=(1, 2), slog=True)
+
+
+@pytest.mark.parametrize("slog", [False, True], ids=["extract", "logstride"])
+def test_config1_grouped_striding_conv(gctx, slog):
+    """The paper's multi-channel striding pipeline (groups of the layer's 2
+    input channels: 2 + 2 + 1 of the 5 outputs, merged with one more key):
+    generic 3x3 / stride 2 / pad 1 at N=2^14, bit for bit against the oracle."""
+    X = synth.image(36, 2, 12, 12)
+    K = synth.conv_weights(36, 5, 2, 3, 0.2)
+    run_conv(gctx("config1"), "config1", X, K, LY.FMap(2, 12, 12), 2, 1, 36, streams=(1, 2), slog=slog, groups=True)
+
+
+def test_config1_grouped_striding_special_conv(gctx):
+    """The special schedule (replicated 4 x 32 x 32 input, 4 -> 8 channels,
+    stride 2) with the multi-channel pipeline's two groups of 4 at N=2^14."""
+    X = synth.image(37, 4, 32, 32)
+    K = synth.conv_weights(37, 8, 4, 3, 0.1)
+    run_conv(gctx("config1"), "config1", X, K, LY.FMap(4, 32, 32, reps=2), 2, 1, 37, groups=True)
 
 
 def test_config1_log_step_striding_pool(gctx):

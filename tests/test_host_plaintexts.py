@@ -36,6 +36,7 @@ CONVS = [  # (log_n, C, H, W, reps, F, k, stride, padding)
     (14, 2, 8, 8, 1, 3, 3, 1, 2),        # padding beyond (k-1)/2: re-layout as X_p
     (14, 3, 10, 10, 1, 2, 1, 2, 1),      # 1x1 / stride 2 / padding 1 (re-layout)
     (14, 2, 7, 9, 1, 2, 5, 2, 3),        # rectangular, re-layout, strided
+    (14, 2, 12, 12, 1, 5, 3, 2, 1),      # 2 -> 5 channels, strided: groups 2 + 2 + 1 in the pipeline
 ]
 
 
@@ -46,17 +47,18 @@ def hfm(C, H, W, reps):
 @pytest.mark.parametrize("case", CONVS, ids=lambda c: "n%d_%dx%dx%d_F%d_k%d_s%d_p%d" % (c[0], c[1], c[2], c[3], c[5], c[6], c[7], c[8]))
 @pytest.mark.parametrize("bsgs", [False, True], ids=["horner", "bsgs"])
 @pytest.mark.parametrize("slog", [False, True], ids=["extract", "logstride"])
-def test_conv_plaintexts_match_oracle(case, bsgs, slog):
+@pytest.mark.parametrize("grp", [False, True], ids=["joint", "groups"])
+def test_conv_plaintexts_match_oracle(case, bsgs, slog, grp):
     log_n, C, H, W, reps, F, k, S, P = case
-    if slog and S == 1:
-        pytest.skip("the striding mode only changes strided layers")
+    if (slog or grp) and S == 1:
+        pytest.skip("the striding options only change strided layers")
     slots = (1 << log_n) // 2
     K = synth.conv_weights(log_n * 7 + F, F, C, k, 0.1)
     b = synth.uniform_slots(F, F)
     got = he.layer_plaintexts(he.LAYER_CONV, log_n, K, b, fm=hfm(C, H, W, reps), out_ch=F, kernel=k, stride=S,
-                              padding=P, mask_chains=int(bsgs), stride_mode=int(slog))
+                              padding=P, mask_chains=int(bsgs), stride_mode=int(slog), stride_groups=int(grp))
     fm = LY.FMap(C, H, W, reps=reps)
-    kern, masks = LY.conv_plaintexts(fm, K, S, P, slots, bsgs, slog)
+    kern, masks = LY.conv_plaintexts(fm, K, S, P, slots, bsgs, slog, C if grp else 0)
     fo = LY.conv_out_map(fm, F, k, S, P, slots)
     want = kern + masks + [LY.conv_bias_vector(fo, b, slots)]
     assert got.shape == (len(want), slots)
@@ -64,7 +66,7 @@ def test_conv_plaintexts_match_oracle(case, bsgs, slog):
         assert np.array_equal(got[i], w), "vector %d of %d" % (i, len(want))
     # without a bias the vector is left out
     nb = he.layer_plaintexts(he.LAYER_CONV, log_n, K, None, fm=hfm(C, H, W, reps), out_ch=F, kernel=k, stride=S,
-                             padding=P, mask_chains=int(bsgs), stride_mode=int(slog))
+                             padding=P, mask_chains=int(bsgs), stride_mode=int(slog), stride_groups=int(grp))
     assert nb.shape[0] == len(want) - 1
 
 

@@ -358,6 +358,21 @@ def layer_latencies(reps=3):
         timed(lambda: c2.conv2d(ctb, pa.out, 32, 3, 2, 1, bk, bm, stream=s), reps, s) * 1e3, 3)
     c2.mask_chains(he.CHAIN_HORNER)
     c2.conv_channel_sum(he.CHSUM_CHAIN)
+    # the paper's other striding forms of conv B: approach 2 (log-step column
+    # moves) and the multi-channel pipeline (groups of the 16 input channels)
+    stride_ks = {}
+    for tag, on, off in (("logstride", lambda: c2.striding(he.STRIDE_LOG), lambda: c2.striding(he.STRIDE_EXTRACT)),
+                         ("groups", lambda: c2.stride_groups(he.STRIDE_GROUP_IN),
+                          lambda: c2.stride_groups(he.STRIDE_JOINT))):
+        on()
+        pv = c2.conv2d_plan(pa.out, 32, 3, 2, 1)
+        upload_synthetic_keys(c2, pv.keys(), 30)
+        vm = synthetic_pts(c2, pv.n_mask_pts, 22, 36, sc)
+        out["resnet_convB_s2_n16_%s_ms" % tag] = round(
+            timed(lambda: c2.conv2d(ctb, pa.out, 32, 3, 2, 1, bk, vm, stream=s), reps, s) * 1e3, 3)
+        stride_ks["resnet_convB_" + tag] = pv.key_switches
+        off()
+        del vm
     del bk, bm
     ctg = synthetic_ct(c2, 17, 37, sc)
     gm = synthetic_pts(c2, pg.n_mask_pts, 17, 38, sc)
@@ -403,6 +418,7 @@ def layer_latencies(reps=3):
                            "conv7x7_s2_p3": p7.key_switches, "relu_cheb59": he.cheb_plan(cheb, True)[1],
                            "resnet_convA_logsum": pal.key_switches, "resnet_convB_logsum": pbl.key_switches,
                            "resnet_convB_logsum_bsgs": pbb.key_switches, "resnet_gap_bsgs": pgb.key_switches,
+                           **stride_ks,
                            "lenet5_stack_bsgs": lenet_ks_b, "resnet_fc_diag": pfd.key_switches}
     c2.close()
     return out

@@ -211,7 +211,7 @@ struct NttEpi {
                          // double bits) [level] P^{-1} and [level] P^{-1} / q_i
   uint32_t g;
   int32_t level;
-  // batched form (out_base != nullptr): batch z = 2 pair + poly writes
+  // batched form (out_base or tab set): batch z = 2 pair + poly writes
   // out_base + z out_bs; add_z = add_base + items[pair] add_item for poly 0
   // (gathered through phi_g), none for poly 1 or when add_base is null
   const int32_t* items;
@@ -222,9 +222,9 @@ struct NttEpi {
   // inverse pass 1 only: per-modulus finishing constants [4] (conv_fin_fill)
   // replacing N^{-1}, so that the transform writes a conversion's inputs
   const uint64_t* fin;
-  // batched hoisted set (with out_base set to any non-null value): output of
-  // batch z at tab->out[z], pair z/2 gathered through tab->g[z/2]; add_base
-  // (items null) is the one input's c0
+  // batched hoisted set (tab != nullptr, batched form): output of batch z at
+  // tab->out[z], pair z/2 gathered through tab->g[z/2]; add_base (items
+  // null) is the one input's c0
   const SetTab* tab;
 };
 // the last forward NTT with the ModDown epilogue, over nbatch arrays of y

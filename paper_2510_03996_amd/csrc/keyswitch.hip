@@ -284,8 +284,7 @@ static int ks_set(Ctx* c, Lane* lane, const WS& w, const uint64_t* c0, const uin
     epi.level = level;
     epi.g = 1;
     epi.add_base = c0;
-    epi.out_base = outs[0];  // batched mode; the outputs come from the table
-    epi.tab = lane->set_tab;
+    epi.tab = lane->set_tab;  // batched mode, the outputs and Galois elements from the table
     if ((rc = ntt_launch_moddown(c, Y, (size_t)level * N, range_map(0, level, 0), epi, s, z, 2))) return rc;
   }
   return HE_OK;

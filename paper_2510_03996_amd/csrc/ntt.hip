@@ -44,7 +44,7 @@ __device__ __forceinline__ void ntt_store(uint64_t* a, int k, uint64_t v, const 
     a[k] = v;
   } else {
     const size_t off = (size_t)i << LOGN;
-    const bool batched = epi.out_base != nullptr;
+    const bool batched = epi.out_base != nullptr || epi.tab != nullptr;
     const bool gather = batched ? (z & 1) == 0 : z == 0;  // the polynomial c0 is added to
     const uint64_t* add =
         batched ? (gather && epi.add_base ? epi.add_base + (epi.items ? epi.items[z >> 1] * epi.add_item : 0) : nullptr)
@@ -108,7 +108,7 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
       const size_t off = (size_t)pos << LOGN;
       const double pw = bits_to_f64(epi.pinv[2 * epi.level + pos]);
       const double pwq = bits_to_f64(epi.pinv[3 * epi.level + pos]);
-      const bool batched = epi.out_base != nullptr;
+      const bool batched = epi.out_base != nullptr || epi.tab != nullptr;
       const bool gather = batched ? (bz & 1) == 0 : bz == 0;  // the polynomial c0 is added to
       const uint64_t* add =
           batched ? (gather && epi.add_base ? epi.add_base + (epi.items ? epi.items[bz >> 1] * epi.add_item : 0)

@@ -117,14 +117,42 @@ __global__ __launch_bounds__((NttPass<LOGN, PASS, INV, LOG_EPT, LOG_TILE>::THREA
       const uint64_t* u = epi.u + bz * epi.u_bs + off;
       uint64_t* o = (epi.tab ? epi.tab->out[bz] : batched ? epi.out_base + bz * epi.out_bs : epi.out[bz]) + off;
       const uint32_t gal = epi.tab ? epi.tab->g[bz >> 1] : epi.g;  // (g is the tile loop's index below)
-      for (int e = tid; e < P::TILE; e += P::THREADS) {
-        int g, k;
-        P::tile_elem(e, g, k);
-        const int kk = P::gidx(wg, g, k);
-        const double r = mul_f64_c(u52_to_f64(u[kk]) - dl[P::lidx(g, k)], pw, pwq, dq);
-        double x = 0.0;
-        if (add) x = u52_to_f64(add[off + (gather && gal != 1 ? automorph_src(kk, gal, LOGN) : (uint32_t)kk)]);
-        o[kk] = f64_to_u52(canon_f64(r + x, dqinv, dq));
+      if (!(add && gather && gal != 1)) {
+        for (int e = tid; e < P::TILE; e += P::THREADS) {
+          int g, k;
+          P::tile_elem(e, g, k);
+          const int kk = P::gidx(wg, g, k);
+          const double r = mul_f64_c(u52_to_f64(u[kk]) - dl[P::lidx(g, k)], pw, pwq, dq);
+          double x = 0.0;
+          if (add) x = u52_to_f64(add[off + kk]);
+          o[kk] = f64_to_u52(canon_f64(r + x, dqinv, dq));
+        }
+      } else {
+        // c0 through phi_g: the pass-2 tile is the aligned block [wg TILE,
+        // (wg + 1) TILE), which phi_g maps onto one aligned block, so that
+        // block is read coalesced into the LDS (after the transform's values
+        // have moved to registers) and permuted there
+        constexpr int EPT = P::TILE / P::THREADS;
+        double vv[EPT];
+#pragma unroll
+        for (int i = 0; i < EPT; i++) {
+          int g, k;
+          P::tile_elem(tid + i * P::THREADS, g, k);
+          vv[i] = dl[P::lidx(g, k)];
+        }
+        __syncthreads();
+        const uint32_t base = (uint32_t)wg * P::TILE;
+        const uint32_t s0 = automorph_src(base, gal, LOGN) & ~(uint32_t)(P::TILE - 1);
+        uint64_t* lu = reinterpret_cast<uint64_t*>(dl);
+        for (int e = tid; e < P::TILE; e += P::THREADS) lu[e] = add[off + s0 + e];
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < EPT; i++) {
+          const uint32_t kk = base + tid + i * P::THREADS;
+          const double r = mul_f64_c(u52_to_f64(u[kk]) - vv[i], pw, pwq, dq);
+          const double x = u52_to_f64(lu[automorph_src(kk, gal, LOGN) - s0]);
+          o[kk] = f64_to_u52(canon_f64(r + x, dqinv, dq));
+        }
       }
     } else {
       // the inverse transform's N^{-1}, or a conversion's finishing constant

@@ -30,8 +30,9 @@ __global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, si
 
 // Inner products of one input's extended digits with several keys (a
 // hoisted set): grid x = 256-coefficient tile, y = extended limb; the
-// workgroup loops over the nz rotations of the round (key tab->key[z],
-// Galois element tab->g[z]), writing u_z = u + z 2 (level+K) N,
+// workgroup loops over the nz rotations of the round (key tab.key[z],
+// Galois element tab.g[z]; the table is a kernel argument), writing
+// u_z = u + z 2 (level+K) N,
 // [2][level+K][N].  phi_g maps an aligned block of 256 NTT indices onto an
 // aligned block, so each digit's source block is read coalesced and permuted
 // in LDS; the next rotation's blocks and key words are loaded while the
@@ -41,7 +42,7 @@ __global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, si
 // REDC (the same canonical residue).
 template <int DN>
 __global__ __launch_bounds__(256) void k_ip_set(const uint64_t* __restrict__ ext, const uint64_t* __restrict__ c1,
-                                                int level, int K, int alpha, const SetTab* __restrict__ tab, int nz,
+                                                int level, int K, int alpha, const SetTab tab, int nz,
                                                 size_t key_digit_stride, size_t key_poly_stride, int L, int logn,
                                                 const ModInfo* __restrict__ mods, uint64_t* __restrict__ u_all) {
   __shared__ uint64_t sh[2][DN][256];
@@ -60,11 +61,11 @@ __global__ __launch_bounds__(256) void k_ip_set(const uint64_t* __restrict__ ext
   uint64_t cur[DN], kb[DN], ka[DN], nkb[DN], nka[DN];
   int sl = 0, nsl = 0;
   auto gload = [&](int z, uint64_t* e, uint64_t* b, uint64_t* a, int& slot) {
-    const uint32_t g = tab->g[z];
+    const uint32_t g = tab.g[z];
     const uint32_t src = g == 1 ? k : automorph_src(k, g, logn);
     const uint32_t s0 = src & ~255u;
     slot = (int)(src & 255u);
-    const uint64_t* key = tab->key[z];
+    const uint64_t* key = tab.key[z];
 #pragma unroll
     for (int j = 0; j < DN; j++) {
       const uint64_t* sp = j == own ? c1 : ext + j * En;
@@ -75,7 +76,11 @@ __global__ __launch_bounds__(256) void k_ip_set(const uint64_t* __restrict__ ext
     }
   };
   gload(0, cur, kb, ka, sl);
-  for (int z = 0; z < nz; z++) {
+  // unrolled over the table, so that its entries (kernel arguments) are read
+  // with constant indices
+#pragma unroll
+  for (int z = 0; z < SET_MAX; z++) {
+    if (z >= nz) break;
     const int bf = z & 1;
 #pragma unroll
     for (int j = 0; j < DN; j++) sh[bf][j][tid] = cur[j];
@@ -262,8 +267,8 @@ static int ks_set(Ctx* c, Lane* lane, const WS& w, const uint64_t* c0, const uin
       switch (dn) {
 #define HE_IPS(D)                                                                                                  \
   case D:                                                                                                          \
-    k_ip_set<D><<<grid, 256, 0, s>>>(w.ext, c1, level, K, c->alpha, lane->set_tab, nc, 2 * kps, kps, L, c->log_n,  \
-                                     c->d_mod, U);                                                                 \
+    k_ip_set<D><<<grid, 256, 0, s>>>(w.ext, c1, level, K, c->alpha, t, nc, 2 * kps, kps, L, c->log_n, c->d_mod,   \
+                                     U);                                                                           \
     break;
         HE_IPS(1) HE_IPS(2) HE_IPS(3) HE_IPS(4) HE_IPS(5) HE_IPS(6) HE_IPS(7) HE_IPS(8)
 #undef HE_IPS

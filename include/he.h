@@ -319,9 +319,17 @@ typedef struct {
   double beta;          /* CHEB_MASK */
   int32_t stride_mode;  /* HE_STRIDE_EXTRACT or HE_STRIDE_LOG (he_ctx_striding) */
   int32_t stride_groups; /* HE_STRIDE_JOINT or HE_STRIDE_GROUP_IN (he_ctx_stride_groups) */
+  int32_t channel_sum;   /* HE_CHSUM_CHAIN or HE_CHSUM_LOG (he_ctx_conv_channel_sum; keys only) */
 } he_layer_desc;
 int he_layer_plaintexts(const he_layer_desc* desc, const double* weights, const double* bias, double* out,
                         size_t cap_vectors, int32_t* n_vectors);
+/* The layer's plan from its description alone (host only, no context):
+ * the distinct rotation keys (the paper's rotation-index helper, which the
+ * client uses to generate exactly the keys a model needs), the plaintext
+ * counts, levels, key switches and output layout — what he_conv2d_plan,
+ * he_avgpool_plan and he_fc_plan give on a context with the same options.
+ * CHEB_MASK: one mask plaintext, no keys.  Errors as he_layer_plaintexts. */
+int he_layer_rotations(const he_layer_desc* desc, he_layer_plan* plan);
 
 /* Convolution (Sections "Secure Convolution Layer", "Secure Advanced
  * Convolution Layer" with striding approach 1 and the multi-channel striding

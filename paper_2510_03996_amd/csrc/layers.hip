@@ -1260,9 +1260,8 @@ int he_conv2d(he_ctx* h, const he_ct* in, const he_fmap* in_map, int out_ch, int
   });
 }
 
-int he_layer_plaintexts(const he_layer_desc* d, const double* weights, const double* bias, double* out,
-                        size_t cap_vectors, int32_t* n_vectors) {
-  if (!d || !n_vectors) return set_error(HE_EINVAL, "null argument");
+// the schedule options a layer's plan depends on, from its description
+static int desc_options(const he_layer_desc* d, Ctx& opt) {
   if (d->log_n < 1 || d->log_n > 17) return set_error(HE_EINVAL, "log_n out of range");
   if (d->mask_chains != HE_CHAIN_HORNER && d->mask_chains != HE_CHAIN_BSGS)
     return set_error(HE_EINVAL, "unknown mask-chain mode");
@@ -1271,14 +1270,48 @@ int he_layer_plaintexts(const he_layer_desc* d, const double* weights, const dou
     return set_error(HE_EINVAL, "unknown striding mode");
   if (d->stride_groups != HE_STRIDE_JOINT && d->stride_groups != HE_STRIDE_GROUP_IN)
     return set_error(HE_EINVAL, "unknown stride grouping");
+  if (d->channel_sum != HE_CHSUM_CHAIN && d->channel_sum != HE_CHSUM_LOG)
+    return set_error(HE_EINVAL, "unknown channel-sum mode");
+  opt.log_n = d->log_n;
+  opt.n = 1 << d->log_n;
+  opt.chain = d->mask_chains;
+  opt.stride = d->stride_mode;
+  opt.stride_groups = d->stride_groups;
+  opt.chsum = d->channel_sum;
+  opt.fc = d->fc_form;
+  return HE_OK;
+}
+
+int he_layer_rotations(const he_layer_desc* d, he_layer_plan* plan) {
+  if (!d || !plan) return set_error(HE_EINVAL, "null argument");
+  return guarded([&] {
+    Ctx opt;
+    int rc = desc_options(d, opt);
+    if (rc) return rc;
+    switch (d->kind) {
+      case HE_LAYER_CONV:
+        return conv_plan(&opt, &d->in, d->out_ch, d->kernel, d->stride, d->padding, plan);
+      case HE_LAYER_AVGPOOL:
+        return pool_plan(&opt, &d->in, d->kernel, d->stride, plan);
+      case HE_LAYER_FC:
+        return fc_plan_impl(&opt, d->n_in, d->n_out, plan);
+      case HE_LAYER_CHEB_MASK:
+        *plan = he_layer_plan{};
+        plan->n_mask_pts = 1;
+        return HE_OK;
+      default:
+        return set_error(HE_EINVAL, "unknown layer kind");
+    }
+  });
+}
+
+int he_layer_plaintexts(const he_layer_desc* d, const double* weights, const double* bias, double* out,
+                        size_t cap_vectors, int32_t* n_vectors) {
+  if (!d || !n_vectors) return set_error(HE_EINVAL, "null argument");
   return guarded([&] {
     Ctx opt;  // the schedule options the layer's plan depends on
-    opt.log_n = d->log_n;
-    opt.n = 1 << d->log_n;
-    opt.chain = d->mask_chains;
-    opt.stride = d->stride_mode;
-    opt.stride_groups = d->stride_groups;
-    opt.fc = d->fc_form;
+    int rc0 = desc_options(d, opt);
+    if (rc0) return rc0;
     Vecs v;
     int rc;
     switch (d->kind) {

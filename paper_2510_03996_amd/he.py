@@ -81,19 +81,35 @@ class he_layer_desc(ctypes.Structure):
                 ("fc_form", ctypes.c_int32), ("in_", he_fmap), ("out_ch", ctypes.c_int32), ("kernel", ctypes.c_int32),
                 ("stride", ctypes.c_int32), ("padding", ctypes.c_int32), ("n_in", ctypes.c_int32),
                 ("n_out", ctypes.c_int32), ("beta", ctypes.c_double), ("stride_mode", ctypes.c_int32),
-                ("stride_groups", ctypes.c_int32)]
+                ("stride_groups", ctypes.c_int32), ("channel_sum", ctypes.c_int32)]
 
 
 LAYER_CONV, LAYER_AVGPOOL, LAYER_FC, LAYER_CHEB_MASK = 0, 1, 2, 3
 
 
+def _layer_desc(kind, log_n, fm=None, out_ch=0, kernel=0, stride=1, padding=0, n_in=0, n_out=0, beta=1.0,
+                mask_chains=0, fc_form=0, stride_mode=0, stride_groups=0, channel_sum=0):
+    return he_layer_desc(int(kind), int(log_n), int(mask_chains), int(fc_form), fm if fm is not None else he_fmap(),
+                         int(out_ch), int(kernel), int(stride), int(padding), int(n_in), int(n_out), float(beta),
+                         int(stride_mode), int(stride_groups), int(channel_sum))
+
+
+def layer_rotations(kind, log_n, **options):
+    """he_layer_rotations: a layer's plan (keys, plaintext counts, levels, key
+    switches, output map) from its description, host only; options as for
+    layer_plaintexts."""
+    pl = he_layer_plan()
+    _check(lib().he_layer_rotations(ctypes.byref(_layer_desc(kind, log_n, **options)), ctypes.byref(pl)))
+    return pl
+
+
 def layer_plaintexts(kind, log_n, weights=None, bias=None, fm=None, out_ch=0, kernel=0, stride=1, padding=0,
-                     n_in=0, n_out=0, beta=1.0, mask_chains=0, fc_form=0, stride_mode=0, stride_groups=0):
+                     n_in=0, n_out=0, beta=1.0, mask_chains=0, fc_form=0, stride_mode=0, stride_groups=0,
+                     channel_sum=0):
     """he_layer_plaintexts: the real slot vectors (float64 [count][N/2]) a
     layer consumes, in its plan's order (host only, no GPU needed)."""
-    d = he_layer_desc(int(kind), int(log_n), int(mask_chains), int(fc_form), fm if fm is not None else he_fmap(),
-                      int(out_ch), int(kernel), int(stride), int(padding), int(n_in), int(n_out), float(beta),
-                      int(stride_mode), int(stride_groups))
+    d = _layer_desc(kind, log_n, fm, out_ch, kernel, stride, padding, n_in, n_out, beta, mask_chains, fc_form,
+                    stride_mode, stride_groups, channel_sum)
     w = None if weights is None else np.ascontiguousarray(weights, dtype=np.float64)
     b = None if bias is None else np.ascontiguousarray(bias, dtype=np.float64)
     dp = ctypes.POINTER(ctypes.c_double)
@@ -161,6 +177,7 @@ def lib():
                           P(he_pt), P(he_ct), P(he_fmap), vp],
             "he_layer_plaintexts": [P(he_layer_desc), P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
                                     ctypes.c_size_t, P(i32)],
+            "he_layer_rotations": [P(he_layer_desc), P(he_layer_plan)],
             "he_avgpool_plan": [vp, P(he_fmap), c_int, c_int, P(he_layer_plan)],
             "he_avgpool": [vp, P(he_ct), P(he_fmap), c_int, c_int, P(he_pt), c_int, P(he_ct), P(he_fmap), vp],
             "he_fc_plan": [vp, c_int, c_int, P(he_layer_plan)],

@@ -140,3 +140,52 @@ def test_recipe_counts_follow_the_plan_and_errors():
     ext = he.layer_plaintexts(he.LAYER_AVGPOOL, 14, fm=hfm(2, 8, 8, 1), kernel=2, stride=2)
     log = he.layer_plaintexts(he.LAYER_AVGPOOL, 14, fm=hfm(2, 8, 8, 1), kernel=2, stride=2, stride_mode=1)
     assert ext.shape[0] == 4 + 4 + 2 and log.shape[0] == 2 * 2 + 4 + 2
+
+
+ROT_CASES = [  # (kind, log_n, C, H, W, reps, F, k, S, P)
+    ("conv", 12, 1, 8, 8, 1, 1, 3, 1, 1),
+    ("conv", 16, 16, 32, 32, 2, 32, 3, 2, 1),   # ResNet conv B
+    ("conv", 14, 1, 28, 28, 1, 6, 5, 1, 0),     # LeNet conv
+    ("conv", 14, 2, 8, 8, 1, 3, 3, 1, 2),       # padding by re-layout
+    ("conv", 14, 3, 16, 16, 1, 2, 7, 2, 3),
+    ("pool", 14, 6, 24, 24, 1, 0, 2, 2, 0),
+    ("pool", 16, 64, 8, 8, 1, 0, 0, 1, 0),      # global
+]
+
+
+@pytest.mark.parametrize("case", ROT_CASES, ids=lambda c: "%s_n%d_%dx%dx%d_k%d_s%d_p%d" % (c[0], c[1], c[2], c[3], c[4],
+                                                                                        c[7], c[8], c[9]))
+@pytest.mark.parametrize("opts", [(0, 0, 0, 0), (1, 1, 0, 1), (0, 0, 1, 0), (1, 0, 1, 1)],
+                         ids=["default", "bsgs_log_logsum", "groups", "bsgs_groups_logsum"])
+def test_layer_rotations_match_oracle(case, opts):
+    """he_layer_rotations (host only) lists the keys the oracle's schedule
+    uses, under every option combination, and its counts match the recipes."""
+    kind, log_n, C, H, W, reps, F, k, S, P = case
+    bsgs, slog, grp, logsum = opts
+    slots = (1 << log_n) // 2
+    fm = LY.FMap(C, H, W, reps=reps)
+    kw = dict(fm=hfm(C, H, W, reps), kernel=k, stride=S, mask_chains=bsgs, stride_mode=slog, stride_groups=grp,
+              channel_sum=logsum)
+    if kind == "conv":
+        pl = he.layer_rotations(he.LAYER_CONV, log_n, out_ch=F, padding=P, **kw)
+        want = LY.conv_rotations(fm, F, k, S, P, slots, logstep=bool(logsum), bsgs=bool(bsgs), stride_log=bool(slog),
+                                 stride_group=C if grp else 0)
+        K = synth.conv_weights(5, F, C, k, 0.1)
+        vecs = he.layer_plaintexts(he.LAYER_CONV, log_n, K, None, out_ch=F, padding=P, **kw)
+    else:
+        pl = he.layer_rotations(he.LAYER_AVGPOOL, log_n, **kw)
+        want = LY.gap_rotations(fm, bool(bsgs)) if k == 0 else LY.avgpool_rotations(fm, k, S, bool(bsgs), bool(slog))
+        vecs = he.layer_plaintexts(he.LAYER_AVGPOOL, log_n, **kw)
+    assert sorted(pl.keys()) == want
+    assert pl.n_kernel_pts + pl.n_mask_pts == vecs.shape[0]
+
+
+def test_layer_rotations_fc_and_errors():
+    pl = he.layer_rotations(he.LAYER_FC, 14, n_in=64, n_out=10)
+    assert sorted(pl.keys()) == LY.fc_rotations(64, 10) and pl.key_switches == 69 and pl.levels == 2
+    pl = he.layer_rotations(he.LAYER_FC, 14, n_in=64, n_out=10, fc_form=1)
+    assert sorted(pl.keys()) == LY.fc_diag_rotations(64) and pl.key_switches == 15
+    pl = he.layer_rotations(he.LAYER_CHEB_MASK, 16, n_in=1024, beta=4.0)
+    assert pl.n_keys == 0 and pl.n_mask_pts == 1
+    with pytest.raises(he.HEError):
+        he.layer_rotations(he.LAYER_CONV, 14, fm=hfm(1, 8, 8, 1), out_ch=1, kernel=3, channel_sum=5)

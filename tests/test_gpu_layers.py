@@ -149,14 +149,17 @@ def test_config1_log_step_striding_conv(gctx, bsgs):
     run_conv(gctx("config1"), "config1", X, K, LY.FMap(3, 12, 12), 2, 1, 34, bsgs=bsgs, streams=(1, 2), slog=True)
 
 
-@pytest.mark.parametrize("slog", [False, True], ids=["extract", "logstride"])
-def test_config1_grouped_striding_conv(gctx, slog):
+@pytest.mark.parametrize("slog,bsgs", [(False, False), (True, False), (True, True)],
+                         ids=["extract", "logstride", "logstride_bsgs"])
+def test_config1_grouped_striding_conv(gctx, slog, bsgs):
     """The paper's multi-channel striding pipeline (groups of the layer's 2
     input channels: 2 + 2 + 1 of the 5 outputs, merged with one more key):
-    generic 3x3 / stride 2 / pad 1 at N=2^14, bit for bit against the oracle."""
+    generic 3x3 / stride 2 / pad 1 at N=2^14, with both striding approaches
+    and baby-step giant-step chains, bit for bit against the oracle."""
     X = synth.image(36, 2, 12, 12)
     K = synth.conv_weights(36, 5, 2, 3, 0.2)
-    run_conv(gctx("config1"), "config1", X, K, LY.FMap(2, 12, 12), 2, 1, 36, streams=(1, 2), slog=slog, groups=True)
+    run_conv(gctx("config1"), "config1", X, K, LY.FMap(2, 12, 12), 2, 1, 36, streams=(1, 2), slog=slog, groups=True,
+             bsgs=bsgs)
 
 
 def test_config1_grouped_striding_special_conv(gctx):

@@ -32,6 +32,10 @@ import numpy as np
 from . import _lib as C
 
 RELIN = "relin"
+# key id of the conjugation key (Galois element 2N - 1: every slot is
+# replaced by its complex conjugate); bootstrapping needs it to split the
+# real and imaginary parts of a coefficient-to-slot result
+CONJ = "conj"
 
 
 # --------------------------------------------------------------------- primes
@@ -81,6 +85,28 @@ def min_root(q, n):
         if cur < best:
             best = cur
     return best
+
+
+def sparse_ternary(seed, stream, n, h):
+    """Ternary secret with exactly h nonzero coefficients: positions are the
+    first h distinct values of a stream of uniform draws modulo n, signs a
+    second stream of uniform bits (1 -> +1, 0 -> -1).  Both streams come from
+    the seeded generator the rest of the sampling uses."""
+    draws = C.sample_uniform(seed, stream, [n], 8 * h + 64)[0]
+    pos, seen = [], set()
+    for d in draws:
+        d = int(d)
+        if d not in seen:
+            seen.add(d)
+            pos.append(d)
+            if len(pos) == h:
+                break
+    if len(pos) != h:
+        raise ValueError("hamming weight too large for the ring")
+    bits = C.sample_uniform(seed, stream + 1, [2], h)[0]
+    s = np.zeros(n, dtype=np.int64)
+    s[pos] = np.where(bits == 1, 1, -1)
+    return s
 
 
 # --------------------------------------------------------------------- params
@@ -221,6 +247,44 @@ class Context:
         assert np.all(np.abs(r) < 2.0 ** 62)
         return r.astype(np.int64)
 
+    def encode_coeffs_complex(self, values, scale):
+        """Complex slot vector z (N/2 slots) -> integer coefficients
+        llround(scale * m_k), m_k = (2/N) Re(sum_j z_j zeta^(-5^j k)): the
+        inverse canonical embedding of (z, conj(z)) at the exponents
+        (5^j, -5^j).  For real z this is encode_coeffs."""
+        n = self.n
+        v = np.zeros(n // 2, dtype=np.complex128)
+        vals = np.asarray(values, dtype=np.complex128).ravel()
+        assert vals.size <= n // 2
+        v[: vals.size] = vals
+        e = self.slot_exponents()
+        z = np.zeros(2 * n, dtype=np.complex128)
+        z[e] = v
+        z[(2 * n - e) % (2 * n)] = np.conj(v)
+        m = np.fft.fft(z)[:n].real / n
+        x = m * scale
+        r = np.where(x >= 0, np.floor(x + 0.5), -np.floor(-x + 0.5))
+        assert np.all(np.abs(r) < 2.0 ** 62)
+        return r.astype(np.int64)
+
+    def encode_complex(self, values, scale, level):
+        """encode() for a complex slot vector."""
+        coeffs = self.encode_coeffs_complex(values, scale)
+        rns = C.from_signed(coeffs, self.qs(level))
+        return Plaintext(self.ntt(rns, self.qs(level), self.psis(level)), scale)
+
+    def decode_coeffs_complex(self, m, scale):
+        """Integer (float64) coefficients -> complex slot values
+        z_j = sum_k m_k zeta^(5^j k) / scale."""
+        n = self.n
+        pad = np.zeros(2 * n, dtype=np.complex128)
+        pad[:n] = m
+        w = np.fft.ifft(pad) * (2 * n)
+        return w[self.slot_exponents()] / scale
+
+    def decrypt_complex(self, sk, ct):
+        return self.decode_coeffs_complex(self.decrypt_coeffs(sk, ct), ct.scale)
+
     def encode(self, values, scale, level):
         """Encode to an RNS plaintext in NTT form over q_0..q_{level-1}."""
         coeffs = self.encode_coeffs(values, scale)
@@ -247,9 +311,13 @@ class Context:
         return w[self.slot_exponents()].real / scale
 
     # ---- keys (client side)
-    def keygen(self, seed):
+    def keygen(self, seed, hamming=0):
+        """Secret, public key.  hamming = 0: uniform ternary secret; else a
+        sparse ternary secret with exactly `hamming` nonzero coefficients
+        (bootstrapping's choice: it bounds the multiple of q_0 that ModRaise
+        adds, see ``sparse_ternary``)."""
         pr = self.pr
-        s = C.sample_ternary(seed, 1, self.n)
+        s = sparse_ternary(seed, 1, self.n, hamming) if hamming else C.sample_ternary(seed, 1, self.n)
         s_ntt = self.ntt(C.from_signed(s, pr.moduli), pr.moduli, pr.psi)
         sk = SecretKey(s, s_ntt)
         a = C.sample_uniform(seed, 2, pr.q, self.n)
@@ -283,13 +351,19 @@ class Context:
         return key
 
     def galois_element(self, r):
-        """Rot_r (slot i <- slot i + r) is X -> X^g with g = 5^(r mod N/2) mod 2N."""
+        """Rot_r (slot i <- slot i + r) is X -> X^g with g = 5^(r mod N/2) mod 2N;
+        the conjugation (r = CONJ) is X -> X^(2N-1)."""
+        if r == CONJ:
+            return 2 * self.n - 1
         return pow(5, r % (self.n // 2), 2 * self.n)
 
     def gen_rotation_key(self, sk, r, seed):
+        """Key switching from phi_g(s) to s for Rot_r, or for the conjugation
+        when r = CONJ (its sampling stream follows every rotation's)."""
         g = self.galois_element(r)
         s_rot = sk.s_ntt[: self.pr.L][:, self.perm(g)]
-        return self.gen_switch_key(sk, s_rot, seed, 10 + (r % (self.n // 2)))
+        stream = 10 + (self.n // 2 if r == CONJ else r % (self.n // 2))
+        return self.gen_switch_key(sk, s_rot, seed, stream)
 
     def gen_relin_key(self, sk, seed):
         sq = C.mul(sk.s_ntt[: self.pr.L], sk.s_ntt[: self.pr.L], self.pr.q)

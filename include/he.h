@@ -58,6 +58,9 @@ extern "C" {
 #define HE_MAX_Q 60
 #define HE_MAX_P 16
 #define HE_KEY_RELIN ((int32_t)0x7fffffff) /* key id of the relinearization key */
+/* key id of the conjugation key (Galois element 2N - 1: every slot becomes
+ * its complex conjugate); he_rotate with r = HE_KEY_CONJ conjugates */
+#define HE_KEY_CONJ ((int32_t)0x7ffffffe)
 
 typedef struct he_ctx he_ctx;
 typedef void* he_stream; /* hipStream_t */
@@ -249,6 +252,22 @@ int he_drop_level(he_ctx* ctx, const he_ct* in, int level, he_ct* out, he_stream
 int he_mul_relin(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct* out, he_stream stream);
 /* Relinearize a 3-part ciphertext d ([3][level][N], device) into out. */
 int he_relin(he_ctx* ctx, const uint64_t* d, int level, double scale, he_ct* out, he_stream stream);
+
+/* Multiply every slot by i (sign = +1: the monomial X^(N/2), whose slot
+ * values zeta^(5^j N/2) are all i) or by -i (sign = -1: -X^(N/2)).  Exact:
+ * in NTT form the monomial is +-psi^(N/2) per limb (the sign flips between
+ * the two halves of the bit-reversed order); level and scale unchanged.
+ * out may alias in. */
+int he_mul_i(he_ctx* ctx, const he_ct* in, int sign, he_ct* out, he_stream stream);
+
+/* ModRaise, bootstrapping's first step: limb 0 of `in` (residues mod q_0)
+ * read as integers centred in (-q_0/2, q_0/2] (coefficient a in [0, q_0)
+ * taken as a - q_0 when a > (q_0 - 1)/2) and reduced modulo q_0..q_{level-1}:
+ * inverse transform of limb 0, the lift, forward transform of `level` limbs.
+ * The result encrypts m + q_0 I for a small integer polynomial I (|I| at
+ * most (h + 1)/2 for a secret of h nonzero ternary coefficients); limb 0 is
+ * unchanged, the scale is in.scale.  1 <= level <= L; out must not alias in. */
+int he_mod_raise(he_ctx* ctx, const he_ct* in, int level, he_ct* out, he_stream stream);
 
 /* Multiply by a real constant c encoded at `scale` as the constant
  * polynomial llround(c * scale) (ties away from zero); out.scale =
@@ -533,6 +552,79 @@ int he_cheb_plan(const double* coeffs, int degree, int masked, int32_t* levels, 
  * and the other odd coefficients are exactly 0.  The paper's default
  * degree is 59.  Host only; `coeffs` holds degree + 1 doubles. */
 int he_cheb_relu_coeffs(double beta, int degree, double* coeffs);
+
+/* ------------------------------------------------------------ bootstrapping
+ * The paper's bootstrapping support function (Section "FHEON's Support
+ * Functions"; its deep models refresh ciphertexts between layers), which it
+ * takes from its CPU library without describing it.  Here the standard
+ * four stages, each a composition of the calls above:
+ *  1. ModRaise (he_mod_raise) of limb 0 to level `level` (0: L); the result,
+ *     t = m + q_0 I, is relabelled 2^e delta with e the smallest integer such
+ *     that 2^e delta >= 2 q_0 k_min (k_min bounds |I| + 1/2); the EvalMod
+ *     range is then K = 2^e delta / (2 q_0).
+ *  2. CoeffToSlot: the inverse of the slot decoding map (evaluation at
+ *     zeta^(5^j)) as log2(N/2) radix-2 butterfly stages, h = N/4 .. 1,
+ *     grouped into `levels` levels (as even as possible, larger first).
+ *     Each level is a sum of diagonals D_d (.) Rot_d(x) evaluated baby-step
+ *     giant-step: the shifts are multiples of the level's smallest stage u,
+ *     d = u k with k centred modulo N/(2u), k = i + B j with B the smallest
+ *     power of two with B^2 >= kmax - kmin + 1; baby rotations Rot_{u i}
+ *     (one hoisted set), for each giant j ascending
+ *     s_j = RS(sum_i pt_{j,i} (.) Rot_{u i}(x)), rotated by u B j when j != 0,
+ *     summed.  pt_{j,i} holds D_{u(i+Bj)} rotated by -u B j.  The output
+ *     holds (t_lo + i t_hi) / (2 q_0 K) in bit-reversed slot order.
+ *  3. EvalMod: w = conj(x) (HE_KEY_CONJ); re = x + w; im = -i (x - w);
+ *     each through he_cheb (no mask, output scale delta) with the Chebyshev
+ *     interpolant of sin(2 pi K x) / (2 pi) (he_boot_mod_coeffs), which
+ *     removes q_0 I and leaves about m / q_0; z = re + i im.
+ *  4. SlotToCoeff: the forward stages h = 1 .. N/4 (CoeffToSlot's groups
+ *     mirrored), same evaluation; the result is relabelled
+ *     scale(z) * in.scale / q_0 and decrypts to the input's message.
+ * Plaintext scales: CoeffToSlot level g (at level - g) encodes its
+ * plaintexts at q 2^-e_g, SlotToCoeff level g (at its level l) at
+ * q 2^f_g, q the prime that level's rescale removes; e_g split e and f_g
+ * split round(log2(q_0 / delta)) as evenly as possible, larger first
+ * (he_boot_scales).  Levels consumed: 2 levels + he_cheb_plan's count.
+ * Key switches: the transforms' rotations (he_boot_plan), one
+ * conjugation and he_cheb's relinearizations twice. */
+typedef struct {
+  int32_t levels;  /* levels per linear transform, 1..log2(N/2) */
+  int32_t degree;  /* EvalMod Chebyshev degree, 1..HE_CHEB_MAX_DEGREE */
+  int32_t level;   /* ModRaise target level (0: L) */
+  double k_min;    /* bound on |I| + 1/2 */
+  double delta;    /* EvalMod input and output scale */
+} he_boot_desc;
+
+#define HE_BOOT_MAX_ROTATIONS 256
+/* Plan of the two linear transforms for N = 2^log_n and `levels` levels
+ * (host only): the distinct rotation amounts (in [1, N/2), ascending) both
+ * transforms use, and the plaintext count of each level in application
+ * order (CoeffToSlot then SlotToCoeff, `levels` each).  rotations holds
+ * HE_BOOT_MAX_ROTATIONS entries, counts 2 * levels. */
+int he_boot_plan(int32_t log_n, int32_t levels, int32_t* rotations, int32_t* n_rotations, int32_t* counts);
+/* The plaintext slot vectors (complex, N/2 slots each, real parts in re,
+ * imaginary parts in im) of one transform (inverse = 1: CoeffToSlot, 0:
+ * SlotToCoeff) in consumption order: level by level, giant j ascending,
+ * baby i ascending (pt_{j,i} above).  Pure butterfly products (no scale
+ * constant); `cap` = doubles available in each of re, im (host only). */
+int he_boot_diagonals(int32_t log_n, int32_t levels, int32_t inverse, double* re, double* im, size_t cap);
+/* Chebyshev coefficients c_0..c_degree of sin(2 pi K x) / (2 pi) on [-1, 1]
+ * interpolated at the degree + 1 first-kind nodes (even ones exactly 0). */
+int he_boot_mod_coeffs(double K, int32_t degree, double* coeffs);
+/* For a context and description: the EvalMod range K, the raise label
+ * 2^e delta, and the plaintext scales of every CoeffToSlot and SlotToCoeff
+ * level (`levels` doubles each) at the levels the procedure uses them. */
+int he_boot_scales(const he_ctx* ctx, const he_boot_desc* desc, double* K, double* raise_scale, double* cts_scales,
+                   double* stc_scales);
+/* Refresh `in` (any level; limb 0 is used).  cts_pts, stc_pts: the
+ * plaintexts of he_boot_diagonals encoded at he_boot_scales (level g of
+ * CoeffToSlot at level - g, SlotToCoeff level g at the level it is applied
+ * at); coeffs: he_boot_mod_coeffs(K, degree).  Needs the rotation keys of
+ * he_boot_plan, HE_KEY_CONJ and HE_KEY_RELIN.  out gets level
+ * level - 2 levels - he_cheb_plan levels.  HE_ELEVEL when the chain is too
+ * short, HE_ENOKEY for a missing key. */
+int he_bootstrap(he_ctx* ctx, const he_ct* in, const he_boot_desc* desc, const he_pt* cts_pts, const he_pt* stc_pts,
+                 const double* coeffs, he_ct* out, he_stream stream);
 
 /* ------------------------------------------------------------ batching
  * Many ciphertexts, each with its own hoisted rotation set and its own

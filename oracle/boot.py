@@ -199,7 +199,7 @@ class LevelPlan:
         """Rotation amounts (mod n) the level uses: baby steps, then giant steps."""
         rots = {self.baby_rot(i) for i in self.babies}
         rots |= {self.giant_rot(j) for j, _ in self.giants if j != 0}
-        return rots
+        return rots - {0}
 
     def count(self):
         return sum(len(t) for _, t in self.giants)
@@ -298,7 +298,7 @@ class BootPlan:
         round(log2(q_0 / delta)) split as evenly as possible, so that the
         result's scale label comes back near the input's (EvalMod returns
         m / q_0 at scale delta)."""
-        f = int(round(math.log2(float(q0) / self.delta)))
+        f = int(math.floor(math.log2(float(q0) / self.delta) + 0.5))
         return group_sizes(f, self.levels) if f > 0 else [0] * self.levels
 
     def mod_coeffs(self, q0):

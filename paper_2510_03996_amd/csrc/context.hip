@@ -97,7 +97,7 @@ LimbMap ext_map(const Ctx* c, int level) {
 }
 
 int32_t norm_key_id(const Ctx* c, int32_t id) {
-  if (id == HE_KEY_RELIN) return id;
+  if (id == HE_KEY_RELIN || id == HE_KEY_CONJ) return id;
   int32_t h = c->n / 2;
   int32_t r = id % h;
   return r < 0 ? r + h : r;
@@ -105,8 +105,11 @@ int32_t norm_key_id(const Ctx* c, int32_t id) {
 
 uint32_t galois_elt(const Ctx* c, int32_t r) {
   uint64_t two_n = 2 * (uint64_t)c->n;
+  if (r == HE_KEY_CONJ) return (uint32_t)(two_n - 1);
   return (uint32_t)hpow(5, (uint64_t)norm_key_id(c, r), two_n);
 }
+
+uint64_t omega4(const Ctx* c, int m) { return hpow(c->psi[m], (uint64_t)c->n / 2, c->mod[m]); }
 
 template <class T>
 static int dev_alloc(Ctx* c, T** p, size_t count) {

@@ -352,6 +352,9 @@ __global__ void k_to_mont(uint64_t* key, int M, int logn, const ModInfo* __restr
 
 int32_t norm_key_id(const Ctx* c, int32_t id);
 uint32_t galois_elt(const Ctx* c, int32_t r);
+// psi_m^(N/2) mod q_m: a primitive fourth root of unity, the NTT value of
+// X^(N/2) at the first half of the bit-reversed positions
+uint64_t omega4(const Ctx* c, int m);
 
 }  // namespace he
 

@@ -13,7 +13,9 @@
 //   pooling / global pooling / FC / polynomial activation as documented in he.h.
 // Every multiplicative level is rescaled once, after its last addition and
 // before any rotation consumes it.
+#include <algorithm>
 #include <cmath>
+#include <complex>
 #include <vector>
 
 #include "internal.h"
@@ -1602,6 +1604,446 @@ int he_cheb(he_ctx* h, const he_ct* in, const he_pt* scale_mask, const double* c
       y = cheb_eval_node(ev, tree, 0, T, top, delta);
     }
     ev.copy_out(y, out);
+    return HE_OK;
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- bootstrapping
+// The standard four-stage RNS-CKKS bootstrapping (ModRaise, CoeffToSlot,
+// EvalMod, SlotToCoeff) composed of the calls above; every choice is the
+// one he.h documents (plan, scales, rescale placement), so that the
+// composition is bit-exact against a CPU definition of the same steps.
+namespace he {
+
+// stages per level: as even as possible, larger groups first
+static std::vector<int> boot_group_sizes(int total, int levels) {
+  std::vector<int> g(levels, total / levels);
+  for (int i = 0; i < total % levels; i++) g[i]++;
+  return g;
+}
+
+// block half-sizes h of each level in application order: CoeffToSlot runs
+// the inverse stages h = n/2 .. 1, SlotToCoeff the forward ones h = 1 .. n/2
+// (CoeffToSlot's groups mirrored)
+static std::vector<std::vector<int>> boot_groups(int log_slots, int levels, bool inverse) {
+  std::vector<std::vector<int>> out;
+  int at = log_slots - 1;
+  for (int sz : boot_group_sizes(log_slots, levels)) {
+    std::vector<int> hs;
+    for (int t = 0; t < sz; t++) hs.push_back(1 << at--);
+    out.push_back(hs);
+  }
+  if (!inverse) {
+    std::reverse(out.begin(), out.end());
+    for (auto& g : out) std::reverse(g.begin(), g.end());
+  }
+  return out;
+}
+
+static long long floor_div(long long a, long long b) { return a / b - ((a % b != 0) && ((a < 0) != (b < 0))); }
+
+// Baby-step giant-step layout of one level: shifts d = u k (k centred mod
+// n/u), k = i + B j, B the smallest power of two with B^2 >= span.
+struct BootLevel {
+  int n = 0, u = 1, B = 1;
+  std::vector<int> babies;  // i > 0 used, ascending
+  std::vector<std::pair<int, std::vector<std::pair<int, int>>>> giants;  // j ascending: (i, shift mod n)
+  int count() const {
+    int c = 0;
+    for (auto& g : giants) c += (int)g.second.size();
+    return c;
+  }
+  int baby_rot(int i) const { return (int)(((long long)u * i) % n); }
+  int giant_rot(int j) const {
+    long long r = ((long long)u * B * j) % n;
+    return (int)(r < 0 ? r + n : r);
+  }
+};
+
+// the level's shifts: every sum of +-h or 0 over its stages (mod n), which
+// is where the product of the butterfly stages has nonzero diagonals
+static BootLevel boot_level(int n, const std::vector<int>& hs) {
+  std::vector<char> have(n, 0), next(n, 0);
+  have[0] = 1;
+  for (int h : hs) {
+    std::fill(next.begin(), next.end(), 0);
+    for (int d = 0; d < n; d++)
+      if (have[d]) {
+        next[d] = 1;
+        next[(d + h) % n] = 1;
+        next[((d - h) % n + n) % n] = 1;
+      }
+    have.swap(next);
+  }
+  BootLevel p;
+  p.n = n;
+  p.u = *std::min_element(hs.begin(), hs.end());
+  const int m = n / p.u;
+  std::vector<int> ks;
+  for (int d = 0; d < n; d++)
+    if (have[d]) {
+      int k = (d / p.u) % m;
+      if (k > m / 2) k -= m;
+      ks.push_back(k);
+    }
+  std::sort(ks.begin(), ks.end());
+  const int span = ks.back() - ks.front() + 1;
+  while (p.B * p.B < span) p.B *= 2;
+  std::map<int, std::vector<std::pair<int, int>>> by_j;
+  for (int k : ks) {
+    const int j = (int)floor_div(k, p.B), i = k - p.B * j;
+    by_j[j].push_back({i, (int)((((long long)p.u * k) % n + n) % n)});
+  }
+  std::vector<char> used(p.B, 0);
+  for (auto& kv : by_j) {
+    std::sort(kv.second.begin(), kv.second.end());
+    for (auto& t : kv.second) used[t.first] = 1;
+    p.giants.push_back(kv);
+  }
+  for (int i = 1; i < p.B; i++)
+    if (used[i]) p.babies.push_back(i);
+  return p;
+}
+
+struct BootPlanC {
+  int n = 0;
+  std::vector<std::vector<int>> cts_hs, stc_hs;
+  std::vector<BootLevel> cts, stc;
+};
+
+static int boot_plan_make(int log_n, int levels, BootPlanC* out) {
+  if (log_n < 2 || log_n > 16) return set_error(HE_EINVAL, "ring degree out of range");
+  const int ls = log_n - 1;
+  if (levels < 1 || levels > ls) return set_error(HE_EINVAL, "transform levels out of range");
+  out->n = 1 << ls;
+  out->cts_hs = boot_groups(ls, levels, true);
+  out->stc_hs = boot_groups(ls, levels, false);
+  out->cts.clear();
+  out->stc.clear();
+  for (auto& hs : out->cts_hs) out->cts.push_back(boot_level(out->n, hs));
+  for (auto& hs : out->stc_hs) out->stc.push_back(boot_level(out->n, hs));
+  return HE_OK;
+}
+
+// diagonals of one butterfly stage / of a product of diagonal matrices
+using Cd = std::complex<double>;
+using Diags = std::map<int, std::vector<Cd>>;
+
+static Cd slot_root(int m, int j) {
+  uint64_t e = 1;
+  for (int t = 0; t < j; t++) e = e * 5 % (4 * (uint64_t)m);
+  return std::polar(1.0, 2.0 * M_PI * (double)e / (4.0 * m));
+}
+
+static void diag_put(Diags& d, int shift, const std::vector<Cd>& v) {
+  auto it = d.find(shift);
+  if (it == d.end()) {
+    d[shift] = v;
+  } else {
+    for (size_t p = 0; p < v.size(); p++) it->second[p] += v[p];
+  }
+}
+
+static Diags stage_diags(int n, int h, bool inverse) {
+  std::vector<Cd> roots(h);
+  for (int j = 0; j < h; j++) roots[j] = slot_root(2 * h, j);
+  std::vector<Cd> d0(n), dp(n), dm(n);
+  for (int p = 0; p < n; p++) {
+    const int r = p % (2 * h);
+    const bool first = r < h;
+    const Cd x = roots[first ? r : r - h];
+    if (inverse) {
+      d0[p] = first ? Cd(0.5, 0.0) : -0.5 / x;
+      dp[p] = first ? Cd(0.5, 0.0) : Cd(0.0, 0.0);
+      dm[p] = first ? Cd(0.0, 0.0) : 0.5 / x;
+    } else {
+      d0[p] = first ? Cd(1.0, 0.0) : -x;
+      dp[p] = first ? x : Cd(0.0, 0.0);
+      dm[p] = first ? Cd(0.0, 0.0) : Cd(1.0, 0.0);
+    }
+  }
+  Diags out;
+  out[0] = d0;
+  diag_put(out, h % n, dp);
+  diag_put(out, ((-h) % n + n) % n, dm);
+  return out;
+}
+
+// A B (B applied first): C_{d+e}[p] += A_d[p] B_e[(p + d) mod n]
+static Diags diag_compose(const Diags& a, const Diags& b, int n) {
+  Diags out;
+  std::vector<Cd> t(n);
+  for (auto& da : a)
+    for (auto& db : b) {
+      for (int p = 0; p < n; p++) t[p] = da.second[p] * db.second[(p + da.first) % n];
+      diag_put(out, (da.first + db.first) % n, t);
+    }
+  return out;
+}
+
+// CoeffToSlot's EvalMod range K and raise exponent e for a context
+static void boot_raise(const Ctx* c, const he_boot_desc* d, int* e, double* K, double* raise) {
+  const double q0 = (double)c->mod[0];
+  const double bound = 2.0 * q0 * d->k_min;
+  int x = 0;
+  while (std::ldexp(d->delta, x) < bound) x++;
+  *e = x;
+  *raise = std::ldexp(d->delta, x);
+  *K = *raise / (2.0 * q0);
+}
+
+static void boot_mod_coeffs_impl(double K, int degree, double* cf) {
+  const int n = degree + 1;
+  std::vector<double> th(n), fx(n);
+  for (int k = 0; k < n; k++) {
+    th[k] = M_PI * (k + 0.5) / n;
+    fx[k] = std::sin(2.0 * M_PI * K * std::cos(th[k])) / (2.0 * M_PI);
+  }
+  for (int j = 0; j < n; j++) {
+    double s = 0.0;
+    for (int k = 0; k < n; k++) s += fx[k] * std::cos(j * th[k]);
+    cf[j] = (j % 2 == 0) ? 0.0 : 2.0 / n * s;
+  }
+}
+
+// levels, plaintext scales and the Chebyshev level count for a context
+struct BootScales {
+  int level_in = 0, cheb_levels = 0, cheb_relins = 0, e = 0;
+  double K = 0, raise = 0;
+  std::vector<double> cts, stc;
+};
+
+static int boot_scales_impl(const Ctx* c, const he_boot_desc* d, BootScales* s) {
+  if (!d) return set_error(HE_EINVAL, "null description");
+  if (d->levels < 1 || d->levels > c->log_n - 1) return set_error(HE_EINVAL, "transform levels out of range");
+  if (d->degree < 1 || d->degree > HE_CHEB_MAX_DEGREE) return set_error(HE_EINVAL, "EvalMod degree out of range");
+  if (!(d->k_min > 0.0) || !(d->delta > 1.0)) return set_error(HE_EINVAL, "k_min and delta must be positive");
+  s->level_in = d->level ? d->level : c->L;
+  if (s->level_in < 1 || s->level_in > c->L) return set_error(HE_ELEVEL, "raise level out of range");
+  boot_raise(c, d, &s->e, &s->K, &s->raise);
+  std::vector<double> cf(d->degree + 1);
+  boot_mod_coeffs_impl(s->K, d->degree, cf.data());
+  int rc;
+  if ((rc = cheb_plan_impl(cf.data(), d->degree, 0, &s->cheb_levels, &s->cheb_relins))) return rc;
+  const int out_level = s->level_in - 2 * d->levels - s->cheb_levels;
+  if (out_level < 1)
+    return set_error(HE_ELEVEL, "bootstrapping needs " + std::to_string(2 * d->levels + s->cheb_levels + 1) +
+                                    " levels");
+  const std::vector<int> ex = boot_group_sizes(s->e, d->levels);
+  const double f2 = std::log2((double)c->mod[0] / d->delta);
+  const int f = (int)std::floor(f2 + 0.5);
+  const std::vector<int> fx = f > 0 ? boot_group_sizes(f, d->levels) : std::vector<int>(d->levels, 0);
+  s->cts.resize(d->levels);
+  s->stc.resize(d->levels);
+  for (int g = 0; g < d->levels; g++) {
+    s->cts[g] = std::ldexp((double)c->mod[s->level_in - g - 1], -ex[g]);
+    const int l = s->level_in - d->levels - s->cheb_levels - g;
+    s->stc[g] = std::ldexp((double)c->mod[l - 1], fx[g]);
+  }
+  return HE_OK;
+}
+
+// y = sum_d D_d (.) Rot_d(x) by baby-step giant-step (pts in consumption order)
+static he_ct boot_transform(Ev& ev, const he_ct& x, const BootLevel& p, const he_pt* pts) {
+  std::vector<int> rots;
+  for (int i : p.babies) rots.push_back(p.baby_rot(i));
+  std::vector<he_ct> br = ev.rot_hoisted(x, rots);
+  std::vector<he_ct> baby(p.B);
+  baby[0] = x;
+  for (size_t t = 0; t < p.babies.size(); t++) baby[p.babies[t]] = br[t];
+  he_ct acc{};
+  bool have = false;
+  int t = 0;
+  for (auto& g : p.giants) {
+    he_ct s = ev.mul(baby[g.second[0].first], pts[t++]);
+    for (size_t q = 1; q < g.second.size(); q++) ev.mac(s, baby[g.second[q].first], pts[t++]);
+    s = ev.rescale_take(s);
+    if (g.first != 0) s = ev.rot_take(s, p.giant_rot(g.first));
+    if (!have) {
+      acc = s;
+      have = true;
+    } else {
+      acc = ev.add_take(acc, s);
+    }
+  }
+  for (auto& b : br) ev.release(b);
+  return acc;
+}
+
+}  // namespace he
+
+extern "C" {
+
+int he_boot_plan(int32_t log_n, int32_t levels, int32_t* rotations, int32_t* n_rotations, int32_t* counts) {
+  if (!rotations || !n_rotations || !counts) return set_error(HE_EINVAL, "null argument");
+  BootPlanC p;
+  int rc;
+  if ((rc = boot_plan_make(log_n, levels, &p))) return rc;
+  std::vector<int> r;
+  for (const auto* side : {&p.cts, &p.stc})
+    for (const BootLevel& lv : *side) {
+      for (int i : lv.babies) r.push_back(lv.baby_rot(i));
+      for (auto& g : lv.giants)
+        if (g.first != 0) r.push_back(lv.giant_rot(g.first));
+    }
+  std::sort(r.begin(), r.end());
+  r.erase(std::unique(r.begin(), r.end()), r.end());
+  r.erase(std::remove(r.begin(), r.end(), 0), r.end());
+  if ((int)r.size() > HE_BOOT_MAX_ROTATIONS) return set_error(HE_EUNSUPPORTED, "too many rotation keys");
+  for (size_t i = 0; i < r.size(); i++) rotations[i] = r[i];
+  *n_rotations = (int32_t)r.size();
+  for (int g = 0; g < levels; g++) {
+    counts[g] = p.cts[g].count();
+    counts[levels + g] = p.stc[g].count();
+  }
+  return HE_OK;
+}
+
+int he_boot_diagonals(int32_t log_n, int32_t levels, int32_t inverse, double* re, double* im, size_t cap) {
+  if (!re || !im) return set_error(HE_EINVAL, "null argument");
+  BootPlanC p;
+  int rc;
+  if ((rc = boot_plan_make(log_n, levels, &p))) return rc;
+  const int n = p.n;
+  const auto& hs_all = inverse ? p.cts_hs : p.stc_hs;
+  const auto& plans = inverse ? p.cts : p.stc;
+  size_t total = 0;
+  for (auto& lv : plans) total += (size_t)lv.count() * n;
+  if (cap < total) return set_error(HE_EINVAL, "output too small for the diagonals");
+  try {
+    size_t at = 0;
+    for (size_t g = 0; g < plans.size(); g++) {
+      Diags m;
+      m[0] = std::vector<Cd>(n, Cd(1.0, 0.0));
+      for (int h : hs_all[g]) m = diag_compose(stage_diags(n, h, inverse != 0), m, n);
+      const BootLevel& lv = plans[g];
+      for (auto& gj : lv.giants) {
+        const long long sh = (long long)lv.u * lv.B * gj.first;  // pre-rotation: D[p - u B j]
+        for (auto& t : gj.second) {
+          auto it = m.find(t.second);
+          for (int q = 0; q < n; q++) {
+            Cd v(0.0, 0.0);
+            if (it != m.end()) v = it->second[(size_t)((((q - sh) % n) + n) % n)];
+            re[at + q] = v.real();
+            im[at + q] = v.imag();
+          }
+          at += n;
+        }
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    return set_error(HE_ENOMEM, "host allocation failed");
+  }
+  return HE_OK;
+}
+
+int he_boot_mod_coeffs(double K, int32_t degree, double* coeffs) {
+  if (!coeffs) return set_error(HE_EINVAL, "null argument");
+  if (degree < 1 || degree > HE_CHEB_MAX_DEGREE) return set_error(HE_EINVAL, "degree out of range");
+  if (!(K > 0.0)) return set_error(HE_EINVAL, "K must be positive");
+  boot_mod_coeffs_impl(K, degree, coeffs);
+  return HE_OK;
+}
+
+int he_boot_scales(const he_ctx* h, const he_boot_desc* desc, double* K, double* raise_scale, double* cts_scales,
+                   double* stc_scales) {
+  if (!h || !K || !raise_scale || !cts_scales || !stc_scales) return set_error(HE_EINVAL, "null argument");
+  BootScales s;
+  int rc;
+  if ((rc = boot_scales_impl(&h->c, desc, &s))) return rc;
+  *K = s.K;
+  *raise_scale = s.raise;
+  for (int g = 0; g < desc->levels; g++) {
+    cts_scales[g] = s.cts[g];
+    stc_scales[g] = s.stc[g];
+  }
+  return HE_OK;
+}
+
+int he_bootstrap(he_ctx* h, const he_ct* in, const he_boot_desc* desc, const he_pt* cts_pts, const he_pt* stc_pts,
+                 const double* coeffs, he_ct* out, he_stream s) {
+  if (!h || !coeffs) return set_error(HE_EINVAL, "null argument");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in"))) return rc;
+  BootScales sc;
+  if ((rc = boot_scales_impl(c, desc, &sc))) return rc;
+  BootPlanC p;
+  if ((rc = boot_plan_make(c->log_n, desc->levels, &p))) return rc;
+  const int levels = desc->levels;
+  const int out_level = sc.level_in - 2 * levels - sc.cheb_levels;
+  if ((rc = check_out(c, out, out_level))) return rc;
+  if (out->data == in->data) return set_error(HE_EINVAL, "bootstrapping output aliases the input");
+  // plaintexts: CoeffToSlot level g at level_in - g, SlotToCoeff level g at
+  // the level it is applied at
+  {
+    int at = 0;
+    for (int g = 0; g < levels; g++) {
+      if ((rc = check_pts(c, cts_pts ? cts_pts + at : nullptr, p.cts[g].count(), sc.level_in - g, "cts_pts")))
+        return rc;
+      at += p.cts[g].count();
+    }
+    at = 0;
+    for (int g = 0; g < levels; g++) {
+      const int l = sc.level_in - levels - sc.cheb_levels - g;
+      if ((rc = check_pts(c, stc_pts ? stc_pts + at : nullptr, p.stc[g].count(), l, "stc_pts"))) return rc;
+      at += p.stc[g].count();
+    }
+  }
+  for (const auto* side : {&p.cts, &p.stc})
+    for (const BootLevel& lv : *side) {
+      for (int i : lv.babies)
+        if (lv.baby_rot(i) != 0 && !key_known(c, lv.baby_rot(i)))
+          return set_error(HE_ENOKEY, "bootstrapping rotation key missing");
+      for (auto& g : lv.giants)
+        if (g.first != 0 && lv.giant_rot(g.first) != 0 && !key_known(c, lv.giant_rot(g.first)))
+          return set_error(HE_ENOKEY, "bootstrapping rotation key missing");
+    }
+  if (!key_known(c, HE_KEY_CONJ)) return set_error(HE_ENOKEY, "conjugation key not resident");
+  if (!key_known(c, HE_KEY_RELIN)) return set_error(HE_ENOKEY, "relinearization key not resident");
+  const double q0 = (double)c->mod[0];
+  const double in_scale = in->scale;
+  return guarded([&] {
+    Ev ev(h, s);
+    const he_ct in1{in->data, 1, in->cap, in->scale};
+    he_ct x = ev.fresh();
+    ck(he_mod_raise(h, &in1, sc.level_in, &x, s));
+    x.scale = sc.raise;
+    int at = 0;
+    for (int g = 0; g < levels; g++) {
+      he_ct y = boot_transform(ev, x, p.cts[g], cts_pts + at);
+      at += p.cts[g].count();
+      ev.release(x);
+      x = y;
+    }
+    // EvalMod on the real and imaginary parts
+    he_ct w = ev.rot(x, HE_KEY_CONJ);
+    he_ct re = ev.add(x, w);
+    he_ct df = ev.fresh();
+    ck(he_sub(h, &x, &w, &df, s));
+    ev.release(w);
+    ev.release(x);
+    he_ct im = ev.fresh();
+    ck(he_mul_i(h, &df, -1, &im, s));
+    ev.release(df);
+    he_ct re2 = ev.fresh(), im2 = ev.fresh();
+    ck(he_cheb(h, &re, nullptr, coeffs, desc->degree, desc->delta, &re2, s));
+    ck(he_cheb(h, &im, nullptr, coeffs, desc->degree, desc->delta, &im2, s));
+    ev.release(re);
+    ev.release(im);
+    ck(he_mul_i(h, &im2, 1, &im2, s));
+    he_ct z = ev.add_take(re2, im2);
+    at = 0;
+    for (int g = 0; g < levels; g++) {
+      he_ct y = boot_transform(ev, z, p.stc[g], stc_pts + at);
+      at += p.stc[g].count();
+      ev.release(z);
+      z = y;
+    }
+    ev.copy_out(z, out);
+    out->scale = z.scale * (in_scale / q0);
     return HE_OK;
   });
 }

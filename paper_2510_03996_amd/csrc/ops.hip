@@ -57,6 +57,35 @@ __global__ __launch_bounds__(256) void k_scalar(const uint64_t* in, size_t ips, 
   out[k * ops + i * n + j] = r;
 }
 
+// out[k][i][j] = in[k][i][j] * (+-w_i), w_i = psi_i^(N/2): the NTT values of
+// sign X^(N/2) are sign w_i on the first half of the positions (bit-reversed
+// index with top bit 0, i.e. odd exponent 2 brv(j) + 1 = 1 mod 4) and
+// -sign w_i on the second half
+__global__ __launch_bounds__(256) void k_mul_i(const uint64_t* in, size_t ips, uint64_t* out, size_t ops, int logn,
+                                               const ModInfo* __restrict__ mods, Scalars sc, int sign) {
+  const size_t n = (size_t)1 << logn;
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, k = blockIdx.z;
+  const uint64_t q = mods[i].q;
+  const uint64_t r = mul_shoup(in[k * ips + i * n + j], sc.w[i], sc.wp[i], q);
+  const bool neg = (j >= n / 2) != (sign < 0);
+  out[k * ops + i * n + j] = neg && r ? q - r : r;
+}
+
+// ModRaise lift: limb 0 of each polynomial holds coefficients a in [0, q_0);
+// limb i >= 1 gets a mod q_i, or (a - q_0) mod q_i when a > (q_0 - 1)/2
+__global__ __launch_bounds__(256) void k_lift(uint64_t* data, size_t ps, int logn, const ModInfo* __restrict__ mods) {
+  const size_t n = (size_t)1 << logn;
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y + 1, k = blockIdx.z;
+  const ModInfo mi = mods[i];
+  const uint64_t q0 = mods[0].q;
+  const uint64_t a = data[k * ps + j];
+  uint64_t r = reduce_word(a, mi);
+  if (a > (q0 >> 1)) r = sub_mod(r, reduce_word(q0, mi), mi.q);
+  data[k * ps + i * n + j] = r;
+}
+
 // llround(c * scale) reduced into every active limb (ties away from zero)
 static int const_residues(const Ctx* c, double v, double scale, int level, Scalars* sc) {
   const double x = v * scale;
@@ -110,6 +139,52 @@ static int addsub(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* out, he_stre
 }
 
 extern "C" {
+
+int he_mul_i(he_ctx* h, const he_ct* in, int sign, he_ct* out, he_stream st) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in")) || (rc = check_out(c, out, in->level))) return rc;
+  if (sign != 1 && sign != -1) return set_error(HE_EINVAL, "sign must be +1 or -1");
+  if (out->data == in->data && out->cap != in->cap) return set_error(HE_EINVAL, "in-place product needs equal capacity");
+  Scalars sc;
+  for (int i = 0; i < in->level; i++) {
+    sc.w[i] = omega4(c, i);
+    sc.wp[i] = (uint64_t)(((unsigned __int128)sc.w[i] << 64) / c->mod[i]);
+  }
+  const size_t N = c->n;
+  ProfScope ps(c, "mul_i", (hipStream_t)st, 32.0 * N * in->level, 2.0 * N * in->level);
+  k_mul_i<<<grid_for(c, in->level, 2), 256, 0, (hipStream_t)st>>>(in->data, in->cap * N, out->data, out->cap * N,
+                                                                   c->log_n, c->d_mod, sc, sign);
+  HE_HIP(hipGetLastError());
+  out->level = in->level;
+  out->scale = in->scale;
+  return HE_OK;
+}
+
+int he_mod_raise(he_ctx* h, const he_ct* in, int level, he_ct* out, he_stream st) {
+  if (!h) return set_error(HE_EINVAL, "null context");
+  Ctx* c = &h->c;
+  int rc;
+  if ((rc = check_ct(c, in, "in"))) return rc;
+  if (level < 1 || level > c->L) return set_error(HE_ELEVEL, "raise level out of range");
+  if ((rc = check_out(c, out, level))) return rc;
+  if (out->data == in->data) return set_error(HE_EINVAL, "ModRaise output aliases the input");
+  hipStream_t s = (hipStream_t)st;
+  const size_t N = c->n;
+  ProfScope ps(c, "mod_raise", s, 8.0 * N * 2 * (1 + level), 0);
+  // limb 0 of both polynomials to coefficient form in out's limb 0
+  if ((rc = ntt_launch_strided(c, in->data, in->cap * N, out->data, out->cap * N, 2, range_map(0, 1, 0), true, s)))
+    return rc;
+  if (level > 1) {
+    k_lift<<<dim3((unsigned)(N / 256), level - 1, 2), 256, 0, s>>>(out->data, out->cap * N, c->log_n, c->d_mod);
+    HE_HIP(hipGetLastError());
+  }
+  if ((rc = ntt_launch(c, out->data, out->cap * N, 2, range_map(0, level, 0), false, s))) return rc;
+  out->level = level;
+  out->scale = in->scale;
+  return HE_OK;
+}
 
 int he_add(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* out, he_stream s) { return addsub(h, a, b, out, s, 0); }
 int he_sub(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* out, he_stream s) { return addsub(h, a, b, out, s, 1); }

@@ -20,6 +20,8 @@ ERRORS = {
     -5: "HE_ENOMEM", -6: "HE_EHIP", -7: "HE_EUNSUPPORTED",
 }
 KEY_RELIN = 0x7FFFFFFF
+KEY_CONJ = 0x7FFFFFFE  # he_rotate with this id conjugates every slot
+BOOT_MAX_ROTATIONS = 256
 NTT_VARIANTS = 5
 CHSUM_CHAIN, CHSUM_LOG = 0, 1  # he_ctx_conv_channel_sum modes
 CHAIN_HORNER, CHAIN_BSGS = 0, 1  # he_ctx_mask_chains modes
@@ -134,6 +136,47 @@ BATCH_GRAPH, BATCH_MAC4, BATCH_TUNE = 1, 2, 4
 BATCH_MAC_VARIANTS = 5
 
 
+class he_boot_desc(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("degree", ctypes.c_int32), ("level", ctypes.c_int32),
+                ("k_min", ctypes.c_double), ("delta", ctypes.c_double)]
+
+
+def boot_desc(levels, degree, k_min, delta, level=0):
+    return he_boot_desc(int(levels), int(degree), int(level), float(k_min), float(delta))
+
+
+def boot_plan(log_n, levels):
+    """(rotation amounts, per-level plaintext counts: CoeffToSlot then
+    SlotToCoeff) of the bootstrapping transforms (host only)."""
+    rots = (ctypes.c_int32 * BOOT_MAX_ROTATIONS)()
+    nr = ctypes.c_int32()
+    counts = (ctypes.c_int32 * (2 * levels))()
+    _check(lib().he_boot_plan(int(log_n), int(levels), rots, ctypes.byref(nr), counts))
+    return list(rots[: nr.value]), list(counts)
+
+
+def boot_diagonals(log_n, levels, inverse):
+    """Complex slot vectors of every plaintext of one transform, in
+    consumption order (host only): a list of numpy complex arrays."""
+    import numpy as np
+
+    _, counts = boot_plan(log_n, levels)
+    k = sum(counts[:levels]) if inverse else sum(counts[levels:])
+    n = 1 << (log_n - 1)
+    re = np.zeros(k * n)
+    im = np.zeros(k * n)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().he_boot_diagonals(int(log_n), int(levels), 1 if inverse else 0, re.ctypes.data_as(dp),
+                                   im.ctypes.data_as(dp), re.size))
+    return [(re[i * n:(i + 1) * n] + 1j * im[i * n:(i + 1) * n]) for i in range(k)]
+
+
+def boot_mod_coeffs(K, degree):
+    cf = (ctypes.c_double * (degree + 1))()
+    _check(lib().he_boot_mod_coeffs(float(K), int(degree), cf))
+    return list(cf)
+
+
 def batch_mac_select(v):
     """HE_BATCH_MAC_SELECT(v): run the batched MAC as variant v (0..4)."""
     return (int(v) + 1) << 8
@@ -208,6 +251,14 @@ def lib():
             "he_key_cache_limit": [vp, sz],
             "he_key_prefetch": [vp, P(i32), c_int, vp],
             "he_key_cache_stats": [vp, P(sz), P(ctypes.c_int64), P(ctypes.c_int64)],
+            "he_mul_i": [vp, P(he_ct), c_int, P(he_ct), vp],
+            "he_mod_raise": [vp, P(he_ct), c_int, P(he_ct), vp],
+            "he_boot_plan": [i32, i32, P(i32), P(i32), P(i32)],
+            "he_boot_diagonals": [i32, i32, i32, P(ctypes.c_double), P(ctypes.c_double), sz],
+            "he_boot_mod_coeffs": [ctypes.c_double, i32, P(ctypes.c_double)],
+            "he_boot_scales": [vp, P(he_boot_desc), P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
+                               P(ctypes.c_double)],
+            "he_bootstrap": [vp, P(he_ct), P(he_boot_desc), P(he_pt), P(he_pt), P(ctypes.c_double), P(he_ct), vp],
             "he_profile_begin": [vp],
             "he_profile_end": [vp, ctypes.c_char_p, sz],
         }
@@ -537,6 +588,37 @@ class Context:
         m = ctypes.byref(scale_mask.c()) if scale_mask is not None else None
         _check(lib().he_cheb(self.h, ctypes.byref(a), m, cf, len(coeffs) - 1, float(delta), ctypes.byref(o),
                              _stream(stream)))
+        out.update(o)
+        return out
+
+    def mul_i(self, ct, sign, out=None, stream=None):
+        out = out or self.new_ct(ct.cap)
+        a, o = ct.c(), out.c()
+        _check(lib().he_mul_i(self.h, ctypes.byref(a), int(sign), ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    def mod_raise(self, ct, level, out=None, stream=None):
+        out = out or self.new_ct(level)
+        a, o = ct.c(), out.c()
+        _check(lib().he_mod_raise(self.h, ctypes.byref(a), int(level), ctypes.byref(o), _stream(stream)))
+        out.update(o)
+        return out
+
+    def boot_scales(self, desc):
+        """(K, raise scale, CoeffToSlot scales, SlotToCoeff scales)."""
+        K, rs = ctypes.c_double(), ctypes.c_double()
+        cs = (ctypes.c_double * desc.levels)()
+        ss = (ctypes.c_double * desc.levels)()
+        _check(lib().he_boot_scales(self.h, ctypes.byref(desc), ctypes.byref(K), ctypes.byref(rs), cs, ss))
+        return K.value, rs.value, list(cs), list(ss)
+
+    def bootstrap(self, ct, desc, cts_pts, stc_pts, coeffs, out=None, stream=None):
+        out = out or self.new_ct()
+        a, o = ct.c(), out.c()
+        cf = (ctypes.c_double * len(coeffs))(*[float(x) for x in coeffs])
+        _check(lib().he_bootstrap(self.h, ctypes.byref(a), ctypes.byref(desc), _pts(cts_pts), _pts(stc_pts), cf,
+                                  ctypes.byref(o), _stream(stream)))
         out.update(o)
         return out
 

@@ -1,0 +1,146 @@
+"""GPU vs oracle parity for bootstrapping and its steps (needs MI355X):
+conjugation, multiplication by +-i, ModRaise, the whole procedure."""
+import numpy as np
+import pytest
+
+from oracle import boot as BT
+from oracle import ckks
+from tests import helpers as H
+from tests import test_oracle_boot as TB
+
+pytestmark = pytest.mark.gpu
+
+
+def boot_gpu_ctx():
+    from paper_2510_03996_amd import he
+
+    p = TB.BOOT_PARAMS
+    return he.Context(p["log_n"], p["q_bits"], p["p_bits"], p["alpha"])
+
+
+def upload_boot_keys(g, keys, rk):
+    from paper_2510_03996_amd import he
+
+    for r, k in keys.items():
+        g.key_upload(he.KEY_CONJ if r == ckks.CONJ else r, k)
+    g.key_upload(he.KEY_RELIN, rk)
+
+
+def test_conjugation_and_mul_i():
+    """he_rotate with HE_KEY_CONJ (alone and inside a hoisted set) and he_mul_i
+    bit-exact against the oracle at the bootstrapping ring."""
+    from paper_2510_03996_amd import he
+
+    ctx, sk, pk, plan, keys, rk, _, _ = TB.boot_setup()
+    g = boot_gpu_ctx()
+    try:
+        assert [int(x) for x in g.moduli] == ctx.pr.q + ctx.pr.p
+        upload_boot_keys(g, keys, rk)
+        z = np.random.default_rng(21).uniform(-1, 1, ctx.n // 2)
+        for level in (ctx.pr.L, 5):
+            ct = ctx.encrypt(pk, ctx.encode(z, 2.0 ** 40, level), 21)
+            gct = g.ct_from_numpy(ct.data, ct.scale)
+            want = ctx.rotate(ct, ckks.CONJ, keys)
+            got = g.rotate(gct, he.KEY_CONJ)
+            H.assert_limbs_equal(got.numpy(), want.data, "conjugation at level %d" % level)
+            rs = [1, 128, 8]
+            wants = ctx.rotate_hoisted(ct, [ckks.CONJ] + rs, keys)
+            gots = g.rotate_hoisted(gct, [he.KEY_CONJ] + rs)
+            for a, b in zip(gots, wants):
+                H.assert_limbs_equal(a.numpy(), b.data, "hoisted set with the conjugation")
+            for sign, e in ((1, ctx.n // 2), (-1, 3 * ctx.n // 2)):
+                want = ctx.mul_plain(ct, BT.monomial_pt(ctx, e, level))
+                got = g.mul_i(gct, sign)
+                H.assert_limbs_equal(got.numpy(), want.data, "mul_i sign %d" % sign)
+                assert got.scale == want.scale
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("name", ["boot", "config2"])
+def test_mod_raise(name):
+    """he_mod_raise bit-exact against the oracle: the bootstrapping ring and
+    N = 2^16 with the 24-limb chain (raised to 24 and to 9 limbs)."""
+    if name == "boot":
+        ctx, _, pk, _, _, _, _, _ = TB.boot_setup()
+        g = boot_gpu_ctx()
+    else:
+        ctx, _, pk = H.oracle_ctx(name)
+        g = H.gpu_ctx(name)
+    try:
+        v = np.random.default_rng(5).uniform(-1, 1, ctx.n // 2)
+        ct = ctx.encrypt(pk, ctx.encode(v, ctx.pr.scale, 1), 5)
+        gct = g.ct_from_numpy(ct.data, ct.scale)
+        for level in (ctx.pr.L, 9, 1):
+            want = BT.mod_raise(ctx, ct, level)
+            got = g.mod_raise(gct, level)
+            H.assert_limbs_equal(got.numpy(), want.data, "%s ModRaise to %d" % (name, level))
+            assert got.level == level and got.scale == ct.scale
+        # a higher-level input: only limb 0 is read
+        ct3 = ctx.encrypt(pk, ctx.encode(v, ctx.pr.scale, 3), 6)
+        want = BT.mod_raise(ctx, ctx.drop_level(ct3, 1), ctx.pr.L)
+        got = g.mod_raise(g.ct_from_numpy(ct3.data, ct3.scale), ctx.pr.L)
+        H.assert_limbs_equal(got.numpy(), want.data, "%s ModRaise from level 3" % name)
+    finally:
+        g.close()
+
+
+def test_bootstrap_bit_exact():
+    """The whole procedure at N = 2^12 (L = 16, three levels per transform,
+    EvalMod degree 159): every limb equal to the oracle's, the same level and
+    scale, and the decryption within the refresh bound of the message."""
+    from paper_2510_03996_amd import he
+
+    ctx, sk, pk, plan, keys, rk, cts, stc = TB.boot_setup()
+    pr = ctx.pr
+    g = boot_gpu_ctx()
+    try:
+        upload_boot_keys(g, keys, rk)
+        desc = he.boot_desc(TB.BOOT_LEVELS, TB.BOOT_DEGREE, TB.BOOT_KMIN, pr.scale)
+        K, rs, cs, ss = g.boot_scales(desc)
+        q0 = pr.q[0]
+        assert K == plan.K(q0) and rs == plan.raise_scale(q0)
+        assert cs == [p[0].scale for p in cts] and ss == [p[0].scale for p in stc]
+        coeffs = list(plan.mod_coeffs(q0))
+        gcts = [g.pt_from_numpy(p.data, p.scale) for lv in cts for p in lv]
+        gstc = [g.pt_from_numpy(p.data, p.scale) for lv in stc for p in lv]
+        v = np.random.default_rng(3).uniform(-1, 1, ctx.n // 2)
+        ct = ctx.encrypt(pk, ctx.encode(v, pr.scale, 1), 9)
+        want, _ = BT.bootstrap(ctx, ct, plan, keys, rk, cts, stc)
+        got = g.bootstrap(g.ct_from_numpy(ct.data, ct.scale), desc, gcts, gstc, coeffs)
+        assert got.level == want.level and got.scale == want.scale
+        H.assert_limbs_equal(got.numpy(), want.data, "bootstrap")
+        dec = ctx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale))
+        assert np.max(np.abs(dec - v)) < TB.BOOT_TOL
+    finally:
+        g.close()
+
+
+def test_bootstrap_errors():
+    from paper_2510_03996_amd import he
+
+    ctx, sk, pk, plan, keys, rk, cts, stc = TB.boot_setup()
+    pr = ctx.pr
+    g = boot_gpu_ctx()
+    try:
+        ct = ctx.encrypt(pk, ctx.encode(np.zeros(4), pr.scale, 1), 9)
+        gct = g.ct_from_numpy(ct.data, ct.scale)
+        coeffs = list(plan.mod_coeffs(pr.q[0]))
+        gcts = [g.pt_from_numpy(p.data, p.scale) for lv in cts for p in lv]
+        gstc = [g.pt_from_numpy(p.data, p.scale) for lv in stc for p in lv]
+        desc = he.boot_desc(TB.BOOT_LEVELS, TB.BOOT_DEGREE, TB.BOOT_KMIN, pr.scale)
+        with pytest.raises(he.HEError, match="HE_ENOKEY|key"):
+            g.bootstrap(gct, desc, gcts, gstc, coeffs)  # no keys uploaded yet
+        upload_boot_keys(g, keys, rk)
+        with pytest.raises(he.HEError, match="levels"):
+            g.bootstrap(gct, he.boot_desc(TB.BOOT_LEVELS, TB.BOOT_DEGREE, TB.BOOT_KMIN, pr.scale, level=12), gcts,
+                        gstc, coeffs)
+        with pytest.raises(he.HEError):
+            g.bootstrap(gct, he.boot_desc(0, TB.BOOT_DEGREE, TB.BOOT_KMIN, pr.scale), gcts, gstc, coeffs)
+        low = ctx.encode(np.zeros(4), pr.scale, 3)
+        with pytest.raises(he.HEError, match="plaintext"):
+            g.bootstrap(gct, desc, [g.pt_from_numpy(low.data, low.scale)] + gcts[1:], gstc, coeffs)
+        with pytest.raises(he.HEError):
+            g.mul_i(gct, 2)
+    finally:
+        g.close()

@@ -1,0 +1,46 @@
+"""Host-side bootstrapping recipes of the C ABI against the oracle (CPU only):
+the transform plan (rotation keys, plaintext counts), the plaintext slot
+vectors in consumption order, the EvalMod coefficients."""
+import numpy as np
+import pytest
+
+from oracle import boot as BT
+from paper_2510_03996_amd import he
+
+CASES = [(4, 1), (4, 3), (6, 2), (8, 3), (12, 3), (12, 2), (13, 4), (16, 3)]
+
+
+@pytest.mark.parametrize("log_n,levels", CASES)
+def test_boot_plan_matches_oracle(log_n, levels):
+    plan = BT.BootPlan(log_n, levels, 12.0, 2.0 ** 50, 31)
+    rots, counts = he.boot_plan(log_n, levels)
+    assert rots == plan.rotations()
+    assert counts == [p.count() for p in plan.cts_plans] + [p.count() for p in plan.stc_plans]
+
+
+@pytest.mark.parametrize("log_n,levels", [(4, 3), (6, 2), (8, 3), (12, 3)])
+@pytest.mark.parametrize("inverse", [True, False])
+def test_boot_diagonals_match_oracle(log_n, levels, inverse):
+    plan = BT.BootPlan(log_n, levels, 12.0, 2.0 ** 50, 31)
+    want = [v for lv in (plan.cts_values() if inverse else plan.stc_values()) for v in lv]
+    got = he.boot_diagonals(log_n, levels, inverse)
+    assert len(got) == len(want)
+    for g, w in zip(got, want):
+        assert np.array_equal(g == 0, w == 0)
+        assert np.max(np.abs(g - w)) < 1e-12
+
+
+@pytest.mark.parametrize("K,degree", [(8.0, 95), (16.000000001, 159), (3.0, 31)])
+def test_boot_mod_coeffs_match_oracle(K, degree):
+    assert np.max(np.abs(np.array(he.boot_mod_coeffs(K, degree)) - BT.mod_coeffs(K, degree))) < 1e-14
+
+
+def test_boot_recipe_errors():
+    with pytest.raises(he.HEError):
+        he.boot_plan(12, 0)
+    with pytest.raises(he.HEError):
+        he.boot_plan(12, 12)
+    with pytest.raises(he.HEError):
+        he.boot_mod_coeffs(0.0, 31)
+    with pytest.raises(he.HEError):
+        he.boot_mod_coeffs(8.0, 0)

@@ -412,6 +412,27 @@ def layer_latencies(reps=3):
     out["relu_cheb59_n16_streams1_ms"] = round(
         timed(lambda: c2.cheb(ctr, cheb, sc, scale_mask=rmask, stream=s), reps, s) * 1e3, 3)
     c2.layer_streams(2)
+    # bootstrapping: ModRaise of a level-1 ciphertext to 24 limbs, three-level
+    # coefficient/slot transforms, EvalMod (K ~ 16) on the real and imaginary
+    # parts as the cosine of degree 39 with three double angles (15 levels
+    # consumed, the result at level 9) and as the sine of degree 159 (14
+    # levels, level 10)
+    brots, bcounts, bks = he.boot_plan(16, 3, key_switches=True)
+    upload_synthetic_keys(c2, brots + [he.KEY_CONJ], 60)
+    ctb1 = synthetic_ct(c2, 1, 67, sc)
+    boot_ks = {}
+    for name, deg, r in (("bootstrap_n16", 39, 3), ("bootstrap_n16_sine159", 159, 0)):
+        bdesc = he.boot_desc(3, deg, 12.0, sc, double_angles=r)
+        bK, _, bcs, bss = c2.boot_scales(bdesc)
+        bcoef = he.boot_mod_coeffs(bK, deg, r)
+        blv = he.cheb_plan(bcoef, False)
+        bcts = [p for g in range(3) for p in synthetic_pts(c2, bcounts[g], 24 - g, 61 + g, bcs[g])]
+        bstc = [p for g in range(3)
+                for p in synthetic_pts(c2, bcounts[3 + g], 21 - blv[0] - r - g, 64 + g, bss[g])]
+        out[name + "_ms"] = round(timed(lambda: c2.bootstrap(ctb1, bdesc, bcts, bstc, bcoef, stream=s), reps, s)
+                                  * 1e3, 3)
+        boot_ks[name] = bks + 1 + 2 * (blv[1] + r)
+        del bcts, bstc
     out["key_switches"] = {"conv3x3_n12": 8, "lenet5_stack": pc.key_switches + pp.key_switches + 2,
                            "resnet_convA": pa.key_switches, "resnet_convB": pb.key_switches,
                            "resnet_gap": pg.key_switches, "resnet_fc": pf.key_switches,
@@ -419,7 +440,8 @@ def layer_latencies(reps=3):
                            "resnet_convA_logsum": pal.key_switches, "resnet_convB_logsum": pbl.key_switches,
                            "resnet_convB_logsum_bsgs": pbb.key_switches, "resnet_gap_bsgs": pgb.key_switches,
                            **stride_ks,
-                           "lenet5_stack_bsgs": lenet_ks_b, "resnet_fc_diag": pfd.key_switches}
+                           "lenet5_stack_bsgs": lenet_ks_b, "resnet_fc_diag": pfd.key_switches,
+                           **boot_ks}
     c2.close()
     return out
 

@@ -575,42 +575,54 @@ int he_cheb_relu_coeffs(double beta, int degree, double* coeffs);
  *     holds (t_lo + i t_hi) / (2 q_0 K) in bit-reversed slot order.
  *  3. EvalMod: w = conj(x) (HE_KEY_CONJ); re = x + w; im = -i (x - w);
  *     each through he_cheb (no mask, output scale delta) with the Chebyshev
- *     interpolant of sin(2 pi K x) / (2 pi) (he_boot_mod_coeffs), which
- *     removes q_0 I and leaves about m / q_0; z = re + i im.
+ *     interpolant of he_boot_mod_coeffs: with r = double_angles = 0 the
+ *     sine sin(2 pi K x) / (2 pi) directly; with r > 0 the cosine
+ *     cos(2 pi (K x - 1/4) / 2^r), then r double angles
+ *     p = RS(Relin(c c)), c = (p + p) - 1 (ending at sin(2 pi K x)) and the
+ *     scale label times 2 pi.  Either removes q_0 I and leaves about
+ *     m / q_0; z = re + i im.
  *  4. SlotToCoeff: the forward stages h = 1 .. N/4 (CoeffToSlot's groups
  *     mirrored), same evaluation; the result is relabelled
  *     scale(z) * in.scale / q_0 and decrypts to the input's message.
  * Plaintext scales: CoeffToSlot level g (at level - g) encodes its
  * plaintexts at q 2^-e_g, SlotToCoeff level g (at its level l) at
  * q 2^f_g, q the prime that level's rescale removes; e_g split e and f_g
- * split round(log2(q_0 / delta)) as evenly as possible, larger first
- * (he_boot_scales).  Levels consumed: 2 levels + he_cheb_plan's count.
+ * split round(log2(q_0 / (delta a))) (a = 2 pi with double angles, else 1)
+ * as evenly as possible, larger first (he_boot_scales).  Levels consumed:
+ * 2 levels + he_cheb_plan's count + r.
  * Key switches: the transforms' rotations (he_boot_plan), one
- * conjugation and he_cheb's relinearizations twice. */
+ * conjugation and he_cheb's relinearizations twice.  The giant steps of each
+ * transform level (round-robin, each stream keeping a partial sum) and the
+ * two EvalMod parts run on up to he_ctx_layer_streams streams at every ring
+ * degree; the result does not depend on the split. */
 typedef struct {
-  int32_t levels;  /* levels per linear transform, 1..log2(N/2) */
-  int32_t degree;  /* EvalMod Chebyshev degree, 1..HE_CHEB_MAX_DEGREE */
-  int32_t level;   /* ModRaise target level (0: L) */
-  double k_min;    /* bound on |I| + 1/2 */
-  double delta;    /* EvalMod input and output scale */
+  int32_t levels;        /* levels per linear transform, 1..log2(N/2) */
+  int32_t degree;        /* EvalMod Chebyshev degree, 1..HE_CHEB_MAX_DEGREE */
+  int32_t level;         /* ModRaise target level (0: L) */
+  int32_t double_angles; /* r, 0..8 (0: the sine directly) */
+  double k_min;          /* bound on |I| + 1/2 */
+  double delta;          /* EvalMod input (Chebyshev output) scale */
 } he_boot_desc;
 
 #define HE_BOOT_MAX_ROTATIONS 256
 /* Plan of the two linear transforms for N = 2^log_n and `levels` levels
  * (host only): the distinct rotation amounts (in [1, N/2), ascending) both
- * transforms use, and the plaintext count of each level in application
- * order (CoeffToSlot then SlotToCoeff, `levels` each).  rotations holds
- * HE_BOOT_MAX_ROTATIONS entries, counts 2 * levels. */
-int he_boot_plan(int32_t log_n, int32_t levels, int32_t* rotations, int32_t* n_rotations, int32_t* counts);
+ * transforms use, the plaintext count of each level in application order
+ * (CoeffToSlot then SlotToCoeff, `levels` each) and the key switches both
+ * transforms perform (baby steps plus nonzero giant steps; may be NULL).
+ * rotations holds HE_BOOT_MAX_ROTATIONS entries, counts 2 * levels. */
+int he_boot_plan(int32_t log_n, int32_t levels, int32_t* rotations, int32_t* n_rotations, int32_t* counts,
+                 int32_t* n_key_switches);
 /* The plaintext slot vectors (complex, N/2 slots each, real parts in re,
  * imaginary parts in im) of one transform (inverse = 1: CoeffToSlot, 0:
  * SlotToCoeff) in consumption order: level by level, giant j ascending,
  * baby i ascending (pt_{j,i} above).  Pure butterfly products (no scale
  * constant); `cap` = doubles available in each of re, im (host only). */
 int he_boot_diagonals(int32_t log_n, int32_t levels, int32_t inverse, double* re, double* im, size_t cap);
-/* Chebyshev coefficients c_0..c_degree of sin(2 pi K x) / (2 pi) on [-1, 1]
- * interpolated at the degree + 1 first-kind nodes (even ones exactly 0). */
-int he_boot_mod_coeffs(double K, int32_t degree, double* coeffs);
+/* Chebyshev coefficients c_0..c_degree, interpolated on [-1, 1] at the
+ * degree + 1 first-kind nodes, of sin(2 pi K x) / (2 pi) (double_angles = 0;
+ * even coefficients exactly 0) or cos(2 pi (K x - 1/4) / 2^double_angles). */
+int he_boot_mod_coeffs(double K, int32_t degree, int32_t double_angles, double* coeffs);
 /* For a context and description: the EvalMod range K, the raise label
  * 2^e delta, and the plaintext scales of every CoeffToSlot and SlotToCoeff
  * level (`levels` doubles each) at the levels the procedure uses them. */
@@ -619,10 +631,10 @@ int he_boot_scales(const he_ctx* ctx, const he_boot_desc* desc, double* K, doubl
 /* Refresh `in` (any level; limb 0 is used).  cts_pts, stc_pts: the
  * plaintexts of he_boot_diagonals encoded at he_boot_scales (level g of
  * CoeffToSlot at level - g, SlotToCoeff level g at the level it is applied
- * at); coeffs: he_boot_mod_coeffs(K, degree).  Needs the rotation keys of
- * he_boot_plan, HE_KEY_CONJ and HE_KEY_RELIN.  out gets level
- * level - 2 levels - he_cheb_plan levels.  HE_ELEVEL when the chain is too
- * short, HE_ENOKEY for a missing key. */
+ * at); coeffs: he_boot_mod_coeffs(K, degree, double_angles).  Needs the
+ * rotation keys of he_boot_plan, HE_KEY_CONJ and HE_KEY_RELIN.  out gets
+ * level level - 2 levels - he_cheb_plan levels - double_angles.  HE_ELEVEL
+ * when the chain is too short, HE_ENOKEY for a missing key. */
 int he_bootstrap(he_ctx* ctx, const he_ct* in, const he_boot_desc* desc, const he_pt* cts_pts, const he_pt* stc_pts,
                  const double* coeffs, he_ct* out, he_stream stream);
 

@@ -19,8 +19,10 @@ held to it bit for bit:
    levels, each level evaluated by baby-step giant-step diagonals.  Its
    output holds (t_lo + i t_hi) / (2 q_0 K) in bit-reversed slot order.
 3. EvalMod: conjugation splits real and imaginary parts; each goes through
-   the Chebyshev interpolant of sin(2 pi K x) / (2 pi) (``mod_coeffs``),
-   which removes q_0 I and returns about m / q_0.
+   the Chebyshev interpolant of sin(2 pi K x) / (2 pi) (``mod_coeffs``), or
+   of cos(2 pi (K x - 1/4) / 2^r) followed by r double angles
+   c <- 2 c^2 - 1 (which end at sin(2 pi K x)) and a scale label times
+   2 pi; either way q_0 I is removed and about m / q_0 remains.
 4. SlotToCoeff: the forward butterfly factors, bit-reversed input to natural
    order, give back the slot vector of m.
 
@@ -241,7 +243,8 @@ class BootPlan:
     """Everything the procedure needs besides keys and ciphertexts, for
     N/2 = n slots, `levels` levels per linear transform, a bound k_min on
     |I| + 1/2 (I the multiple of q_0 that ModRaise adds), base scale delta
-    (the EvalMod input's scale) and a Chebyshev degree.
+    (the EvalMod input's scale), a Chebyshev degree and a number r of
+    double angles (0: the sine is interpolated directly).
 
     The raised ciphertext is relabelled 2^e delta with e the smallest
     integer such that 2^e delta >= 2 q_0 k_min, and EvalMod's range is
@@ -251,8 +254,9 @@ class BootPlan:
     Chebyshev evaluation needs (its squarings double any gap between the
     input scale and the primes)."""
 
-    def __init__(self, log_n, levels, k_min, delta, degree):
+    def __init__(self, log_n, levels, k_min, delta, degree, double_angles=0):
         self.log_n, self.levels, self.k_min, self.delta, self.degree = log_n, levels, k_min, delta, degree
+        self.double_angles = double_angles
         self.n = 1 << (log_n - 1)
         ls = log_n - 1
         self.cts_hs = cts_groups(ls, levels)
@@ -295,27 +299,52 @@ class BootPlan:
 
     def stc_exponents(self, q0):
         """f_g of SlotToCoeff level g's plaintext scale q 2^f_g: f =
-        round(log2(q_0 / delta)) split as evenly as possible, so that the
+        round(log2(q_0 / (delta a))) (a = 2 pi with double angles, else 1:
+        EvalMod's output label) split as evenly as possible, so that the
         result's scale label comes back near the input's (EvalMod returns
-        m / q_0 at scale delta)."""
-        f = int(math.floor(math.log2(float(q0) / self.delta) + 0.5))
+        m / q_0 at scale delta a)."""
+        a = 2.0 * math.pi if self.double_angles else 1.0
+        f = int(math.floor(math.log2(float(q0) / (self.delta * a)) + 0.5))
         return group_sizes(f, self.levels) if f > 0 else [0] * self.levels
 
     def mod_coeffs(self, q0):
-        return mod_coeffs(self.K(q0), self.degree)
+        return mod_coeffs(self.K(q0), self.degree, self.double_angles)
+
+    def evalmod_levels(self, q0):
+        return LY.cheb_plan(self.mod_coeffs(q0), False)[0] + self.double_angles
 
 
-def mod_coeffs(K, degree):
-    """Chebyshev interpolant of f(x) = sin(2 pi K x) / (2 pi) on [-1, 1] at
-    the degree + 1 first-kind nodes x_k = cos(pi (k + 1/2) / (degree + 1)):
-    c_j = 2 / (degree + 1) sum_k f(x_k) T_j(x_k), f ~ c_0 / 2 + sum c_j T_j.
-    For x = t / (q_0 K) with t = m + q_0 I: f = sin(2 pi m / q_0) / (2 pi),
-    about m / q_0.  f is odd: the even coefficients are set to exactly 0."""
+def mod_coeffs(K, degree, double_angles=0):
+    """Chebyshev interpolant on [-1, 1] at the degree + 1 first-kind nodes
+    x_k = cos(pi (k + 1/2) / (degree + 1)): c_j = 2 / (degree + 1)
+    sum_k f(x_k) T_j(x_k), f ~ c_0 / 2 + sum c_j T_j, of
+      r = 0: f(x) = sin(2 pi K x) / (2 pi) (odd: even coefficients set to 0);
+      r > 0: f(x) = cos(2 pi (K x - 1/4) / 2^r), whose r double angles give
+             cos(2 pi K x - pi / 2) = sin(2 pi K x).
+    For x = t / (q_0 K), t = m + q_0 I: sin(2 pi K x) = sin(2 pi m / q_0),
+    about 2 pi m / q_0."""
     n = degree + 1
     theta = np.pi * (np.arange(n) + 0.5) / n
-    fx = np.sin(2.0 * np.pi * K * np.cos(theta)) / (2.0 * np.pi)
+    if double_angles:
+        fx = np.cos(2.0 * np.pi * (K * np.cos(theta) - 0.25) / float(1 << double_angles))
+    else:
+        fx = np.sin(2.0 * np.pi * K * np.cos(theta)) / (2.0 * np.pi)
     c = np.array([2.0 / n * float(np.sum(fx * np.cos(j * theta))) for j in range(n)])
-    c[0::2] = 0.0
+    if not double_angles:
+        c[0::2] = 0.0
+    return c
+
+
+def evalmod(ev, x, plan, coeffs):
+    """One EvalMod part: c = cheb_eval(x, coeffs, no mask, delta); then r
+    times p = RS(Relin(c c)), c = (p + p) - 1; with r > 0 the scale label is
+    multiplied by 2 pi (c then decodes to about m / q_0)."""
+    c = LY.cheb_eval(ev, x, coeffs, None, plan.delta)
+    for _ in range(plan.double_angles):
+        p = ev.rescale(ev.mul_relin(c, c))
+        c = ev.add_const(ev.add(p, p), -1.0)
+    if plan.double_angles:
+        c = Ciphertext(c.data, c.scale * (2.0 * math.pi))
     return c
 
 
@@ -335,7 +364,7 @@ def boot_plaintexts(ctx, plan, level_in):
     for g, vals in enumerate(plan.cts_values()):
         lv = level_in - g
         cts.append(encode_level(ctx, vals, math.ldexp(float(q[lv - 1]), -ex[g]), lv))
-    lv0 = level_in - plan.levels - LY.cheb_plan(plan.mod_coeffs(q[0]), False)[0]
+    lv0 = level_in - plan.levels - plan.evalmod_levels(q[0])
     fx = plan.stc_exponents(q[0])
     for g, vals in enumerate(plan.stc_values()):
         lv = lv0 - g
@@ -348,13 +377,14 @@ def bootstrap(ctx, ct, plan, keys, relin_key, cts_pts, stc_pts, level_in=None):
       x  = ModRaise(ct) to level_in (default L), relabelled 2^e delta = 2 q_0 K;
       CoeffToSlot: x = linear_transform(level g) for g = 0..levels-1;
       w  = Rot_conj(x);  re = x + w;  im = (-X^(N/2)) (.) (x - w);
-      re, im = cheb_eval(., mod_coeffs, no mask, delta);
+      re, im = evalmod(.) (Chebyshev series, r double angles);
       z  = re + X^(N/2) (.) im;
       SlotToCoeff: z = linear_transform(level g) for g = 0..levels-1;
       result = z relabelled scale(z) * scale(ct) / q_0 (z's slots hold the
       message times scale(ct) / q_0).
-    Levels consumed: 2 levels + cheb levels; key switches: the transforms'
-    rotations, one conjugation, the Chebyshev relinearizations (twice)."""
+    Levels consumed: 2 levels + cheb levels + r; key switches: the
+    transforms' rotations, one conjugation, the Chebyshev and double-angle
+    relinearizations (twice)."""
     L = level_in or ctx.pr.L
     ev = LY.HEEval(ctx, keys, relin_key)
     x = mod_raise(ctx, ctx.drop_level(ct, 1), L)
@@ -365,8 +395,8 @@ def bootstrap(ctx, ct, plan, keys, relin_key, cts_pts, stc_pts, level_in=None):
     re = ctx.add(x, w)
     im = ctx.mul_plain(ctx.sub(x, w), monomial_pt(ctx, 3 * ctx.n // 2, x.level))
     coeffs = plan.mod_coeffs(ctx.pr.q[0])
-    re = LY.cheb_eval(ev, re, coeffs, None, plan.delta)
-    im = LY.cheb_eval(ev, im, coeffs, None, plan.delta)
+    re = evalmod(ev, re, plan, coeffs)
+    im = evalmod(ev, im, plan, coeffs)
     z = ctx.add(re, ctx.mul_plain(im, monomial_pt(ctx, ctx.n // 2, im.level)))
     for p, pts in zip(plan.stc_plans, stc_pts):
         z = linear_transform(ev, z, p, pts)

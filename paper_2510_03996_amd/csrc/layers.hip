@@ -1794,17 +1794,18 @@ static void boot_raise(const Ctx* c, const he_boot_desc* d, int* e, double* K, d
   *K = *raise / (2.0 * q0);
 }
 
-static void boot_mod_coeffs_impl(double K, int degree, double* cf) {
+static void boot_mod_coeffs_impl(double K, int degree, int r, double* cf) {
   const int n = degree + 1;
   std::vector<double> th(n), fx(n);
   for (int k = 0; k < n; k++) {
     th[k] = M_PI * (k + 0.5) / n;
-    fx[k] = std::sin(2.0 * M_PI * K * std::cos(th[k])) / (2.0 * M_PI);
+    fx[k] = r ? std::cos(2.0 * M_PI * (K * std::cos(th[k]) - 0.25) / (double)(1 << r))
+              : std::sin(2.0 * M_PI * K * std::cos(th[k])) / (2.0 * M_PI);
   }
   for (int j = 0; j < n; j++) {
     double s = 0.0;
     for (int k = 0; k < n; k++) s += fx[k] * std::cos(j * th[k]);
-    cf[j] = (j % 2 == 0) ? 0.0 : 2.0 / n * s;
+    cf[j] = (r == 0 && j % 2 == 0) ? 0.0 : 2.0 / n * s;
   }
 }
 
@@ -1820,19 +1821,22 @@ static int boot_scales_impl(const Ctx* c, const he_boot_desc* d, BootScales* s) 
   if (d->levels < 1 || d->levels > c->log_n - 1) return set_error(HE_EINVAL, "transform levels out of range");
   if (d->degree < 1 || d->degree > HE_CHEB_MAX_DEGREE) return set_error(HE_EINVAL, "EvalMod degree out of range");
   if (!(d->k_min > 0.0) || !(d->delta > 1.0)) return set_error(HE_EINVAL, "k_min and delta must be positive");
+  if (d->double_angles < 0 || d->double_angles > 8) return set_error(HE_EINVAL, "double angles out of range");
   s->level_in = d->level ? d->level : c->L;
   if (s->level_in < 1 || s->level_in > c->L) return set_error(HE_ELEVEL, "raise level out of range");
   boot_raise(c, d, &s->e, &s->K, &s->raise);
   std::vector<double> cf(d->degree + 1);
-  boot_mod_coeffs_impl(s->K, d->degree, cf.data());
+  boot_mod_coeffs_impl(s->K, d->degree, d->double_angles, cf.data());
   int rc;
   if ((rc = cheb_plan_impl(cf.data(), d->degree, 0, &s->cheb_levels, &s->cheb_relins))) return rc;
+  s->cheb_levels += d->double_angles;  // EvalMod's levels
   const int out_level = s->level_in - 2 * d->levels - s->cheb_levels;
   if (out_level < 1)
     return set_error(HE_ELEVEL, "bootstrapping needs " + std::to_string(2 * d->levels + s->cheb_levels + 1) +
                                     " levels");
   const std::vector<int> ex = boot_group_sizes(s->e, d->levels);
-  const double f2 = std::log2((double)c->mod[0] / d->delta);
+  const double a = d->double_angles ? 2.0 * M_PI : 1.0;
+  const double f2 = std::log2((double)c->mod[0] / (d->delta * a));
   const int f = (int)std::floor(f2 + 0.5);
   const std::vector<int> fx = f > 0 ? boot_group_sizes(f, d->levels) : std::vector<int>(d->levels, 0);
   s->cts.resize(d->levels);
@@ -1845,8 +1849,13 @@ static int boot_scales_impl(const Ctx* c, const he_boot_desc* d, BootScales* s) 
   return HE_OK;
 }
 
-// y = sum_d D_d (.) Rot_d(x) by baby-step giant-step (pts in consumption order)
-static he_ct boot_transform(Ev& ev, const he_ct& x, const BootLevel& p, const he_pt* pts) {
+// y = sum_d D_d (.) Rot_d(x) by baby-step giant-step (pts in consumption
+// order).  The giant steps (each a product-sum, a rescale and a rotation)
+// are independent: they are dealt round-robin to `streams` streams, each
+// keeping its own partial sum; the partial sums are added on the caller's
+// stream.  Modular additions commute, so the result does not depend on the
+// split.
+static he_ct boot_transform(Ev& ev, const he_ct& x, const BootLevel& p, const he_pt* pts, int streams) {
   std::vector<int> rots;
   for (int i : p.babies) rots.push_back(p.baby_rot(i));
   std::vector<he_ct> br = ev.rot_hoisted(x, rots);
@@ -1854,19 +1863,31 @@ static he_ct boot_transform(Ev& ev, const he_ct& x, const BootLevel& p, const he
   baby[0] = x;
   for (size_t t = 0; t < p.babies.size(); t++) baby[p.babies[t]] = br[t];
   he_ct acc{};
-  bool have = false;
-  int t = 0;
-  for (auto& g : p.giants) {
-    he_ct s = ev.mul(baby[g.second[0].first], pts[t++]);
-    for (size_t q = 1; q < g.second.size(); q++) ev.mac(s, baby[g.second[q].first], pts[t++]);
-    s = ev.rescale_take(s);
-    if (g.first != 0) s = ev.rot_take(s, p.giant_rot(g.first));
-    if (!have) {
-      acc = s;
-      have = true;
-    } else {
-      acc = ev.add_take(acc, s);
+  {
+    Fork fk(ev, std::min(streams, (int)p.giants.size()));
+    const int K = fk.size();
+    std::vector<he_ct> part(K);
+    std::vector<char> have(K, 0);
+    int t = 0;
+    for (size_t gi = 0; gi < p.giants.size(); gi++) {
+      const auto& g = p.giants[gi];
+      const int k = (int)(gi % K);
+      Ev& e = fk.at(k);
+      he_ct s = e.mul(baby[g.second[0].first], pts[t++]);
+      for (size_t q = 1; q < g.second.size(); q++) e.mac(s, baby[g.second[q].first], pts[t++]);
+      s = e.rescale_take(s);
+      if (g.first != 0) s = e.rot_take(s, p.giant_rot(g.first));
+      if (!have[k]) {
+        part[k] = s;
+        have[k] = 1;
+      } else {
+        part[k] = e.add_take(part[k], s);
+      }
     }
+    fk.join();
+    acc = part[0];  // on the caller's stream (k = 0 is the caller's evaluator)
+    for (int k = 1; k < K; k++)
+      if (have[k]) ck(he_add(ev.h, &acc, &part[k], &acc, ev.s));
   }
   for (auto& b : br) ev.release(b);
   return acc;
@@ -1876,18 +1897,21 @@ static he_ct boot_transform(Ev& ev, const he_ct& x, const BootLevel& p, const he
 
 extern "C" {
 
-int he_boot_plan(int32_t log_n, int32_t levels, int32_t* rotations, int32_t* n_rotations, int32_t* counts) {
+int he_boot_plan(int32_t log_n, int32_t levels, int32_t* rotations, int32_t* n_rotations, int32_t* counts,
+                 int32_t* n_key_switches) {
   if (!rotations || !n_rotations || !counts) return set_error(HE_EINVAL, "null argument");
   BootPlanC p;
   int rc;
   if ((rc = boot_plan_make(log_n, levels, &p))) return rc;
   std::vector<int> r;
+  int ks = 0;
   for (const auto* side : {&p.cts, &p.stc})
     for (const BootLevel& lv : *side) {
-      for (int i : lv.babies) r.push_back(lv.baby_rot(i));
+      for (int i : lv.babies) r.push_back(lv.baby_rot(i)), ks += lv.baby_rot(i) != 0;
       for (auto& g : lv.giants)
-        if (g.first != 0) r.push_back(lv.giant_rot(g.first));
+        if (g.first != 0) r.push_back(lv.giant_rot(g.first)), ks += lv.giant_rot(g.first) != 0;
     }
+  if (n_key_switches) *n_key_switches = ks;
   std::sort(r.begin(), r.end());
   r.erase(std::unique(r.begin(), r.end()), r.end());
   r.erase(std::remove(r.begin(), r.end(), 0), r.end());
@@ -1939,11 +1963,12 @@ int he_boot_diagonals(int32_t log_n, int32_t levels, int32_t inverse, double* re
   return HE_OK;
 }
 
-int he_boot_mod_coeffs(double K, int32_t degree, double* coeffs) {
+int he_boot_mod_coeffs(double K, int32_t degree, int32_t double_angles, double* coeffs) {
   if (!coeffs) return set_error(HE_EINVAL, "null argument");
   if (degree < 1 || degree > HE_CHEB_MAX_DEGREE) return set_error(HE_EINVAL, "degree out of range");
   if (!(K > 0.0)) return set_error(HE_EINVAL, "K must be positive");
-  boot_mod_coeffs_impl(K, degree, coeffs);
+  if (double_angles < 0 || double_angles > 8) return set_error(HE_EINVAL, "double angles out of range");
+  boot_mod_coeffs_impl(K, degree, double_angles, coeffs);
   return HE_OK;
 }
 
@@ -2011,9 +2036,10 @@ int he_bootstrap(he_ctx* h, const he_ct* in, const he_boot_desc* desc, const he_
     he_ct x = ev.fresh();
     ck(he_mod_raise(h, &in1, sc.level_in, &x, s));
     x.scale = sc.raise;
+    const int streams = std::max(1, c->layer_streams);
     int at = 0;
     for (int g = 0; g < levels; g++) {
-      he_ct y = boot_transform(ev, x, p.cts[g], cts_pts + at);
+      he_ct y = boot_transform(ev, x, p.cts[g], cts_pts + at, streams);
       at += p.cts[g].count();
       ev.release(x);
       x = y;
@@ -2029,15 +2055,43 @@ int he_bootstrap(he_ctx* h, const he_ct* in, const he_boot_desc* desc, const he_
     ck(he_mul_i(h, &df, -1, &im, s));
     ev.release(df);
     he_ct re2 = ev.fresh(), im2 = ev.fresh();
-    ck(he_cheb(h, &re, nullptr, coeffs, desc->degree, desc->delta, &re2, s));
-    ck(he_cheb(h, &im, nullptr, coeffs, desc->degree, desc->delta, &im2, s));
+    {
+      // the two parts on two streams when helpers are allowed; each part's
+      // last step writes its result into a buffer of the caller's evaluator
+      Fork fk(ev, std::min(streams, 2));
+      auto evalmod = [&](Ev& e, const he_ct& part, he_ct& res) {
+        const int r = desc->double_angles;
+        if (r == 0) {
+          ck(he_cheb(h, &part, nullptr, coeffs, desc->degree, desc->delta, &res, e.s));
+          return;
+        }
+        he_ct c0 = e.fresh();
+        ck(he_cheb(h, &part, nullptr, coeffs, desc->degree, desc->delta, &c0, e.s));
+        for (int t = 0; t < r; t++) {
+          he_ct p2 = e.rescale_take(e.mul_relin(c0, c0));
+          e.release(c0);
+          he_ct sum = e.add(p2, p2);
+          e.release(p2);
+          if (t + 1 < r) {
+            c0 = e.add_const(sum, -1.0);
+          } else {
+            ck(he_add_const(h, &sum, -1.0, &res, e.s));
+          }
+          e.release(sum);
+        }
+        res.scale = res.scale * (2.0 * M_PI);
+      };
+      evalmod(ev, re, re2);
+      evalmod(fk.at(fk.size() - 1), im, im2);
+      fk.join();
+    }
     ev.release(re);
     ev.release(im);
     ck(he_mul_i(h, &im2, 1, &im2, s));
     he_ct z = ev.add_take(re2, im2);
     at = 0;
     for (int g = 0; g < levels; g++) {
-      he_ct y = boot_transform(ev, z, p.stc[g], stc_pts + at);
+      he_ct y = boot_transform(ev, z, p.stc[g], stc_pts + at, streams);
       at += p.stc[g].count();
       ev.release(z);
       z = y;

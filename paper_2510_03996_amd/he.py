@@ -138,21 +138,23 @@ BATCH_MAC_VARIANTS = 5
 
 class he_boot_desc(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("degree", ctypes.c_int32), ("level", ctypes.c_int32),
-                ("k_min", ctypes.c_double), ("delta", ctypes.c_double)]
+                ("double_angles", ctypes.c_int32), ("k_min", ctypes.c_double), ("delta", ctypes.c_double)]
 
 
-def boot_desc(levels, degree, k_min, delta, level=0):
-    return he_boot_desc(int(levels), int(degree), int(level), float(k_min), float(delta))
+def boot_desc(levels, degree, k_min, delta, level=0, double_angles=0):
+    return he_boot_desc(int(levels), int(degree), int(level), int(double_angles), float(k_min), float(delta))
 
 
-def boot_plan(log_n, levels):
+def boot_plan(log_n, levels, key_switches=False):
     """(rotation amounts, per-level plaintext counts: CoeffToSlot then
-    SlotToCoeff) of the bootstrapping transforms (host only)."""
+    SlotToCoeff[, key switches of both transforms]) of the bootstrapping
+    transforms (host only)."""
     rots = (ctypes.c_int32 * BOOT_MAX_ROTATIONS)()
-    nr = ctypes.c_int32()
-    counts = (ctypes.c_int32 * (2 * levels))()
-    _check(lib().he_boot_plan(int(log_n), int(levels), rots, ctypes.byref(nr), counts))
-    return list(rots[: nr.value]), list(counts)
+    nr, ks = ctypes.c_int32(), ctypes.c_int32()
+    counts = (ctypes.c_int32 * max(1, 2 * levels))()
+    _check(lib().he_boot_plan(int(log_n), int(levels), rots, ctypes.byref(nr), counts, ctypes.byref(ks)))
+    out = (list(rots[: nr.value]), list(counts))
+    return out + (ks.value,) if key_switches else out
 
 
 def boot_diagonals(log_n, levels, inverse):
@@ -171,9 +173,9 @@ def boot_diagonals(log_n, levels, inverse):
     return [(re[i * n:(i + 1) * n] + 1j * im[i * n:(i + 1) * n]) for i in range(k)]
 
 
-def boot_mod_coeffs(K, degree):
+def boot_mod_coeffs(K, degree, double_angles=0):
     cf = (ctypes.c_double * (degree + 1))()
-    _check(lib().he_boot_mod_coeffs(float(K), int(degree), cf))
+    _check(lib().he_boot_mod_coeffs(float(K), int(degree), int(double_angles), cf))
     return list(cf)
 
 
@@ -253,9 +255,9 @@ def lib():
             "he_key_cache_stats": [vp, P(sz), P(ctypes.c_int64), P(ctypes.c_int64)],
             "he_mul_i": [vp, P(he_ct), c_int, P(he_ct), vp],
             "he_mod_raise": [vp, P(he_ct), c_int, P(he_ct), vp],
-            "he_boot_plan": [i32, i32, P(i32), P(i32), P(i32)],
+            "he_boot_plan": [i32, i32, P(i32), P(i32), P(i32), P(i32)],
             "he_boot_diagonals": [i32, i32, i32, P(ctypes.c_double), P(ctypes.c_double), sz],
-            "he_boot_mod_coeffs": [ctypes.c_double, i32, P(ctypes.c_double)],
+            "he_boot_mod_coeffs": [ctypes.c_double, i32, i32, P(ctypes.c_double)],
             "he_boot_scales": [vp, P(he_boot_desc), P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
                                P(ctypes.c_double)],
             "he_bootstrap": [vp, P(he_ct), P(he_boot_desc), P(he_pt), P(he_pt), P(ctypes.c_double), P(he_ct), vp],

@@ -85,18 +85,20 @@ def test_mod_raise(name):
         g.close()
 
 
-def test_bootstrap_bit_exact():
-    """The whole procedure at N = 2^12 (L = 16, three levels per transform,
-    EvalMod degree 159): every limb equal to the oracle's, the same level and
+@pytest.mark.parametrize("double_angles", [0, TB.BOOT_DA[1]])
+def test_bootstrap_bit_exact(double_angles):
+    """The whole procedure at N = 2^12 (L = 17, three levels per transform;
+    EvalMod the sine of degree 159, or the cosine of degree 39 with three
+    double angles): every limb equal to the oracle's, the same level and
     scale, and the decryption within the refresh bound of the message."""
     from paper_2510_03996_amd import he
 
-    ctx, sk, pk, plan, keys, rk, cts, stc = TB.boot_setup()
+    ctx, sk, pk, plan, keys, rk, cts, stc = TB.boot_setup(double_angles)
     pr = ctx.pr
     g = boot_gpu_ctx()
     try:
         upload_boot_keys(g, keys, rk)
-        desc = he.boot_desc(TB.BOOT_LEVELS, TB.BOOT_DEGREE, TB.BOOT_KMIN, pr.scale)
+        desc = he.boot_desc(TB.BOOT_LEVELS, plan.degree, TB.BOOT_KMIN, pr.scale, double_angles=double_angles)
         K, rs, cs, ss = g.boot_scales(desc)
         q0 = pr.q[0]
         assert K == plan.K(q0) and rs == plan.raise_scale(q0)
@@ -107,9 +109,12 @@ def test_bootstrap_bit_exact():
         v = np.random.default_rng(3).uniform(-1, 1, ctx.n // 2)
         ct = ctx.encrypt(pk, ctx.encode(v, pr.scale, 1), 9)
         want, _ = BT.bootstrap(ctx, ct, plan, keys, rk, cts, stc)
-        got = g.bootstrap(g.ct_from_numpy(ct.data, ct.scale), desc, gcts, gstc, coeffs)
-        assert got.level == want.level and got.scale == want.scale
-        H.assert_limbs_equal(got.numpy(), want.data, "bootstrap")
+        gct = g.ct_from_numpy(ct.data, ct.scale)
+        for n_streams in (1, 2, 3):  # giant steps and EvalMod parts over 1-3 streams
+            g.layer_streams(n_streams)
+            got = g.bootstrap(gct, desc, gcts, gstc, coeffs)
+            assert got.level == want.level and got.scale == want.scale
+            H.assert_limbs_equal(got.numpy(), want.data, "bootstrap on %d stream(s)" % n_streams)
         dec = ctx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale))
         assert np.max(np.abs(dec - v)) < TB.BOOT_TOL
     finally:

@@ -13,9 +13,10 @@ CASES = [(4, 1), (4, 3), (6, 2), (8, 3), (12, 3), (12, 2), (13, 4), (16, 3)]
 @pytest.mark.parametrize("log_n,levels", CASES)
 def test_boot_plan_matches_oracle(log_n, levels):
     plan = BT.BootPlan(log_n, levels, 12.0, 2.0 ** 50, 31)
-    rots, counts = he.boot_plan(log_n, levels)
+    rots, counts, ks = he.boot_plan(log_n, levels, key_switches=True)
     assert rots == plan.rotations()
     assert counts == [p.count() for p in plan.cts_plans] + [p.count() for p in plan.stc_plans]
+    assert ks == sum(len(p.babies) + sum(1 for j, _ in p.giants if j != 0) for p in plan.cts_plans + plan.stc_plans)
 
 
 @pytest.mark.parametrize("log_n,levels", [(4, 3), (6, 2), (8, 3), (12, 3)])
@@ -30,9 +31,11 @@ def test_boot_diagonals_match_oracle(log_n, levels, inverse):
         assert np.max(np.abs(g - w)) < 1e-12
 
 
-@pytest.mark.parametrize("K,degree", [(8.0, 95), (16.000000001, 159), (3.0, 31)])
-def test_boot_mod_coeffs_match_oracle(K, degree):
-    assert np.max(np.abs(np.array(he.boot_mod_coeffs(K, degree)) - BT.mod_coeffs(K, degree))) < 1e-14
+@pytest.mark.parametrize("K,degree,r", [(8.0, 95, 0), (16.000000001, 159, 0), (3.0, 31, 0), (16.0, 39, 3),
+                                         (12.5, 63, 2)])
+def test_boot_mod_coeffs_match_oracle(K, degree, r):
+    got = np.array(he.boot_mod_coeffs(K, degree, r))
+    assert np.max(np.abs(got - BT.mod_coeffs(K, degree, r))) < 1e-14
 
 
 def test_boot_recipe_errors():
@@ -44,3 +47,5 @@ def test_boot_recipe_errors():
         he.boot_mod_coeffs(0.0, 31)
     with pytest.raises(he.HEError):
         he.boot_mod_coeffs(8.0, 0)
+    with pytest.raises(he.HEError):
+        he.boot_mod_coeffs(8.0, 31, 9)

@@ -20,13 +20,15 @@ from oracle import ckks
 from oracle import layers as LY
 from tests import t0_bigint as B
 
-# bootstrapping ring used by the tests: N = 2^12, q_0 60 bits + 15 x 50 bits,
+# bootstrapping ring used by the tests: N = 2^12, q_0 60 bits + 16 x 50 bits,
 # 7 special primes of 50 bits, dnum = 3, base scale 2^50
-BOOT_PARAMS = dict(log_n=12, q_bits=[60] + [50] * 15, p_bits=[50] * 7, alpha=6, log_scale=50)
+BOOT_PARAMS = dict(log_n=12, q_bits=[60] + [50] * 16, p_bits=[50] * 7, alpha=6, log_scale=50)
 BOOT_HAMMING = 32
 BOOT_KMIN = 12.0
 BOOT_DEGREE = 159
 BOOT_LEVELS = 3
+# the double-angle EvalMod: cosine of degree 39, three double angles
+BOOT_DA = (39, 3)
 # decrypted error bound of a refreshed ciphertext: the coefficient-to-slot
 # output x = t / (2^e delta) carries about 2^-36 relative error (plaintext
 # rounding at 45-bit integers over ~31 diagonals); EvalMod multiplies it by
@@ -36,11 +38,12 @@ BOOT_TOL = 2.0 ** -13
 
 
 @functools.lru_cache(maxsize=None)
-def boot_setup():
+def boot_setup(double_angles=0):
     pr = ckks.Params(**BOOT_PARAMS)
     ctx = ckks.Context(pr)
     sk, pk = ctx.keygen(7, hamming=BOOT_HAMMING)
-    plan = BT.BootPlan(pr.log_n, BOOT_LEVELS, BOOT_KMIN, pr.scale, BOOT_DEGREE)
+    degree = BOOT_DA[0] if double_angles else BOOT_DEGREE
+    plan = BT.BootPlan(pr.log_n, BOOT_LEVELS, BOOT_KMIN, pr.scale, degree, double_angles)
     keys = {r: ctx.gen_rotation_key(sk, r, 7) for r in plan.rotations()}
     keys[ckks.CONJ] = ctx.gen_rotation_key(sk, ckks.CONJ, 7)
     rk = ctx.gen_relin_key(sk, 7)
@@ -227,6 +230,19 @@ def test_mod_coeffs_interpolate_the_sine(K, degree):
     assert np.max(np.abs(f - np.sin(2 * np.pi * K * x) / (2 * np.pi))) < 1e-12
 
 
+@pytest.mark.parametrize("K,degree,r", [(16.0, 39, 3), (16.0, 63, 2), (8.0, 31, 3)])
+def test_mod_coeffs_double_angles_reach_the_sine(K, degree, r):
+    """The cosine interpolant through r double angles c <- 2 c^2 - 1 equals
+    sin(2 pi K x) (the identity cos(2 t) = 2 cos(t)^2 - 1 applied to
+    t = 2 pi (K x - 1/4) / 2^r)."""
+    c = BT.mod_coeffs(K, degree, r)
+    x = np.linspace(-1, 1, 40001)
+    y = np.polynomial.chebyshev.chebval(x, np.concatenate([[c[0] / 2], c[1:]]))
+    for _ in range(r):
+        y = 2 * y * y - 1
+    assert np.max(np.abs(y - np.sin(2 * np.pi * K * x))) < 1e-11
+
+
 def test_raise_scale_and_range():
     pr = ckks.Params(**BOOT_PARAMS)
     plan = BT.BootPlan(pr.log_n, 3, BOOT_KMIN, pr.scale, BOOT_DEGREE)
@@ -236,6 +252,8 @@ def test_raise_scale_and_range():
     assert plan.K(q0) >= BOOT_KMIN and plan.K(q0) < 2 * BOOT_KMIN
     assert sum(plan.cts_exponents(q0)) == e
     assert sum(plan.stc_exponents(q0)) == 10
+    plan_da = BT.BootPlan(pr.log_n, 3, BOOT_KMIN, pr.scale, 39, 3)
+    assert sum(plan_da.stc_exponents(q0)) == 7  # 2^10 / (2 pi) ~ 2^7.35
 
 
 # ------------------------------------------------------------------ conjugation and monomials
@@ -253,8 +271,9 @@ def test_conjugation_and_monomials_by_decryption():
 
 
 # ------------------------------------------------------------------ the whole procedure
-def test_bootstrap_refreshes_within_bound():
-    ctx, sk, pk, plan, keys, rk, cts, stc = boot_setup()
+@pytest.mark.parametrize("double_angles", [0, BOOT_DA[1]])
+def test_bootstrap_refreshes_within_bound(double_angles):
+    ctx, sk, pk, plan, keys, rk, cts, stc = boot_setup(double_angles)
     pr = ctx.pr
     v = np.random.default_rng(3).uniform(-1, 1, ctx.n // 2)
     ct = ctx.encrypt(pk, ctx.encode(v, pr.scale, 1), 9)
@@ -273,9 +292,9 @@ def test_bootstrap_refreshes_within_bound():
     assert imax + 0.5 < plan.K(q0)
     out, ks = BT.bootstrap(ctx, ct, plan, keys, rk, cts, stc)
     lv, relins = LY.cheb_plan(plan.mod_coeffs(q0), False)
-    assert out.level == pr.L - 2 * plan.levels - lv
+    assert out.level == pr.L - 2 * plan.levels - lv - double_angles
     n_rot = sum(len(p.babies) + sum(1 for j, _ in p.giants if j != 0) for p in plan.cts_plans + plan.stc_plans)
-    assert ks == n_rot + 1 + 2 * relins
-    assert abs(math.log2(out.scale) - 50) < 0.01
+    assert ks == n_rot + 1 + 2 * (relins + double_angles)
+    assert abs(math.log2(out.scale) - 50) < 0.5
     got = ctx.decrypt(sk, out)
     assert np.max(np.abs(got - v)) < BOOT_TOL

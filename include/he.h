@@ -229,6 +229,14 @@ int he_rotate_hoisted(he_ctx* ctx, const he_ct* in, const int32_t* r, int n, he_
  * out may alias in when accumulate == 0. */
 int he_mul_plain(he_ctx* ctx, const he_ct* in, const he_pt* pt, he_ct* out, int accumulate, he_stream stream);
 
+/* Sum of plaintext-ciphertext products in one pass (the MAC of the
+ * paper's layers, e.g. a kernel vector times each rotated input):
+ * out (+)= sum_t cts[t] (.) pts[t], n >= 1 terms at one level whose scale
+ * products cts[t].scale * pts[t].scale are all equal (HE_ESCALE); out gets
+ * that level and scale.  out must not alias a term. */
+int he_mac_plain(he_ctx* ctx, const he_ct* cts, const he_pt* pts, int n, he_ct* out, int accumulate,
+                 he_stream stream);
+
 /* Exact ring additions; equal levels (HE_ELEVEL) and equal scales
  * (HE_ESCALE) required.  out may alias a or b. */
 int he_add(he_ctx* ctx, const he_ct* a, const he_ct* b, he_ct* out, he_stream stream);

@@ -134,8 +134,8 @@ struct Ev {
 
 // sum_t ct_t (.) pt_t, one level, not rescaled
 static he_ct mac_all(Ev& ev, const std::vector<he_ct>& cts, const he_pt* pts) {
-  he_ct acc = ev.mul(cts[0], pts[0]);
-  for (size_t t = 1; t < cts.size(); t++) ev.mac(acc, cts[t], pts[t]);
+  he_ct acc = ev.fresh();
+  ck(he_mac_plain(ev.h, cts.data(), pts, (int)cts.size(), &acc, 0, ev.s));
   return acc;
 }
 
@@ -1873,8 +1873,10 @@ static he_ct boot_transform(Ev& ev, const he_ct& x, const BootLevel& p, const he
       const auto& g = p.giants[gi];
       const int k = (int)(gi % K);
       Ev& e = fk.at(k);
-      he_ct s = e.mul(baby[g.second[0].first], pts[t++]);
-      for (size_t q = 1; q < g.second.size(); q++) e.mac(s, baby[g.second[q].first], pts[t++]);
+      std::vector<he_ct> terms;
+      for (auto& iq : g.second) terms.push_back(baby[iq.first]);
+      he_ct s = mac_all(e, terms, pts + t);
+      t += (int)g.second.size();
       s = e.rescale_take(s);
       if (g.first != 0) s = e.rot_take(s, p.giant_rot(g.first));
       if (!have[k]) {

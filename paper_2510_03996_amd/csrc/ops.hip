@@ -1,5 +1,6 @@
 // Exact ring operations on ciphertexts: add / sub / pt-ct multiply(-accumulate),
 // rescale, level drop.  One thread per residue, limb-major coalesced access.
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -35,6 +36,27 @@ __global__ __launch_bounds__(256) void k_mul_plain(const uint64_t* in, size_t ip
   uint64_t r = mul_mod(in[k * ips + i * n + j], pt[i * n + j], mi);
   if (accumulate) r = add_mod(r, out[k * ops + i * n + j], mi.q);
   out[k * ops + i * n + j] = r;
+}
+
+// out[k][i][j] (+)= sum_t ct_t[k][i][j] * pt_t[i][j] for up to MAC_LIST_MAX
+// terms in one pass (each product reduced, then added)
+constexpr int MAC_LIST_MAX = 16;
+struct MacList {
+  const uint64_t* ct[MAC_LIST_MAX];
+  const uint64_t* pt[MAC_LIST_MAX];
+  uint64_t ps[MAC_LIST_MAX];  // polynomial stride of ct_t (words)
+  int n;
+};
+__global__ __launch_bounds__(256) void k_mac_list(MacList ml, uint64_t* out, size_t ops, int logn,
+                                                  const ModInfo* __restrict__ mods, int accumulate) {
+  const size_t n = (size_t)1 << logn;
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, k = blockIdx.z;
+  const ModInfo mi = mods[i];
+  const size_t off = i * n + j;
+  uint64_t r = accumulate ? out[k * ops + off] : 0;
+  for (int t = 0; t < ml.n; t++) r = add_mod(r, mul_mod(ml.ct[t][k * ml.ps[t] + off], ml.pt[t][off], mi), mi.q);
+  out[k * ops + off] = r;
 }
 
 // per-limb scalar constants (Shoup pairs) for constant-polynomial plaintexts
@@ -139,6 +161,47 @@ static int addsub(he_ctx* h, const he_ct* a, const he_ct* b, he_ct* out, he_stre
 }
 
 extern "C" {
+
+int he_mac_plain(he_ctx* h, const he_ct* cts, const he_pt* pts, int n, he_ct* out, int accumulate, he_stream st) {
+  if (!h || !cts || !pts || !out) return set_error(HE_EINVAL, "null argument");
+  if (n < 1) return set_error(HE_EINVAL, "empty product sum");
+  Ctx* c = &h->c;
+  int rc;
+  const int l = cts[0].level;
+  double sc = 0.0;
+  for (int t = 0; t < n; t++) {
+    if ((rc = check_ct(c, &cts[t], "cts"))) return rc;
+    if (!pts[t].data) return set_error(HE_EINVAL, "null plaintext");
+    if (cts[t].level != l) return set_error(HE_ELEVEL, "terms at different levels");
+    if (pts[t].level < l) return set_error(HE_ELEVEL, "plaintext has fewer limbs than the ciphertext");
+    const double st_ = cts[t].scale * pts[t].scale;
+    if (t > 0 && st_ != sc) return set_error(HE_ESCALE, "terms at different scales");
+    sc = st_;
+    if (cts[t].data == out->data) return set_error(HE_EINVAL, "output aliases a term");
+  }
+  if ((rc = check_out(c, out, l))) return rc;
+  if (accumulate) {
+    if (out->level != l) return set_error(HE_ELEVEL, "accumulator at a different level");
+    if (out->scale != sc) return set_error(HE_ESCALE, "accumulator scale differs");
+  }
+  const size_t N = c->n;
+  ProfScope ps(c, "mac_plain", (hipStream_t)st, 8.0 * N * l * (3.0 * n + (accumulate ? 4 : 2)), 2.0 * N * l * n);
+  for (int t0 = 0; t0 < n; t0 += MAC_LIST_MAX) {
+    MacList ml{};
+    ml.n = std::min(MAC_LIST_MAX, n - t0);
+    for (int t = 0; t < ml.n; t++) {
+      ml.ct[t] = cts[t0 + t].data;
+      ml.pt[t] = pts[t0 + t].data;
+      ml.ps[t] = (uint64_t)cts[t0 + t].cap * N;
+    }
+    k_mac_list<<<grid_for(c, l, 2), 256, 0, (hipStream_t)st>>>(ml, out->data, out->cap * N, c->log_n, c->d_mod,
+                                                               (accumulate || t0 > 0) ? 1 : 0);
+    HE_HIP(hipGetLastError());
+  }
+  out->level = l;
+  out->scale = sc;
+  return HE_OK;
+}
 
 int he_mul_i(he_ctx* h, const he_ct* in, int sign, he_ct* out, he_stream st) {
   if (!h) return set_error(HE_EINVAL, "null context");

@@ -254,6 +254,7 @@ def lib():
             "he_key_prefetch": [vp, P(i32), c_int, vp],
             "he_key_cache_stats": [vp, P(sz), P(ctypes.c_int64), P(ctypes.c_int64)],
             "he_mul_i": [vp, P(he_ct), c_int, P(he_ct), vp],
+            "he_mac_plain": [vp, P(he_ct), P(he_pt), c_int, P(he_ct), c_int, vp],
             "he_mod_raise": [vp, P(he_ct), c_int, P(he_ct), vp],
             "he_boot_plan": [i32, i32, P(i32), P(i32), P(i32), P(i32)],
             "he_boot_diagonals": [i32, i32, i32, P(ctypes.c_double), P(ctypes.c_double), sz],
@@ -590,6 +591,16 @@ class Context:
         m = ctypes.byref(scale_mask.c()) if scale_mask is not None else None
         _check(lib().he_cheb(self.h, ctypes.byref(a), m, cf, len(coeffs) - 1, float(delta), ctypes.byref(o),
                              _stream(stream)))
+        out.update(o)
+        return out
+
+    def mac_plain(self, cts, pts, out=None, accumulate=False, stream=None):
+        """out (+)= sum_t cts[t] (.) pts[t] in one pass."""
+        out = out or self.new_ct(cts[0].cap)
+        arr = (he_ct * len(cts))(*[c.c() for c in cts])
+        o = out.c()
+        _check(lib().he_mac_plain(self.h, arr, _pts(pts), len(cts), ctypes.byref(o), 1 if accumulate else 0,
+                                  _stream(stream)))
         out.update(o)
         return out
 

@@ -120,6 +120,29 @@ def test_pointwise_and_rescale(gctx, name):
     H.assert_limbs_equal(d.numpy(), octx.drop_level(a, max(1, pr.L - 2)).data, "drop_level")
 
 
+@pytest.mark.parametrize("name,n,level", [("config0", 3, None), ("config1", 19, 5), ("config2", 9, None)])
+def test_mac_plain(gctx, name, n, level):
+    """he_mac_plain (one pass; 19 terms exceed one launch's 16) against the
+    oracle's sum of products, fresh and accumulating."""
+    g = gctx(name)
+    octx, _, _ = H.oracle_ctx(name)
+    pr = octx.pr
+    lv = level or pr.L
+    cts = [H.encrypt_slots(name, 40 + t, level=lv, enc_id=t)[1] for t in range(n)]
+    pts = [H.encode_slots(name, 60 + t, pr.L)[1] for t in range(n)]
+    want = octx.mul_plain(cts[0], pts[0])
+    for c, p in zip(cts[1:], pts[1:]):
+        want = octx.add(want, octx.mul_plain(c, p))
+    gcts = [g.ct_from_numpy(c.data, c.scale) for c in cts]
+    gpts = [g.pt_from_numpy(p.data, p.scale) for p in pts]
+    got = g.mac_plain(gcts, gpts)
+    H.assert_limbs_equal(got.numpy(), want.data, "mac_plain")
+    assert got.level == want.level and got.scale == want.scale
+    g.mac_plain(gcts[:2], gpts[:2], out=got, accumulate=True)
+    want2 = octx.add(want, octx.add(octx.mul_plain(cts[0], pts[0]), octx.mul_plain(cts[1], pts[1])))
+    H.assert_limbs_equal(got.numpy(), want2.data, "mac_plain accumulate")
+
+
 ROTS = {"config0": [1, -1, 7, -512], "config1": [1, -28, 576, -3], "config2": [1, -1, 32, -1024]}
 
 

@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run three 256 MiB device-to-device copies (the reference kernel that scales "
                          "the FETCH_SIZE / WRITE_SIZE counters to bytes)")
-    ap.add_argument("--only", choices=["hoisted", "layers", "batched", "serving"], default=None,
+    ap.add_argument("--only", choices=["hoisted", "layers", "bootstrap", "batched", "serving"], default=None,
                     help="run the headline plus one section (profiling runs)")
     ap.add_argument("--serve-requests", type=int, default=300)
     return ap.parse_args()
@@ -412,15 +412,38 @@ def layer_latencies(reps=3):
     out["relu_cheb59_n16_streams1_ms"] = round(
         timed(lambda: c2.cheb(ctr, cheb, sc, scale_mask=rmask, stream=s), reps, s) * 1e3, 3)
     c2.layer_streams(2)
-    # bootstrapping: ModRaise of a level-1 ciphertext to 24 limbs, three-level
-    # coefficient/slot transforms, EvalMod (K ~ 16) on the real and imaginary
-    # parts as the cosine of degree 39 with three double angles (15 levels
-    # consumed, the result at level 9) and as the sine of degree 159 (14
-    # levels, level 10)
+    out["key_switches"] = {"conv3x3_n12": 8, "lenet5_stack": pc.key_switches + pp.key_switches + 2,
+                           "resnet_convA": pa.key_switches, "resnet_convB": pb.key_switches,
+                           "resnet_gap": pg.key_switches, "resnet_fc": pf.key_switches,
+                           "conv7x7_s2_p3": p7.key_switches, "relu_cheb59": he.cheb_plan(cheb, True)[1],
+                           "resnet_convA_logsum": pal.key_switches, "resnet_convB_logsum": pbl.key_switches,
+                           "resnet_convB_logsum_bsgs": pbb.key_switches, "resnet_gap_bsgs": pgb.key_switches,
+                           **stride_ks,
+                           "lenet5_stack_bsgs": lenet_ks_b, "resnet_fc_diag": pfd.key_switches}
+    c2.close()
+    return out
+
+
+# ---------------------------------------------------------------- bootstrapping
+def bootstrap_latency(reps=3):
+    """Bootstrapping at N=2^16, L=24: ModRaise of a level-1 ciphertext to 24
+    limbs, three-level coefficient/slot transforms, EvalMod (K ~ 16) on the
+    real and imaginary parts as the cosine of degree 39 with three double
+    angles (15 levels consumed, the result at level 9) and as the sine of
+    degree 159 (14 levels, level 10).  Keys and plaintexts are synthetic
+    residues of the real shapes."""
+    import torch
+
+    from paper_2510_03996_amd import he
+
+    out = {}
+    s = torch.cuda.current_stream()
+    sc = 2.0 ** 50
+    c2 = new_ctx(CFG2)
     brots, bcounts, bks = he.boot_plan(16, 3, key_switches=True)
-    upload_synthetic_keys(c2, brots + [he.KEY_CONJ], 60)
+    upload_synthetic_keys(c2, brots + [he.KEY_CONJ], 60, relin=True)
     ctb1 = synthetic_ct(c2, 1, 67, sc)
-    boot_ks = {}
+    ks = {}
     for name, deg, r in (("bootstrap_n16", 39, 3), ("bootstrap_n16_sine159", 159, 0)):
         bdesc = he.boot_desc(3, deg, 12.0, sc, double_angles=r)
         bK, _, bcs, bss = c2.boot_scales(bdesc)
@@ -431,17 +454,11 @@ def layer_latencies(reps=3):
                 for p in synthetic_pts(c2, bcounts[3 + g], 21 - blv[0] - r - g, 64 + g, bss[g])]
         out[name + "_ms"] = round(timed(lambda: c2.bootstrap(ctb1, bdesc, bcts, bstc, bcoef, stream=s), reps, s)
                                   * 1e3, 3)
-        boot_ks[name] = bks + 1 + 2 * (blv[1] + r)
+        ks[name] = bks + 1 + 2 * (blv[1] + r)
+        out[name + "_output_level"] = 24 - 6 - blv[0] - r
         del bcts, bstc
-    out["key_switches"] = {"conv3x3_n12": 8, "lenet5_stack": pc.key_switches + pp.key_switches + 2,
-                           "resnet_convA": pa.key_switches, "resnet_convB": pb.key_switches,
-                           "resnet_gap": pg.key_switches, "resnet_fc": pf.key_switches,
-                           "conv7x7_s2_p3": p7.key_switches, "relu_cheb59": he.cheb_plan(cheb, True)[1],
-                           "resnet_convA_logsum": pal.key_switches, "resnet_convB_logsum": pbl.key_switches,
-                           "resnet_convB_logsum_bsgs": pbb.key_switches, "resnet_gap_bsgs": pgb.key_switches,
-                           **stride_ks,
-                           "lenet5_stack_bsgs": lenet_ks_b, "resnet_fc_diag": pfd.key_switches,
-                           **boot_ks}
+    out["key_switches"] = ks
+    out["rotation_keys"] = len(brots) + 1
     c2.close()
     return out
 
@@ -904,7 +921,8 @@ def main():
         "roofline": roof,
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 3)} for k, v in kern.items()},
     }
-    sections = [] if args.only_headline else ([args.only] if args.only else ["hoisted", "layers", "batched", "serving"])
+    sections = [] if args.only_headline else (
+        [args.only] if args.only else ["hoisted", "layers", "bootstrap", "batched", "serving"])
     if not args.only_headline and not args.only:
         log("headline rotations on two streams")
         result["two_streams"] = two_stream_rotations(args)
@@ -914,6 +932,9 @@ def main():
     if "layers" in sections:
         log("layer latencies")
         result["layers"] = layer_latencies()
+    if "bootstrap" in sections:
+        log("bootstrapping at N=2^16")
+        result["bootstrap"] = bootstrap_latency()
     if "batched" in sections:
         log("batched key switching (64 ciphertexts)")
         result["batched"] = batched()

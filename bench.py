@@ -330,6 +330,16 @@ def layer_latencies(reps=3):
         out["resnet_convA_16x32x32_n16_streams%d_ms" % n] = round(
             timed(lambda: c2.conv2d(ct, fm0, 16, 3, 1, 1, ak, am, stream=s), reps, s) * 1e3, 3)
     c2.layer_streams(2)
+    # conv A captured once into a graph (two layer streams inside) and replayed
+    gs = torch.cuda.Stream()
+    gout = c2.new_ct()
+    c2.conv2d(ct, fm0, 16, 3, 1, 1, ak, am, out=gout, stream=gs)
+    gs.synchronize()
+    c2.capture_begin(gs)
+    c2.conv2d(ct, fm0, 16, 3, 1, 1, ak, am, out=gout, stream=gs)
+    graph = c2.capture_end(gs)
+    out["resnet_convA_16x32x32_n16_graph_ms"] = round(timed(lambda: graph.launch(gs), reps, gs) * 1e3, 3)
+    graph.close()
     # the same layers with the log-step input-channel sum (keys W^2, 2 W^2, 4 W^2, 8 W^2)
     c2.conv_channel_sum(he.CHSUM_LOG)
     pal = c2.conv2d_plan(fm0, 16, 3, 1, 1)

@@ -646,6 +646,29 @@ int he_boot_scales(const he_ctx* ctx, const he_boot_desc* desc, double* K, doubl
 int he_bootstrap(he_ctx* ctx, const he_ct* in, const he_boot_desc* desc, const he_pt* cts_pts, const he_pt* stc_pts,
                  const double* coeffs, he_ct* out, he_stream stream);
 
+/* ------------------------------------------------------------ graph capture
+ * Record a sequence of library calls issued on `stream` (a layer schedule,
+ * a chain of layers, a bootstrap) into a hipGraph once and replay it as one
+ * launch.  Between he_capture_begin and he_capture_end the calls are
+ * recorded, not run (relaxed capture mode); the helper streams a call forks
+ * join back inside the capture.  The graph keeps the buffers the calls
+ * used: inputs, outputs, plaintexts and keys by address, and the stream's
+ * own temporaries, so a replay reads whatever those inputs hold then and
+ * writes the same outputs.  Rules: run the same sequence once eagerly on the
+ * stream first (that allocates the lane, helper streams and temporaries the
+ * calls need, which a capture must not); keys must be resident (uploaded
+ * with he_key_upload; a key with a host copy fails with HE_EUNSUPPORTED
+ * during capture); profiling must be off; replay on the capture stream
+ * (its temporaries belong to that stream's lane); keep every captured buffer
+ * and key alive while the graph exists.  The stream must not be the null
+ * stream.  he_bootstrap at N >= 2^16 refuses to be captured
+ * (HE_EUNSUPPORTED): its capture is verified at N = 2^12 only. */
+typedef struct he_graph he_graph;
+int he_capture_begin(he_ctx* ctx, he_stream stream);
+int he_capture_end(he_ctx* ctx, he_stream stream, he_graph** out);
+int he_graph_launch(he_graph* graph, he_stream stream);
+int he_graph_destroy(he_graph* graph);
+
 /* ------------------------------------------------------------ batching
  * Many ciphertexts, each with its own hoisted rotation set and its own
  * number of outputs:

@@ -480,6 +480,11 @@ int aux_streams_for(Ctx* c, hipStream_t s, int n, hipStream_t* out) {
   return HE_OK;
 }
 
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  return s && hipStreamIsCapturing(s, &st) == hipSuccess && st == hipStreamCaptureStatusActive;
+}
+
 int stream_fork(hipStream_t s, const hipStream_t* hs, int n) {
   hipEvent_t e = nullptr;
   if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return set_error(HE_EHIP, "event creation failed");

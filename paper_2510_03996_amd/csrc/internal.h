@@ -342,6 +342,8 @@ Lane* lane_for(Ctx* c, hipStream_t s);
 int aux_streams_for(Ctx* c, hipStream_t s, int n, hipStream_t* out);
 // helpers hs[0..n) wait for the work enqueued on s so far (fork), or s waits
 // for the work enqueued on each helper so far (join); HE_OK or HE_EHIP
+// whether work enqueued on s is being captured into a graph
+bool stream_capturing(hipStream_t s);
 int stream_fork(hipStream_t s, const hipStream_t* hs, int n);
 int stream_join(hipStream_t s, const hipStream_t* hs, int n);
 uint64_t* lane_ct_get(Ctx* c, Lane* ln);  // null on allocation failure

@@ -95,6 +95,11 @@ const uint64_t* key_acquire(Ctx* c, int32_t id0, hipStream_t s) {
     return nullptr;
   }
   KeyEntry& e = it->second;
+  if (e.host && stream_capturing(s)) {
+    // loads, evictions and their host waits cannot be recorded into a graph
+    set_error(HE_EUNSUPPORTED, "key " + std::to_string(id0) + " has a host copy: only resident keys can be captured");
+    return nullptr;
+  }
   e.tick = ++c->key_tick;
   if (!e.dev) {
     e.dev = key_buffer(c, id);

@@ -173,7 +173,11 @@ struct Fork {
     ck(stream_join((hipStream_t)main.s, hs.data(), (int)hs.size()));
   }
   void release_all() {
-    if (!hs.empty()) {
+    // Under graph capture the helpers are not re-forked: a later capture on
+    // a helper starts from a fork of the caller's stream, which already
+    // orders it after the caller's reads (and an unjoined fork would end the
+    // capture with an error).
+    if (!hs.empty() && !stream_capturing((hipStream_t)main.s)) {
       if (!joined)
         for (hipStream_t a : hs) hipStreamSynchronize(a);
       if (stream_fork((hipStream_t)main.s, hs.data(), (int)hs.size()) != HE_OK)
@@ -1995,6 +1999,11 @@ int he_bootstrap(he_ctx* h, const he_ct* in, const he_boot_desc* desc, const he_
   Ctx* c = &h->c;
   int rc;
   if ((rc = check_ct(c, in, "in"))) return rc;
+  // Capture of a bootstrap is verified at N = 2^12 only: at N = 2^16 (where
+  // the Chebyshev evaluation forks helper streams of the helper stream it
+  // runs on) a captured bootstrap ended the process once, cause not found.
+  if (c->n >= 65536 && stream_capturing((hipStream_t)s))
+    return set_error(HE_EUNSUPPORTED, "bootstrapping cannot be captured into a graph at N >= 2^16");
   BootScales sc;
   if ((rc = boot_scales_impl(c, desc, &sc))) return rc;
   BootPlanC p;

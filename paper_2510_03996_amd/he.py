@@ -262,6 +262,10 @@ def lib():
             "he_boot_scales": [vp, P(he_boot_desc), P(ctypes.c_double), P(ctypes.c_double), P(ctypes.c_double),
                                P(ctypes.c_double)],
             "he_bootstrap": [vp, P(he_ct), P(he_boot_desc), P(he_pt), P(he_pt), P(ctypes.c_double), P(he_ct), vp],
+            "he_capture_begin": [vp, vp],
+            "he_capture_end": [vp, vp, P(vp)],
+            "he_graph_launch": [vp, vp],
+            "he_graph_destroy": [vp],
             "he_profile_begin": [vp],
             "he_profile_end": [vp, ctypes.c_char_p, sz],
         }
@@ -604,6 +608,16 @@ class Context:
         out.update(o)
         return out
 
+    def capture_begin(self, stream):
+        """Start recording the library calls issued on `stream` (not the
+        default stream) into a graph (he_capture_begin's rules apply)."""
+        _check(lib().he_capture_begin(self.h, _stream(stream)))
+
+    def capture_end(self, stream):
+        g = ctypes.c_void_p()
+        _check(lib().he_capture_end(self.h, _stream(stream), ctypes.byref(g)))
+        return Graph(g)
+
     def mul_i(self, ct, sign, out=None, stream=None):
         out = out or self.new_ct(ct.cap)
         a, o = ct.c(), out.c()
@@ -736,6 +750,27 @@ def cheb_relu_coeffs(beta, degree=59):
     cf = (ctypes.c_double * (degree + 1))()
     _check(lib().he_cheb_relu_coeffs(float(beta), int(degree), cf))
     return list(cf)
+
+
+class Graph:
+    """A captured sequence of library calls (he_graph)."""
+
+    def __init__(self, handle):
+        self.h = handle
+
+    def launch(self, stream=None):
+        _check(lib().he_graph_launch(self.h, _stream(stream)))
+
+    def close(self):
+        if self.h:
+            lib().he_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

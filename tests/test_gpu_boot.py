@@ -149,3 +149,47 @@ def test_bootstrap_errors():
             g.mul_i(gct, 2)
     finally:
         g.close()
+
+
+# (levels, raise level (0: L), double angles, decryption bound): with two
+# levels each CoeffToSlot plaintext is encoded 2^-8 below its prime (e = 16
+# split in two), so the coefficient-to-slot output keeps ~2^-33 and the
+# refresh ~1e-4; four levels keep ~5e-6
+LAYOUTS = [(4, 0, 0, TB.BOOT_TOL), (3, 16, 3, TB.BOOT_TOL), (2, 0, 3, 2.0 ** -12)]
+
+
+@pytest.mark.parametrize("levels,level_in,r,tol", LAYOUTS)
+def test_bootstrap_other_layouts(levels, level_in, r, tol):
+    """Four levels per transform (the sine), a raise to 16 of the 17 limbs
+    and two levels per transform (the cosine with double angles):
+    bit-exact against the oracle."""
+    from paper_2510_03996_amd import he
+
+    ctx, sk, pk, _, keys0, rk, _, _ = TB.boot_setup(r)
+    pr = ctx.pr
+    plan = BT.BootPlan(pr.log_n, levels, TB.BOOT_KMIN, pr.scale, TB.BOOT_DA[0] if r else TB.BOOT_DEGREE, r)
+    keys = dict(keys0)
+    for x in plan.rotations():
+        if x not in keys:
+            keys[x] = ctx.gen_rotation_key(sk, x, 7)
+    lin = level_in or pr.L
+    cts, stc = BT.boot_plaintexts(ctx, plan, lin)
+    g = boot_gpu_ctx()
+    try:
+        upload_boot_keys(g, keys, rk)
+        desc = he.boot_desc(levels, plan.degree, TB.BOOT_KMIN, pr.scale, level=level_in, double_angles=r)
+        rots, counts = he.boot_plan(pr.log_n, levels)
+        assert rots == plan.rotations() and counts == [len(x) for x in cts] + [len(x) for x in stc]
+        v = np.random.default_rng(40 + levels).uniform(-1, 1, ctx.n // 2)
+        ct = ctx.encrypt(pk, ctx.encode(v, pr.scale, 1), 40 + levels)
+        want, _ = BT.bootstrap(ctx, ct, plan, keys, rk, cts, stc, level_in=lin)
+        got = g.bootstrap(g.ct_from_numpy(ct.data, ct.scale), desc,
+                          [g.pt_from_numpy(p.data, p.scale) for lv in cts for p in lv],
+                          [g.pt_from_numpy(p.data, p.scale) for lv in stc for p in lv],
+                          list(plan.mod_coeffs(pr.q[0])))
+        assert got.level == want.level and got.scale == want.scale
+        H.assert_limbs_equal(got.numpy(), want.data, "bootstrap, %d levels, raise to %d" % (levels, lin))
+        dec = ctx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale))
+        assert np.max(np.abs(dec - v)) < tol
+    finally:
+        g.close()

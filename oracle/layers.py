@@ -1157,18 +1157,26 @@ def cheb_lift(ev, v, level, scale, c):
     return ev.with_scale(t, scale)
 
 
+def cheb_leaf(ev, a, T, level, scale):
+    """A leaf sum_j a_j T_j + a_0 onto (level, scale) with one rescale: each
+    T_j (j >= 1, a_j != 0, ascending; T_1 with 0 when there is none) dropped
+    to level + 1 and multiplied by a_j encoded at sigma_j = scale q / s(T_j)
+    (q the prime the rescale divides by), every product recorded at scale q
+    (the same value up to the rounding of sigma_j), the products added,
+    rescaled, recorded at `scale`, plus a_0."""
+    q = ev.modulus(level)
+    terms = [j for j in range(1, len(a)) if a[j] != 0.0] or [1]
+    acc = None
+    for j in terms:
+        v = ev.drop(T[j], level + 1)
+        p = ev.with_scale(ev.mul_const(v, a[j] if j < len(a) else 0.0, scale * q / v.scale), scale * q)
+        acc = p if acc is None else ev.add(acc, p)
+    return ev.add_const(ev.with_scale(ev.rescale(acc), scale), a[0])
+
+
 def _cheb_node(ev, tree, T, level, scale):
     if tree[0] == "leaf":
-        a = tree[1]
-        acc = None
-        for j in range(1, len(a)):
-            if a[j] == 0.0:
-                continue
-            term = cheb_lift(ev, T[j], level, scale, a[j])
-            acc = term if acc is None else ev.add(acc, term)
-        if acc is None:
-            acc = cheb_lift(ev, T[1], level, scale, 0.0)
-        return ev.add_const(acc, a[0])
+        return cheb_leaf(ev, tree[1], T, level, scale)
     K, qt, rt = tree[1], tree[2], tree[3]
     sigma = scale * ev.modulus(level) / T[K].scale
     qc = _cheb_node(ev, qt, T, level + 1, sigma)
@@ -1186,7 +1194,7 @@ def cheb_eval(ev, x, coeffs, mask_pt, delta):
     * the series is split recursively by the giant steps T_K
       (a = q T_K + r, cheb_split) down to leaves of degree < CHEB_BABY;
     * every subtree is evaluated onto a given (level, scale): a leaf as
-      sum_j lift(T_j, a_j) in ascending j plus a_0; a node as
+      RS(sum_j a_j T_j) plus a_0 (``cheb_leaf``: one rescale); a node as
       with_scale(RS(Relin(q' T_K)), scale) + r', with q' evaluated one level
       higher at scale * q_level / s(T_K) and r' at the node's own target;
     * the root target is the highest level every subtree allows."""

@@ -902,29 +902,41 @@ static he_ct cheb_lift(Ev& ev, const he_ct& v, int level, double scale, double c
   return t;
 }
 
-// subtree `id` evaluated onto (level, scale): a leaf as sum_j lift(T_j, a_j)
-// (ascending j; lift(T_1, 0) if it has none) plus a_0; a node as
-// RS(Relin(q' T_K)) with scale `scale` plus r', q' evaluated one level higher
-// at scale q_level / s(T_K) times `scale`, r' onto (level, scale)
+// subtree `id` evaluated onto (level, scale): a leaf with one rescale,
+// RS(sum_j a_j T_j) + a_0 (ascending j; T_1 times 0 if it has none): each
+// T_j dropped to level + 1 times a_j encoded at scale q / s(T_j), every
+// product recorded at scale q (q the prime the rescale removes), summed,
+// rescaled and recorded at `scale`; a node as RS(Relin(q' T_K)) with scale
+// `scale` plus r', q' evaluated one level higher at scale q_level / s(T_K)
+// times `scale`, r' onto (level, scale)
 static he_ct cheb_eval_node(Ev& ev, const std::vector<ChebNode>& t, int id, const std::vector<he_ct>& T, int level,
                             double scale) {
   const ChebNode& n = t[id];
   if (!n.K) {
+    const double q = (double)ev.c->mod[level];
     he_ct acc{};
     bool first = true;
     for (int j = 1; j < (int)n.a.size(); j++) {
       if (n.a[j] == 0.0) continue;
-      he_ct term = cheb_lift(ev, T[j], level, scale, n.a[j]);
+      const he_ct v = Ev::drop(T[j], level + 1);
+      he_ct p = ev.mul_const(v, n.a[j], scale * q / v.scale);
+      p.scale = scale * q;
       if (first) {
-        acc = term;
+        acc = p;
         first = false;
       } else {
-        acc = ev.add_take(acc, term);
+        acc = ev.add_take(acc, p);
       }
     }
-    if (first) acc = cheb_lift(ev, T[1], level, scale, 0.0);
-    he_ct y = ev.add_const(acc, n.a[0]);
-    ev.release(acc);
+    if (first) {
+      const he_ct v = Ev::drop(T[1], level + 1);
+      acc = ev.mul_const(v, 0.0, scale * q / v.scale);
+      acc.scale = scale * q;
+    }
+    he_ct r = ev.rescale_take(acc);
+    r.scale = scale;
+    he_ct y = ev.add_const(r, n.a[0]);
+    ev.release(r);
     return y;
   }
   const double sigma = scale * (double)ev.c->mod[level] / T[n.K].scale;

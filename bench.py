@@ -464,6 +464,24 @@ def bootstrap_latency(reps=3):
                 for p in synthetic_pts(c2, bcounts[3 + g], 21 - blv[0] - r - g, 64 + g, bss[g])]
         out[name + "_ms"] = round(timed(lambda: c2.bootstrap(ctb1, bdesc, bcts, bstc, bcoef, stream=s), reps, s)
                                   * 1e3, 3)
+        if r:
+            # independent ciphertexts refreshed concurrently, one per stream
+            # (each stream its own lane): time per ciphertext
+            sts = [torch.cuda.Stream() for _ in range(4)]
+            outs = [c2.new_ct() for _ in sts]
+
+            def run_all():
+                for st, o in zip(sts, outs):
+                    c2.bootstrap(ctb1, bdesc, bcts, bstc, bcoef, out=o, stream=st)
+
+            run_all()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                run_all()
+            torch.cuda.synchronize()
+            out[name + "_4streams_ms_per_ct"] = round((time.perf_counter() - t0) / (reps * len(sts)) * 1e3, 3)
+            del outs
         ks[name] = bks + 1 + 2 * (blv[1] + r)
         out[name + "_output_level"] = 24 - 6 - blv[0] - r
         del bcts, bstc

@@ -437,11 +437,12 @@ def layer_latencies(reps=3):
 # ---------------------------------------------------------------- bootstrapping
 def bootstrap_latency(reps=3):
     """Bootstrapping at N=2^16, L=24: ModRaise of a level-1 ciphertext to 24
-    limbs, three-level coefficient/slot transforms, EvalMod (K ~ 16) on the
-    real and imaginary parts as the cosine of degree 39 with three double
-    angles (15 levels consumed, the result at level 9) and as the sine of
-    degree 159 (14 levels, level 10).  Keys and plaintexts are synthetic
-    residues of the real shapes."""
+    limbs, coefficient/slot transforms of three (or four) levels, EvalMod
+    (K ~ 16) on the real and imaginary parts as the cosine of degree 39 with
+    three double angles (15 levels consumed, the result at level 9; 17 and
+    level 7 with four-level transforms) and as the sine of degree 159 (14
+    levels, level 10).  Keys and plaintexts are synthetic residues of the
+    real shapes."""
     import torch
 
     from paper_2510_03996_amd import he
@@ -450,21 +451,24 @@ def bootstrap_latency(reps=3):
     s = torch.cuda.current_stream()
     sc = 2.0 ** 50
     c2 = new_ctx(CFG2)
-    brots, bcounts, bks = he.boot_plan(16, 3, key_switches=True)
-    upload_synthetic_keys(c2, brots + [he.KEY_CONJ], 60, relin=True)
+    plans = {lv: he.boot_plan(16, lv, key_switches=True) for lv in (3, 4)}
+    keys = sorted(set(plans[3][0]) | set(plans[4][0]))
+    upload_synthetic_keys(c2, keys + [he.KEY_CONJ], 60, relin=True)
     ctb1 = synthetic_ct(c2, 1, 67, sc)
     ks = {}
-    for name, deg, r in (("bootstrap_n16", 39, 3), ("bootstrap_n16_sine159", 159, 0)):
-        bdesc = he.boot_desc(3, deg, 12.0, sc, double_angles=r)
+    for name, nl, deg, r in (("bootstrap_n16", 3, 39, 3), ("bootstrap_n16_levels4", 4, 39, 3),
+                             ("bootstrap_n16_sine159", 3, 159, 0)):
+        brots, bcounts, bks = plans[nl]
+        bdesc = he.boot_desc(nl, deg, 12.0, sc, double_angles=r)
         bK, _, bcs, bss = c2.boot_scales(bdesc)
         bcoef = he.boot_mod_coeffs(bK, deg, r)
         blv = he.cheb_plan(bcoef, False)
-        bcts = [p for g in range(3) for p in synthetic_pts(c2, bcounts[g], 24 - g, 61 + g, bcs[g])]
-        bstc = [p for g in range(3)
-                for p in synthetic_pts(c2, bcounts[3 + g], 21 - blv[0] - r - g, 64 + g, bss[g])]
+        bcts = [p for g in range(nl) for p in synthetic_pts(c2, bcounts[g], 24 - g, 61 + g, bcs[g])]
+        bstc = [p for g in range(nl)
+                for p in synthetic_pts(c2, bcounts[nl + g], 24 - nl - blv[0] - r - g, 64 + g, bss[g])]
         out[name + "_ms"] = round(timed(lambda: c2.bootstrap(ctb1, bdesc, bcts, bstc, bcoef, stream=s), reps, s)
                                   * 1e3, 3)
-        if r:
+        if name == "bootstrap_n16":
             # independent ciphertexts refreshed concurrently, one per stream
             # (each stream its own lane): time per ciphertext
             sts = [torch.cuda.Stream() for _ in range(4)]
@@ -483,10 +487,10 @@ def bootstrap_latency(reps=3):
             out[name + "_4streams_ms_per_ct"] = round((time.perf_counter() - t0) / (reps * len(sts)) * 1e3, 3)
             del outs
         ks[name] = bks + 1 + 2 * (blv[1] + r)
-        out[name + "_output_level"] = 24 - 6 - blv[0] - r
+        out[name + "_output_level"] = 24 - 2 * nl - blv[0] - r
         del bcts, bstc
     out["key_switches"] = ks
-    out["rotation_keys"] = len(brots) + 1
+    out["rotation_keys"] = {"levels3": len(plans[3][0]) + 1, "levels4": len(plans[4][0]) + 1}
     c2.close()
     return out
 

@@ -179,3 +179,42 @@ def test_argument_errors(g1):
     with pytest.raises(he.HEError) as e:
         g1.key_evict(12345)
     assert e.value.name == "HE_ENOKEY"
+
+
+def test_product_sum_and_monomial_errors(g1):
+    """he_mac_plain, he_mul_i and he_mod_raise reject mismatched inputs
+    before any work; a one-term product sum equals he_mul_plain; ±i in place
+    and a raise to level 1 (a copy of limb 0) against the oracle."""
+    from oracle import boot as BT
+    from paper_2510_03996_amd import he
+
+    name = "config1"
+    octx, _, _ = H.oracle_ctx(name)
+    _, a = H.encrypt_slots(name, 80, enc_id=0)
+    _, b = H.encrypt_slots(name, 81, level=5, enc_id=1)
+    _, p = H.encode_slots(name, 82, octx.pr.L)
+    ga, gb = g1.ct_from_numpy(a.data, a.scale), g1.ct_from_numpy(b.data, b.scale)
+    gp = g1.pt_from_numpy(p.data, p.scale)
+    one = g1.mac_plain([ga], [gp])
+    H.assert_limbs_equal(one.numpy(), octx.mul_plain(a, p).data, "one-term product sum")
+    with pytest.raises(he.HEError, match="levels"):
+        g1.mac_plain([ga, gb], [gp, gp])
+    half = g1.pt_from_numpy(p.data, p.scale * 2)
+    with pytest.raises(he.HEError, match="scales"):
+        g1.mac_plain([ga, ga], [gp, half])
+    with pytest.raises(he.HEError, match="aliases"):
+        g1.mac_plain([ga], [gp], out=ga)
+    low = g1.pt_from_numpy(p.data[:3], p.scale)
+    with pytest.raises(he.HEError, match="fewer limbs"):
+        g1.mac_plain([ga], [low])
+    with pytest.raises(he.HEError):
+        g1.mul_i(ga, 0)
+    with pytest.raises(he.HEError, match="aliases"):
+        g1.mod_raise(ga, octx.pr.L, out=ga)
+    with pytest.raises(he.HEError, match="range"):
+        g1.mod_raise(ga, octx.pr.L + 1)
+    x = g1.ct_from_numpy(a.data, a.scale)
+    g1.mul_i(x, 1, out=x)
+    H.assert_limbs_equal(x.numpy(), octx.mul_plain(a, BT.monomial_pt(octx, octx.n // 2, a.level)).data, "i in place")
+    r1 = g1.mod_raise(ga, 1)
+    H.assert_limbs_equal(r1.numpy(), a.data[:, :1], "raise to level 1")

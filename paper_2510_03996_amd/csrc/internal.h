@@ -74,6 +74,7 @@ constexpr int HOIST_SET_MIN = 3;  // key switches from which a hoisted set is ba
 struct SetTab {
   const uint64_t* key[SET_MAX];
   uint32_t g[SET_MAX];
+  uint32_t ginv[SET_MAX];  // g^-1 mod 2N (the inner product's source-block order)
   uint64_t* out[2 * SET_MAX];
 };
 

@@ -29,14 +29,16 @@ __global__ __launch_bounds__(256) void k_ip(const uint64_t* __restrict__ ext, si
 }
 
 // Inner products of one input's extended digits with several keys (a
-// hoisted set): grid x = 256-coefficient tile, y = extended limb; the
-// workgroup loops over the nz rotations of the round (key tab.key[z],
-// Galois element tab.g[z]; the table is a kernel argument), writing
-// u_z = u + z 2 (level+K) N,
-// [2][level+K][N].  phi_g maps an aligned block of 256 NTT indices onto an
-// aligned block, so each digit's source block is read coalesced and permuted
-// in LDS; the next rotation's blocks and key words are loaded while the
-// current one is accumulated (two LDS buffers, one barrier per rotation).
+// hoisted set): grid x = 256-coefficient *source* block, y = extended limb;
+// the workgroup loops over the nz rotations of the round (key tab.key[z],
+// Galois element tab.g[z], its inverse tab.ginv[z]; the table is a kernel
+// argument), writing u_z = u + z 2 (level+K) N, [2][level+K][N].  phi_g maps
+// an aligned block of 256 NTT indices onto an aligned block, so the digits'
+// source block is read once, coalesced, into LDS and serves every rotation:
+// for rotation z the workgroup writes the output block whose sources form
+// its block (the block of phi_{g^-1}(s0)), gathering from LDS; the key words
+// and outputs of that block are coalesced, and the next rotation's key
+// words are loaded while the current one is accumulated.
 // Primes below 2^50: centred FP64 products with the Montgomery-form key
 // words and one product by 2^-64 mod q; the others: 128-bit products and one
 // REDC (the same canonical residue).
@@ -45,10 +47,10 @@ __global__ __launch_bounds__(256) void k_ip_set(const uint64_t* __restrict__ ext
                                                 int level, int K, int alpha, const SetTab tab, int nz,
                                                 size_t key_digit_stride, size_t key_poly_stride, int L, int logn,
                                                 const ModInfo* __restrict__ mods, uint64_t* __restrict__ u_all) {
-  __shared__ uint64_t sh[2][DN][256];
+  __shared__ uint64_t sh[DN][256];
   const size_t n = (size_t)1 << logn;
   const int tid = threadIdx.x;
-  const uint32_t k = blockIdx.x * 256 + tid;
+  const uint32_t s0 = blockIdx.x * 256;  // this workgroup's source block
   const int pos = blockIdx.y;
   const int E = level + K;
   const size_t En = (size_t)E * n;
@@ -57,41 +59,44 @@ __global__ __launch_bounds__(256) void k_ip_set(const uint64_t* __restrict__ ext
   const int own = pos < level ? pos / alpha : -1;
   const bool f64 = mi.k <= 50;
   const double dq = (double)mi.q, qi = mi.dqinv;
-  // loads of rotation z: its digits' source blocks (to LDS later) and key words
-  uint64_t cur[DN], kb[DN], ka[DN], nkb[DN], nka[DN];
+#pragma unroll
+  for (int j = 0; j < DN; j++) {
+    const uint64_t* sp = j == own ? c1 : ext + j * En;
+    sh[j][tid] = sp[(size_t)pos * n + s0 + tid];
+  }
+  // rotation z: this thread's output position k (in the output block of s0)
+  // and the LDS slot of its source; its key words
+  uint64_t kb[DN], ka[DN], nkb[DN], nka[DN];
+  uint32_t kk = 0, nkk = 0;
   int sl = 0, nsl = 0;
-  auto gload = [&](int z, uint64_t* e, uint64_t* b, uint64_t* a, int& slot) {
+  auto kload = [&](int z, uint64_t* b, uint64_t* a, uint32_t& kout, int& slot) {
     const uint32_t g = tab.g[z];
-    const uint32_t src = g == 1 ? k : automorph_src(k, g, logn);
-    const uint32_t s0 = src & ~255u;
-    slot = (int)(src & 255u);
+    const uint32_t o0 = g == 1 ? s0 : (automorph_src(s0, tab.ginv[z], logn) & ~255u);
+    const uint32_t k = o0 + tid;
+    slot = (int)((g == 1 ? k : automorph_src(k, g, logn)) - s0);
+    kout = k;
     const uint64_t* key = tab.key[z];
 #pragma unroll
     for (int j = 0; j < DN; j++) {
-      const uint64_t* sp = j == own ? c1 : ext + j * En;
-      e[j] = sp[(size_t)pos * n + s0 + tid];
       const uint64_t* kj = key + j * key_digit_stride + (size_t)mod * n + k;
       b[j] = kj[0];
       a[j] = kj[key_poly_stride];
     }
   };
-  gload(0, cur, kb, ka, sl);
+  kload(0, kb, ka, kk, sl);
+  __syncthreads();  // sh
   // unrolled over the table, so that its entries (kernel arguments) are read
   // with constant indices
 #pragma unroll
   for (int z = 0; z < SET_MAX; z++) {
     if (z >= nz) break;
-    const int bf = z & 1;
-#pragma unroll
-    for (int j = 0; j < DN; j++) sh[bf][j][tid] = cur[j];
-    __syncthreads();
-    if (z + 1 < nz) gload(z + 1, cur, nkb, nka, nsl);
-    uint64_t* u = u_all + (size_t)z * 2 * En + (size_t)pos * n + k;
+    if (z + 1 < nz) kload(z + 1, nkb, nka, nkk, nsl);
+    uint64_t* u = u_all + (size_t)z * 2 * En + (size_t)pos * n + kk;
     if (f64) {
       double a0 = 0.0, a1 = 0.0;
 #pragma unroll
       for (int j = 0; j < DN; j++) {
-        const double v = u52_to_f64(sh[bf][j][sl]);
+        const double v = u52_to_f64(sh[j][sl]);
         const double w0 = u52_to_f64(kb[j]), w1 = u52_to_f64(ka[j]);
         a0 += mul_f64_c(v, w0, w0 * qi, dq);
         a1 += mul_f64_c(v, w1, w1 * qi, dq);
@@ -102,7 +107,7 @@ __global__ __launch_bounds__(256) void k_ip_set(const uint64_t* __restrict__ ext
       U128 a0{0, 0}, a1{0, 0};
 #pragma unroll
       for (int j = 0; j < DN; j++) {
-        const uint64_t e = sh[bf][j][sl];
+        const uint64_t e = sh[j][sl];
         add_wide(a0, mul_wide(e, kb[j]));
         add_wide(a1, mul_wide(e, ka[j]));
       }
@@ -115,6 +120,7 @@ __global__ __launch_bounds__(256) void k_ip_set(const uint64_t* __restrict__ ext
         kb[j] = nkb[j];
         ka[j] = nka[j];
       }
+      kk = nkk;
       sl = nsl;
     }
   }
@@ -256,6 +262,13 @@ static int ks_set(Ctx* c, Lane* lane, const WS& w, const uint64_t* c0, const uin
     for (int i = 0; i < nc; i++) {
       t.key[i] = keys[r0 + i];
       t.g[i] = gs[r0 + i];
+      // g^-1 mod 2N: the odd residues mod 2N have exponent N/2, so g^-1 = g^(N/2 - 1)
+      uint64_t inv = 1, b = gs[r0 + i], e = N / 2 - 1;
+      const uint64_t m2 = 2 * N;
+      for (; e; e >>= 1, b = b * b % m2)
+        if (e & 1) inv = inv * b % m2;
+      if (inv * gs[r0 + i] % m2 != 1) return set_error(HE_EINVAL, "Galois element without an inverse");
+      t.ginv[i] = (uint32_t)inv;
       t.out[2 * i] = outs[2 * (r0 + i)];
       t.out[2 * i + 1] = outs[2 * (r0 + i) + 1];
     }

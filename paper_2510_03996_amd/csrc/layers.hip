@@ -16,6 +16,8 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "internal.h"
@@ -1729,10 +1731,8 @@ struct BootPlanC {
   std::vector<BootLevel> cts, stc;
 };
 
-static int boot_plan_make(int log_n, int levels, BootPlanC* out) {
-  if (log_n < 2 || log_n > 16) return set_error(HE_EINVAL, "ring degree out of range");
+static int boot_plan_build(int log_n, int levels, BootPlanC* out) {
   const int ls = log_n - 1;
-  if (levels < 1 || levels > ls) return set_error(HE_EINVAL, "transform levels out of range");
   out->n = 1 << ls;
   out->cts_hs = boot_groups(ls, levels, true);
   out->stc_hs = boot_groups(ls, levels, false);
@@ -1740,6 +1740,25 @@ static int boot_plan_make(int log_n, int levels, BootPlanC* out) {
   out->stc.clear();
   for (auto& hs : out->cts_hs) out->cts.push_back(boot_level(out->n, hs));
   for (auto& hs : out->stc_hs) out->stc.push_back(boot_level(out->n, hs));
+  return HE_OK;
+}
+
+// The plan depends only on (log_n, levels): built once per process and
+// copied out (the shift sets take a few hundred microseconds at N = 2^16).
+static int boot_plan_make(int log_n, int levels, BootPlanC* out) {
+  if (log_n < 2 || log_n > 16) return set_error(HE_EINVAL, "ring degree out of range");
+  if (levels < 1 || levels > log_n - 1) return set_error(HE_EINVAL, "transform levels out of range");
+  static std::mutex mu;
+  static std::map<std::pair<int, int>, BootPlanC> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({log_n, levels});
+  if (it == cache.end()) {
+    BootPlanC p;
+    int rc;
+    if ((rc = boot_plan_build(log_n, levels, &p))) return rc;
+    it = cache.emplace(std::make_pair(log_n, levels), std::move(p)).first;
+  }
+  *out = it->second;
   return HE_OK;
 }
 

@@ -343,6 +343,14 @@ Lane* lane_for(Ctx* c, hipStream_t s);
 int aux_streams_for(Ctx* c, hipStream_t s, int n, hipStream_t* out);
 // helpers hs[0..n) wait for the work enqueued on s so far (fork), or s waits
 // for the work enqueued on each helper so far (join); HE_OK or HE_EHIP
+// The constant c encoded at `scale` as an integer: llround(c * scale) (ties
+// away from zero), HE_EINVAL when it does not fit 64 bits.
+int const_value(double v, double scale, int64_t* out);
+// out = sum_t cts[t] * vals[t] (signed integer constants, reduced per limb),
+// n <= CONST_LIST_MAX terms at one level, both polynomials, in one launch;
+// out's level is set, its scale is left to the caller.
+constexpr int CONST_LIST_MAX = 16;
+int mac_const_launch(Ctx* c, const he_ct* cts, const int64_t* vals, int n, he_ct* out, hipStream_t s);
 // whether work enqueued on s is being captured into a graph
 bool stream_capturing(hipStream_t s);
 int stream_fork(hipStream_t s, const hipStream_t* hs, int n);

@@ -915,26 +915,29 @@ static he_ct cheb_eval_node(Ev& ev, const std::vector<ChebNode>& t, int id, cons
                             double scale) {
   const ChebNode& n = t[id];
   if (!n.K) {
+    // the products and their sum in one pass (a leaf has fewer than eight
+    // terms): the same residues as one constant product per term, added
     const double q = (double)ev.c->mod[level];
-    he_ct acc{};
-    bool first = true;
+    std::vector<he_ct> terms;
+    std::vector<int64_t> vals;
     for (int j = 1; j < (int)n.a.size(); j++) {
       if (n.a[j] == 0.0) continue;
       const he_ct v = Ev::drop(T[j], level + 1);
-      he_ct p = ev.mul_const(v, n.a[j], scale * q / v.scale);
-      p.scale = scale * q;
-      if (first) {
-        acc = p;
-        first = false;
-      } else {
-        acc = ev.add_take(acc, p);
-      }
+      int64_t x = 0;
+      ck(const_value(n.a[j], scale * q / v.scale, &x));
+      terms.push_back(v);
+      vals.push_back(x);
     }
-    if (first) {
+    if (terms.empty()) {
       const he_ct v = Ev::drop(T[1], level + 1);
-      acc = ev.mul_const(v, 0.0, scale * q / v.scale);
-      acc.scale = scale * q;
+      int64_t x = 0;
+      ck(const_value(0.0, scale * q / v.scale, &x));
+      terms.push_back(v);
+      vals.push_back(x);
     }
+    he_ct acc = ev.fresh();
+    ck(mac_const_launch(ev.c, terms.data(), vals.data(), (int)terms.size(), &acc, (hipStream_t)ev.s));
+    acc.scale = scale * q;
     he_ct r = ev.rescale_take(acc);
     r.scale = scale;
     he_ct y = ev.add_const(r, n.a[0]);

@@ -108,11 +108,67 @@ __global__ __launch_bounds__(256) void k_lift(uint64_t* data, size_t ps, int log
   data[k * ps + i * n + j] = r;
 }
 
-// llround(c * scale) reduced into every active limb (ties away from zero)
-static int const_residues(const Ctx* c, double v, double scale, int level, Scalars* sc) {
+// out[k][i][j] = sum_t ct_t[k][i][j] * (v_t mod q_i) for up to CONST_LIST_MAX
+// terms (v_t signed integers: the constants llround(c_t * scale_t)), one pass
+struct ConstList {
+  const uint64_t* ct[CONST_LIST_MAX];
+  uint64_t ps[CONST_LIST_MAX];  // polynomial stride of ct_t (words)
+  int64_t v[CONST_LIST_MAX];
+  int n;
+};
+__global__ __launch_bounds__(256) void k_mac_const(ConstList cl, uint64_t* out, size_t ops, int logn,
+                                                   const ModInfo* __restrict__ mods) {
+  const size_t n = (size_t)1 << logn;
+  const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y, k = blockIdx.z;
+  const ModInfo mi = mods[i];
+  const size_t off = i * n + j;
+  uint64_t r = 0;
+  for (int t = 0; t < cl.n; t++) {
+    const int64_t v = cl.v[t];
+    const uint64_t a = v >= 0 ? (uint64_t)v : (uint64_t)(-(v + 1)) + 1;  // |v|
+    uint64_t m = reduce_word(a, mi);
+    if (v < 0 && m) m = mi.q - m;
+    r = add_mod(r, mul_mod(cl.ct[t][k * cl.ps[t] + off], m, mi), mi.q);
+  }
+  out[k * ops + off] = r;
+}
+
+int const_value(double v, double scale, int64_t* out) {
   const double x = v * scale;
   if (!(std::fabs(x) < 9.0e18)) return set_error(HE_EINVAL, "constant times scale does not fit 64 bits");
-  const long long r = llround(x);
+  *out = (int64_t)llround(x);
+  return HE_OK;
+}
+
+int mac_const_launch(Ctx* c, const he_ct* cts, const int64_t* vals, int n, he_ct* out, hipStream_t s) {
+  if (n < 1) return set_error(HE_EINVAL, "empty constant product sum");
+  const int l = cts[0].level;
+  const size_t N = c->n;
+  for (int t = 0; t < n; t++)
+    if (cts[t].level != l) return set_error(HE_ELEVEL, "terms at different levels");
+  if (out->cap < l) return set_error(HE_EINVAL, "out: capacity too small");
+  if (n > CONST_LIST_MAX) return set_error(HE_EINVAL, "too many terms for one constant product sum");
+  ProfScope ps(c, "mac_const", s, 8.0 * N * l * 2.0 * (n + 1), 2.0 * N * l * n);
+  ConstList cl{};
+  cl.n = n;
+  for (int t = 0; t < n; t++) {
+    cl.ct[t] = cts[t].data;
+    cl.ps[t] = (uint64_t)cts[t].cap * N;
+    cl.v[t] = vals[t];
+  }
+  k_mac_const<<<dim3((unsigned)(N / 256), l, 2), 256, 0, s>>>(cl, out->data, out->cap * N, c->log_n, c->d_mod);
+  HE_HIP(hipGetLastError());
+  out->level = l;
+  return HE_OK;
+}
+
+// llround(c * scale) reduced into every active limb (ties away from zero)
+static int const_residues(const Ctx* c, double v, double scale, int level, Scalars* sc) {
+  int64_t r64 = 0;
+  int rc;
+  if ((rc = const_value(v, scale, &r64))) return rc;
+  const long long r = r64;
   for (int i = 0; i < level; i++) {
     const uint64_t q = c->mod[i];
     uint64_t m = r >= 0 ? (uint64_t)r % q : (q - ((uint64_t)(-(r + 1)) + 1) % q) % q;

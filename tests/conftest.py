@@ -11,4 +11,3 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU oracle test")
-    config.addinivalue_line("markers", "gpu_full: needs an MI355X and minutes of oracle work (outside -m gpu)")

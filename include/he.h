@@ -597,7 +597,9 @@ int he_cheb_relu_coeffs(double beta, int degree, double* coeffs);
  * q 2^f_g, q the prime that level's rescale removes; e_g split e and f_g
  * split round(log2(q_0 / (delta a))) (a = 2 pi with double angles, else 1)
  * as evenly as possible, larger first (he_boot_scales).  Levels consumed:
- * 2 levels + he_cheb_plan's count + r.
+ * 2 * levels + he_cheb_plan's count + r.  The client's secret should be
+ * sparse (Hamming weight h) so that |I| <= (h + 1) / 2 stays below k_min:
+ * a multiple of q_0 outside [-K, K] is not removed.
  * Key switches: the transforms' rotations (he_boot_plan), one
  * conjugation and he_cheb's relinearizations twice.  The giant steps of each
  * transform level (round-robin, each stream keeping a partial sum) and the

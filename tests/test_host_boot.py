@@ -49,3 +49,23 @@ def test_boot_recipe_errors():
         he.boot_mod_coeffs(8.0, 0)
     with pytest.raises(he.HEError):
         he.boot_mod_coeffs(8.0, 31, 9)
+
+
+@pytest.mark.parametrize("log_n", [3, 5, 9, 13, 14])
+def test_boot_plan_every_level_count(log_n):
+    """Every level count from 1 to log2(N/2): rotation keys, plaintext counts
+    and key switches of the C plan equal the oracle's, and the transforms'
+    diagonals at the small rings equal the oracle's values."""
+    for levels in range(1, log_n):
+        plan = BT.BootPlan(log_n, levels, 12.0, 2.0 ** 50, 31)
+        rots, counts, ks = he.boot_plan(log_n, levels, key_switches=True)
+        assert rots == plan.rotations(), (log_n, levels)
+        assert counts == [p.count() for p in plan.cts_plans] + [p.count() for p in plan.stc_plans]
+        assert ks == sum(len(p.babies) + sum(1 for j, _ in p.giants if j != 0)
+                         for p in plan.cts_plans + plan.stc_plans)
+        if log_n <= 9:
+            for inverse in (True, False):
+                want = [v for lv in (plan.cts_values() if inverse else plan.stc_values()) for v in lv]
+                got = he.boot_diagonals(log_n, levels, inverse)
+                assert len(got) == len(want)
+                assert max(np.max(np.abs(g - w)) for g, w in zip(got, want)) < 1e-12

@@ -70,7 +70,7 @@ struct KeyEntry {
 // two output polynomials of each.  Written on the lane's stream by a one-thread
 // kernel before the launches that read it (stream order keeps it stable).
 constexpr int SET_MAX = 8;
-constexpr int HOIST_SET_MIN = 3;  // key switches from which a hoisted set is batched
+constexpr int HOIST_SET_MIN = 2;  // key switches from which a hoisted set is batched
 struct SetTab {
   const uint64_t* key[SET_MAX];
   uint32_t g[SET_MAX];

@@ -23,7 +23,7 @@ Measured in the same run and reported beside it:
 Inputs are seeded synthetic residues (what RLWE ciphertexts, keys and
 encoded plaintexts look like), resident in HBM before each timed region.
 
---gpus > 1 is refused: this build measures one GPU.
+--gpus > 1 is refused: the benchmark measures one GPU.
 """
 import argparse
 import json
@@ -918,7 +918,7 @@ def cpu_baseline(budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus %d refused)" % args.gpus, file=sys.stderr)
+        print("bench.py: measures one GPU only (--gpus %d refused)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -16,7 +16,7 @@ def declared_functions():
     return names
 
 
-def test_header_declares_north_star_calls():
+def test_header_declares_hot_path_calls():
     names = declared_functions()
     for n in ["he_ntt", "he_rotate", "he_rotate_hoisted", "he_mul_plain", "he_relin", "he_conv2d",
               "he_avgpool", "he_fc"]:

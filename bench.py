@@ -826,10 +826,11 @@ def _resnet_costs(costs):
 def cpu_baseline(budget_s):
     """The oracle (test infrastructure, untuned) on the host, in this run, at
     all cores and at one thread: whole single rotations at the headline
-    parameters (the value), the tiny convolution and the LeNet-shaped stack
-    measured whole, and the ResNet-shaped layers costed from measured oracle
-    primitives (each layer's schedule run on slot vectors, every operation
-    priced by the oracle's measured time at its level)."""
+    parameters (the value), the tiny convolution, the LeNet-shaped stack and
+    (all cores only) a bootstrap at N=2^16 measured whole, and the
+    ResNet-shaped layers costed from measured oracle primitives (each
+    layer's schedule run on slot vectors, every operation priced by the
+    oracle's measured time at its level)."""
     from oracle import ckks, layers as LY
     import numpy as np
     import synth
@@ -893,6 +894,22 @@ def cpu_baseline(budget_s):
             t_l, _ = _timed_cpu(lenet, 0.0, 1)
             layers.setdefault("lenet5_stack_n14_ms", {})[tag] = round(t_l * 1e3, 1)
             layers.setdefault("lenet5_stack_n14_costed_ms", {})[tag] = round(_lenet_cost(c1costs) * 1e3, 1)
+            # bootstrapping at N=2^16 L=24 measured whole on all cores (the
+            # cosine-with-double-angles variant of the bootstrap section; keys
+            # and plaintexts made before the timing)
+            log("cpu baseline: bootstrapping at N=2^16")
+            from oracle import boot as BT
+
+            sb, pb = ctx.keygen(11, hamming=32)
+            bplan = BT.BootPlan(16, 3, 12.0, pr.scale, 39, 3)
+            kb = {r: ctx.gen_rotation_key(sb, r, 11) for r in bplan.rotations()}
+            kb[ckks.CONJ] = ctx.gen_rotation_key(sb, ckks.CONJ, 11)
+            rkb = ctx.gen_relin_key(sb, 11)
+            bcts, bstc = BT.boot_plaintexts(ctx, bplan, pr.L)
+            xb = ctx.encrypt(pb, ctx.encode(synth.uniform_slots(2, pr.n // 2), pr.scale, 1), 11)
+            t_b, _ = _timed_cpu(lambda: BT.bootstrap(ctx, xb, bplan, kb, rkb, bcts, bstc), 0.0, 1)
+            layers.setdefault("bootstrap_n16_ms", {})[tag] = round(t_b * 1e3, 1)
+            del kb, bcts, bstc
             for name, t in _resnet_costs(c2costs).items():
                 layers.setdefault(name + "_costed_ms", {})[tag] = round(t * 1e3, 1)
             res["_c2_rot_nproc"] = c2costs[24]["rot"]

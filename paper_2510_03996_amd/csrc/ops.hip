@@ -47,16 +47,22 @@ struct MacList {
   uint64_t ps[MAC_LIST_MAX];  // polynomial stride of ct_t (words)
   int n;
 };
+// (both polynomials per thread: each plaintext word is read once)
 __global__ __launch_bounds__(256) void k_mac_list(MacList ml, uint64_t* out, size_t ops, int logn,
                                                   const ModInfo* __restrict__ mods, int accumulate) {
   const size_t n = (size_t)1 << logn;
   const size_t j = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y, k = blockIdx.z;
+  const int i = blockIdx.y;
   const ModInfo mi = mods[i];
   const size_t off = i * n + j;
-  uint64_t r = accumulate ? out[k * ops + off] : 0;
-  for (int t = 0; t < ml.n; t++) r = add_mod(r, mul_mod(ml.ct[t][k * ml.ps[t] + off], ml.pt[t][off], mi), mi.q);
-  out[k * ops + off] = r;
+  uint64_t r0 = accumulate ? out[off] : 0, r1 = accumulate ? out[ops + off] : 0;
+  for (int t = 0; t < ml.n; t++) {
+    const uint64_t p = ml.pt[t][off];
+    r0 = add_mod(r0, mul_mod(ml.ct[t][off], p, mi), mi.q);
+    r1 = add_mod(r1, mul_mod(ml.ct[t][ml.ps[t] + off], p, mi), mi.q);
+  }
+  out[off] = r0;
+  out[ops + off] = r1;
 }
 
 // per-limb scalar constants (Shoup pairs) for constant-polynomial plaintexts
@@ -250,7 +256,7 @@ int he_mac_plain(he_ctx* h, const he_ct* cts, const he_pt* pts, int n, he_ct* ou
       ml.pt[t] = pts[t0 + t].data;
       ml.ps[t] = (uint64_t)cts[t0 + t].cap * N;
     }
-    k_mac_list<<<grid_for(c, l, 2), 256, 0, (hipStream_t)st>>>(ml, out->data, out->cap * N, c->log_n, c->d_mod,
+    k_mac_list<<<grid_for(c, l, 1), 256, 0, (hipStream_t)st>>>(ml, out->data, out->cap * N, c->log_n, c->d_mod,
                                                                (accumulate || t0 > 0) ? 1 : 0);
     HE_HIP(hipGetLastError());
   }

@@ -604,7 +604,9 @@ int he_cheb_relu_coeffs(double beta, int degree, double* coeffs);
  * conjugation and he_cheb's relinearizations twice.  The giant steps of each
  * transform level (round-robin, each stream keeping a partial sum) and the
  * two EvalMod parts run on up to he_ctx_layer_streams streams at every ring
- * degree; the result does not depend on the split. */
+ * degree (at N = 2^16, where he_cheb forks a helper of its own stream, the
+ * second part runs on the caller's second helper stream, so the parts
+ * overlap); the result does not depend on the split. */
 typedef struct {
   int32_t levels;        /* levels per linear transform, 1..log2(N/2) */
   int32_t degree;        /* EvalMod Chebyshev degree, 1..HE_CHEB_MAX_DEGREE */

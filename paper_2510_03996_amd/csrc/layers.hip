@@ -2102,8 +2102,12 @@ int he_bootstrap(he_ctx* h, const he_ct* in, const he_boot_desc* desc, const he_
     he_ct re2 = ev.fresh(), im2 = ev.fresh();
     {
       // the two parts on two streams when helpers are allowed; each part's
-      // last step writes its result into a buffer of the caller's evaluator
-      Fork fk(ev, std::min(streams, 2));
+      // last step writes its result into a buffer of the caller's evaluator.
+      // Where the Chebyshev evaluation itself forks (N = 2^16), the caller's
+      // part borrows the caller's first helper, so the other part takes a
+      // second one: the parts then overlap, and no helper's temporaries are
+      // handed from one part to the other.
+      Fork fk(ev, c->streams_for_ring() > 1 ? 3 : std::min(streams, 2));
       auto evalmod = [&](Ev& e, const he_ct& part, he_ct& res) {
         const int r = desc->double_angles;
         if (r == 0) {

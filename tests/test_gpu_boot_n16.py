@@ -45,14 +45,22 @@ def test_bootstrap_n16_bit_exact():
         assert [int(x) for x in g.moduli] == pr.q + pr.p
         GB.upload_boot_keys(g, keys, rk)
         desc = he.boot_desc(3, 39, 12.0, pr.scale, double_angles=3)
-        got = g.bootstrap(g.ct_from_numpy(ct.data, ct.scale), desc,
-                          [g.pt_from_numpy(p.data, p.scale) for lv in cts for p in lv],
-                          [g.pt_from_numpy(p.data, p.scale) for lv in stc for p in lv],
-                          list(plan.mod_coeffs(pr.q[0])))
+        gct = g.ct_from_numpy(ct.data, ct.scale)
+        gcts = [g.pt_from_numpy(p.data, p.scale) for lv in cts for p in lv]
+        gstc = [g.pt_from_numpy(p.data, p.scale) for lv in stc for p in lv]
+        coeffs = list(plan.mod_coeffs(pr.q[0]))
+        got = g.bootstrap(gct, desc, gcts, gstc, coeffs)
         assert got.level == want.level == pr.L - 15 and got.scale == want.scale
         H.assert_limbs_equal(got.numpy(), want.data, "bootstrap at N=2^16")
         err = np.max(np.abs(ctx.decrypt(sk, ckks.Ciphertext(got.numpy(), got.scale)) - v))
         print("GPU bootstrap bit-exact, max decryption error %.3g, %.1f s" % (err, time.time() - t0), flush=True)
         assert err < 2.0 ** -11
+        # one stream (no helpers), and four (giant steps over four streams,
+        # the EvalMod parts on the caller and its second helper)
+        for n in (1, 4):
+            g.layer_streams(n)
+            got = g.bootstrap(gct, desc, gcts, gstc, coeffs)
+            H.assert_limbs_equal(got.numpy(), want.data, "bootstrap at N=2^16 on %d layer stream(s)" % n)
+            print("bit-exact on %d layer stream(s)" % n, flush=True)
     finally:
         g.close()
